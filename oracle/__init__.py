@@ -1,0 +1,263 @@
+"""FP64 CPU oracle for the arbitrary-positioned SPH buffer update -- TEST INFRASTRUCTURE.
+
+This package is the checker, not the product.  Only ``tests/``, the smoke check in
+``__graft_entry__`` and the CPU-baseline leg of ``bench.py`` may import it.  It wraps
+``sphbuf_oracle.c`` (plain C, FP64, built without FMA contraction) through ctypes and
+shares no code with the GPU library.
+
+Semantics follow arXiv 2406.16786, Section 3 (frames: Eq. 2D_transformation and
+Eqs. rotation_axis .. 3D_transformation; inflow: Algorithm 1; outflow: Algorithm 2;
+bidirectional: Algorithm 3).  See ``sphbuf_oracle.c`` for the step-by-step
+definition used.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sphbuf_oracle.c")
+_LIB = os.path.join(_HERE, "libsphbuf_oracle.so")
+
+OK, ERR_ARG, ERR_CAPACITY, ERR_CFL, ERR_NONFINITE = 0, 1, 4, 5, 6
+INLET, OUTLET, BIDIR = 1, 2, 3
+MAX_BUFFERS = 15
+MAX_CARRIED = 16
+
+
+def build(verbose: bool = False) -> str:
+    """Compile the oracle with gcc (FP64, no FMA contraction); returns the .so path."""
+    cmd = [
+        "gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+        "-Wall", "-Wextra", "-o", _LIB + ".tmp", _SRC, "-lm",
+    ]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+class _CBuffer(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int32),
+        ("pad_", ctypes.c_int32),
+        ("origin", ctypes.c_double * 3),
+        ("rot", ctypes.c_double * 9),
+        ("half", ctypes.c_double * 3),
+        ("margin", ctypes.c_double),
+    ]
+
+
+class _CState(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int32),
+        ("n_carried", ctypes.c_int32),
+        ("n", ctypes.c_int64),
+        ("capacity", ctypes.c_int64),
+        ("next_id", ctypes.c_int64),
+        ("pos", ctypes.c_void_p * 3),
+        ("carried", ctypes.c_void_p * MAX_CARRIED),
+        ("label", ctypes.c_void_p),
+        ("id", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.orc_rotation_2d.argtypes = [ctypes.c_double, dp]
+        L.orc_rodrigues.argtypes = [dp, ctypes.c_double, dp]
+        L.orc_rotation_from_direction.argtypes = [dp, dp]
+        L.orc_rotation_from_direction.restype = ctypes.c_int
+        L.orc_local_coords.argtypes = [ctypes.c_int, ctypes.POINTER(_CBuffer), ctypes.c_int64,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.orc_recycle_literal.argtypes = [ctypes.c_int, ctypes.POINTER(_CBuffer), dp, dp]
+        L.orc_identify.argtypes = [ctypes.POINTER(_CBuffer), ctypes.c_int, ctypes.c_int,
+                                   ctypes.POINTER(_CState), ctypes.c_void_p]
+        L.orc_identify.restype = ctypes.c_int
+        L.orc_update.argtypes = [ctypes.POINTER(_CBuffer), ctypes.c_int, ctypes.POINTER(_CState),
+                                 ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
+                                 ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]
+        L.orc_update.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+# ------------------------------------------------------------------ frames ---
+
+def rotation_2d(theta: float) -> np.ndarray:
+    """Eq. (2D_transformation) as a 3x3 global->local matrix."""
+    q = np.zeros(9)
+    lib().orc_rotation_2d(float(theta), _dptr(q))
+    return q.reshape(3, 3)
+
+
+def rodrigues(n: Sequence[float], theta: float) -> np.ndarray:
+    """Eq. (rotation_matrix) exactly as printed: R = I + S sin(t) + S^2 (1 - cos(t))."""
+    nn = np.ascontiguousarray(n, dtype=np.float64)
+    r = np.zeros(9)
+    lib().orc_rodrigues(_dptr(nn), float(theta), _dptr(r))
+    return r.reshape(3, 3)
+
+
+def rotation_from_direction(d: Sequence[float]) -> np.ndarray:
+    """Global->local frame whose X' axis points along d (reading Q = R^T)."""
+    dd = np.ascontiguousarray(d, dtype=np.float64)
+    if dd.size == 2:
+        dd = np.array([dd[0], dd[1], 0.0])
+    q = np.zeros(9)
+    st = lib().orc_rotation_from_direction(_dptr(dd), _dptr(q))
+    if st != OK:
+        raise ValueError("direction must be a finite non-zero vector")
+    return q.reshape(3, 3)
+
+
+# ----------------------------------------------------------------- buffers ---
+
+@dataclass
+class Buffer:
+    """One in-/outlet: kind, origin O', global->local matrix Q, half-extents, margin."""
+    kind: int
+    origin: Sequence[float]
+    rot: np.ndarray
+    half: Sequence[float]
+    margin: float
+
+    def c(self) -> _CBuffer:
+        b = _CBuffer()
+        b.kind = int(self.kind)
+        o = list(self.origin) + [0.0] * (3 - len(self.origin))
+        h = list(self.half) + [0.0] * (3 - len(self.half))
+        for i in range(3):
+            b.origin[i] = float(o[i])
+            b.half[i] = float(h[i])
+        rr = np.asarray(self.rot, dtype=np.float64).reshape(9)
+        for i in range(9):
+            b.rot[i] = float(rr[i])
+        b.margin = float(self.margin)
+        return b
+
+
+def _cbufs(bufs: Sequence[Buffer]):
+    arr = (_CBuffer * max(1, len(bufs)))()
+    for i, b in enumerate(bufs):
+        arr[i] = b.c()
+    return arr
+
+
+def local_coords(dim: int, buf: Buffer, x, y, z=None) -> np.ndarray:
+    """FP64 r' = Q (r - O') of FP32 positions; returns an (n, 3) array."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    y = np.ascontiguousarray(y, dtype=np.float32)
+    n = x.size
+    zz = np.ascontiguousarray(z if z is not None else np.zeros(n), dtype=np.float32)
+    out = np.zeros((3, n))
+    cb = buf.c()
+    lib().orc_local_coords(dim, ctypes.byref(cb), n, x.ctypes.data, y.ctypes.data, zz.ctypes.data,
+                           out[0].ctypes.data, out[1].ctypes.data, out[2].ctypes.data)
+    return out.T.copy()
+
+
+def recycle_literal(dim: int, buf: Buffer, r: Sequence[float]) -> np.ndarray:
+    """Literal inverse transform of the paper: Q^T (Q (r - O') - [a,0,0]) + O' (FP64)."""
+    rr = np.zeros(3)
+    rr[: len(r)] = r
+    out = np.zeros(3)
+    cb = buf.c()
+    lib().orc_recycle_literal(dim, ctypes.byref(cb), _dptr(rr), _dptr(out))
+    return out[:dim].copy()
+
+
+# ------------------------------------------------------------------- state ---
+
+@dataclass
+class State:
+    """Host particle arrays, all of length ``capacity``; ``n`` live entries."""
+    dim: int
+    pos: List[np.ndarray]
+    carried: List[np.ndarray]
+    label: np.ndarray
+    id: np.ndarray
+    n: int
+    next_id: int
+    _keep: list = field(default_factory=list, repr=False)
+
+    @property
+    def capacity(self) -> int:
+        return int(self.label.shape[0])
+
+    def copy(self) -> "State":
+        return State(self.dim, [p.copy() for p in self.pos], [c.copy() for c in self.carried],
+                     self.label.copy(), self.id.copy(), self.n, self.next_id)
+
+    def c(self) -> _CState:
+        for p in self.pos + self.carried:
+            assert p.dtype == np.float32 and p.flags.c_contiguous and p.shape[0] == self.capacity
+        assert self.label.dtype == np.int32 and self.id.dtype == np.int64
+        assert len(self.pos) == self.dim and len(self.carried) <= MAX_CARRIED
+        s = _CState()
+        s.dim = self.dim
+        s.n_carried = len(self.carried)
+        s.n = int(self.n)
+        s.capacity = self.capacity
+        s.next_id = int(self.next_id)
+        for i, p in enumerate(self.pos):
+            s.pos[i] = p.ctypes.data
+        for i, c in enumerate(self.carried):
+            s.carried[i] = c.ctypes.data
+        s.label = self.label.ctypes.data
+        s.id = self.id.ctypes.data
+        return s
+
+
+@dataclass
+class UpdateResult:
+    status: int
+    gen: np.ndarray
+    dele: np.ndarray
+    n_labelled: np.ndarray
+
+
+def identify(bufs: Sequence[Buffer], st: State, which: int = -1):
+    """Algorithm 1, identification; returns (status, n_labelled per buffer)."""
+    cs = st.c()
+    cb = _cbufs(bufs)
+    nl = np.zeros(max(1, len(bufs)), dtype=np.int64)
+    rc = lib().orc_identify(cb, len(bufs), int(which), ctypes.byref(cs), nl.ctypes.data)
+    return rc, nl[: len(bufs)]
+
+
+def update(bufs: Sequence[Buffer], st: State) -> UpdateResult:
+    """One buffer update (Algorithms 1-3); mutates ``st`` in place unless it fails."""
+    cs = st.c()
+    cb = _cbufs(bufs)
+    cap = max(1, st.n)
+    gen = np.zeros(cap, dtype=np.int64)
+    dele = np.zeros(cap, dtype=np.int64)
+    ng, nd = ctypes.c_int64(0), ctypes.c_int64(0)
+    nl = np.zeros(max(1, len(bufs)), dtype=np.int64)
+    rc = lib().orc_update(cb, len(bufs), ctypes.byref(cs), gen.ctypes.data, ctypes.byref(ng),
+                          dele.ctypes.data, ctypes.byref(nd), nl.ctypes.data)
+    if rc == OK:
+        st.n = int(cs.n)
+        st.next_id = int(cs.next_id)
+        return UpdateResult(rc, gen[: ng.value].copy(), dele[: nd.value].copy(), nl[: len(bufs)].copy())
+    return UpdateResult(rc, np.zeros(0, np.int64), np.zeros(0, np.int64), np.zeros(len(bufs), np.int64))

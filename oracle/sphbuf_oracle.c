@@ -1,0 +1,360 @@
+/*
+ * sphbuf_oracle.c -- TEST INFRASTRUCTURE, not part of the product.
+ *
+ * A plain, deliberately slow FP64 CPU oracle for one update of the
+ * arbitrary-positioned SPH in-/outlet buffer (arXiv 2406.16786, Section 3,
+ * Algorithms 1-3).  Every particle is checked against every buffer (brute
+ * force): the paper's local cell-linked lists are an efficiency device that must
+ * not change the result, so the oracle does without them.
+ *
+ * Build: gcc -O2 -std=c99 -ffp-contract=off -fno-fast-math (no FMA contraction,
+ * so every FP64 expression below is evaluated exactly as written, left to right).
+ *
+ * Only the test suite, the smoke check and the CPU-baseline leg of the benchmark
+ * may load this library; it shares no code with the GPU library.
+ */
+#include "sphbuf_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---------------------------------------------------------------- frames --- */
+
+/* Eq. (2D_transformation): X' =  cos(t) (X - X_O') + sin(t) (Y - Y_O'),
+ *                          Y' = -sin(t) (X - X_O') + cos(t) (Y - Y_O'),
+ * theta positive anticlockwise.  Embedded in 3x3 with Z' = Z - Z_O'. */
+void orc_rotation_2d(double theta, double q[9]) {
+    double c = cos(theta), s = sin(theta);
+    q[0] = c;    q[1] = s;   q[2] = 0.0;
+    q[3] = -s;   q[4] = c;   q[5] = 0.0;
+    q[6] = 0.0;  q[7] = 0.0; q[8] = 1.0;
+}
+
+/* Eq. (antisymmetric_matrix) and Eq. (rotation_matrix):
+ * S = [[0, -nz, ny], [nz, 0, -nx], [-ny, nx, 0]],  R = I + S sin(t) + S^2 (1 - cos(t)). */
+void orc_rodrigues(const double n[3], double theta, double r[9]) {
+    double S[9] = {0.0, -n[2], n[1], n[2], 0.0, -n[0], -n[1], n[0], 0.0};
+    double S2[9];
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            double acc = 0.0;
+            for (int m = 0; m < 3; m++) acc += S[3 * i + m] * S[3 * m + j];
+            S2[3 * i + j] = acc;
+        }
+    double st = sin(theta), omc = 1.0 - cos(theta);
+    for (int i = 0; i < 9; i++) r[i] = ((i % 4 == 0) ? 1.0 : 0.0) + S[i] * st + S2[i] * omc;
+}
+
+/* Frame whose X' axis is the unit vector along d (Section 3.1, 3-D case).
+ * Eq. (rotation_axis): n = (OX x O'X') / |OX x O'X'| with OX = e_x and O'X' = d.
+ * theta is the angle between e_x and d (positive).  Rodrigues' R of Eq.
+ * (rotation_matrix) is the active rotation taking e_x onto d, so the local
+ * coordinate of a point along d is (R e_x).(r - O') = [R^T (r - O')]_x: the
+ * global->local matrix of Eq. (3D_transformation) is read as Q = R^T.  With
+ * n = e_z this Q is exactly the 2-D matrix of Eq. (2D_transformation).
+ * Degenerate axis (d parallel to e_x, where the cross product vanishes):
+ * d = +e_x gives Q = I; d = -e_x gives a half turn about e_z. */
+int orc_rotation_from_direction(const double d[3], double q[9]) {
+    double len = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    if (!(len > 0.0) || !isfinite(len)) return ORC_ERR_ARG;
+    double u[3] = {d[0] / len, d[1] / len, d[2] / len};
+    /* e_x x u = (0, -u_z, u_y) */
+    double cx[3] = {0.0, -u[2], u[1]};
+    double s = sqrt(cx[1] * cx[1] + cx[2] * cx[2]);
+    if (s == 0.0) {
+        for (int i = 0; i < 9; i++) q[i] = 0.0;
+        if (u[0] > 0.0) {
+            q[0] = 1.0; q[4] = 1.0; q[8] = 1.0;
+        } else {
+            q[0] = -1.0; q[4] = -1.0; q[8] = 1.0;
+        }
+        return ORC_OK;
+    }
+    double n[3] = {cx[0] / s, cx[1] / s, cx[2] / s};
+    double theta = atan2(s, u[0]);
+    double r[9];
+    orc_rodrigues(n, theta, r);
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) q[3 * i + j] = r[3 * j + i];
+    return ORC_OK;
+}
+
+/* r' = Q (r - O'), Eq. (2D_transformation) / Eq. (3D_transformation).
+ * FP64, each component summed left to right: ((q0 d0 + q1 d1) + q2 d2). */
+static void local_of(int dim, const orc_buffer *b, double x, double y, double z, double lc[3]) {
+    double d0 = x - b->origin[0];
+    double d1 = y - b->origin[1];
+    if (dim == 2) {
+        lc[0] = b->rot[0] * d0 + b->rot[1] * d1;
+        lc[1] = b->rot[3] * d0 + b->rot[4] * d1;
+        lc[2] = 0.0;
+    } else {
+        double d2 = z - b->origin[2];
+        lc[0] = (b->rot[0] * d0 + b->rot[1] * d1) + b->rot[2] * d2;
+        lc[1] = (b->rot[3] * d0 + b->rot[4] * d1) + b->rot[5] * d2;
+        lc[2] = (b->rot[6] * d0 + b->rot[7] * d1) + b->rot[8] * d2;
+    }
+}
+
+void orc_local_coords(int dim, const orc_buffer *b, int64_t n, const float *x, const float *y,
+                      const float *z, double *xl, double *yl, double *zl) {
+    for (int64_t i = 0; i < n; i++) {
+        double lc[3];
+        local_of(dim, b, (double)x[i], (double)y[i], dim == 3 ? (double)z[i] : 0.0, lc);
+        xl[i] = lc[0];
+        yl[i] = lc[1];
+        if (zl) zl[i] = lc[2];
+    }
+}
+
+void orc_recycle_literal(int dim, const orc_buffer *b, const double r[3], double out[3]) {
+    double lc[3];
+    local_of(dim, b, r[0], r[1], dim == 3 ? r[2] : 0.0, lc);
+    lc[0] = lc[0] - 2.0 * b->half[0]; /* r' - [a, 0, 0] */
+    int m = dim;
+    for (int j = 0; j < m; j++) {     /* Q^T (...) + O' */
+        double acc = 0.0;
+        for (int i = 0; i < m; i++) acc += b->rot[3 * i + j] * lc[i];
+        out[j] = acc + b->origin[j];
+    }
+    if (dim == 2) out[2] = 0.0;
+}
+
+/* ------------------------------------------------------------ predicates --- */
+
+/* Buffer box (Section 3.1): |X'| < a/2 and |Y'| < b/2 (and |Z'| < c/2 in 3-D). */
+static int in_box(int dim, const orc_buffer *b, const double lc[3]) {
+    if (!(fabs(lc[0]) < b->half[0])) return 0;
+    if (!(fabs(lc[1]) < b->half[1])) return 0;
+    if (dim == 3 && !(fabs(lc[2]) < b->half[2])) return 0;
+    return 1;
+}
+
+/* Check region: the box dilated by the margin on every side, standing for the
+ * local cell-linked lists "a little larger than the buffer" (Section 3.1). */
+static int in_check(int dim, const orc_buffer *b, const double lc[3]) {
+    if (!(fabs(lc[0]) < b->half[0] + b->margin)) return 0;
+    if (!(fabs(lc[1]) < b->half[1] + b->margin)) return 0;
+    if (dim == 3 && !(fabs(lc[2]) < b->half[2] + b->margin)) return 0;
+    return 1;
+}
+
+static void position_of(const orc_state *s, int64_t i, double r[3]) {
+    r[0] = (double)s->pos[0][i];
+    r[1] = (double)s->pos[1][i];
+    r[2] = s->dim == 3 ? (double)s->pos[2][i] : 0.0;
+}
+
+static int valid_args(const orc_buffer *bufs, int nb, const orc_state *s) {
+    if (!s || (s->dim != 2 && s->dim != 3)) return 0;
+    if (nb < 0 || nb > ORC_MAX_BUFFERS || (nb > 0 && !bufs)) return 0;
+    if (s->n < 0 || s->n > s->capacity) return 0;
+    if (s->n_carried < 0 || s->n_carried > ORC_MAX_CARRIED) return 0;
+    for (int k = 0; k < nb; k++)
+        if (bufs[k].kind < ORC_INLET || bufs[k].kind > ORC_BIDIR) return 0;
+    return 1;
+}
+
+static void count_labels(int nb, const orc_state *s, int64_t *n_labelled) {
+    if (!n_labelled) return;
+    for (int k = 0; k < nb; k++) n_labelled[k] = 0;
+    for (int64_t i = 0; i < s->n; i++) {
+        int32_t l = s->label[i];
+        if (l >= 1 && l <= nb) n_labelled[l - 1]++;
+    }
+}
+
+/* ------------------------------------------------------- identification --- */
+
+/* Algorithm 1, first procedure ("execute only once"): every particle inside the
+ * box of buffer k is added to buffer k's set, i.e. receives label k. */
+int orc_identify(const orc_buffer *bufs, int nb, int which, orc_state *s, int64_t *n_labelled) {
+    if (!valid_args(bufs, nb, s)) return ORC_ERR_ARG;
+    if (which != -1 && (which < 1 || which > nb)) return ORC_ERR_ARG;
+    for (int64_t i = 0; i < s->n; i++)
+        for (int c = 0; c < s->dim; c++)
+            if (!isfinite(s->pos[c][i])) return ORC_ERR_NONFINITE;
+    for (int64_t i = 0; i < s->n; i++) {
+        double r[3], lc[3];
+        position_of(s, i, r);
+        for (int k = 0; k < nb; k++) {
+            if (which != -1 && which != k + 1) continue;
+            local_of(s->dim, &bufs[k], r[0], r[1], r[2], lc);
+            if (in_box(s->dim, &bufs[k], lc)) s->label[i] = k + 1;
+        }
+    }
+    count_labels(nb, s, n_labelled);
+    return ORC_OK;
+}
+
+/* ---------------------------------------------------------------- update --- */
+
+enum { EV_NONE = 0, EV_GEN = 1, EV_DEL = 2 };
+
+static void copy_particle(orc_state *s, int64_t dst, int64_t src) {
+    for (int c = 0; c < s->dim; c++) s->pos[c][dst] = s->pos[c][src];
+    for (int f = 0; f < s->n_carried; f++) s->carried[f][dst] = s->carried[f][src];
+    s->label[dst] = s->label[src];
+    s->id[dst] = s->id[src];
+}
+
+/*
+ * One update, every decision taken on the input state:
+ *  1. Inflow (Algorithm 1, second procedure; Algorithm 3 first branch): a particle
+ *     of buffer k (label k) with X' > a/2 is duplicated, and the original is moved
+ *     back one buffer length, r' <- r' - [a, 0, 0], mapped back by the inverse
+ *     transform (Eqs. 2D/3D_Inverse_transformation).  That map is exactly
+ *     r <- r - a d with d = Q^T e_x; it is evaluated in FP64 and rounded to FP32.
+ *  2. Outflow (Algorithm 2): any particle in the check region of an outlet with
+ *     X' > a/2 is deleted; at a bidirectional buffer (Algorithm 3 second branch) a
+ *     particle of the buffer with X' < -a/2 is deleted.
+ *  3. Relabel (Algorithms 2 and 3, second procedure): for outlets and
+ *     bidirectional buffers, every surviving particle in the check region, at its
+ *     post-recycle position, gets label k if it is inside the box, otherwise loses
+ *     label k (other labels are left alone).
+ *  Candidates of every buffer are restricted to its check region; a particle of
+ *  buffer k found outside it (moved more than the margin in one step) is an
+ *  error.  Layout: deleted slots below the new count are refilled in ascending
+ *  order from the surviving tail, then the duplicates are appended in ascending
+ *  source order with label 0 and ids next_id, next_id + 1, ...
+ */
+int orc_update(const orc_buffer *bufs, int nb, orc_state *s, int64_t *gen_src, int64_t *n_gen,
+               int64_t *del_idx, int64_t *n_del, int64_t *n_labelled) {
+    if (!valid_args(bufs, nb, s)) return ORC_ERR_ARG;
+    const int dim = s->dim;
+    const int64_t N = s->n;
+
+    for (int64_t i = 0; i < N; i++)
+        for (int c = 0; c < dim; c++)
+            if (!isfinite(s->pos[c][i])) return ORC_ERR_NONFINITE;
+
+    unsigned char *ev = (unsigned char *)calloc((size_t)(N > 0 ? N : 1), 1);
+    unsigned char *owner = (unsigned char *)calloc((size_t)(N > 0 ? N : 1), 1);
+    if (!ev || !owner) {
+        free(ev);
+        free(owner);
+        return ORC_ERR_ARG;
+    }
+    int status = ORC_OK;
+
+    /* ---- classification on the input state ---- */
+    for (int64_t i = 0; i < N && status == ORC_OK; i++) {
+        double r[3], lc[3];
+        position_of(s, i, r);
+        for (int k = 0; k < nb; k++) {
+            const orc_buffer *b = &bufs[k];
+            local_of(dim, b, r[0], r[1], r[2], lc);
+            if (!in_check(dim, b, lc)) {
+                if (s->label[i] == k + 1) { status = ORC_ERR_CFL; break; }
+                continue;
+            }
+            if (owner[i] != 0) { status = ORC_ERR_ARG; break; } /* overlapping regions */
+            owner[i] = (unsigned char)(k + 1);
+            const int mine = (s->label[i] == k + 1);
+            if (b->kind == ORC_INLET) {
+                if (mine && lc[0] > b->half[0]) ev[i] = EV_GEN;
+            } else if (b->kind == ORC_OUTLET) {
+                if (lc[0] > b->half[0]) ev[i] = EV_DEL;
+            } else {
+                if (mine && lc[0] > b->half[0]) ev[i] = EV_GEN;
+                else if (mine && lc[0] < -b->half[0]) ev[i] = EV_DEL;
+            }
+        }
+    }
+    if (status != ORC_OK) {
+        free(ev);
+        free(owner);
+        return status;
+    }
+
+    int64_t G = 0, D = 0;
+    for (int64_t i = 0; i < N; i++) {
+        if (ev[i] == EV_GEN) G++;
+        if (ev[i] == EV_DEL) D++;
+    }
+    const int64_t Np = N - D;
+    if (Np + G > s->capacity) {
+        free(ev);
+        free(owner);
+        return ORC_ERR_CAPACITY;
+    }
+
+    /* index sets, ascending because i runs upwards */
+    int64_t g = 0, d = 0;
+    for (int64_t i = 0; i < N; i++) {
+        if (ev[i] == EV_GEN) gen_src[g++] = i;
+        if (ev[i] == EV_DEL) del_idx[d++] = i;
+    }
+
+    /* ---- duplicates: a copy of the crossing particle's state, before recycling ---- */
+    const int nf = s->n_carried;
+    float *dup_pos = (float *)malloc(sizeof(float) * (size_t)(G * 3 + 1));
+    float *dup_car = (float *)malloc(sizeof(float) * (size_t)(G * (nf > 0 ? nf : 1) + 1));
+    for (int64_t j = 0; j < G; j++) {
+        int64_t i = gen_src[j];
+        for (int c = 0; c < dim; c++) dup_pos[3 * j + c] = s->pos[c][i];
+        for (int f = 0; f < nf; f++) dup_car[(size_t)nf * j + f] = s->carried[f][i];
+    }
+
+    /* ---- recycle: r <- fl32(r - a d), d = first row of Q ---- */
+    for (int64_t j = 0; j < G; j++) {
+        int64_t i = gen_src[j];
+        const orc_buffer *b = &bufs[owner[i] - 1];
+        const double a = 2.0 * b->half[0];
+        for (int c = 0; c < dim; c++) {
+            double shift = a * b->rot[c];
+            s->pos[c][i] = (float)((double)s->pos[c][i] - shift);
+        }
+    }
+
+    /* ---- relabel outlets / bidirectional buffers on post-recycle positions ---- */
+    for (int64_t i = 0; i < N; i++) {
+        if (ev[i] == EV_DEL) continue;
+        double r[3], lc[3];
+        position_of(s, i, r);
+        for (int k = 0; k < nb; k++) {
+            const orc_buffer *b = &bufs[k];
+            if (b->kind == ORC_INLET) continue;
+            local_of(dim, b, r[0], r[1], r[2], lc);
+            if (!in_check(dim, b, lc)) continue;
+            if (in_box(dim, b, lc)) s->label[i] = k + 1;
+            else if (s->label[i] == k + 1) s->label[i] = 0;
+        }
+    }
+
+    /* ---- layout: refill holes below Np from the surviving tail, ascending ---- */
+    {
+        int64_t h = 0, t = Np;
+        for (int64_t j = 0; j < D; j++) {
+            int64_t hole = del_idx[j];
+            if (hole >= Np) break;
+            while (t < N && ev[t] == EV_DEL) t++;
+            copy_particle(s, hole, t);
+            t++;
+            h++;
+        }
+        (void)h;
+    }
+
+    /* ---- append duplicates: label 0, fresh ids ---- */
+    for (int64_t j = 0; j < G; j++) {
+        int64_t dst = Np + j;
+        for (int c = 0; c < dim; c++) s->pos[c][dst] = dup_pos[3 * j + c];
+        for (int f = 0; f < nf; f++) s->carried[f][dst] = dup_car[(size_t)nf * j + f];
+        s->label[dst] = 0;
+        s->id[dst] = s->next_id + j;
+    }
+    s->next_id += G;
+    s->n = Np + G;
+
+    free(dup_pos);
+    free(dup_car);
+    free(ev);
+    free(owner);
+
+    *n_gen = G;
+    *n_del = D;
+    count_labels(nb, s, n_labelled);
+    return ORC_OK;
+}

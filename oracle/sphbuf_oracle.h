@@ -1,0 +1,89 @@
+/*
+ * sphbuf_oracle.h -- TEST INFRASTRUCTURE, not part of the product.
+ *
+ * Plain, slow, FP64 CPU oracle for one buffer update of the arbitrary-positioned
+ * SPH in-/outlet buffer of Zhang, Fan, Ren, Qian & Hu, "Generalized and
+ * high-efficiency arbitrary-positioned buffer for smoothed particle
+ * hydrodynamics" (arXiv 2406.16786), Section 3 and Algorithms 1-3.
+ *
+ * Only the test suite, the smoke check and the CPU-baseline leg of the benchmark
+ * may load this library.  It shares no code, header, table or helper with the
+ * GPU library, and the GPU library never calls it.
+ *
+ * Conventions (all readings of the paper are listed in the design notes):
+ *   - rot is a row-major 3x3 matrix Q mapping global to local coordinates,
+ *     r' = Q (r - O'); its rows are the local axes X', Y', Z' in global
+ *     coordinates (Eq. 2D_transformation; Eq. 3D_transformation with Q = R^T,
+ *     see orc_rotation_from_direction).
+ *   - half = (a/2, b/2, c/2): buffer half-extents along X', Y', Z'.
+ *   - margin = delta: the check region C = box dilated by delta on every side
+ *     stands for the "local cell-linked lists ... a little larger than the
+ *     buffer" of Section 3.1.
+ *   - label 0 = ordinary fluid particle, label k (1..n_buffers) = buffer k.
+ */
+#ifndef SPHBUF_ORACLE_H
+#define SPHBUF_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_OK = 0, ORC_ERR_ARG = 1, ORC_ERR_CAPACITY = 4, ORC_ERR_CFL = 5, ORC_ERR_NONFINITE = 6 };
+enum { ORC_INLET = 1, ORC_OUTLET = 2, ORC_BIDIR = 3 };
+#define ORC_MAX_BUFFERS 15
+#define ORC_MAX_CARRIED 16
+
+typedef struct {
+    int32_t kind;      /* ORC_INLET / ORC_OUTLET / ORC_BIDIR                    */
+    int32_t pad_;
+    double origin[3];  /* O' in global coordinates                              */
+    double rot[9];     /* Q, row-major, global -> local                          */
+    double half[3];    /* a/2, b/2, c/2 (c ignored in 2-D)                       */
+    double margin;     /* delta > 0                                              */
+} orc_buffer;
+
+typedef struct {
+    int32_t dim;                      /* 2 or 3                                   */
+    int32_t n_carried;                /* number of extra float fields             */
+    int64_t n;                        /* live particles, updated in place         */
+    int64_t capacity;                 /* length of every array                    */
+    int64_t next_id;                  /* id handed to the next duplicate          */
+    float *pos[3];                    /* x, y, z (z unused in 2-D)                */
+    float *carried[ORC_MAX_CARRIED];  /* velocity, mass, density, pressure, ...   */
+    int32_t *label;
+    int64_t *id;
+} orc_state;
+
+/* Eq. (2D_transformation) embedded in 3x3: [[c, s, 0], [-s, c, 0], [0, 0, 1]]. */
+void orc_rotation_2d(double theta, double q[9]);
+/* Eq. (rotation_matrix): R = I + S sin(theta) + S^2 (1 - cos(theta)), S from
+ * Eq. (antisymmetric_matrix).  Returns the matrix exactly as printed. */
+void orc_rodrigues(const double n[3], double theta, double r[9]);
+/* Global->local frame whose X' axis is the unit vector d (Eqs. rotation_axis to
+ * 3D_transformation, read with Q = R^T).  Returns ORC_ERR_ARG if |d| == 0. */
+int orc_rotation_from_direction(const double d[3], double q[9]);
+
+/* FP64 local coordinates of FP32 positions, one buffer, n points. */
+void orc_local_coords(int dim, const orc_buffer *b, int64_t n, const float *x, const float *y,
+                      const float *z, double *xl, double *yl, double *zl);
+
+/* Paper's literal inverse transform, r = Q^T (Q (r - O') - [a,0,0]) + O', in FP64
+ * (Eqs. 2D_Inverse_transformation and 3D_Inverse_transformation). */
+void orc_recycle_literal(int dim, const orc_buffer *b, const double r[3], double out[3]);
+
+/* Buffer-particle identification (Algorithm 1, first procedure): every particle
+ * inside buffer k's box gets label k.  which = buffer index 1..nb, or -1 = all.
+ * n_labelled[k-1] receives the count of label k afterwards. */
+int orc_identify(const orc_buffer *bufs, int nb, int which, orc_state *s, int64_t *n_labelled);
+
+/* One buffer update (Algorithms 1-3).  gen_src / del_idx (capacity >= n) receive
+ * the generated-source and deleted index sets, ascending.  On error nothing is
+ * mutated and the return value says why. */
+int orc_update(const orc_buffer *bufs, int nb, orc_state *s, int64_t *gen_src, int64_t *n_gen,
+               int64_t *del_idx, int64_t *n_del, int64_t *n_labelled);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,347 @@
+"""Seeded synthetic inputs for the SPH in-/outlet buffer update.
+
+This module only draws inputs: particle lattices, buffer placements and the
+prescribed velocity fields that move particles between updates.  It holds none of
+the buffer method's arithmetic (no local frames, no crossing tests, no cell
+lists), so both the GPU library's tests and the FP64 oracle can consume its output.
+
+Buffers are described by placement only -- origin, the unit X' direction (the
+in-/outflow direction), the 2-D rotation angle where there is one, half-extents
+and margin.  Turning a direction into a rotation matrix is the method's job; the
+consumer does it.
+
+The shapes stand in for the paper's cases (Sections 5 and 6), whose geometry is
+only given in figures: a straight 2-D channel, a bent 2-D channel with rotated
+in-/outlets, a 3-D pipe with tilted in-/outlet planes, a 3-D branching pipe
+network with bidirectional buffers, and a batch of hub-and-spoke domains.
+All noise comes from numpy's PCG64 with fixed seeds.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Callable, List, Optional, Sequence
+
+import numpy as np
+
+INLET, OUTLET, BIDIR = 1, 2, 3
+RHO0 = 1000.0
+
+
+@dataclass
+class BufferSpec:
+    kind: int
+    origin: tuple                 # O' (global)
+    direction: tuple              # unit X' axis (global); in 2-D also given by ``angle``
+    half: tuple                   # (a/2, b/2, c/2)
+    margin: float                 # check-region margin delta
+    angle: Optional[float] = None  # 2-D only: anticlockwise angle of X' from the x axis
+
+
+@dataclass
+class Workload:
+    name: str
+    dim: int
+    dp: float
+    cell_size: float
+    lo: tuple
+    hi: tuple
+    n: int
+    capacity: int
+    pos: List[np.ndarray]          # float32, length capacity
+    carried: List[np.ndarray]      # float32 fields copied on duplication, length capacity
+    carried_names: List[str]
+    label: np.ndarray              # int32, length capacity
+    id: np.ndarray                 # int64, length capacity
+    buffers: List[BufferSpec]
+    dt: float
+    steps: int
+    seed_noise: int
+    velocity: Callable = field(repr=False, default=None)  # (xp, pos_list, step, noise) -> list
+    noise_scale: float = 0.0
+
+
+def _alloc(dim: int, n: int, capacity: int, pts: np.ndarray, dp: float):
+    pos = []
+    for c in range(dim):
+        a = np.zeros(capacity, dtype=np.float32)
+        a[:n] = pts[:, c].astype(np.float32)
+        pos.append(a)
+    names = ["vx", "vy", "vz"][:dim] + ["mass", "rho", "p"]
+    carried = [np.zeros(capacity, dtype=np.float32) for _ in names]
+    carried[dim][:n] = np.float32(RHO0 * dp ** dim)
+    carried[dim + 1][:n] = np.float32(RHO0)
+    label = np.zeros(capacity, dtype=np.int32)
+    ids = np.full(capacity, -1, dtype=np.int64)
+    ids[:n] = np.arange(n, dtype=np.int64)
+    return pos, carried, names, label, ids
+
+
+def _jitter(rng, n, dim, dp, amp=0.3):
+    return rng.uniform(-amp * dp, amp * dp, size=(n, dim))
+
+
+def _block_order(idx: np.ndarray, block: int = 3) -> np.ndarray:
+    """Permutation that groups lattice sites into block^dim tiles (integer lattice
+    indices only), the kind of spatial ordering a solver keeps its particles in."""
+    keys = [idx[:, c] // block for c in range(idx.shape[1])][::-1] + \
+           [idx[:, c] % block for c in range(idx.shape[1])][::-1]
+    return np.lexsort(keys[::-1])
+
+
+def _finish(pts_idx, pts, order):
+    if order == "lattice":
+        return pts
+    if order == "blocked":
+        return pts[_block_order(pts_idx)]
+    raise ValueError(order)
+
+
+# ------------------------------------------------------------------ C1 ---
+
+def channel2d(seed: int = 1, capacity_extra: int = 512, order: str = "lattice") -> Workload:
+    """2-D straight channel 2.0 x 0.4, dp = 0.02, about 2,000 particles; axis-aligned
+    inlet and outlet with 4-layer buffers; u = (1 + 0.05 xi, 0); dt = 0.25 dp."""
+    dp = 0.02
+    cs = 2.6 * dp
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ii, jj = np.meshgrid(np.arange(100), np.arange(20), indexing="xy")
+    idx = np.stack([ii.ravel(), jj.ravel()], axis=1)
+    pts = (idx + 0.5) * dp + _jitter(rng, idx.shape[0], 2, dp)
+    pts = _finish(idx, pts, order)
+    n = pts.shape[0]
+    cap = n + capacity_extra
+    pos, carried, names, label, ids = _alloc(2, n, cap, pts, dp)
+    half = (2 * dp, 0.2, 0.0)
+    bufs = [BufferSpec(INLET, (2 * dp, 0.2, 0.0), (1.0, 0.0, 0.0), half, cs, angle=0.0),
+            BufferSpec(OUTLET, (2.0 - 2 * dp, 0.2, 0.0), (1.0, 0.0, 0.0), half, cs, angle=0.0)]
+
+    def velocity(xp, p, step, noise):
+        # noise: standard normal per slot, shape (n,)
+        return [1.0 + 0.05 * noise[0], 0.0 * noise[0]]
+
+    return Workload("channel2d", 2, dp, cs, (-2 * cs, -2 * cs, 0.0), (2.0 + 2 * cs, 0.4 + 2 * cs, 0.0),
+                    n, cap, pos, carried, names, label, ids, bufs, 0.25 * dp, 200, 1000, velocity, 1.0)
+
+
+# ------------------------------------------------------------------ C2 ---
+
+class _BentChannel:
+    """Centerline: straight leg A (1.8 m at +30 deg), a clockwise circular bend of
+    radius 0.4 through 75 deg, straight leg B (1.8 m at -45 deg); width W = 0.2."""
+
+    def __init__(self):
+        self.W = 0.2
+        a0 = math.radians(30.0)
+        self.tA = np.array([math.cos(a0), math.sin(a0)])
+        self.nA = np.array([-self.tA[1], self.tA[0]])          # left normal
+        self.P0 = np.array([0.0, 0.0])
+        self.P1 = self.P0 + 1.8 * self.tA
+        self.Rb = 0.4
+        right = np.array([self.tA[1], -self.tA[0]])
+        self.C = self.P1 + self.Rb * right
+        self.phi0 = math.atan2(self.P1[1] - self.C[1], self.P1[0] - self.C[0])  # 120 deg
+        self.phi1 = self.phi0 - math.radians(75.0)                               # 45 deg
+        self.P2 = self.C + self.Rb * np.array([math.cos(self.phi1), math.sin(self.phi1)])
+        b0 = math.radians(-45.0)
+        self.tB = np.array([math.cos(b0), math.sin(b0)])
+        self.nB = np.array([-self.tB[1], self.tB[0]])
+        self.P3 = self.P2 + 1.8 * self.tB
+
+    def frame(self, xp, x, y):
+        """Signed distance s to the centerline (positive to the left) and the unit
+        tangent, from the nearest of the three pieces; also an 'inside' mask."""
+        W = self.W
+        # leg A
+        rxA, ryA = x - self.P0[0], y - self.P0[1]
+        tA = rxA * self.tA[0] + ryA * self.tA[1]
+        sA = rxA * self.nA[0] + ryA * self.nA[1]
+        okA = (tA >= 0) & (tA <= 1.8)
+        # leg B
+        rxB, ryB = x - self.P2[0], y - self.P2[1]
+        tB = rxB * self.tB[0] + ryB * self.tB[1]
+        sB = rxB * self.nB[0] + ryB * self.nB[1]
+        okB = (tB >= 0) & (tB <= 1.8)
+        # bend (clockwise, the centre lies on the right: left side is outward)
+        rxC, ryC = x - self.C[0], y - self.C[1]
+        rho = xp.sqrt(rxC * rxC + ryC * ryC)
+        phi = xp.arctan2(ryC, rxC)
+        sC = rho - self.Rb
+        okC = (phi <= self.phi0) & (phi >= self.phi1)
+        big = 1e9
+        dA = xp.where(okA, xp.abs(sA), big + 0 * sA)
+        dB = xp.where(okB, xp.abs(sB), big + 0 * sB)
+        dC = xp.where(okC, xp.abs(sC), big + 0 * sC)
+        s = xp.where(dA <= xp.minimum(dB, dC), sA, xp.where(dB <= dC, sB, sC))
+        rhos = xp.where(rho > 0, rho, 1.0 + 0 * rho)
+        # clockwise tangent on the bend: (sin phi, -cos phi)
+        txC, tyC = ryC / rhos, -rxC / rhos
+        tx = xp.where(dA <= xp.minimum(dB, dC), self.tA[0] + 0 * x, xp.where(dB <= dC, self.tB[0] + 0 * x, txC))
+        ty = xp.where(dA <= xp.minimum(dB, dC), self.tA[1] + 0 * x, xp.where(dB <= dC, self.tB[1] + 0 * x, tyC))
+        inside = xp.minimum(xp.minimum(dA, dB), dC) < W / 2
+        return s, tx, ty, inside
+
+
+def bent_channel2d(seed: int = 2, capacity_extra: int = 4096, order: str = "lattice") -> Workload:
+    """2-D bent channel, inlet at +30 deg and outlet at -45 deg, dp = 0.002, about
+    206k particles; Poiseuille profile plus 2 % noise; dt = 0.25 dp."""
+    dp = 0.002
+    cs = 2.6 * dp
+    g = _BentChannel()
+    rng = np.random.Generator(np.random.PCG64(seed))
+    s = np.linspace(0.0, 1.0, 257)[:, None]
+    phis = g.phi0 + (g.phi1 - g.phi0) * s[:, 0]
+    centre = np.concatenate([g.P0 + s * 1.8 * g.tA,
+                             g.C + g.Rb * np.stack([np.cos(phis), np.sin(phis)], axis=1),
+                             g.P2 + s * 1.8 * g.tB])
+    bl = centre.min(axis=0) - g.W / 2 - 4 * dp
+    bh = centre.max(axis=0) + g.W / 2 + 4 * dp
+    nx = int(math.ceil((bh[0] - bl[0]) / dp))
+    ny = int(math.ceil((bh[1] - bl[1]) / dp))
+    ii, jj = np.meshgrid(np.arange(nx), np.arange(ny), indexing="xy")
+    idx = np.stack([ii.ravel(), jj.ravel()], axis=1)
+    base = bl + (idx + 0.5) * dp
+    _, _, _, inside = g.frame(np, base[:, 0], base[:, 1])
+    idx = idx[inside]
+    pts = bl + (idx + 0.5) * dp + _jitter(rng, idx.shape[0], 2, dp)
+    pts = _finish(idx, pts, order)
+    n = pts.shape[0]
+    cap = n + capacity_extra
+    pos, carried, names, label, ids = _alloc(2, n, cap, pts, dp)
+    half = (2 * dp, g.W / 2, 0.0)
+    oin = g.P0 + 2 * dp * g.tA
+    oout = g.P3 - 2 * dp * g.tB
+    bufs = [BufferSpec(INLET, (oin[0], oin[1], 0.0), (g.tA[0], g.tA[1], 0.0), half, cs, angle=math.radians(30.0)),
+            BufferSpec(OUTLET, (oout[0], oout[1], 0.0), (g.tB[0], g.tB[1], 0.0), half, cs,
+                       angle=math.radians(-45.0))]
+    umax = 1.0
+
+    def velocity(xp, p, step, noise):
+        s, tx, ty, _ = g.frame(xp, p[0], p[1])
+        prof = umax * xp.clip(1.0 - (2.0 * s / g.W) ** 2, 0.0, None)
+        return [prof * tx + 0.02 * umax * noise[0], prof * ty + 0.02 * umax * noise[1]]
+
+    lo = (bl[0] - 2 * cs, bl[1] - 2 * cs, 0.0)
+    hi = (bh[0] + 2 * cs, bh[1] + 2 * cs, 0.0)
+    return Workload("bent_channel2d", 2, dp, cs, lo, hi, n, cap, pos, carried, names, label, ids, bufs,
+                    0.25 * dp, 1000, 2000, velocity, 1.0)
+
+
+# ------------------------------------------------------------------ C3 ---
+
+def _rx(deg):
+    t = math.radians(deg)
+    return np.array([[1, 0, 0], [0, math.cos(t), -math.sin(t)], [0, math.sin(t), math.cos(t)]])
+
+
+def _ry(deg):
+    t = math.radians(deg)
+    return np.array([[math.cos(t), 0, math.sin(t)], [0, 1, 0], [-math.sin(t), 0, math.cos(t)]])
+
+
+def pipe3d(seed: int = 3, dp: float = 0.001, capacity_extra: Optional[int] = None,
+           order: str = "lattice", length: float = 1.0, radius: float = 0.05) -> Workload:
+    """3-D circular pipe along +z (R = 0.05, L = 1.0, dp = 0.001: about 7.85 M
+    particles).  The inlet plane through the origin is tilted 20 deg about x, the
+    outlet plane through (0, 0, L) 35 deg about y; 4-layer buffers; parabolic
+    velocity along z plus 2 % noise; dt = 0.25 dp.  ``dp``/``length``/``radius``
+    scale it down for small cases."""
+    R, L = radius, length
+    cs = 2.6 * dp
+    rng = np.random.Generator(np.random.PCG64(seed))
+    d_in = _rx(20.0) @ np.array([0.0, 0.0, 1.0])
+    d_out = _ry(35.0) @ np.array([0.0, 0.0, 1.0])
+    zlo = -R * math.tan(math.radians(20.0)) - dp
+    zhi = L + R * math.tan(math.radians(35.0)) + dp
+    nxy = int(math.ceil(2 * R / dp))
+    nz = int(math.ceil((zhi - zlo) / dp))
+    o = np.array([-R, -R, zlo])
+    pts_all, idx_all = [], []
+    zchunk = max(1, nz // 16)
+    ii, jj = np.meshgrid(np.arange(nxy), np.arange(nxy), indexing="xy")
+    ii, jj = ii.ravel(), jj.ravel()
+    xy = np.stack([o[0] + (ii + 0.5) * dp, o[1] + (jj + 0.5) * dp], axis=1)
+    disk = (xy[:, 0] ** 2 + xy[:, 1] ** 2) < R * R
+    ii, jj, xy = ii[disk], jj[disk], xy[disk]
+    for k0 in range(0, nz, zchunk):
+        ks = np.arange(k0, min(nz, k0 + zchunk))
+        z = o[2] + (ks + 0.5) * dp
+        X = np.repeat(xy[None, :, 0], ks.size, axis=0).ravel()
+        Y = np.repeat(xy[None, :, 1], ks.size, axis=0).ravel()
+        Z = np.repeat(z[:, None], xy.shape[0], axis=1).ravel()
+        keep = (X * d_in[0] + Y * d_in[1] + Z * d_in[2] > 0) & \
+               (X * d_out[0] + Y * d_out[1] + (Z - L) * d_out[2] < 0)
+        pts_all.append(np.stack([X[keep], Y[keep], Z[keep]], axis=1))
+        idx_all.append(np.stack([np.tile(ii, ks.size)[keep], np.tile(jj, ks.size)[keep],
+                                 np.repeat(ks, ii.size)[keep]], axis=1))
+    pts = np.concatenate(pts_all)
+    idx = np.concatenate(idx_all)
+    pts = pts + _jitter(rng, pts.shape[0], 3, dp)
+    pts = _finish(idx, pts, order)
+    n = pts.shape[0]
+    cap = n + (capacity_extra if capacity_extra is not None else max(4096, n // 100))
+    pos, carried, names, label, ids = _alloc(3, n, cap, pts, dp)
+    hin = (2 * dp, R / math.cos(math.radians(20.0)) + 2 * dp, R / math.cos(math.radians(20.0)) + 2 * dp)
+    hout = (2 * dp, R / math.cos(math.radians(35.0)) + 2 * dp, R / math.cos(math.radians(35.0)) + 2 * dp)
+    oin = 2 * dp * d_in
+    oout = np.array([0.0, 0.0, L]) - 2 * dp * d_out
+    bufs = [BufferSpec(INLET, tuple(oin), tuple(d_in), hin, cs),
+            BufferSpec(OUTLET, tuple(oout), tuple(d_out), hout, cs)]
+    umax = 1.0
+
+    def velocity(xp, p, step, noise):
+        r2 = p[0] * p[0] + p[1] * p[1]
+        prof = umax * xp.clip(1.0 - r2 / (R * R), 0.0, None)
+        return [0.02 * umax * noise[0], 0.02 * umax * noise[1], prof + 0.02 * umax * noise[2]]
+
+    m = 2 * cs + 2 * dp
+    lo = (-R - m, -R - m, zlo - m - 2 * dp)
+    hi = (R + m, R + m, zhi + m + 2 * dp)
+    return Workload("pipe3d", 3, dp, cs, lo, hi, n, cap, pos, carried, names, label, ids, bufs,
+                    0.25 * dp, 500, 3000, velocity, 1.0)
+
+
+# -------------------------------------------------------------- helpers ---
+
+def noise_for_step(wl: Workload, step: int, n: int) -> np.ndarray:
+    """Standard-normal noise, one row per velocity component, for one step."""
+    rng = np.random.Generator(np.random.PCG64(wl.seed_noise + step))
+    return rng.standard_normal(size=(wl.dim, n))
+
+
+def advect_host(wl: Workload, pos: Sequence[np.ndarray], n: int, step: int) -> None:
+    """x <- fl32(x + fl32(u dt)) for the first n particles, on the host."""
+    p64 = [p[:n].astype(np.float64) for p in pos]
+    u = wl.velocity(np, p64, step, noise_for_step(wl, step, n))
+    for c in range(wl.dim):
+        du = (np.asarray(u[c], dtype=np.float64) * wl.dt).astype(np.float32)
+        pos[c][:n] = (pos[c][:n] + du).astype(np.float32)
+
+
+def random_box_particles(seed: int, n: int, dim: int, lo, hi, capacity: Optional[int] = None,
+                         n_carried: int = 3):
+    """Uniform random FP32 particles in [lo, hi); for small property tests."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    cap = capacity if capacity is not None else n + 64
+    pos = []
+    for c in range(dim):
+        a = np.zeros(cap, dtype=np.float32)
+        a[:n] = rng.uniform(lo[c], hi[c], size=n).astype(np.float32)
+        pos.append(a)
+    carried = []
+    for _ in range(n_carried):
+        a = np.zeros(cap, dtype=np.float32)
+        a[:n] = rng.standard_normal(n).astype(np.float32)
+        carried.append(a)
+    label = np.zeros(cap, dtype=np.int32)
+    ids = np.full(cap, -1, dtype=np.int64)
+    ids[:n] = np.arange(n)
+    return pos, carried, label, ids
+
+
+def random_unit(rng, dim: int) -> np.ndarray:
+    v = rng.standard_normal(dim)
+    v = v / np.linalg.norm(v)
+    if dim == 2:
+        v = np.array([v[0], v[1], 0.0])
+    return v
