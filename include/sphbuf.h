@@ -1,0 +1,203 @@
+/*
+ * sphbuf.h -- C ABI of the MI355X (gfx950) buffer-update library for the
+ * arbitrary-positioned SPH in-/outlet buffer of Zhang, Fan, Ren, Qian & Hu,
+ * "Generalized and high-efficiency arbitrary-positioned buffer for smoothed
+ * particle hydrodynamics" (arXiv 2406.16786).
+ *
+ * One update runs five steps on the GPU:
+ *   1. a cell-linked list over all particles (counting sort: cell_start, cell_idx),
+ *   2. per in-/outlet, candidates gathered only from the cells that overlap its
+ *      check region (Section 3.1, the "local cell-linked lists"),
+ *   3. each candidate rotated into the buffer's local frame (Eq. 2D_transformation,
+ *      Eq. 3D_transformation) so that crossing is a one-coordinate comparison,
+ *   4. inlet generation: the crossing buffer particle is duplicated and recycled
+ *      one buffer length back (Algorithm 1, Algorithm 3),
+ *   5. outlet deletion by stream compaction (Algorithm 2, Algorithm 3), with
+ *      relabelling of outlet / bidirectional buffer particles.
+ *
+ * Conventions
+ *   - Every particle array is a caller-owned DEVICE array (structure of arrays),
+ *     at least `capacity` elements long.  Positions and carried fields are FP32,
+ *     labels int32 (0 = ordinary fluid, k = 1..15 = buffer k), ids int64.
+ *   - The live particle count is a device-resident int64 (`n_dev`) that the
+ *     library reads at the start of each call and rewrites after an update.
+ *   - Rotation matrices are row-major 3x3, global -> local: r' = Q (r - O').  Row 0
+ *     is the in-/outflow direction X'.  In 2-D only the upper-left 2x2 block is
+ *     used and it must be a proper rotation.
+ *   - All calls return sph_status; nothing throws across the ABI.  On any error
+ *     an update leaves every particle array and the library's own counters as
+ *     they were (checks run on the GPU before the first write).
+ *   - A context is bound to one HIP stream and is not thread-safe.  All device
+ *     work of a context is enqueued on that stream.  Calls marked "sync" wait for
+ *     the stream; the others only enqueue.
+ *   - The library allocates its device scratch in sph_create and
+ *     sph_buffer_define; build and update calls allocate nothing.
+ */
+#ifndef SPHBUF_H
+#define SPHBUF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SPH_OK = 0,
+    SPH_ERR_ARG = 1,              /* bad pointer, size, dimension or kind                  */
+    SPH_ERR_ROTATION = 2,         /* matrix not orthonormal with det +1 (tol 1e-9)          */
+    SPH_ERR_OVERLAP = 3,          /* check region intersects an existing buffer's           */
+    SPH_ERR_CAPACITY = 4,         /* N - |deleted| + |generated| would exceed capacity      */
+    SPH_ERR_CFL = 5,              /* a buffer particle left its buffer's check region       */
+    SPH_ERR_NONFINITE = 6,        /* NaN / Inf position among the live particles            */
+    SPH_ERR_TOO_MANY_BUFFERS = 7, /* more than SPH_MAX_BUFFERS buffers in one context       */
+    SPH_ERR_EVENTS = 8,           /* more events in one update than max_events              */
+    SPH_ERR_HIP = 9,              /* a HIP runtime call failed                              */
+    SPH_ERR_STATE = 10            /* call out of order (e.g. update before any cell list)   */
+} sph_status;
+
+typedef enum { SPH_INLET = 1, SPH_OUTLET = 2, SPH_BIDIR = 3 } sph_kind;
+
+#define SPH_MAX_BUFFERS 15
+#define SPH_MAX_CARRIED 16
+#define SPH_MAX_EVENTS_LIMIT 8192
+
+typedef struct sph_ctx sph_ctx;
+
+/* Caller-owned device arrays of one domain. */
+typedef struct {
+    float *pos[3];                      /* x, y, z; pos[2] ignored (may be NULL) in 2-D        */
+    float *carried[SPH_MAX_CARRIED];    /* fields copied on duplication (velocity, mass, ...)  */
+    int32_t n_carried;                  /* 0..SPH_MAX_CARRIED                                  */
+    int32_t pad_;
+    int32_t *label;                     /* 0 = fluid, k = buffer k; written by the library     */
+    int64_t *id;                        /* duplicates get next_id, next_id + 1, ...            */
+    int64_t *n_dev;                     /* device int64: live count, updated in place          */
+    int64_t capacity;                   /* length of every array above (< 2^31)                */
+} sph_particles;
+
+typedef struct {
+    int32_t dim;            /* 2 or 3                                                         */
+    int32_t pad_;
+    double lo[3], hi[3];    /* cell-grid bounds; particles outside are binned into edge cells */
+    double cell_size;       /* cell edge (2h = 2.6 dp in the paper's setting)                 */
+    double dp;              /* particle spacing: the FP32 guard band is max(1e-4 dp, bound)   */
+    int64_t capacity;       /* largest particle capacity that will be passed                  */
+    int64_t max_events;     /* per update, for generated and for deleted; <= 8192             */
+    int64_t next_id;        /* id of the first duplicate                                      */
+    void *stream;           /* hipStream_t (NULL = the null stream)                           */
+} sph_config;
+
+/* Result of the last update (see sph_last_result). */
+typedef struct {
+    int32_t status;                      /* sph_status of the update                          */
+    int32_t n_buffers;
+    int64_t n_generated;                 /* |G|                                               */
+    int64_t n_deleted;                   /* |D|                                               */
+    int64_t n_before;                    /* N on entry                                        */
+    int64_t n_after;                     /* N - |D| + |G| (== n_before on error)              */
+    int64_t next_id;
+    int64_t n_labelled[SPH_MAX_BUFFERS]; /* particles carrying each buffer's label afterwards  */
+} sph_result;
+
+/* ------------------------------------------------------------------ lifetime -- */
+
+/* Create a context: validates cfg, allocates the cell grid and all scratch on the
+ * current HIP device.  SPH_ERR_ARG for a bad config (dim, cell_size <= 0, empty or
+ * non-finite bounds, more than 2^31 cells, capacity <= 0 or >= 2^31, max_events
+ * outside 1..8192); SPH_ERR_HIP if allocation fails.  *out is NULL on error. */
+sph_status sph_create(const sph_config *cfg, sph_ctx **out);
+sph_status sph_destroy(sph_ctx *ctx);
+
+/* Define one in-/outlet buffer (Section 3.1: translation O' and rotation of the
+ * local frame, box of half-extents a/2, b/2, c/2 centred at O').  margin > 0 is
+ * the check-region margin delta (<= 0 selects cell_size): the check region is the
+ * box dilated by delta on every side and stands for the local cell-linked lists
+ * "a little larger than the buffer".  Host FP64 work only (frame validation,
+ * cell cover of the check region, guard band), then one small upload.
+ * Errors: SPH_ERR_ARG (kind, non-positive or non-finite extents, a check region
+ * wider than 2^20 cells), SPH_ERR_ROTATION, SPH_ERR_OVERLAP (check regions of two
+ * buffers intersect), SPH_ERR_TOO_MANY_BUFFERS.  *buffer_id receives 1..15. */
+sph_status sph_buffer_define(sph_ctx *ctx, sph_kind kind, const double origin[3], const double rot[9],
+                             const double half[3], double margin, int32_t *buffer_id);
+
+/* ------------------------------------------------------------------ hot path -- */
+
+/* Step 1: counting-sort cell list of the live particles on the context stream
+ * (async).  Flags non-finite positions for the next update. */
+sph_status sph_celllist_build(sph_ctx *ctx, const sph_particles *p);
+
+/* Algorithm 1, identification ("execute only once"): label k for every live
+ * particle inside buffer k's box; buffer_id = -1 for all buffers.  Full pass over
+ * the particles (sync).  SPH_ERR_NONFINITE leaves labels untouched. */
+sph_status sph_buffer_identify(sph_ctx *ctx, sph_particles *p, int32_t buffer_id);
+
+/* Steps 2-5 with local-cell candidates (needs sph_celllist_build on the same
+ * positions first).  Sync: waits for the stream and returns |G| and |D|.
+ * Errors SPH_ERR_CFL / CAPACITY / NONFINITE / EVENTS leave everything unchanged. */
+sph_status sph_buffer_update(sph_ctx *ctx, sph_particles *p, int64_t *n_generated, int64_t *n_deleted);
+
+/* Same as sph_buffer_update but only enqueues; read the outcome with
+ * sph_last_result (which syncs). */
+sph_status sph_buffer_update_async(sph_ctx *ctx, sph_particles *p);
+
+/* Baseline: the same update with every live particle as a candidate of every
+ * buffer (no cell list; the all-particle scan the paper replaces). Sync. */
+sph_status sph_buffer_update_fullscan(sph_ctx *ctx, sph_particles *p, int64_t *n_generated,
+                                      int64_t *n_deleted);
+sph_status sph_buffer_update_fullscan_async(sph_ctx *ctx, sph_particles *p);
+
+/* Sync: outcome of the last update enqueued on this context. */
+sph_status sph_last_result(sph_ctx *ctx, sph_result *out);
+
+/* Sync: sorted index sets of the last successful update (pre-update indices).
+ * gen_src: sources of the duplicates; del_idx: deleted particles.  Copies at most
+ * cap entries of each. */
+sph_status sph_last_events(sph_ctx *ctx, int64_t *gen_src, int64_t *del_idx, int64_t cap, int64_t *n_gen,
+                           int64_t *n_del);
+
+/* Device pointers to the library-owned cell list of the last build: cell_start
+ * has n_cells + 1 entries, cell_idx has N entries (pre-update indices). */
+sph_status sph_celllist_view(sph_ctx *ctx, const int32_t **cell_start, const int32_t **cell_idx,
+                             int64_t *n_cells, int32_t dims[3]);
+
+/* Library state that is not in the particle arrays: next_id and each buffer's
+ * labelled count (sync).  Lets a caller checkpoint and restore a run. */
+sph_status sph_state_get(sph_ctx *ctx, int64_t *next_id, int64_t n_labelled[SPH_MAX_BUFFERS]);
+sph_status sph_state_set(sph_ctx *ctx, int64_t next_id, const int64_t n_labelled[SPH_MAX_BUFFERS]);
+
+/* ------------------------------------------------------------ host helpers -- */
+/* Pure host FP64; usable without a GPU. */
+
+/* Eq. (2D_transformation) embedded in 3x3: [[cos, sin, 0], [-sin, cos, 0], [0, 0, 1]]. */
+sph_status sph_rotation_2d(double theta, double rot[9]);
+/* Eq. (rotation_matrix) exactly as printed (active rotation by theta about unit n). */
+sph_status sph_rotation_axis_angle(const double n[3], double theta, double rot[9]);
+/* Global->local frame with X' along dir (Eqs. rotation_axis to 3D_transformation,
+ * read with Q = R^T so that Q dir = |dir| e_x).  dir parallel to -e_x gives a half
+ * turn about e_z.  SPH_ERR_ARG for a zero or non-finite dir. */
+sph_status sph_rotation_from_direction(const double dir[3], double rot[9]);
+/* SPH_OK if rot (2x2 block in 2-D) is orthonormal with det +1 within 1e-9. */
+sph_status sph_check_rotation(int32_t dim, const double rot[9]);
+
+/* Cells of a dense grid (lo, cell_size, dims) whose boxes, dilated by 1e-2 of a
+ * cell and with edge cells extended to infinity, intersect the check region of a
+ * buffer (separating-axis test).  Written as runs along x: first cell (linear
+ * index ix + dims[0] * (iy + dims[1] * iz)) and run length, at most cap runs.
+ * SPH_ERR_ARG if more than cap runs are needed (*n_runs then holds the need). */
+sph_status sph_grid_cover(int32_t dim, const double lo[3], double cell_size, const int32_t dims[3],
+                          const double origin[3], const double rot[9], const double half[3], double margin,
+                          int32_t *run_first, int32_t *run_len, int64_t cap, int64_t *n_runs);
+
+/* FP32 guard band of a buffer: max(1e-4 dp, 2 E) with E a bound on the FP32
+ * error of a local coordinate of any candidate (hi/lo split origin). */
+double sph_guard_band(int32_t dim, const double origin[3], const double half[3], double margin,
+                      double cell_size, double dp);
+
+const char *sph_status_str(sph_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

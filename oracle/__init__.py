@@ -93,6 +93,10 @@ def lib():
                                  ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
                                  ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]
         L.orc_update.restype = ctypes.c_int
+        L.orc_cell_list.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_float, ctypes.c_void_p, ctypes.c_int64,
+                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p]
+        L.orc_cell_list.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -261,3 +265,23 @@ def update(bufs: Sequence[Buffer], st: State) -> UpdateResult:
         st.next_id = int(cs.next_id)
         return UpdateResult(rc, gen[: ng.value].copy(), dele[: nd.value].copy(), nl[: len(bufs)].copy())
     return UpdateResult(rc, np.zeros(0, np.int64), np.zeros(0, np.int64), np.zeros(len(bufs), np.int64))
+
+
+def cell_list(dim: int, lo, inv_cs: float, dims, x, y, z=None):
+    """Stable counting-sort cell list (cell_start[C+1], cell_idx[n]); FP32 binning."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    y = np.ascontiguousarray(y, dtype=np.float32)
+    n = x.size
+    zz = np.ascontiguousarray(z if z is not None else np.zeros(n), dtype=np.float32)
+    lo32 = np.zeros(3, np.float32)
+    lo32[: len(lo)] = lo
+    d = np.ones(3, np.int32)
+    d[: len(dims)] = dims
+    C = int(d[0]) * int(d[1]) * (int(d[2]) if dim == 3 else 1)
+    start = np.zeros(C + 1, np.int32)
+    idx = np.zeros(max(1, n), np.int32)
+    rc = lib().orc_cell_list(dim, lo32.ctypes.data, float(np.float32(inv_cs)), d.ctypes.data, n, x.ctypes.data,
+                             y.ctypes.data, zz.ctypes.data, start.ctypes.data, idx.ctypes.data)
+    if rc != OK:
+        raise ValueError("bad cell-list arguments")
+    return start, idx[:n]

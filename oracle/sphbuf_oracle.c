@@ -358,3 +358,35 @@ int orc_update(const orc_buffer *bufs, int nb, orc_state *s, int64_t *gen_src, i
     count_labels(nb, s, n_labelled);
     return ORC_OK;
 }
+
+/* ------------------------------------------------------------- cell list --- */
+
+static int64_t axis_cell(float v, float lo, float inv_cs, int32_t n) {
+    float f = floorf((v - lo) * inv_cs);
+    if (!(f >= 0.0f)) f = 0.0f; /* also maps NaN to cell 0 */
+    if (f > (float)(n - 1)) f = (float)(n - 1);
+    return (int64_t)f;
+}
+
+int orc_cell_list(int dim, const float lo[3], float inv_cs, const int32_t dims[3], int64_t n, const float *x,
+                  const float *y, const float *z, int32_t *cell_start, int32_t *cell_idx) {
+    if (dim != 2 && dim != 3) return ORC_ERR_ARG;
+    const int64_t nz = dim == 3 ? dims[2] : 1;
+    const int64_t C = (int64_t)dims[0] * dims[1] * nz;
+    int64_t *key = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    if (!key) return ORC_ERR_ARG;
+    for (int64_t c = 0; c <= C; c++) cell_start[c] = 0;
+    for (int64_t i = 0; i < n; i++) {
+        int64_t k = axis_cell(x[i], lo[0], inv_cs, dims[0]) + (int64_t)dims[0] * axis_cell(y[i], lo[1], inv_cs, dims[1]);
+        if (dim == 3) k += (int64_t)dims[0] * dims[1] * axis_cell(z[i], lo[2], inv_cs, dims[2]);
+        key[i] = k;
+        cell_start[k + 1]++;
+    }
+    for (int64_t c = 0; c < C; c++) cell_start[c + 1] += cell_start[c];
+    int32_t *fill = (int32_t *)malloc(sizeof(int32_t) * (size_t)(C > 0 ? C : 1));
+    for (int64_t c = 0; c < C; c++) fill[c] = cell_start[c];
+    for (int64_t i = 0; i < n; i++) cell_idx[fill[key[i]]++] = (int32_t)i;
+    free(fill);
+    free(key);
+    return ORC_OK;
+}

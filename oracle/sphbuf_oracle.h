@@ -83,6 +83,16 @@ int orc_identify(const orc_buffer *bufs, int nb, int which, orc_state *s, int64_
 int orc_update(const orc_buffer *bufs, int nb, orc_state *s, int64_t *gen_src, int64_t *n_gen,
                int64_t *del_idx, int64_t *n_del, int64_t *n_labelled);
 
+/* Cell-linked list of the first n particles on a dense grid of dims cells with
+ * FP32 origin lo and FP32 inverse cell size inv_cs: cell index per axis is
+ * floor(fl32(fl32(x - lo) * inv_cs)) clamped to [0, dims-1] (the binning
+ * precision is the GPU library's own choice, so the oracle takes the same FP32
+ * decision), linear key ix + dims0 * (iy + dims1 * iz).  cell_start has
+ * dims0*dims1*dims2 + 1 entries (exclusive prefix counts), cell_idx n entries
+ * in ascending particle order within each cell (stable counting sort). */
+int orc_cell_list(int dim, const float lo[3], float inv_cs, const int32_t dims[3], int64_t n, const float *x,
+                  const float *y, const float *z, int32_t *cell_start, int32_t *cell_idx);
+
 #ifdef __cplusplus
 }
 #endif

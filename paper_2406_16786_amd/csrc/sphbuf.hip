@@ -1,0 +1,1279 @@
+// MI355X (gfx950, CDNA4) kernels and C ABI of the arbitrary-positioned SPH
+// in-/outlet buffer update (arXiv 2406.16786, Section 3, Algorithms 1-3).
+//
+// Per update:
+//   K0a count   : cell key of every particle (FP32 floor), per-cell rank from
+//                 wave-run-aggregated atomics (one atomic per run of equal keys).
+//   K0b scan    : single-pass decoupled look-back exclusive scan of the cell
+//                 counts -> cell_start; zeroes the counts for the next build.
+//   K0c scatter : cell_idx[cell_start[key] + rank] = i.
+//   K1  classify: one wave per run of cover cells of one buffer; candidates are
+//                 rotated into the buffer frame in FP32 (hi/lo origin), decisions
+//                 inside the guard band are redone in FP64 exactly as defined;
+//                 ballot/mbcnt wave compaction appends generation, deletion and
+//                 relabel events.  (K1f: the same over every particle.)
+//   K2  finalize: one workgroup: status checks before any write, LDS bitonic
+//                 sort of the event lists, duplicate capture, recycle, relabel,
+//                 hole refill from the tail, append, counters.
+// Everything reads the live count from device memory, so the whole chain can be
+// enqueued without host round trips.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "sphbuf.h"
+#include "sphbuf_internal.h"
+
+using sphbuf::BufDev;
+
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kBuildBlock = 256;
+constexpr int kScanBlock = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanBlock * kScanItems;
+constexpr int kClassifyBlock = 256;
+constexpr int kFinBlock = 1024;
+constexpr unsigned kMaxEv = SPH_MAX_EVENTS_LIMIT;
+constexpr int kRelPerEvent = 4;
+
+constexpr unsigned kIn = 1u, kBox = 2u, kFront = 4u, kBack = 8u;
+constexpr int kEvNone = 0, kEvGen = 1, kEvDel = 2;
+
+struct Grid {
+    float lo[3];
+    float inv_cs;
+    int32_t dims[3];
+    int32_t dim;
+};
+
+struct Parts {
+    float *pos[3];
+    float *car[SPH_MAX_CARRIED];
+    int32_t nc;
+    int32_t dim;
+    int32_t *label;
+    int64_t *id;
+    int64_t *n_dev;
+    int64_t capacity;
+};
+
+// Device-resident counters and library state.
+struct Ctl {
+    unsigned int n_gen, n_del, n_rel, pad0;
+    unsigned long long found[16];  // label-k candidates inside C_k (pre-update)
+    unsigned long long post[16];   // label-k particles among C_k candidates afterwards
+    unsigned int tile_counter;
+    unsigned int nonfinite_epoch;  // epoch of the last build/scan that met a non-finite position
+    unsigned int scan_fault;       // set if a look-back wait ran past its spin limit
+    unsigned int pad2;
+    long long next_id;
+    long long n_labelled[16];
+    unsigned int ident_bad;
+    unsigned int pad1;
+    unsigned long long ident_count[16];
+};
+
+// ------------------------------------------------------------ device utils --
+
+__device__ __forceinline__ unsigned mbcnt(unsigned long long mask) {
+    return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+}
+
+__device__ __forceinline__ int lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+
+// Live count clamped to [0, capacity]: a bad count can never send an index out
+// of the arrays (the finalize step reports it as an argument error).
+__device__ __forceinline__ int64_t live_count(const int64_t *n_dev, int64_t capacity) {
+    const int64_t n = *n_dev;
+    return n < 0 ? 0 : (n > capacity ? capacity : n);
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs; renumber them so that each
+// XCD owns a contiguous range of logical blocks (and so of particles).
+__device__ __forceinline__ int logical_block() {
+    const int b = blockIdx.x, g = gridDim.x;
+    if (g & 7) return b;
+    return (b & 7) * (g >> 3) + (b >> 3);
+}
+
+__device__ __forceinline__ uint32_t cell_key(const Grid &g, float x, float y, float z) {
+    float fx = floorf((x - g.lo[0]) * g.inv_cs);
+    float fy = floorf((y - g.lo[1]) * g.inv_cs);
+    fx = fminf(fmaxf(fx, 0.0f), (float)(g.dims[0] - 1));
+    fy = fminf(fmaxf(fy, 0.0f), (float)(g.dims[1] - 1));
+    uint32_t k = (uint32_t)fx + (uint32_t)g.dims[0] * (uint32_t)fy;
+    if (g.dim == 3) {
+        float fz = floorf((z - g.lo[2]) * g.inv_cs);
+        fz = fminf(fmaxf(fz, 0.0f), (float)(g.dims[2] - 1));
+        k += (uint32_t)g.dims[0] * (uint32_t)g.dims[1] * (uint32_t)fz;
+    }
+    return k;
+}
+
+// Exact FP64 decision: local coordinates r' = Q (r - O') evaluated as
+// ((q0 d0 + q1 d1) + q2 d2) with every product and sum rounded separately (no
+// FMA), then the strict comparisons of the box and the check region.
+__device__ __attribute__((noinline)) unsigned classify64(const BufDev &b, int dim, float x, float y, float z) {
+#pragma clang fp contract(off)
+    const double d0 = __dadd_rn((double)x, -b.o[0]);
+    const double d1 = __dadd_rn((double)y, -b.o[1]);
+    double l0, l1, l2 = 0.0;
+    if (dim == 2) {
+        l0 = __dadd_rn(__dmul_rn(b.q[0], d0), __dmul_rn(b.q[1], d1));
+        l1 = __dadd_rn(__dmul_rn(b.q[3], d0), __dmul_rn(b.q[4], d1));
+    } else {
+        const double d2 = __dadd_rn((double)z, -b.o[2]);
+        l0 = __dadd_rn(__dadd_rn(__dmul_rn(b.q[0], d0), __dmul_rn(b.q[1], d1)), __dmul_rn(b.q[2], d2));
+        l1 = __dadd_rn(__dadd_rn(__dmul_rn(b.q[3], d0), __dmul_rn(b.q[4], d1)), __dmul_rn(b.q[5], d2));
+        l2 = __dadd_rn(__dadd_rn(__dmul_rn(b.q[6], d0), __dmul_rn(b.q[7], d1)), __dmul_rn(b.q[8], d2));
+    }
+    const double a0 = fabs(l0), a1 = fabs(l1), a2 = fabs(l2);
+    unsigned bits = 0;
+    if (a0 < b.thr[3] && a1 < b.thr[4] && (dim == 2 || a2 < b.thr[5])) bits |= kIn;
+    if (a0 < b.thr[0] && a1 < b.thr[1] && (dim == 2 || a2 < b.thr[2])) bits |= kBox;
+    if (l0 > b.thr[0]) bits |= kFront;
+    if (l0 < -b.thr[0]) bits |= kBack;
+    return bits;
+}
+
+// Bulk FP32 decision with the FP64 recheck inside the guard band.
+__device__ __forceinline__ unsigned classify(const BufDev &b, int dim, float x, float y, float z) {
+    const float d0 = (x - b.ohi[0]) - b.olo[0];
+    const float d1 = (y - b.ohi[1]) - b.olo[1];
+    const float d2 = dim == 3 ? (z - b.ohi[2]) - b.olo[2] : 0.0f;
+    if (d0 * d0 + d1 * d1 + d2 * d2 > b.rsq) return 0u;  // outside a sphere holding C_k
+    const float l0 = b.qf[0] * d0 + b.qf[1] * d1 + b.qf[2] * d2;
+    const float l1 = b.qf[3] * d0 + b.qf[4] * d1 + b.qf[5] * d2;
+    const float l2 = b.qf[6] * d0 + b.qf[7] * d1 + b.qf[8] * d2;
+    const float a0 = fabsf(l0), a1 = fabsf(l1), a2 = fabsf(l2);
+    const float g = b.guard;
+    bool near = fabsf(a0 - b.thrf[0]) < g || fabsf(a0 - b.thrf[3]) < g || fabsf(a1 - b.thrf[1]) < g ||
+                fabsf(a1 - b.thrf[4]) < g;
+    if (dim == 3) near = near || fabsf(a2 - b.thrf[2]) < g || fabsf(a2 - b.thrf[5]) < g;
+    if (near) return classify64(b, dim, x, y, z);
+    unsigned bits = 0;
+    if (a0 < b.thrf[3] && a1 < b.thrf[4] && (dim == 2 || a2 < b.thrf[5])) bits |= kIn;
+    if (a0 < b.thrf[0] && a1 < b.thrf[1] && (dim == 2 || a2 < b.thrf[2])) bits |= kBox;
+    if (l0 > b.thrf[0]) bits |= kFront;
+    if (l0 < -b.thrf[0]) bits |= kBack;
+    return bits;
+}
+
+// Wave-compacted append: one atomic per wave, slot = base + mbcnt(ballot).
+__device__ __forceinline__ void wave_append(bool pred, unsigned long long value, unsigned *counter,
+                                            unsigned long long *list, unsigned cap) {
+    const unsigned long long m = __ballot(pred);
+    if (m == 0ull) return;
+    const int leader = __ffsll((long long)m) - 1;
+    unsigned base = 0;
+    if (lane_id() == leader) base = atomicAdd(counter, (unsigned)__popcll(m));
+    base = __shfl(base, leader);
+    if (pred) {
+        const unsigned pos = base + mbcnt(m);
+        if (pos < cap) list[pos] = value;
+    }
+}
+
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// Outcome of one candidate of buffer k (0-based): event kind, label after the
+// update (-1: particle not in C_k, untouched).
+struct Outcome {
+    int ev;
+    int newlab;
+    bool mine;
+};
+
+__device__ __forceinline__ Outcome decide(const BufDev &b, int k, int dim, unsigned bits, int lab, float x,
+                                          float y, float z) {
+    Outcome o{kEvNone, -1, false};
+    if (!(bits & kIn)) return o;
+    const int me = k + 1;
+    o.mine = (lab == me);
+    o.newlab = lab;
+    if (b.kind == SPH_INLET) {  // Algorithm 1: labels fixed after identification
+        if (o.mine && (bits & kFront)) o.ev = kEvGen;
+    } else if (b.kind == SPH_OUTLET) {  // Algorithm 2
+        if (bits & kFront) {
+            o.ev = kEvDel;
+        } else {
+            o.newlab = (bits & kBox) ? me : (o.mine ? 0 : lab);
+        }
+    } else {  // Algorithm 3
+        if (o.mine && (bits & kFront)) {
+            o.ev = kEvGen;
+            // relabel on the recycled position r - a d (FP64, rounded to FP32)
+            const float xr = (float)((double)x - b.shift[0]);
+            const float yr = (float)((double)y - b.shift[1]);
+            const float zr = dim == 3 ? (float)((double)z - b.shift[2]) : 0.0f;
+            const unsigned b2 = classify(b, dim, xr, yr, zr);
+            if (b2 & kIn) o.newlab = (b2 & kBox) ? me : 0;
+        } else if (o.mine && (bits & kBack)) {
+            o.ev = kEvDel;
+        } else {
+            o.newlab = (bits & kBox) ? me : (o.mine ? 0 : lab);
+        }
+    }
+    return o;
+}
+
+struct EventArgs {
+    Ctl *ctl;
+    unsigned long long *gen;
+    unsigned long long *del;
+    unsigned long long *rel;
+    unsigned cap_ev;
+    unsigned cap_rel;
+};
+
+// Emit the wave's events for buffer k and accumulate its label counts.
+__device__ __forceinline__ void emit(const EventArgs &e, int k, bool valid, int64_t i, int lab, const Outcome &o,
+                                     unsigned long long &found, unsigned long long &post) {
+    const bool in = valid && o.newlab >= 0;
+    if (in && o.mine) found++;
+    if (in && o.ev != kEvDel && o.newlab == k + 1) post++;
+    wave_append(in && o.ev == kEvGen, ((unsigned long long)i << 32) | (unsigned)k, &e.ctl->n_gen, e.gen, e.cap_ev);
+    wave_append(in && o.ev == kEvDel, (unsigned long long)i << 32, &e.ctl->n_del, e.del, e.cap_ev);
+    wave_append(in && o.ev != kEvDel && o.newlab != lab, ((unsigned long long)i << 32) | (unsigned)o.newlab,
+                &e.ctl->n_rel, e.rel, e.cap_rel);
+}
+
+// --------------------------------------------------------------- K0 build --
+
+struct CountArgs {
+    const float *x, *y, *z;
+    const int64_t *n_dev;
+    int64_t capacity;
+    Grid g;
+    int32_t *count;
+    unsigned long long *keyrank;
+    unsigned long long *tile_state;
+    int64_t n_tiles;
+    Ctl *ctl;
+    unsigned epoch;
+};
+
+__global__ __launch_bounds__(kBuildBlock) void k_count(CountArgs a) {
+    const int64_t N = live_count(a.n_dev, a.capacity);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
+    const int lb = logical_block();
+    // reset the scan's tile state for this build
+    for (int64_t t = (int64_t)lb * blockDim.x + threadIdx.x; t < a.n_tiles; t += nthreads) a.tile_state[t] = 0ull;
+    if (lb == 0 && threadIdx.x == 0) {
+        a.ctl->tile_counter = 0u;
+        a.ctl->scan_fault = 0u;
+    }
+    // each logical block walks one contiguous segment
+    const int64_t per = ((N + gridDim.x - 1) / gridDim.x + blockDim.x - 1) / blockDim.x * blockDim.x;
+    const int64_t s0 = (int64_t)lb * per;
+    const int64_t s1 = min(N, s0 + per);
+    bool bad = false;
+    for (int64_t base = s0; base < s1; base += blockDim.x) {
+        const int64_t i = base + threadIdx.x;
+        const bool valid = i < s1;
+        uint32_t key = 0xffffffffu;
+        if (valid) {
+            const float x = a.x[i], y = a.y[i], z = a.g.dim == 3 ? a.z[i] : 0.0f;
+            bad |= !(isfinite(x) && isfinite(y) && isfinite(z));
+            key = cell_key(a.g, x, y, z);
+        }
+        // runs of equal keys inside the wave share one atomic
+        const uint32_t prev = __shfl_up(key, 1);
+        const bool head = !valid || lane == 0 || key != prev;
+        const unsigned long long heads = __ballot(head);
+        const unsigned long long le = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+        const int my_head = 63 - __clzll((long long)(heads & le));
+        const unsigned long long gt = heads & ~le;
+        const int next = gt ? __ffsll((long long)gt) - 1 : 64;
+        int old = 0;
+        if (valid && lane == my_head) old = atomicAdd(&a.count[key], next - my_head);
+        const int rank = __shfl(old, my_head) + (lane - my_head);
+        if (valid) a.keyrank[i] = ((unsigned long long)key << 32) | (unsigned)rank;
+    }
+    if (__ballot(bad) != 0ull && lane == 0) atomicMax(&a.ctl->nonfinite_epoch, a.epoch);
+}
+
+// Decoupled look-back scan state: bits 62..63 = flag (1 aggregate, 2 prefix),
+// low 32 bits = value.
+constexpr unsigned long long kAgg = 1ull << 62, kPre = 2ull << 62;
+
+__device__ __forceinline__ unsigned long long load_state(unsigned long long *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_state(unsigned long long *p, unsigned long long v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+struct ScanArgs {
+    int32_t *count;        // C + 1 entries (last is always 0); zeroed on the way
+    int32_t *cell_start;   // C + 1 entries
+    int64_t m;             // C + 1
+    unsigned long long *tile_state;
+    Ctl *ctl;
+};
+
+__global__ __launch_bounds__(kScanBlock) void k_scan(ScanArgs a) {
+    __shared__ unsigned s_tile;
+    __shared__ int s_wave[kScanBlock / kWave];
+    __shared__ int s_excl;
+    if (threadIdx.x == 0) s_tile = atomicAdd(&a.ctl->tile_counter, 1u);
+    __syncthreads();
+    const unsigned tile = s_tile;
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int64_t base = (int64_t)tile * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int v[kScanItems];
+    int sum = 0;
+#pragma unroll
+    for (int q = 0; q < kScanItems; ++q) {
+        const int64_t j = base + q;
+        v[q] = j < a.m ? a.count[j] : 0;
+        sum += v[q];
+    }
+#pragma unroll
+    for (int q = 0; q < kScanItems; ++q) {
+        const int64_t j = base + q;
+        if (j < a.m) a.count[j] = 0;
+    }
+    // inclusive wave scan of per-thread sums
+    int incl = sum;
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int t = __shfl_up(incl, off);
+        if (lane >= off) incl += t;
+    }
+    if (lane == kWave - 1) s_wave[wave] = incl;
+    __syncthreads();
+    int wave_off = 0, total = 0;
+    for (int w = 0; w < kScanBlock / kWave; ++w) {
+        if (w < wave) wave_off += s_wave[w];
+        total += s_wave[w];
+    }
+    // publish the tile aggregate, then look back (wave 0)
+    if (wave == 0) {
+        if (lane == 0) store_state(&a.tile_state[tile], (tile == 0 ? kPre : kAgg) | (unsigned)total);
+        int excl = 0;
+        if (tile > 0) {
+            int64_t t = (int64_t)tile - 1;
+            while (true) {
+                const int64_t tt = t - lane;
+                unsigned long long s = tt >= 0 ? load_state(&a.tile_state[tt]) : kPre;
+                unsigned spins = 0;
+                while (__ballot((s >> 62) == 0ull) != 0ull) {
+                    if ((s >> 62) == 0ull) s = load_state(&a.tile_state[tt]);
+                    if (++spins > (1u << 22)) {  // predecessors never published: give up loudly
+                        if (lane == 0) atomicOr(&a.ctl->scan_fault, 1u);
+                        s = kPre;
+                    }
+                }
+                const unsigned long long pre = __ballot((s >> 62) == 2ull);
+                const int stop = pre ? __ffsll((long long)pre) - 1 : kWave;  // nearest tile with a prefix
+                int contrib = (lane <= stop && tt >= 0) ? (int)(unsigned)(s & 0xffffffffull) : 0;
+                for (int off = 32; off > 0; off >>= 1) contrib += __shfl_xor(contrib, off);
+                excl += contrib;
+                if (pre) break;
+                t -= kWave;
+            }
+            if (lane == 0) store_state(&a.tile_state[tile], kPre | (unsigned)(excl + total));
+        }
+        if (lane == 0) s_excl = excl;
+    }
+    __syncthreads();
+    int run = s_excl + wave_off + incl - sum;
+#pragma unroll
+    for (int q = 0; q < kScanItems; ++q) {
+        const int64_t j = base + q;
+        if (j < a.m) a.cell_start[j] = run;
+        run += v[q];
+    }
+}
+
+struct ScatterArgs {
+    const int64_t *n_dev;
+    int64_t capacity;
+    const Ctl *ctl;
+    const unsigned long long *keyrank;
+    const int32_t *cell_start;
+    int32_t *cell_idx;
+};
+
+__global__ __launch_bounds__(kBuildBlock) void k_scatter(ScatterArgs a) {
+    if (a.ctl->scan_fault) return;
+    const int64_t N = live_count(a.n_dev, a.capacity);
+    const int lb = logical_block();
+    const int64_t per = ((N + gridDim.x - 1) / gridDim.x + blockDim.x - 1) / blockDim.x * blockDim.x;
+    const int64_t s0 = (int64_t)lb * per;
+    const int64_t s1 = min(N, s0 + per);
+    for (int64_t i = s0 + threadIdx.x; i < s1; i += blockDim.x) {
+        const unsigned long long kr = a.keyrank[i];
+        const uint32_t key = (uint32_t)(kr >> 32);
+        a.cell_idx[a.cell_start[key] + (int)(unsigned)(kr & 0xffffffffull)] = (int32_t)i;
+    }
+}
+
+// ------------------------------------------------------------- K1 classify --
+
+struct LocalArgs {
+    Parts p;
+    const BufDev *bufs;
+    int nb;
+    const int32_t *run_first;
+    const int32_t *run_len;
+    const uint8_t *run_buf;
+    int n_runs;
+    const int32_t *cell_start;
+    const int32_t *cell_idx;
+    EventArgs e;
+};
+
+__global__ __launch_bounds__(kClassifyBlock) void k_classify_local(LocalArgs a) {
+    __shared__ BufDev sb[SPH_MAX_BUFFERS];
+    for (int t = threadIdx.x; t < a.nb * (int)(sizeof(BufDev) / 4); t += blockDim.x)
+        reinterpret_cast<uint32_t *>(sb)[t] = reinterpret_cast<const uint32_t *>(a.bufs)[t];
+    __syncthreads();
+    if (a.e.ctl->scan_fault) return;
+    const int64_t N = live_count(a.p.n_dev, a.p.capacity);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const int wpb = blockDim.x / kWave;
+    const int dim = a.p.dim;
+    for (int r = blockIdx.x * wpb + wave; r < a.n_runs; r += gridDim.x * wpb) {
+        const int k = a.run_buf[r];
+        const BufDev &b = sb[k];
+        const int c0 = a.run_first[r];
+        const int j0 = a.cell_start[c0];
+        const int j1 = a.cell_start[c0 + a.run_len[r]];
+        unsigned long long found = 0, post = 0;
+        for (int jb = j0; jb < j1; jb += kWave) {
+            const int j = jb + lane;
+            int64_t i = j < j1 ? a.cell_idx[j] : 0;
+            const bool valid = j < j1 && i < N;  // a list older than the live count cannot index past it
+            int lab = 0;
+            Outcome o{kEvNone, -1, false};
+            if (valid) {
+                const float x = a.p.pos[0][i], y = a.p.pos[1][i], z = dim == 3 ? a.p.pos[2][i] : 0.0f;
+                const unsigned bits = classify(b, dim, x, y, z);
+                if (bits & kIn) {
+                    lab = a.p.label[i];
+                    o = decide(b, k, dim, bits, lab, x, y, z);
+                }
+            }
+            emit(a.e, k, valid, i, lab, o, found, post);
+        }
+        found = wave_sum(found);
+        post = wave_sum(post);
+        if (lane == 0 && (found | post)) {
+            atomicAdd(&a.e.ctl->found[k], found);
+            atomicAdd(&a.e.ctl->post[k], post);
+        }
+    }
+}
+
+struct FullArgs {
+    Parts p;
+    const BufDev *bufs;
+    int nb;
+    EventArgs e;
+    unsigned epoch;
+};
+
+__global__ __launch_bounds__(kClassifyBlock) void k_classify_full(FullArgs a) {
+    __shared__ BufDev sb[SPH_MAX_BUFFERS];
+    __shared__ unsigned long long s_found[SPH_MAX_BUFFERS], s_post[SPH_MAX_BUFFERS];
+    for (int t = threadIdx.x; t < a.nb * (int)(sizeof(BufDev) / 4); t += blockDim.x)
+        reinterpret_cast<uint32_t *>(sb)[t] = reinterpret_cast<const uint32_t *>(a.bufs)[t];
+    if (threadIdx.x < SPH_MAX_BUFFERS) s_found[threadIdx.x] = s_post[threadIdx.x] = 0ull;
+    __syncthreads();
+    const int64_t N = live_count(a.p.n_dev, a.p.capacity);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int dim = a.p.dim;
+    const int lb = logical_block();
+    const int64_t per = ((N + gridDim.x - 1) / gridDim.x + blockDim.x - 1) / blockDim.x * blockDim.x;
+    const int64_t s0 = (int64_t)lb * per;
+    const int64_t s1 = min(N, s0 + per);
+    bool bad = false;
+    for (int64_t base = s0; base < s1; base += blockDim.x) {
+        const int64_t i = base + threadIdx.x;
+        const bool valid = i < s1;
+        float x = 0.0f, y = 0.0f, z = 0.0f;
+        if (valid) {
+            x = a.p.pos[0][i];
+            y = a.p.pos[1][i];
+            z = dim == 3 ? a.p.pos[2][i] : 0.0f;
+            bad |= !(isfinite(x) && isfinite(y) && isfinite(z));
+        }
+        for (int k = 0; k < a.nb; ++k) {
+            const unsigned bits = valid ? classify(sb[k], dim, x, y, z) : 0u;
+            if (__ballot(bits & kIn) == 0ull) continue;
+            int lab = 0;
+            Outcome o{kEvNone, -1, false};
+            if (bits & kIn) {
+                lab = a.p.label[i];
+                o = decide(sb[k], k, dim, bits, lab, x, y, z);
+            }
+            unsigned long long found = 0, post = 0;
+            emit(a.e, k, valid, i, lab, o, found, post);
+            found = wave_sum(found);
+            post = wave_sum(post);
+            if (lane == 0 && (found | post)) {
+                atomicAdd(&s_found[k], found);
+                atomicAdd(&s_post[k], post);
+            }
+        }
+    }
+    if (__ballot(bad) != 0ull && lane == 0) atomicMax(&a.e.ctl->nonfinite_epoch, a.epoch);
+    __syncthreads();
+    if (threadIdx.x < a.nb && (s_found[threadIdx.x] | s_post[threadIdx.x])) {
+        atomicAdd(&a.e.ctl->found[threadIdx.x], s_found[threadIdx.x]);
+        atomicAdd(&a.e.ctl->post[threadIdx.x], s_post[threadIdx.x]);
+    }
+}
+
+// ------------------------------------------------------------- K2 finalize --
+
+struct FinArgs {
+    Parts p;
+    const BufDev *bufs;
+    int nb;
+    int local;
+    unsigned epoch;
+    EventArgs e;
+    float *dup;
+    int dup_stride;
+    sph_result *result;
+};
+
+__device__ void block_sort(unsigned long long *list, unsigned n, unsigned long long *s) {
+    unsigned P = 1;
+    while (P < n) P <<= 1;
+    for (unsigned j = threadIdx.x; j < P; j += blockDim.x) s[j] = j < n ? list[j] : ~0ull;
+    __syncthreads();
+    for (unsigned k = 2; k <= P; k <<= 1) {
+        for (unsigned j = k >> 1; j > 0; j >>= 1) {
+            for (unsigned t = threadIdx.x; t < P / 2; t += blockDim.x) {
+                const unsigned i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+                const unsigned l = i + j;
+                const bool asc = (i & k) == 0;
+                const unsigned long long u = s[i], w = s[l];
+                if ((u > w) == asc) {
+                    s[i] = w;
+                    s[l] = u;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (unsigned j = threadIdx.x; j < n; j += blockDim.x) list[j] = s[j];
+    __syncthreads();
+}
+
+__device__ __forceinline__ void copy_particle(const Parts &p, int64_t dst, int64_t src) {
+    for (int c = 0; c < p.dim; ++c) p.pos[c][dst] = p.pos[c][src];
+    for (int f = 0; f < p.nc; ++f) p.car[f][dst] = p.car[f][src];
+    p.label[dst] = p.label[src];
+    p.id[dst] = p.id[src];
+}
+
+__global__ __launch_bounds__(kFinBlock) void k_finalize(FinArgs a) {
+    __shared__ unsigned long long s_key[kMaxEv];
+    __shared__ unsigned s_bits[kMaxEv / 32];
+    __shared__ unsigned s_wpre[kMaxEv / 32];
+    __shared__ int32_t s_mov[kMaxEv];
+    __shared__ int s_status;
+    __shared__ unsigned s_G, s_D, s_R;
+    __shared__ long long s_N, s_next;
+    Ctl *c = a.e.ctl;
+    if (threadIdx.x == 0) {
+        const unsigned G = c->n_gen, D = c->n_del, R = c->n_rel;
+        const long long N_raw = *a.p.n_dev;
+        const long long N = live_count(a.p.n_dev, a.p.capacity);
+        const long long next = c->next_id;
+        int st = SPH_OK;
+        if (N_raw != N) st = SPH_ERR_ARG;
+        else if (a.local && c->scan_fault) st = SPH_ERR_HIP;
+        else if (c->nonfinite_epoch == a.epoch) st = SPH_ERR_NONFINITE;
+        for (int k = 0; k < a.nb && st == SPH_OK; ++k)
+            if ((long long)c->found[k] < c->n_labelled[k]) st = SPH_ERR_CFL;
+        if (st == SPH_OK && (G > a.e.cap_ev || D > a.e.cap_ev || R > a.e.cap_rel)) st = SPH_ERR_EVENTS;
+        if (st == SPH_OK && N - (long long)D + (long long)G > a.p.capacity) st = SPH_ERR_CAPACITY;
+        sph_result *r = a.result;
+        r->status = st;
+        r->n_buffers = a.nb;
+        r->n_generated = st == SPH_OK ? G : 0;
+        r->n_deleted = st == SPH_OK ? D : 0;
+        r->n_before = N;
+        r->n_after = st == SPH_OK ? N - (long long)D + (long long)G : N;
+        r->next_id = st == SPH_OK ? next + G : next;
+        for (int k = 0; k < SPH_MAX_BUFFERS; ++k) {
+            const long long post = k < a.nb ? (long long)c->post[k] : 0;
+            const long long nl = st == SPH_OK && k < a.nb ? post : c->n_labelled[k];
+            r->n_labelled[k] = nl;
+            c->n_labelled[k] = nl;
+            c->found[k] = 0ull;
+            c->post[k] = 0ull;
+        }
+        c->n_gen = c->n_del = c->n_rel = 0u;
+        if (st == SPH_OK) {
+            c->next_id = next + G;
+            *a.p.n_dev = N - (long long)D + (long long)G;
+        }
+        s_status = st;
+        s_G = G;
+        s_D = D;
+        s_R = R;
+        s_N = N;
+        s_next = next;
+    }
+    __syncthreads();
+    if (s_status != SPH_OK) return;
+    const Parts &p = a.p;
+    const unsigned G = s_G, D = s_D, R = s_R;
+    const long long N = s_N, Np = N - (long long)D;
+    const int dim = p.dim, nc = p.nc, ds = a.dup_stride;
+
+    // generated sources in ascending index order; capture, then recycle
+    block_sort(a.e.gen, G, s_key);
+    for (unsigned j = threadIdx.x; j < G; j += blockDim.x) {
+        const unsigned long long key = s_key[j];
+        const int64_t i = (int64_t)(key >> 32);
+        const BufDev &b = a.bufs[key & 0xffu];
+        for (int q = 0; q < dim; ++q) {
+            const float v = p.pos[q][i];
+            a.dup[(size_t)j * ds + q] = v;
+            p.pos[q][i] = (float)((double)v - b.shift[q]);
+        }
+        for (int f = 0; f < nc; ++f) a.dup[(size_t)j * ds + dim + f] = p.car[f][i];
+    }
+    for (unsigned r = threadIdx.x; r < R; r += blockDim.x) {
+        const unsigned long long e = a.e.rel[r];
+        p.label[(int64_t)(e >> 32)] = (int32_t)(unsigned)(e & 0xffffffffull);
+    }
+    __syncthreads();
+
+    // deleted indices ascending; holes below Np are refilled from the tail
+    block_sort(a.e.del, D, s_key);
+    const unsigned nw = (D + 31) / 32;
+    for (unsigned w = threadIdx.x; w < nw; w += blockDim.x) s_bits[w] = 0u;
+    __syncthreads();
+    for (unsigned j = threadIdx.x; j < D; j += blockDim.x) {
+        const long long idx = (long long)(s_key[j] >> 32);
+        if (idx >= Np) atomicOr(&s_bits[(idx - Np) >> 5], 1u << ((idx - Np) & 31));
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned acc = 0;
+        for (unsigned w = 0; w < nw; ++w) {
+            s_wpre[w] = acc;
+            acc += 32u - (unsigned)__popc(s_bits[w]);
+        }
+    }
+    __syncthreads();
+    for (unsigned q = threadIdx.x; q < D; q += blockDim.x) {
+        const unsigned w = q >> 5, bit = q & 31;
+        if (!(s_bits[w] >> bit & 1u)) {
+            const unsigned rank = s_wpre[w] + bit - (unsigned)__popc(s_bits[w] & ((1u << bit) - 1u));
+            s_mov[rank] = (int32_t)(Np + q);
+        }
+    }
+    __syncthreads();
+    unsigned tail_del = 0;
+    for (unsigned w = 0; w < nw; ++w) tail_del += (unsigned)__popc(s_bits[w]);
+    const unsigned h = D - tail_del;
+    for (unsigned j = threadIdx.x; j < h; j += blockDim.x)
+        copy_particle(p, (int64_t)(s_key[j] >> 32), s_mov[j]);
+    __syncthreads();
+
+    // append the duplicates: label 0, fresh ids
+    for (unsigned j = threadIdx.x; j < G; j += blockDim.x) {
+        const int64_t dst = Np + j;
+        for (int q = 0; q < dim; ++q) p.pos[q][dst] = a.dup[(size_t)j * ds + q];
+        for (int f = 0; f < nc; ++f) p.car[f][dst] = a.dup[(size_t)j * ds + dim + f];
+        p.label[dst] = 0;
+        p.id[dst] = s_next + (long long)j;
+    }
+}
+
+// ------------------------------------------------------------- identify --
+
+struct IdentArgs {
+    Parts p;
+    const BufDev *bufs;
+    int nb;
+    int which;  // 0-based buffer or -1
+    Ctl *ctl;
+};
+
+__global__ __launch_bounds__(kBuildBlock) void k_ident_check(IdentArgs a) {
+    const int64_t N = live_count(a.p.n_dev, a.p.capacity);
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+        const float x = a.p.pos[0][i], y = a.p.pos[1][i], z = a.p.dim == 3 ? a.p.pos[2][i] : 0.0f;
+        bad |= !(isfinite(x) && isfinite(y) && isfinite(z));
+    }
+    if (__ballot(bad) != 0ull && (threadIdx.x & 63) == 0) atomicOr(&a.ctl->ident_bad, 1u);
+}
+
+__global__ __launch_bounds__(kBuildBlock) void k_ident_apply(IdentArgs a) {
+    __shared__ unsigned long long s_cnt[SPH_MAX_BUFFERS];
+    if (threadIdx.x < SPH_MAX_BUFFERS) s_cnt[threadIdx.x] = 0ull;
+    __syncthreads();
+    if (a.ctl->ident_bad) return;
+    const int64_t N = live_count(a.p.n_dev, a.p.capacity);
+    const int dim = a.p.dim;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t iters = (N + stride - 1) / stride;
+    for (int64_t it = 0; it < iters; ++it) {
+        const int64_t i = it * stride + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        const bool valid = i < N;
+        int lab = -1;
+        if (valid) {
+            lab = a.p.label[i];
+            const float x = a.p.pos[0][i], y = a.p.pos[1][i], z = dim == 3 ? a.p.pos[2][i] : 0.0f;
+            for (int k = 0; k < a.nb; ++k) {
+                if (a.which >= 0 && a.which != k) continue;
+                const unsigned bits = classify(a.bufs[k], dim, x, y, z);
+                if (bits & kBox) lab = k + 1;
+            }
+            a.p.label[i] = lab;
+        }
+        for (int k = 0; k < a.nb; ++k) {
+            const unsigned long long n = (unsigned long long)__popcll(__ballot(valid && lab == k + 1));
+            if ((threadIdx.x & 63) == 0 && n) atomicAdd(&s_cnt[k], n);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < a.nb && s_cnt[threadIdx.x]) atomicAdd(&a.ctl->ident_count[threadIdx.x], s_cnt[threadIdx.x]);
+}
+
+__global__ void k_ident_commit(IdentArgs a) {
+    if (threadIdx.x == 0 && !a.ctl->ident_bad)
+        for (int k = 0; k < a.nb; ++k) a.ctl->n_labelled[k] = (long long)a.ctl->ident_count[k];
+}
+
+}  // namespace
+
+// ====================================================================== host ==
+
+struct sph_ctx {
+    int dim = 2;
+    double lo[3] = {0, 0, 0};
+    double cs = 0, dp = 0;
+    int32_t dims[3] = {1, 1, 1};
+    int64_t n_cells = 0;
+    int64_t capacity = 0;
+    unsigned max_events = 0;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int build_blocks = 0;
+    int full_blocks = 0;
+    unsigned epoch = 0;          // incremented per build / full scan
+    bool built = false;          // a build is pending for the next local update
+    int64_t built_capacity = 0;
+
+    int nb = 0;
+    BufDev hb[SPH_MAX_BUFFERS];
+    double b_origin[SPH_MAX_BUFFERS][3], b_rot[SPH_MAX_BUFFERS][9], b_half[SPH_MAX_BUFFERS][3],
+        b_margin[SPH_MAX_BUFFERS];
+    std::vector<int32_t> h_run_first, h_run_len;
+    std::vector<uint8_t> h_run_buf;
+
+    BufDev *d_bufs = nullptr;
+    int32_t *d_run_first = nullptr, *d_run_len = nullptr;
+    uint8_t *d_run_buf = nullptr;
+    int n_runs = 0;
+
+    int32_t *d_count = nullptr, *d_cell_start = nullptr, *d_cell_idx = nullptr;
+    unsigned long long *d_keyrank = nullptr, *d_tile_state = nullptr;
+    int64_t n_tiles = 0;
+
+    unsigned long long *d_gen = nullptr, *d_del = nullptr, *d_rel = nullptr;
+    float *d_dup = nullptr;
+    Ctl *d_ctl = nullptr;
+    sph_result *d_result = nullptr;
+    sph_result *h_result = nullptr;  // pinned
+    bool any_update = false;
+};
+
+namespace {
+
+#define HIP_TRY(expr)                               \
+    do {                                            \
+        if ((expr) != hipSuccess) return SPH_ERR_HIP; \
+    } while (0)
+
+sph_status parts_of(const sph_ctx *ctx, const sph_particles *p, Parts &out) {
+    if (!p || !p->pos[0] || !p->pos[1] || (ctx->dim == 3 && !p->pos[2]) || !p->label || !p->id || !p->n_dev)
+        return SPH_ERR_ARG;
+    if (p->n_carried < 0 || p->n_carried > SPH_MAX_CARRIED) return SPH_ERR_ARG;
+    if (p->capacity <= 0 || p->capacity > ctx->capacity) return SPH_ERR_ARG;
+    for (int f = 0; f < p->n_carried; ++f)
+        if (!p->carried[f]) return SPH_ERR_ARG;
+    std::memset(&out, 0, sizeof(out));
+    for (int c = 0; c < 3; ++c) out.pos[c] = p->pos[c];
+    if (ctx->dim == 2) out.pos[2] = nullptr;
+    for (int f = 0; f < p->n_carried; ++f) out.car[f] = p->carried[f];
+    out.nc = p->n_carried;
+    out.dim = ctx->dim;
+    out.label = p->label;
+    out.id = p->id;
+    out.n_dev = p->n_dev;
+    out.capacity = p->capacity;
+    return SPH_OK;
+}
+
+Grid grid_of(const sph_ctx *ctx) {
+    Grid g{};
+    for (int c = 0; c < 3; ++c) {
+        g.lo[c] = (float)ctx->lo[c];
+        g.dims[c] = ctx->dims[c];
+    }
+    g.inv_cs = (float)(1.0 / ctx->cs);
+    g.dim = ctx->dim;
+    return g;
+}
+
+EventArgs events_of(const sph_ctx *ctx) {
+    EventArgs e{};
+    e.ctl = ctx->d_ctl;
+    e.gen = ctx->d_gen;
+    e.del = ctx->d_del;
+    e.rel = ctx->d_rel;
+    e.cap_ev = ctx->max_events;
+    e.cap_rel = ctx->max_events * kRelPerEvent;
+    return e;
+}
+
+sph_status launch_finalize(sph_ctx *ctx, const Parts &pp, bool local) {
+    FinArgs f{};
+    f.p = pp;
+    f.local = local ? 1 : 0;
+    f.bufs = ctx->d_bufs;
+    f.nb = ctx->nb;
+    f.epoch = ctx->epoch;
+    f.e = events_of(ctx);
+    f.dup = ctx->d_dup;
+    f.dup_stride = 3 + SPH_MAX_CARRIED;
+    f.result = ctx->d_result;
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinBlock), 0, ctx->stream, f);
+    HIP_TRY(hipGetLastError());
+    ctx->any_update = true;
+    return SPH_OK;
+}
+
+sph_status wait_result(sph_ctx *ctx) {
+    HIP_TRY(hipMemcpyAsync(ctx->h_result, ctx->d_result, sizeof(sph_result), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return SPH_OK;
+}
+
+void free_ctx(sph_ctx *c) {
+    if (!c) return;
+    (void)hipFree(c->d_bufs);
+    (void)hipFree(c->d_run_first);
+    (void)hipFree(c->d_run_len);
+    (void)hipFree(c->d_run_buf);
+    (void)hipFree(c->d_count);
+    (void)hipFree(c->d_cell_start);
+    (void)hipFree(c->d_cell_idx);
+    (void)hipFree(c->d_keyrank);
+    (void)hipFree(c->d_tile_state);
+    (void)hipFree(c->d_gen);
+    (void)hipFree(c->d_del);
+    (void)hipFree(c->d_rel);
+    (void)hipFree(c->d_dup);
+    (void)hipFree(c->d_ctl);
+    (void)hipFree(c->d_result);
+    if (c->h_result) (void)hipHostFree(c->h_result);
+    delete c;
+}
+
+}  // namespace
+
+extern "C" sph_status sph_create(const sph_config *cfg, sph_ctx **out) {
+    if (!out) return SPH_ERR_ARG;
+    *out = nullptr;
+    if (!cfg || (cfg->dim != 2 && cfg->dim != 3)) return SPH_ERR_ARG;
+    if (!(cfg->cell_size > 0.0) || !std::isfinite(cfg->cell_size) || !(cfg->dp > 0.0)) return SPH_ERR_ARG;
+    if (cfg->capacity <= 0 || cfg->capacity >= (int64_t(1) << 31)) return SPH_ERR_ARG;
+    if (cfg->max_events < 1 || cfg->max_events > SPH_MAX_EVENTS_LIMIT) return SPH_ERR_ARG;
+    int32_t dims[3] = {1, 1, 1};
+    double cells = 1.0;
+    for (int c = 0; c < cfg->dim; ++c) {
+        if (!std::isfinite(cfg->lo[c]) || !std::isfinite(cfg->hi[c]) || !(cfg->hi[c] > cfg->lo[c])) return SPH_ERR_ARG;
+        const double n = std::ceil((cfg->hi[c] - cfg->lo[c]) / cfg->cell_size);
+        if (n > (double)(1 << 24)) return SPH_ERR_ARG;
+        dims[c] = (int32_t)std::max(1.0, n);
+        cells *= dims[c];
+    }
+    if (cells >= 2147483000.0) return SPH_ERR_ARG;
+
+    sph_ctx *c = new (std::nothrow) sph_ctx();
+    if (!c) return SPH_ERR_HIP;
+    c->dim = cfg->dim;
+    for (int q = 0; q < 3; ++q) {
+        c->lo[q] = q < cfg->dim ? cfg->lo[q] : 0.0;
+        c->dims[q] = dims[q];
+    }
+    c->cs = cfg->cell_size;
+    c->dp = cfg->dp;
+    c->n_cells = (int64_t)cells;
+    c->capacity = cfg->capacity;
+    c->max_events = (unsigned)cfg->max_events;
+    c->stream = (hipStream_t)cfg->stream;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return SPH_ERR_HIP;
+    }
+    // grid sizes: a multiple of 8 blocks (XCD renumbering), enough to fill 256 CUs
+    const int64_t want = (cfg->capacity + kBuildBlock - 1) / kBuildBlock;
+    c->build_blocks = (int)std::max<int64_t>(8, std::min<int64_t>(8192, (want + 7) / 8 * 8));
+    c->full_blocks = c->build_blocks;
+    const int64_t m = c->n_cells + 1;
+    c->n_tiles = (m + kScanTile - 1) / kScanTile;
+    const size_t ev = c->max_events;
+    bool ok = hipMalloc(&c->d_bufs, sizeof(BufDev) * SPH_MAX_BUFFERS) == hipSuccess &&
+              hipMalloc(&c->d_count, sizeof(int32_t) * m) == hipSuccess &&
+              hipMalloc(&c->d_cell_start, sizeof(int32_t) * m) == hipSuccess &&
+              hipMalloc(&c->d_cell_idx, sizeof(int32_t) * c->capacity) == hipSuccess &&
+              hipMalloc(&c->d_keyrank, sizeof(unsigned long long) * c->capacity) == hipSuccess &&
+              hipMalloc(&c->d_tile_state, sizeof(unsigned long long) * c->n_tiles) == hipSuccess &&
+              hipMalloc(&c->d_gen, sizeof(unsigned long long) * ev) == hipSuccess &&
+              hipMalloc(&c->d_del, sizeof(unsigned long long) * ev) == hipSuccess &&
+              hipMalloc(&c->d_rel, sizeof(unsigned long long) * ev * kRelPerEvent) == hipSuccess &&
+              hipMalloc(&c->d_dup, sizeof(float) * ev * (3 + SPH_MAX_CARRIED)) == hipSuccess &&
+              hipMalloc(&c->d_ctl, sizeof(Ctl)) == hipSuccess &&
+              hipMalloc(&c->d_result, sizeof(sph_result)) == hipSuccess &&
+              hipHostMalloc(&c->h_result, sizeof(sph_result), hipHostMallocDefault) == hipSuccess;
+    if (ok) {
+        Ctl init{};
+        init.next_id = cfg->next_id;
+        init.nonfinite_epoch = 0;
+        sph_result r0{};
+        ok = hipMemsetAsync(c->d_count, 0, sizeof(int32_t) * m, c->stream) == hipSuccess &&
+             hipMemsetAsync(c->d_cell_start, 0, sizeof(int32_t) * m, c->stream) == hipSuccess &&
+             hipMemsetAsync(c->d_tile_state, 0, sizeof(unsigned long long) * c->n_tiles, c->stream) == hipSuccess &&
+             hipMemcpyAsync(c->d_ctl, &init, sizeof(Ctl), hipMemcpyHostToDevice, c->stream) == hipSuccess &&
+             hipMemcpyAsync(c->d_result, &r0, sizeof(r0), hipMemcpyHostToDevice, c->stream) == hipSuccess &&
+             hipStreamSynchronize(c->stream) == hipSuccess;
+    }
+    if (!ok) {
+        free_ctx(c);
+        return SPH_ERR_HIP;
+    }
+    c->epoch = 1;
+    *out = c;
+    return SPH_OK;
+}
+
+extern "C" sph_status sph_destroy(sph_ctx *ctx) {
+    if (!ctx) return SPH_ERR_ARG;
+    (void)hipStreamSynchronize(ctx->stream);
+    free_ctx(ctx);
+    return SPH_OK;
+}
+
+extern "C" sph_status sph_buffer_define(sph_ctx *ctx, sph_kind kind, const double origin[3], const double rot[9],
+                                        const double half[3], double margin, int32_t *buffer_id) {
+    if (!ctx || !origin || !rot || !half) return SPH_ERR_ARG;
+    if (kind != SPH_INLET && kind != SPH_OUTLET && kind != SPH_BIDIR) return SPH_ERR_ARG;
+    const int dim = ctx->dim;
+    double o[3] = {origin[0], origin[1], dim == 3 ? origin[2] : 0.0};
+    double h[3] = {half[0], half[1], dim == 3 ? half[2] : 0.0};
+    for (int c = 0; c < dim; ++c)
+        if (!std::isfinite(o[c]) || !std::isfinite(h[c]) || !(h[c] > 0.0)) return SPH_ERR_ARG;
+    if (!std::isfinite(margin)) return SPH_ERR_ARG;
+    if (!(margin > 0.0)) margin = ctx->cs;
+    const sph_status rs = sph_check_rotation(dim, rot);
+    if (rs != SPH_OK) return rs;
+    if (ctx->nb >= SPH_MAX_BUFFERS) return SPH_ERR_TOO_MANY_BUFFERS;
+    double q[9];
+    std::copy(rot, rot + 9, q);
+    if (dim == 2) {
+        q[2] = q[5] = q[6] = q[7] = 0.0;
+        q[8] = 1.0;
+    }
+    for (int k = 0; k < ctx->nb; ++k)
+        if (sphbuf::check_regions_overlap(dim, o, q, h, margin, ctx->b_origin[k], ctx->b_rot[k], ctx->b_half[k],
+                                          ctx->b_margin[k]))
+            return SPH_ERR_OVERLAP;
+    std::vector<int32_t> first, len;
+    const sph_status cs = sphbuf::grid_cover(dim, ctx->lo, ctx->cs, ctx->dims, o, q, h, margin, first, len);
+    if (cs != SPH_OK) return cs;
+
+    const int k = ctx->nb;
+    BufDev b{};
+    for (int i = 0; i < 9; ++i) {
+        b.q[i] = q[i];
+        b.qf[i] = (float)q[i];
+    }
+    for (int c = 0; c < 3; ++c) {
+        b.o[c] = o[c];
+        b.ohi[c] = (float)o[c];
+        b.olo[c] = (float)(o[c] - (double)b.ohi[c]);
+        b.thr[c] = h[c];
+        b.thr[3 + c] = h[c] + margin;
+        b.thrf[c] = (float)b.thr[c];
+        b.thrf[3 + c] = (float)b.thr[3 + c];
+    }
+    const double a = 2.0 * h[0];
+    for (int c = 0; c < 3; ++c) b.shift[c] = c < dim ? a * q[c] : 0.0;
+    b.guard = (float)sphbuf::guard_band(dim, o, h, margin, ctx->cs, ctx->dp);
+    const double R = sphbuf::sphere_radius(dim, h, margin);
+    b.rsq = (float)(R * R);
+    b.kind = (int32_t)kind;
+
+    // rebuild the device run list with the new buffer's runs appended
+    std::vector<int32_t> rf = ctx->h_run_first, rl = ctx->h_run_len;
+    std::vector<uint8_t> rb = ctx->h_run_buf;
+    rf.insert(rf.end(), first.begin(), first.end());
+    rl.insert(rl.end(), len.begin(), len.end());
+    rb.insert(rb.end(), first.size(), (uint8_t)k);
+    int32_t *nf = nullptr, *nl = nullptr;
+    uint8_t *nbuf = nullptr;
+    const size_t nr = rf.size();
+    if (nr > 0) {
+        if (hipMalloc(&nf, sizeof(int32_t) * nr) != hipSuccess || hipMalloc(&nl, sizeof(int32_t) * nr) != hipSuccess ||
+            hipMalloc(&nbuf, nr) != hipSuccess) {
+            (void)hipFree(nf);
+            (void)hipFree(nl);
+            (void)hipFree(nbuf);
+            return SPH_ERR_HIP;
+        }
+        if (hipMemcpyAsync(nf, rf.data(), sizeof(int32_t) * nr, hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
+            hipMemcpyAsync(nl, rl.data(), sizeof(int32_t) * nr, hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
+            hipMemcpyAsync(nbuf, rb.data(), nr, hipMemcpyHostToDevice, ctx->stream) != hipSuccess)
+            return SPH_ERR_HIP;
+    }
+    ctx->hb[k] = b;
+    HIP_TRY(hipMemcpyAsync(ctx->d_bufs + k, &ctx->hb[k], sizeof(BufDev), hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    (void)hipFree(ctx->d_run_first);
+    (void)hipFree(ctx->d_run_len);
+    (void)hipFree(ctx->d_run_buf);
+    ctx->d_run_first = nf;
+    ctx->d_run_len = nl;
+    ctx->d_run_buf = nbuf;
+    ctx->n_runs = (int)nr;
+    ctx->h_run_first.swap(rf);
+    ctx->h_run_len.swap(rl);
+    ctx->h_run_buf.swap(rb);
+    for (int c = 0; c < 3; ++c) {
+        ctx->b_origin[k][c] = o[c];
+        ctx->b_half[k][c] = h[c];
+    }
+    std::copy(q, q + 9, ctx->b_rot[k]);
+    ctx->b_margin[k] = margin;
+    ctx->nb = k + 1;
+    if (buffer_id) *buffer_id = k + 1;
+    return SPH_OK;
+}
+
+extern "C" sph_status sph_celllist_build(sph_ctx *ctx, const sph_particles *p) {
+    if (!ctx) return SPH_ERR_ARG;
+    Parts pp;
+    const sph_status st = parts_of(ctx, p, pp);
+    if (st != SPH_OK) return st;
+    ctx->epoch++;
+    CountArgs ca{};
+    ca.x = pp.pos[0];
+    ca.y = pp.pos[1];
+    ca.z = pp.pos[2];
+    ca.n_dev = pp.n_dev;
+    ca.capacity = pp.capacity;
+    ca.g = grid_of(ctx);
+    ca.count = ctx->d_count;
+    ca.keyrank = ctx->d_keyrank;
+    ca.tile_state = ctx->d_tile_state;
+    ca.n_tiles = ctx->n_tiles;
+    ca.ctl = ctx->d_ctl;
+    ca.epoch = ctx->epoch;
+    hipLaunchKernelGGL(k_count, dim3(ctx->build_blocks), dim3(kBuildBlock), 0, ctx->stream, ca);
+    HIP_TRY(hipGetLastError());
+    ScanArgs sa{};
+    sa.count = ctx->d_count;
+    sa.cell_start = ctx->d_cell_start;
+    sa.m = ctx->n_cells + 1;
+    sa.tile_state = ctx->d_tile_state;
+    sa.ctl = ctx->d_ctl;
+    hipLaunchKernelGGL(k_scan, dim3((unsigned)ctx->n_tiles), dim3(kScanBlock), 0, ctx->stream, sa);
+    HIP_TRY(hipGetLastError());
+    ScatterArgs xa{};
+    xa.n_dev = pp.n_dev;
+    xa.capacity = pp.capacity;
+    xa.ctl = ctx->d_ctl;
+    xa.keyrank = ctx->d_keyrank;
+    xa.cell_start = ctx->d_cell_start;
+    xa.cell_idx = ctx->d_cell_idx;
+    hipLaunchKernelGGL(k_scatter, dim3(ctx->build_blocks), dim3(kBuildBlock), 0, ctx->stream, xa);
+    HIP_TRY(hipGetLastError());
+    ctx->built = true;
+    return SPH_OK;
+}
+
+extern "C" sph_status sph_buffer_update_async(sph_ctx *ctx, sph_particles *p) {
+    if (!ctx) return SPH_ERR_ARG;
+    if (!ctx->built) return SPH_ERR_STATE;
+    Parts pp;
+    const sph_status st = parts_of(ctx, p, pp);
+    if (st != SPH_OK) return st;
+    if (ctx->n_runs > 0) {
+        LocalArgs la{};
+        la.p = pp;
+        la.bufs = ctx->d_bufs;
+        la.nb = ctx->nb;
+        la.run_first = ctx->d_run_first;
+        la.run_len = ctx->d_run_len;
+        la.run_buf = ctx->d_run_buf;
+        la.n_runs = ctx->n_runs;
+        la.cell_start = ctx->d_cell_start;
+        la.cell_idx = ctx->d_cell_idx;
+        la.e = events_of(ctx);
+        const int wpb = kClassifyBlock / kWave;
+        const int blocks = std::max(1, std::min(65535, (ctx->n_runs + wpb - 1) / wpb));
+        hipLaunchKernelGGL(k_classify_local, dim3(blocks), dim3(kClassifyBlock), 0, ctx->stream, la);
+        HIP_TRY(hipGetLastError());
+    }
+    ctx->built = false;
+    return launch_finalize(ctx, pp, true);
+}
+
+static sph_status fullscan_enqueue(sph_ctx *ctx, sph_particles *p) {
+    if (!ctx) return SPH_ERR_ARG;
+    Parts pp;
+    const sph_status st = parts_of(ctx, p, pp);
+    if (st != SPH_OK) return st;
+    ctx->epoch++;
+    FullArgs fa{};
+    fa.p = pp;
+    fa.bufs = ctx->d_bufs;
+    fa.nb = ctx->nb;
+    fa.e = events_of(ctx);
+    fa.epoch = ctx->epoch;
+    hipLaunchKernelGGL(k_classify_full, dim3(ctx->full_blocks), dim3(kClassifyBlock), 0, ctx->stream, fa);
+    HIP_TRY(hipGetLastError());
+    ctx->built = false;
+    return launch_finalize(ctx, pp, false);
+}
+
+extern "C" sph_status sph_buffer_update_fullscan_async(sph_ctx *ctx, sph_particles *p) {
+    return fullscan_enqueue(ctx, p);
+}
+
+static sph_status finish_sync(sph_ctx *ctx, int64_t *n_generated, int64_t *n_deleted) {
+    const sph_status w = wait_result(ctx);
+    if (w != SPH_OK) return w;
+    if (n_generated) *n_generated = ctx->h_result->n_generated;
+    if (n_deleted) *n_deleted = ctx->h_result->n_deleted;
+    return (sph_status)ctx->h_result->status;
+}
+
+extern "C" sph_status sph_buffer_update(sph_ctx *ctx, sph_particles *p, int64_t *n_generated, int64_t *n_deleted) {
+    const sph_status st = sph_buffer_update_async(ctx, p);
+    if (st != SPH_OK) return st;
+    return finish_sync(ctx, n_generated, n_deleted);
+}
+
+extern "C" sph_status sph_buffer_update_fullscan(sph_ctx *ctx, sph_particles *p, int64_t *n_generated,
+                                                 int64_t *n_deleted) {
+    const sph_status st = fullscan_enqueue(ctx, p);
+    if (st != SPH_OK) return st;
+    return finish_sync(ctx, n_generated, n_deleted);
+}
+
+extern "C" sph_status sph_last_result(sph_ctx *ctx, sph_result *out) {
+    if (!ctx || !out) return SPH_ERR_ARG;
+    const sph_status w = wait_result(ctx);
+    if (w != SPH_OK) return w;
+    *out = *ctx->h_result;
+    return SPH_OK;
+}
+
+extern "C" sph_status sph_last_events(sph_ctx *ctx, int64_t *gen_src, int64_t *del_idx, int64_t cap, int64_t *n_gen,
+                                      int64_t *n_del) {
+    if (!ctx || !n_gen || !n_del || cap < 0) return SPH_ERR_ARG;
+    const sph_status w = wait_result(ctx);
+    if (w != SPH_OK) return w;
+    const sph_result r = *ctx->h_result;
+    *n_gen = r.status == SPH_OK ? r.n_generated : 0;
+    *n_del = r.status == SPH_OK ? r.n_deleted : 0;
+    const int64_t g = std::min<int64_t>(cap, *n_gen), d = std::min<int64_t>(cap, *n_del);
+    std::vector<unsigned long long> tmp((size_t)std::max<int64_t>(1, std::max(g, d)));
+    if (g > 0) {
+        if (!gen_src) return SPH_ERR_ARG;
+        HIP_TRY(hipMemcpy(tmp.data(), ctx->d_gen, sizeof(unsigned long long) * g, hipMemcpyDeviceToHost));
+        for (int64_t j = 0; j < g; ++j) gen_src[j] = (int64_t)(tmp[j] >> 32);
+    }
+    if (d > 0) {
+        if (!del_idx) return SPH_ERR_ARG;
+        HIP_TRY(hipMemcpy(tmp.data(), ctx->d_del, sizeof(unsigned long long) * d, hipMemcpyDeviceToHost));
+        for (int64_t j = 0; j < d; ++j) del_idx[j] = (int64_t)(tmp[j] >> 32);
+    }
+    return SPH_OK;
+}
+
+extern "C" sph_status sph_celllist_view(sph_ctx *ctx, const int32_t **cell_start, const int32_t **cell_idx,
+                                        int64_t *n_cells, int32_t dims[3]) {
+    if (!ctx) return SPH_ERR_ARG;
+    if (cell_start) *cell_start = ctx->d_cell_start;
+    if (cell_idx) *cell_idx = ctx->d_cell_idx;
+    if (n_cells) *n_cells = ctx->n_cells;
+    if (dims)
+        for (int c = 0; c < 3; ++c) dims[c] = ctx->dims[c];
+    return SPH_OK;
+}
+
+extern "C" sph_status sph_buffer_identify(sph_ctx *ctx, sph_particles *p, int32_t buffer_id) {
+    if (!ctx) return SPH_ERR_ARG;
+    if (buffer_id != -1 && (buffer_id < 1 || buffer_id > ctx->nb)) return SPH_ERR_ARG;
+    Parts pp;
+    const sph_status st = parts_of(ctx, p, pp);
+    if (st != SPH_OK) return st;
+    HIP_TRY(hipMemsetAsync(&ctx->d_ctl->ident_bad, 0, sizeof(unsigned), ctx->stream));
+    HIP_TRY(hipMemsetAsync(ctx->d_ctl->ident_count, 0, sizeof(unsigned long long) * 16, ctx->stream));
+    IdentArgs ia{};
+    ia.p = pp;
+    ia.bufs = ctx->d_bufs;
+    ia.nb = ctx->nb;
+    ia.which = buffer_id < 0 ? -1 : buffer_id - 1;
+    ia.ctl = ctx->d_ctl;
+    hipLaunchKernelGGL(k_ident_check, dim3(ctx->build_blocks), dim3(kBuildBlock), 0, ctx->stream, ia);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_ident_apply, dim3(ctx->build_blocks), dim3(kBuildBlock), 0, ctx->stream, ia);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_ident_commit, dim3(1), dim3(64), 0, ctx->stream, ia);
+    HIP_TRY(hipGetLastError());
+    unsigned bad = 0;
+    HIP_TRY(hipMemcpyAsync(&bad, &ctx->d_ctl->ident_bad, sizeof(unsigned), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return bad ? SPH_ERR_NONFINITE : SPH_OK;
+}
+
+extern "C" sph_status sph_state_get(sph_ctx *ctx, int64_t *next_id, int64_t n_labelled[SPH_MAX_BUFFERS]) {
+    if (!ctx) return SPH_ERR_ARG;
+    Ctl h{};
+    HIP_TRY(hipMemcpyAsync(&h, ctx->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    if (next_id) *next_id = h.next_id;
+    if (n_labelled)
+        for (int k = 0; k < SPH_MAX_BUFFERS; ++k) n_labelled[k] = h.n_labelled[k];
+    return SPH_OK;
+}
+
+extern "C" sph_status sph_state_set(sph_ctx *ctx, int64_t next_id, const int64_t n_labelled[SPH_MAX_BUFFERS]) {
+    if (!ctx) return SPH_ERR_ARG;
+    HIP_TRY(hipMemcpyAsync(&ctx->d_ctl->next_id, &next_id, sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
+    if (n_labelled)
+        HIP_TRY(hipMemcpyAsync(ctx->d_ctl->n_labelled, n_labelled, sizeof(int64_t) * SPH_MAX_BUFFERS,
+                               hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return SPH_OK;
+}

@@ -1,0 +1,37 @@
+// Internal declarations shared by the host geometry and the HIP translation unit.
+#pragma once
+#include <cstdint>
+#include <vector>
+
+#include "sphbuf.h"
+
+namespace sphbuf {
+
+struct Obb;
+
+sph_status grid_cover(int dim, const double glo[3], double cs, const int32_t dims[3], const double origin[3],
+                      const double rot[9], const double half[3], double margin, std::vector<int32_t> &first,
+                      std::vector<int32_t> &len);
+double guard_band(int dim, const double origin[3], const double half[3], double margin, double cs, double dp);
+double sphere_radius(int dim, const double half[3], double margin);
+bool check_regions_overlap(int dim, const double o1[3], const double r1[9], const double h1[3], double m1,
+                           const double o2[3], const double r2[9], const double h2[3], double m2);
+
+// Per-buffer record read by the kernels.  FP32 members drive the bulk test; the
+// FP64 members reproduce the exact FP64 decision inside the guard band.
+struct BufDev {
+    float qf[9];      // rotation, FP32
+    float ohi[3];     // origin, FP32 high part
+    float olo[3];     // origin, FP32 low part (origin - ohi)
+    float thrf[6];    // FP32 thresholds: a/2, b/2, c/2, a/2 + d, b/2 + d, c/2 + d
+    float guard;      // FP32 guard band
+    float rsq;        // squared radius of a sphere around O' holding the check region
+    int32_t kind;     // SPH_INLET / SPH_OUTLET / SPH_BIDIR
+    int32_t pad_[3];
+    double q[9];      // rotation, FP64
+    double o[3];      // origin, FP64
+    double thr[6];    // FP64 thresholds, same order as thrf
+    double shift[3];  // recycle shift a d = (2 * a/2) * q[0..2], FP64
+};
+
+}  // namespace sphbuf

@@ -1,0 +1,299 @@
+"""ctypes binding of ``libsphbuf.so`` (declared in ``include/sphbuf.h``).
+
+Argument marshalling only: every function keeps the C name and forwards to the
+library, which runs every step of the buffer update in its own HIP kernels.
+PyTorch supplies device memory (``tensor.data_ptr()``) and the stream.  There is
+no fallback: if the shared library is missing, loading it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsphbuf.so")
+
+SPH_OK, SPH_ERR_ARG, SPH_ERR_ROTATION, SPH_ERR_OVERLAP, SPH_ERR_CAPACITY = 0, 1, 2, 3, 4
+SPH_ERR_CFL, SPH_ERR_NONFINITE, SPH_ERR_TOO_MANY_BUFFERS, SPH_ERR_EVENTS = 5, 6, 7, 8
+SPH_ERR_HIP, SPH_ERR_STATE = 9, 10
+SPH_INLET, SPH_OUTLET, SPH_BIDIR = 1, 2, 3
+SPH_MAX_BUFFERS = 15
+SPH_MAX_CARRIED = 16
+SPH_MAX_EVENTS_LIMIT = 8192
+
+EXPORTED = (
+    "sph_create", "sph_destroy", "sph_buffer_define", "sph_celllist_build", "sph_buffer_identify",
+    "sph_buffer_update", "sph_buffer_update_async", "sph_buffer_update_fullscan",
+    "sph_buffer_update_fullscan_async", "sph_last_result", "sph_last_events", "sph_celllist_view",
+    "sph_state_get", "sph_state_set", "sph_rotation_2d", "sph_rotation_axis_angle",
+    "sph_rotation_from_direction", "sph_check_rotation", "sph_grid_cover", "sph_guard_band",
+    "sph_status_str",
+)
+
+
+class sph_particles(ctypes.Structure):
+    _fields_ = [
+        ("pos", ctypes.c_void_p * 3),
+        ("carried", ctypes.c_void_p * SPH_MAX_CARRIED),
+        ("n_carried", ctypes.c_int32),
+        ("pad_", ctypes.c_int32),
+        ("label", ctypes.c_void_p),
+        ("id", ctypes.c_void_p),
+        ("n_dev", ctypes.c_void_p),
+        ("capacity", ctypes.c_int64),
+    ]
+
+
+class sph_config(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int32),
+        ("pad_", ctypes.c_int32),
+        ("lo", ctypes.c_double * 3),
+        ("hi", ctypes.c_double * 3),
+        ("cell_size", ctypes.c_double),
+        ("dp", ctypes.c_double),
+        ("capacity", ctypes.c_int64),
+        ("max_events", ctypes.c_int64),
+        ("next_id", ctypes.c_int64),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class sph_result(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32),
+        ("n_buffers", ctypes.c_int32),
+        ("n_generated", ctypes.c_int64),
+        ("n_deleted", ctypes.c_int64),
+        ("n_before", ctypes.c_int64),
+        ("n_after", ctypes.c_int64),
+        ("next_id", ctypes.c_int64),
+        ("n_labelled", ctypes.c_int64 * SPH_MAX_BUFFERS),
+    ]
+
+
+class SphError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = int(status)
+        super().__init__(f"{what}: {sph_status_str(status)} (status {status})")
+
+
+_lib = None
+_D = ctypes.POINTER(ctypes.c_double)
+_I64 = ctypes.POINTER(ctypes.c_int64)
+_I32 = ctypes.POINTER(ctypes.c_int32)
+_VP = ctypes.c_void_p
+
+
+def lib() -> ctypes.CDLL:
+    """Load the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        sig = {
+            "sph_create": ([ctypes.POINTER(sph_config), ctypes.POINTER(_VP)], ctypes.c_int),
+            "sph_destroy": ([_VP], ctypes.c_int),
+            "sph_buffer_define": ([_VP, ctypes.c_int, _D, _D, _D, ctypes.c_double, _I32], ctypes.c_int),
+            "sph_celllist_build": ([_VP, ctypes.POINTER(sph_particles)], ctypes.c_int),
+            "sph_buffer_identify": ([_VP, ctypes.POINTER(sph_particles), ctypes.c_int32], ctypes.c_int),
+            "sph_buffer_update": ([_VP, ctypes.POINTER(sph_particles), _I64, _I64], ctypes.c_int),
+            "sph_buffer_update_async": ([_VP, ctypes.POINTER(sph_particles)], ctypes.c_int),
+            "sph_buffer_update_fullscan": ([_VP, ctypes.POINTER(sph_particles), _I64, _I64], ctypes.c_int),
+            "sph_buffer_update_fullscan_async": ([_VP, ctypes.POINTER(sph_particles)], ctypes.c_int),
+            "sph_last_result": ([_VP, ctypes.POINTER(sph_result)], ctypes.c_int),
+            "sph_last_events": ([_VP, _I64, _I64, ctypes.c_int64, _I64, _I64], ctypes.c_int),
+            "sph_celllist_view": ([_VP, ctypes.POINTER(_VP), ctypes.POINTER(_VP), _I64, _I32], ctypes.c_int),
+            "sph_state_get": ([_VP, _I64, _I64], ctypes.c_int),
+            "sph_state_set": ([_VP, ctypes.c_int64, _I64], ctypes.c_int),
+            "sph_rotation_2d": ([ctypes.c_double, _D], ctypes.c_int),
+            "sph_rotation_axis_angle": ([_D, ctypes.c_double, _D], ctypes.c_int),
+            "sph_rotation_from_direction": ([_D, _D], ctypes.c_int),
+            "sph_check_rotation": ([ctypes.c_int32, _D], ctypes.c_int),
+            "sph_grid_cover": ([ctypes.c_int32, _D, ctypes.c_double, _I32, _D, _D, _D, ctypes.c_double, _I32, _I32,
+                                ctypes.c_int64, _I64], ctypes.c_int),
+            "sph_guard_band": ([ctypes.c_int32, _D, _D, ctypes.c_double, ctypes.c_double, ctypes.c_double],
+                               ctypes.c_double),
+            "sph_status_str": ([ctypes.c_int], ctypes.c_char_p),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _d3(v) -> ctypes.Array:
+    a = list(v) + [0.0] * (3 - len(v))
+    return (ctypes.c_double * 3)(*[float(x) for x in a[:3]])
+
+
+def _d9(m) -> ctypes.Array:
+    a = np.asarray(m, dtype=np.float64).reshape(9)
+    return (ctypes.c_double * 9)(*[float(x) for x in a])
+
+
+def check(status: int, what: str = "sphbuf") -> None:
+    if status != SPH_OK:
+        raise SphError(status, what)
+
+
+# ------------------------------------------------------------------ C names ---
+
+def sph_status_str(status: int) -> str:
+    return lib().sph_status_str(int(status)).decode()
+
+
+def sph_create(dim: int, lo, hi, cell_size: float, dp: float, capacity: int, max_events: int = 4096,
+               next_id: int = 0, stream: int = 0) -> Tuple[int, Optional[int]]:
+    cfg = sph_config()
+    cfg.dim = dim
+    cfg.lo = _d3(lo)
+    cfg.hi = _d3(hi)
+    cfg.cell_size = cell_size
+    cfg.dp = dp
+    cfg.capacity = capacity
+    cfg.max_events = max_events
+    cfg.next_id = next_id
+    cfg.stream = stream or None
+    out = _VP()
+    st = lib().sph_create(ctypes.byref(cfg), ctypes.byref(out))
+    return st, out.value
+
+
+def sph_destroy(ctx: int) -> int:
+    return lib().sph_destroy(ctx)
+
+
+def sph_buffer_define(ctx: int, kind: int, origin, rot, half, margin: float) -> Tuple[int, int]:
+    bid = ctypes.c_int32(0)
+    st = lib().sph_buffer_define(ctx, int(kind), _d3(origin), _d9(rot), _d3(half), float(margin), ctypes.byref(bid))
+    return st, bid.value
+
+
+def sph_celllist_build(ctx: int, p: sph_particles) -> int:
+    return lib().sph_celllist_build(ctx, ctypes.byref(p))
+
+
+def sph_buffer_identify(ctx: int, p: sph_particles, buffer_id: int = -1) -> int:
+    return lib().sph_buffer_identify(ctx, ctypes.byref(p), int(buffer_id))
+
+
+def sph_buffer_update(ctx: int, p: sph_particles) -> Tuple[int, int, int]:
+    g, d = ctypes.c_int64(0), ctypes.c_int64(0)
+    st = lib().sph_buffer_update(ctx, ctypes.byref(p), ctypes.byref(g), ctypes.byref(d))
+    return st, g.value, d.value
+
+
+def sph_buffer_update_async(ctx: int, p: sph_particles) -> int:
+    return lib().sph_buffer_update_async(ctx, ctypes.byref(p))
+
+
+def sph_buffer_update_fullscan(ctx: int, p: sph_particles) -> Tuple[int, int, int]:
+    g, d = ctypes.c_int64(0), ctypes.c_int64(0)
+    st = lib().sph_buffer_update_fullscan(ctx, ctypes.byref(p), ctypes.byref(g), ctypes.byref(d))
+    return st, g.value, d.value
+
+
+def sph_buffer_update_fullscan_async(ctx: int, p: sph_particles) -> int:
+    return lib().sph_buffer_update_fullscan_async(ctx, ctypes.byref(p))
+
+
+def sph_last_result(ctx: int) -> Tuple[int, sph_result]:
+    r = sph_result()
+    st = lib().sph_last_result(ctx, ctypes.byref(r))
+    return st, r
+
+
+def sph_last_events(ctx: int, cap: int) -> Tuple[int, np.ndarray, np.ndarray]:
+    gen = np.zeros(max(1, cap), dtype=np.int64)
+    dele = np.zeros(max(1, cap), dtype=np.int64)
+    ng, nd = ctypes.c_int64(0), ctypes.c_int64(0)
+    st = lib().sph_last_events(ctx, gen.ctypes.data_as(_I64), dele.ctypes.data_as(_I64), int(cap), ctypes.byref(ng),
+                               ctypes.byref(nd))
+    return st, gen[: min(cap, ng.value)].copy(), dele[: min(cap, nd.value)].copy()
+
+
+def sph_celllist_view(ctx: int):
+    cs, ci = _VP(), _VP()
+    nc = ctypes.c_int64(0)
+    dims = (ctypes.c_int32 * 3)()
+    st = lib().sph_celllist_view(ctx, ctypes.byref(cs), ctypes.byref(ci), ctypes.byref(nc), dims)
+    return st, cs.value, ci.value, nc.value, tuple(dims)
+
+
+def sph_state_get(ctx: int) -> Tuple[int, int, np.ndarray]:
+    nid = ctypes.c_int64(0)
+    nl = np.zeros(SPH_MAX_BUFFERS, dtype=np.int64)
+    st = lib().sph_state_get(ctx, ctypes.byref(nid), nl.ctypes.data_as(_I64))
+    return st, nid.value, nl
+
+
+def sph_state_set(ctx: int, next_id: int, n_labelled) -> int:
+    nl = np.zeros(SPH_MAX_BUFFERS, dtype=np.int64)
+    nl[: len(n_labelled)] = n_labelled
+    return lib().sph_state_set(ctx, int(next_id), nl.ctypes.data_as(_I64))
+
+
+def sph_rotation_2d(theta: float) -> Tuple[int, np.ndarray]:
+    r = (ctypes.c_double * 9)()
+    st = lib().sph_rotation_2d(float(theta), r)
+    return st, np.array(r[:]).reshape(3, 3)
+
+
+def sph_rotation_axis_angle(n, theta: float) -> Tuple[int, np.ndarray]:
+    r = (ctypes.c_double * 9)()
+    st = lib().sph_rotation_axis_angle(_d3(n), float(theta), r)
+    return st, np.array(r[:]).reshape(3, 3)
+
+
+def sph_rotation_from_direction(d) -> Tuple[int, np.ndarray]:
+    r = (ctypes.c_double * 9)()
+    st = lib().sph_rotation_from_direction(_d3(d), r)
+    return st, np.array(r[:]).reshape(3, 3)
+
+
+def sph_check_rotation(dim: int, rot) -> int:
+    return lib().sph_check_rotation(int(dim), _d9(rot))
+
+
+def sph_grid_cover(dim: int, lo, cell_size: float, dims, origin, rot, half, margin: float, cap: int = 1 << 20):
+    f = np.zeros(max(1, cap), dtype=np.int32)
+    ln = np.zeros(max(1, cap), dtype=np.int32)
+    n = ctypes.c_int64(0)
+    d3 = (ctypes.c_int32 * 3)(*[int(x) for x in (list(dims) + [1, 1, 1])[:3]])
+    st = lib().sph_grid_cover(int(dim), _d3(lo), float(cell_size), d3, _d3(origin), _d9(rot), _d3(half),
+                              float(margin), f.ctypes.data_as(_I32), ln.ctypes.data_as(_I32), int(cap),
+                              ctypes.byref(n))
+    return st, f[: n.value].copy(), ln[: n.value].copy()
+
+
+def sph_guard_band(dim: int, origin, half, margin: float, cell_size: float, dp: float) -> float:
+    return lib().sph_guard_band(int(dim), _d3(origin), _d3(half), float(margin), float(cell_size), float(dp))
+
+
+# ------------------------------------------------------------- marshalling ---
+
+def particles_from_tensors(pos: Sequence, carried: Sequence, label, ids, n_dev) -> sph_particles:
+    """Fill an sph_particles from torch device tensors (all of one capacity)."""
+    p = sph_particles()
+    cap = int(label.shape[0])
+    for c, t in enumerate(pos):
+        assert t.is_contiguous() and t.shape[0] == cap and str(t.dtype) == "torch.float32"
+        p.pos[c] = t.data_ptr()
+    assert len(carried) <= SPH_MAX_CARRIED
+    for f, t in enumerate(carried):
+        assert t.is_contiguous() and t.shape[0] == cap and str(t.dtype) == "torch.float32"
+        p.carried[f] = t.data_ptr()
+    p.n_carried = len(carried)
+    assert str(label.dtype) == "torch.int32" and str(ids.dtype) == "torch.int64" and str(n_dev.dtype) == "torch.int64"
+    p.label = label.data_ptr()
+    p.id = ids.data_ptr()
+    p.n_dev = n_dev.data_ptr()
+    p.capacity = cap
+    return p

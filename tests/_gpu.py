@@ -1,0 +1,55 @@
+"""GPU-side helpers for the parity tests: a library Domain fed with the same seeded
+inputs (and the oracle's own frames) as the FP64 oracle, plus comparisons."""
+from __future__ import annotations
+
+from typing import List, Sequence
+
+import numpy as np
+
+import oracle
+import workloads as W
+from tests._support import oracle_buffers, oracle_state
+
+
+def make_domain_raw(dim, lo, hi, cell_size, dp, bufs: Sequence[oracle.Buffer], st: oracle.State,
+                    max_events: int = 4096):
+    from paper_2406_16786_amd.domain import Domain
+    d = Domain(dim, lo, hi, cell_size, dp, st.capacity, st.pos, st.carried, st.label, st.id, st.n, st.next_id,
+               max_events=max_events)
+    for b in bufs:
+        d.define(b.kind, b.origin, b.rot, b.half, b.margin)
+    return d
+
+
+def make_domain(wl, bufs: Sequence[oracle.Buffer], st: oracle.State = None, max_events: int = 4096,
+                cell_size: float = None, lo=None, hi=None):
+    st = st if st is not None else oracle_state(wl)
+    return make_domain_raw(wl.dim, lo if lo is not None else wl.lo, hi if hi is not None else wl.hi,
+                           cell_size if cell_size is not None else wl.cell_size, wl.dp, bufs, st, max_events)
+
+
+def upload_state(d, st: oracle.State) -> None:
+    d.upload(st.pos, st.carried, st.label, st.id, st.n)
+
+
+def assert_same_state(d, st: oracle.State, what: str = "") -> None:
+    pos, car, lab, ids, n = d.download()
+    assert n == st.n, f"{what}: n {n} != {st.n}"
+    for c in range(st.dim):
+        np.testing.assert_array_equal(pos[c][:n], st.pos[c][:n], err_msg=f"{what}: pos[{c}]")
+    for f in range(len(st.carried)):
+        np.testing.assert_array_equal(car[f][:n], st.carried[f][:n], err_msg=f"{what}: carried[{f}]")
+    np.testing.assert_array_equal(lab[:n], st.label[:n], err_msg=f"{what}: label")
+    np.testing.assert_array_equal(ids[:n], st.id[:n], err_msg=f"{what}: id")
+
+
+def step_both(d, bufs, st: oracle.State, mode: str = "local"):
+    """One update on the GPU (local or full scan) and on the oracle; returns both."""
+    from paper_2406_16786_amd import sphbuf as S
+    if mode == "local":
+        d.build()
+        gst, g, dl = d.update()
+    else:
+        gst, g, dl = d.update_fullscan()
+    res = oracle.update(bufs, st)
+    return gst, g, dl, res
