@@ -1,0 +1,327 @@
+#!/usr/bin/env python
+"""Benchmark of the buffer-update hot path on one MI355X.
+
+One step = one pass of the whole path over one particle state: the cell-list
+build (count, scan, scatter) followed by the buffer update (local-cell
+candidates, frame rotation, crossing tests, generation/recycle, deletion by
+compaction, relabel).  The workload is the 3-D pipe (R = 0.05, L = 1, dp = 0.001,
+about 7.86 M particles, inlet and outlet planes tilted 20 and 35 degrees) unless
+--workload says otherwise.
+
+The particle states the timed steps consume are prepared beforehand by running
+the real loop (update, then advection with the prescribed velocity) and keeping
+a device copy of each pre-update state; the timed region replays those states
+in order, so every timed step does the full work of a real step (events
+included) on inputs already resident in HBM, and nothing else.
+
+Printed: one JSON line with the throughput, the roofline of the dominant
+kernel, the full-scan baseline and the FP64 CPU oracle timed on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "buffer-update Mparticles/s, speedup vs full scan, % HBM peak; batched vs plain"
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def rotation_of(S, spec, dim):
+    if dim == 2:
+        st, q = S.sph_rotation_2d(spec.angle)
+    else:
+        st, q = S.sph_rotation_from_direction(spec.direction)
+    S.check(st, "rotation")
+    return q
+
+
+def make_workload(name: str, order: str):
+    import workloads as W
+    if name == "pipe3d":
+        return W.pipe3d(order=order)
+    if name == "bent_channel2d":
+        return W.bent_channel2d(order=order)
+    if name == "channel2d":
+        return W.channel2d(order=order)
+    raise SystemExit(f"unknown workload {name}")
+
+
+class Snapshot:
+    """Device copy of one pre-update state."""
+
+    def __init__(self, dom, torch):
+        self.pos = [t.clone() for t in dom.pos]
+        self.carried = [t.clone() for t in dom.carried]
+        self.label = dom.label.clone()
+        self.id = dom.id.clone()
+        self.n_dev = dom.n_dev.clone()
+
+    def tensors(self):
+        return self.pos + self.carried + [self.label, self.id, self.n_dev]
+
+
+def phase_bytes(dim: int, n: int, n_cells: int, cand: int, g: int, d: int, n_carried: int):
+    """Algorithmic bytes per launch of each kernel phase (what the step must move)."""
+    state = 4 * dim + 4 * n_carried + 4 + 8          # bytes of one particle's state
+    return {
+        "build": (4 * dim + 4) * n + 4 * (n_cells + 1), # read positions, write cell_idx and cell_start
+        "count": 4 * dim * n,                           # read positions
+        "scan": 8 * (n_cells + 1),                      # read counts, write cell starts
+        "scatter": 4 * n,                               # write the cell-ordered index list
+        "classify": cand * (4 * dim + 8),               # candidate index, position, label
+        "fullscan": 4 * dim * n,                        # read positions
+        "finalize": (g + d) * 8 + g * (2 * state) + d * 2 * state,  # events, duplicates, refills
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="pipe3d", choices=["pipe3d", "bent_channel2d", "channel2d"])
+    ap.add_argument("--order", default="lattice", choices=["lattice", "blocked"])
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile-pass", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus_requested": args.gpus}), flush=True)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2406_16786_amd import sphbuf as S
+    from paper_2406_16786_amd.domain import Domain
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    K, Wm = args.steps, args.warmup
+    t_all = time.perf_counter()
+
+    wl = make_workload(args.workload, args.order)
+    log(f"workload {wl.name}: N = {wl.n}, dim {wl.dim}, capacity {wl.capacity}")
+    rots = [rotation_of(S, b, wl.dim) for b in wl.buffers]
+    dom = Domain(wl.dim, wl.lo, wl.hi, wl.cell_size, wl.dp, wl.capacity, wl.pos, wl.carried, wl.label, wl.id,
+                 wl.n, wl.n, max_events=S.SPH_MAX_EVENTS_LIMIT)
+    for b, q in zip(wl.buffers, rots):
+        dom.define(b.kind, b.origin, q, b.half, b.margin)
+    S.check(dom.identify(-1), "identify")
+    stream = dom.stream
+
+    # ---- prepare the states the timed steps consume (the real loop, untimed) ----
+    n_snap = Wm + K
+    snaps, states, n_list = [], [], []
+    gen = torch.Generator(device=dev)
+    for s in range(n_snap):
+        st, nid, nl = S.sph_state_get(dom.ctx)
+        states.append((nid, nl.copy()))
+        snaps.append(Snapshot(dom, torch))
+        dom.build()
+        S.check(dom.update_async(), "update")
+        rs, r = dom.result()
+        S.check(r.status, f"update in preparation step {s}")
+        n_list.append((r.n_before, r.n_after, r.n_generated, r.n_deleted))
+        n = r.n_after
+        gen.manual_seed(wl.seed_noise + s)
+        with torch.cuda.stream(stream):
+            p = [t[:n] for t in dom.pos]
+            noise = torch.randn((wl.dim, n), generator=gen, device=dev, dtype=torch.float32)
+            u = wl.velocity(torch, p, s, noise)
+            for c in range(wl.dim):
+                p[c].add_(u[c] * wl.dt)
+    stream.synchronize()
+    log(f"prepared {n_snap} states in {time.perf_counter() - t_all:.1f} s; events/step "
+        f"G={np.mean([x[2] for x in n_list]):.0f} D={np.mean([x[3] for x in n_list]):.0f}")
+
+    # ---- candidate count of the local path (for the classify bytes) ----
+    _, cs_ptr, _, n_cells, dims = S.sph_celllist_view(dom.ctx)
+    cand = 0
+    start = torch.zeros(n_cells + 1, dtype=torch.int32, device=dev)
+    # rebuild on the first state to read its cell starts
+    work0 = Snapshot(dom, torch)
+    for dst, src in zip(work0.tensors(), snaps[0].tensors()):
+        dst.copy_(src)
+    p0 = S.particles_from_tensors(work0.pos, work0.carried, work0.label, work0.id, work0.n_dev)
+    S.check(S.sph_celllist_build(dom.ctx, p0), "build")
+    stream.synchronize()
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so")
+    host_start = np.zeros(n_cells + 1, dtype=np.int32)
+    hip.hipMemcpy(ctypes.c_void_p(host_start.ctypes.data), ctypes.c_void_p(cs_ptr),
+                  ctypes.c_size_t(host_start.nbytes), 2)
+    for b, q in zip(wl.buffers, rots):
+        st, f, ln = S.sph_grid_cover(wl.dim, wl.lo, wl.cell_size, dims, b.origin, q, b.half, b.margin)
+        cand += int(np.sum(host_start[f + ln] - host_start[f]))
+    del work0, p0
+
+    # ---- working copies + replay ----
+    work = [Snapshot(dom, torch) for _ in range(n_snap)]
+    parts = [S.particles_from_tensors(w.pos, w.carried, w.label, w.id, w.n_dev) for w in work]
+    flush = torch.empty(1 << 27, dtype=torch.float32, device=dev)      # 512 MB
+    flush_src = torch.ones_like(flush)
+
+    def reset_work():
+        with torch.cuda.stream(stream):
+            for w, s in zip(work, snaps):
+                for dst, src in zip(w.tensors(), s.tensors()):
+                    dst.copy_(src)
+            flush.copy_(flush_src)                                     # plain 512 MB copy: flushes caches
+        stream.synchronize()
+        nid, nl = states[0]
+        S.check(S.sph_state_set(dom.ctx, nid, nl), "state_set")
+
+    def replay(mode: str, profile: bool):
+        reset_work()
+        S.check(S.sph_profile_enable(dom.ctx, False), "profile")
+        for s in range(Wm):
+            if mode == "local":
+                S.check(S.sph_celllist_build(dom.ctx, parts[s]), "build")
+                S.check(S.sph_buffer_update_async(dom.ctx, parts[s]), "update")
+            else:
+                S.check(S.sph_buffer_update_fullscan_async(dom.ctx, parts[s]), "fullscan")
+        stream.synchronize()
+        if profile:
+            S.check(S.sph_profile_enable(dom.ctx, True), "profile")
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for s in range(Wm, Wm + K):
+            if mode == "local":
+                S.sph_celllist_build(dom.ctx, parts[s])
+                S.sph_buffer_update_async(dom.ctx, parts[s])
+            else:
+                S.sph_buffer_update_fullscan_async(dom.ctx, parts[s])
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = e0.elapsed_time(e1) / K
+        rs, r = S.sph_last_result(dom.ctx)
+        S.check(r.status, f"{mode} replay")
+        expect = n_list[Wm + K - 1]
+        assert (r.n_before, r.n_after, r.n_generated, r.n_deleted) == expect, (mode, expect, r.n_after)
+        prof = None
+        if profile:
+            st, pms, pn = S.sph_profile_read(dom.ctx, reset=True)
+            S.check(S.sph_profile_enable(dom.ctx, False), "profile")
+            prof = {S.PHASES[i]: (float(pms[i]) / max(1, int(pn[i])), int(pn[i])) for i in range(S.SPH_NPHASE)
+                    if pn[i] > 0}
+        return ms, wall / K * 1e3, prof
+
+    ms_local, wall_local, _ = replay("local", False)
+    ms_full, wall_full, _ = replay("fullscan", False)
+    prof_local = prof_full = None
+    if not args.no_profile_pass:
+        _, _, prof_local = replay("local", True)
+        _, _, prof_full = replay("fullscan", True)
+    log(f"local step {ms_local * 1e3:.1f} us (wall {wall_local * 1e3:.1f} us); "
+        f"full-scan update {ms_full * 1e3:.1f} us")
+    log(f"local phases (us): " + ", ".join(f"{k} {v[0] * 1e3:.1f}" for k, v in (prof_local or {}).items()))
+    log(f"full phases (us): " + ", ".join(f"{k} {v[0] * 1e3:.1f}" for k, v in (prof_full or {}).items()))
+
+    n_mean = float(np.mean([x[0] for x in n_list[Wm:]]))
+    g_mean = float(np.mean([x[2] for x in n_list[Wm:]]))
+    d_mean = float(np.mean([x[3] for x in n_list[Wm:]]))
+    pb = phase_bytes(wl.dim, int(n_mean), int(n_cells), cand, int(g_mean), int(d_mean), len(wl.carried))
+    step_bytes = pb["build"] + pb["classify"] + pb["finalize"]
+    upd_local_bytes = pb["classify"] + pb["finalize"]
+
+    roof = None
+    if prof_local:
+        dom_phase = max((k for k in prof_local if k != "fullscan"), key=lambda k: prof_local[k][0])
+        avg_ms = prof_local[dom_phase][0]
+        achieved = pb[dom_phase] / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": dom_phase, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "avg_launch_us": round(avg_ms * 1e3, 2), "algorithmic_bytes_per_launch": int(pb[dom_phase])}
+
+    t_upd_local = None
+    if prof_local:
+        t_upd_local = (prof_local.get("classify", (0, 0))[0] + prof_local.get("finalize", (0, 0))[0])
+    value = n_mean / (ms_local * 1e-3) / 1e6
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "Mparticles/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": Wm,
+        "ms_per_step": round(ms_local, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (f64 recheck in the guard band)",
+        "data": "synthetic",
+        "config": {"workload": f"{wl.name} (3-D pipe R=0.05 L=1.0 dp=0.001, inlet 20 deg, outlet 35 deg)"
+                   if wl.name == "pipe3d" else wl.name,
+                   "n_particles": int(n_mean), "dim": wl.dim, "buffers": len(wl.buffers), "cells": int(n_cells),
+                   "candidates_per_update": cand, "events_per_step": {"generated": g_mean, "deleted": d_mean},
+                   "particle_order": args.order, "path": "cell-list build + local-cell update"},
+        "pct_hbm_peak_step": round(step_bytes / (ms_local * 1e-3) / 1e9 / HBM_PEAK_GBS * 100, 2),
+        "fullscan": {"ms_per_update": round(ms_full, 5),
+                     "Mparticles_per_s": round(n_mean / (ms_full * 1e-3) / 1e6, 1)},
+        "speedup_step_vs_fullscan": round(ms_full / ms_local, 3),
+        "roofline": roof,
+    }
+    if t_upd_local:
+        out["local_update_only"] = {"ms": round(t_upd_local, 5),
+                                    "Mparticles_per_s": round(n_mean / (t_upd_local * 1e-3) / 1e6, 1),
+                                    "speedup_vs_fullscan": round(prof_full["fullscan"][0] / t_upd_local, 2)
+                                    if prof_full else None}
+    if prof_local:
+        out["phases_us"] = {k: round(v[0] * 1e3, 2) for k, v in prof_local.items()}
+    if prof_full:
+        out["fullscan_phases_us"] = {k: round(v[0] * 1e3, 2) for k, v in prof_full.items()}
+
+    # ---- CPU baseline: the FP64 oracle on this host, bounded sample ----
+    if not args.no_cpu_baseline:
+        import oracle
+        pos = [t.cpu().numpy() for t in snaps[Wm].pos]
+        car = [t.cpu().numpy() for t in snaps[Wm].carried]
+        lab = snaps[Wm].label.cpu().numpy()
+        ids = snaps[Wm].id.cpu().numpy()
+        n0 = int(snaps[Wm].n_dev.item())
+        ob = []
+        for b in wl.buffers:
+            q = oracle.rotation_2d(b.angle) if wl.dim == 2 else oracle.rotation_from_direction(b.direction)
+            ob.append(oracle.Buffer(b.kind, b.origin, q, b.half, b.margin))
+        times = []
+        t_start = time.perf_counter()
+        while not times or (time.perf_counter() - t_start < args.cpu_seconds and len(times) < 50):
+            st_o = oracle.State(wl.dim, [a.copy() for a in pos], [a.copy() for a in car], lab.copy(), ids.copy(),
+                                n0, int(states[Wm][0]))
+            t0 = time.perf_counter()
+            res = oracle.update(ob, st_o)
+            times.append(time.perf_counter() - t0)
+            assert res.status == 0
+        t_o = float(np.median(times))
+        out["cpu_baseline"] = {"value": round(n0 / t_o / 1e6, 2), "unit": "Mparticles/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"{len(times)} FP64 brute-force oracle updates of the first timed state "
+                                         f"(N = {n0}), median {t_o * 1e3:.0f} ms; single-threaded C"}
+        log(f"cpu oracle: {len(times)} updates, median {t_o * 1e3:.1f} ms")
+    log(f"total {time.perf_counter() - t_all:.1f} s")
+    print(json.dumps(out), flush=True)
+    dom.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

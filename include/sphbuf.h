@@ -167,6 +167,28 @@ sph_status sph_celllist_view(sph_ctx *ctx, const int32_t **cell_start, const int
 sph_status sph_state_get(sph_ctx *ctx, int64_t *next_id, int64_t n_labelled[SPH_MAX_BUFFERS]);
 sph_status sph_state_set(sph_ctx *ctx, int64_t next_id, const int64_t n_labelled[SPH_MAX_BUFFERS]);
 
+/* ---------------------------------------------------------------- profiling -- */
+
+/* Kernel phases timed by the optional per-launch HIP events. */
+typedef enum {
+    SPH_PHASE_COUNT = 0,      /* cell keys + per-cell ranks (atomics)            */
+    SPH_PHASE_SCAN = 1,       /* exclusive scan of the cell counts                */
+    SPH_PHASE_SCATTER = 2,    /* particle indices into cell order                 */
+    SPH_PHASE_CLASSIFY = 3,   /* local-cell candidates, frame, crossing tests     */
+    SPH_PHASE_FULLSCAN = 4,   /* every particle against every buffer (baseline)   */
+    SPH_PHASE_FINALIZE = 5,   /* status, sort, duplicate/recycle/relabel/compact  */
+    SPH_PHASE_BUILD = 6,      /* count + scan + scatter in one cooperative launch */
+    SPH_NPHASE = 7
+} sph_phase;
+
+/* When on, every kernel launch of the context is bracketed by two HIP events on
+ * the context stream (events are created here, up to 8192 launches are kept).
+ * Off by default; turning it on or off drops the recorded launches. */
+sph_status sph_profile_enable(sph_ctx *ctx, int32_t on);
+/* Sync: total milliseconds and launch counts per phase since the last reset
+ * (arrays of SPH_NPHASE); reset != 0 clears them afterwards. */
+sph_status sph_profile_read(sph_ctx *ctx, double ms[SPH_NPHASE], int64_t launches[SPH_NPHASE], int32_t reset);
+
 /* ------------------------------------------------------------ host helpers -- */
 /* Pure host FP64; usable without a GPU. */
 

@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -42,6 +43,7 @@ constexpr int kClassifyBlock = 256;
 constexpr int kFinBlock = 1024;
 constexpr unsigned kMaxEv = SPH_MAX_EVENTS_LIMIT;
 constexpr int kRelPerEvent = 4;
+constexpr int kMaxPartBlocks = 8192;  // upper bound on classify / full-scan grid sizes
 
 constexpr unsigned kIn = 1u, kBox = 2u, kFront = 4u, kBack = 8u;
 constexpr int kEvNone = 0, kEvGen = 1, kEvDel = 2;
@@ -67,11 +69,11 @@ struct Parts {
 // Device-resident counters and library state.
 struct Ctl {
     unsigned int n_gen, n_del, n_rel, pad0;
-    unsigned long long found[16];  // label-k candidates inside C_k (pre-update)
-    unsigned long long post[16];   // label-k particles among C_k candidates afterwards
     unsigned int tile_counter;
     unsigned int nonfinite_epoch;  // epoch of the last build/scan that met a non-finite position
-    unsigned int scan_fault;       // set if a look-back wait ran past its spin limit
+    unsigned int scan_fault;       // set if a look-back or grid-barrier wait ran past its spin limit
+    unsigned int bar_count;        // grid barrier of the fused build: arrivals
+    unsigned int bar_gen;          // grid barrier generation
     unsigned int pad2;
     long long next_id;
     long long n_labelled[16];
@@ -166,19 +168,16 @@ __device__ __forceinline__ unsigned classify(const BufDev &b, int dim, float x, 
     return bits;
 }
 
-// Wave-compacted append: one atomic per wave, slot = base + mbcnt(ballot).
-__device__ __forceinline__ void wave_append(bool pred, unsigned long long value, unsigned *counter,
-                                            unsigned long long *list, unsigned cap) {
+// Wave-compacted slot allocation: one atomic per wave, slot = base + mbcnt(ballot).
+// Returns the lane's slot, or 0xffffffff for lanes that do not append.
+__device__ __forceinline__ unsigned wave_slot(bool pred, unsigned *counter) {
     const unsigned long long m = __ballot(pred);
-    if (m == 0ull) return;
+    if (m == 0ull) return 0xffffffffu;
     const int leader = __ffsll((long long)m) - 1;
     unsigned base = 0;
     if (lane_id() == leader) base = atomicAdd(counter, (unsigned)__popcll(m));
     base = __shfl(base, leader);
-    if (pred) {
-        const unsigned pos = base + mbcnt(m);
-        if (pos < cap) list[pos] = value;
-    }
+    return pred ? base + mbcnt(m) : 0xffffffffu;
 }
 
 __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
@@ -227,28 +226,119 @@ __device__ __forceinline__ Outcome decide(const BufDev &b, int k, int dim, unsig
     return o;
 }
 
+constexpr int kDupStride = 3 + SPH_MAX_CARRIED;  // floats per captured duplicate
+
 struct EventArgs {
     Ctl *ctl;
-    unsigned long long *gen;
-    unsigned long long *del;
-    unsigned long long *rel;
+    uint32_t *gen_idx;         // [cap_ev] generated-source index (append order)
+    float *gen_new;            // [cap_ev * 3] its recycled position
+    float *dup;                // [cap_ev * kDupStride] its pre-recycle position and carried fields
+    uint32_t *del_idx;         // [cap_ev] deleted index (append order)
+    unsigned long long *rel;   // [cap_rel] (index << 32) | new label
     unsigned cap_ev;
     unsigned cap_rel;
+    unsigned *part;  // per-block label counts: part[(block * 16 + k) * 2 + {0: found, 1: post}]
 };
 
-// Emit the wave's events for buffer k and accumulate its label counts.
-__device__ __forceinline__ void emit(const EventArgs &e, int k, bool valid, int64_t i, int lab, const Outcome &o,
+// Block-level label counts of each buffer: waves add into LDS, then the block
+// writes its own slot of the partial array (no contended global atomics; the
+// finalize step sums the slots).
+__device__ __forceinline__ void block_counts_init(unsigned *s_cnt) {
+    if (threadIdx.x < 2 * SPH_MAX_BUFFERS) s_cnt[threadIdx.x] = 0u;
+}
+__device__ __forceinline__ void block_counts_add(unsigned *s_cnt, int k, unsigned long long found,
+                                                 unsigned long long post) {
+    found = wave_sum(found);
+    post = wave_sum(post);
+    if (lane_id() == 0 && (found | post)) {
+        atomicAdd(&s_cnt[2 * k], (unsigned)found);
+        atomicAdd(&s_cnt[2 * k + 1], (unsigned)post);
+    }
+}
+__device__ __forceinline__ void block_counts_store(const EventArgs &e, const unsigned *s_cnt, int nb) {
+    if (threadIdx.x < 2 * nb) e.part[(size_t)blockIdx.x * 2 * SPH_MAX_BUFFERS + threadIdx.x] = s_cnt[threadIdx.x];
+}
+
+// Emit the wave's events for buffer k and accumulate its label counts.  A
+// generating lane also captures the duplicate's payload (the state before the
+// recycle) and the recycled position r - a d (FP64, rounded to FP32): nothing of
+// the caller's arrays is written here, so a failed status check can still leave
+// them untouched, and the finalize step has no random reads left to do.
+__device__ __forceinline__ void emit(const EventArgs &e, const Parts &p, const BufDev &b, int k, bool valid,
+                                     int64_t i, int lab, const Outcome &o, float x, float y, float z,
                                      unsigned long long &found, unsigned long long &post) {
     const bool in = valid && o.newlab >= 0;
     if (in && o.mine) found++;
     if (in && o.ev != kEvDel && o.newlab == k + 1) post++;
-    wave_append(in && o.ev == kEvGen, ((unsigned long long)i << 32) | (unsigned)k, &e.ctl->n_gen, e.gen, e.cap_ev);
-    wave_append(in && o.ev == kEvDel, (unsigned long long)i << 32, &e.ctl->n_del, e.del, e.cap_ev);
-    wave_append(in && o.ev != kEvDel && o.newlab != lab, ((unsigned long long)i << 32) | (unsigned)o.newlab,
-                &e.ctl->n_rel, e.rel, e.cap_rel);
+    unsigned s = wave_slot(in && o.ev == kEvGen, &e.ctl->n_gen);
+    if (s < e.cap_ev) {
+        e.gen_idx[s] = (uint32_t)i;
+        const float r[3] = {x, y, z};
+        float *d = e.dup + (size_t)s * kDupStride;
+        for (int c = 0; c < p.dim; ++c) {
+            d[c] = r[c];
+            e.gen_new[3 * (size_t)s + c] = (float)((double)r[c] - b.shift[c]);
+        }
+        for (int f = 0; f < p.nc; ++f) d[3 + f] = p.car[f][i];
+    }
+    s = wave_slot(in && o.ev == kEvDel, &e.ctl->n_del);
+    if (s < e.cap_ev) e.del_idx[s] = (uint32_t)i;
+    s = wave_slot(in && o.ev != kEvDel && o.newlab != lab, &e.ctl->n_rel);
+    if (s < e.cap_rel) e.rel[s] = ((unsigned long long)i << 32) | (unsigned)o.newlab;
 }
 
 // --------------------------------------------------------------- K0 build --
+
+// Cell keys and per-cell ranks of J particles per thread at once: all position
+// loads are issued first, then the wave-level run detection, then all atomics,
+// and only then are the returned bases read -- so J load and J atomic round
+// trips overlap instead of queueing.  Particle of slot j: i0 + j * stride;
+// lanes past s1 take no part.  Wave-uniform call.
+template <int J>
+__device__ __forceinline__ void key_rank_batch(const Grid &g, const float *__restrict__ x,
+                                               const float *__restrict__ y, const float *__restrict__ z,
+                                               int32_t *count, int64_t i0, int64_t stride, int64_t s1, int lane,
+                                               uint32_t (&key)[J], int32_t (&rank)[J], bool &bad) {
+    float px[J], py[J], pz[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const int64_t i = i0 + (int64_t)j * stride;
+        px[j] = py[j] = pz[j] = 0.0f;
+        if (i < s1) {
+            px[j] = x[i];
+            py[j] = y[i];
+            if (g.dim == 3) pz[j] = z[i];
+        }
+    }
+    int my_head[J], len[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const bool valid = i0 + (int64_t)j * stride < s1;
+        key[j] = 0xffffffffu;
+        if (valid) {
+            bad |= !(isfinite(px[j]) && isfinite(py[j]) && isfinite(pz[j]));
+            key[j] = cell_key(g, px[j], py[j], pz[j]);
+        }
+        const uint32_t prev = __shfl_up(key[j], 1);
+        const bool head = !valid || lane == 0 || key[j] != prev;
+        const unsigned long long heads = __ballot(head);
+        const unsigned long long le = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+        my_head[j] = 63 - __clzll((long long)(heads & le));
+        const unsigned long long gt = heads & ~le;
+        len[j] = (gt ? __ffsll((long long)gt) - 1 : 64) - my_head[j];
+        if (!valid) len[j] = 0;
+    }
+    int old[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        old[j] = 0;
+        if (len[j] > 0 && lane == my_head[j]) old[j] = atomicAdd(&count[key[j]], len[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < J; ++j) rank[j] = __shfl(old[j], my_head[j]) + (lane - my_head[j]);
+}
+
+constexpr int kCountBatch = 4;
 
 struct CountArgs {
     const float *x, *y, *z;
@@ -279,27 +369,16 @@ __global__ __launch_bounds__(kBuildBlock) void k_count(CountArgs a) {
     const int64_t s0 = (int64_t)lb * per;
     const int64_t s1 = min(N, s0 + per);
     bool bad = false;
-    for (int64_t base = s0; base < s1; base += blockDim.x) {
-        const int64_t i = base + threadIdx.x;
-        const bool valid = i < s1;
-        uint32_t key = 0xffffffffu;
-        if (valid) {
-            const float x = a.x[i], y = a.y[i], z = a.g.dim == 3 ? a.z[i] : 0.0f;
-            bad |= !(isfinite(x) && isfinite(y) && isfinite(z));
-            key = cell_key(a.g, x, y, z);
+    const int64_t B = blockDim.x;
+    for (int64_t base = s0; base < s1; base += B * kCountBatch) {
+        uint32_t key[kCountBatch];
+        int32_t rank[kCountBatch];
+        key_rank_batch<kCountBatch>(a.g, a.x, a.y, a.z, a.count, base + threadIdx.x, B, s1, lane, key, rank, bad);
+#pragma unroll
+        for (int j = 0; j < kCountBatch; ++j) {
+            const int64_t i = base + threadIdx.x + j * B;
+            if (i < s1) a.keyrank[i] = ((unsigned long long)key[j] << 32) | (unsigned)rank[j];
         }
-        // runs of equal keys inside the wave share one atomic
-        const uint32_t prev = __shfl_up(key, 1);
-        const bool head = !valid || lane == 0 || key != prev;
-        const unsigned long long heads = __ballot(head);
-        const unsigned long long le = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
-        const int my_head = 63 - __clzll((long long)(heads & le));
-        const unsigned long long gt = heads & ~le;
-        const int next = gt ? __ffsll((long long)gt) - 1 : 64;
-        int old = 0;
-        if (valid && lane == my_head) old = atomicAdd(&a.count[key], next - my_head);
-        const int rank = __shfl(old, my_head) + (lane - my_head);
-        if (valid) a.keyrank[i] = ((unsigned long long)key << 32) | (unsigned)rank;
     }
     if (__ballot(bad) != 0ull && lane == 0) atomicMax(&a.ctl->nonfinite_epoch, a.epoch);
 }
@@ -420,6 +499,177 @@ __global__ __launch_bounds__(kBuildBlock) void k_scatter(ScatterArgs a) {
     }
 }
 
+// ---------------------------------------------------- K0 fused (one launch) --
+//
+// Count, scan and scatter in one cooperative launch with three grid barriers
+// (after the counts, after the scan's block sums, after the cell starts).  Each
+// block owns one contiguous particle segment; for up to kFusedSlots particles per
+// thread the cell key stays in LDS and the rank in registers from the count phase
+// to the scatter phase, so the only per-particle HBM traffic is the position read
+// and the cell_idx write.  Particles beyond those slots (very large N) go through
+// the keyrank buffer as in the three-kernel build.
+
+constexpr int kFusedBlock = 1024;
+constexpr int kFusedSlots = 32;
+constexpr int kFusedGroup = 8;
+
+struct FusedArgs {
+    const float *x, *y, *z;
+    const int64_t *n_dev;
+    int64_t capacity;
+    Grid g;
+    int32_t *count;
+    int32_t *cell_start;
+    int32_t *cell_idx;
+    unsigned long long *keyrank;
+    int32_t *block_sum;
+    int64_t m;  // cells + 1
+    Ctl *ctl;
+    unsigned epoch;
+};
+
+// Grid-wide barrier for a cooperative launch (all blocks resident).  Every
+// thread releases its writes at agent scope, one thread per block arrives on a
+// counter, the last arrival opens the next generation.  A wait that runs past
+// its spin limit flags a fault and returns false so the kernel can stop before
+// using data it cannot trust.
+__device__ bool grid_barrier(Ctl *c, unsigned nblocks) {
+    __shared__ int s_ok;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        const unsigned gen = __hip_atomic_load(&c->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned arrived = __hip_atomic_fetch_add(&c->bar_count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (arrived == nblocks - 1) {
+            __hip_atomic_store(&c->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&c->bar_gen, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            unsigned spins = 0;
+            while (__hip_atomic_load(&c->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > (1u << 24)) {
+                    atomicOr(&c->scan_fault, 1u);
+                    ok = 0;
+                    break;
+                }
+            }
+        }
+        s_ok = ok;
+    }
+    __syncthreads();
+    __threadfence();
+    return s_ok != 0;
+}
+
+__device__ __forceinline__ int block_sum_1024(int v, int *s_red) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    const int wave = threadIdx.x / kWave;
+    __syncthreads();
+    if ((threadIdx.x & (kWave - 1)) == 0) s_red[wave] = v;
+    __syncthreads();
+    int t = 0;
+    for (int w = 0; w < kFusedBlock / kWave; ++w) t += s_red[w];
+    return t;
+}
+
+// Inclusive block scan of one value per thread; also returns the block total.
+__device__ __forceinline__ int block_scan_1024(int v, int *s_red, int &total) {
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    int incl = v;
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int t = __shfl_up(incl, off);
+        if (lane >= off) incl += t;
+    }
+    __syncthreads();
+    if (lane == kWave - 1) s_red[wave] = incl;
+    __syncthreads();
+    int before = 0;
+    total = 0;
+    for (int w = 0; w < kFusedBlock / kWave; ++w) {
+        const int s = s_red[w];
+        if (w < wave) before += s;
+        total += s;
+    }
+    return before + incl;
+}
+
+__global__ __launch_bounds__(kFusedBlock) void k_build_fused(FusedArgs a) {
+    __shared__ int s_red[kFusedBlock / kWave];
+    __shared__ uint32_t s_key[kFusedSlots * kFusedBlock];
+    const int64_t N = live_count(a.n_dev, a.capacity);
+    const unsigned G = gridDim.x;
+    const int lb = logical_block();
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t per = ((N + G - 1) / G + kFusedBlock - 1) / kFusedBlock * kFusedBlock;
+    const int64_t s0 = (int64_t)lb * per;
+    const int64_t s1 = min(N, s0 + per);
+    int32_t rank[kFusedSlots];
+    bool bad = false;
+    // ---- count: keys to LDS, ranks kept in registers, kFusedGroup slots at a time ----
+#pragma unroll
+    for (int j0 = 0; j0 < kFusedSlots; j0 += kFusedGroup) {
+        if (s0 + (int64_t)j0 * kFusedBlock < s1) {
+            uint32_t k[kFusedGroup];
+            int32_t r[kFusedGroup];
+            key_rank_batch<kFusedGroup>(a.g, a.x, a.y, a.z, a.count, s0 + (int64_t)j0 * kFusedBlock + threadIdx.x,
+                                        kFusedBlock, s1, lane, k, r, bad);
+#pragma unroll
+            for (int j = 0; j < kFusedGroup; ++j) {
+                s_key[(j0 + j) * kFusedBlock + threadIdx.x] = k[j];
+                rank[j0 + j] = r[j];
+            }
+        }
+    }
+    for (int64_t base = s0 + (int64_t)kFusedSlots * kFusedBlock; base < s1; base += kFusedBlock * kFusedGroup) {
+        uint32_t k[kFusedGroup];
+        int32_t r[kFusedGroup];
+        key_rank_batch<kFusedGroup>(a.g, a.x, a.y, a.z, a.count, base + threadIdx.x, kFusedBlock, s1, lane, k, r,
+                                    bad);
+#pragma unroll
+        for (int j = 0; j < kFusedGroup; ++j) {
+            const int64_t i = base + threadIdx.x + (int64_t)j * kFusedBlock;
+            if (i < s1) a.keyrank[i] = ((unsigned long long)k[j] << 32) | (unsigned)r[j];
+        }
+    }
+    if (__ballot(bad) != 0ull && lane == 0) atomicMax(&a.ctl->nonfinite_epoch, a.epoch);
+    if (!grid_barrier(a.ctl, G)) return;
+    // ---- scan: block sums of contiguous cell chunks, then the chunk scan ----
+    const int64_t chunk = (a.m + G - 1) / G;
+    const int64_t c0 = (int64_t)lb * chunk;
+    const int64_t c1 = min(a.m, c0 + chunk);
+    int part = 0;
+    for (int64_t c = c0 + threadIdx.x; c < c1; c += kFusedBlock) part += a.count[c];
+    part = block_sum_1024(part, s_red);
+    if (threadIdx.x == 0) a.block_sum[lb] = part;
+    if (!grid_barrier(a.ctl, G)) return;
+    int pre = 0;
+    for (int b = threadIdx.x; b < lb; b += kFusedBlock) pre += a.block_sum[b];
+    int running = block_sum_1024(pre, s_red);
+    for (int64_t t0 = c0; t0 < c1; t0 += kFusedBlock) {
+        const int64_t c = t0 + threadIdx.x;
+        const int v = c < c1 ? a.count[c] : 0;
+        int total;
+        const int incl = block_scan_1024(v, s_red, total);
+        if (c < c1) {
+            a.cell_start[c] = running + incl - v;
+            a.count[c] = 0;
+        }
+        running += total;
+    }
+    if (!grid_barrier(a.ctl, G)) return;
+    // ---- scatter from registers (and from the spill buffer) ----
+#pragma unroll
+    for (int j = 0; j < kFusedSlots; ++j) {
+        const int64_t i = s0 + (int64_t)j * kFusedBlock + threadIdx.x;
+        if (i < s1) a.cell_idx[a.cell_start[s_key[j * kFusedBlock + threadIdx.x]] + rank[j]] = (int32_t)i;
+    }
+    for (int64_t i = s0 + (int64_t)kFusedSlots * kFusedBlock + threadIdx.x; i < s1; i += kFusedBlock) {
+        const unsigned long long kr = a.keyrank[i];
+        a.cell_idx[a.cell_start[(uint32_t)(kr >> 32)] + (int)(unsigned)(kr & 0xffffffffull)] = (int32_t)i;
+    }
+}
+
 // ------------------------------------------------------------- K1 classify --
 
 struct LocalArgs {
@@ -437,10 +687,15 @@ struct LocalArgs {
 
 __global__ __launch_bounds__(kClassifyBlock) void k_classify_local(LocalArgs a) {
     __shared__ BufDev sb[SPH_MAX_BUFFERS];
+    __shared__ unsigned s_cnt[2 * SPH_MAX_BUFFERS];
     for (int t = threadIdx.x; t < a.nb * (int)(sizeof(BufDev) / 4); t += blockDim.x)
         reinterpret_cast<uint32_t *>(sb)[t] = reinterpret_cast<const uint32_t *>(a.bufs)[t];
+    block_counts_init(s_cnt);
     __syncthreads();
-    if (a.e.ctl->scan_fault) return;
+    if (a.e.ctl->scan_fault) {
+        block_counts_store(a.e, s_cnt, a.nb);
+        return;
+    }
     const int64_t N = live_count(a.p.n_dev, a.p.capacity);
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
@@ -458,24 +713,22 @@ __global__ __launch_bounds__(kClassifyBlock) void k_classify_local(LocalArgs a) 
             int64_t i = j < j1 ? a.cell_idx[j] : 0;
             const bool valid = j < j1 && i < N;  // a list older than the live count cannot index past it
             int lab = 0;
+            float x = 0.0f, y = 0.0f, z = 0.0f;
             Outcome o{kEvNone, -1, false};
             if (valid) {
-                const float x = a.p.pos[0][i], y = a.p.pos[1][i], z = dim == 3 ? a.p.pos[2][i] : 0.0f;
+                x = a.p.pos[0][i];
+                y = a.p.pos[1][i];
+                z = dim == 3 ? a.p.pos[2][i] : 0.0f;
+                lab = a.p.label[i];  // loaded with the position: one dependent round trip less
                 const unsigned bits = classify(b, dim, x, y, z);
-                if (bits & kIn) {
-                    lab = a.p.label[i];
-                    o = decide(b, k, dim, bits, lab, x, y, z);
-                }
+                if (bits & kIn) o = decide(b, k, dim, bits, lab, x, y, z);
             }
-            emit(a.e, k, valid, i, lab, o, found, post);
+            emit(a.e, a.p, b, k, valid, i, lab, o, x, y, z, found, post);
         }
-        found = wave_sum(found);
-        post = wave_sum(post);
-        if (lane == 0 && (found | post)) {
-            atomicAdd(&a.e.ctl->found[k], found);
-            atomicAdd(&a.e.ctl->post[k], post);
-        }
+        block_counts_add(s_cnt, k, found, post);
     }
+    __syncthreads();
+    block_counts_store(a.e, s_cnt, a.nb);
 }
 
 struct FullArgs {
@@ -488,10 +741,10 @@ struct FullArgs {
 
 __global__ __launch_bounds__(kClassifyBlock) void k_classify_full(FullArgs a) {
     __shared__ BufDev sb[SPH_MAX_BUFFERS];
-    __shared__ unsigned long long s_found[SPH_MAX_BUFFERS], s_post[SPH_MAX_BUFFERS];
+    __shared__ unsigned s_cnt[2 * SPH_MAX_BUFFERS];
     for (int t = threadIdx.x; t < a.nb * (int)(sizeof(BufDev) / 4); t += blockDim.x)
         reinterpret_cast<uint32_t *>(sb)[t] = reinterpret_cast<const uint32_t *>(a.bufs)[t];
-    if (threadIdx.x < SPH_MAX_BUFFERS) s_found[threadIdx.x] = s_post[threadIdx.x] = 0ull;
+    block_counts_init(s_cnt);
     __syncthreads();
     const int64_t N = live_count(a.p.n_dev, a.p.capacity);
     const int lane = threadIdx.x & (kWave - 1);
@@ -521,182 +774,249 @@ __global__ __launch_bounds__(kClassifyBlock) void k_classify_full(FullArgs a) {
                 o = decide(sb[k], k, dim, bits, lab, x, y, z);
             }
             unsigned long long found = 0, post = 0;
-            emit(a.e, k, valid, i, lab, o, found, post);
-            found = wave_sum(found);
-            post = wave_sum(post);
-            if (lane == 0 && (found | post)) {
-                atomicAdd(&s_found[k], found);
-                atomicAdd(&s_post[k], post);
-            }
+            emit(a.e, a.p, sb[k], k, valid, i, lab, o, x, y, z, found, post);
+            block_counts_add(s_cnt, k, found, post);
         }
     }
     if (__ballot(bad) != 0ull && lane == 0) atomicMax(&a.e.ctl->nonfinite_epoch, a.epoch);
     __syncthreads();
-    if (threadIdx.x < a.nb && (s_found[threadIdx.x] | s_post[threadIdx.x])) {
-        atomicAdd(&a.e.ctl->found[threadIdx.x], s_found[threadIdx.x]);
-        atomicAdd(&a.e.ctl->post[threadIdx.x], s_post[threadIdx.x]);
-    }
+    block_counts_store(a.e, s_cnt, a.nb);
 }
 
 // ------------------------------------------------------------- K2 finalize --
 
 struct FinArgs {
     Parts p;
-    const BufDev *bufs;
     int nb;
     int local;
+    int n_part;  // blocks of the classify launch that wrote label-count partials
     unsigned epoch;
     EventArgs e;
-    float *dup;
-    int dup_stride;
+    uint32_t *gen_sorted;  // [cap_ev] sources in ascending order (for sph_last_events)
+    uint32_t *del_sorted;  // [cap_ev] deleted indices in ascending order
     sph_result *result;
 };
 
-__device__ void block_sort(unsigned long long *list, unsigned n, unsigned long long *s) {
-    unsigned P = 1;
-    while (P < n) P <<= 1;
-    for (unsigned j = threadIdx.x; j < P; j += blockDim.x) s[j] = j < n ? list[j] : ~0ull;
-    __syncthreads();
-    for (unsigned k = 2; k <= P; k <<= 1) {
-        for (unsigned j = k >> 1; j > 0; j >>= 1) {
-            for (unsigned t = threadIdx.x; t < P / 2; t += blockDim.x) {
-                const unsigned i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
-                const unsigned l = i + j;
-                const bool asc = (i & k) == 0;
-                const unsigned long long u = s[i], w = s[l];
-                if ((u > w) == asc) {
-                    s[i] = w;
-                    s[l] = u;
-                }
+// Bitonic sort of 64 keys (one per lane) with a payload, in registers.
+__device__ __forceinline__ void wave_sort64(uint32_t &key, uint32_t &val) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int k = 2; k <= kWave; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const uint32_t ok = __shfl_xor(key, j), ov = __shfl_xor(val, j);
+            const bool lower = (lane & j) == 0, asc = (lane & k) == 0;
+            if (lower == asc ? ok < key : ok > key) {
+                key = ok;
+                val = ov;
             }
-            __syncthreads();
         }
     }
-    for (unsigned j = threadIdx.x; j < n; j += blockDim.x) list[j] = s[j];
+}
+
+// Number of entries of a sorted 64-entry chunk below key.
+__device__ __forceinline__ unsigned count_below64(const uint32_t *c, uint32_t key) {
+    unsigned lo = 0;
+#pragma unroll
+    for (unsigned step = 32; step > 0; step >>= 1)
+        if (c[lo + step - 1] < key) lo += step;
+    if (c[lo] < key) ++lo;  // lo <= 63 here; this settles "all 64 below"
+    return lo;
+}
+
+// Sort n (<= kMaxEv) unique 32-bit keys taken from in[]: every wave sorts
+// 64-key chunks in registers, then each key's final rank is its place in its
+// chunk plus, for every other chunk, the number of keys there below it (binary
+// search).  out_key[rank] = key (global), out_val[rank] = its position in in[]
+// (LDS, optional).  Ends with a barrier.
+__device__ void block_sort_u32(const uint32_t *in, unsigned n, uint32_t *s_ck, uint32_t *s_cv, uint32_t *out_key,
+                               uint32_t *out_val) {
+    const unsigned nch = (n + kWave - 1) / kWave;
+    const unsigned wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+    for (unsigned c = wave; c < nch; c += blockDim.x / kWave) {
+        const unsigned e = c * kWave + lane;
+        uint32_t key = e < n ? in[e] : 0xffffffffu, val = e;
+        wave_sort64(key, val);
+        s_ck[e] = key;
+        s_cv[e] = val;
+    }
+    __syncthreads();
+    for (unsigned e = threadIdx.x; e < nch * kWave; e += blockDim.x) {
+        const uint32_t key = s_ck[e];
+        if (key == 0xffffffffu) continue;
+        const unsigned mine = e / kWave;
+        unsigned rank = e % kWave;
+        for (unsigned c = 0; c < nch; ++c)
+            if (c != mine) rank += count_below64(s_ck + c * kWave, key);
+        if (rank >= n) continue;  // cannot happen for unique keys; never write out of range
+        out_key[rank] = key;
+        if (out_val) out_val[rank] = s_cv[e];
+    }
     __syncthreads();
 }
 
 __device__ __forceinline__ void copy_particle(const Parts &p, int64_t dst, int64_t src) {
-    for (int c = 0; c < p.dim; ++c) p.pos[c][dst] = p.pos[c][src];
-    for (int f = 0; f < p.nc; ++f) p.car[f][dst] = p.car[f][src];
-    p.label[dst] = p.label[src];
-    p.id[dst] = p.id[src];
+    float v[3 + SPH_MAX_CARRIED];
+    for (int c = 0; c < p.dim; ++c) v[c] = p.pos[c][src];
+    for (int f = 0; f < p.nc; ++f) v[3 + f] = p.car[f][src];
+    const int32_t lab = p.label[src];
+    const int64_t id = p.id[src];
+    for (int c = 0; c < p.dim; ++c) p.pos[c][dst] = v[c];
+    for (int f = 0; f < p.nc; ++f) p.car[f][dst] = v[3 + f];
+    p.label[dst] = lab;
+    p.id[dst] = id;
 }
 
+// One workgroup: status checks before any write, then (only if all pass) the
+// canonical layout: sort generated sources and deleted indices, write recycled
+// positions and relabels, refill holes below the new count from the surviving
+// tail in ascending order, append the duplicates with fresh ids.
 __global__ __launch_bounds__(kFinBlock) void k_finalize(FinArgs a) {
-    __shared__ unsigned long long s_key[kMaxEv];
+    __shared__ uint32_t s_ck[kMaxEv];     // sort chunks; later the movers
+    __shared__ uint32_t s_cv[kMaxEv];     // sort chunk payloads
+    __shared__ uint32_t s_gslot[kMaxEv];  // duplicate slot of the j-th smallest source
+    __shared__ uint32_t s_del[kMaxEv];    // deleted indices, ascending
     __shared__ unsigned s_bits[kMaxEv / 32];
     __shared__ unsigned s_wpre[kMaxEv / 32];
-    __shared__ int32_t s_mov[kMaxEv];
     __shared__ int s_status;
-    __shared__ unsigned s_G, s_D, s_R;
+    __shared__ unsigned s_G, s_D, s_R, s_taildel;
     __shared__ long long s_N, s_next;
+    __shared__ unsigned s_found[SPH_MAX_BUFFERS], s_post[SPH_MAX_BUFFERS];
+    __shared__ long long s_nl[SPH_MAX_BUFFERS];
+    __shared__ unsigned s_flags[2];
     Ctl *c = a.e.ctl;
-    if (threadIdx.x == 0) {
-        const unsigned G = c->n_gen, D = c->n_del, R = c->n_rel;
-        const long long N_raw = *a.p.n_dev;
-        const long long N = live_count(a.p.n_dev, a.p.capacity);
-        const long long next = c->next_id;
-        int st = SPH_OK;
-        if (N_raw != N) st = SPH_ERR_ARG;
-        else if (a.local && c->scan_fault) st = SPH_ERR_HIP;
-        else if (c->nonfinite_epoch == a.epoch) st = SPH_ERR_NONFINITE;
-        for (int k = 0; k < a.nb && st == SPH_OK; ++k)
-            if ((long long)c->found[k] < c->n_labelled[k]) st = SPH_ERR_CFL;
-        if (st == SPH_OK && (G > a.e.cap_ev || D > a.e.cap_ev || R > a.e.cap_rel)) st = SPH_ERR_EVENTS;
-        if (st == SPH_OK && N - (long long)D + (long long)G > a.p.capacity) st = SPH_ERR_CAPACITY;
-        sph_result *r = a.result;
-        r->status = st;
-        r->n_buffers = a.nb;
-        r->n_generated = st == SPH_OK ? G : 0;
-        r->n_deleted = st == SPH_OK ? D : 0;
-        r->n_before = N;
-        r->n_after = st == SPH_OK ? N - (long long)D + (long long)G : N;
-        r->next_id = st == SPH_OK ? next + G : next;
-        for (int k = 0; k < SPH_MAX_BUFFERS; ++k) {
-            const long long post = k < a.nb ? (long long)c->post[k] : 0;
-            const long long nl = st == SPH_OK && k < a.nb ? post : c->n_labelled[k];
-            r->n_labelled[k] = nl;
-            c->n_labelled[k] = nl;
-            c->found[k] = 0ull;
-            c->post[k] = 0ull;
-        }
-        c->n_gen = c->n_del = c->n_rel = 0u;
-        if (st == SPH_OK) {
-            c->next_id = next + G;
-            *a.p.n_dev = N - (long long)D + (long long)G;
-        }
-        s_status = st;
-        s_G = G;
-        s_D = D;
-        s_R = R;
-        s_N = N;
-        s_next = next;
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    // ---- gather what the status decision needs, in parallel ----
+    if (tid < SPH_MAX_BUFFERS) {
+        s_found[tid] = 0u;
+        s_post[tid] = 0u;
+        s_nl[tid] = c->n_labelled[tid];
+    }
+    if (tid == kWave) {
+        s_G = c->n_gen;
+        s_D = c->n_del;
+        s_R = c->n_rel;
+        s_next = c->next_id;
+        s_N = *a.p.n_dev;
+        s_flags[0] = c->scan_fault;
+        s_flags[1] = c->nonfinite_epoch;
     }
     __syncthreads();
-    if (s_status != SPH_OK) return;
+    for (int b0 = 0; b0 < a.n_part; b0 += blockDim.x) {  // uniform trip count: waves stay converged
+        const int b = b0 + tid;
+        const unsigned *pp = a.e.part + (size_t)b * 2 * SPH_MAX_BUFFERS;
+        for (int k = 0; k < a.nb; ++k) {
+            unsigned f = b < a.n_part ? pp[2 * k] : 0u, q = b < a.n_part ? pp[2 * k + 1] : 0u;
+            for (int off = 32; off > 0; off >>= 1) {
+                f += __shfl_xor(f, off);
+                q += __shfl_xor(q, off);
+            }
+            if (lane == 0 && (f | q)) {
+                atomicAdd(&s_found[k], f);
+                atomicAdd(&s_post[k], q);
+            }
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        const unsigned G = s_G, D = s_D, R = s_R;
+        const long long N_raw = s_N;
+        const long long N = N_raw < 0 ? 0 : (N_raw > a.p.capacity ? a.p.capacity : N_raw);
+        int st = SPH_OK;
+        if (N_raw != N) st = SPH_ERR_ARG;
+        else if (a.local && s_flags[0]) st = SPH_ERR_HIP;
+        else if (s_flags[1] == a.epoch) st = SPH_ERR_NONFINITE;
+        for (int k = 0; k < a.nb && st == SPH_OK; ++k)
+            if ((long long)s_found[k] < s_nl[k]) st = SPH_ERR_CFL;
+        if (st == SPH_OK && (G > a.e.cap_ev || D > a.e.cap_ev || R > a.e.cap_rel)) st = SPH_ERR_EVENTS;
+        if (st == SPH_OK && N - (long long)D + (long long)G > a.p.capacity) st = SPH_ERR_CAPACITY;
+        s_status = st;
+        s_N = N;
+    }
+    __syncthreads();
+    {
+        const int st = s_status;
+        const unsigned G = s_G, D = s_D;
+        const long long N = s_N;
+        sph_result *r = a.result;
+        if (tid < SPH_MAX_BUFFERS) {
+            const long long nl = st == SPH_OK && tid < a.nb ? (long long)s_post[tid] : s_nl[tid];
+            r->n_labelled[tid] = nl;
+            c->n_labelled[tid] = nl;
+        }
+        if (tid == kWave) {
+            r->status = st;
+            r->n_buffers = a.nb;
+            r->n_generated = st == SPH_OK ? G : 0;
+            r->n_deleted = st == SPH_OK ? D : 0;
+            r->n_before = N;
+            r->n_after = st == SPH_OK ? N - (long long)D + (long long)G : N;
+            r->next_id = st == SPH_OK ? s_next + G : s_next;
+            c->n_gen = c->n_del = c->n_rel = 0u;
+            if (st == SPH_OK) {
+                c->next_id = s_next + G;
+                *a.p.n_dev = N - (long long)D + (long long)G;
+            }
+        }
+    }
+    if (s_status != SPH_OK) return;  // block-uniform
     const Parts &p = a.p;
     const unsigned G = s_G, D = s_D, R = s_R;
     const long long N = s_N, Np = N - (long long)D;
-    const int dim = p.dim, nc = p.nc, ds = a.dup_stride;
+    const int dim = p.dim, nc = p.nc;
 
-    // generated sources in ascending index order; capture, then recycle
-    block_sort(a.e.gen, G, s_key);
-    for (unsigned j = threadIdx.x; j < G; j += blockDim.x) {
-        const unsigned long long key = s_key[j];
-        const int64_t i = (int64_t)(key >> 32);
-        const BufDev &b = a.bufs[key & 0xffu];
-        for (int q = 0; q < dim; ++q) {
-            const float v = p.pos[q][i];
-            a.dup[(size_t)j * ds + q] = v;
-            p.pos[q][i] = (float)((double)v - b.shift[q]);
-        }
-        for (int f = 0; f < nc; ++f) a.dup[(size_t)j * ds + dim + f] = p.car[f][i];
+    // ---- order: sources ascending (with their duplicate slots), deleted ascending ----
+    block_sort_u32(a.e.gen_idx, G, s_ck, s_cv, a.gen_sorted, s_gslot);
+    block_sort_u32(a.e.del_idx, D, s_ck, s_cv, s_del, nullptr);
+    for (unsigned j = tid; j < D; j += blockDim.x) a.del_sorted[j] = s_del[j];
+    const unsigned nw = (D + 31) / 32;
+    for (unsigned w = tid; w < nw; w += blockDim.x) s_bits[w] = 0u;
+
+    // ---- recycle and relabel: plain stores of values prepared by the classify step ----
+    for (unsigned s = tid; s < G; s += blockDim.x) {
+        const int64_t i = a.e.gen_idx[s];
+        for (int q = 0; q < dim; ++q) p.pos[q][i] = a.e.gen_new[3 * (size_t)s + q];
     }
-    for (unsigned r = threadIdx.x; r < R; r += blockDim.x) {
+    for (unsigned r = tid; r < R; r += blockDim.x) {
         const unsigned long long e = a.e.rel[r];
         p.label[(int64_t)(e >> 32)] = (int32_t)(unsigned)(e & 0xffffffffull);
     }
     __syncthreads();
 
-    // deleted indices ascending; holes below Np are refilled from the tail
-    block_sort(a.e.del, D, s_key);
-    const unsigned nw = (D + 31) / 32;
-    for (unsigned w = threadIdx.x; w < nw; w += blockDim.x) s_bits[w] = 0u;
-    __syncthreads();
-    for (unsigned j = threadIdx.x; j < D; j += blockDim.x) {
-        const long long idx = (long long)(s_key[j] >> 32);
+    // ---- movers: surviving particles of the tail [Np, N), ascending ----
+    for (unsigned j = tid; j < D; j += blockDim.x) {
+        const long long idx = s_del[j];
         if (idx >= Np) atomicOr(&s_bits[(idx - Np) >> 5], 1u << ((idx - Np) & 31));
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned acc = 0;
+    if (tid == 0) {
+        unsigned acc = 0, td = 0;
         for (unsigned w = 0; w < nw; ++w) {
+            const unsigned pc = (unsigned)__popc(s_bits[w]);
             s_wpre[w] = acc;
-            acc += 32u - (unsigned)__popc(s_bits[w]);
+            acc += 32u - pc;
+            td += pc;
         }
+        s_taildel = td;
     }
     __syncthreads();
-    for (unsigned q = threadIdx.x; q < D; q += blockDim.x) {
+    for (unsigned q = tid; q < D; q += blockDim.x) {
         const unsigned w = q >> 5, bit = q & 31;
-        if (!(s_bits[w] >> bit & 1u)) {
-            const unsigned rank = s_wpre[w] + bit - (unsigned)__popc(s_bits[w] & ((1u << bit) - 1u));
-            s_mov[rank] = (int32_t)(Np + q);
-        }
+        if (!(s_bits[w] >> bit & 1u))
+            s_ck[s_wpre[w] + bit - (unsigned)__popc(s_bits[w] & ((1u << bit) - 1u))] = (uint32_t)(Np + q);
     }
     __syncthreads();
-    unsigned tail_del = 0;
-    for (unsigned w = 0; w < nw; ++w) tail_del += (unsigned)__popc(s_bits[w]);
-    const unsigned h = D - tail_del;
-    for (unsigned j = threadIdx.x; j < h; j += blockDim.x)
-        copy_particle(p, (int64_t)(s_key[j] >> 32), s_mov[j]);
+    const unsigned h = D - s_taildel;
+    for (unsigned j = tid; j < h; j += blockDim.x) copy_particle(p, s_del[j], s_ck[j]);
     __syncthreads();
 
-    // append the duplicates: label 0, fresh ids
-    for (unsigned j = threadIdx.x; j < G; j += blockDim.x) {
+    // ---- append the duplicates in ascending source order: label 0, fresh ids ----
+    for (unsigned j = tid; j < G; j += blockDim.x) {
         const int64_t dst = Np + j;
-        for (int q = 0; q < dim; ++q) p.pos[q][dst] = a.dup[(size_t)j * ds + q];
-        for (int f = 0; f < nc; ++f) p.car[f][dst] = a.dup[(size_t)j * ds + dim + f];
+        const float *d = a.e.dup + (size_t)s_gslot[j] * kDupStride;
+        for (int q = 0; q < dim; ++q) p.pos[q][dst] = d[q];
+        for (int f = 0; f < nc; ++f) p.car[f][dst] = d[3 + f];
         p.label[dst] = 0;
         p.id[dst] = s_next + (long long)j;
     }
@@ -775,6 +1095,7 @@ struct sph_ctx {
     int device = 0;
     int build_blocks = 0;
     int full_blocks = 0;
+    int fused_blocks = 0;        // grid of the one-launch build (0: three-kernel build)
     unsigned epoch = 0;          // incremented per build / full scan
     bool built = false;          // a build is pending for the next local update
     int64_t built_capacity = 0;
@@ -795,12 +1116,23 @@ struct sph_ctx {
     unsigned long long *d_keyrank = nullptr, *d_tile_state = nullptr;
     int64_t n_tiles = 0;
 
-    unsigned long long *d_gen = nullptr, *d_del = nullptr, *d_rel = nullptr;
-    float *d_dup = nullptr;
+    uint32_t *d_gen_idx = nullptr, *d_del_idx = nullptr, *d_gen_sorted = nullptr, *d_del_sorted = nullptr;
+    float *d_gen_new = nullptr, *d_dup = nullptr;
+    unsigned long long *d_rel = nullptr;
     Ctl *d_ctl = nullptr;
+    unsigned *d_part = nullptr;
+    int32_t *d_block_sum = nullptr;
     sph_result *d_result = nullptr;
     sph_result *h_result = nullptr;  // pinned
     bool any_update = false;
+
+    // optional per-launch timing
+    bool prof_on = false;
+    std::vector<hipEvent_t> prof_ev;  // 2 per slot
+    std::vector<int> prof_phase;      // phase of each used slot
+    size_t prof_used = 0;
+    double prof_ms[SPH_NPHASE] = {};
+    int64_t prof_n[SPH_NPHASE] = {};
 };
 
 namespace {
@@ -809,6 +1141,36 @@ namespace {
     do {                                            \
         if ((expr) != hipSuccess) return SPH_ERR_HIP; \
     } while (0)
+
+constexpr size_t kProfSlots = 8192;
+
+// Bracket one launch with events when profiling is on (a no-op otherwise).
+struct ProfScope {
+    sph_ctx *c;
+    size_t slot = 0;
+    bool on = false;
+    ProfScope(sph_ctx *ctx, int phase) : c(ctx) {
+        if (!c->prof_on || c->prof_used >= kProfSlots) return;
+        slot = c->prof_used++;
+        c->prof_phase[slot] = phase;
+        on = hipEventRecord(c->prof_ev[2 * slot], c->stream) == hipSuccess;
+    }
+    ~ProfScope() {
+        if (on) (void)hipEventRecord(c->prof_ev[2 * slot + 1], c->stream);
+    }
+};
+
+void prof_drain(sph_ctx *c) {
+    for (size_t s = 0; s < c->prof_used; ++s) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(c->prof_ev[2 * s + 1]) == hipSuccess &&
+            hipEventElapsedTime(&ms, c->prof_ev[2 * s], c->prof_ev[2 * s + 1]) == hipSuccess) {
+            c->prof_ms[c->prof_phase[s]] += ms;
+            c->prof_n[c->prof_phase[s]] += 1;
+        }
+    }
+    c->prof_used = 0;
+}
 
 sph_status parts_of(const sph_ctx *ctx, const sph_particles *p, Parts &out) {
     if (!p || !p->pos[0] || !p->pos[1] || (ctx->dim == 3 && !p->pos[2]) || !p->label || !p->id || !p->n_dev)
@@ -844,26 +1206,32 @@ Grid grid_of(const sph_ctx *ctx) {
 EventArgs events_of(const sph_ctx *ctx) {
     EventArgs e{};
     e.ctl = ctx->d_ctl;
-    e.gen = ctx->d_gen;
-    e.del = ctx->d_del;
+    e.gen_idx = ctx->d_gen_idx;
+    e.gen_new = ctx->d_gen_new;
+    e.dup = ctx->d_dup;
+    e.del_idx = ctx->d_del_idx;
     e.rel = ctx->d_rel;
     e.cap_ev = ctx->max_events;
     e.cap_rel = ctx->max_events * kRelPerEvent;
+    e.part = ctx->d_part;
     return e;
 }
 
-sph_status launch_finalize(sph_ctx *ctx, const Parts &pp, bool local) {
+sph_status launch_finalize(sph_ctx *ctx, const Parts &pp, bool local, int n_part) {
     FinArgs f{};
     f.p = pp;
     f.local = local ? 1 : 0;
-    f.bufs = ctx->d_bufs;
+    f.n_part = n_part;
     f.nb = ctx->nb;
     f.epoch = ctx->epoch;
     f.e = events_of(ctx);
-    f.dup = ctx->d_dup;
-    f.dup_stride = 3 + SPH_MAX_CARRIED;
+    f.gen_sorted = ctx->d_gen_sorted;
+    f.del_sorted = ctx->d_del_sorted;
     f.result = ctx->d_result;
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinBlock), 0, ctx->stream, f);
+    {
+        ProfScope ps(ctx, SPH_PHASE_FINALIZE);
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinBlock), 0, ctx->stream, f);
+    }
     HIP_TRY(hipGetLastError());
     ctx->any_update = true;
     return SPH_OK;
@@ -886,13 +1254,19 @@ void free_ctx(sph_ctx *c) {
     (void)hipFree(c->d_cell_idx);
     (void)hipFree(c->d_keyrank);
     (void)hipFree(c->d_tile_state);
-    (void)hipFree(c->d_gen);
-    (void)hipFree(c->d_del);
+    (void)hipFree(c->d_gen_idx);
+    (void)hipFree(c->d_del_idx);
+    (void)hipFree(c->d_gen_sorted);
+    (void)hipFree(c->d_del_sorted);
+    (void)hipFree(c->d_gen_new);
     (void)hipFree(c->d_rel);
     (void)hipFree(c->d_dup);
     (void)hipFree(c->d_ctl);
+    (void)hipFree(c->d_part);
+    (void)hipFree(c->d_block_sum);
     (void)hipFree(c->d_result);
     if (c->h_result) (void)hipHostFree(c->h_result);
+    for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
     delete c;
 }
 
@@ -936,7 +1310,7 @@ extern "C" sph_status sph_create(const sph_config *cfg, sph_ctx **out) {
     // grid sizes: a multiple of 8 blocks (XCD renumbering), enough to fill 256 CUs
     const int64_t want = (cfg->capacity + kBuildBlock - 1) / kBuildBlock;
     c->build_blocks = (int)std::max<int64_t>(8, std::min<int64_t>(8192, (want + 7) / 8 * 8));
-    c->full_blocks = c->build_blocks;
+    c->full_blocks = std::min(c->build_blocks, kMaxPartBlocks);
     const int64_t m = c->n_cells + 1;
     c->n_tiles = (m + kScanTile - 1) / kScanTile;
     const size_t ev = c->max_events;
@@ -946,11 +1320,16 @@ extern "C" sph_status sph_create(const sph_config *cfg, sph_ctx **out) {
               hipMalloc(&c->d_cell_idx, sizeof(int32_t) * c->capacity) == hipSuccess &&
               hipMalloc(&c->d_keyrank, sizeof(unsigned long long) * c->capacity) == hipSuccess &&
               hipMalloc(&c->d_tile_state, sizeof(unsigned long long) * c->n_tiles) == hipSuccess &&
-              hipMalloc(&c->d_gen, sizeof(unsigned long long) * ev) == hipSuccess &&
-              hipMalloc(&c->d_del, sizeof(unsigned long long) * ev) == hipSuccess &&
+              hipMalloc(&c->d_gen_idx, sizeof(uint32_t) * ev) == hipSuccess &&
+              hipMalloc(&c->d_del_idx, sizeof(uint32_t) * ev) == hipSuccess &&
+              hipMalloc(&c->d_gen_sorted, sizeof(uint32_t) * ev) == hipSuccess &&
+              hipMalloc(&c->d_del_sorted, sizeof(uint32_t) * ev) == hipSuccess &&
+              hipMalloc(&c->d_gen_new, sizeof(float) * ev * 3) == hipSuccess &&
               hipMalloc(&c->d_rel, sizeof(unsigned long long) * ev * kRelPerEvent) == hipSuccess &&
-              hipMalloc(&c->d_dup, sizeof(float) * ev * (3 + SPH_MAX_CARRIED)) == hipSuccess &&
+              hipMalloc(&c->d_dup, sizeof(float) * ev * kDupStride) == hipSuccess &&
               hipMalloc(&c->d_ctl, sizeof(Ctl)) == hipSuccess &&
+              hipMalloc(&c->d_part, sizeof(unsigned) * 2 * SPH_MAX_BUFFERS * kMaxPartBlocks) == hipSuccess &&
+              hipMalloc(&c->d_block_sum, sizeof(int32_t) * kMaxPartBlocks) == hipSuccess &&
               hipMalloc(&c->d_result, sizeof(sph_result)) == hipSuccess &&
               hipHostMalloc(&c->h_result, sizeof(sph_result), hipHostMallocDefault) == hipSuccess;
     if (ok) {
@@ -970,6 +1349,21 @@ extern "C" sph_status sph_create(const sph_config *cfg, sph_ctx **out) {
         return SPH_ERR_HIP;
     }
     c->epoch = 1;
+    // one-launch build: every block must be resident at once (cooperative launch)
+    {
+        int coop = 0, cus = 0, per_cu = 0;
+        if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, c->device) == hipSuccess && coop &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess &&
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(k_build_fused),
+                                                         kFusedBlock, 0) == hipSuccess &&
+            per_cu > 0) {
+            int g = cus * per_cu;
+            g = std::min(g, kMaxPartBlocks) / 8 * 8;
+            c->fused_blocks = g >= 8 ? g : 0;
+        }
+        const char *env = std::getenv("SPHBUF_BUILD");
+        if (env && std::strcmp(env, "split") == 0) c->fused_blocks = 0;
+    }
     *out = c;
     return SPH_OK;
 }
@@ -1006,8 +1400,18 @@ extern "C" sph_status sph_buffer_define(sph_ctx *ctx, sph_kind kind, const doubl
                                           ctx->b_margin[k]))
             return SPH_ERR_OVERLAP;
     std::vector<int32_t> first, len;
-    const sph_status cs = sphbuf::grid_cover(dim, ctx->lo, ctx->cs, ctx->dims, o, q, h, margin, first, len);
-    if (cs != SPH_OK) return cs;
+    {
+        std::vector<int32_t> f0, l0;
+        const sph_status cs = sphbuf::grid_cover(dim, ctx->lo, ctx->cs, ctx->dims, o, q, h, margin, f0, l0);
+        if (cs != SPH_OK) return cs;
+        // one wave takes one run: cap runs at about a wave's worth of candidates
+        const int cap = dim == 3 ? 4 : 12;
+        for (size_t r = 0; r < f0.size(); ++r)
+            for (int s = 0; s < l0[r]; s += cap) {
+                first.push_back(f0[r] + s);
+                len.push_back(std::min(cap, l0[r] - s));
+            }
+    }
 
     const int k = ctx->nb;
     BufDev b{};
@@ -1083,6 +1487,36 @@ extern "C" sph_status sph_celllist_build(sph_ctx *ctx, const sph_particles *p) {
     const sph_status st = parts_of(ctx, p, pp);
     if (st != SPH_OK) return st;
     ctx->epoch++;
+    if (ctx->fused_blocks > 0) {
+        FusedArgs fa{};
+        fa.x = pp.pos[0];
+        fa.y = pp.pos[1];
+        fa.z = pp.pos[2];
+        fa.n_dev = pp.n_dev;
+        fa.capacity = pp.capacity;
+        fa.g = grid_of(ctx);
+        fa.count = ctx->d_count;
+        fa.cell_start = ctx->d_cell_start;
+        fa.cell_idx = ctx->d_cell_idx;
+        fa.keyrank = ctx->d_keyrank;
+        fa.block_sum = ctx->d_block_sum;
+        fa.m = ctx->n_cells + 1;
+        fa.ctl = ctx->d_ctl;
+        fa.epoch = ctx->epoch;
+        void *args[] = {&fa};
+        hipError_t e;
+        {
+            ProfScope ps(ctx, SPH_PHASE_BUILD);
+            e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_build_fused), dim3(ctx->fused_blocks),
+                                           dim3(kFusedBlock), args, 0, ctx->stream);
+        }
+        if (e == hipSuccess) {
+            ctx->built = true;
+            return SPH_OK;
+        }
+        (void)hipGetLastError();
+        ctx->fused_blocks = 0;  // not available here: fall back to the three-kernel build
+    }
     CountArgs ca{};
     ca.x = pp.pos[0];
     ca.y = pp.pos[1];
@@ -1096,7 +1530,10 @@ extern "C" sph_status sph_celllist_build(sph_ctx *ctx, const sph_particles *p) {
     ca.n_tiles = ctx->n_tiles;
     ca.ctl = ctx->d_ctl;
     ca.epoch = ctx->epoch;
-    hipLaunchKernelGGL(k_count, dim3(ctx->build_blocks), dim3(kBuildBlock), 0, ctx->stream, ca);
+    {
+        ProfScope ps(ctx, SPH_PHASE_COUNT);
+        hipLaunchKernelGGL(k_count, dim3(ctx->build_blocks), dim3(kBuildBlock), 0, ctx->stream, ca);
+    }
     HIP_TRY(hipGetLastError());
     ScanArgs sa{};
     sa.count = ctx->d_count;
@@ -1104,7 +1541,10 @@ extern "C" sph_status sph_celllist_build(sph_ctx *ctx, const sph_particles *p) {
     sa.m = ctx->n_cells + 1;
     sa.tile_state = ctx->d_tile_state;
     sa.ctl = ctx->d_ctl;
-    hipLaunchKernelGGL(k_scan, dim3((unsigned)ctx->n_tiles), dim3(kScanBlock), 0, ctx->stream, sa);
+    {
+        ProfScope ps(ctx, SPH_PHASE_SCAN);
+        hipLaunchKernelGGL(k_scan, dim3((unsigned)ctx->n_tiles), dim3(kScanBlock), 0, ctx->stream, sa);
+    }
     HIP_TRY(hipGetLastError());
     ScatterArgs xa{};
     xa.n_dev = pp.n_dev;
@@ -1113,7 +1553,10 @@ extern "C" sph_status sph_celllist_build(sph_ctx *ctx, const sph_particles *p) {
     xa.keyrank = ctx->d_keyrank;
     xa.cell_start = ctx->d_cell_start;
     xa.cell_idx = ctx->d_cell_idx;
-    hipLaunchKernelGGL(k_scatter, dim3(ctx->build_blocks), dim3(kBuildBlock), 0, ctx->stream, xa);
+    {
+        ProfScope ps(ctx, SPH_PHASE_SCATTER);
+        hipLaunchKernelGGL(k_scatter, dim3(ctx->build_blocks), dim3(kBuildBlock), 0, ctx->stream, xa);
+    }
     HIP_TRY(hipGetLastError());
     ctx->built = true;
     return SPH_OK;
@@ -1125,6 +1568,7 @@ extern "C" sph_status sph_buffer_update_async(sph_ctx *ctx, sph_particles *p) {
     Parts pp;
     const sph_status st = parts_of(ctx, p, pp);
     if (st != SPH_OK) return st;
+    int n_part = 0;
     if (ctx->n_runs > 0) {
         LocalArgs la{};
         la.p = pp;
@@ -1138,12 +1582,13 @@ extern "C" sph_status sph_buffer_update_async(sph_ctx *ctx, sph_particles *p) {
         la.cell_idx = ctx->d_cell_idx;
         la.e = events_of(ctx);
         const int wpb = kClassifyBlock / kWave;
-        const int blocks = std::max(1, std::min(65535, (ctx->n_runs + wpb - 1) / wpb));
-        hipLaunchKernelGGL(k_classify_local, dim3(blocks), dim3(kClassifyBlock), 0, ctx->stream, la);
+        n_part = std::max(1, std::min(kMaxPartBlocks, (ctx->n_runs + wpb - 1) / wpb));
+        ProfScope ps(ctx, SPH_PHASE_CLASSIFY);
+        hipLaunchKernelGGL(k_classify_local, dim3(n_part), dim3(kClassifyBlock), 0, ctx->stream, la);
         HIP_TRY(hipGetLastError());
     }
     ctx->built = false;
-    return launch_finalize(ctx, pp, true);
+    return launch_finalize(ctx, pp, true, n_part);
 }
 
 static sph_status fullscan_enqueue(sph_ctx *ctx, sph_particles *p) {
@@ -1158,10 +1603,13 @@ static sph_status fullscan_enqueue(sph_ctx *ctx, sph_particles *p) {
     fa.nb = ctx->nb;
     fa.e = events_of(ctx);
     fa.epoch = ctx->epoch;
-    hipLaunchKernelGGL(k_classify_full, dim3(ctx->full_blocks), dim3(kClassifyBlock), 0, ctx->stream, fa);
+    {
+        ProfScope ps(ctx, SPH_PHASE_FULLSCAN);
+        hipLaunchKernelGGL(k_classify_full, dim3(ctx->full_blocks), dim3(kClassifyBlock), 0, ctx->stream, fa);
+    }
     HIP_TRY(hipGetLastError());
     ctx->built = false;
-    return launch_finalize(ctx, pp, false);
+    return launch_finalize(ctx, pp, false, ctx->full_blocks);
 }
 
 extern "C" sph_status sph_buffer_update_fullscan_async(sph_ctx *ctx, sph_particles *p) {
@@ -1206,16 +1654,16 @@ extern "C" sph_status sph_last_events(sph_ctx *ctx, int64_t *gen_src, int64_t *d
     *n_gen = r.status == SPH_OK ? r.n_generated : 0;
     *n_del = r.status == SPH_OK ? r.n_deleted : 0;
     const int64_t g = std::min<int64_t>(cap, *n_gen), d = std::min<int64_t>(cap, *n_del);
-    std::vector<unsigned long long> tmp((size_t)std::max<int64_t>(1, std::max(g, d)));
+    std::vector<uint32_t> tmp((size_t)std::max<int64_t>(1, std::max(g, d)));
     if (g > 0) {
         if (!gen_src) return SPH_ERR_ARG;
-        HIP_TRY(hipMemcpy(tmp.data(), ctx->d_gen, sizeof(unsigned long long) * g, hipMemcpyDeviceToHost));
-        for (int64_t j = 0; j < g; ++j) gen_src[j] = (int64_t)(tmp[j] >> 32);
+        HIP_TRY(hipMemcpy(tmp.data(), ctx->d_gen_sorted, sizeof(uint32_t) * g, hipMemcpyDeviceToHost));
+        for (int64_t j = 0; j < g; ++j) gen_src[j] = (int64_t)tmp[j];
     }
     if (d > 0) {
         if (!del_idx) return SPH_ERR_ARG;
-        HIP_TRY(hipMemcpy(tmp.data(), ctx->d_del, sizeof(unsigned long long) * d, hipMemcpyDeviceToHost));
-        for (int64_t j = 0; j < d; ++j) del_idx[j] = (int64_t)(tmp[j] >> 32);
+        HIP_TRY(hipMemcpy(tmp.data(), ctx->d_del_sorted, sizeof(uint32_t) * d, hipMemcpyDeviceToHost));
+        for (int64_t j = 0; j < d; ++j) del_idx[j] = (int64_t)tmp[j];
     }
     return SPH_OK;
 }
@@ -1275,5 +1723,38 @@ extern "C" sph_status sph_state_set(sph_ctx *ctx, int64_t next_id, const int64_t
         HIP_TRY(hipMemcpyAsync(ctx->d_ctl->n_labelled, n_labelled, sizeof(int64_t) * SPH_MAX_BUFFERS,
                                hipMemcpyHostToDevice, ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return SPH_OK;
+}
+
+extern "C" sph_status sph_profile_enable(sph_ctx *ctx, int32_t on) {
+    if (!ctx) return SPH_ERR_ARG;
+    if (on && ctx->prof_ev.empty()) {
+        ctx->prof_ev.resize(2 * kProfSlots);
+        ctx->prof_phase.resize(kProfSlots);
+        for (auto &e : ctx->prof_ev)
+            if (hipEventCreate(&e) != hipSuccess) return SPH_ERR_HIP;
+    }
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    ctx->prof_used = 0;
+    for (int i = 0; i < SPH_NPHASE; ++i) {
+        ctx->prof_ms[i] = 0.0;
+        ctx->prof_n[i] = 0;
+    }
+    ctx->prof_on = on != 0;
+    return SPH_OK;
+}
+
+extern "C" sph_status sph_profile_read(sph_ctx *ctx, double ms[SPH_NPHASE], int64_t launches[SPH_NPHASE],
+                                       int32_t reset) {
+    if (!ctx) return SPH_ERR_ARG;
+    prof_drain(ctx);
+    for (int i = 0; i < SPH_NPHASE; ++i) {
+        if (ms) ms[i] = ctx->prof_ms[i];
+        if (launches) launches[i] = ctx->prof_n[i];
+        if (reset) {
+            ctx->prof_ms[i] = 0.0;
+            ctx->prof_n[i] = 0;
+        }
+    }
     return SPH_OK;
 }

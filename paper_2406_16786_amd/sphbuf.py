@@ -30,8 +30,10 @@ EXPORTED = (
     "sph_buffer_update_fullscan_async", "sph_last_result", "sph_last_events", "sph_celllist_view",
     "sph_state_get", "sph_state_set", "sph_rotation_2d", "sph_rotation_axis_angle",
     "sph_rotation_from_direction", "sph_check_rotation", "sph_grid_cover", "sph_guard_band",
-    "sph_status_str",
+    "sph_status_str", "sph_profile_enable", "sph_profile_read",
 )
+SPH_NPHASE = 7
+PHASES = ("count", "scan", "scatter", "classify", "fullscan", "finalize", "build")
 
 
 class sph_particles(ctypes.Structure):
@@ -119,6 +121,8 @@ def lib() -> ctypes.CDLL:
             "sph_guard_band": ([ctypes.c_int32, _D, _D, ctypes.c_double, ctypes.c_double, ctypes.c_double],
                                ctypes.c_double),
             "sph_status_str": ([ctypes.c_int], ctypes.c_char_p),
+            "sph_profile_enable": ([_VP, ctypes.c_int32], ctypes.c_int),
+            "sph_profile_read": ([_VP, _D, _I64, ctypes.c_int32], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -275,6 +279,17 @@ def sph_grid_cover(dim: int, lo, cell_size: float, dims, origin, rot, half, marg
 
 def sph_guard_band(dim: int, origin, half, margin: float, cell_size: float, dp: float) -> float:
     return lib().sph_guard_band(int(dim), _d3(origin), _d3(half), float(margin), float(cell_size), float(dp))
+
+
+def sph_profile_enable(ctx: int, on: bool) -> int:
+    return lib().sph_profile_enable(ctx, 1 if on else 0)
+
+
+def sph_profile_read(ctx: int, reset: bool = False):
+    ms = np.zeros(SPH_NPHASE)
+    n = np.zeros(SPH_NPHASE, dtype=np.int64)
+    st = lib().sph_profile_read(ctx, ms.ctypes.data_as(_D), n.ctypes.data_as(_I64), 1 if reset else 0)
+    return st, ms, n
 
 
 # ------------------------------------------------------------- marshalling ---

@@ -83,8 +83,10 @@ def _run_steps(wl, steps, mode="local", identify=True, check_every=1, cell_size=
 
 # ------------------------------------------------------------- cell list ---
 
+@pytest.mark.parametrize("build", ["fused", "split"])
 @pytest.mark.parametrize("name", ["channel2d", "bent_channel2d", "pipe3d_small"])
-def test_celllist_matches_oracle(name):
+def test_celllist_matches_oracle(name, build, monkeypatch):
+    monkeypatch.setenv("SPHBUF_BUILD", build)
     wl = {"channel2d": W.channel2d, "bent_channel2d": W.bent_channel2d,
           "pipe3d_small": lambda: W.pipe3d(dp=0.004)}[name]()
     bufs = oracle_buffers(wl)
@@ -102,6 +104,24 @@ def test_celllist_matches_oracle(name):
     got = ci[np.lexsort((ci, cell_of))]
     exp = oci[np.lexsort((oci, cell_of))]
     np.testing.assert_array_equal(got, exp)
+    d.close()
+
+
+def test_celllist_beyond_register_slots():
+    """9.5 M random particles: more than the one-launch build keeps on chip
+    (256 blocks x 1024 threads x 32 slots), so part of them take the spill path."""
+    n = 9_500_000
+    pos, car, lab, ids = W.random_box_particles(7, n, 3, (0, 0, 0), (1.0, 0.5, 0.5), capacity=n + 16, n_carried=1)
+    st = make_state(3, np.zeros((0, 3)))
+    st = oracle.State(3, pos, car, lab, ids, n, n)
+    d = make_domain_raw(3, (0, 0, 0), (1.0, 0.5, 0.5), 0.01, 0.004, [], st)
+    d.build()
+    cs, ci, dims = _cell_list(d, n)
+    ocs, oci = oracle.cell_list(3, np.float32([0, 0, 0]), np.float32(1.0 / 0.01), dims, pos[0][:n], pos[1][:n],
+                                pos[2][:n])
+    np.testing.assert_array_equal(cs, ocs)
+    cell_of = np.repeat(np.arange(len(ocs) - 1), np.diff(ocs))
+    np.testing.assert_array_equal(ci[np.lexsort((ci, cell_of))], oci)
     d.close()
 
 
