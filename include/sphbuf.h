@@ -61,7 +61,7 @@ typedef enum { SPH_INLET = 1, SPH_OUTLET = 2, SPH_BIDIR = 3 } sph_kind;
 
 #define SPH_MAX_BUFFERS 15
 #define SPH_MAX_CARRIED 16
-#define SPH_MAX_EVENTS_LIMIT 8192
+#define SPH_MAX_EVENTS_LIMIT 4096
 
 typedef struct sph_ctx sph_ctx;
 
@@ -84,7 +84,7 @@ typedef struct {
     double cell_size;       /* cell edge (2h = 2.6 dp in the paper's setting)                 */
     double dp;              /* particle spacing: the FP32 guard band is max(1e-4 dp, bound)   */
     int64_t capacity;       /* largest particle capacity that will be passed                  */
-    int64_t max_events;     /* per update, for generated and for deleted; <= 8192             */
+    int64_t max_events;     /* per update, for generated and for deleted; <= 4096             */
     int64_t next_id;        /* id of the first duplicate                                      */
     void *stream;           /* hipStream_t (NULL = the null stream)                           */
 } sph_config;
@@ -106,7 +106,7 @@ typedef struct {
 /* Create a context: validates cfg, allocates the cell grid and all scratch on the
  * current HIP device.  SPH_ERR_ARG for a bad config (dim, cell_size <= 0, empty or
  * non-finite bounds, more than 2^31 cells, capacity <= 0 or >= 2^31, max_events
- * outside 1..8192); SPH_ERR_HIP if allocation fails.  *out is NULL on error. */
+ * outside 1..4096); SPH_ERR_HIP if allocation fails.  *out is NULL on error. */
 sph_status sph_create(const sph_config *cfg, sph_ctx **out);
 sph_status sph_destroy(sph_ctx *ctx);
 

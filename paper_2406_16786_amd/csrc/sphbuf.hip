@@ -42,6 +42,7 @@ constexpr int kScanTile = kScanBlock * kScanItems;
 constexpr int kClassifyBlock = 256;
 constexpr int kFinBlock = 1024;
 constexpr unsigned kMaxEv = SPH_MAX_EVENTS_LIMIT;
+static_assert(kMaxEv % kWave == 0, "event lists are sorted in 64-key chunks");
 constexpr int kRelPerEvent = 4;
 constexpr int kMaxPartBlocks = 8192;  // upper bound on classify / full-scan grid sizes
 
@@ -237,12 +238,15 @@ struct EventArgs {
     unsigned long long *rel;   // [cap_rel] (index << 32) | new label
     unsigned cap_ev;
     unsigned cap_rel;
-    unsigned *part;  // per-block label counts: part[(block * 16 + k) * 2 + {0: found, 1: post}]
+    unsigned *part;  // label counts, kCountReplicas copies: part[(copy * 16 + k) * 2 + {0: found, 1: post}]
 };
 
-// Block-level label counts of each buffer: waves add into LDS, then the block
-// writes its own slot of the partial array (no contended global atomics; the
-// finalize step sums the slots).
+// Label counts of each buffer: waves add into LDS, then one thread per buffer
+// adds the block's total into one of kCountReplicas copies of the global
+// counters (picked by block index, so concurrent blocks rarely hit the same
+// address); the finalize step sums the copies and clears them.
+constexpr int kCountReplicas = 64;
+
 __device__ __forceinline__ void block_counts_init(unsigned *s_cnt) {
     if (threadIdx.x < 2 * SPH_MAX_BUFFERS) s_cnt[threadIdx.x] = 0u;
 }
@@ -256,7 +260,9 @@ __device__ __forceinline__ void block_counts_add(unsigned *s_cnt, int k, unsigne
     }
 }
 __device__ __forceinline__ void block_counts_store(const EventArgs &e, const unsigned *s_cnt, int nb) {
-    if (threadIdx.x < 2 * nb) e.part[(size_t)blockIdx.x * 2 * SPH_MAX_BUFFERS + threadIdx.x] = s_cnt[threadIdx.x];
+    if (threadIdx.x < 2 * nb && s_cnt[threadIdx.x])
+        atomicAdd(&e.part[(size_t)(blockIdx.x % kCountReplicas) * 2 * SPH_MAX_BUFFERS + threadIdx.x],
+                  s_cnt[threadIdx.x]);
 }
 
 // Emit the wave's events for buffer k and accumulate its label counts.  A
@@ -528,26 +534,29 @@ struct FusedArgs {
     unsigned epoch;
 };
 
-// Grid-wide barrier for a cooperative launch (all blocks resident).  Every
-// thread releases its writes at agent scope, one thread per block arrives on a
-// counter, the last arrival opens the next generation.  A wait that runs past
-// its spin limit flags a fault and returns false so the kernel can stop before
-// using data it cannot trust.
+// Grid-wide barrier for a cooperative launch (all blocks resident).  Every wave
+// first waits for its own memory operations to complete; one thread per block
+// then releases at agent scope, arrives on a counter and (after the last
+// arrival opens the next generation) acquires at agent scope, which also
+// invalidates the CU's and XCD's caches for the other waves of the block.  A
+// wait that runs past its spin limit flags a fault and returns false so the
+// kernel can stop before using data it cannot trust.
 __device__ bool grid_barrier(Ctl *c, unsigned nblocks) {
     __shared__ int s_ok;
-    __threadfence();
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
         int ok = 1;
-        const unsigned gen = __hip_atomic_load(&c->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const unsigned gen = __hip_atomic_load(&c->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const unsigned arrived = __hip_atomic_fetch_add(&c->bar_count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
         if (arrived == nblocks - 1) {
             __hip_atomic_store(&c->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&c->bar_gen, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             unsigned spins = 0;
-            while (__hip_atomic_load(&c->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-                __builtin_amdgcn_s_sleep(2);
+            while (__hip_atomic_load(&c->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                __builtin_amdgcn_s_sleep(1);
                 if (++spins > (1u << 24)) {
                     atomicOr(&c->scan_fault, 1u);
                     ok = 0;
@@ -555,10 +564,10 @@ __device__ bool grid_barrier(Ctl *c, unsigned nblocks) {
                 }
             }
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         s_ok = ok;
     }
     __syncthreads();
-    __threadfence();
     return s_ok != 0;
 }
 
@@ -824,33 +833,54 @@ __device__ __forceinline__ unsigned count_below64(const uint32_t *c, uint32_t ke
     return lo;
 }
 
-// Sort n (<= kMaxEv) unique 32-bit keys taken from in[]: every wave sorts
-// 64-key chunks in registers, then each key's final rank is its place in its
-// chunk plus, for every other chunk, the number of keys there below it (binary
-// search).  out_key[rank] = key (global), out_val[rank] = its position in in[]
-// (LDS, optional).  Ends with a barrier.
-__device__ void block_sort_u32(const uint32_t *in, unsigned n, uint32_t *s_ck, uint32_t *s_cv, uint32_t *out_key,
-                               uint32_t *out_val) {
-    const unsigned nch = (n + kWave - 1) / kWave;
+// Sort two lists of unique 32-bit keys at once (generated sources, with their
+// list positions as payload, and deleted indices).  The first half of the waves
+// sorts 64-key chunks of list A in registers, the second half those of list B;
+// then each key's final rank is its place in its chunk plus, for every other
+// chunk of its list, the number of keys there below it (binary search).
+// Ends with a barrier.
+__device__ void block_sort_pair(const uint32_t *in_a, unsigned na, const uint32_t *in_b, unsigned nb_,
+                                uint32_t *s_ca, uint32_t *s_va, uint32_t *s_cb, uint32_t *out_a, uint32_t *out_va,
+                                uint32_t *out_b) {
+    const unsigned ncha = (na + kWave - 1) / kWave, nchb = (nb_ + kWave - 1) / kWave;
+    const unsigned nwave = blockDim.x / kWave, half = nwave / 2;
     const unsigned wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-    for (unsigned c = wave; c < nch; c += blockDim.x / kWave) {
-        const unsigned e = c * kWave + lane;
-        uint32_t key = e < n ? in[e] : 0xffffffffu, val = e;
-        wave_sort64(key, val);
-        s_ck[e] = key;
-        s_cv[e] = val;
+    if (wave < half) {
+        for (unsigned c = wave; c < ncha; c += half) {
+            const unsigned e = c * kWave + lane;
+            uint32_t key = e < na ? in_a[e] : 0xffffffffu, val = e;
+            wave_sort64(key, val);
+            s_ca[e] = key;
+            s_va[e] = val;
+        }
+    } else {
+        for (unsigned c = wave - half; c < nchb; c += nwave - half) {
+            const unsigned e = c * kWave + lane;
+            uint32_t key = e < nb_ ? in_b[e] : 0xffffffffu, val = e;
+            wave_sort64(key, val);
+            s_cb[e] = key;
+        }
     }
     __syncthreads();
-    for (unsigned e = threadIdx.x; e < nch * kWave; e += blockDim.x) {
-        const uint32_t key = s_ck[e];
+    const unsigned tot = (ncha + nchb) * kWave;
+    for (unsigned t = threadIdx.x; t < tot; t += blockDim.x) {
+        const bool is_a = t < ncha * kWave;
+        const unsigned e = is_a ? t : t - ncha * kWave;
+        const uint32_t *chunks = is_a ? s_ca : s_cb;
+        const unsigned nch = is_a ? ncha : nchb, n = is_a ? na : nb_;
+        const uint32_t key = chunks[e];
         if (key == 0xffffffffu) continue;
         const unsigned mine = e / kWave;
         unsigned rank = e % kWave;
         for (unsigned c = 0; c < nch; ++c)
-            if (c != mine) rank += count_below64(s_ck + c * kWave, key);
+            if (c != mine) rank += count_below64(chunks + c * kWave, key);
         if (rank >= n) continue;  // cannot happen for unique keys; never write out of range
-        out_key[rank] = key;
-        if (out_val) out_val[rank] = s_cv[e];
+        if (is_a) {
+            out_a[rank] = key;
+            out_va[rank] = s_va[e];
+        } else {
+            out_b[rank] = key;
+        }
     }
     __syncthreads();
 }
@@ -872,8 +902,9 @@ __device__ __forceinline__ void copy_particle(const Parts &p, int64_t dst, int64
 // positions and relabels, refill holes below the new count from the surviving
 // tail in ascending order, append the duplicates with fresh ids.
 __global__ __launch_bounds__(kFinBlock) void k_finalize(FinArgs a) {
-    __shared__ uint32_t s_ck[kMaxEv];     // sort chunks; later the movers
-    __shared__ uint32_t s_cv[kMaxEv];     // sort chunk payloads
+    __shared__ uint32_t s_ck[kMaxEv];     // sort chunks of the sources; later the movers
+    __shared__ uint32_t s_cv[kMaxEv];     // their payloads (positions in the source list)
+    __shared__ uint32_t s_cd[kMaxEv];     // sort chunks of the deleted indices
     __shared__ uint32_t s_gslot[kMaxEv];  // duplicate slot of the j-th smallest source
     __shared__ uint32_t s_del[kMaxEv];    // deleted indices, ascending
     __shared__ unsigned s_bits[kMaxEv / 32];
@@ -903,19 +934,17 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(FinArgs a) {
         s_flags[1] = c->nonfinite_epoch;
     }
     __syncthreads();
-    for (int b0 = 0; b0 < a.n_part; b0 += blockDim.x) {  // uniform trip count: waves stay converged
-        const int b = b0 + tid;
-        const unsigned *pp = a.e.part + (size_t)b * 2 * SPH_MAX_BUFFERS;
-        for (int k = 0; k < a.nb; ++k) {
-            unsigned f = b < a.n_part ? pp[2 * k] : 0u, q = b < a.n_part ? pp[2 * k + 1] : 0u;
-            for (int off = 32; off > 0; off >>= 1) {
-                f += __shfl_xor(f, off);
-                q += __shfl_xor(q, off);
+    {   // the counter copies: 64 x 15 x 2 words, one per thread; zero them for the next update
+        const int words = kCountReplicas * 2 * SPH_MAX_BUFFERS;
+        for (int w0 = 0; w0 < words; w0 += blockDim.x) {  // uniform trip count: waves stay converged
+            const int w = w0 + tid;
+            unsigned v = 0u;
+            if (w < words) {
+                v = a.e.part[w];
+                if (v) a.e.part[w] = 0u;
             }
-            if (lane == 0 && (f | q)) {
-                atomicAdd(&s_found[k], f);
-                atomicAdd(&s_post[k], q);
-            }
+            const int slot = w % (2 * SPH_MAX_BUFFERS);
+            if (v) atomicAdd(slot & 1 ? &s_post[slot >> 1] : &s_found[slot >> 1], v);
         }
     }
     __syncthreads();
@@ -967,8 +996,7 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(FinArgs a) {
     const int dim = p.dim, nc = p.nc;
 
     // ---- order: sources ascending (with their duplicate slots), deleted ascending ----
-    block_sort_u32(a.e.gen_idx, G, s_ck, s_cv, a.gen_sorted, s_gslot);
-    block_sort_u32(a.e.del_idx, D, s_ck, s_cv, s_del, nullptr);
+    block_sort_pair(a.e.gen_idx, G, a.e.del_idx, D, s_ck, s_cv, s_cd, a.gen_sorted, s_gslot, s_del);
     for (unsigned j = tid; j < D; j += blockDim.x) a.del_sorted[j] = s_del[j];
     const unsigned nw = (D + 31) / 32;
     for (unsigned w = tid; w < nw; w += blockDim.x) s_bits[w] = 0u;
@@ -1340,6 +1368,8 @@ extern "C" sph_status sph_create(const sph_config *cfg, sph_ctx **out) {
         ok = hipMemsetAsync(c->d_count, 0, sizeof(int32_t) * m, c->stream) == hipSuccess &&
              hipMemsetAsync(c->d_cell_start, 0, sizeof(int32_t) * m, c->stream) == hipSuccess &&
              hipMemsetAsync(c->d_tile_state, 0, sizeof(unsigned long long) * c->n_tiles, c->stream) == hipSuccess &&
+             hipMemsetAsync(c->d_part, 0, sizeof(unsigned) * 2 * SPH_MAX_BUFFERS * kMaxPartBlocks, c->stream) ==
+                 hipSuccess &&
              hipMemcpyAsync(c->d_ctl, &init, sizeof(Ctl), hipMemcpyHostToDevice, c->stream) == hipSuccess &&
              hipMemcpyAsync(c->d_result, &r0, sizeof(r0), hipMemcpyHostToDevice, c->stream) == hipSuccess &&
              hipStreamSynchronize(c->stream) == hipSuccess;

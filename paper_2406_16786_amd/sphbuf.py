@@ -22,7 +22,7 @@ SPH_ERR_HIP, SPH_ERR_STATE = 9, 10
 SPH_INLET, SPH_OUTLET, SPH_BIDIR = 1, 2, 3
 SPH_MAX_BUFFERS = 15
 SPH_MAX_CARRIED = 16
-SPH_MAX_EVENTS_LIMIT = 8192
+SPH_MAX_EVENTS_LIMIT = 4096
 
 EXPORTED = (
     "sph_create", "sph_destroy", "sph_buffer_define", "sph_celllist_build", "sph_buffer_identify",

@@ -304,7 +304,7 @@ def test_guard_band_decisions_equal_fp64(dim, seed):
         origin[2] = 0.0
     kinds = [oracle.OUTLET, oracle.BIDIR, oracle.INLET][seed]
     b = oracle.Buffer(kinds, tuple(origin), q, tuple(half), margin)
-    n = 20000
+    n = 10000
     L = rng.uniform(-(half + margin), half + margin, size=(n, 3))
     thr = [half[0], -half[0], half[0] + margin, -(half[0] + margin)]
     c = rng.integers(0, dim, n)
@@ -322,7 +322,7 @@ def test_guard_band_decisions_equal_fp64(dim, seed):
     inc = np.all(np.abs(lc[:, :dim]) < (half + margin)[:dim], axis=1)
     labels = ((rng.uniform(size=n) < 0.5) & inc).astype(np.int32)
     st = make_state(dim, pts, capacity=2 * n, labels=labels, carried=2)
-    d = make_domain_raw(dim, origin - 0.2, origin + 0.2, 2.6 * dp, dp, [bl], st, max_events=8192)
+    d = make_domain_raw(dim, origin - 0.2, origin + 0.2, 2.6 * dp, dp, [bl], st, max_events=4096)
     from paper_2406_16786_amd import sphbuf as S
     assert S.sph_state_set(d.ctx, st.next_id, [int(labels.sum())]) == 0
     d.build()
