@@ -87,6 +87,8 @@ typedef struct {
     int64_t max_events;     /* per update, for generated and for deleted; <= 4096             */
     int64_t next_id;        /* id of the first duplicate                                      */
     void *stream;           /* hipStream_t (NULL = the null stream)                           */
+    int32_t brick_log2;     /* 0: dense grid; 1..5: brick-sparse grid of 2^b cells per axis   */
+    int32_t brick_margin;   /* sparse grid: active bricks = occupied ones dilated by this     */
 } sph_config;
 
 /* Result of the last update (see sph_last_result). */
@@ -123,6 +125,15 @@ sph_status sph_buffer_define(sph_ctx *ctx, sph_kind kind, const double origin[3]
                              const double half[3], double margin, int32_t *buffer_id);
 
 /* ------------------------------------------------------------------ hot path -- */
+
+/* Brick-sparse grid only (a no-op for a dense grid): activate the bricks that hold
+ * live particles now, dilated by brick_margin bricks; every other brick maps to
+ * one overflow cell, which joins each buffer's candidate cells when its check
+ * region reaches an inactive brick.  Cell keys: slot * 2^(dim b) + local cell.
+ * Re-derives the candidate cells of the defined buffers.  Setup call (sync,
+ * allocates); call it again if the particles drift far from the active bricks
+ * (results stay exact, only the overflow cell gets crowded). */
+sph_status sph_grid_fit(sph_ctx *ctx, const sph_particles *p);
 
 /* Step 1: counting-sort cell list of the live particles on the context stream
  * (async).  Flags non-finite positions for the next update. */

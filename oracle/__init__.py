@@ -97,6 +97,14 @@ def lib():
                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_void_p]
         L.orc_cell_list.restype = ctypes.c_int
+        L.orc_sparse_active.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_float, ctypes.c_void_p, ctypes.c_int,
+                                        ctypes.c_int, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p]
+        L.orc_sparse_active.restype = ctypes.c_int64
+        L.orc_cell_list_sparse.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_float, ctypes.c_void_p,
+                                           ctypes.c_int, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        L.orc_cell_list_sparse.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -284,4 +292,46 @@ def cell_list(dim: int, lo, inv_cs: float, dims, x, y, z=None):
                              y.ctypes.data, zz.ctypes.data, start.ctypes.data, idx.ctypes.data)
     if rc != OK:
         raise ValueError("bad cell-list arguments")
+    return start, idx[:n]
+
+
+def _grid_args(dim, lo, dims):
+    lo32 = np.zeros(3, np.float32)
+    lo32[: len(lo)] = lo
+    d = np.ones(3, np.int32)
+    d[: len(dims)] = dims
+    return lo32, d
+
+
+def sparse_active(dim: int, lo, inv_cs: float, dims, blog2: int, margin: int, x, y, z=None) -> np.ndarray:
+    """Active-brick mask of the brick-sparse grid (occupied bricks dilated by margin)."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    y = np.ascontiguousarray(y, dtype=np.float32)
+    zz = np.ascontiguousarray(z if z is not None else np.zeros(x.size), dtype=np.float32)
+    lo32, d = _grid_args(dim, lo, dims)
+    bd = [(int(d[a]) + (1 << blog2) - 1) >> blog2 if a < dim else 1 for a in range(3)]
+    act = np.zeros(bd[0] * bd[1] * bd[2], np.uint8)
+    na = lib().orc_sparse_active(dim, lo32.ctypes.data, float(np.float32(inv_cs)), d.ctypes.data, blog2, margin,
+                                 x.size, x.ctypes.data, y.ctypes.data, zz.ctypes.data, act.ctypes.data)
+    if na < 0:
+        raise ValueError("bad sparse-grid arguments")
+    return act
+
+
+def cell_list_sparse(dim: int, lo, inv_cs: float, dims, blog2: int, active: np.ndarray, x, y, z=None):
+    """Stable counting-sort cell list on the brick-sparse grid (overflow key last)."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    y = np.ascontiguousarray(y, dtype=np.float32)
+    n = x.size
+    zz = np.ascontiguousarray(z if z is not None else np.zeros(n), dtype=np.float32)
+    lo32, d = _grid_args(dim, lo, dims)
+    active = np.ascontiguousarray(active, dtype=np.uint8)
+    C = int(active.sum()) * (1 << (dim * blog2)) + 1
+    start = np.zeros(C + 1, np.int32)
+    idx = np.zeros(max(1, n), np.int32)
+    rc = lib().orc_cell_list_sparse(dim, lo32.ctypes.data, float(np.float32(inv_cs)), d.ctypes.data, blog2,
+                                    active.ctypes.data, n, x.ctypes.data, y.ctypes.data, zz.ctypes.data,
+                                    start.ctypes.data, idx.ctypes.data)
+    if rc != OK:
+        raise ValueError("bad sparse-grid arguments")
     return start, idx[:n]

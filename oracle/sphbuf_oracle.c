@@ -390,3 +390,76 @@ int orc_cell_list(int dim, const float lo[3], float inv_cs, const int32_t dims[3
     free(key);
     return ORC_OK;
 }
+
+/* ------------------------------------------------------ brick-sparse grid --- */
+
+static void cell_of(int dim, const float lo[3], float inv_cs, const int32_t dims[3], float x, float y, float z,
+                    int64_t c[3]) {
+    c[0] = axis_cell(x, lo[0], inv_cs, dims[0]);
+    c[1] = axis_cell(y, lo[1], inv_cs, dims[1]);
+    c[2] = dim == 3 ? axis_cell(z, lo[2], inv_cs, dims[2]) : 0;
+}
+
+int64_t orc_sparse_active(int dim, const float lo[3], float inv_cs, const int32_t dims[3], int blog2, int margin,
+                          int64_t n, const float *x, const float *y, const float *z, unsigned char *active) {
+    if ((dim != 2 && dim != 3) || blog2 < 1 || margin < 0) return -1;
+    int64_t bd[3] = {1, 1, 1};
+    for (int a = 0; a < dim; a++) bd[a] = (dims[a] + (1 << blog2) - 1) >> blog2;
+    const int64_t nb = bd[0] * bd[1] * bd[2];
+    unsigned char *occ = (unsigned char *)calloc((size_t)nb, 1);
+    for (int64_t b = 0; b < nb; b++) active[b] = 0;
+    for (int64_t i = 0; i < n; i++) {
+        int64_t c[3];
+        cell_of(dim, lo, inv_cs, dims, x[i], y[i], dim == 3 ? z[i] : 0.0f, c);
+        occ[(c[0] >> blog2) + bd[0] * ((c[1] >> blog2) + bd[1] * (c[2] >> blog2))] = 1;
+    }
+    const int mz = dim == 3 ? margin : 0;
+    for (int64_t bz = 0; bz < bd[2]; bz++)
+        for (int64_t by = 0; by < bd[1]; by++)
+            for (int64_t bx = 0; bx < bd[0]; bx++) {
+                if (!occ[bx + bd[0] * (by + bd[1] * bz)]) continue;
+                for (int64_t dz = -mz; dz <= mz; dz++)
+                    for (int64_t dy = -margin; dy <= margin; dy++)
+                        for (int64_t dx = -margin; dx <= margin; dx++) {
+                            int64_t X = bx + dx, Y = by + dy, Z = bz + dz;
+                            if (X < 0 || Y < 0 || Z < 0 || X >= bd[0] || Y >= bd[1] || Z >= bd[2]) continue;
+                            active[X + bd[0] * (Y + bd[1] * Z)] = 1;
+                        }
+            }
+    free(occ);
+    int64_t na = 0;
+    for (int64_t b = 0; b < nb; b++) na += active[b];
+    return na;
+}
+
+int orc_cell_list_sparse(int dim, const float lo[3], float inv_cs, const int32_t dims[3], int blog2,
+                         const unsigned char *active, int64_t n, const float *x, const float *y, const float *z,
+                         int32_t *cell_start, int32_t *cell_idx) {
+    if ((dim != 2 && dim != 3) || blog2 < 1) return ORC_ERR_ARG;
+    int64_t bd[3] = {1, 1, 1};
+    for (int a = 0; a < dim; a++) bd[a] = (dims[a] + (1 << blog2) - 1) >> blog2;
+    const int64_t nb = bd[0] * bd[1] * bd[2];
+    int64_t *slot = (int64_t *)malloc(sizeof(int64_t) * (size_t)nb);
+    int64_t na = 0;
+    for (int64_t b = 0; b < nb; b++) slot[b] = active[b] ? na++ : -1;
+    const int64_t per = (int64_t)1 << (dim * blog2), mask = (1 << blog2) - 1;
+    const int64_t C = na * per + 1; /* the last key is the overflow cell */
+    int64_t *key = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t c = 0; c <= C; c++) cell_start[c] = 0;
+    for (int64_t i = 0; i < n; i++) {
+        int64_t c[3];
+        cell_of(dim, lo, inv_cs, dims, x[i], y[i], dim == 3 ? z[i] : 0.0f, c);
+        int64_t s = slot[(c[0] >> blog2) + bd[0] * ((c[1] >> blog2) + bd[1] * (c[2] >> blog2))];
+        int64_t local = (c[0] & mask) + ((c[1] & mask) << blog2) + ((c[2] & mask) << (2 * blog2));
+        key[i] = s < 0 ? na * per : s * per + local;
+        cell_start[key[i] + 1]++;
+    }
+    for (int64_t c = 0; c < C; c++) cell_start[c + 1] += cell_start[c];
+    int32_t *fill = (int32_t *)malloc(sizeof(int32_t) * (size_t)C);
+    for (int64_t c = 0; c < C; c++) fill[c] = cell_start[c];
+    for (int64_t i = 0; i < n; i++) cell_idx[fill[key[i]]++] = (int32_t)i;
+    free(fill);
+    free(key);
+    free(slot);
+    return ORC_OK;
+}

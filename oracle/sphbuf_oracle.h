@@ -93,6 +93,22 @@ int orc_update(const orc_buffer *bufs, int nb, orc_state *s, int64_t *gen_src, i
 int orc_cell_list(int dim, const float lo[3], float inv_cs, const int32_t dims[3], int64_t n, const float *x,
                   const float *y, const float *z, int32_t *cell_start, int32_t *cell_idx);
 
+/* Brick-sparse grid.  Bricks of 2^blog2 cells per axis cover the dense grid of
+ * dims cells (cell coordinates as in orc_cell_list).  A brick is active if a
+ * brick holding one of the n particles lies within Chebyshev distance margin of
+ * it.  active must hold bdims0*bdims1*bdims2 bytes, bdims = ceil(dims / 2^blog2).
+ * Returns the number of active bricks (or -1 on bad arguments). */
+int64_t orc_sparse_active(int dim, const float lo[3], float inv_cs, const int32_t dims[3], int blog2, int margin,
+                          int64_t n, const float *x, const float *y, const float *z, unsigned char *active);
+/* Cell list on the brick-sparse grid: an active brick's slot is its rank among
+ * active bricks in ascending brick index; its cells have keys
+ * slot * 2^(dim blog2) + lx + 2^blog2 (ly + 2^blog2 lz); every cell of an
+ * inactive brick has the single overflow key n_active * 2^(dim blog2).
+ * cell_start has n_active * 2^(dim blog2) + 2 entries. */
+int orc_cell_list_sparse(int dim, const float lo[3], float inv_cs, const int32_t dims[3], int blog2,
+                         const unsigned char *active, int64_t n, const float *x, const float *y, const float *z,
+                         int32_t *cell_start, int32_t *cell_idx);
+
 #ifdef __cplusplus
 }
 #endif

@@ -49,11 +49,19 @@ constexpr int kMaxPartBlocks = 8192;  // upper bound on classify / full-scan gri
 constexpr unsigned kIn = 1u, kBox = 2u, kFront = 4u, kBack = 8u;
 constexpr int kEvNone = 0, kEvGen = 1, kEvDel = 2;
 
+// Cell grid.  Dense: key = ix + dims0 * (iy + dims1 * iz).  Brick-sparse
+// (blog2 > 0): cells are grouped in bricks of 2^blog2 cells per axis; an active
+// brick with slot s owns keys s * B + local (B cells per brick, local = lx + b *
+// (ly + b * lz)); every cell of an inactive brick maps to the single overflow key.
 struct Grid {
     float lo[3];
     float inv_cs;
     int32_t dims[3];
     int32_t dim;
+    int32_t blog2;
+    int32_t bdims[3];
+    const int32_t *brick_slot;  // per brick: slot or -1
+    uint32_t overflow_key;
 };
 
 struct Parts {
@@ -106,18 +114,34 @@ __device__ __forceinline__ int logical_block() {
     return (b & 7) * (g >> 3) + (b >> 3);
 }
 
-__device__ __forceinline__ uint32_t cell_key(const Grid &g, float x, float y, float z) {
+// Dense cell coordinates: floor(fl32(fl32(x - lo) * inv_cs)) clamped to the grid
+// (particles outside the bounds land in edge cells; NaN lands in cell 0).
+__device__ __forceinline__ void cell_coords(const Grid &g, float x, float y, float z, uint32_t &ix, uint32_t &iy,
+                                            uint32_t &iz) {
     float fx = floorf((x - g.lo[0]) * g.inv_cs);
     float fy = floorf((y - g.lo[1]) * g.inv_cs);
     fx = fminf(fmaxf(fx, 0.0f), (float)(g.dims[0] - 1));
     fy = fminf(fmaxf(fy, 0.0f), (float)(g.dims[1] - 1));
-    uint32_t k = (uint32_t)fx + (uint32_t)g.dims[0] * (uint32_t)fy;
+    ix = (uint32_t)fx;
+    iy = (uint32_t)fy;
+    iz = 0;
     if (g.dim == 3) {
         float fz = floorf((z - g.lo[2]) * g.inv_cs);
         fz = fminf(fmaxf(fz, 0.0f), (float)(g.dims[2] - 1));
-        k += (uint32_t)g.dims[0] * (uint32_t)g.dims[1] * (uint32_t)fz;
+        iz = (uint32_t)fz;
     }
-    return k;
+}
+
+__device__ __forceinline__ uint32_t cell_key(const Grid &g, float x, float y, float z) {
+    uint32_t ix, iy, iz;
+    cell_coords(g, x, y, z, ix, iy, iz);
+    if (g.blog2 == 0) return ix + (uint32_t)g.dims[0] * (iy + (uint32_t)g.dims[1] * iz);
+    const uint32_t b = (uint32_t)g.blog2, m = (1u << b) - 1u;
+    const uint32_t brick = (ix >> b) + (uint32_t)g.bdims[0] * ((iy >> b) + (uint32_t)g.bdims[1] * (iz >> b));
+    const int32_t slot = g.brick_slot[brick];
+    if (slot < 0) return g.overflow_key;
+    const uint32_t local = (ix & m) + ((iy & m) << b) + (g.dim == 3 ? ((iz & m) << (2 * b)) : 0u);
+    return ((uint32_t)slot << (g.dim * b)) + local;
 }
 
 // Exact FP64 decision: local coordinates r' = Q (r - O') evaluated as
@@ -532,6 +556,7 @@ struct FusedArgs {
     int64_t m;  // cells + 1
     Ctl *ctl;
     unsigned epoch;
+    int vec;    // positions 16-byte aligned: vector loads allowed
 };
 
 // Grid-wide barrier for a cooperative launch (all blocks resident).  Every wave
@@ -603,6 +628,32 @@ __device__ __forceinline__ int block_scan_1024(int v, int *s_red, int &total) {
     return before + incl;
 }
 
+// Ranks of J wave-rows of keys already known (lanes with valid[j] false take no
+// part): run detection, then all J atomics, then the bases.  Wave-uniform call.
+template <int J>
+__device__ __forceinline__ void rank_batch(int32_t *count, const uint32_t (&key)[J], const bool (&valid)[J],
+                                           int lane, int32_t (&rank)[J]) {
+    int my_head[J], len[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const uint32_t prev = __shfl_up(key[j], 1);
+        const bool head = !valid[j] || lane == 0 || key[j] != prev;
+        const unsigned long long heads = __ballot(head);
+        const unsigned long long le = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+        my_head[j] = 63 - __clzll((long long)(heads & le));
+        const unsigned long long gt = heads & ~le;
+        len[j] = valid[j] ? (gt ? __ffsll((long long)gt) - 1 : 64) - my_head[j] : 0;
+    }
+    int old[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        old[j] = 0;
+        if (len[j] > 0 && lane == my_head[j]) old[j] = atomicAdd(&count[key[j]], len[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < J; ++j) rank[j] = __shfl(old[j], my_head[j]) + (lane - my_head[j]);
+}
+
 __global__ __launch_bounds__(kFusedBlock) void k_build_fused(FusedArgs a) {
     __shared__ int s_red[kFusedBlock / kWave];
     __shared__ uint32_t s_key[kFusedSlots * kFusedBlock];
@@ -610,27 +661,70 @@ __global__ __launch_bounds__(kFusedBlock) void k_build_fused(FusedArgs a) {
     const unsigned G = gridDim.x;
     const int lb = logical_block();
     const int lane = threadIdx.x & (kWave - 1);
-    const int64_t per = ((N + G - 1) / G + kFusedBlock - 1) / kFusedBlock * kFusedBlock;
+    const int wave = threadIdx.x / kWave;
+    constexpr int kVec = 4;                              // particles per 16-byte load
+    constexpr int64_t kQuant = (int64_t)kFusedBlock * kVec;
+    const int64_t per = ((N + G - 1) / G + kQuant - 1) / kQuant * kQuant;  // keeps segments 16-byte aligned
     const int64_t s0 = (int64_t)lb * per;
     const int64_t s1 = min(N, s0 + per);
+    const int64_t nreg = max((int64_t)0, min(s1 - s0, (int64_t)kFusedSlots * kFusedBlock));
     int32_t rank[kFusedSlots];
     bool bad = false;
-    // ---- count: keys to LDS, ranks kept in registers, kFusedGroup slots at a time ----
+    // ---- count, part 1: cell keys of the on-chip part of the segment into LDS,
+    //      four consecutive particles per thread per 16-byte load ----
+#pragma unroll 2
+    for (int q = 0; q < kFusedSlots / kVec; ++q) {
+        const int64_t lp = (int64_t)kVec * (threadIdx.x + (int64_t)kFusedBlock * q);
+        if ((int64_t)kVec * kFusedBlock * q >= nreg) break;   // block-uniform
+        float px[kVec], py[kVec], pz[kVec];
+        if (a.vec && lp + kVec <= nreg) {
+            const float4 vx = *reinterpret_cast<const float4 *>(a.x + s0 + lp);
+            const float4 vy = *reinterpret_cast<const float4 *>(a.y + s0 + lp);
+            px[0] = vx.x; px[1] = vx.y; px[2] = vx.z; px[3] = vx.w;
+            py[0] = vy.x; py[1] = vy.y; py[2] = vy.z; py[3] = vy.w;
+            if (a.g.dim == 3) {
+                const float4 vz = *reinterpret_cast<const float4 *>(a.z + s0 + lp);
+                pz[0] = vz.x; pz[1] = vz.y; pz[2] = vz.z; pz[3] = vz.w;
+            } else {
+                pz[0] = pz[1] = pz[2] = pz[3] = 0.0f;
+            }
+        } else {
 #pragma unroll
-    for (int j0 = 0; j0 < kFusedSlots; j0 += kFusedGroup) {
-        if (s0 + (int64_t)j0 * kFusedBlock < s1) {
-            uint32_t k[kFusedGroup];
-            int32_t r[kFusedGroup];
-            key_rank_batch<kFusedGroup>(a.g, a.x, a.y, a.z, a.count, s0 + (int64_t)j0 * kFusedBlock + threadIdx.x,
-                                        kFusedBlock, s1, lane, k, r, bad);
+            for (int c = 0; c < kVec; ++c) {
+                const bool ok = lp + c < nreg;
+                px[c] = ok ? a.x[s0 + lp + c] : 0.0f;
+                py[c] = ok ? a.y[s0 + lp + c] : 0.0f;
+                pz[c] = ok && a.g.dim == 3 ? a.z[s0 + lp + c] : 0.0f;
+            }
+        }
 #pragma unroll
-            for (int j = 0; j < kFusedGroup; ++j) {
-                s_key[(j0 + j) * kFusedBlock + threadIdx.x] = k[j];
-                rank[j0 + j] = r[j];
+        for (int c = 0; c < kVec; ++c) {
+            if (lp + c < nreg) {
+                bad |= !(isfinite(px[c]) && isfinite(py[c]) && isfinite(pz[c]));
+                s_key[lp + c] = cell_key(a.g, px[c], py[c], pz[c]);
             }
         }
     }
-    for (int64_t base = s0 + (int64_t)kFusedSlots * kFusedBlock; base < s1; base += kFusedBlock * kFusedGroup) {
+    __syncthreads();
+    // ---- count, part 2: ranks, one wave-row of 64 consecutive keys at a time ----
+#pragma unroll
+    for (int r0 = 0; r0 < kFusedSlots; r0 += kFusedGroup) {
+        if ((int64_t)kWave * (kFusedBlock / kWave) * r0 >= nreg) break;  // block-uniform
+        uint32_t k[kFusedGroup];
+        bool v[kFusedGroup];
+        int32_t r[kFusedGroup];
+#pragma unroll
+        for (int j = 0; j < kFusedGroup; ++j) {
+            const int64_t p = (int64_t)kWave * (wave + (kFusedBlock / kWave) * (r0 + j)) + lane;
+            v[j] = p < nreg;
+            k[j] = v[j] ? s_key[p] : 0xffffffffu;
+        }
+        rank_batch<kFusedGroup>(a.count, k, v, lane, r);
+#pragma unroll
+        for (int j = 0; j < kFusedGroup; ++j) rank[r0 + j] = r[j];
+    }
+    // ---- count, rest of the segment (very large N): through the keyrank buffer ----
+    for (int64_t base = s0 + nreg; base < s1; base += kFusedBlock * kFusedGroup) {
         uint32_t k[kFusedGroup];
         int32_t r[kFusedGroup];
         key_rank_batch<kFusedGroup>(a.g, a.x, a.y, a.z, a.count, base + threadIdx.x, kFusedBlock, s1, lane, k, r,
@@ -667,15 +761,28 @@ __global__ __launch_bounds__(kFusedBlock) void k_build_fused(FusedArgs a) {
         running += total;
     }
     if (!grid_barrier(a.ctl, G)) return;
-    // ---- scatter from registers (and from the spill buffer) ----
+    // ---- scatter: keys from LDS, ranks from registers (and the spill buffer) ----
 #pragma unroll
-    for (int j = 0; j < kFusedSlots; ++j) {
-        const int64_t i = s0 + (int64_t)j * kFusedBlock + threadIdx.x;
-        if (i < s1) a.cell_idx[a.cell_start[s_key[j * kFusedBlock + threadIdx.x]] + rank[j]] = (int32_t)i;
+    for (int r = 0; r < kFusedSlots; ++r) {
+        const int64_t p = (int64_t)kWave * (wave + (kFusedBlock / kWave) * r) + lane;
+        if (p < nreg) a.cell_idx[a.cell_start[s_key[p]] + rank[r]] = (int32_t)(s0 + p);
     }
-    for (int64_t i = s0 + (int64_t)kFusedSlots * kFusedBlock + threadIdx.x; i < s1; i += kFusedBlock) {
+    for (int64_t i = s0 + nreg + threadIdx.x; i < s1; i += kFusedBlock) {
         const unsigned long long kr = a.keyrank[i];
         a.cell_idx[a.cell_start[(uint32_t)(kr >> 32)] + (int)(unsigned)(kr & 0xffffffffull)] = (int32_t)i;
+    }
+}
+
+// Occupied bricks of the sparse grid (setup: sph_grid_fit).
+__global__ __launch_bounds__(kBuildBlock) void k_mark_bricks(const float *x, const float *y, const float *z,
+                                                             const int64_t *n_dev, int64_t capacity, Grid g,
+                                                             uint8_t *mask) {
+    const int64_t N = live_count(n_dev, capacity);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t ix, iy, iz;
+        cell_coords(g, x[i], y[i], g.dim == 3 ? z[i] : 0.0f, ix, iy, iz);
+        const uint32_t b = (uint32_t)g.blog2;
+        mask[(ix >> b) + (uint32_t)g.bdims[0] * ((iy >> b) + (uint32_t)g.bdims[1] * (iz >> b))] = 1;
     }
 }
 
@@ -746,6 +853,7 @@ struct FullArgs {
     int nb;
     EventArgs e;
     unsigned epoch;
+    int vec;  // positions 16-byte aligned: vector loads allowed
 };
 
 __global__ __launch_bounds__(kClassifyBlock) void k_classify_full(FullArgs a) {
@@ -759,32 +867,54 @@ __global__ __launch_bounds__(kClassifyBlock) void k_classify_full(FullArgs a) {
     const int lane = threadIdx.x & (kWave - 1);
     const int dim = a.p.dim;
     const int lb = logical_block();
-    const int64_t per = ((N + gridDim.x - 1) / gridDim.x + blockDim.x - 1) / blockDim.x * blockDim.x;
+    constexpr int kVec = 4;  // particles per thread per step: one 16-byte load per coordinate
+    const int64_t quant = (int64_t)blockDim.x * kVec;
+    const int64_t per = ((N + gridDim.x - 1) / gridDim.x + quant - 1) / quant * quant;
     const int64_t s0 = (int64_t)lb * per;
     const int64_t s1 = min(N, s0 + per);
     bool bad = false;
-    for (int64_t base = s0; base < s1; base += blockDim.x) {
-        const int64_t i = base + threadIdx.x;
-        const bool valid = i < s1;
-        float x = 0.0f, y = 0.0f, z = 0.0f;
-        if (valid) {
-            x = a.p.pos[0][i];
-            y = a.p.pos[1][i];
-            z = dim == 3 ? a.p.pos[2][i] : 0.0f;
-            bad |= !(isfinite(x) && isfinite(y) && isfinite(z));
-        }
-        for (int k = 0; k < a.nb; ++k) {
-            const unsigned bits = valid ? classify(sb[k], dim, x, y, z) : 0u;
-            if (__ballot(bits & kIn) == 0ull) continue;
-            int lab = 0;
-            Outcome o{kEvNone, -1, false};
-            if (bits & kIn) {
-                lab = a.p.label[i];
-                o = decide(sb[k], k, dim, bits, lab, x, y, z);
+    for (int64_t base = s0; base < s1; base += quant) {
+        const int64_t i0 = base + (int64_t)kVec * threadIdx.x;
+        float px[kVec], py[kVec], pz[kVec];
+        if (a.vec && i0 + kVec <= s1) {
+            const float4 vx = *reinterpret_cast<const float4 *>(a.p.pos[0] + i0);
+            const float4 vy = *reinterpret_cast<const float4 *>(a.p.pos[1] + i0);
+            px[0] = vx.x; px[1] = vx.y; px[2] = vx.z; px[3] = vx.w;
+            py[0] = vy.x; py[1] = vy.y; py[2] = vy.z; py[3] = vy.w;
+            if (dim == 3) {
+                const float4 vz = *reinterpret_cast<const float4 *>(a.p.pos[2] + i0);
+                pz[0] = vz.x; pz[1] = vz.y; pz[2] = vz.z; pz[3] = vz.w;
+            } else {
+                pz[0] = pz[1] = pz[2] = pz[3] = 0.0f;
             }
-            unsigned long long found = 0, post = 0;
-            emit(a.e, a.p, sb[k], k, valid, i, lab, o, x, y, z, found, post);
-            block_counts_add(s_cnt, k, found, post);
+        } else {
+#pragma unroll
+            for (int c = 0; c < kVec; ++c) {
+                const bool ok = i0 + c < s1;
+                px[c] = ok ? a.p.pos[0][i0 + c] : 0.0f;
+                py[c] = ok ? a.p.pos[1][i0 + c] : 0.0f;
+                pz[c] = ok && dim == 3 ? a.p.pos[2][i0 + c] : 0.0f;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < kVec; ++c) {
+            const int64_t i = i0 + c;
+            const bool valid = i < s1;
+            const float x = px[c], y = py[c], z = pz[c];
+            if (valid) bad |= !(isfinite(x) && isfinite(y) && isfinite(z));
+            for (int k = 0; k < a.nb; ++k) {
+                const unsigned bits = valid ? classify(sb[k], dim, x, y, z) : 0u;
+                if (__ballot(bits & kIn) == 0ull) continue;
+                int lab = 0;
+                Outcome o{kEvNone, -1, false};
+                if (bits & kIn) {
+                    lab = a.p.label[i];
+                    o = decide(sb[k], k, dim, bits, lab, x, y, z);
+                }
+                unsigned long long found = 0, post = 0;
+                emit(a.e, a.p, sb[k], k, valid, i, lab, o, x, y, z, found, post);
+                block_counts_add(s_cnt, k, found, post);
+            }
         }
     }
     if (__ballot(bad) != 0ull && lane == 0) atomicMax(&a.e.ctl->nonfinite_epoch, a.epoch);
@@ -1117,6 +1247,12 @@ struct sph_ctx {
     double cs = 0, dp = 0;
     int32_t dims[3] = {1, 1, 1};
     int64_t n_cells = 0;
+    // brick-sparse grid (blog2 > 0)
+    int blog2 = 0, bmargin = 1;
+    int32_t bdims[3] = {1, 1, 1};
+    int64_t n_bricks = 0;
+    std::vector<int32_t> h_brick_slot;
+    int32_t *d_brick_slot = nullptr;
     int64_t capacity = 0;
     unsigned max_events = 0;
     hipStream_t stream = nullptr;
@@ -1200,6 +1336,8 @@ void prof_drain(sph_ctx *c) {
     c->prof_used = 0;
 }
 
+bool aligned16(const void *q) { return q == nullptr || (reinterpret_cast<uintptr_t>(q) & 15u) == 0; }
+
 sph_status parts_of(const sph_ctx *ctx, const sph_particles *p, Parts &out) {
     if (!p || !p->pos[0] || !p->pos[1] || (ctx->dim == 3 && !p->pos[2]) || !p->label || !p->id || !p->n_dev)
         return SPH_ERR_ARG;
@@ -1225,9 +1363,13 @@ Grid grid_of(const sph_ctx *ctx) {
     for (int c = 0; c < 3; ++c) {
         g.lo[c] = (float)ctx->lo[c];
         g.dims[c] = ctx->dims[c];
+        g.bdims[c] = ctx->bdims[c];
     }
     g.inv_cs = (float)(1.0 / ctx->cs);
     g.dim = ctx->dim;
+    g.blog2 = ctx->blog2;
+    g.brick_slot = ctx->d_brick_slot;
+    g.overflow_key = (uint32_t)(ctx->n_cells - 1);
     return g;
 }
 
@@ -1278,6 +1420,7 @@ void free_ctx(sph_ctx *c) {
     (void)hipFree(c->d_run_len);
     (void)hipFree(c->d_run_buf);
     (void)hipFree(c->d_count);
+    (void)hipFree(c->d_brick_slot);
     (void)hipFree(c->d_cell_start);
     (void)hipFree(c->d_cell_idx);
     (void)hipFree(c->d_keyrank);
@@ -1300,6 +1443,89 @@ void free_ctx(sph_ctx *c) {
 
 }  // namespace
 
+// Candidate cells of one check region as runs of consecutive cell keys, at most
+// a wave's worth of candidates per run (one wave takes one run).  For the
+// brick-sparse grid the dense cover is mapped to keys and the overflow cell is
+// added whenever part of the region lies in inactive bricks.
+static sph_status cover_runs(const sph_ctx *ctx, const double o[3], const double q[9], const double h[3],
+                             double margin, std::vector<int32_t> &first, std::vector<int32_t> &len) {
+    first.clear();
+    len.clear();
+    std::vector<int32_t> f0, l0;
+    const sph_status cs = sphbuf::grid_cover(ctx->dim, ctx->lo, ctx->cs, ctx->dims, o, q, h, margin, f0, l0);
+    if (cs != SPH_OK) return cs;
+    const int cap = ctx->dim == 3 ? 4 : 12;
+    if (ctx->blog2 == 0) {
+        for (size_t r = 0; r < f0.size(); ++r)
+            for (int s = 0; s < l0[r]; s += cap) {
+                first.push_back(f0[r] + s);
+                len.push_back(std::min(cap, l0[r] - s));
+            }
+        return SPH_OK;
+    }
+    const int b = ctx->blog2, m = (1 << b) - 1;
+    std::vector<int64_t> keys;
+    bool overflow = false;
+    for (size_t r = 0; r < f0.size(); ++r)
+        for (int s = 0; s < l0[r]; ++s) {
+            const int64_t lin = (int64_t)f0[r] + s;
+            const int64_t ix = lin % ctx->dims[0], iy = (lin / ctx->dims[0]) % ctx->dims[1],
+                          iz = lin / ((int64_t)ctx->dims[0] * ctx->dims[1]);
+            const int64_t brick = (ix >> b) + (int64_t)ctx->bdims[0] * ((iy >> b) + (int64_t)ctx->bdims[1] * (iz >> b));
+            const int32_t slot = ctx->h_brick_slot[(size_t)brick];
+            if (slot < 0) {
+                overflow = true;
+                continue;
+            }
+            const int64_t local = (ix & m) + ((iy & m) << b) + (ctx->dim == 3 ? ((iz & m) << (2 * b)) : 0);
+            keys.push_back(((int64_t)slot << (ctx->dim * b)) + local);
+        }
+    if (overflow) keys.push_back(ctx->n_cells - 1);
+    std::sort(keys.begin(), keys.end());
+    keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+    for (size_t i = 0; i < keys.size();) {
+        size_t j = i + 1;
+        while (j < keys.size() && keys[j] == keys[j - 1] + 1 && (int)(j - i) < cap) ++j;
+        first.push_back((int32_t)keys[i]);
+        len.push_back((int32_t)(j - i));
+        i = j;
+    }
+    return SPH_OK;
+}
+
+// Replace the device copy of the run list of all buffers (allocation: setup only).
+static sph_status upload_runs(sph_ctx *ctx, std::vector<int32_t> &rf, std::vector<int32_t> &rl,
+                              std::vector<uint8_t> &rb) {
+    int32_t *nf = nullptr, *nl = nullptr;
+    uint8_t *nbuf = nullptr;
+    const size_t nr = rf.size();
+    if (nr > 0) {
+        if (hipMalloc(&nf, sizeof(int32_t) * nr) != hipSuccess || hipMalloc(&nl, sizeof(int32_t) * nr) != hipSuccess ||
+            hipMalloc(&nbuf, nr) != hipSuccess) {
+            (void)hipFree(nf);
+            (void)hipFree(nl);
+            (void)hipFree(nbuf);
+            return SPH_ERR_HIP;
+        }
+        if (hipMemcpyAsync(nf, rf.data(), sizeof(int32_t) * nr, hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
+            hipMemcpyAsync(nl, rl.data(), sizeof(int32_t) * nr, hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
+            hipMemcpyAsync(nbuf, rb.data(), nr, hipMemcpyHostToDevice, ctx->stream) != hipSuccess)
+            return SPH_ERR_HIP;
+    }
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    (void)hipFree(ctx->d_run_first);
+    (void)hipFree(ctx->d_run_len);
+    (void)hipFree(ctx->d_run_buf);
+    ctx->d_run_first = nf;
+    ctx->d_run_len = nl;
+    ctx->d_run_buf = nbuf;
+    ctx->n_runs = (int)nr;
+    ctx->h_run_first.swap(rf);
+    ctx->h_run_len.swap(rl);
+    ctx->h_run_buf.swap(rb);
+    return SPH_OK;
+}
+
 extern "C" sph_status sph_create(const sph_config *cfg, sph_ctx **out) {
     if (!out) return SPH_ERR_ARG;
     *out = nullptr;
@@ -1316,7 +1542,21 @@ extern "C" sph_status sph_create(const sph_config *cfg, sph_ctx **out) {
         dims[c] = (int32_t)std::max(1.0, n);
         cells *= dims[c];
     }
-    if (cells >= 2147483000.0) return SPH_ERR_ARG;
+    if (cfg->brick_log2 < 0 || cfg->brick_log2 > 5 || cfg->brick_margin < 0 || cfg->brick_margin > 64)
+        return SPH_ERR_ARG;
+    const int blog2 = cfg->brick_log2;
+    int32_t bdims[3] = {1, 1, 1};
+    double bricks = 1.0;
+    if (blog2 > 0) {
+        for (int c = 0; c < cfg->dim; ++c) {
+            bdims[c] = (dims[c] + (1 << blog2) - 1) >> blog2;
+            bricks *= bdims[c];
+        }
+        if (bricks >= 2147483000.0) return SPH_ERR_ARG;
+        cells = 1.0;  // only the overflow cell until sph_grid_fit activates bricks
+    } else if (cells >= 2147483000.0) {
+        return SPH_ERR_ARG;
+    }
 
     sph_ctx *c = new (std::nothrow) sph_ctx();
     if (!c) return SPH_ERR_HIP;
@@ -1328,6 +1568,11 @@ extern "C" sph_status sph_create(const sph_config *cfg, sph_ctx **out) {
     c->cs = cfg->cell_size;
     c->dp = cfg->dp;
     c->n_cells = (int64_t)cells;
+    c->blog2 = blog2;
+    c->bmargin = cfg->brick_margin;
+    for (int q = 0; q < 3; ++q) c->bdims[q] = bdims[q];
+    c->n_bricks = blog2 > 0 ? (int64_t)bricks : 0;
+    if (blog2 > 0) c->h_brick_slot.assign((size_t)c->n_bricks, -1);
     c->capacity = cfg->capacity;
     c->max_events = (unsigned)cfg->max_events;
     c->stream = (hipStream_t)cfg->stream;
@@ -1356,6 +1601,7 @@ extern "C" sph_status sph_create(const sph_config *cfg, sph_ctx **out) {
               hipMalloc(&c->d_rel, sizeof(unsigned long long) * ev * kRelPerEvent) == hipSuccess &&
               hipMalloc(&c->d_dup, sizeof(float) * ev * kDupStride) == hipSuccess &&
               hipMalloc(&c->d_ctl, sizeof(Ctl)) == hipSuccess &&
+              (blog2 == 0 || hipMalloc(&c->d_brick_slot, sizeof(int32_t) * c->n_bricks) == hipSuccess) &&
               hipMalloc(&c->d_part, sizeof(unsigned) * 2 * SPH_MAX_BUFFERS * kMaxPartBlocks) == hipSuccess &&
               hipMalloc(&c->d_block_sum, sizeof(int32_t) * kMaxPartBlocks) == hipSuccess &&
               hipMalloc(&c->d_result, sizeof(sph_result)) == hipSuccess &&
@@ -1371,6 +1617,8 @@ extern "C" sph_status sph_create(const sph_config *cfg, sph_ctx **out) {
              hipMemsetAsync(c->d_part, 0, sizeof(unsigned) * 2 * SPH_MAX_BUFFERS * kMaxPartBlocks, c->stream) ==
                  hipSuccess &&
              hipMemcpyAsync(c->d_ctl, &init, sizeof(Ctl), hipMemcpyHostToDevice, c->stream) == hipSuccess &&
+             (blog2 == 0 || hipMemsetAsync(c->d_brick_slot, 0xff, sizeof(int32_t) * c->n_bricks, c->stream) ==
+                                hipSuccess) &&
              hipMemcpyAsync(c->d_result, &r0, sizeof(r0), hipMemcpyHostToDevice, c->stream) == hipSuccess &&
              hipStreamSynchronize(c->stream) == hipSuccess;
     }
@@ -1391,8 +1639,11 @@ extern "C" sph_status sph_create(const sph_config *cfg, sph_ctx **out) {
             g = std::min(g, kMaxPartBlocks) / 8 * 8;
             c->fused_blocks = g >= 8 ? g : 0;
         }
+        // The three-kernel build is the default: in the one-launch build each of the
+        // three grid barriers costs about as much as a kernel boundary.  Opt in with
+        // SPHBUF_BUILD=fused.
         const char *env = std::getenv("SPHBUF_BUILD");
-        if (env && std::strcmp(env, "split") == 0) c->fused_blocks = 0;
+        if (!env || std::strcmp(env, "fused") != 0) c->fused_blocks = 0;
     }
     *out = c;
     return SPH_OK;
@@ -1431,16 +1682,8 @@ extern "C" sph_status sph_buffer_define(sph_ctx *ctx, sph_kind kind, const doubl
             return SPH_ERR_OVERLAP;
     std::vector<int32_t> first, len;
     {
-        std::vector<int32_t> f0, l0;
-        const sph_status cs = sphbuf::grid_cover(dim, ctx->lo, ctx->cs, ctx->dims, o, q, h, margin, f0, l0);
+        const sph_status cs = cover_runs(ctx, o, q, h, margin, first, len);
         if (cs != SPH_OK) return cs;
-        // one wave takes one run: cap runs at about a wave's worth of candidates
-        const int cap = dim == 3 ? 4 : 12;
-        for (size_t r = 0; r < f0.size(); ++r)
-            for (int s = 0; s < l0[r]; s += cap) {
-                first.push_back(f0[r] + s);
-                len.push_back(std::min(cap, l0[r] - s));
-            }
     }
 
     const int k = ctx->nb;
@@ -1471,35 +1714,10 @@ extern "C" sph_status sph_buffer_define(sph_ctx *ctx, sph_kind kind, const doubl
     rf.insert(rf.end(), first.begin(), first.end());
     rl.insert(rl.end(), len.begin(), len.end());
     rb.insert(rb.end(), first.size(), (uint8_t)k);
-    int32_t *nf = nullptr, *nl = nullptr;
-    uint8_t *nbuf = nullptr;
-    const size_t nr = rf.size();
-    if (nr > 0) {
-        if (hipMalloc(&nf, sizeof(int32_t) * nr) != hipSuccess || hipMalloc(&nl, sizeof(int32_t) * nr) != hipSuccess ||
-            hipMalloc(&nbuf, nr) != hipSuccess) {
-            (void)hipFree(nf);
-            (void)hipFree(nl);
-            (void)hipFree(nbuf);
-            return SPH_ERR_HIP;
-        }
-        if (hipMemcpyAsync(nf, rf.data(), sizeof(int32_t) * nr, hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
-            hipMemcpyAsync(nl, rl.data(), sizeof(int32_t) * nr, hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
-            hipMemcpyAsync(nbuf, rb.data(), nr, hipMemcpyHostToDevice, ctx->stream) != hipSuccess)
-            return SPH_ERR_HIP;
-    }
     ctx->hb[k] = b;
     HIP_TRY(hipMemcpyAsync(ctx->d_bufs + k, &ctx->hb[k], sizeof(BufDev), hipMemcpyHostToDevice, ctx->stream));
-    HIP_TRY(hipStreamSynchronize(ctx->stream));
-    (void)hipFree(ctx->d_run_first);
-    (void)hipFree(ctx->d_run_len);
-    (void)hipFree(ctx->d_run_buf);
-    ctx->d_run_first = nf;
-    ctx->d_run_len = nl;
-    ctx->d_run_buf = nbuf;
-    ctx->n_runs = (int)nr;
-    ctx->h_run_first.swap(rf);
-    ctx->h_run_len.swap(rl);
-    ctx->h_run_buf.swap(rb);
+    const sph_status us = upload_runs(ctx, rf, rl, rb);
+    if (us != SPH_OK) return us;
     for (int c = 0; c < 3; ++c) {
         ctx->b_origin[k][c] = o[c];
         ctx->b_half[k][c] = h[c];
@@ -1533,6 +1751,7 @@ extern "C" sph_status sph_celllist_build(sph_ctx *ctx, const sph_particles *p) {
         fa.m = ctx->n_cells + 1;
         fa.ctl = ctx->d_ctl;
         fa.epoch = ctx->epoch;
+        fa.vec = aligned16(fa.x) && aligned16(fa.y) && aligned16(fa.z) ? 1 : 0;
         void *args[] = {&fa};
         hipError_t e;
         {
@@ -1633,6 +1852,7 @@ static sph_status fullscan_enqueue(sph_ctx *ctx, sph_particles *p) {
     fa.nb = ctx->nb;
     fa.e = events_of(ctx);
     fa.epoch = ctx->epoch;
+    fa.vec = aligned16(pp.pos[0]) && aligned16(pp.pos[1]) && aligned16(pp.pos[2]) ? 1 : 0;
     {
         ProfScope ps(ctx, SPH_PHASE_FULLSCAN);
         hipLaunchKernelGGL(k_classify_full, dim3(ctx->full_blocks), dim3(kClassifyBlock), 0, ctx->stream, fa);
@@ -1787,4 +2007,83 @@ extern "C" sph_status sph_profile_read(sph_ctx *ctx, double ms[SPH_NPHASE], int6
         }
     }
     return SPH_OK;
+}
+
+extern "C" sph_status sph_grid_fit(sph_ctx *ctx, const sph_particles *p) {
+    if (!ctx) return SPH_ERR_ARG;
+    if (ctx->blog2 == 0) return SPH_OK;
+    Parts pp;
+    const sph_status st = parts_of(ctx, p, pp);
+    if (st != SPH_OK) return st;
+    const int64_t nb = ctx->n_bricks;
+    uint8_t *d_mask = nullptr;
+    HIP_TRY(hipMalloc(&d_mask, (size_t)nb));
+    std::vector<uint8_t> occ((size_t)nb);
+    bool ok = hipMemsetAsync(d_mask, 0, (size_t)nb, ctx->stream) == hipSuccess;
+    if (ok) {
+        hipLaunchKernelGGL(k_mark_bricks, dim3(ctx->build_blocks), dim3(kBuildBlock), 0, ctx->stream, pp.pos[0],
+                           pp.pos[1], pp.pos[2], pp.n_dev, pp.capacity, grid_of(ctx), d_mask);
+        ok = hipGetLastError() == hipSuccess &&
+             hipMemcpyAsync(occ.data(), d_mask, (size_t)nb, hipMemcpyDeviceToHost, ctx->stream) == hipSuccess &&
+             hipStreamSynchronize(ctx->stream) == hipSuccess;
+    }
+    (void)hipFree(d_mask);
+    if (!ok) return SPH_ERR_HIP;
+    // dilate by the margin (Chebyshev distance in bricks), one axis at a time
+    const int bd[3] = {ctx->bdims[0], ctx->bdims[1], ctx->bdims[2]};
+    const int64_t stride[3] = {1, bd[0], (int64_t)bd[0] * bd[1]};
+    std::vector<uint8_t> act = occ, tmp((size_t)nb);
+    for (int ax = 0; ax < ctx->dim; ++ax) {
+        tmp.assign((size_t)nb, 0);
+        for (int64_t i = 0; i < nb; ++i) {
+            if (!act[(size_t)i]) continue;
+            const int64_t c = (i / stride[ax]) % bd[ax];
+            for (int64_t d = -ctx->bmargin; d <= ctx->bmargin; ++d)
+                if (c + d >= 0 && c + d < bd[ax]) tmp[(size_t)(i + d * stride[ax])] = 1;
+        }
+        act.swap(tmp);
+    }
+    int64_t n_active = 0;
+    for (int64_t i = 0; i < nb; ++i) ctx->h_brick_slot[(size_t)i] = act[(size_t)i] ? (int32_t)n_active++ : -1;
+    const int64_t per_brick = (int64_t)1 << (ctx->dim * ctx->blog2);
+    const int64_t cells = n_active * per_brick + 1;
+    if (cells >= 2147483000LL) return SPH_ERR_ARG;
+    const int64_t m = cells + 1;
+    const int64_t tiles = (m + kScanTile - 1) / kScanTile;
+    int32_t *cnt = nullptr, *start = nullptr;
+    unsigned long long *ts = nullptr;
+    if (hipMalloc(&cnt, sizeof(int32_t) * m) != hipSuccess || hipMalloc(&start, sizeof(int32_t) * m) != hipSuccess ||
+        hipMalloc(&ts, sizeof(unsigned long long) * tiles) != hipSuccess) {
+        (void)hipFree(cnt);
+        (void)hipFree(start);
+        (void)hipFree(ts);
+        return SPH_ERR_HIP;
+    }
+    HIP_TRY(hipMemsetAsync(cnt, 0, sizeof(int32_t) * m, ctx->stream));
+    HIP_TRY(hipMemsetAsync(start, 0, sizeof(int32_t) * m, ctx->stream));
+    HIP_TRY(hipMemsetAsync(ts, 0, sizeof(unsigned long long) * tiles, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(ctx->d_brick_slot, ctx->h_brick_slot.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice,
+                           ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    (void)hipFree(ctx->d_count);
+    (void)hipFree(ctx->d_cell_start);
+    (void)hipFree(ctx->d_tile_state);
+    ctx->d_count = cnt;
+    ctx->d_cell_start = start;
+    ctx->d_tile_state = ts;
+    ctx->n_cells = cells;
+    ctx->n_tiles = tiles;
+    ctx->built = false;
+    // candidate cells of every buffer in the new key space
+    std::vector<int32_t> rf, rl;
+    std::vector<uint8_t> rb;
+    for (int k = 0; k < ctx->nb; ++k) {
+        std::vector<int32_t> f, l;
+        const sph_status cs = cover_runs(ctx, ctx->b_origin[k], ctx->b_rot[k], ctx->b_half[k], ctx->b_margin[k], f, l);
+        if (cs != SPH_OK) return cs;
+        rf.insert(rf.end(), f.begin(), f.end());
+        rl.insert(rl.end(), l.begin(), l.end());
+        rb.insert(rb.end(), f.size(), (uint8_t)k);
+    }
+    return upload_runs(ctx, rf, rl, rb);
 }

@@ -30,7 +30,7 @@ EXPORTED = (
     "sph_buffer_update_fullscan_async", "sph_last_result", "sph_last_events", "sph_celllist_view",
     "sph_state_get", "sph_state_set", "sph_rotation_2d", "sph_rotation_axis_angle",
     "sph_rotation_from_direction", "sph_check_rotation", "sph_grid_cover", "sph_guard_band",
-    "sph_status_str", "sph_profile_enable", "sph_profile_read",
+    "sph_status_str", "sph_profile_enable", "sph_profile_read", "sph_grid_fit",
 )
 SPH_NPHASE = 7
 PHASES = ("count", "scan", "scatter", "classify", "fullscan", "finalize", "build")
@@ -61,6 +61,8 @@ class sph_config(ctypes.Structure):
         ("max_events", ctypes.c_int64),
         ("next_id", ctypes.c_int64),
         ("stream", ctypes.c_void_p),
+        ("brick_log2", ctypes.c_int32),
+        ("brick_margin", ctypes.c_int32),
     ]
 
 
@@ -102,6 +104,7 @@ def lib() -> ctypes.CDLL:
             "sph_destroy": ([_VP], ctypes.c_int),
             "sph_buffer_define": ([_VP, ctypes.c_int, _D, _D, _D, ctypes.c_double, _I32], ctypes.c_int),
             "sph_celllist_build": ([_VP, ctypes.POINTER(sph_particles)], ctypes.c_int),
+            "sph_grid_fit": ([_VP, ctypes.POINTER(sph_particles)], ctypes.c_int),
             "sph_buffer_identify": ([_VP, ctypes.POINTER(sph_particles), ctypes.c_int32], ctypes.c_int),
             "sph_buffer_update": ([_VP, ctypes.POINTER(sph_particles), _I64, _I64], ctypes.c_int),
             "sph_buffer_update_async": ([_VP, ctypes.POINTER(sph_particles)], ctypes.c_int),
@@ -154,7 +157,8 @@ def sph_status_str(status: int) -> str:
 
 
 def sph_create(dim: int, lo, hi, cell_size: float, dp: float, capacity: int, max_events: int = 4096,
-               next_id: int = 0, stream: int = 0) -> Tuple[int, Optional[int]]:
+               next_id: int = 0, stream: int = 0, brick_log2: int = 0,
+               brick_margin: int = 1) -> Tuple[int, Optional[int]]:
     cfg = sph_config()
     cfg.dim = dim
     cfg.lo = _d3(lo)
@@ -165,6 +169,8 @@ def sph_create(dim: int, lo, hi, cell_size: float, dp: float, capacity: int, max
     cfg.max_events = max_events
     cfg.next_id = next_id
     cfg.stream = stream or None
+    cfg.brick_log2 = brick_log2
+    cfg.brick_margin = brick_margin
     out = _VP()
     st = lib().sph_create(ctypes.byref(cfg), ctypes.byref(out))
     return st, out.value
@@ -178,6 +184,10 @@ def sph_buffer_define(ctx: int, kind: int, origin, rot, half, margin: float) -> 
     bid = ctypes.c_int32(0)
     st = lib().sph_buffer_define(ctx, int(kind), _d3(origin), _d9(rot), _d3(half), float(margin), ctypes.byref(bid))
     return st, bid.value
+
+
+def sph_grid_fit(ctx: int, p: sph_particles) -> int:
+    return lib().sph_grid_fit(ctx, ctypes.byref(p))
 
 
 def sph_celllist_build(ctx: int, p: sph_particles) -> int:

@@ -12,20 +12,23 @@ from tests._support import oracle_buffers, oracle_state
 
 
 def make_domain_raw(dim, lo, hi, cell_size, dp, bufs: Sequence[oracle.Buffer], st: oracle.State,
-                    max_events: int = 4096):
+                    max_events: int = 4096, brick_log2: int = 0, brick_margin: int = 1):
     from paper_2406_16786_amd.domain import Domain
     d = Domain(dim, lo, hi, cell_size, dp, st.capacity, st.pos, st.carried, st.label, st.id, st.n, st.next_id,
-               max_events=max_events)
+               max_events=max_events, brick_log2=brick_log2, brick_margin=brick_margin)
     for b in bufs:
         d.define(b.kind, b.origin, b.rot, b.half, b.margin)
+    if brick_log2:
+        d.fit()
     return d
 
 
 def make_domain(wl, bufs: Sequence[oracle.Buffer], st: oracle.State = None, max_events: int = 4096,
-                cell_size: float = None, lo=None, hi=None):
+                cell_size: float = None, lo=None, hi=None, brick_log2: int = 0, brick_margin: int = 1):
     st = st if st is not None else oracle_state(wl)
     return make_domain_raw(wl.dim, lo if lo is not None else wl.lo, hi if hi is not None else wl.hi,
-                           cell_size if cell_size is not None else wl.cell_size, wl.dp, bufs, st, max_events)
+                           cell_size if cell_size is not None else wl.cell_size, wl.dp, bufs, st, max_events,
+                           brick_log2, brick_margin)
 
 
 def upload_state(d, st: oracle.State) -> None:

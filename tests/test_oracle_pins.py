@@ -391,3 +391,59 @@ def test_channel2d_balances_over_200_steps():
             assert np.all(np.abs(lc[sel, 0]) < b.half[0] + b.margin)
     # steady inflow: u = 1, height 0.4, dp = 0.02, dt = 0.005 -> 1 * 0.4 / dp^2 * dt = 5 per step
     assert 4.5 < np.mean(gens[20:]) < 5.5
+
+
+# -------------------------------------------------------------- cell lists ---
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_cell_list_properties(dim):
+    """Counting sort: a permutation, ascending within each cell, and every
+    particle's cell box (exact FP64 geometry) contains it unless it lies within
+    1e-4 of a cell of a face, where FP32 binning may pick the neighbour."""
+    rng = np.random.default_rng(dim)
+    n = 5000
+    lo, cs = np.array([-0.3, -0.2, -0.1]), 0.05
+    dims = [16, 12, 9]
+    P = rng.uniform(lo, lo + np.array(dims) * cs, size=(n, 3)).astype(np.float32)
+    start, idx = oracle.cell_list(dim, np.float32(lo[:dim]), np.float32(1 / cs), dims[:dim], P[:, 0], P[:, 1],
+                                  P[:, 2] if dim == 3 else None)
+    assert start[0] == 0 and start[-1] == n and np.all(np.diff(start) >= 0)
+    assert np.array_equal(np.sort(idx), np.arange(n))
+    C = len(start) - 1
+    for c in range(C):
+        members = idx[start[c]:start[c + 1]]
+        assert np.all(np.diff(members) > 0)
+        ix = c % dims[0]
+        iy = (c // dims[0]) % dims[1]
+        iz = c // (dims[0] * dims[1])
+        for i in members:
+            for a, k in zip(range(dim), (ix, iy, iz)):
+                t = (float(P[i, a]) - lo[a]) / cs
+                assert k - 1e-4 < t < k + 1 + 1e-4
+
+
+def test_cell_list_clamps_outsiders_to_edge_cells():
+    start, idx = oracle.cell_list(2, np.float32([0, 0]), np.float32(1.0), [4, 4], np.float32([-5.0, 9.5, 1.5]),
+                                  np.float32([1.5, 1.5, 99.0]))
+    # cells: (-5, 1.5) -> (0, 1) = 4; (9.5, 1.5) -> (3, 1) = 7; (1.5, 99) -> (1, 3) = 13
+    assert list(np.repeat(np.arange(16), np.diff(start))[np.argsort(idx)]) == [4, 7, 13]
+
+
+def test_sparse_grid_hand_example():
+    # 16 x 16 cells of size 1, bricks of 4 x 4 cells (4 x 4 bricks)
+    lo, inv, dims = np.float32([0, 0]), np.float32(1.0), [16, 16]
+    x = np.float32([5.5, 13.5])   # cells (5, 5) in brick (1, 1) and (13, 2) in brick (3, 0)
+    y = np.float32([5.5, 2.5])
+    act0 = oracle.sparse_active(2, lo, inv, dims, 2, 0, x, y)
+    assert list(np.nonzero(act0)[0]) == [3, 5]          # bricks 3 + 4 * 0 and 1 + 4 * 1
+    start, idx = oracle.cell_list_sparse(2, lo, inv, dims, 2, act0, x, y)
+    keys = np.repeat(np.arange(len(start) - 1), np.diff(start))[np.argsort(idx)]
+    # brick 3 -> slot 0: key 0 * 16 + 1 + 4 * 2 = 9; brick 5 -> slot 1: 16 + 1 + 4 * 1 = 21
+    assert list(keys) == [21, 9] and len(start) == 2 * 16 + 2
+    act1 = oracle.sparse_active(2, lo, inv, dims, 2, 1, x, y)
+    assert int(act1.sum()) == 11                         # 3 x 3 around (1,1) plus 2 x 2 at (2..3, 0..1), 2 shared
+    # a particle in an inactive brick goes to the overflow key (last)
+    x2, y2 = np.float32([5.5, 13.5, 15.5]), np.float32([5.5, 2.5, 15.5])
+    s2, i2 = oracle.cell_list_sparse(2, lo, inv, dims, 2, act0, x2, y2)
+    keys2 = np.repeat(np.arange(len(s2) - 1), np.diff(s2))[np.argsort(i2)]
+    assert list(keys2) == [21, 9, 32]

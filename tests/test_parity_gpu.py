@@ -45,10 +45,10 @@ def _cell_list(d, n):
     return cs, ci[:n], dims
 
 
-def _run_steps(wl, steps, mode="local", identify=True, check_every=1, cell_size=None):
+def _run_steps(wl, steps, mode="local", identify=True, check_every=1, cell_size=None, brick_log2=0):
     bufs = oracle_buffers(wl)
     st = oracle_state(wl)
-    d = make_domain(wl, bufs, st, cell_size=cell_size)
+    d = make_domain(wl, bufs, st, cell_size=cell_size, brick_log2=brick_log2)
     if identify:
         rc_o, nl_o = oracle.identify(bufs, st, -1)
         assert d.identify(-1) == 0
@@ -107,9 +107,10 @@ def test_celllist_matches_oracle(name, build, monkeypatch):
     d.close()
 
 
-def test_celllist_beyond_register_slots():
+def test_celllist_beyond_register_slots(monkeypatch):
     """9.5 M random particles: more than the one-launch build keeps on chip
     (256 blocks x 1024 threads x 32 slots), so part of them take the spill path."""
+    monkeypatch.setenv("SPHBUF_BUILD", "fused")
     n = 9_500_000
     pos, car, lab, ids = W.random_box_particles(7, n, 3, (0, 0, 0), (1.0, 0.5, 0.5), capacity=n + 16, n_carried=1)
     st = make_state(3, np.zeros((0, 3)))
@@ -366,3 +367,38 @@ def test_pipe3d_full_size_three_steps(mode):
     """The 3-D pipe at dp = 0.001 (7.86 M particles), the size the benchmark
     times: events and every array against the oracle for three updates."""
     _run_steps(W.pipe3d(), 3, mode=mode)
+
+
+# -------------------------------------------- bidirectional tree, sparse grid ---
+
+def test_celllist_sparse_matches_oracle():
+    wl = W.tree3d(dp=0.004)
+    bufs = oracle_buffers(wl)
+    d = make_domain(wl, bufs, brick_log2=3, brick_margin=1)
+    d.build()
+    cs, ci, dims = _cell_list(d, wl.n)
+    lo32 = np.float32(wl.lo[:3])
+    inv = np.float32(1.0 / wl.cell_size)
+    x, y, z = wl.pos[0][: wl.n], wl.pos[1][: wl.n], wl.pos[2][: wl.n]
+    act = oracle.sparse_active(3, lo32, inv, dims, 3, 1, x, y, z)
+    ocs, oci = oracle.cell_list_sparse(3, lo32, inv, dims, 3, act, x, y, z)
+    np.testing.assert_array_equal(cs, ocs)
+    cell_of = np.repeat(np.arange(len(ocs) - 1), np.diff(ocs))
+    np.testing.assert_array_equal(ci[np.lexsort((ci, cell_of))], oci)
+    d.close()
+
+
+@pytest.mark.parametrize("mode", ["local", "fullscan"])
+def test_tree_bidirectional_one_period(mode):
+    """Branching pipe network, dp = 0.004 (about 250k particles), four
+    bidirectional buffers, one full period of the reversing flow: every buffer
+    generates and deletes; brick-sparse grid for the local path."""
+    wl = W.tree3d(dp=0.004)
+    g, dl = _run_steps(wl, 200, mode=mode, check_every=25, brick_log2=3)
+    assert g > 100 and dl > 100
+
+
+def test_tree_full_size_two_steps():
+    """The branching network at dp = 0.001 (about 16 M particles) on the
+    brick-sparse grid: events and every array against the oracle."""
+    _run_steps(W.tree3d(), 2, mode="local", brick_log2=3)

@@ -345,3 +345,167 @@ def random_unit(rng, dim: int) -> np.ndarray:
     if dim == 2:
         v = np.array([v[0], v[1], 0.0])
     return v
+
+
+# ------------------------------------------------------------------ C4 ---
+
+def _perp_basis(t):
+    a = np.array([1.0, 0.0, 0.0]) if abs(t[0]) < 0.9 else np.array([0.0, 1.0, 0.0])
+    u = np.cross(t, a)
+    u /= np.linalg.norm(u)
+    v = np.cross(t, u)
+    return u, v
+
+
+def _child_dir(parent, polar_deg, azim):
+    u, v = _perp_basis(parent)
+    th = math.radians(polar_deg)
+    d = math.cos(th) * parent + math.sin(th) * (math.cos(azim) * u + math.sin(azim) * v)
+    return d / np.linalg.norm(d)
+
+
+class _Tree:
+    """Trunk (R 0.05, L 0.8) along +z from the origin; two daughters (R 0.04, L 0.6)
+    at its end; the second daughter splits into two granddaughters (R 0.03, L 0.5);
+    all lengths scaled by 1.08.
+    Branch polar angles U(25, 50) deg from the parent, azimuths random; spheres of
+    the parent radius fill the junctions."""
+
+    def __init__(self, seed):
+        rng = np.random.Generator(np.random.PCG64(seed))
+        segs = []
+        t0 = np.array([0.0, 0.0, 1.0])
+        f = 1.08  # lengths scaled so that dp = 0.001 gives about 16 M particles
+        segs.append((np.zeros(3), t0, 0.8 * f, 0.05))
+        j1 = segs[0][0] + 0.8 * f * t0
+        phi = rng.uniform(0, 2 * math.pi)
+        d1 = _child_dir(t0, rng.uniform(25, 50), phi)
+        d2 = _child_dir(t0, rng.uniform(25, 50), phi + math.pi + rng.uniform(-0.5, 0.5))
+        segs.append((j1, d1, 0.6 * f, 0.04))
+        segs.append((j1, d2, 0.6 * f, 0.04))
+        j2 = j1 + 0.6 * f * d2
+        psi = rng.uniform(0, 2 * math.pi)
+        g1 = _child_dir(d2, rng.uniform(25, 50), psi)
+        g2 = _child_dir(d2, rng.uniform(25, 50), psi + math.pi + rng.uniform(-0.5, 0.5))
+        segs.append((j2, g1, 0.5 * f, 0.03))
+        segs.append((j2, g2, 0.5 * f, 0.03))
+        self.segs = segs
+        self.spheres = [(j1, 0.05), (j2, 0.04)]
+        self.leaves = [1, 3, 4]
+
+    def inside(self, P):
+        """Membership in the union of the segments and junction spheres; also the
+        segment a point belongs to (nearest axis among those containing it)."""
+        n = P.shape[0]
+        seg_of = np.full(n, -1, dtype=np.int64)
+        best = np.full(n, np.inf)
+        for s, (a, t, L, R) in enumerate(self.segs):
+            rel = P - a
+            u = rel @ t
+            rho2 = np.einsum("ij,ij->i", rel, rel) - u * u
+            ok = (u > 0) & (u < L) & (rho2 < R * R)
+            better = ok & (rho2 < best)
+            seg_of[better] = s
+            best[better] = rho2[better]
+        for (c, R), s_par in zip(self.spheres, (0, 2)):
+            d2 = np.einsum("ij,ij->i", P - c, P - c)
+            ok = (d2 < R * R) & (seg_of < 0)
+            seg_of[ok] = s_par
+        return seg_of >= 0, seg_of
+
+    def frame(self, xp, x, y, z):
+        """Segment axis direction and radial profile factor for the velocity."""
+        best = None
+        tx = ty = tz = prof = None
+        for a, t, L, R in self.segs:
+            rx, ry, rz = x - a[0], y - a[1], z - a[2]
+            u = rx * t[0] + ry * t[1] + rz * t[2]
+            uc = xp.clip(u, 0.0, L)
+            dx, dy, dz = rx - uc * t[0], ry - uc * t[1], rz - uc * t[2]
+            d2 = dx * dx + dy * dy + dz * dz
+            rho2 = rx * rx + ry * ry + rz * rz - u * u
+            pr = xp.clip(1.0 - rho2 / (R * R), 0.0, None)
+            if best is None:
+                best, tx, ty, tz, prof = d2, t[0] + 0 * x, t[1] + 0 * x, t[2] + 0 * x, pr
+            else:
+                take = d2 < best
+                best = xp.where(take, d2, best)
+                tx = xp.where(take, t[0] + 0 * x, tx)
+                ty = xp.where(take, t[1] + 0 * x, ty)
+                tz = xp.where(take, t[2] + 0 * x, tz)
+                prof = xp.where(take, pr, prof)
+        return tx, ty, tz, prof
+
+
+def tree3d(seed: int = 4, dp: float = 0.001, capacity_extra: Optional[int] = None, order: str = "lattice") -> Workload:
+    """3-D branching pipe network (trunk, two daughters, two granddaughters), about
+    16 M particles at dp = 0.001; one bidirectional buffer at the trunk inlet and one
+    at each of the three leaf outlets, X' pointing into the domain; reversing
+    sinusoidal velocity (period 200 dt) with a parabolic profile per segment plus
+    2 % noise, so every buffer both generates and deletes; dt = 0.25 dp."""
+    tree = _Tree(seed)
+    rng = np.random.Generator(np.random.PCG64(seed + 100))
+    idx_all = []
+    # lattice sites ((i + 1/2) dp, ...) inside the union; each site is produced by
+    # the pass of the segment that owns it.  Per z-slice only the bounding box of
+    # the axis points within R of the slice is scanned.
+    for s, (a, t, L, R) in enumerate(tree.segs):
+        zlo = min(a[2], a[2] + L * t[2]) - R - dp
+        zhi = max(a[2], a[2] + L * t[2]) + R + dp
+        k0, k1 = int(math.floor(zlo / dp)), int(math.ceil(zhi / dp))
+        for k in range(k0, k1):
+            z = (k + 0.5) * dp
+            if abs(t[2]) < 1e-9:
+                if abs(a[2] - z) > R:
+                    continue
+                ua, ub = 0.0, L
+            else:
+                u1, u2 = (z - R - a[2]) / t[2], (z + R - a[2]) / t[2]
+                ua, ub = max(0.0, min(u1, u2)), min(L, max(u1, u2))
+                if ua > ub:
+                    ua = ub = min(max(u1, 0.0), L)
+            pa, pb = a + ua * t, a + ub * t
+            x0 = int(math.floor((min(pa[0], pb[0]) - R) / dp)) - 1
+            x1 = int(math.ceil((max(pa[0], pb[0]) + R) / dp)) + 1
+            y0 = int(math.floor((min(pa[1], pb[1]) - R) / dp)) - 1
+            y1 = int(math.ceil((max(pa[1], pb[1]) + R) / dp)) + 1
+            I, J = np.meshgrid(np.arange(x0, x1), np.arange(y0, y1), indexing="ij")
+            I, J = I.ravel(), J.ravel()
+            P = np.stack([(I + 0.5) * dp, (J + 0.5) * dp, np.full(I.size, z)], axis=1)
+            ins, seg = tree.inside(P)
+            keep = ins & (seg == s)
+            if keep.any():
+                idx_all.append(np.stack([I[keep], J[keep], np.full(int(keep.sum()), k)], axis=1))
+    idx = np.concatenate(idx_all)
+    # global lattice order: z slowest, then y, then x
+    idx = idx[np.lexsort((idx[:, 0], idx[:, 1], idx[:, 2]))]
+    pts = (idx + 0.5) * dp + _jitter(rng, idx.shape[0], 3, dp)
+    pts = _finish(idx, pts, order)
+    n = pts.shape[0]
+    cap = n + (capacity_extra if capacity_extra is not None else max(8192, n // 50))
+    pos, carried, names, label, ids = _alloc(3, n, cap, pts, dp)
+    bufs = []
+    a, t, L, R = tree.segs[0]
+    o = a + 2 * dp * t
+    bufs.append(BufferSpec(BIDIR, tuple(o), tuple(t), (2 * dp, R + 2 * dp, R + 2 * dp), 2.6 * dp))
+    for s in tree.leaves:
+        a, t, L, R = tree.segs[s]
+        e = a + L * t
+        o = e - 2 * dp * t
+        bufs.append(BufferSpec(BIDIR, tuple(o), tuple(-t), (2 * dp, R + 2 * dp, R + 2 * dp), 2.6 * dp))
+    dt = 0.25 * dp
+    period = 200
+
+    def velocity(xp, p, step, noise):
+        tx, ty, tz, prof = tree.frame(xp, p[0], p[1], p[2])
+        amp = math.sin(2 * math.pi * step / period)
+        return [amp * prof * tx + 0.02 * noise[0], amp * prof * ty + 0.02 * noise[1],
+                amp * prof * tz + 0.02 * noise[2]]
+
+    m = 2 * 2.6 * dp + 2 * dp
+    lo = tuple(pts.min(axis=0) - m)
+    hi = tuple(pts.max(axis=0) + m)
+    wl = Workload("tree3d", 3, dp, 2.6 * dp, lo, hi, n, cap, pos, carried, names, label, ids, bufs,
+                  dt, 500, 4000, velocity, 1.0)
+    wl.tree = tree
+    return wl
