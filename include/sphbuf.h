@@ -200,6 +200,41 @@ sph_status sph_profile_enable(sph_ctx *ctx, int32_t on);
  * (arrays of SPH_NPHASE); reset != 0 clears them afterwards. */
 sph_status sph_profile_read(sph_ctx *ctx, double ms[SPH_NPHASE], int64_t launches[SPH_NPHASE], int32_t reset);
 
+/* ------------------------------------------------------------------ batches -- */
+
+/* Many independent domains stepped together.  One step runs the cell-list build
+ * and the local-cell update of every domain with five launches in total (count,
+ * scan, scatter, classify, finalize over all domains: a static table maps each
+ * block to a domain), either enqueued directly or replayed from a HIP graph
+ * captured at the first step.  Member contexts keep their own results
+ * (sph_last_result, sph_last_events) and must be fully set up first: a later
+ * sph_buffer_define or sph_grid_fit on a member invalidates the batch. */
+typedef struct sph_batch sph_batch;
+typedef enum { SPH_BATCH_KERNELS = 0, SPH_BATCH_GRAPH = 1 } sph_batch_mode;
+
+/* domains[d] is stepped with particles[d] (pointers are baked into the batch).
+ * stream: hipStream_t for all batch work; NULL makes a private non-blocking
+ * stream (graphs cannot be captured on the null stream).  The caller orders
+ * the batch stream after any work of the members' own streams.  Allocates. */
+sph_status sph_batch_create(sph_ctx *const *domains, const sph_particles *particles, int32_t n_domains,
+                            void *stream, sph_batch **out);
+sph_status sph_batch_destroy(sph_batch *b);
+/* SPH_BATCH_KERNELS or SPH_BATCH_GRAPH (default). */
+sph_status sph_batch_set_mode(sph_batch *b, int32_t mode);
+/* Particles per block of the count and scatter launches (256 .. 2^20; default
+ * 2048).  Sync; drops a captured graph. */
+sph_status sph_batch_set_count_block(sph_batch *b, int32_t particles_per_block);
+/* Async: one step (build + local-cell update) of every domain. */
+sph_status sph_batch_step(sph_batch *b);
+/* Sync: out[d] = result of domain d's last update. */
+sph_status sph_batch_results(sph_batch *b, sph_result *out);
+/* Autotuner: times `trials` steps of each launch mode x particles-per-block
+ * candidate and keeps the fastest (steps are real updates of the current
+ * states).  cache_path (optional) holds earlier choices keyed by device, domain
+ * count and total capacity; a hit skips the sweep.  Outputs may be NULL. */
+sph_status sph_batch_tune(sph_batch *b, int32_t trials, const char *cache_path, int32_t *mode,
+                          int32_t *particles_per_block, double *ms_per_step);
+
 /* ------------------------------------------------------------ host helpers -- */
 /* Pure host FP64; usable without a GPU. */
 

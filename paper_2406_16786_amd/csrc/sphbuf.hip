@@ -79,7 +79,9 @@ struct Parts {
 struct Ctl {
     unsigned int n_gen, n_del, n_rel, pad0;
     unsigned int tile_counter;
-    unsigned int nonfinite_epoch;  // epoch of the last build/scan that met a non-finite position
+    unsigned int nonfinite_build;  // set by the count phase of a build that met a non-finite position
+    unsigned int nonfinite_seen;   // the latest completed build's flag (moved there by its scan phase)
+    unsigned int nonfinite_full;   // set by a full-scan classify; consumed by its finalize
     unsigned int scan_fault;       // set if a look-back or grid-barrier wait ran past its spin limit
     unsigned int bar_count;        // grid barrier of the fused build: arrivals
     unsigned int bar_gen;          // grid barrier generation
@@ -380,14 +382,12 @@ struct CountArgs {
     unsigned long long *tile_state;
     int64_t n_tiles;
     Ctl *ctl;
-    unsigned epoch;
 };
 
-__global__ __launch_bounds__(kBuildBlock) void k_count(CountArgs a) {
+__device__ __forceinline__ void count_body(const CountArgs &a, const int lb, const int G) {
     const int64_t N = live_count(a.n_dev, a.capacity);
     const int lane = threadIdx.x & (kWave - 1);
-    const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
-    const int lb = logical_block();
+    const int64_t nthreads = (int64_t)G * blockDim.x;
     // reset the scan's tile state for this build
     for (int64_t t = (int64_t)lb * blockDim.x + threadIdx.x; t < a.n_tiles; t += nthreads) a.tile_state[t] = 0ull;
     if (lb == 0 && threadIdx.x == 0) {
@@ -395,7 +395,7 @@ __global__ __launch_bounds__(kBuildBlock) void k_count(CountArgs a) {
         a.ctl->scan_fault = 0u;
     }
     // each logical block walks one contiguous segment
-    const int64_t per = ((N + gridDim.x - 1) / gridDim.x + blockDim.x - 1) / blockDim.x * blockDim.x;
+    const int64_t per = ((N + G - 1) / G + blockDim.x - 1) / blockDim.x * blockDim.x;
     const int64_t s0 = (int64_t)lb * per;
     const int64_t s1 = min(N, s0 + per);
     bool bad = false;
@@ -410,8 +410,10 @@ __global__ __launch_bounds__(kBuildBlock) void k_count(CountArgs a) {
             if (i < s1) a.keyrank[i] = ((unsigned long long)key[j] << 32) | (unsigned)rank[j];
         }
     }
-    if (__ballot(bad) != 0ull && lane == 0) atomicMax(&a.ctl->nonfinite_epoch, a.epoch);
+    if (__ballot(bad) != 0ull && lane == 0) atomicOr(&a.ctl->nonfinite_build, 1u);
 }
+
+__global__ __launch_bounds__(kBuildBlock) void k_count(CountArgs a) { count_body(a, logical_block(), gridDim.x); }
 
 // Decoupled look-back scan state: bits 62..63 = flag (1 aggregate, 2 prefix),
 // low 32 bits = value.
@@ -432,11 +434,17 @@ struct ScanArgs {
     Ctl *ctl;
 };
 
-__global__ __launch_bounds__(kScanBlock) void k_scan(ScanArgs a) {
+__device__ __forceinline__ void scan_body(const ScanArgs &a) {
     __shared__ unsigned s_tile;
     __shared__ int s_wave[kScanBlock / kWave];
     __shared__ int s_excl;
-    if (threadIdx.x == 0) s_tile = atomicAdd(&a.ctl->tile_counter, 1u);
+    if (threadIdx.x == 0) {
+        s_tile = atomicAdd(&a.ctl->tile_counter, 1u);
+        if (s_tile == 0u) {  // the count phase is complete: keep its verdict for the next update
+            a.ctl->nonfinite_seen = a.ctl->nonfinite_build;
+            a.ctl->nonfinite_build = 0u;
+        }
+    }
     __syncthreads();
     const unsigned tile = s_tile;
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
@@ -506,6 +514,8 @@ __global__ __launch_bounds__(kScanBlock) void k_scan(ScanArgs a) {
     }
 }
 
+__global__ __launch_bounds__(kScanBlock) void k_scan(ScanArgs a) { scan_body(a); }
+
 struct ScatterArgs {
     const int64_t *n_dev;
     int64_t capacity;
@@ -515,11 +525,10 @@ struct ScatterArgs {
     int32_t *cell_idx;
 };
 
-__global__ __launch_bounds__(kBuildBlock) void k_scatter(ScatterArgs a) {
+__device__ __forceinline__ void scatter_body(const ScatterArgs &a, const int lb, const int G) {
     if (a.ctl->scan_fault) return;
     const int64_t N = live_count(a.n_dev, a.capacity);
-    const int lb = logical_block();
-    const int64_t per = ((N + gridDim.x - 1) / gridDim.x + blockDim.x - 1) / blockDim.x * blockDim.x;
+    const int64_t per = ((N + G - 1) / G + blockDim.x - 1) / blockDim.x * blockDim.x;
     const int64_t s0 = (int64_t)lb * per;
     const int64_t s1 = min(N, s0 + per);
     for (int64_t i = s0 + threadIdx.x; i < s1; i += blockDim.x) {
@@ -528,6 +537,8 @@ __global__ __launch_bounds__(kBuildBlock) void k_scatter(ScatterArgs a) {
         a.cell_idx[a.cell_start[key] + (int)(unsigned)(kr & 0xffffffffull)] = (int32_t)i;
     }
 }
+
+__global__ __launch_bounds__(kBuildBlock) void k_scatter(ScatterArgs a) { scatter_body(a, logical_block(), gridDim.x); }
 
 // ---------------------------------------------------- K0 fused (one launch) --
 //
@@ -555,7 +566,6 @@ struct FusedArgs {
     int32_t *block_sum;
     int64_t m;  // cells + 1
     Ctl *ctl;
-    unsigned epoch;
     int vec;    // positions 16-byte aligned: vector loads allowed
 };
 
@@ -735,8 +745,12 @@ __global__ __launch_bounds__(kFusedBlock) void k_build_fused(FusedArgs a) {
             if (i < s1) a.keyrank[i] = ((unsigned long long)k[j] << 32) | (unsigned)r[j];
         }
     }
-    if (__ballot(bad) != 0ull && lane == 0) atomicMax(&a.ctl->nonfinite_epoch, a.epoch);
+    if (__ballot(bad) != 0ull && lane == 0) atomicOr(&a.ctl->nonfinite_build, 1u);
     if (!grid_barrier(a.ctl, G)) return;
+    if (lb == 0 && threadIdx.x == 0) {  // this build's verdict for the next update
+        a.ctl->nonfinite_seen = a.ctl->nonfinite_build;
+        a.ctl->nonfinite_build = 0u;
+    }
     // ---- scan: block sums of contiguous cell chunks, then the chunk scan ----
     const int64_t chunk = (a.m + G - 1) / G;
     const int64_t c0 = (int64_t)lb * chunk;
@@ -801,7 +815,7 @@ struct LocalArgs {
     EventArgs e;
 };
 
-__global__ __launch_bounds__(kClassifyBlock) void k_classify_local(LocalArgs a) {
+__device__ __forceinline__ void classify_body(const LocalArgs &a, const int vb, const int vg) {
     __shared__ BufDev sb[SPH_MAX_BUFFERS];
     __shared__ unsigned s_cnt[2 * SPH_MAX_BUFFERS];
     for (int t = threadIdx.x; t < a.nb * (int)(sizeof(BufDev) / 4); t += blockDim.x)
@@ -817,7 +831,7 @@ __global__ __launch_bounds__(kClassifyBlock) void k_classify_local(LocalArgs a) 
     const int wave = threadIdx.x / kWave;
     const int wpb = blockDim.x / kWave;
     const int dim = a.p.dim;
-    for (int r = blockIdx.x * wpb + wave; r < a.n_runs; r += gridDim.x * wpb) {
+    for (int r = vb * wpb + wave; r < a.n_runs; r += vg * wpb) {
         const int k = a.run_buf[r];
         const BufDev &b = sb[k];
         const int c0 = a.run_first[r];
@@ -847,12 +861,15 @@ __global__ __launch_bounds__(kClassifyBlock) void k_classify_local(LocalArgs a) 
     block_counts_store(a.e, s_cnt, a.nb);
 }
 
+__global__ __launch_bounds__(kClassifyBlock) void k_classify_local(LocalArgs a) {
+    classify_body(a, blockIdx.x, gridDim.x);
+}
+
 struct FullArgs {
     Parts p;
     const BufDev *bufs;
     int nb;
     EventArgs e;
-    unsigned epoch;
     int vec;  // positions 16-byte aligned: vector loads allowed
 };
 
@@ -917,7 +934,7 @@ __global__ __launch_bounds__(kClassifyBlock) void k_classify_full(FullArgs a) {
             }
         }
     }
-    if (__ballot(bad) != 0ull && lane == 0) atomicMax(&a.e.ctl->nonfinite_epoch, a.epoch);
+    if (__ballot(bad) != 0ull && lane == 0) atomicOr(&a.e.ctl->nonfinite_full, 1u);
     __syncthreads();
     block_counts_store(a.e, s_cnt, a.nb);
 }
@@ -928,8 +945,7 @@ struct FinArgs {
     Parts p;
     int nb;
     int local;
-    int n_part;  // blocks of the classify launch that wrote label-count partials
-    unsigned epoch;
+    int n_part;  // unused
     EventArgs e;
     uint32_t *gen_sorted;  // [cap_ev] sources in ascending order (for sph_last_events)
     uint32_t *del_sorted;  // [cap_ev] deleted indices in ascending order
@@ -1031,7 +1047,7 @@ __device__ __forceinline__ void copy_particle(const Parts &p, int64_t dst, int64
 // canonical layout: sort generated sources and deleted indices, write recycled
 // positions and relabels, refill holes below the new count from the surviving
 // tail in ascending order, append the duplicates with fresh ids.
-__global__ __launch_bounds__(kFinBlock) void k_finalize(FinArgs a) {
+__device__ __forceinline__ void finalize_body(const FinArgs &a) {
     __shared__ uint32_t s_ck[kMaxEv];     // sort chunks of the sources; later the movers
     __shared__ uint32_t s_cv[kMaxEv];     // their payloads (positions in the source list)
     __shared__ uint32_t s_cd[kMaxEv];     // sort chunks of the deleted indices
@@ -1061,7 +1077,8 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(FinArgs a) {
         s_next = c->next_id;
         s_N = *a.p.n_dev;
         s_flags[0] = c->scan_fault;
-        s_flags[1] = c->nonfinite_epoch;
+        s_flags[1] = a.local ? c->nonfinite_seen : c->nonfinite_full;
+        if (!a.local) c->nonfinite_full = 0u;
     }
     __syncthreads();
     {   // the counter copies: 64 x 15 x 2 words, one per thread; zero them for the next update
@@ -1085,7 +1102,7 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(FinArgs a) {
         int st = SPH_OK;
         if (N_raw != N) st = SPH_ERR_ARG;
         else if (a.local && s_flags[0]) st = SPH_ERR_HIP;
-        else if (s_flags[1] == a.epoch) st = SPH_ERR_NONFINITE;
+        else if (s_flags[1]) st = SPH_ERR_NONFINITE;
         for (int k = 0; k < a.nb && st == SPH_OK; ++k)
             if ((long long)s_found[k] < s_nl[k]) st = SPH_ERR_CFL;
         if (st == SPH_OK && (G > a.e.cap_ev || D > a.e.cap_ev || R > a.e.cap_rel)) st = SPH_ERR_EVENTS;
@@ -1180,6 +1197,8 @@ __global__ __launch_bounds__(kFinBlock) void k_finalize(FinArgs a) {
     }
 }
 
+__global__ __launch_bounds__(kFinBlock) void k_finalize(FinArgs a) { finalize_body(a); }
+
 // ------------------------------------------------------------- identify --
 
 struct IdentArgs {
@@ -1237,6 +1256,40 @@ __global__ void k_ident_commit(IdentArgs a) {
         for (int k = 0; k < a.nb; ++k) a.ctl->n_labelled[k] = (long long)a.ctl->ident_count[k];
 }
 
+// ----------------------------------------------------------------- batches --
+//
+// Every phase of every domain of a batch in one launch: a static table maps each
+// block to (domain, block index within that domain's share of the launch).
+
+struct BlockMap {
+    int32_t d;   // domain
+    int32_t vb;  // block within the domain
+};
+
+__global__ __launch_bounds__(kBuildBlock) void kb_count(const CountArgs *args, const BlockMap *map,
+                                                        const int32_t *vg) {
+    const BlockMap m = map[blockIdx.x];
+    count_body(args[m.d], m.vb, vg[m.d]);
+}
+
+__global__ __launch_bounds__(kScanBlock) void kb_scan(const ScanArgs *args, const BlockMap *map) {
+    scan_body(args[map[blockIdx.x].d]);
+}
+
+__global__ __launch_bounds__(kBuildBlock) void kb_scatter(const ScatterArgs *args, const BlockMap *map,
+                                                          const int32_t *vg) {
+    const BlockMap m = map[blockIdx.x];
+    scatter_body(args[m.d], m.vb, vg[m.d]);
+}
+
+__global__ __launch_bounds__(kClassifyBlock) void kb_classify(const LocalArgs *args, const BlockMap *map,
+                                                              const int32_t *vg) {
+    const BlockMap m = map[blockIdx.x];
+    classify_body(args[m.d], m.vb, vg[m.d]);
+}
+
+__global__ __launch_bounds__(kFinBlock) void kb_finalize(const FinArgs *args) { finalize_body(args[blockIdx.x]); }
+
 }  // namespace
 
 // ====================================================================== host ==
@@ -1260,7 +1313,6 @@ struct sph_ctx {
     int build_blocks = 0;
     int full_blocks = 0;
     int fused_blocks = 0;        // grid of the one-launch build (0: three-kernel build)
-    unsigned epoch = 0;          // incremented per build / full scan
     bool built = false;          // a build is pending for the next local update
     int64_t built_capacity = 0;
 
@@ -1387,17 +1439,73 @@ EventArgs events_of(const sph_ctx *ctx) {
     return e;
 }
 
-sph_status launch_finalize(sph_ctx *ctx, const Parts &pp, bool local, int n_part) {
+CountArgs count_args(const sph_ctx *ctx, const Parts &pp) {
+    CountArgs ca{};
+    ca.x = pp.pos[0];
+    ca.y = pp.pos[1];
+    ca.z = pp.pos[2];
+    ca.n_dev = pp.n_dev;
+    ca.capacity = pp.capacity;
+    ca.g = grid_of(ctx);
+    ca.count = ctx->d_count;
+    ca.keyrank = ctx->d_keyrank;
+    ca.tile_state = ctx->d_tile_state;
+    ca.n_tiles = ctx->n_tiles;
+    ca.ctl = ctx->d_ctl;
+    return ca;
+}
+
+ScanArgs scan_args(const sph_ctx *ctx) {
+    ScanArgs sa{};
+    sa.count = ctx->d_count;
+    sa.cell_start = ctx->d_cell_start;
+    sa.m = ctx->n_cells + 1;
+    sa.tile_state = ctx->d_tile_state;
+    sa.ctl = ctx->d_ctl;
+    return sa;
+}
+
+ScatterArgs scatter_args(const sph_ctx *ctx, const Parts &pp) {
+    ScatterArgs xa{};
+    xa.n_dev = pp.n_dev;
+    xa.capacity = pp.capacity;
+    xa.ctl = ctx->d_ctl;
+    xa.keyrank = ctx->d_keyrank;
+    xa.cell_start = ctx->d_cell_start;
+    xa.cell_idx = ctx->d_cell_idx;
+    return xa;
+}
+
+LocalArgs local_args(const sph_ctx *ctx, const Parts &pp) {
+    LocalArgs la{};
+    la.p = pp;
+    la.bufs = ctx->d_bufs;
+    la.nb = ctx->nb;
+    la.run_first = ctx->d_run_first;
+    la.run_len = ctx->d_run_len;
+    la.run_buf = ctx->d_run_buf;
+    la.n_runs = ctx->n_runs;
+    la.cell_start = ctx->d_cell_start;
+    la.cell_idx = ctx->d_cell_idx;
+    la.e = events_of(ctx);
+    return la;
+}
+
+FinArgs fin_args(const sph_ctx *ctx, const Parts &pp, bool local) {
     FinArgs f{};
     f.p = pp;
     f.local = local ? 1 : 0;
-    f.n_part = n_part;
     f.nb = ctx->nb;
-    f.epoch = ctx->epoch;
     f.e = events_of(ctx);
     f.gen_sorted = ctx->d_gen_sorted;
     f.del_sorted = ctx->d_del_sorted;
     f.result = ctx->d_result;
+    return f;
+}
+
+sph_status launch_finalize(sph_ctx *ctx, const Parts &pp, bool local, int n_part) {
+    (void)n_part;
+    const FinArgs f = fin_args(ctx, pp, local);
     {
         ProfScope ps(ctx, SPH_PHASE_FINALIZE);
         hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinBlock), 0, ctx->stream, f);
@@ -1609,7 +1717,6 @@ extern "C" sph_status sph_create(const sph_config *cfg, sph_ctx **out) {
     if (ok) {
         Ctl init{};
         init.next_id = cfg->next_id;
-        init.nonfinite_epoch = 0;
         sph_result r0{};
         ok = hipMemsetAsync(c->d_count, 0, sizeof(int32_t) * m, c->stream) == hipSuccess &&
              hipMemsetAsync(c->d_cell_start, 0, sizeof(int32_t) * m, c->stream) == hipSuccess &&
@@ -1626,7 +1733,6 @@ extern "C" sph_status sph_create(const sph_config *cfg, sph_ctx **out) {
         free_ctx(c);
         return SPH_ERR_HIP;
     }
-    c->epoch = 1;
     // one-launch build: every block must be resident at once (cooperative launch)
     {
         int coop = 0, cus = 0, per_cu = 0;
@@ -1734,7 +1840,6 @@ extern "C" sph_status sph_celllist_build(sph_ctx *ctx, const sph_particles *p) {
     Parts pp;
     const sph_status st = parts_of(ctx, p, pp);
     if (st != SPH_OK) return st;
-    ctx->epoch++;
     if (ctx->fused_blocks > 0) {
         FusedArgs fa{};
         fa.x = pp.pos[0];
@@ -1750,7 +1855,6 @@ extern "C" sph_status sph_celllist_build(sph_ctx *ctx, const sph_particles *p) {
         fa.block_sum = ctx->d_block_sum;
         fa.m = ctx->n_cells + 1;
         fa.ctl = ctx->d_ctl;
-        fa.epoch = ctx->epoch;
         fa.vec = aligned16(fa.x) && aligned16(fa.y) && aligned16(fa.z) ? 1 : 0;
         void *args[] = {&fa};
         hipError_t e;
@@ -1766,42 +1870,19 @@ extern "C" sph_status sph_celllist_build(sph_ctx *ctx, const sph_particles *p) {
         (void)hipGetLastError();
         ctx->fused_blocks = 0;  // not available here: fall back to the three-kernel build
     }
-    CountArgs ca{};
-    ca.x = pp.pos[0];
-    ca.y = pp.pos[1];
-    ca.z = pp.pos[2];
-    ca.n_dev = pp.n_dev;
-    ca.capacity = pp.capacity;
-    ca.g = grid_of(ctx);
-    ca.count = ctx->d_count;
-    ca.keyrank = ctx->d_keyrank;
-    ca.tile_state = ctx->d_tile_state;
-    ca.n_tiles = ctx->n_tiles;
-    ca.ctl = ctx->d_ctl;
-    ca.epoch = ctx->epoch;
+    const CountArgs ca = count_args(ctx, pp);
     {
         ProfScope ps(ctx, SPH_PHASE_COUNT);
         hipLaunchKernelGGL(k_count, dim3(ctx->build_blocks), dim3(kBuildBlock), 0, ctx->stream, ca);
     }
     HIP_TRY(hipGetLastError());
-    ScanArgs sa{};
-    sa.count = ctx->d_count;
-    sa.cell_start = ctx->d_cell_start;
-    sa.m = ctx->n_cells + 1;
-    sa.tile_state = ctx->d_tile_state;
-    sa.ctl = ctx->d_ctl;
+    const ScanArgs sa = scan_args(ctx);
     {
         ProfScope ps(ctx, SPH_PHASE_SCAN);
         hipLaunchKernelGGL(k_scan, dim3((unsigned)ctx->n_tiles), dim3(kScanBlock), 0, ctx->stream, sa);
     }
     HIP_TRY(hipGetLastError());
-    ScatterArgs xa{};
-    xa.n_dev = pp.n_dev;
-    xa.capacity = pp.capacity;
-    xa.ctl = ctx->d_ctl;
-    xa.keyrank = ctx->d_keyrank;
-    xa.cell_start = ctx->d_cell_start;
-    xa.cell_idx = ctx->d_cell_idx;
+    const ScatterArgs xa = scatter_args(ctx, pp);
     {
         ProfScope ps(ctx, SPH_PHASE_SCATTER);
         hipLaunchKernelGGL(k_scatter, dim3(ctx->build_blocks), dim3(kBuildBlock), 0, ctx->stream, xa);
@@ -1819,17 +1900,7 @@ extern "C" sph_status sph_buffer_update_async(sph_ctx *ctx, sph_particles *p) {
     if (st != SPH_OK) return st;
     int n_part = 0;
     if (ctx->n_runs > 0) {
-        LocalArgs la{};
-        la.p = pp;
-        la.bufs = ctx->d_bufs;
-        la.nb = ctx->nb;
-        la.run_first = ctx->d_run_first;
-        la.run_len = ctx->d_run_len;
-        la.run_buf = ctx->d_run_buf;
-        la.n_runs = ctx->n_runs;
-        la.cell_start = ctx->d_cell_start;
-        la.cell_idx = ctx->d_cell_idx;
-        la.e = events_of(ctx);
+        const LocalArgs la = local_args(ctx, pp);
         const int wpb = kClassifyBlock / kWave;
         n_part = std::max(1, std::min(kMaxPartBlocks, (ctx->n_runs + wpb - 1) / wpb));
         ProfScope ps(ctx, SPH_PHASE_CLASSIFY);
@@ -1845,13 +1916,11 @@ static sph_status fullscan_enqueue(sph_ctx *ctx, sph_particles *p) {
     Parts pp;
     const sph_status st = parts_of(ctx, p, pp);
     if (st != SPH_OK) return st;
-    ctx->epoch++;
     FullArgs fa{};
     fa.p = pp;
     fa.bufs = ctx->d_bufs;
     fa.nb = ctx->nb;
     fa.e = events_of(ctx);
-    fa.epoch = ctx->epoch;
     fa.vec = aligned16(pp.pos[0]) && aligned16(pp.pos[1]) && aligned16(pp.pos[2]) ? 1 : 0;
     {
         ProfScope ps(ctx, SPH_PHASE_FULLSCAN);
@@ -2086,4 +2155,308 @@ extern "C" sph_status sph_grid_fit(sph_ctx *ctx, const sph_particles *p) {
         rb.insert(rb.end(), f.size(), (uint8_t)k);
     }
     return upload_runs(ctx, rf, rl, rb);
+}
+
+// ================================================================== batches ==
+
+struct sph_batch {
+    std::vector<sph_ctx *> doms;
+    std::vector<Parts> parts;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int mode = SPH_BATCH_GRAPH;
+    int count_ppb = 2048;  // particles per block of the count / scatter phases
+    CountArgs *d_ca = nullptr;
+    ScanArgs *d_sa = nullptr;
+    ScatterArgs *d_xa = nullptr;
+    LocalArgs *d_la = nullptr;
+    FinArgs *d_fa = nullptr;
+    BlockMap *d_map_count = nullptr, *d_map_scan = nullptr, *d_map_cls = nullptr;
+    int32_t *d_vg_count = nullptr, *d_vg_cls = nullptr;
+    int nb_count = 0, nb_scan = 0, nb_cls = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    sph_result *h_res = nullptr;  // pinned, one per domain
+};
+
+namespace {
+
+void batch_drop_graph(sph_batch *b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+template <class T>
+sph_status upload_table(T *&dst, const std::vector<T> &v, hipStream_t s) {
+    (void)hipFree(dst);
+    dst = nullptr;
+    if (v.empty()) return SPH_OK;
+    HIP_TRY(hipMalloc(&dst, sizeof(T) * v.size()));
+    HIP_TRY(hipMemcpyAsync(dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, s));
+    return SPH_OK;
+}
+
+// Block maps of the count/scatter, scan and classify launches.
+sph_status batch_layout(sph_batch *b) {
+    batch_drop_graph(b);
+    std::vector<BlockMap> mc, ms, ml;
+    std::vector<int32_t> vgc, vgl;
+    const int wpb = kClassifyBlock / kWave;
+    for (size_t d = 0; d < b->doms.size(); ++d) {
+        const sph_ctx *c = b->doms[d];
+        const int64_t cap = b->parts[d].capacity;
+        const int vc = (int)std::max<int64_t>(1, std::min<int64_t>(8192, (cap + b->count_ppb - 1) / b->count_ppb));
+        vgc.push_back(vc);
+        for (int v = 0; v < vc; ++v) mc.push_back({(int32_t)d, v});
+        for (int64_t t = 0; t < c->n_tiles; ++t) ms.push_back({(int32_t)d, (int32_t)t});
+        const int vl = c->n_runs > 0 ? std::max(1, std::min(kMaxPartBlocks, (c->n_runs + wpb - 1) / wpb)) : 0;
+        vgl.push_back(vl);
+        for (int v = 0; v < vl; ++v) ml.push_back({(int32_t)d, v});
+    }
+    sph_status st;
+    if ((st = upload_table(b->d_map_count, mc, b->stream)) != SPH_OK) return st;
+    if ((st = upload_table(b->d_map_scan, ms, b->stream)) != SPH_OK) return st;
+    if ((st = upload_table(b->d_map_cls, ml, b->stream)) != SPH_OK) return st;
+    if ((st = upload_table(b->d_vg_count, vgc, b->stream)) != SPH_OK) return st;
+    if ((st = upload_table(b->d_vg_cls, vgl, b->stream)) != SPH_OK) return st;
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    b->nb_count = (int)mc.size();
+    b->nb_scan = (int)ms.size();
+    b->nb_cls = (int)ml.size();
+    return SPH_OK;
+}
+
+// One step of every domain: five launches whatever the number of domains.
+sph_status batch_enqueue(sph_batch *b) {
+    const int nd = (int)b->doms.size();
+    hipLaunchKernelGGL(kb_count, dim3(b->nb_count), dim3(kBuildBlock), 0, b->stream, b->d_ca, b->d_map_count,
+                       b->d_vg_count);
+    hipLaunchKernelGGL(kb_scan, dim3(b->nb_scan), dim3(kScanBlock), 0, b->stream, b->d_sa, b->d_map_scan);
+    hipLaunchKernelGGL(kb_scatter, dim3(b->nb_count), dim3(kBuildBlock), 0, b->stream, b->d_xa, b->d_map_count,
+                       b->d_vg_count);
+    if (b->nb_cls > 0)
+        hipLaunchKernelGGL(kb_classify, dim3(b->nb_cls), dim3(kClassifyBlock), 0, b->stream, b->d_la, b->d_map_cls,
+                           b->d_vg_cls);
+    hipLaunchKernelGGL(kb_finalize, dim3(nd), dim3(kFinBlock), 0, b->stream, b->d_fa);
+    HIP_TRY(hipGetLastError());
+    return SPH_OK;
+}
+
+void batch_free(sph_batch *b) {
+    if (!b) return;
+    batch_drop_graph(b);
+    (void)hipFree(b->d_ca);
+    (void)hipFree(b->d_sa);
+    (void)hipFree(b->d_xa);
+    (void)hipFree(b->d_la);
+    (void)hipFree(b->d_fa);
+    (void)hipFree(b->d_map_count);
+    (void)hipFree(b->d_map_scan);
+    (void)hipFree(b->d_map_cls);
+    (void)hipFree(b->d_vg_count);
+    (void)hipFree(b->d_vg_cls);
+    if (b->h_res) (void)hipHostFree(b->h_res);
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+}  // namespace
+
+extern "C" sph_status sph_batch_create(sph_ctx *const *domains, const sph_particles *particles, int32_t n_domains,
+                                       void *stream, sph_batch **out) {
+    if (!out) return SPH_ERR_ARG;
+    *out = nullptr;
+    if (!domains || !particles || n_domains < 1 || n_domains > 65535) return SPH_ERR_ARG;
+    sph_batch *b = new (std::nothrow) sph_batch();
+    if (!b) return SPH_ERR_HIP;
+    b->stream = (hipStream_t)stream;
+    if (!b->stream) {  // graphs cannot be captured on the null stream
+        if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete b;
+            return SPH_ERR_HIP;
+        }
+        b->own_stream = true;
+    }
+    std::vector<CountArgs> ca;
+    std::vector<ScanArgs> sa;
+    std::vector<ScatterArgs> xa;
+    std::vector<LocalArgs> la;
+    std::vector<FinArgs> fa;
+    for (int d = 0; d < n_domains; ++d) {
+        sph_ctx *c = domains[d];
+        Parts pp;
+        sph_status st = c ? parts_of(c, &particles[d], pp) : SPH_ERR_ARG;
+        if (st != SPH_OK) {
+            batch_free(b);
+            return st;
+        }
+        (void)hipStreamSynchronize(c->stream);
+        b->doms.push_back(c);
+        b->parts.push_back(pp);
+        ca.push_back(count_args(c, pp));
+        sa.push_back(scan_args(c));
+        xa.push_back(scatter_args(c, pp));
+        la.push_back(local_args(c, pp));
+        fa.push_back(fin_args(c, pp, true));
+    }
+    sph_status st = SPH_OK;
+    if ((st = upload_table(b->d_ca, ca, b->stream)) != SPH_OK || (st = upload_table(b->d_sa, sa, b->stream)) != SPH_OK ||
+        (st = upload_table(b->d_xa, xa, b->stream)) != SPH_OK || (st = upload_table(b->d_la, la, b->stream)) != SPH_OK ||
+        (st = upload_table(b->d_fa, fa, b->stream)) != SPH_OK || (st = batch_layout(b)) != SPH_OK ||
+        hipHostMalloc(&b->h_res, sizeof(sph_result) * n_domains, hipHostMallocDefault) != hipSuccess) {
+        batch_free(b);
+        return st != SPH_OK ? st : SPH_ERR_HIP;
+    }
+    *out = b;
+    return SPH_OK;
+}
+
+extern "C" sph_status sph_batch_destroy(sph_batch *b) {
+    if (!b) return SPH_ERR_ARG;
+    (void)hipStreamSynchronize(b->stream);
+    batch_free(b);
+    return SPH_OK;
+}
+
+extern "C" sph_status sph_batch_set_mode(sph_batch *b, int32_t mode) {
+    if (!b || mode < SPH_BATCH_KERNELS || mode > SPH_BATCH_GRAPH) return SPH_ERR_ARG;
+    b->mode = mode;
+    return SPH_OK;
+}
+
+extern "C" sph_status sph_batch_set_count_block(sph_batch *b, int32_t particles_per_block) {
+    if (!b || particles_per_block < 256 || particles_per_block > (1 << 20)) return SPH_ERR_ARG;
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    b->count_ppb = particles_per_block;
+    return batch_layout(b);
+}
+
+extern "C" sph_status sph_batch_step(sph_batch *b) {
+    if (!b) return SPH_ERR_ARG;
+    if (b->mode == SPH_BATCH_KERNELS) return batch_enqueue(b);
+    if (!b->exec) {
+        HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+        const sph_status st = batch_enqueue(b);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(b->stream, &g);
+        if (st != SPH_OK || e != hipSuccess || !g) {
+            if (g) (void)hipGraphDestroy(g);
+            return st != SPH_OK ? st : SPH_ERR_HIP;
+        }
+        b->graph = g;
+        if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+            batch_drop_graph(b);
+            return SPH_ERR_HIP;
+        }
+    }
+    HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+    return SPH_OK;
+}
+
+extern "C" sph_status sph_batch_results(sph_batch *b, sph_result *out) {
+    if (!b || !out) return SPH_ERR_ARG;
+    for (size_t d = 0; d < b->doms.size(); ++d)
+        HIP_TRY(hipMemcpyAsync(&b->h_res[d], b->doms[d]->d_result, sizeof(sph_result), hipMemcpyDeviceToHost,
+                               b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    for (size_t d = 0; d < b->doms.size(); ++d) out[d] = b->h_res[d];
+    return SPH_OK;
+}
+
+// Autotuner: times `trials` real steps of every candidate (launch mode x
+// particles per count block) and keeps the fastest.  Steps during tuning are
+// genuine updates; once a state has been updated, further updates of unchanged
+// positions change nothing.  With a cache path, the choice is read from / appended
+// to a text file keyed by device, domain count and total capacity.
+extern "C" sph_status sph_batch_tune(sph_batch *b, int32_t trials, const char *cache_path, int32_t *mode_out,
+                                     int32_t *ppb_out, double *ms_out) {
+    if (!b || trials < 1) return SPH_ERR_ARG;
+    int64_t total = 0;
+    for (const Parts &p : b->parts) total += p.capacity;
+    char key[160];
+    hipDeviceProp_t prop{};
+    HIP_TRY(hipGetDeviceProperties(&prop, b->doms[0]->device));
+    std::snprintf(key, sizeof(key), "%s nd=%zu cap=%lld", prop.gcnArchName, b->doms.size(), (long long)total);
+    if (cache_path) {
+        if (FILE *f = std::fopen(cache_path, "r")) {
+            char line[256];
+            int m = -1, ppb = 0;
+            double ms = 0;
+            while (std::fgets(line, sizeof(line), f)) {
+                char k2[160];
+                int mm, pp2;
+                double t;
+                if (std::sscanf(line, "%159[^|]|%d|%d|%lf", k2, &mm, &pp2, &t) == 4 && std::strcmp(k2, key) == 0) {
+                    m = mm;
+                    ppb = pp2;
+                    ms = t;
+                }
+            }
+            std::fclose(f);
+            if (m >= 0) {
+                b->mode = m;
+                if (ppb != b->count_ppb) {
+                    b->count_ppb = ppb;
+                    sph_status st = batch_layout(b);
+                    if (st != SPH_OK) return st;
+                }
+                if (mode_out) *mode_out = m;
+                if (ppb_out) *ppb_out = ppb;
+                if (ms_out) *ms_out = ms;
+                return SPH_OK;
+            }
+        }
+    }
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    const int ppbs[] = {1024, 2048, 4096, 8192};
+    double best = 1e30;
+    int best_mode = b->mode, best_ppb = b->count_ppb;
+    for (int mode = SPH_BATCH_KERNELS; mode <= SPH_BATCH_GRAPH; ++mode)
+        for (int ppb : ppbs) {
+            b->mode = mode;
+            if (ppb != b->count_ppb) {
+                b->count_ppb = ppb;
+                sph_status st = batch_layout(b);
+                if (st != SPH_OK) return st;
+            }
+            for (int w = 0; w < 2; ++w) {
+                sph_status st = sph_batch_step(b);
+                if (st != SPH_OK) return st;
+            }
+            HIP_TRY(hipEventRecord(e0, b->stream));
+            for (int t = 0; t < trials; ++t) {
+                sph_status st = sph_batch_step(b);
+                if (st != SPH_OK) return st;
+            }
+            HIP_TRY(hipEventRecord(e1, b->stream));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            if (ms / trials < best) {
+                best = ms / trials;
+                best_mode = mode;
+                best_ppb = ppb;
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    b->mode = best_mode;
+    if (best_ppb != b->count_ppb) {
+        b->count_ppb = best_ppb;
+        sph_status st = batch_layout(b);
+        if (st != SPH_OK) return st;
+    }
+    if (cache_path)
+        if (FILE *f = std::fopen(cache_path, "a")) {
+            std::fprintf(f, "%s|%d|%d|%.6f\n", key, best_mode, best_ppb, best);
+            std::fclose(f);
+        }
+    if (mode_out) *mode_out = best_mode;
+    if (ppb_out) *ppb_out = best_ppb;
+    if (ms_out) *ms_out = best;
+    return SPH_OK;
 }

@@ -31,7 +31,10 @@ EXPORTED = (
     "sph_state_get", "sph_state_set", "sph_rotation_2d", "sph_rotation_axis_angle",
     "sph_rotation_from_direction", "sph_check_rotation", "sph_grid_cover", "sph_guard_band",
     "sph_status_str", "sph_profile_enable", "sph_profile_read", "sph_grid_fit",
+    "sph_batch_create", "sph_batch_destroy", "sph_batch_set_mode", "sph_batch_set_count_block",
+    "sph_batch_step", "sph_batch_results", "sph_batch_tune",
 )
+SPH_BATCH_KERNELS, SPH_BATCH_GRAPH = 0, 1
 SPH_NPHASE = 7
 PHASES = ("count", "scan", "scatter", "classify", "fullscan", "finalize", "build")
 
@@ -125,6 +128,14 @@ def lib() -> ctypes.CDLL:
                                ctypes.c_double),
             "sph_status_str": ([ctypes.c_int], ctypes.c_char_p),
             "sph_profile_enable": ([_VP, ctypes.c_int32], ctypes.c_int),
+            "sph_batch_create": ([ctypes.POINTER(_VP), ctypes.POINTER(sph_particles), ctypes.c_int32, _VP,
+                                  ctypes.POINTER(_VP)], ctypes.c_int),
+            "sph_batch_destroy": ([_VP], ctypes.c_int),
+            "sph_batch_set_mode": ([_VP, ctypes.c_int32], ctypes.c_int),
+            "sph_batch_set_count_block": ([_VP, ctypes.c_int32], ctypes.c_int),
+            "sph_batch_step": ([_VP], ctypes.c_int),
+            "sph_batch_results": ([_VP, ctypes.POINTER(sph_result)], ctypes.c_int),
+            "sph_batch_tune": ([_VP, ctypes.c_int32, ctypes.c_char_p, _I32, _I32, _D], ctypes.c_int),
             "sph_profile_read": ([_VP, _D, _I64, ctypes.c_int32], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
@@ -300,6 +311,44 @@ def sph_profile_read(ctx: int, reset: bool = False):
     n = np.zeros(SPH_NPHASE, dtype=np.int64)
     st = lib().sph_profile_read(ctx, ms.ctypes.data_as(_D), n.ctypes.data_as(_I64), 1 if reset else 0)
     return st, ms, n
+
+
+def sph_batch_create(ctxs, parts, stream: int = 0):
+    n = len(ctxs)
+    arr = (_VP * n)(*ctxs)
+    parr = (sph_particles * n)(*parts)
+    out = _VP()
+    st = lib().sph_batch_create(arr, parr, n, stream or None, ctypes.byref(out))
+    return st, out.value
+
+
+def sph_batch_destroy(b: int) -> int:
+    return lib().sph_batch_destroy(b)
+
+
+def sph_batch_set_mode(b: int, mode: int) -> int:
+    return lib().sph_batch_set_mode(b, int(mode))
+
+
+def sph_batch_set_count_block(b: int, ppb: int) -> int:
+    return lib().sph_batch_set_count_block(b, int(ppb))
+
+
+def sph_batch_step(b: int) -> int:
+    return lib().sph_batch_step(b)
+
+
+def sph_batch_results(b: int, n: int):
+    res = (sph_result * n)()
+    st = lib().sph_batch_results(b, res)
+    return st, list(res)
+
+
+def sph_batch_tune(b: int, trials: int = 5, cache_path: Optional[str] = None):
+    mode, ppb, ms = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_double(0)
+    st = lib().sph_batch_tune(b, int(trials), cache_path.encode() if cache_path else None, ctypes.byref(mode),
+                              ctypes.byref(ppb), ctypes.byref(ms))
+    return st, mode.value, ppb.value, ms.value
 
 
 # ------------------------------------------------------------- marshalling ---

@@ -509,3 +509,141 @@ def tree3d(seed: int = 4, dp: float = 0.001, capacity_extra: Optional[int] = Non
                   dt, 500, 4000, velocity, 1.0)
     wl.tree = tree
     return wl
+
+
+# ------------------------------------------------------------------ C5 ---
+
+def _hub_lattice(dim, dp, Rh, legs, r, L):
+    """Lattice sites ((i + 1/2) dp) in a hub disk/sphere of radius Rh at the origin
+    united with straight legs (half-width / radius r) from the origin to distance L
+    along the unit directions in legs; each site once."""
+    def inside(P):
+        ok = np.einsum("ij,ij->i", P, P) < Rh * Rh
+        for t in legs:
+            u = P @ t[: P.shape[1]]
+            rho2 = np.einsum("ij,ij->i", P, P) - u * u
+            ok |= (u > 0) & (u < L) & (rho2 < r * r)
+        return ok
+    out = []
+    ext = L + r + 2 * dp
+    n1 = int(math.ceil(ext / dp))
+    if dim == 2:
+        ax = np.arange(-n1, n1)
+        for c in range(0, ax.size, 256):
+            I, J = np.meshgrid(ax, ax[c:c + 256], indexing="ij")
+            idx = np.stack([I.ravel(), J.ravel()], axis=1)
+            P = (idx + 0.5) * dp
+            # cheap reject: outside every leg's and the hub's bounding disc
+            out.append(idx[inside(P)])
+        return np.concatenate(out)
+    # 3-D: per z-slice, the union's bounding box in x, y
+    for k in range(-n1, n1):
+        z = (k + 0.5) * dp
+        boxes = []
+        if abs(z) < Rh:
+            boxes.append((-Rh, Rh, -Rh, Rh))
+        for t in legs:
+            if abs(t[2]) < 1e-9:
+                if abs(z) > r:
+                    continue
+                ua, ub = 0.0, L
+            else:
+                u1, u2 = (z - r) / t[2], (z + r) / t[2]
+                ua, ub = max(0.0, min(u1, u2)), min(L, max(u1, u2))
+                if ua > ub:
+                    continue
+            pa, pb = ua * t, ub * t
+            boxes.append((min(pa[0], pb[0]) - r, max(pa[0], pb[0]) + r, min(pa[1], pb[1]) - r, max(pa[1], pb[1]) + r))
+        if not boxes:
+            continue
+        bx = np.array(boxes)
+        x0, x1 = int(math.floor(bx[:, 0].min() / dp)) - 1, int(math.ceil(bx[:, 1].max() / dp)) + 1
+        y0, y1 = int(math.floor(bx[:, 2].min() / dp)) - 1, int(math.ceil(bx[:, 3].max() / dp)) + 1
+        I, J = np.meshgrid(np.arange(x0, x1), np.arange(y0, y1), indexing="ij")
+        I, J = I.ravel(), J.ravel()
+        P = np.stack([(I + 0.5) * dp, (J + 0.5) * dp, np.full(I.size, z)], axis=1)
+        keep = inside(P)
+        if keep.any():
+            out.append(np.stack([I[keep], J[keep], np.full(int(keep.sum()), k)], axis=1))
+    return np.concatenate(out)
+
+
+def hub_domain(index: int, n_target: int, dim: int, n_legs: int, seed_base: int = 5000) -> Workload:
+    """One hub-and-spoke domain: a hub of radius 1 with n_legs straight legs (radius
+    0.35, reaching distance 4 from the centre) in random directions at least 40 deg
+    apart; dp chosen so the domain holds about n_target particles.  Leg 0 ends in an
+    inlet, the others in outlets; a single leg ends in a bidirectional buffer with
+    oscillating flow.  Poiseuille flow along each leg, 2 % noise, dt = 0.25 dp."""
+    rng = np.random.Generator(np.random.PCG64(seed_base + index))
+    Rh, r, L = 1.0, 0.35, 4.0
+    legs = []
+    while len(legs) < n_legs:
+        v = rng.standard_normal(3)
+        if dim == 2:
+            v[2] = 0.0
+        v /= np.linalg.norm(v)
+        if all(float(v @ w) < math.cos(math.radians(40.0)) for w in legs):
+            legs.append(v)
+    if dim == 2:
+        vol = math.pi * Rh * Rh + n_legs * 2 * r * (L - Rh)
+    else:
+        vol = 4.0 / 3.0 * math.pi * Rh ** 3 + n_legs * math.pi * r * r * (L - Rh)
+    dp = (vol / n_target) ** (1.0 / dim)
+    idx = _hub_lattice(dim, dp, Rh, legs, r, L)
+    idx = idx[np.lexsort(tuple(idx[:, c] for c in range(dim)))]
+    pts = (idx + 0.5) * dp + _jitter(rng, idx.shape[0], dim, dp)
+    n = pts.shape[0]
+    cap = n + max(1024, n // 20)
+    pos, carried, names, label, ids = _alloc(dim, n, cap, pts, dp)
+    bufs = []
+    for j, t in enumerate(legs):
+        e = L * t
+        o = e - 2 * dp * t
+        half = (2 * dp, r + 2 * dp, r + 2 * dp if dim == 3 else 0.0)
+        if n_legs == 1:
+            kind, d = BIDIR, -t
+        elif j == 0:
+            kind, d = INLET, -t
+        else:
+            kind, d = OUTLET, t
+        ang = math.atan2(d[1], d[0]) if dim == 2 else None
+        bufs.append(BufferSpec(kind, tuple(o), tuple(d), half, 2.6 * dp, angle=ang))
+    sign = np.array([-1.0 if (j == 0 or n_legs == 1) else 1.0 for j in range(n_legs)])
+
+    def velocity(xp, p, step, noise):
+        x, y = p[0], p[1]
+        z = p[2] if dim == 3 else 0.0 * x
+        amp = math.sin(2 * math.pi * step / 200.0) if n_legs == 1 else 1.0
+        vx, vy, vz = 0.0 * x, 0.0 * x, 0.0 * x
+        for j, t in enumerate(legs):
+            u = x * t[0] + y * t[1] + z * t[2]
+            rho2 = x * x + y * y + z * z - u * u
+            prof = xp.clip(1.0 - rho2 / (r * r), 0.0, None) * ((u > Rh) & (u < L + r))
+            s = amp * sign[j]
+            vx = vx + s * prof * t[0]
+            vy = vy + s * prof * t[1]
+            vz = vz + s * prof * t[2]
+        u_ = [vx + 0.02 * noise[0], vy + 0.02 * noise[1]]
+        if dim == 3:
+            u_.append(vz + 0.02 * noise[2])
+        return u_
+
+    m = 2 * 2.6 * dp + 2 * dp
+    lo = tuple(list(pts.min(axis=0) - m) + [0.0] * (3 - dim))
+    hi = tuple(list(pts.max(axis=0) + m) + [0.0] * (3 - dim))
+    wl = Workload(f"hub{index}", dim, dp, 2.6 * dp, lo, hi, n, cap, pos, carried, names, label, ids, bufs,
+                  0.25 * dp, 200, 6000 + 100 * index, velocity, 1.0)
+    return wl
+
+
+def hub_batch(n_domains: int = 64, n_min: float = 1e4, n_max: float = 2e6, seed: int = 5) -> List[Workload]:
+    """A batch of independent hub-and-spoke domains: dimension 2 or 3 with equal
+    odds, particle counts log-uniform over [n_min, n_max], 1-6 legs each."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for i in range(n_domains):
+        dim = int(rng.integers(2, 4))
+        n_t = int(round(math.exp(rng.uniform(math.log(n_min), math.log(n_max)))))
+        n_legs = int(rng.integers(1, 7))
+        out.append(hub_domain(i, n_t, dim, n_legs))
+    return out
