@@ -75,9 +75,20 @@ struct Parts {
     int64_t capacity;
 };
 
+// Event lists are split into kSeg segments, each with its own counters on a
+// 128-byte line of its own: a wave appends to segment (wave index mod kSeg), so
+// concurrent waves spread their slot atomics over kSeg addresses instead of
+// queueing on one (same-address device atomics serialise at about 12 ns each).
+constexpr int kSeg = 16;
+
+struct SegCtr {
+    unsigned int n_gen, n_del, n_rel;
+    unsigned int pad[29];
+};
+
 // Device-resident counters and library state.
 struct Ctl {
-    unsigned int n_gen, n_del, n_rel, pad0;
+    SegCtr seg[kSeg];
     unsigned int tile_counter;
     unsigned int nonfinite_build;  // set by the count phase of a build that met a non-finite position
     unsigned int nonfinite_seen;   // the latest completed build's flag (moved there by its scan phase)
@@ -85,7 +96,7 @@ struct Ctl {
     unsigned int scan_fault;       // set if a look-back or grid-barrier wait ran past its spin limit
     unsigned int bar_count;        // grid barrier of the fused build: arrivals
     unsigned int bar_gen;          // grid barrier generation
-    unsigned int pad2;
+    unsigned int fin_ticket;       // finalize blocks that have read the counters
     long long next_id;
     long long n_labelled[16];
     unsigned int ident_bad;
@@ -195,18 +206,6 @@ __device__ __forceinline__ unsigned classify(const BufDev &b, int dim, float x, 
     return bits;
 }
 
-// Wave-compacted slot allocation: one atomic per wave, slot = base + mbcnt(ballot).
-// Returns the lane's slot, or 0xffffffff for lanes that do not append.
-__device__ __forceinline__ unsigned wave_slot(bool pred, unsigned *counter) {
-    const unsigned long long m = __ballot(pred);
-    if (m == 0ull) return 0xffffffffu;
-    const int leader = __ffsll((long long)m) - 1;
-    unsigned base = 0;
-    if (lane_id() == leader) base = atomicAdd(counter, (unsigned)__popcll(m));
-    base = __shfl(base, leader);
-    return pred ? base + mbcnt(m) : 0xffffffffu;
-}
-
 __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
     return v;
@@ -253,15 +252,16 @@ __device__ __forceinline__ Outcome decide(const BufDev &b, int k, int dim, unsig
     return o;
 }
 
-constexpr int kDupStride = 3 + SPH_MAX_CARRIED;  // floats per captured duplicate
-
+// Event storage: kSeg segments of cap_ev generation / deletion slots and cap_rel
+// relabel slots.  Slot t of segment g is entry g * cap + t of each array; a
+// duplicate payload takes 3 + n_carried floats.
 struct EventArgs {
     Ctl *ctl;
-    uint32_t *gen_idx;         // [cap_ev] generated-source index (append order)
-    float *gen_new;            // [cap_ev * 3] its recycled position
-    float *dup;                // [cap_ev * kDupStride] its pre-recycle position and carried fields
-    uint32_t *del_idx;         // [cap_ev] deleted index (append order)
-    unsigned long long *rel;   // [cap_rel] (index << 32) | new label
+    uint32_t *gen_idx;         // [kSeg * cap_ev] generated-source index
+    float *gen_new;            // [kSeg * cap_ev * 3] its recycled position
+    float *dup;                // [kSeg * cap_ev * (3 + nc)] its pre-recycle position and carried fields
+    uint32_t *del_idx;         // [kSeg * cap_ev] deleted index
+    unsigned long long *rel;   // [kSeg * cap_rel] (index << 32) | new label
     unsigned cap_ev;
     unsigned cap_rel;
     unsigned *part;  // label counts, kCountReplicas copies: part[(copy * 16 + k) * 2 + {0: found, 1: post}]
@@ -291,32 +291,54 @@ __device__ __forceinline__ void block_counts_store(const EventArgs &e, const uns
                   s_cnt[threadIdx.x]);
 }
 
-// Emit the wave's events for buffer k and accumulate its label counts.  A
-// generating lane also captures the duplicate's payload (the state before the
-// recycle) and the recycled position r - a d (FP64, rounded to FP32): nothing of
-// the caller's arrays is written here, so a failed status check can still leave
-// them untouched, and the finalize step has no random reads left to do.
-__device__ __forceinline__ void emit(const EventArgs &e, const Parts &p, const BufDev &b, int k, bool valid,
-                                     int64_t i, int lab, const Outcome &o, float x, float y, float z,
+// Emit the wave's events for buffer k into event segment seg and accumulate its
+// label counts.  The three slot atomics are issued together.  A generating lane
+// also captures the duplicate's payload (the state before the recycle) and the
+// recycled position r - a d (FP64, rounded to FP32): nothing of the caller's
+// arrays is written here, so a failed status check can still leave them
+// untouched, and the finalize step has no random reads left to do.
+__device__ __forceinline__ void emit(const EventArgs &e, const Parts &p, const BufDev &b, int k, int seg,
+                                     bool valid, int64_t i, int lab, const Outcome &o, float x, float y, float z,
                                      unsigned long long &found, unsigned long long &post) {
     const bool in = valid && o.newlab >= 0;
     if (in && o.mine) found++;
     if (in && o.ev != kEvDel && o.newlab == k + 1) post++;
-    unsigned s = wave_slot(in && o.ev == kEvGen, &e.ctl->n_gen);
-    if (s < e.cap_ev) {
-        e.gen_idx[s] = (uint32_t)i;
-        const float r[3] = {x, y, z};
-        float *d = e.dup + (size_t)s * kDupStride;
-        for (int c = 0; c < p.dim; ++c) {
-            d[c] = r[c];
-            e.gen_new[3 * (size_t)s + c] = (float)((double)r[c] - b.shift[c]);
+    const bool pg = in && o.ev == kEvGen, pd = in && o.ev == kEvDel, pr = in && o.ev != kEvDel && o.newlab != lab;
+    const unsigned long long mg = __ballot(pg), md = __ballot(pd), mr = __ballot(pr);
+    if ((mg | md | mr) == 0ull) return;
+    SegCtr &sc = e.ctl->seg[seg];
+    const int lane = lane_id();
+    const int lg = mg ? __ffsll((long long)mg) - 1 : 0, ld = md ? __ffsll((long long)md) - 1 : 0,
+              lr = mr ? __ffsll((long long)mr) - 1 : 0;
+    unsigned bg = 0, bd = 0, br = 0;
+    if (mg && lane == lg) bg = atomicAdd(&sc.n_gen, (unsigned)__popcll(mg));
+    if (md && lane == ld) bd = atomicAdd(&sc.n_del, (unsigned)__popcll(md));
+    if (mr && lane == lr) br = atomicAdd(&sc.n_rel, (unsigned)__popcll(mr));
+    bg = __shfl(bg, lg);
+    bd = __shfl(bd, ld);
+    br = __shfl(br, lr);
+    if (pg) {
+        const unsigned s = bg + mbcnt(mg);
+        if (s < e.cap_ev) {
+            const size_t ev = (size_t)seg * e.cap_ev + s;
+            e.gen_idx[ev] = (uint32_t)i;
+            const float r[3] = {x, y, z};
+            float *d = e.dup + ev * (size_t)(3 + p.nc);
+            for (int c = 0; c < p.dim; ++c) {
+                d[c] = r[c];
+                e.gen_new[3 * ev + c] = (float)((double)r[c] - b.shift[c]);
+            }
+            for (int f = 0; f < p.nc; ++f) d[3 + f] = p.car[f][i];
         }
-        for (int f = 0; f < p.nc; ++f) d[3 + f] = p.car[f][i];
     }
-    s = wave_slot(in && o.ev == kEvDel, &e.ctl->n_del);
-    if (s < e.cap_ev) e.del_idx[s] = (uint32_t)i;
-    s = wave_slot(in && o.ev != kEvDel && o.newlab != lab, &e.ctl->n_rel);
-    if (s < e.cap_rel) e.rel[s] = ((unsigned long long)i << 32) | (unsigned)o.newlab;
+    if (pd) {
+        const unsigned s = bd + mbcnt(md);
+        if (s < e.cap_ev) e.del_idx[(size_t)seg * e.cap_ev + s] = (uint32_t)i;
+    }
+    if (pr) {
+        const unsigned s = br + mbcnt(mr);
+        if (s < e.cap_rel) e.rel[(size_t)seg * e.cap_rel + s] = ((unsigned long long)i << 32) | (unsigned)o.newlab;
+    }
 }
 
 // --------------------------------------------------------------- K0 build --
@@ -834,6 +856,7 @@ __device__ __forceinline__ void classify_body(const LocalArgs &a, const int vb, 
     for (int r = vb * wpb + wave; r < a.n_runs; r += vg * wpb) {
         const int k = a.run_buf[r];
         const BufDev &b = sb[k];
+        const int seg = r % kSeg;
         const int c0 = a.run_first[r];
         const int j0 = a.cell_start[c0];
         const int j1 = a.cell_start[c0 + a.run_len[r]];
@@ -853,7 +876,7 @@ __device__ __forceinline__ void classify_body(const LocalArgs &a, const int vb, 
                 const unsigned bits = classify(b, dim, x, y, z);
                 if (bits & kIn) o = decide(b, k, dim, bits, lab, x, y, z);
             }
-            emit(a.e, a.p, b, k, valid, i, lab, o, x, y, z, found, post);
+            emit(a.e, a.p, b, k, seg, valid, i, lab, o, x, y, z, found, post);
         }
         block_counts_add(s_cnt, k, found, post);
     }
@@ -884,6 +907,7 @@ __global__ __launch_bounds__(kClassifyBlock) void k_classify_full(FullArgs a) {
     const int lane = threadIdx.x & (kWave - 1);
     const int dim = a.p.dim;
     const int lb = logical_block();
+    const int seg = (lb * (int)(blockDim.x / kWave) + (int)(threadIdx.x / kWave)) % kSeg;
     constexpr int kVec = 4;  // particles per thread per step: one 16-byte load per coordinate
     const int64_t quant = (int64_t)blockDim.x * kVec;
     const int64_t per = ((N + gridDim.x - 1) / gridDim.x + quant - 1) / quant * quant;
@@ -929,7 +953,7 @@ __global__ __launch_bounds__(kClassifyBlock) void k_classify_full(FullArgs a) {
                     o = decide(sb[k], k, dim, bits, lab, x, y, z);
                 }
                 unsigned long long found = 0, post = 0;
-                emit(a.e, a.p, sb[k], k, valid, i, lab, o, x, y, z, found, post);
+                emit(a.e, a.p, sb[k], k, seg, valid, i, lab, o, x, y, z, found, post);
                 block_counts_add(s_cnt, k, found, post);
             }
         }
@@ -940,188 +964,564 @@ __global__ __launch_bounds__(kClassifyBlock) void k_classify_full(FullArgs a) {
 }
 
 // ------------------------------------------------------------- K2 finalize --
+//
+// nfb workgroups per domain.  Every block reads the counters and takes the
+// status decision (all checks come before any write), loads the event lists
+// and sorts the generated sources and the deleted indices in LDS; each block
+// then applies its share of the writes, and no block writes a location that
+// another block reads:
+//   * recycle and relabel of particles below the new count N' = N - |D| are
+//     done in place (those particles neither move nor are deleted), split by
+//     event number;
+//   * the positions p of the tail [N', N' + max(|G|, |D|)) are split among the
+//     blocks: the thread of p first moves the survivor at p (its recycle and
+//     relabel applied from an LDS map of the tail) into its hole, then writes
+//     the duplicate appended at p.  Holes are deleted particles below N'.
+// The block that takes the last ticket (every block has read the counters by
+// then) writes the result and clears the counters for the next update.
+
+constexpr int kFinBlocksMax = 32;
 
 struct FinArgs {
     Parts p;
     int nb;
     int local;
-    int n_part;  // unused
     EventArgs e;
     uint32_t *gen_sorted;  // [cap_ev] sources in ascending order (for sph_last_events)
     uint32_t *del_sorted;  // [cap_ev] deleted indices in ascending order
     sph_result *result;
 };
 
-// Bitonic sort of 64 keys (one per lane) with a payload, in registers.
-__device__ __forceinline__ void wave_sort64(uint32_t &key, uint32_t &val) {
-    const int lane = lane_id();
-#pragma unroll
-    for (int k = 2; k <= kWave; k <<= 1) {
-#pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            const uint32_t ok = __shfl_xor(key, j), ov = __shfl_xor(val, j);
-            const bool lower = (lane & j) == 0, asc = (lane & k) == 0;
-            if (lower == asc ? ok < key : ok > key) {
-                key = ok;
-                val = ov;
-            }
-        }
+// Value held by lane (lane ^ J).  J = 1, 2: one DPP quad permutation; J = 4, 8:
+// two DPP moves (mirror within 8 or 16 lanes, then xor 3 or xor 7); J = 16:
+// ds_swizzle in xor mode (within 32 lanes); J = 32: ds_bpermute.
+template <int J>
+__device__ __forceinline__ uint32_t xor_lane(uint32_t x) {
+    const int v = (int)x;
+    if constexpr (J == 1) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true);
+    } else if constexpr (J == 2) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true);
+    } else if constexpr (J == 4) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp(__builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, true), 0x1B, 0xF, 0xF,
+                                                  true);
+    } else if constexpr (J == 8) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp(__builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, true), 0x141, 0xF,
+                                                  0xF, true);
+    } else if constexpr (J == 16) {
+        return (uint32_t)__builtin_amdgcn_ds_swizzle(v, 0x401F);
+    } else {
+        static_assert(J == 32, "lane distance");
+        return (uint32_t)__builtin_amdgcn_ds_bpermute((lane_id() ^ 32) << 2, v);
     }
 }
 
-// Number of entries of a sorted 64-entry chunk below key.
-__device__ __forceinline__ unsigned count_below64(const uint32_t *c, uint32_t key) {
-    unsigned lo = 0;
-#pragma unroll
-    for (unsigned step = 32; step > 0; step >>= 1)
-        if (c[lo + step - 1] < key) lo += step;
-    if (c[lo] < key) ++lo;  // lo <= 63 here; this settles "all 64 below"
-    return lo;
-}
+// Bitonic sort of 256 keys with payloads held by one wave, four per lane
+// (element r * 64 + lane in register r).  Partners at distance >= 64 sit in
+// another register of the same lane; closer ones in another lane.
+constexpr int kChunk = 4 * kWave;
 
-// Sort two lists of unique 32-bit keys at once (generated sources, with their
-// list positions as payload, and deleted indices).  The first half of the waves
-// sorts 64-key chunks of list A in registers, the second half those of list B;
-// then each key's final rank is its place in its chunk plus, for every other
-// chunk of its list, the number of keys there below it (binary search).
-// Ends with a barrier.
-__device__ void block_sort_pair(const uint32_t *in_a, unsigned na, const uint32_t *in_b, unsigned nb_,
-                                uint32_t *s_ca, uint32_t *s_va, uint32_t *s_cb, uint32_t *out_a, uint32_t *out_va,
-                                uint32_t *out_b) {
-    const unsigned ncha = (na + kWave - 1) / kWave, nchb = (nb_ + kWave - 1) / kWave;
-    const unsigned nwave = blockDim.x / kWave, half = nwave / 2;
-    const unsigned wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-    if (wave < half) {
-        for (unsigned c = wave; c < ncha; c += half) {
-            const unsigned e = c * kWave + lane;
-            uint32_t key = e < na ? in_a[e] : 0xffffffffu, val = e;
-            wave_sort64(key, val);
-            s_ca[e] = key;
-            s_va[e] = val;
+template <int K, int J>
+__device__ __forceinline__ void bitonic_step(uint32_t (&k)[4], uint32_t (&v)[4], int lane) {
+    if constexpr (J >= kWave) {
+        constexpr int RJ = J / kWave;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            if (r & RJ) continue;
+            const int rp = r | RJ;
+            const bool asc = ((r * kWave) & K) == 0;
+            const bool sw = asc ? k[rp] < k[r] : k[rp] > k[r];
+            const uint32_t k0 = k[r], v0 = v[r];
+            k[r] = sw ? k[rp] : k0;
+            v[r] = sw ? v[rp] : v0;
+            k[rp] = sw ? k0 : k[rp];
+            v[rp] = sw ? v0 : v[rp];
         }
     } else {
-        for (unsigned c = wave - half; c < nchb; c += nwave - half) {
-            const unsigned e = c * kWave + lane;
-            uint32_t key = e < nb_ ? in_b[e] : 0xffffffffu, val = e;
-            wave_sort64(key, val);
-            s_cb[e] = key;
+        const bool lower = (lane & J) == 0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const bool asc = ((r * kWave + lane) & K) == 0;
+            const uint32_t kp = xor_lane<J>(k[r]), vp = xor_lane<J>(v[r]);
+            const bool take = lower == asc ? kp < k[r] : kp > k[r];
+            k[r] = take ? kp : k[r];
+            v[r] = take ? vp : v[r];
         }
     }
-    __syncthreads();
-    const unsigned tot = (ncha + nchb) * kWave;
-    for (unsigned t = threadIdx.x; t < tot; t += blockDim.x) {
-        const bool is_a = t < ncha * kWave;
-        const unsigned e = is_a ? t : t - ncha * kWave;
-        const uint32_t *chunks = is_a ? s_ca : s_cb;
-        const unsigned nch = is_a ? ncha : nchb, n = is_a ? na : nb_;
-        const uint32_t key = chunks[e];
-        if (key == 0xffffffffu) continue;
-        const unsigned mine = e / kWave;
-        unsigned rank = e % kWave;
-        for (unsigned c = 0; c < nch; ++c)
-            if (c != mine) rank += count_below64(chunks + c * kWave, key);
-        if (rank >= n) continue;  // cannot happen for unique keys; never write out of range
-        if (is_a) {
-            out_a[rank] = key;
-            out_va[rank] = s_va[e];
-        } else {
-            out_b[rank] = key;
+}
+
+template <int K, int J>
+__device__ __forceinline__ void bitonic_merge(uint32_t (&k)[4], uint32_t (&v)[4], int lane) {
+    bitonic_step<K, J>(k, v, lane);
+    if constexpr (J > 1) bitonic_merge<K, J / 2>(k, v, lane);
+}
+
+template <int K>
+__device__ __forceinline__ void bitonic_sort256(uint32_t (&k)[4], uint32_t (&v)[4], int lane) {
+    bitonic_merge<K, K / 2>(k, v, lane);
+    if constexpr (K < kChunk) bitonic_sort256<K * 2>(k, v, lane);
+}
+
+// For two keys at once (independent searches, so their LDS reads overlap): the
+// number of entries of the sorted run r[0, len) below the key (or not above it,
+// if or_equal).  w is a power of two >= len; len 0 means no search.
+__device__ __forceinline__ void run_rank2(const uint32_t *r0, unsigned len0, uint32_t key0, bool oe0,
+                                          const uint32_t *r1, unsigned len1, uint32_t key1, bool oe1, unsigned w,
+                                          unsigned &c0, unsigned &c1) {
+    unsigned lo0 = 0, lo1 = 0;
+    for (unsigned step = w >> 1; step > 0; step >>= 1) {
+        const unsigned j0 = lo0 + step - 1, j1 = lo1 + step - 1;
+        bool t0 = false, t1 = false;
+        if (j0 < len0) {
+            const uint32_t x = r0[j0];
+            t0 = oe0 ? x <= key0 : x < key0;
         }
+        if (j1 < len1) {
+            const uint32_t x = r1[j1];
+            t1 = oe1 ? x <= key1 : x < key1;
+        }
+        lo0 += t0 ? step : 0u;
+        lo1 += t1 ? step : 0u;
     }
-    __syncthreads();
+    if (lo0 < len0) {
+        const uint32_t x = r0[lo0];
+        lo0 += (oe0 ? x <= key0 : x < key0) ? 1u : 0u;
+    }
+    if (lo1 < len1) {
+        const uint32_t x = r1[lo1];
+        lo1 += (oe1 ? x <= key1 : x < key1) ? 1u : 0u;
+    }
+    c0 = lo0;
+    c1 = lo1;
 }
 
-__device__ __forceinline__ void copy_particle(const Parts &p, int64_t dst, int64_t src) {
-    float v[3 + SPH_MAX_CARRIED];
-    for (int c = 0; c < p.dim; ++c) v[c] = p.pos[c][src];
-    for (int f = 0; f < p.nc; ++f) v[3 + f] = p.car[f][src];
-    const int32_t lab = p.label[src];
-    const int64_t id = p.id[src];
-    for (int c = 0; c < p.dim; ++c) p.pos[c][dst] = v[c];
-    for (int f = 0; f < p.nc; ++f) p.car[f][dst] = v[3 + f];
-    p.label[dst] = lab;
-    p.id[dst] = id;
+// Even split of [0, n) among nparts: part q gets [lo, hi).
+__device__ __forceinline__ void share_of(unsigned n, int q, int nparts, unsigned &lo, unsigned &hi) {
+    const unsigned chunk = (n + (unsigned)nparts - 1u) / (unsigned)nparts;
+    lo = min(n, (unsigned)q * chunk);
+    hi = min(n, lo + chunk);
 }
 
-// One workgroup: status checks before any write, then (only if all pass) the
-// canonical layout: sort generated sources and deleted indices, write recycled
-// positions and relabels, refill holes below the new count from the surviving
-// tail in ascending order, append the duplicates with fresh ids.
-__device__ __forceinline__ void finalize_body(const FinArgs &a) {
-    __shared__ uint32_t s_ck[kMaxEv];     // sort chunks of the sources; later the movers
-    __shared__ uint32_t s_cv[kMaxEv];     // their payloads (positions in the source list)
-    __shared__ uint32_t s_cd[kMaxEv];     // sort chunks of the deleted indices
-    __shared__ uint32_t s_gslot[kMaxEv];  // duplicate slot of the j-th smallest source
-    __shared__ uint32_t s_del[kMaxEv];    // deleted indices, ascending
-    __shared__ unsigned s_bits[kMaxEv / 32];
-    __shared__ unsigned s_wpre[kMaxEv / 32];
+// Segment of a flat event number e, given the exclusive segment offsets.
+__device__ __forceinline__ int seg_of(const unsigned *off, unsigned e) {
+    int g = 0;
+    while (g + 1 < kSeg && off[g + 1] <= e) ++g;
+    return g;
+}
+
+constexpr uint32_t kMapRelShift = 20;  // tail map: bits 0..19 recycle entry + 1, bits 20.. new label + 1
+constexpr int kSortBuckets = 8192;   // buckets per list of the finalize's counting sort (16-bit counters)
+constexpr int kSortBucketMax = 64;   // fuller buckets: comparison sort instead
+static_assert(kMaxEv % kFinBlock == 0 && kSortBuckets % kFinBlock == 0 && kMaxEv < 65536, "finalize sort layout");
+
+__device__ __forceinline__ void finalize_body(const FinArgs &a, const int fb, const int nfb) {
+    __shared__ uint32_t s_k[2][2][kMaxEv];  // [list: 0 sources, 1 deleted][ping-pong] keys
+    __shared__ uint32_t s_v[2][kMaxEv];     // [ping-pong] event entry of each source
+    __shared__ uint32_t s_map[kMaxEv];      // tail position t = p - N': recycle entry and new label
+    __shared__ unsigned s_bits[kMaxEv / 32], s_wpre[kMaxEv / 32];  // deleted tail positions, prefix per word
+    __shared__ unsigned s_off[3][kSeg + 1];  // per list: segment counts, then exclusive offsets; [kSeg] = total
     __shared__ int s_status;
-    __shared__ unsigned s_G, s_D, s_R, s_taildel;
+    __shared__ unsigned s_last;
     __shared__ long long s_N, s_next;
     __shared__ unsigned s_found[SPH_MAX_BUFFERS], s_post[SPH_MAX_BUFFERS];
     __shared__ long long s_nl[SPH_MAX_BUFFERS];
     __shared__ unsigned s_flags[2];
+    __shared__ uint32_t s_hist[kSortBuckets];      // per list, two buckets per word: counts, then starts
+    __shared__ uint32_t s_mm[2][2];                // per list: min and max key
+    __shared__ unsigned s_fat[2];                  // per list: keys in the fullest bucket
+    __shared__ unsigned s_wsum[kFinBlock / kWave];
     Ctl *c = a.e.ctl;
     const int tid = threadIdx.x;
-    const int lane = tid & (kWave - 1);
-    // ---- gather what the status decision needs, in parallel ----
+    const unsigned bd = blockDim.x;
+    const int words = kCountReplicas * 2 * SPH_MAX_BUFFERS;
+    // ---- read everything the status decision needs in one round trip ----
     if (tid < SPH_MAX_BUFFERS) {
         s_found[tid] = 0u;
         s_post[tid] = 0u;
         s_nl[tid] = c->n_labelled[tid];
     }
-    if (tid == kWave) {
-        s_G = c->n_gen;
-        s_D = c->n_del;
-        s_R = c->n_rel;
+    if (tid >= kWave && tid < kWave + kSeg) {
+        const int g = tid - kWave;
+        s_off[0][g] = c->seg[g].n_gen;
+        s_off[1][g] = c->seg[g].n_del;
+        s_off[2][g] = c->seg[g].n_rel;
+    }
+    if (tid == 2 * kWave) {
         s_next = c->next_id;
         s_N = *a.p.n_dev;
         s_flags[0] = c->scan_fault;
         s_flags[1] = a.local ? c->nonfinite_seen : c->nonfinite_full;
-        if (!a.local) c->nonfinite_full = 0u;
+    }
+    unsigned pv[(kCountReplicas * 2 * SPH_MAX_BUFFERS + 1023) / 1024];
+#pragma unroll
+    for (int q = 0; q < (int)(sizeof(pv) / sizeof(pv[0])); ++q) {
+        const int w = q * (int)bd + tid;
+        pv[q] = w < words ? a.e.part[w] : 0u;
+    }
+    for (unsigned t = tid; t < kMaxEv; t += bd) s_map[t] = 0u;
+    for (unsigned w = tid; w < kMaxEv / 32; w += bd) s_bits[w] = 0u;
+    for (unsigned t = tid; t < kSortBuckets; t += bd) s_hist[t] = 0u;
+    if (tid < 2) {
+        s_mm[tid][0] = 0xffffffffu;
+        s_mm[tid][1] = 0u;
+        s_fat[tid] = 0u;
     }
     __syncthreads();
-    {   // the counter copies: 64 x 15 x 2 words, one per thread; zero them for the next update
-        const int words = kCountReplicas * 2 * SPH_MAX_BUFFERS;
-        for (int w0 = 0; w0 < words; w0 += blockDim.x) {  // uniform trip count: waves stay converged
-            const int w = w0 + tid;
-            unsigned v = 0u;
-            if (w < words) {
-                v = a.e.part[w];
-                if (v) a.e.part[w] = 0u;
-            }
-            const int slot = w % (2 * SPH_MAX_BUFFERS);
-            if (v) atomicAdd(slot & 1 ? &s_post[slot >> 1] : &s_found[slot >> 1], v);
+#pragma unroll
+    for (int q = 0; q < (int)(sizeof(pv) / sizeof(pv[0])); ++q) {
+        const int w = q * (int)bd + tid;
+        const int slot = w % (2 * SPH_MAX_BUFFERS);
+        if (pv[q]) atomicAdd(slot & 1 ? &s_post[slot >> 1] : &s_found[slot >> 1], pv[q]);
+    }
+    __syncthreads();
+    unsigned ticket = 0u;
+    if (tid < kWave) {  // segment offsets (lane l * kSeg + g: segment g of list l), totals, status
+        const int l = tid / kSeg, g = tid % kSeg;
+        const unsigned v = tid < 3 * kSeg ? s_off[l][g] : 0u;
+        unsigned incl = v;
+        for (int off = 1; off < kSeg; off <<= 1) {
+            const unsigned t = __shfl_up(incl, off, kSeg);
+            if (g >= off) incl += t;
+        }
+        if (tid < 3 * kSeg) {
+            s_off[l][g] = incl - v;
+            if (g == kSeg - 1) s_off[l][kSeg] = incl;
+        }
+        const unsigned tot0 = __shfl(incl, kSeg - 1), tot1 = __shfl(incl, 2 * kSeg - 1),
+                       tot2 = __shfl(incl, 3 * kSeg - 1);
+        if (tid == 0) {
+            const long long N_raw = s_N;
+            const long long N = N_raw < 0 ? 0 : (N_raw > a.p.capacity ? a.p.capacity : N_raw);
+            int st = SPH_OK;
+            if (N_raw != N) st = SPH_ERR_ARG;
+            else if (a.local && s_flags[0]) st = SPH_ERR_HIP;
+            else if (s_flags[1]) st = SPH_ERR_NONFINITE;
+            for (int k = 0; k < a.nb && st == SPH_OK; ++k)
+                if ((long long)s_found[k] < s_nl[k]) st = SPH_ERR_CFL;
+            if (st == SPH_OK && (tot0 > a.e.cap_ev || tot1 > a.e.cap_ev || tot2 > a.e.cap_rel)) st = SPH_ERR_EVENTS;
+            if (st == SPH_OK && N - (long long)tot1 + (long long)tot0 > a.p.capacity) st = SPH_ERR_CAPACITY;
+            s_status = st;
+            s_N = N;
+            // Every counter this block reads has been read (the values are used
+            // above); the ticket's result is only needed at the end.
+            ticket = __hip_atomic_fetch_add(&c->fin_ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
     __syncthreads();
-    if (tid == 0) {
-        const unsigned G = s_G, D = s_D, R = s_R;
-        const long long N_raw = s_N;
-        const long long N = N_raw < 0 ? 0 : (N_raw > a.p.capacity ? a.p.capacity : N_raw);
-        int st = SPH_OK;
-        if (N_raw != N) st = SPH_ERR_ARG;
-        else if (a.local && s_flags[0]) st = SPH_ERR_HIP;
-        else if (s_flags[1]) st = SPH_ERR_NONFINITE;
-        for (int k = 0; k < a.nb && st == SPH_OK; ++k)
-            if ((long long)s_found[k] < s_nl[k]) st = SPH_ERR_CFL;
-        if (st == SPH_OK && (G > a.e.cap_ev || D > a.e.cap_ev || R > a.e.cap_rel)) st = SPH_ERR_EVENTS;
-        if (st == SPH_OK && N - (long long)D + (long long)G > a.p.capacity) st = SPH_ERR_CAPACITY;
-        s_status = st;
-        s_N = N;
+    const int st = s_status;
+    const unsigned G = s_off[0][kSeg], D = s_off[1][kSeg], R = s_off[2][kSeg];
+    const long long N = s_N;
+    if (st == SPH_OK) {
+        const Parts &p = a.p;
+        const long long Np = N - (long long)D;
+        const int dim = p.dim, nc = p.nc, ds = 3 + nc;
+        const unsigned cap = a.e.cap_ev;
+        // ---- event lists into LDS; tail map and deleted bits; in-place writes below N' ----
+        unsigned g0, g1, r0, r1;
+        share_of(G, fb, nfb, g0, g1);
+        share_of(R, fb, nfb, r0, r1);
+        for (unsigned e = tid; e < G; e += bd) {
+            const int g = seg_of(s_off[0], e);
+            const unsigned ev = (unsigned)g * cap + (e - s_off[0][g]);
+            const bool mine = e >= g0 && e < g1;
+            float rn[3] = {0.0f, 0.0f, 0.0f};
+            if (mine)
+                for (int q = 0; q < dim; ++q) rn[q] = a.e.gen_new[3 * (size_t)ev + q];
+            const uint32_t i = a.e.gen_idx[ev];
+            s_k[0][0][e] = i;
+            s_v[0][e] = ev;
+            if ((long long)i >= Np) atomicOr(&s_map[i - Np], ev + 1u);
+            else if (mine)
+                for (int q = 0; q < dim; ++q) p.pos[q][i] = rn[q];
+        }
+        for (unsigned e = tid; e < D; e += bd) {
+            const int g = seg_of(s_off[1], e);
+            const uint32_t i = a.e.del_idx[(size_t)g * cap + (e - s_off[1][g])];
+            s_k[1][0][e] = i;
+            if ((long long)i >= Np) atomicOr(&s_bits[(i - Np) >> 5], 1u << ((i - Np) & 31));
+        }
+        for (unsigned q = tid; q < R; q += bd) {
+            const int g = seg_of(s_off[2], q);
+            const unsigned long long v = a.e.rel[(size_t)g * a.e.cap_rel + (q - s_off[2][g])];
+            const long long i = (long long)(v >> 32);
+            const uint32_t lab = (uint32_t)(v & 0xffffffffull);
+            if (i >= Np) atomicOr(&s_map[i - Np], (lab + 1u) << kMapRelShift);
+            else if (q >= r0 && q < r1) p.label[i] = (int32_t)lab;
+        }
+        __syncthreads();
+        // ---- sort both lists.  Counting sort into kSortBuckets buckets over each
+        //      list's key range, then the rank inside a bucket by comparing with
+        //      its other keys; if a bucket holds more than kSortBucketMax keys,
+        //      256-key chunk sorts in registers and merge rounds instead. ----
+        constexpr int kPer = kMaxEv / kFinBlock;  // keys of one list per thread at most
+        const unsigned nl[2] = {G, D};
+        if (tid >= kFinBlock - kWave) {  // exclusive prefix of the deleted bits per 32-position word (<= 128 words)
+            const unsigned lane = (unsigned)tid & (kWave - 1), nw = (D + 31) / 32;
+            const unsigned w0 = 2u * lane, w1 = w0 + 1u;
+            const unsigned c0 = w0 < nw ? (unsigned)__popc(s_bits[w0]) : 0u;
+            const unsigned c1 = w1 < nw ? (unsigned)__popc(s_bits[w1]) : 0u;
+            unsigned incl = c0 + c1;
+            for (unsigned off = 1; off < kWave; off <<= 1) {
+                const unsigned t = __shfl_up(incl, off);
+                if (lane >= off) incl += t;
+            }
+            const unsigned excl = incl - c0 - c1;
+            if (w0 < nw) s_wpre[w0] = excl;
+            if (w1 < nw) s_wpre[w1] = excl + c0;
+        }
+        {   // key range of each list
+            uint32_t mn[2] = {0xffffffffu, 0xffffffffu}, mx[2] = {0u, 0u};
+#pragma unroll
+            for (int l = 0; l < 2; ++l)
+#pragma unroll
+                for (int q = 0; q < kPer; ++q) {
+                    const unsigned e = (unsigned)q * kFinBlock + tid;
+                    if (e < nl[l]) {
+                        const uint32_t k = s_k[l][0][e];
+                        mn[l] = min(mn[l], k);
+                        mx[l] = max(mx[l], k);
+                    }
+                }
+#pragma unroll
+            for (int l = 0; l < 2; ++l) {
+                for (int off = 32; off > 0; off >>= 1) {
+                    mn[l] = min(mn[l], (uint32_t)__shfl_xor(mn[l], off));
+                    mx[l] = max(mx[l], (uint32_t)__shfl_xor(mx[l], off));
+                }
+                if ((tid & (kWave - 1)) == 0 && nl[l] > 0) {
+                    atomicMin(&s_mm[l][0], mn[l]);
+                    atomicMax(&s_mm[l][1], mx[l]);
+                }
+            }
+        }
+        __syncthreads();
+        unsigned shift[2];
+#pragma unroll
+        for (int l = 0; l < 2; ++l) {
+            const uint32_t span = nl[l] > 0 ? s_mm[l][1] - s_mm[l][0] : 0u;
+            unsigned sh = 0;
+            while ((span >> sh) >= (uint32_t)kSortBuckets) ++sh;
+            shift[l] = sh;
+        }
+        uint32_t slot[2][kPer];
+#pragma unroll
+        for (int l = 0; l < 2; ++l)
+#pragma unroll
+            for (int q = 0; q < kPer; ++q) {
+                const unsigned e = (unsigned)q * kFinBlock + tid;
+                slot[l][q] = 0u;
+                if (e < nl[l]) {
+                    const uint32_t b = (s_k[l][0][e] - s_mm[l][0]) >> shift[l], sh = (b & 1u) * 16u;
+                    slot[l][q] = (atomicAdd(&s_hist[l * (kSortBuckets / 2) + (b >> 1)], 1u << sh) >> sh) & 0xffffu;
+                }
+            }
+        __syncthreads();
+        {   // exclusive bucket starts; list 0 in the first half of the waves, list 1 in the second
+            constexpr int kWords = kSortBuckets / kFinBlock;  // words of 16-bit counters per thread
+            const int lane = tid & (kWave - 1), wave = tid / kWave, half = kFinBlock / kWave / 2;
+            uint32_t v[kWords], sum = 0, fat = 0;
+#pragma unroll
+            for (int q = 0; q < kWords; ++q) {
+                v[q] = s_hist[kWords * tid + q];
+                const uint32_t lo = v[q] & 0xffffu, hi = v[q] >> 16;
+                sum += lo + hi;
+                fat = max(fat, max(lo, hi));
+            }
+            uint32_t incl = sum;
+            for (int off = 1; off < kWave; off <<= 1) {
+                const uint32_t t = __shfl_up(incl, off);
+                if (lane >= off) incl += t;
+            }
+            for (int off = 32; off > 0; off >>= 1) fat = max(fat, (uint32_t)__shfl_xor(fat, off));
+            if (lane == kWave - 1) s_wsum[wave] = incl;
+            if (lane == 0) atomicMax(&s_fat[wave / half], fat);
+            __syncthreads();
+            uint32_t run = incl - sum;
+            for (int w = (wave / half) * half; w < wave; ++w) run += s_wsum[w];
+#pragma unroll
+            for (int q = 0; q < kWords; ++q) {
+                const uint32_t lo = run;
+                run += v[q] & 0xffffu;
+                s_hist[kWords * tid + q] = lo | (run << 16);
+                run += v[q] >> 16;
+            }
+        }
+        __syncthreads();
+        const bool fast = s_fat[0] <= (unsigned)kSortBucketMax && s_fat[1] <= (unsigned)kSortBucketMax;
+        unsigned cur = 0;
+        if (fast) {
+#pragma unroll
+            for (int l = 0; l < 2; ++l)  // keys (and source entries) grouped by bucket
+#pragma unroll
+                for (int q = 0; q < kPer; ++q) {
+                    const unsigned e = (unsigned)q * kFinBlock + tid;
+                    if (e < nl[l]) {
+                        const uint32_t k = s_k[l][0][e];
+                        const uint32_t b = (k - s_mm[l][0]) >> shift[l];
+                        const uint32_t pos =
+                            ((s_hist[l * (kSortBuckets / 2) + (b >> 1)] >> ((b & 1u) * 16u)) & 0xffffu) + slot[l][q];
+                        s_k[l][1][pos] = k;
+                        if (l == 0) s_v[1][pos] = s_v[0][e];
+                    }
+                }
+            __syncthreads();
+#pragma unroll
+            for (int l = 0; l < 2; ++l)  // rank inside the bucket
+#pragma unroll
+                for (int q = 0; q < kPer; ++q) {
+                    const unsigned t = (unsigned)q * kFinBlock + tid;
+                    if (t < nl[l]) {
+                        const uint32_t k = s_k[l][1][t];
+                        const uint32_t b = (k - s_mm[l][0]) >> shift[l];
+                        const uint32_t *hs = s_hist + l * (kSortBuckets / 2);
+                        const uint32_t b0 = (hs[b >> 1] >> ((b & 1u) * 16u)) & 0xffffu;
+                        const uint32_t b1 =
+                            b + 1 < (uint32_t)kSortBuckets ? (hs[(b + 1) >> 1] >> (((b + 1) & 1u) * 16u)) & 0xffffu : nl[l];
+                        uint32_t rank = b0;
+                        for (uint32_t j = b0; j < b1; ++j) rank += s_k[l][1][j] < k ? 1u : 0u;
+                        s_k[l][0][rank] = k;
+                        if (l == 0) s_v[0][rank] = s_v[1][t];
+                    }
+                }
+            __syncthreads();
+        } else {
+            // ---- sort: 256-key chunks in registers, then merge rounds (runs of w -> 2w) ----
+            const unsigned PA = (G + kChunk - 1) / kChunk * kChunk, PB = (D + kChunk - 1) / kChunk * kChunk;
+            {
+                const unsigned wave = (unsigned)tid / kWave, lane = (unsigned)tid & (kWave - 1), nwave = bd / kWave;
+                const unsigned ncha = PA / kChunk, nch = ncha + PB / kChunk;
+                for (unsigned ch = wave; ch < nch; ch += nwave) {  // wave-uniform
+                    const bool is_a = ch < ncha;
+                    const unsigned base = (is_a ? ch : ch - ncha) * kChunk, n = is_a ? G : D;
+                    uint32_t *kk = s_k[is_a ? 0 : 1][0];
+                    uint32_t key[4], val[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const unsigned e = base + (unsigned)r * kWave + lane;
+                        key[r] = e < n ? kk[e] : 0xffffffffu;
+                        val[r] = is_a && e < n ? s_v[0][e] : 0u;
+                    }
+                    bitonic_sort256<2>(key, val, (int)lane);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const unsigned e = base + (unsigned)r * kWave + lane;
+                        kk[e] = key[r];
+                        if (is_a) s_v[0][e] = val[r];
+                    }
+                }
+            }
+            __syncthreads();
+            const unsigned PM = PA > PB ? PA : PB, tot = PA + PB;
+            for (unsigned w = kChunk; w < PM; w <<= 1) {
+                // two elements per thread (t and t + bd); each wave's 64 lie in one run of one list
+                for (unsigned t = tid; t < tot; t += 2 * bd) {
+                    unsigned e[2], len[2], rr[2], cnt[2];
+                    uint32_t key[2];
+                    bool isa[2], oe[2];
+                    const uint32_t *base[2];
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const unsigned tt = t + (unsigned)h * bd;
+                        const bool ok = tt < tot;
+                        isa[h] = tt < PA;
+                        e[h] = isa[h] ? tt : tt - PA;
+                        const unsigned P = isa[h] ? PA : PB;
+                        const uint32_t *src = s_k[isa[h] ? 0 : 1][cur];
+                        key[h] = ok ? src[e[h]] : 0u;
+                        rr[h] = e[h] / w;
+                        const unsigned sr = rr[h] ^ 1u;
+                        len[h] = ok && sr * w < P ? min(w, P - sr * w) : 0u;
+                        base[h] = src + (size_t)sr * w;
+                        oe[h] = (rr[h] & 1u) != 0u;
+                    }
+                    run_rank2(base[0], len[0], key[0], oe[0], base[1], len[1], key[1], oe[1], w, cnt[0], cnt[1]);
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        if (t + (unsigned)h * bd >= tot) continue;
+                        const unsigned dst = (rr[h] & ~1u) * w + (e[h] - rr[h] * w) + cnt[h];
+                        s_k[isa[h] ? 0 : 1][cur ^ 1u][dst] = key[h];
+                        if (isa[h]) s_v[cur ^ 1u][dst] = s_v[cur][e[h]];
+                    }
+                }
+                cur ^= 1u;
+                __syncthreads();
+            }
+        }
+        const uint32_t *gsrc = s_k[0][cur], *gslot = s_v[cur], *del = s_k[1][cur];
+        if (fb == 0) {
+            for (unsigned j = tid; j < G; j += bd) a.gen_sorted[j] = gsrc[j];
+            for (unsigned j = tid; j < D; j += bd) a.del_sorted[j] = del[j];
+        }
+        // ---- tail positions: move the survivor at p into its hole, then append at p ----
+        unsigned t0, t1;
+        share_of(G > D ? G : D, fb, nfb, t0, t1);
+        for (unsigned t = t0 + tid; t < t1; t += bd) {
+            const long long pi = Np + t;
+            const bool survivor = t < D && !((s_bits[t >> 5] >> (t & 31)) & 1u);
+            const bool append = t < G;
+            float v[3 + SPH_MAX_CARRIED], d[3 + SPH_MAX_CARRIED];
+            int32_t lab = 0;
+            int64_t id = 0;
+            long long hole = 0;
+            if (survivor) {  // issue every load before any store
+                const unsigned below = s_wpre[t >> 5] + (unsigned)__popc(s_bits[t >> 5] & ((1u << (t & 31)) - 1u));
+                hole = del[t - below];  // the k-th survivor of the tail fills the k-th smallest hole
+                const uint32_t m = s_map[t];
+                const uint32_t ge = m & ((1u << kMapRelShift) - 1u), rl = m >> kMapRelShift;
+#pragma unroll
+                for (int q = 0; q < 3; ++q)
+                    if (q < dim) v[q] = ge ? a.e.gen_new[3 * (size_t)(ge - 1u) + q] : p.pos[q][pi];
+#pragma unroll
+                for (int f = 0; f < SPH_MAX_CARRIED; ++f)
+                    if (f < nc) v[3 + f] = p.car[f][pi];
+                lab = rl ? (int32_t)(rl - 1u) : p.label[pi];
+                id = p.id[pi];
+            }
+            if (append) {
+                const float *src = a.e.dup + (size_t)gslot[t] * (size_t)ds;
+#pragma unroll
+                for (int q = 0; q < 3 + SPH_MAX_CARRIED; ++q)
+                    if (q < dim || (q >= 3 && q < 3 + nc)) d[q] = src[q];
+            }
+            if (survivor) {
+#pragma unroll
+                for (int q = 0; q < 3; ++q)
+                    if (q < dim) p.pos[q][hole] = v[q];
+#pragma unroll
+                for (int f = 0; f < SPH_MAX_CARRIED; ++f)
+                    if (f < nc) p.car[f][hole] = v[3 + f];
+                p.label[hole] = lab;
+                p.id[hole] = id;
+            }
+            if (append) {  // duplicate of the t-th smallest source: label 0, fresh id
+#pragma unroll
+                for (int q = 0; q < 3; ++q)
+                    if (q < dim) p.pos[q][pi] = d[q];
+#pragma unroll
+                for (int f = 0; f < SPH_MAX_CARRIED; ++f)
+                    if (f < nc) p.car[f][pi] = d[3 + f];
+                p.label[pi] = 0;
+                p.id[pi] = s_next + (long long)t;
+            }
+        }
     }
+    // ---- the last block to take a ticket publishes the result and clears the counters ----
+    if (tid == 0) s_last = ticket == (unsigned)nfb - 1u ? 1u : 0u;
     __syncthreads();
-    {
-        const int st = s_status;
-        const unsigned G = s_G, D = s_D;
-        const long long N = s_N;
+    if (s_last) {
         sph_result *r = a.result;
         if (tid < SPH_MAX_BUFFERS) {
             const long long nl = st == SPH_OK && tid < a.nb ? (long long)s_post[tid] : s_nl[tid];
             r->n_labelled[tid] = nl;
             c->n_labelled[tid] = nl;
         }
-        if (tid == kWave) {
+        if (tid >= kWave && tid < kWave + kSeg) {
+            SegCtr &sc = c->seg[tid - kWave];
+            sc.n_gen = 0u;
+            sc.n_del = 0u;
+            sc.n_rel = 0u;
+        }
+        if (tid == 2 * kWave) {
             r->status = st;
             r->n_buffers = a.nb;
             r->n_generated = st == SPH_OK ? G : 0;
@@ -1129,75 +1529,18 @@ __device__ __forceinline__ void finalize_body(const FinArgs &a) {
             r->n_before = N;
             r->n_after = st == SPH_OK ? N - (long long)D + (long long)G : N;
             r->next_id = st == SPH_OK ? s_next + G : s_next;
-            c->n_gen = c->n_del = c->n_rel = 0u;
+            if (!a.local) c->nonfinite_full = 0u;
+            c->fin_ticket = 0u;
             if (st == SPH_OK) {
                 c->next_id = s_next + G;
                 *a.p.n_dev = N - (long long)D + (long long)G;
             }
         }
-    }
-    if (s_status != SPH_OK) return;  // block-uniform
-    const Parts &p = a.p;
-    const unsigned G = s_G, D = s_D, R = s_R;
-    const long long N = s_N, Np = N - (long long)D;
-    const int dim = p.dim, nc = p.nc;
-
-    // ---- order: sources ascending (with their duplicate slots), deleted ascending ----
-    block_sort_pair(a.e.gen_idx, G, a.e.del_idx, D, s_ck, s_cv, s_cd, a.gen_sorted, s_gslot, s_del);
-    for (unsigned j = tid; j < D; j += blockDim.x) a.del_sorted[j] = s_del[j];
-    const unsigned nw = (D + 31) / 32;
-    for (unsigned w = tid; w < nw; w += blockDim.x) s_bits[w] = 0u;
-
-    // ---- recycle and relabel: plain stores of values prepared by the classify step ----
-    for (unsigned s = tid; s < G; s += blockDim.x) {
-        const int64_t i = a.e.gen_idx[s];
-        for (int q = 0; q < dim; ++q) p.pos[q][i] = a.e.gen_new[3 * (size_t)s + q];
-    }
-    for (unsigned r = tid; r < R; r += blockDim.x) {
-        const unsigned long long e = a.e.rel[r];
-        p.label[(int64_t)(e >> 32)] = (int32_t)(unsigned)(e & 0xffffffffull);
-    }
-    __syncthreads();
-
-    // ---- movers: surviving particles of the tail [Np, N), ascending ----
-    for (unsigned j = tid; j < D; j += blockDim.x) {
-        const long long idx = s_del[j];
-        if (idx >= Np) atomicOr(&s_bits[(idx - Np) >> 5], 1u << ((idx - Np) & 31));
-    }
-    __syncthreads();
-    if (tid == 0) {
-        unsigned acc = 0, td = 0;
-        for (unsigned w = 0; w < nw; ++w) {
-            const unsigned pc = (unsigned)__popc(s_bits[w]);
-            s_wpre[w] = acc;
-            acc += 32u - pc;
-            td += pc;
-        }
-        s_taildel = td;
-    }
-    __syncthreads();
-    for (unsigned q = tid; q < D; q += blockDim.x) {
-        const unsigned w = q >> 5, bit = q & 31;
-        if (!(s_bits[w] >> bit & 1u))
-            s_ck[s_wpre[w] + bit - (unsigned)__popc(s_bits[w] & ((1u << bit) - 1u))] = (uint32_t)(Np + q);
-    }
-    __syncthreads();
-    const unsigned h = D - s_taildel;
-    for (unsigned j = tid; j < h; j += blockDim.x) copy_particle(p, s_del[j], s_ck[j]);
-    __syncthreads();
-
-    // ---- append the duplicates in ascending source order: label 0, fresh ids ----
-    for (unsigned j = tid; j < G; j += blockDim.x) {
-        const int64_t dst = Np + j;
-        const float *d = a.e.dup + (size_t)s_gslot[j] * kDupStride;
-        for (int q = 0; q < dim; ++q) p.pos[q][dst] = d[q];
-        for (int f = 0; f < nc; ++f) p.car[f][dst] = d[3 + f];
-        p.label[dst] = 0;
-        p.id[dst] = s_next + (long long)j;
+        for (int w = tid; w < words; w += (int)bd) a.e.part[w] = 0u;
     }
 }
 
-__global__ __launch_bounds__(kFinBlock) void k_finalize(FinArgs a) { finalize_body(a); }
+__global__ __launch_bounds__(kFinBlock) void k_finalize(FinArgs a) { finalize_body(a, blockIdx.x, gridDim.x); }
 
 // ------------------------------------------------------------- identify --
 
@@ -1288,7 +1631,9 @@ __global__ __launch_bounds__(kClassifyBlock) void kb_classify(const LocalArgs *a
     classify_body(args[m.d], m.vb, vg[m.d]);
 }
 
-__global__ __launch_bounds__(kFinBlock) void kb_finalize(const FinArgs *args) { finalize_body(args[blockIdx.x]); }
+__global__ __launch_bounds__(kFinBlock) void kb_finalize(const FinArgs *args, int nfb) {
+    finalize_body(args[blockIdx.x / nfb], blockIdx.x % nfb, nfb);
+}
 
 }  // namespace
 
@@ -1508,7 +1853,7 @@ sph_status launch_finalize(sph_ctx *ctx, const Parts &pp, bool local, int n_part
     const FinArgs f = fin_args(ctx, pp, local);
     {
         ProfScope ps(ctx, SPH_PHASE_FINALIZE);
-        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinBlock), 0, ctx->stream, f);
+        hipLaunchKernelGGL(k_finalize, dim3(kFinBlocksMax), dim3(kFinBlock), 0, ctx->stream, f);
     }
     HIP_TRY(hipGetLastError());
     ctx->any_update = true;
@@ -1701,13 +2046,13 @@ extern "C" sph_status sph_create(const sph_config *cfg, sph_ctx **out) {
               hipMalloc(&c->d_cell_idx, sizeof(int32_t) * c->capacity) == hipSuccess &&
               hipMalloc(&c->d_keyrank, sizeof(unsigned long long) * c->capacity) == hipSuccess &&
               hipMalloc(&c->d_tile_state, sizeof(unsigned long long) * c->n_tiles) == hipSuccess &&
-              hipMalloc(&c->d_gen_idx, sizeof(uint32_t) * ev) == hipSuccess &&
-              hipMalloc(&c->d_del_idx, sizeof(uint32_t) * ev) == hipSuccess &&
+              hipMalloc(&c->d_gen_idx, sizeof(uint32_t) * ev * kSeg) == hipSuccess &&
+              hipMalloc(&c->d_del_idx, sizeof(uint32_t) * ev * kSeg) == hipSuccess &&
               hipMalloc(&c->d_gen_sorted, sizeof(uint32_t) * ev) == hipSuccess &&
               hipMalloc(&c->d_del_sorted, sizeof(uint32_t) * ev) == hipSuccess &&
-              hipMalloc(&c->d_gen_new, sizeof(float) * ev * 3) == hipSuccess &&
-              hipMalloc(&c->d_rel, sizeof(unsigned long long) * ev * kRelPerEvent) == hipSuccess &&
-              hipMalloc(&c->d_dup, sizeof(float) * ev * kDupStride) == hipSuccess &&
+              hipMalloc(&c->d_gen_new, sizeof(float) * ev * kSeg * 3) == hipSuccess &&
+              hipMalloc(&c->d_rel, sizeof(unsigned long long) * ev * kSeg * kRelPerEvent) == hipSuccess &&
+              hipMalloc(&c->d_dup, sizeof(float) * ev * kSeg * (3 + SPH_MAX_CARRIED)) == hipSuccess &&
               hipMalloc(&c->d_ctl, sizeof(Ctl)) == hipSuccess &&
               (blog2 == 0 || hipMalloc(&c->d_brick_slot, sizeof(int32_t) * c->n_bricks) == hipSuccess) &&
               hipMalloc(&c->d_part, sizeof(unsigned) * 2 * SPH_MAX_BUFFERS * kMaxPartBlocks) == hipSuccess &&
@@ -2166,6 +2511,7 @@ struct sph_batch {
     bool own_stream = false;
     int mode = SPH_BATCH_GRAPH;
     int count_ppb = 2048;  // particles per block of the count / scatter phases
+    int fin_blocks = 1;    // finalize workgroups per domain
     CountArgs *d_ca = nullptr;
     ScanArgs *d_sa = nullptr;
     ScatterArgs *d_xa = nullptr;
@@ -2239,7 +2585,7 @@ sph_status batch_enqueue(sph_batch *b) {
     if (b->nb_cls > 0)
         hipLaunchKernelGGL(kb_classify, dim3(b->nb_cls), dim3(kClassifyBlock), 0, b->stream, b->d_la, b->d_map_cls,
                            b->d_vg_cls);
-    hipLaunchKernelGGL(kb_finalize, dim3(nd), dim3(kFinBlock), 0, b->stream, b->d_fa);
+    hipLaunchKernelGGL(kb_finalize, dim3(nd * b->fin_blocks), dim3(kFinBlock), 0, b->stream, b->d_fa, b->fin_blocks);
     HIP_TRY(hipGetLastError());
     return SPH_OK;
 }
@@ -2301,6 +2647,8 @@ extern "C" sph_status sph_batch_create(sph_ctx *const *domains, const sph_partic
         la.push_back(local_args(c, pp));
         fa.push_back(fin_args(c, pp, true));
     }
+    // one round of finalize workgroups over the CUs: fewer per domain in large batches
+    b->fin_blocks = std::max(1, std::min(kFinBlocksMax, 256 / n_domains));
     sph_status st = SPH_OK;
     if ((st = upload_table(b->d_ca, ca, b->stream)) != SPH_OK || (st = upload_table(b->d_sa, sa, b->stream)) != SPH_OK ||
         (st = upload_table(b->d_xa, xa, b->stream)) != SPH_OK || (st = upload_table(b->d_la, la, b->stream)) != SPH_OK ||

@@ -284,6 +284,40 @@ def test_every_particle_deleted():
     d.close()
 
 
+@pytest.mark.parametrize("mode", ["local", "fullscan"])
+@pytest.mark.parametrize("n", [200_000, 700_000])
+def test_clustered_event_indices(n, mode):
+    """Generated sources and deleted particles in long runs of consecutive
+    indices plus one far away: with 700k particles a run fills a bucket of the
+    finalize's counting sort past its limit (the comparison sort takes over),
+    with 200k it does not.  Events and arrays must still equal the oracle's."""
+    rng = np.random.default_rng(7)
+    pts = np.column_stack([rng.uniform(1.5, 3.5, n), rng.uniform(0.0, 1.0, n)])
+    labels = np.zeros(n, np.int32)
+    gen = np.r_[np.arange(0, 300), n - 1]
+    dele = np.r_[np.arange(1000, 1300), n - 2]
+    pts[gen, 0] = rng.uniform(1.01, 1.2, gen.size)     # labelled inlet particles past X' = a/2
+    labels[gen] = 1
+    pts[dele, 0] = rng.uniform(5.01, 5.2, dele.size)   # past the outlet's X' = a/2
+    wl, bufs, st = _two_buffer_case(pts, labels, capacity=n + 400)
+    d = make_domain(wl, bufs, st)
+    _identify_counts(d, bufs, st)
+    if mode == "local":
+        d.build()
+        gst, g, dl = d.update()
+    else:
+        gst, g, dl = d.update_fullscan()
+    res = oracle.update(bufs, st)
+    assert gst == res.status == 0
+    np.testing.assert_array_equal(res.gen, gen)
+    np.testing.assert_array_equal(res.dele, dele)
+    eg, gg, dd = d.events()
+    np.testing.assert_array_equal(gg, res.gen)
+    np.testing.assert_array_equal(dd, res.dele)
+    assert_same_state(d, st, "clustered")
+    d.close()
+
+
 # ---------------------------------------------------------------- guard band ---
 
 @pytest.mark.parametrize("dim", [2, 3])
