@@ -36,8 +36,8 @@ namespace {
 
 constexpr int kWave = 64;
 constexpr int kBuildBlock = 256;
-constexpr int kScanBlock = 256;
-constexpr int kScanItems = 16;
+constexpr int kScanBlock = 1024;
+constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanBlock * kScanItems;
 constexpr int kClassifyBlock = 256;
 constexpr int kFinBlock = 1024;
@@ -342,6 +342,18 @@ __device__ __forceinline__ void emit(const EventArgs &e, const Parts &p, const B
 }
 
 // --------------------------------------------------------------- K0 build --
+//
+// Counting sort of the particle indices by cell in three launches:
+//   count  : cell key of every particle and its rank among the particles of its
+//            cell (one returning atomic per run of equal keys in consecutive
+//            lanes), stored packed in 32 bits: key << rbits | rank, where rbits
+//            is what the largest key leaves free.  A rank that does not fit
+//            (rank >= 2^rbits - 1, a very crowded cell) stores the all-ones
+//            marker and spills the full (key, rank) to a 64-bit buffer;
+//   scan   : exclusive prefix of the counts -> cell_start, counts zeroed;
+//   scatter: cell_idx[cell_start[key] + rank] = i.
+// The order inside a cell is whatever the atomics make it; nothing downstream
+// depends on it.
 
 // Cell keys and per-cell ranks of J particles per thread at once: all position
 // loads are issued first, then the wave-level run detection, then all atomics,
@@ -392,7 +404,7 @@ __device__ __forceinline__ void key_rank_batch(const Grid &g, const float *__res
     for (int j = 0; j < J; ++j) rank[j] = __shfl(old[j], my_head[j]) + (lane - my_head[j]);
 }
 
-constexpr int kCountBatch = 4;
+constexpr int kCountBatch = 2;
 
 struct CountArgs {
     const float *x, *y, *z;
@@ -400,7 +412,9 @@ struct CountArgs {
     int64_t capacity;
     Grid g;
     int32_t *count;
-    unsigned long long *keyrank;
+    uint32_t *packed;               // key << rbits | rank, or all ones
+    unsigned long long *spill;      // (key << 32 | rank) of the particles marked all ones
+    int32_t rbits;
     unsigned long long *tile_state;
     int64_t n_tiles;
     Ctl *ctl;
@@ -422,14 +436,25 @@ __device__ __forceinline__ void count_body(const CountArgs &a, const int lb, con
     const int64_t s1 = min(N, s0 + per);
     bool bad = false;
     const int64_t B = blockDim.x;
-    for (int64_t base = s0; base < s1; base += B * kCountBatch) {
+    const uint32_t rmask = (1u << a.rbits) - 1u;
+    // the kCountBatch rows of one step lie in different parts of the segment, so a
+    // wave's atomics of one step rarely meet on one cell (same-address atomics
+    // queue at the memory side)
+    const int64_t sub = ((s1 - s0 + kCountBatch - 1) / kCountBatch + B - 1) / B * B;
+    for (int64_t base = s0; base < s0 + sub; base += B) {
         uint32_t key[kCountBatch];
         int32_t rank[kCountBatch];
-        key_rank_batch<kCountBatch>(a.g, a.x, a.y, a.z, a.count, base + threadIdx.x, B, s1, lane, key, rank, bad);
+        key_rank_batch<kCountBatch>(a.g, a.x, a.y, a.z, a.count, base + threadIdx.x, sub, s1, lane, key, rank, bad);
 #pragma unroll
         for (int j = 0; j < kCountBatch; ++j) {
-            const int64_t i = base + threadIdx.x + j * B;
-            if (i < s1) a.keyrank[i] = ((unsigned long long)key[j] << 32) | (unsigned)rank[j];
+            const int64_t i = base + threadIdx.x + j * sub;
+            if (i >= s1) continue;
+            if ((uint32_t)rank[j] < rmask) {
+                a.packed[i] = (key[j] << a.rbits) | (uint32_t)rank[j];
+            } else {
+                a.packed[i] = 0xffffffffu;
+                a.spill[i] = ((unsigned long long)key[j] << 32) | (unsigned)rank[j];
+            }
         }
     }
     if (__ballot(bad) != 0ull && lane == 0) atomicOr(&a.ctl->nonfinite_build, 1u);
@@ -456,10 +481,15 @@ struct ScanArgs {
     Ctl *ctl;
 };
 
+// One tile of kScanTile counts per block: coalesced loads through LDS into
+// per-thread runs of kScanItems, wave and block scans, a decoupled look-back
+// over the preceding tiles (tile order from an atomic ticket, so a tile only
+// ever waits on tiles that started before it), and coalesced stores.
 __device__ __forceinline__ void scan_body(const ScanArgs &a) {
     __shared__ unsigned s_tile;
     __shared__ int s_wave[kScanBlock / kWave];
     __shared__ int s_excl;
+    __shared__ int s_buf[kScanTile + kScanTile / 32];  // padded: index j at j + j / 32
     if (threadIdx.x == 0) {
         s_tile = atomicAdd(&a.ctl->tile_counter, 1u);
         if (s_tile == 0u) {  // the count phase is complete: keep its verdict for the next update
@@ -470,19 +500,26 @@ __device__ __forceinline__ void scan_body(const ScanArgs &a) {
     __syncthreads();
     const unsigned tile = s_tile;
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    const int64_t base = (int64_t)tile * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    const int64_t t0 = (int64_t)tile * kScanTile;
+#pragma unroll
+    for (int q = 0; q < kScanItems; ++q) {
+        const int j = q * kScanBlock + (int)threadIdx.x;
+        const int64_t gj = t0 + j;
+        int v = 0;
+        if (gj < a.m) {
+            v = a.count[gj];
+            a.count[gj] = 0;
+        }
+        s_buf[j + j / 32] = v;
+    }
+    __syncthreads();
     int v[kScanItems];
     int sum = 0;
 #pragma unroll
     for (int q = 0; q < kScanItems; ++q) {
-        const int64_t j = base + q;
-        v[q] = j < a.m ? a.count[j] : 0;
+        const int j = (int)threadIdx.x * kScanItems + q;
+        v[q] = s_buf[j + j / 32];
         sum += v[q];
-    }
-#pragma unroll
-    for (int q = 0; q < kScanItems; ++q) {
-        const int64_t j = base + q;
-        if (j < a.m) a.count[j] = 0;
     }
     // inclusive wave scan of per-thread sums
     int incl = sum;
@@ -530,9 +567,16 @@ __device__ __forceinline__ void scan_body(const ScanArgs &a) {
     int run = s_excl + wave_off + incl - sum;
 #pragma unroll
     for (int q = 0; q < kScanItems; ++q) {
-        const int64_t j = base + q;
-        if (j < a.m) a.cell_start[j] = run;
+        const int j = (int)threadIdx.x * kScanItems + q;
+        s_buf[j + j / 32] = run;
         run += v[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kScanItems; ++q) {
+        const int j = q * kScanBlock + (int)threadIdx.x;
+        const int64_t gj = t0 + j;
+        if (gj < a.m) a.cell_start[gj] = s_buf[j + j / 32];
     }
 }
 
@@ -542,10 +586,14 @@ struct ScatterArgs {
     const int64_t *n_dev;
     int64_t capacity;
     const Ctl *ctl;
-    const unsigned long long *keyrank;
+    const uint32_t *packed;
+    const unsigned long long *spill;
+    int32_t rbits;
     const int32_t *cell_start;
     int32_t *cell_idx;
 };
+
+constexpr int kScatterBatch = 4;
 
 __device__ __forceinline__ void scatter_body(const ScatterArgs &a, const int lb, const int G) {
     if (a.ctl->scan_fault) return;
@@ -553,10 +601,32 @@ __device__ __forceinline__ void scatter_body(const ScatterArgs &a, const int lb,
     const int64_t per = ((N + G - 1) / G + blockDim.x - 1) / blockDim.x * blockDim.x;
     const int64_t s0 = (int64_t)lb * per;
     const int64_t s1 = min(N, s0 + per);
-    for (int64_t i = s0 + threadIdx.x; i < s1; i += blockDim.x) {
-        const unsigned long long kr = a.keyrank[i];
-        const uint32_t key = (uint32_t)(kr >> 32);
-        a.cell_idx[a.cell_start[key] + (int)(unsigned)(kr & 0xffffffffull)] = (int32_t)i;
+    const uint32_t rmask = (1u << a.rbits) - 1u;
+    const int64_t B = blockDim.x;
+    for (int64_t base = s0 + threadIdx.x; base < s1; base += B * kScatterBatch) {
+        uint32_t v[kScatterBatch];  // every load of the batch first
+#pragma unroll
+        for (int j = 0; j < kScatterBatch; ++j) {
+            const int64_t i = base + j * B;
+            v[j] = i < s1 ? a.packed[i] : 0u;
+        }
+        uint32_t key[kScatterBatch], rank[kScatterBatch];
+#pragma unroll
+        for (int j = 0; j < kScatterBatch; ++j) {
+            key[j] = v[j] >> a.rbits;
+            rank[j] = v[j] & rmask;
+            if (v[j] == 0xffffffffu) {
+                const unsigned long long kr = a.spill[base + j * B];
+                key[j] = (uint32_t)(kr >> 32);
+                rank[j] = (uint32_t)(kr & 0xffffffffull);
+            }
+        }
+        int32_t start[kScatterBatch];
+#pragma unroll
+        for (int j = 0; j < kScatterBatch; ++j) start[j] = base + j * B < s1 ? a.cell_start[key[j]] : 0;
+#pragma unroll
+        for (int j = 0; j < kScatterBatch; ++j)
+            if (base + j * B < s1) a.cell_idx[start[j] + (int32_t)rank[j]] = (int32_t)(base + j * B);
     }
 }
 
@@ -570,7 +640,7 @@ __global__ __launch_bounds__(kBuildBlock) void k_scatter(ScatterArgs a) { scatte
 // thread the cell key stays in LDS and the rank in registers from the count phase
 // to the scatter phase, so the only per-particle HBM traffic is the position read
 // and the cell_idx write.  Particles beyond those slots (very large N) go through
-// the keyrank buffer as in the three-kernel build.
+// a 64-bit (key, rank) spill buffer.
 
 constexpr int kFusedBlock = 1024;
 constexpr int kFusedSlots = 32;
@@ -888,6 +958,8 @@ __global__ __launch_bounds__(kClassifyBlock) void k_classify_local(LocalArgs a) 
     classify_body(a, blockIdx.x, gridDim.x);
 }
 
+constexpr int kFullVec = 4;  // particles per thread per step of the full scan (a multiple of 4)
+
 struct FullArgs {
     Parts p;
     const BufDev *bufs;
@@ -908,7 +980,7 @@ __global__ __launch_bounds__(kClassifyBlock) void k_classify_full(FullArgs a) {
     const int dim = a.p.dim;
     const int lb = logical_block();
     const int seg = (lb * (int)(blockDim.x / kWave) + (int)(threadIdx.x / kWave)) % kSeg;
-    constexpr int kVec = 4;  // particles per thread per step: one 16-byte load per coordinate
+    constexpr int kVec = kFullVec;  // particles per thread per step: 16-byte loads per coordinate
     const int64_t quant = (int64_t)blockDim.x * kVec;
     const int64_t per = ((N + gridDim.x - 1) / gridDim.x + quant - 1) / quant * quant;
     const int64_t s0 = (int64_t)lb * per;
@@ -918,15 +990,18 @@ __global__ __launch_bounds__(kClassifyBlock) void k_classify_full(FullArgs a) {
         const int64_t i0 = base + (int64_t)kVec * threadIdx.x;
         float px[kVec], py[kVec], pz[kVec];
         if (a.vec && i0 + kVec <= s1) {
-            const float4 vx = *reinterpret_cast<const float4 *>(a.p.pos[0] + i0);
-            const float4 vy = *reinterpret_cast<const float4 *>(a.p.pos[1] + i0);
-            px[0] = vx.x; px[1] = vx.y; px[2] = vx.z; px[3] = vx.w;
-            py[0] = vy.x; py[1] = vy.y; py[2] = vy.z; py[3] = vy.w;
-            if (dim == 3) {
-                const float4 vz = *reinterpret_cast<const float4 *>(a.p.pos[2] + i0);
-                pz[0] = vz.x; pz[1] = vz.y; pz[2] = vz.z; pz[3] = vz.w;
-            } else {
-                pz[0] = pz[1] = pz[2] = pz[3] = 0.0f;
+#pragma unroll
+            for (int h = 0; h < kVec; h += 4) {
+                const float4 vx = *reinterpret_cast<const float4 *>(a.p.pos[0] + i0 + h);
+                const float4 vy = *reinterpret_cast<const float4 *>(a.p.pos[1] + i0 + h);
+                px[h] = vx.x; px[h + 1] = vx.y; px[h + 2] = vx.z; px[h + 3] = vx.w;
+                py[h] = vy.x; py[h + 1] = vy.y; py[h + 2] = vy.z; py[h + 3] = vy.w;
+                if (dim == 3) {
+                    const float4 vz = *reinterpret_cast<const float4 *>(a.p.pos[2] + i0 + h);
+                    pz[h] = vz.x; pz[h + 1] = vz.y; pz[h + 2] = vz.z; pz[h + 3] = vz.w;
+                } else {
+                    pz[h] = pz[h + 1] = pz[h + 2] = pz[h + 3] = 0.0f;
+                }
             }
         } else {
 #pragma unroll
@@ -1674,7 +1749,10 @@ struct sph_ctx {
     int n_runs = 0;
 
     int32_t *d_count = nullptr, *d_cell_start = nullptr, *d_cell_idx = nullptr;
-    unsigned long long *d_keyrank = nullptr, *d_tile_state = nullptr;
+    uint32_t *d_keys = nullptr;                  // packed (key, rank) of each particle (three-kernel build)
+    unsigned long long *d_keyrank = nullptr;     // full (key, rank) of the particles that do not fit
+    int32_t rbits = 1;                           // rank bits of the packed form
+    unsigned long long *d_tile_state = nullptr;
     int64_t n_tiles = 0;
 
     uint32_t *d_gen_idx = nullptr, *d_del_idx = nullptr, *d_gen_sorted = nullptr, *d_del_sorted = nullptr;
@@ -1731,6 +1809,13 @@ void prof_drain(sph_ctx *c) {
         }
     }
     c->prof_used = 0;
+}
+
+// Rank bits of the packed (key, rank) form: what the largest cell key leaves of 32.
+int32_t rank_bits(int64_t n_cells) {
+    int kb = 1;
+    while (kb < 31 && ((int64_t)1 << kb) < n_cells) ++kb;
+    return 32 - kb;
 }
 
 bool aligned16(const void *q) { return q == nullptr || (reinterpret_cast<uintptr_t>(q) & 15u) == 0; }
@@ -1793,7 +1878,9 @@ CountArgs count_args(const sph_ctx *ctx, const Parts &pp) {
     ca.capacity = pp.capacity;
     ca.g = grid_of(ctx);
     ca.count = ctx->d_count;
-    ca.keyrank = ctx->d_keyrank;
+    ca.packed = ctx->d_keys;
+    ca.spill = ctx->d_keyrank;
+    ca.rbits = ctx->rbits;
     ca.tile_state = ctx->d_tile_state;
     ca.n_tiles = ctx->n_tiles;
     ca.ctl = ctx->d_ctl;
@@ -1815,7 +1902,9 @@ ScatterArgs scatter_args(const sph_ctx *ctx, const Parts &pp) {
     xa.n_dev = pp.n_dev;
     xa.capacity = pp.capacity;
     xa.ctl = ctx->d_ctl;
-    xa.keyrank = ctx->d_keyrank;
+    xa.packed = ctx->d_keys;
+    xa.spill = ctx->d_keyrank;
+    xa.rbits = ctx->rbits;
     xa.cell_start = ctx->d_cell_start;
     xa.cell_idx = ctx->d_cell_idx;
     return xa;
@@ -1877,6 +1966,7 @@ void free_ctx(sph_ctx *c) {
     (void)hipFree(c->d_cell_start);
     (void)hipFree(c->d_cell_idx);
     (void)hipFree(c->d_keyrank);
+    (void)hipFree(c->d_keys);
     (void)hipFree(c->d_tile_state);
     (void)hipFree(c->d_gen_idx);
     (void)hipFree(c->d_del_idx);
@@ -2021,6 +2111,7 @@ extern "C" sph_status sph_create(const sph_config *cfg, sph_ctx **out) {
     c->cs = cfg->cell_size;
     c->dp = cfg->dp;
     c->n_cells = (int64_t)cells;
+    c->rbits = rank_bits(c->n_cells);
     c->blog2 = blog2;
     c->bmargin = cfg->brick_margin;
     for (int q = 0; q < 3; ++q) c->bdims[q] = bdims[q];
@@ -2042,9 +2133,10 @@ extern "C" sph_status sph_create(const sph_config *cfg, sph_ctx **out) {
     const size_t ev = c->max_events;
     bool ok = hipMalloc(&c->d_bufs, sizeof(BufDev) * SPH_MAX_BUFFERS) == hipSuccess &&
               hipMalloc(&c->d_count, sizeof(int32_t) * m) == hipSuccess &&
-              hipMalloc(&c->d_cell_start, sizeof(int32_t) * m) == hipSuccess &&
+              hipMalloc(&c->d_cell_start, sizeof(int32_t) * (m + 1)) == hipSuccess &&
               hipMalloc(&c->d_cell_idx, sizeof(int32_t) * c->capacity) == hipSuccess &&
               hipMalloc(&c->d_keyrank, sizeof(unsigned long long) * c->capacity) == hipSuccess &&
+              hipMalloc(&c->d_keys, sizeof(uint32_t) * c->capacity) == hipSuccess &&
               hipMalloc(&c->d_tile_state, sizeof(unsigned long long) * c->n_tiles) == hipSuccess &&
               hipMalloc(&c->d_gen_idx, sizeof(uint32_t) * ev * kSeg) == hipSuccess &&
               hipMalloc(&c->d_del_idx, sizeof(uint32_t) * ev * kSeg) == hipSuccess &&
@@ -2064,7 +2156,7 @@ extern "C" sph_status sph_create(const sph_config *cfg, sph_ctx **out) {
         init.next_id = cfg->next_id;
         sph_result r0{};
         ok = hipMemsetAsync(c->d_count, 0, sizeof(int32_t) * m, c->stream) == hipSuccess &&
-             hipMemsetAsync(c->d_cell_start, 0, sizeof(int32_t) * m, c->stream) == hipSuccess &&
+             hipMemsetAsync(c->d_cell_start, 0, sizeof(int32_t) * (m + 1), c->stream) == hipSuccess &&
              hipMemsetAsync(c->d_tile_state, 0, sizeof(unsigned long long) * c->n_tiles, c->stream) == hipSuccess &&
              hipMemsetAsync(c->d_part, 0, sizeof(unsigned) * 2 * SPH_MAX_BUFFERS * kMaxPartBlocks, c->stream) ==
                  hipSuccess &&
@@ -2466,7 +2558,7 @@ extern "C" sph_status sph_grid_fit(sph_ctx *ctx, const sph_particles *p) {
     const int64_t tiles = (m + kScanTile - 1) / kScanTile;
     int32_t *cnt = nullptr, *start = nullptr;
     unsigned long long *ts = nullptr;
-    if (hipMalloc(&cnt, sizeof(int32_t) * m) != hipSuccess || hipMalloc(&start, sizeof(int32_t) * m) != hipSuccess ||
+    if (hipMalloc(&cnt, sizeof(int32_t) * m) != hipSuccess || hipMalloc(&start, sizeof(int32_t) * (m + 1)) != hipSuccess ||
         hipMalloc(&ts, sizeof(unsigned long long) * tiles) != hipSuccess) {
         (void)hipFree(cnt);
         (void)hipFree(start);
@@ -2474,7 +2566,7 @@ extern "C" sph_status sph_grid_fit(sph_ctx *ctx, const sph_particles *p) {
         return SPH_ERR_HIP;
     }
     HIP_TRY(hipMemsetAsync(cnt, 0, sizeof(int32_t) * m, ctx->stream));
-    HIP_TRY(hipMemsetAsync(start, 0, sizeof(int32_t) * m, ctx->stream));
+    HIP_TRY(hipMemsetAsync(start, 0, sizeof(int32_t) * (m + 1), ctx->stream));
     HIP_TRY(hipMemsetAsync(ts, 0, sizeof(unsigned long long) * tiles, ctx->stream));
     HIP_TRY(hipMemcpyAsync(ctx->d_brick_slot, ctx->h_brick_slot.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice,
                            ctx->stream));
@@ -2486,6 +2578,7 @@ extern "C" sph_status sph_grid_fit(sph_ctx *ctx, const sph_particles *p) {
     ctx->d_cell_start = start;
     ctx->d_tile_state = ts;
     ctx->n_cells = cells;
+    ctx->rbits = rank_bits(cells);
     ctx->n_tiles = tiles;
     ctx->built = false;
     // candidate cells of every buffer in the new key space

@@ -126,6 +126,29 @@ def test_celllist_beyond_register_slots(monkeypatch):
     d.close()
 
 
+def test_celllist_crowded_cell_on_a_fine_grid():
+    """33 M cells leave 6 bits for the rank in the packed (key, rank) word, so
+    500 particles in one cell take the full-width spill path of the build."""
+    n_rand, n_crowd = 100_000, 500
+    rng = np.random.default_rng(11)
+    cs_ = 1.0 / 5800.0
+    pts = np.concatenate([rng.uniform(0.0, 1.0, (n_rand, 2)),
+                          (0.5 + 0.5 * cs_) + rng.uniform(-0.2 * cs_, 0.2 * cs_, (n_crowd, 2))])
+    n = len(pts)
+    st = make_state(2, pts, capacity=n + 16)
+    d = make_domain_raw(2, (0, 0, 0), (1.0, 1.0, 0.0), cs_, cs_, [], st)
+    d.build()
+    cs, ci, dims = _cell_list(d, n)
+    assert dims[0] * dims[1] > (1 << 25)
+    ocs, oci = oracle.cell_list(2, np.float32([0, 0]), np.float32(1.0 / cs_), dims[:2], st.pos[0][:n], st.pos[1][:n],
+                                None)
+    np.testing.assert_array_equal(cs, ocs)
+    assert np.diff(ocs).max() >= n_crowd
+    cell_of = np.repeat(np.arange(len(ocs) - 1), np.diff(ocs))
+    np.testing.assert_array_equal(ci[np.lexsort((ci, cell_of))], oci[np.lexsort((oci, cell_of))])
+    d.close()
+
+
 # ----------------------------------------------------------- update parity ---
 
 def test_channel2d_200_steps_local():
