@@ -26,6 +26,8 @@ _LIB = os.path.join(_HERE, "libsphbuf_oracle.so")
 
 OK, ERR_ARG, ERR_CAPACITY, ERR_CFL, ERR_NONFINITE = 0, 1, 4, 5, 6
 INLET, OUTLET, BIDIR = 1, 2, 3
+BC_NONE, BC_VELOCITY, BC_PRESSURE = 0, 1, 2
+PROFILE_PLUG, PROFILE_PARABOLIC_Y, PROFILE_PARABOLIC_R = 0, 1, 2
 MAX_BUFFERS = 15
 MAX_CARRIED = 16
 
@@ -52,6 +54,22 @@ class _CBuffer(ctypes.Structure):
         ("half", ctypes.c_double * 3),
         ("margin", ctypes.c_double),
     ]
+
+
+class _CBc(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int32),
+        ("profile", ctypes.c_int32),
+        ("u", ctypes.c_double),
+        ("radius", ctypes.c_double),
+        ("p_b", ctypes.c_double),
+        ("rho0", ctypes.c_double),
+        ("c0", ctypes.c_double),
+    ]
+
+
+class _CFields(ctypes.Structure):
+    _fields_ = [("vel", ctypes.c_int32 * 3), ("rho", ctypes.c_int32)]
 
 
 class _CState(ctypes.Structure):
@@ -93,6 +111,16 @@ def lib():
                                  ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
                                  ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]
         L.orc_update.restype = ctypes.c_int
+        L.orc_update_bc.argtypes = [ctypes.POINTER(_CBuffer), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                    ctypes.POINTER(_CState), ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
+                                    ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]
+        L.orc_update_bc.restype = ctypes.c_int
+        L.orc_apply_bc.argtypes = [ctypes.POINTER(_CBuffer), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                   ctypes.POINTER(_CState)]
+        L.orc_apply_bc.restype = ctypes.c_int
+        L.orc_rotate_buffer.argtypes = [ctypes.POINTER(_CBuffer), ctypes.c_int, ctypes.c_int, dp, dp,
+                                        ctypes.c_void_p, ctypes.POINTER(_CState)]
+        L.orc_rotate_buffer.restype = ctypes.c_int
         L.orc_cell_list.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_float, ctypes.c_void_p, ctypes.c_int64,
                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_void_p]
@@ -166,6 +194,49 @@ class Buffer:
             b.rot[i] = float(rr[i])
         b.margin = float(self.margin)
         return b
+
+
+@dataclass
+class BC:
+    """Boundary condition of one buffer (Section 4): velocity profile or boundary pressure."""
+    kind: int = BC_NONE
+    profile: int = PROFILE_PLUG
+    u: float = 0.0
+    radius: float = 1.0
+    p_b: float = 0.0
+    rho0: float = 1.0
+    c0: float = 1.0
+
+    def c(self) -> _CBc:
+        b = _CBc()
+        b.kind, b.profile = int(self.kind), int(self.profile)
+        b.u, b.radius, b.p_b, b.rho0, b.c0 = (float(self.u), float(self.radius), float(self.p_b),
+                                              float(self.rho0), float(self.c0))
+        return b
+
+
+@dataclass
+class Fields:
+    """Carried-field indices of the velocity components and the density (-1: absent)."""
+    vel: Sequence[int] = (-1, -1, -1)
+    rho: int = -1
+
+    def c(self) -> _CFields:
+        f = _CFields()
+        v = list(self.vel) + [-1] * (3 - len(self.vel))
+        for i in range(3):
+            f.vel[i] = int(v[i])
+        f.rho = int(self.rho)
+        return f
+
+
+def _cbcs(bcs: Optional[Sequence[BC]], nb: int):
+    if bcs is None:
+        return None
+    arr = (_CBc * max(1, nb))()
+    for i, b in enumerate(bcs):
+        arr[i] = b.c()
+    return arr
 
 
 def _cbufs(bufs: Sequence[Buffer]):
@@ -257,8 +328,11 @@ def identify(bufs: Sequence[Buffer], st: State, which: int = -1):
     return rc, nl[: len(bufs)]
 
 
-def update(bufs: Sequence[Buffer], st: State) -> UpdateResult:
-    """One buffer update (Algorithms 1-3); mutates ``st`` in place unless it fails."""
+def update(bufs: Sequence[Buffer], st: State, bcs: Optional[Sequence[BC]] = None,
+           fields: Optional[Fields] = None) -> UpdateResult:
+    """One buffer update (Algorithms 1-3); mutates ``st`` in place unless it fails.
+    With boundary conditions, a particle recycled at a pressure boundary takes the
+    density of Eq. (postulate-density)."""
     cs = st.c()
     cb = _cbufs(bufs)
     cap = max(1, st.n)
@@ -266,13 +340,48 @@ def update(bufs: Sequence[Buffer], st: State) -> UpdateResult:
     dele = np.zeros(cap, dtype=np.int64)
     ng, nd = ctypes.c_int64(0), ctypes.c_int64(0)
     nl = np.zeros(max(1, len(bufs)), dtype=np.int64)
-    rc = lib().orc_update(cb, len(bufs), ctypes.byref(cs), gen.ctypes.data, ctypes.byref(ng),
-                          dele.ctypes.data, ctypes.byref(nd), nl.ctypes.data)
+    cbc = _cbcs(bcs, len(bufs))
+    cf = fields.c() if fields is not None else None
+    rc = lib().orc_update_bc(cb, ctypes.cast(cbc, ctypes.c_void_p) if cbc is not None else None,
+                             ctypes.cast(ctypes.pointer(cf), ctypes.c_void_p) if cf is not None else None,
+                             len(bufs), ctypes.byref(cs), gen.ctypes.data, ctypes.byref(ng),
+                             dele.ctypes.data, ctypes.byref(nd), nl.ctypes.data)
     if rc == OK:
         st.n = int(cs.n)
         st.next_id = int(cs.next_id)
         return UpdateResult(rc, gen[: ng.value].copy(), dele[: nd.value].copy(), nl[: len(bufs)].copy())
     return UpdateResult(rc, np.zeros(0, np.int64), np.zeros(0, np.int64), np.zeros(len(bufs), np.int64))
+
+
+def apply_bc(bufs: Sequence[Buffer], bcs: Sequence[BC], fields: Fields, st: State) -> int:
+    """Velocity / pressure boundary conditions on the buffer particles (Section 4);
+    returns the status (ERR_CFL if a buffer particle lies outside its check region)."""
+    cs = st.c()
+    cb = _cbufs(bufs)
+    cbc = _cbcs(bcs, len(bufs))
+    cf = fields.c()
+    return lib().orc_apply_bc(cb, ctypes.cast(cbc, ctypes.c_void_p), ctypes.cast(ctypes.pointer(cf), ctypes.c_void_p),
+                              len(bufs), ctypes.byref(cs))
+
+
+def rotate_buffer(bufs: List[Buffer], which: int, center: Sequence[float], m, fields: Optional[Fields],
+                  st: State) -> int:
+    """Rigid rotation of buffer ``which`` (1-based) and its particles about ``center``
+    (Section 5.3); updates ``bufs[which - 1]`` in place and returns the status."""
+    cs = st.c()
+    cb = _cbufs(bufs)
+    c = np.zeros(3)
+    c[: len(center)] = center
+    mm = np.ascontiguousarray(m, dtype=np.float64).reshape(9)
+    cf = fields.c() if fields is not None else None
+    rc = lib().orc_rotate_buffer(cb, len(bufs), int(which), _dptr(c), _dptr(mm),
+                                 ctypes.cast(ctypes.pointer(cf), ctypes.c_void_p) if cf is not None else None,
+                                 ctypes.byref(cs))
+    b = cb[which - 1]
+    bufs[which - 1] = Buffer(bufs[which - 1].kind, tuple(b.origin[i] for i in range(3)),
+                             np.array([b.rot[i] for i in range(9)]).reshape(3, 3), bufs[which - 1].half,
+                             bufs[which - 1].margin)
+    return rc
 
 
 def cell_list(dim: int, lo, inv_cs: float, dims, x, y, z=None):

@@ -221,7 +221,26 @@ static void copy_particle(orc_state *s, int64_t dst, int64_t src) {
  */
 int orc_update(const orc_buffer *bufs, int nb, orc_state *s, int64_t *gen_src, int64_t *n_gen,
                int64_t *del_idx, int64_t *n_del, int64_t *n_labelled) {
-    if (!valid_args(bufs, nb, s)) return ORC_ERR_ARG;
+    return orc_update_bc(bufs, NULL, NULL, nb, s, gen_src, n_gen, del_idx, n_del, n_labelled);
+}
+
+/* Field roles must name existing carried arrays (or be -1). */
+static int valid_fields(const orc_fields *f, const orc_state *s) {
+    if (!f) return 1;
+    for (int c = 0; c < 3; c++)
+        if (f->vel[c] < -1 || f->vel[c] >= s->n_carried) return 0;
+    return f->rho >= -1 && f->rho < s->n_carried;
+}
+
+/* Density of a particle recycled at a pressure boundary, Eq. (postulate-density)
+ * with the EoS p = c0^2 (rho - rho0) (Eq. state_equation). */
+static float recycled_density(const orc_bc *bc) {
+    return (float)(bc->rho0 + bc->p_b / (bc->c0 * bc->c0));
+}
+
+int orc_update_bc(const orc_buffer *bufs, const orc_bc *bcs, const orc_fields *fields, int nb, orc_state *s,
+                  int64_t *gen_src, int64_t *n_gen, int64_t *del_idx, int64_t *n_del, int64_t *n_labelled) {
+    if (!valid_args(bufs, nb, s) || !valid_fields(fields, s)) return ORC_ERR_ARG;
     const int dim = s->dim;
     const int64_t N = s->n;
 
@@ -306,6 +325,9 @@ int orc_update(const orc_buffer *bufs, int nb, orc_state *s, int64_t *gen_src, i
             double shift = a * b->rot[c];
             s->pos[c][i] = (float)((double)s->pos[c][i] - shift);
         }
+        const orc_bc *bc = bcs ? &bcs[owner[i] - 1] : NULL;
+        if (bc && bc->kind == ORC_BC_PRESSURE && fields && fields->rho >= 0)
+            s->carried[fields->rho][i] = recycled_density(bc);
     }
 
     /* ---- relabel outlets / bidirectional buffers on post-recycle positions ---- */
@@ -357,6 +379,107 @@ int orc_update(const orc_buffer *bufs, int nb, orc_state *s, int64_t *gen_src, i
     *n_del = D;
     count_labels(nb, s, n_labelled);
     return ORC_OK;
+}
+
+/* ------------------------------------------------- boundary conditions --- */
+
+/* Profile factor f(Y', Z') of the velocity boundary condition (Section 4.2). */
+static double profile_factor(const orc_bc *bc, const double lc[3]) {
+    if (bc->profile == ORC_PROFILE_PARABOLIC_Y) {
+        double q = lc[1] / bc->radius;
+        return 1.0 - q * q;
+    }
+    if (bc->profile == ORC_PROFILE_PARABOLIC_R) {
+        double r2 = lc[1] * lc[1] + lc[2] * lc[2];
+        return 1.0 - r2 / (bc->radius * bc->radius);
+    }
+    return 1.0;
+}
+
+int orc_apply_bc(const orc_buffer *bufs, const orc_bc *bcs, const orc_fields *fields, int nb, orc_state *s) {
+    if (!valid_args(bufs, nb, s) || !bcs || !fields || !valid_fields(fields, s)) return ORC_ERR_ARG;
+    const int dim = s->dim;
+    for (int c = 0; c < dim; c++)
+        if (fields->vel[c] < 0) return ORC_ERR_ARG;
+    int st = ORC_OK;
+    for (int64_t i = 0; i < s->n; i++) {
+        int32_t l = s->label[i];
+        if (l < 1 || l > nb) continue;
+        const orc_buffer *b = &bufs[l - 1];
+        const orc_bc *bc = &bcs[l - 1];
+        if (bc->kind == ORC_BC_NONE) continue;
+        double r[3], lc[3];
+        position_of(s, i, r);
+        local_of(dim, b, r[0], r[1], r[2], lc);
+        if (!in_check(dim, b, lc)) {
+            st = ORC_ERR_CFL;
+            continue;
+        }
+        if (bc->kind == ORC_BC_VELOCITY) {
+            /* v' = (u f, 0, 0); v = Q^T v' */
+            double w = bc->u * profile_factor(bc, lc);
+            for (int c = 0; c < dim; c++) s->carried[fields->vel[c]][i] = (float)(b->rot[c] * w);
+        } else {
+            /* v <- (v . u_hat) u_hat, u_hat = Q^T e_x = first row of Q */
+            double v[3] = {0.0, 0.0, 0.0};
+            for (int c = 0; c < dim; c++) v[c] = (double)s->carried[fields->vel[c]][i];
+            double dot = b->rot[0] * v[0] + b->rot[1] * v[1];
+            if (dim == 3) dot = dot + b->rot[2] * v[2];
+            for (int c = 0; c < dim; c++) s->carried[fields->vel[c]][i] = (float)(dot * b->rot[c]);
+        }
+    }
+    return st;
+}
+
+/* y = m x for a row-major 3x3 m, each row summed left to right (two terms in 2-D). */
+static void mat_vec(int dim, const double m[9], const double x[3], double y[3]) {
+    for (int r = 0; r < 3; r++) {
+        double acc = m[3 * r] * x[0] + m[3 * r + 1] * x[1];
+        if (dim == 3) acc = acc + m[3 * r + 2] * x[2];
+        y[r] = acc;
+    }
+}
+
+int orc_rotate_buffer(orc_buffer *bufs, int nb, int which, const double center[3], const double m[9],
+                      const orc_fields *fields, orc_state *s) {
+    if (!valid_args(bufs, nb, s) || which < 1 || which > nb || !center || !m || !valid_fields(fields, s))
+        return ORC_ERR_ARG;
+    const int dim = s->dim;
+    orc_buffer *b = &bufs[which - 1];
+    int st = ORC_OK;
+    for (int64_t i = 0; i < s->n; i++) {
+        if (s->label[i] != which) continue;
+        double r[3], lc[3];
+        position_of(s, i, r);
+        local_of(dim, b, r[0], r[1], r[2], lc);
+        if (!in_check(dim, b, lc)) {
+            st = ORC_ERR_CFL;
+            continue;
+        }
+        double d[3] = {r[0] - center[0], r[1] - center[1], dim == 3 ? r[2] - center[2] : 0.0}, e[3];
+        mat_vec(dim, m, d, e);
+        for (int c = 0; c < dim; c++) s->pos[c][i] = (float)(center[c] + e[c]);
+        if (fields && fields->vel[0] >= 0) {
+            double v[3] = {0.0, 0.0, 0.0}, w[3];
+            for (int c = 0; c < dim; c++) v[c] = fields->vel[c] >= 0 ? (double)s->carried[fields->vel[c]][i] : 0.0;
+            mat_vec(dim, m, v, w);
+            for (int c = 0; c < dim; c++)
+                if (fields->vel[c] >= 0) s->carried[fields->vel[c]][i] = (float)w[c];
+        }
+    }
+    /* the frame follows the body: O' <- C + m (O' - C), rows of Q <- m (rows of Q) */
+    double d[3] = {b->origin[0] - center[0], b->origin[1] - center[1], dim == 3 ? b->origin[2] - center[2] : 0.0};
+    double e[3];
+    mat_vec(dim, m, d, e);
+    for (int c = 0; c < dim; c++) b->origin[c] = center[c] + e[c];
+    double q[9];
+    for (int r = 0; r < 3; r++) {
+        double row[3] = {b->rot[3 * r], b->rot[3 * r + 1], b->rot[3 * r + 2]}, nr[3];
+        mat_vec(dim, m, row, nr);
+        for (int c = 0; c < 3; c++) q[3 * r + c] = c < dim ? nr[c] : b->rot[3 * r + c];
+    }
+    memcpy(b->rot, q, sizeof q);
+    return st;
 }
 
 /* ------------------------------------------------------------- cell list --- */

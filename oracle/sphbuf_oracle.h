@@ -109,6 +109,57 @@ int orc_cell_list_sparse(int dim, const float lo[3], float inv_cs, const int32_t
                          const unsigned char *active, int64_t n, const float *x, const float *y, const float *z,
                          int32_t *cell_start, int32_t *cell_idx);
 
+/* ------------- in-/outlet boundary conditions (Section 4) and moving buffers --- */
+
+enum { ORC_BC_NONE = 0, ORC_BC_VELOCITY = 1, ORC_BC_PRESSURE = 2 };
+enum { ORC_PROFILE_PLUG = 0, ORC_PROFILE_PARABOLIC_Y = 1, ORC_PROFILE_PARABOLIC_R = 2 };
+
+typedef struct {
+    int32_t kind;      /* ORC_BC_NONE / ORC_BC_VELOCITY / ORC_BC_PRESSURE             */
+    int32_t profile;   /* velocity BC: ORC_PROFILE_*                                  */
+    double u;          /* velocity BC: speed scale of the profile along X'             */
+    double radius;     /* velocity BC: R of the parabolic profiles                     */
+    double p_b;        /* pressure BC: boundary pressure                               */
+    double rho0;       /* pressure BC: reference density of the EoS                   */
+    double c0;         /* pressure BC: artificial sound speed of the EoS               */
+} orc_bc;
+
+typedef struct {
+    int32_t vel[3];    /* carried-field index of v_x, v_y, v_z (-1: absent)             */
+    int32_t rho;       /* carried-field index of the density (-1: absent)               */
+} orc_fields;
+
+/* orc_update with the pressure boundary condition on the recycle path: a
+ * particle recycled by a pressure-BC buffer takes the density
+ * fl32(rho0 + p_b / (c0 c0)) (Eq. postulate-density); its duplicate keeps the
+ * state before the recycle.  bcs and fields may be NULL (no boundary conditions). */
+int orc_update_bc(const orc_buffer *bufs, const orc_bc *bcs, const orc_fields *fields, int nb, orc_state *s,
+                  int64_t *gen_src, int64_t *n_gen, int64_t *del_idx, int64_t *n_del, int64_t *n_labelled);
+
+/* Boundary conditions on the particles of each buffer (label k) inside its check
+ * region:
+ *   velocity BC (Section 4.2): the prescribed profile in the local frame,
+ *     v' = (u f(Y', Z'), 0, 0), mapped to global by Q^T (Eqs. 2D/3D_velocity_profile
+ *     and 2D/3D_velocity_transformation): v_c = fl32(Q[0][c] * (u * f)), with
+ *     f = 1 (plug), f = 1 - (Y'/R)^2 (parabolic in Y', as printed), or
+ *     f = 1 - (Y'^2 + Z'^2) / (R R) (parabolic in the radius of a pipe);
+ *   pressure BC (Section 4.1): the velocity projected on the boundary normal
+ *     u_hat = Q^T e_x (Eqs. velocity_correction, 2D/3D_normal_transformation):
+ *     v_c = fl32((v . u_hat) u_hat_c), the dot product summed left to right.
+ * Particles of a buffer found outside its check region are left alone and the
+ * call returns ORC_ERR_CFL (the others are still set). */
+int orc_apply_bc(const orc_buffer *bufs, const orc_bc *bcs, const orc_fields *fields, int nb, orc_state *s);
+
+/* Rotate buffer `which` (1..nb) rigidly about `center` by the orthonormal matrix
+ * m (row-major, global coordinates), as the rotating sprinkler of Section 5.3
+ * turns its buffer each step: every particle of the buffer inside its check
+ * region moves to r = C + m (r - C) and its velocity to m v (FP64, rounded to
+ * FP32); then the buffer's frame follows, O' <- C + m (O' - C) and Q <- Q m^T,
+ * so that the particle keeps its local coordinates.  Labelled particles outside
+ * the check region are left alone and the call returns ORC_ERR_CFL. */
+int orc_rotate_buffer(orc_buffer *bufs, int nb, int which, const double center[3], const double m[9],
+                      const orc_fields *fields, orc_state *s);
+
 #ifdef __cplusplus
 }
 #endif
