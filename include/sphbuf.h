@@ -173,6 +173,69 @@ sph_status sph_last_events(sph_ctx *ctx, int64_t *gen_src, int64_t *del_idx, int
 sph_status sph_celllist_view(sph_ctx *ctx, const int32_t **cell_start, const int32_t **cell_idx,
                              int64_t *n_cells, int32_t dims[3]);
 
+/* ---------------------------------- boundary conditions and moving buffers -- */
+
+/* Roles of the caller's carried arrays: indices into sph_particles.carried of the
+ * velocity components and of the density, -1 where absent.  Checked against
+ * n_carried at every call that uses them (SPH_ERR_ARG). */
+typedef struct {
+    int32_t vel[3];
+    int32_t rho;
+} sph_fields;
+sph_status sph_set_fields(sph_ctx *ctx, const sph_fields *fields);
+
+typedef enum { SPH_BC_NONE = 0, SPH_BC_VELOCITY = 1, SPH_BC_PRESSURE = 2 } sph_bc_kind;
+typedef enum {
+    SPH_PROFILE_PLUG = 0,        /* f = 1                                            */
+    SPH_PROFILE_PARABOLIC_Y = 1, /* f = 1 - (Y'/R)^2 (Eqs. 2D/3D_velocity_profile)   */
+    SPH_PROFILE_PARABOLIC_R = 2  /* f = 1 - (Y'^2 + Z'^2)/(R R): a pipe's profile    */
+} sph_profile;
+
+/* In-/outlet boundary condition of one buffer (Section 4).
+ * Velocity BC (Section 4.2): the buffer's particles move with the prescribed
+ * local-frame velocity v' = (u f(Y', Z'), 0, 0), i.e. v = Q^T v'
+ * (Eqs. 2D/3D_velocity_transformation).  Pressure BC (Section 4.1): their
+ * velocity is projected on the boundary normal u_hat = Q^T e_x
+ * (Eq. velocity_correction), and a particle the update recycles at this buffer
+ * takes the density rho0 + p_b / c0^2 (Eq. postulate-density; EoS
+ * p = c0^2 (rho - rho0)).  The momentum-equation part of the pressure BC belongs
+ * to the solver.  u and p_b may change between steps (call again). */
+typedef struct {
+    int32_t kind;      /* sph_bc_kind                                      */
+    int32_t profile;   /* sph_profile (velocity BC)                        */
+    double u;          /* velocity BC: speed scale along X'                 */
+    double radius;     /* velocity BC: R of the parabolic profiles (> 0)    */
+    double p_b;        /* pressure BC: boundary pressure                    */
+    double rho0;       /* pressure BC: reference density                    */
+    double c0;         /* pressure BC: artificial sound speed (> 0)         */
+} sph_bc;
+/* Host validation plus one small upload on the context stream.  SPH_ERR_ARG for
+ * an unknown buffer, kind or profile, a non-finite value, radius <= 0 (parabolic)
+ * or c0 <= 0 (pressure). */
+sph_status sph_buffer_set_bc(sph_ctx *ctx, int32_t buffer_id, const sph_bc *bc);
+
+/* Apply every buffer's boundary condition to its particles (label k inside the
+ * check region), exactly as defined in FP64 and rounded to FP32 once.  Needs a
+ * cell list of the current positions (sph_celllist_build; it stays valid, the
+ * positions do not change) and velocity fields.  Sync.  SPH_ERR_CFL if some
+ * buffer particle lies outside its check region: those are left alone, the
+ * others are set (the call is not transactional).  SPH_ERR_STATE without a
+ * current cell list. */
+sph_status sph_buffer_apply_bc(sph_ctx *ctx, sph_particles *p);
+
+/* Turn buffer buffer_id rigidly about center by the orthonormal matrix m
+ * (row-major, global coordinates; det +1), as the rotating sprinkler of
+ * Section 5.3 turns its buffer every step: each of its particles inside the
+ * check region moves to C + m (r - C), its velocity (if velocity fields are set)
+ * to m v, both in FP64 rounded to FP32 once; then the frame follows,
+ * O' <- C + m (O' - C), Q <- Q m^T, and the cell cover of the check region is
+ * recomputed.  Needs a cell list of the current positions; invalidates it
+ * (rebuild before the next update).  Sync.  Errors: SPH_ERR_ROTATION (m not
+ * orthonormal), SPH_ERR_OVERLAP (the turned check region would meet another
+ * buffer's: nothing changes), SPH_ERR_CFL as for sph_buffer_apply_bc. */
+sph_status sph_buffer_rotate(sph_ctx *ctx, sph_particles *p, int32_t buffer_id, const double center[3],
+                             const double m[9]);
+
 /* Library state that is not in the particle arrays: next_id and each buffer's
  * labelled count (sync).  Lets a caller checkpoint and restore a run. */
 sph_status sph_state_get(sph_ctx *ctx, int64_t *next_id, int64_t n_labelled[SPH_MAX_BUFFERS]);
@@ -189,7 +252,9 @@ typedef enum {
     SPH_PHASE_FULLSCAN = 4,   /* every particle against every buffer (baseline)   */
     SPH_PHASE_FINALIZE = 5,   /* status, sort, duplicate/recycle/relabel/compact  */
     SPH_PHASE_BUILD = 6,      /* count + scan + scatter in one cooperative launch */
-    SPH_NPHASE = 7
+    SPH_PHASE_BC = 7,         /* boundary conditions on buffer particles          */
+    SPH_PHASE_ROTATE = 8,     /* rigid turn of a buffer's particles               */
+    SPH_NPHASE = 9
 } sph_phase;
 
 /* When on, every kernel launch of the context is bracketed by two HIP events on

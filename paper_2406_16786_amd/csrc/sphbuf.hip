@@ -97,6 +97,7 @@ struct Ctl {
     unsigned int bar_count;        // grid barrier of the fused build: arrivals
     unsigned int bar_gen;          // grid barrier generation
     unsigned int fin_ticket;       // finalize blocks that have read the counters
+    unsigned int bc_status;        // outcome of the last boundary-condition or rotation pass
     long long next_id;
     long long n_labelled[16];
     unsigned int ident_bad;
@@ -258,13 +259,14 @@ __device__ __forceinline__ Outcome decide(const BufDev &b, int k, int dim, unsig
 struct EventArgs {
     Ctl *ctl;
     uint32_t *gen_idx;         // [kSeg * cap_ev] generated-source index
-    float *gen_new;            // [kSeg * cap_ev * 3] its recycled position
+    float *gen_new;            // [kSeg * cap_ev * 4] its recycled position and density
     float *dup;                // [kSeg * cap_ev * (3 + nc)] its pre-recycle position and carried fields
     uint32_t *del_idx;         // [kSeg * cap_ev] deleted index
     unsigned long long *rel;   // [kSeg * cap_rel] (index << 32) | new label
     unsigned cap_ev;
     unsigned cap_rel;
     unsigned *part;  // label counts, kCountReplicas copies: part[(copy * 16 + k) * 2 + {0: found, 1: post}]
+    int32_t rho_field;  // carried index of the density, or -1
 };
 
 // Label counts of each buffer: waves add into LDS, then one thread per buffer
@@ -326,9 +328,13 @@ __device__ __forceinline__ void emit(const EventArgs &e, const Parts &p, const B
             float *d = e.dup + ev * (size_t)(3 + p.nc);
             for (int c = 0; c < p.dim; ++c) {
                 d[c] = r[c];
-                e.gen_new[3 * ev + c] = (float)((double)r[c] - b.shift[c]);
+                e.gen_new[4 * ev + c] = (float)((double)r[c] - b.shift[c]);
             }
             for (int f = 0; f < p.nc; ++f) d[3 + f] = p.car[f][i];
+            // density of the recycled particle: the boundary value at a pressure
+            // boundary (Eq. postulate-density), otherwise unchanged
+            if (e.rho_field >= 0)
+                e.gen_new[4 * ev + 3] = b.bc_kind == SPH_BC_PRESSURE ? b.rho_rec : d[3 + e.rho_field];
         }
     }
     if (pd) {
@@ -1299,15 +1305,19 @@ __device__ __forceinline__ void finalize_body(const FinArgs &a, const int fb, co
             const int g = seg_of(s_off[0], e);
             const unsigned ev = (unsigned)g * cap + (e - s_off[0][g]);
             const bool mine = e >= g0 && e < g1;
-            float rn[3] = {0.0f, 0.0f, 0.0f};
+            float rn[4] = {0.0f, 0.0f, 0.0f, 0.0f};
             if (mine)
-                for (int q = 0; q < dim; ++q) rn[q] = a.e.gen_new[3 * (size_t)ev + q];
+                for (int q = 0; q < 4; ++q)
+                    if (q < dim || (q == 3 && a.e.rho_field >= 0)) rn[q] = a.e.gen_new[4 * (size_t)ev + q];
             const uint32_t i = a.e.gen_idx[ev];
             s_k[0][0][e] = i;
             s_v[0][e] = ev;
-            if ((long long)i >= Np) atomicOr(&s_map[i - Np], ev + 1u);
-            else if (mine)
+            if ((long long)i >= Np) {
+                atomicOr(&s_map[i - Np], ev + 1u);
+            } else if (mine) {
                 for (int q = 0; q < dim; ++q) p.pos[q][i] = rn[q];
+                if (a.e.rho_field >= 0) p.car[a.e.rho_field][i] = rn[3];
+            }
         }
         for (unsigned e = tid; e < D; e += bd) {
             const int g = seg_of(s_off[1], e);
@@ -1545,10 +1555,10 @@ __device__ __forceinline__ void finalize_body(const FinArgs &a, const int fb, co
                 const uint32_t ge = m & ((1u << kMapRelShift) - 1u), rl = m >> kMapRelShift;
 #pragma unroll
                 for (int q = 0; q < 3; ++q)
-                    if (q < dim) v[q] = ge ? a.e.gen_new[3 * (size_t)(ge - 1u) + q] : p.pos[q][pi];
+                    if (q < dim) v[q] = ge ? a.e.gen_new[4 * (size_t)(ge - 1u) + q] : p.pos[q][pi];
 #pragma unroll
                 for (int f = 0; f < SPH_MAX_CARRIED; ++f)
-                    if (f < nc) v[3 + f] = p.car[f][pi];
+                    if (f < nc) v[3 + f] = ge && f == a.e.rho_field ? a.e.gen_new[4 * (size_t)(ge - 1u) + 3] : p.car[f][pi];
                 lab = rl ? (int32_t)(rl - 1u) : p.label[pi];
                 id = p.id[pi];
             }
@@ -1674,6 +1684,152 @@ __global__ void k_ident_commit(IdentArgs a) {
         for (int k = 0; k < a.nb; ++k) a.ctl->n_labelled[k] = (long long)a.ctl->ident_count[k];
 }
 
+// ------------------------------------- boundary conditions, rotating buffers --
+//
+// One wave per run of cover cells (as the classify step); a candidate is handled
+// if it carries the buffer's label and lies in the check region (the exact
+// decision, guard band included).  Every value is computed in FP64 with the
+// expression order of the definition and rounded to FP32 once.
+
+struct BcArgs {
+    Parts p;
+    const BufDev *bufs;
+    int nb;
+    const int32_t *run_first;
+    const int32_t *run_len;
+    const uint8_t *run_buf;
+    int n_runs;
+    const int32_t *cell_start;
+    const int32_t *cell_idx;
+    int32_t vel[3];
+    int which;         // rotation of this buffer (0-based); -1: boundary conditions of every buffer
+    double center[3];  // rotation centre
+    double m[9];       // rotation matrix, row-major
+    unsigned *found;   // kCountReplicas copies of the per-buffer count of handled particles
+};
+
+// y = m x, rows summed left to right (two terms in 2-D).
+__device__ __forceinline__ void mat_vec64(int dim, const double *m, const double x[3], double y[3]) {
+#pragma clang fp contract(off)
+    for (int r = 0; r < 3; ++r) {
+        double acc = __dadd_rn(__dmul_rn(m[3 * r], x[0]), __dmul_rn(m[3 * r + 1], x[1]));
+        if (dim == 3) acc = __dadd_rn(acc, __dmul_rn(m[3 * r + 2], x[2]));
+        y[r] = acc;
+    }
+}
+
+__device__ void apply_bc_one(const BcArgs &a, const BufDev &b, int64_t i, float x, float y, float z) {
+#pragma clang fp contract(off)
+    const Parts &p = a.p;
+    const int dim = p.dim;
+    if (b.bc_kind == SPH_BC_VELOCITY) {
+        // local frame: r' = Q (r - O'), rows summed left to right
+        const double d0 = __dadd_rn((double)x, -b.o[0]), d1 = __dadd_rn((double)y, -b.o[1]);
+        const double d2 = dim == 3 ? __dadd_rn((double)z, -b.o[2]) : 0.0;
+        double l1 = __dadd_rn(__dmul_rn(b.q[3], d0), __dmul_rn(b.q[4], d1));
+        double l2 = 0.0;
+        if (dim == 3) {
+            l1 = __dadd_rn(l1, __dmul_rn(b.q[5], d2));
+            l2 = __dadd_rn(__dadd_rn(__dmul_rn(b.q[6], d0), __dmul_rn(b.q[7], d1)), __dmul_rn(b.q[8], d2));
+        }
+        double f = 1.0;
+        if (b.profile == SPH_PROFILE_PARABOLIC_Y) {
+            const double q = __ddiv_rn(l1, b.bc_radius);
+            f = __dadd_rn(1.0, -__dmul_rn(q, q));
+        } else if (b.profile == SPH_PROFILE_PARABOLIC_R) {
+            const double r2 = __dadd_rn(__dmul_rn(l1, l1), __dmul_rn(l2, l2));
+            f = __dadd_rn(1.0, -__ddiv_rn(r2, __dmul_rn(b.bc_radius, b.bc_radius)));
+        }
+        const double w = __dmul_rn(b.bc_u, f);  // v' = (u f, 0, 0); v = Q^T v'
+        for (int c = 0; c < dim; ++c) p.car[a.vel[c]][i] = (float)__dmul_rn(b.q[c], w);
+    } else {
+        // v <- (v . u_hat) u_hat with u_hat = Q^T e_x, the first row of Q
+        double v[3] = {0.0, 0.0, 0.0};
+        for (int c = 0; c < dim; ++c) v[c] = (double)p.car[a.vel[c]][i];
+        double dot = __dadd_rn(__dmul_rn(b.q[0], v[0]), __dmul_rn(b.q[1], v[1]));
+        if (dim == 3) dot = __dadd_rn(dot, __dmul_rn(b.q[2], v[2]));
+        for (int c = 0; c < dim; ++c) p.car[a.vel[c]][i] = (float)__dmul_rn(dot, b.q[c]);
+    }
+}
+
+__device__ void rotate_one(const BcArgs &a, int64_t i, float x, float y, float z) {
+#pragma clang fp contract(off)
+    const Parts &p = a.p;
+    const int dim = p.dim;
+    const double d[3] = {__dadd_rn((double)x, -a.center[0]), __dadd_rn((double)y, -a.center[1]),
+                         dim == 3 ? __dadd_rn((double)z, -a.center[2]) : 0.0};
+    double e[3];
+    mat_vec64(dim, a.m, d, e);
+    for (int c = 0; c < dim; ++c) p.pos[c][i] = (float)__dadd_rn(a.center[c], e[c]);
+    if (a.vel[0] >= 0) {
+        double v[3] = {0.0, 0.0, 0.0}, w[3];
+        for (int c = 0; c < dim; ++c) v[c] = a.vel[c] >= 0 ? (double)p.car[a.vel[c]][i] : 0.0;
+        mat_vec64(dim, a.m, v, w);
+        for (int c = 0; c < dim; ++c)
+            if (a.vel[c] >= 0) p.car[a.vel[c]][i] = (float)w[c];
+    }
+}
+
+__global__ __launch_bounds__(kClassifyBlock) void k_buffer_bc(BcArgs a) {
+    __shared__ BufDev sb[SPH_MAX_BUFFERS];
+    __shared__ unsigned s_cnt[SPH_MAX_BUFFERS];
+    for (int t = threadIdx.x; t < a.nb * (int)(sizeof(BufDev) / 4); t += blockDim.x)
+        reinterpret_cast<uint32_t *>(sb)[t] = reinterpret_cast<const uint32_t *>(a.bufs)[t];
+    if (threadIdx.x < SPH_MAX_BUFFERS) s_cnt[threadIdx.x] = 0u;
+    __syncthreads();
+    const int64_t N = live_count(a.p.n_dev, a.p.capacity);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const int wpb = blockDim.x / kWave;
+    const int dim = a.p.dim;
+    for (int r = blockIdx.x * wpb + wave; r < a.n_runs; r += gridDim.x * wpb) {
+        const int k = a.run_buf[r];
+        const BufDev &b = sb[k];
+        if (a.which < 0 ? b.bc_kind == SPH_BC_NONE : k != a.which) continue;  // wave-uniform
+        const int c0 = a.run_first[r];
+        const int j0 = a.cell_start[c0];
+        const int j1 = a.cell_start[c0 + a.run_len[r]];
+        unsigned long long handled = 0;
+        for (int jb = j0; jb < j1; jb += kWave) {
+            const int j = jb + lane;
+            const int64_t i = j < j1 ? a.cell_idx[j] : 0;
+            if (!(j < j1 && i < N)) continue;
+            const float x = a.p.pos[0][i], y = a.p.pos[1][i], z = dim == 3 ? a.p.pos[2][i] : 0.0f;
+            if (a.p.label[i] != k + 1) continue;
+            if (!(classify(b, dim, x, y, z) & kIn)) continue;  // outside the check region: reported
+            ++handled;
+            if (a.which < 0) apply_bc_one(a, b, i, x, y, z);
+            else rotate_one(a, i, x, y, z);
+        }
+        handled = wave_sum(handled);
+        if (lane == 0 && handled) atomicAdd(&s_cnt[k], (unsigned)handled);
+    }
+    __syncthreads();
+    if (threadIdx.x < a.nb && s_cnt[threadIdx.x])
+        atomicAdd(&a.found[(size_t)(blockIdx.x % kCountReplicas) * SPH_MAX_BUFFERS + threadIdx.x], s_cnt[threadIdx.x]);
+}
+
+// Sum the per-buffer counts, clear them, and compare with the labelled counts of
+// the buffers the pass was meant to handle.
+__global__ void k_bc_finish(unsigned *found, const BufDev *bufs, int nb, int which, Ctl *ctl) {
+    __shared__ unsigned s_bad;
+    if (threadIdx.x == 0) s_bad = 0u;
+    __syncthreads();
+    if ((int)threadIdx.x < nb) {
+        const int k = threadIdx.x;
+        unsigned long long tot = 0;
+        for (int r = 0; r < kCountReplicas; ++r) {
+            unsigned *w = &found[(size_t)r * SPH_MAX_BUFFERS + k];
+            tot += *w;
+            *w = 0u;
+        }
+        const bool involved = which < 0 ? bufs[k].bc_kind != SPH_BC_NONE : k == which;
+        if (involved && (long long)tot != ctl->n_labelled[k]) atomicOr(&s_bad, 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) ctl->bc_status = s_bad ? (unsigned)SPH_ERR_CFL : (unsigned)SPH_OK;
+}
+
 // ----------------------------------------------------------------- batches --
 //
 // Every phase of every domain of a batch in one launch: a static table maps each
@@ -1760,6 +1916,9 @@ struct sph_ctx {
     unsigned long long *d_rel = nullptr;
     Ctl *d_ctl = nullptr;
     unsigned *d_part = nullptr;
+    unsigned *d_bcfound = nullptr;    // per-buffer counts of a boundary-condition / rotation pass
+    unsigned *h_bc_status = nullptr;  // pinned
+    sph_fields fields = {{-1, -1, -1}, -1};
     int32_t *d_block_sum = nullptr;
     sph_result *d_result = nullptr;
     sph_result *h_result = nullptr;  // pinned
@@ -1866,6 +2025,7 @@ EventArgs events_of(const sph_ctx *ctx) {
     e.cap_ev = ctx->max_events;
     e.cap_rel = ctx->max_events * kRelPerEvent;
     e.part = ctx->d_part;
+    e.rho_field = ctx->fields.rho;
     return e;
 }
 
@@ -1977,6 +2137,8 @@ void free_ctx(sph_ctx *c) {
     (void)hipFree(c->d_dup);
     (void)hipFree(c->d_ctl);
     (void)hipFree(c->d_part);
+    (void)hipFree(c->d_bcfound);
+    if (c->h_bc_status) (void)hipHostFree(c->h_bc_status);
     (void)hipFree(c->d_block_sum);
     (void)hipFree(c->d_result);
     if (c->h_result) (void)hipHostFree(c->h_result);
@@ -1985,6 +2147,44 @@ void free_ctx(sph_ctx *c) {
 }
 
 }  // namespace
+
+// Device record of one buffer's frame: FP64 and FP32 forms of the rotation,
+// hi/lo split of the origin, thresholds, guard band, bounding sphere, recycle
+// shift.  Boundary-condition members are zero (none).
+static BufDev frame_record(const sph_ctx *ctx, int kind, const double o[3], const double q[9], const double h[3],
+                           double margin) {
+    const int dim = ctx->dim;
+    BufDev b{};
+    for (int i = 0; i < 9; ++i) {
+        b.q[i] = q[i];
+        b.qf[i] = (float)q[i];
+    }
+    for (int c = 0; c < 3; ++c) {
+        b.o[c] = o[c];
+        b.ohi[c] = (float)o[c];
+        b.olo[c] = (float)(o[c] - (double)b.ohi[c]);
+        b.thr[c] = h[c];
+        b.thr[3 + c] = h[c] + margin;
+        b.thrf[c] = (float)b.thr[c];
+        b.thrf[3 + c] = (float)b.thr[3 + c];
+    }
+    const double a = 2.0 * h[0];
+    for (int c = 0; c < 3; ++c) b.shift[c] = c < dim ? a * q[c] : 0.0;
+    b.guard = (float)sphbuf::guard_band(dim, o, h, margin, ctx->cs, ctx->dp);
+    const double R = sphbuf::sphere_radius(dim, h, margin);
+    b.rsq = (float)(R * R);
+    b.kind = (int32_t)kind;
+    return b;
+}
+
+// Copy the boundary-condition members of one record into another.
+static void copy_bc(BufDev &dst, const BufDev &src) {
+    dst.bc_kind = src.bc_kind;
+    dst.profile = src.profile;
+    dst.rho_rec = src.rho_rec;
+    dst.bc_u = src.bc_u;
+    dst.bc_radius = src.bc_radius;
+}
 
 // Candidate cells of one check region as runs of consecutive cell keys, at most
 // a wave's worth of candidates per run (one wave takes one run).  For the
@@ -2142,7 +2342,7 @@ extern "C" sph_status sph_create(const sph_config *cfg, sph_ctx **out) {
               hipMalloc(&c->d_del_idx, sizeof(uint32_t) * ev * kSeg) == hipSuccess &&
               hipMalloc(&c->d_gen_sorted, sizeof(uint32_t) * ev) == hipSuccess &&
               hipMalloc(&c->d_del_sorted, sizeof(uint32_t) * ev) == hipSuccess &&
-              hipMalloc(&c->d_gen_new, sizeof(float) * ev * kSeg * 3) == hipSuccess &&
+              hipMalloc(&c->d_gen_new, sizeof(float) * ev * kSeg * 4) == hipSuccess &&
               hipMalloc(&c->d_rel, sizeof(unsigned long long) * ev * kSeg * kRelPerEvent) == hipSuccess &&
               hipMalloc(&c->d_dup, sizeof(float) * ev * kSeg * (3 + SPH_MAX_CARRIED)) == hipSuccess &&
               hipMalloc(&c->d_ctl, sizeof(Ctl)) == hipSuccess &&
@@ -2150,6 +2350,8 @@ extern "C" sph_status sph_create(const sph_config *cfg, sph_ctx **out) {
               hipMalloc(&c->d_part, sizeof(unsigned) * 2 * SPH_MAX_BUFFERS * kMaxPartBlocks) == hipSuccess &&
               hipMalloc(&c->d_block_sum, sizeof(int32_t) * kMaxPartBlocks) == hipSuccess &&
               hipMalloc(&c->d_result, sizeof(sph_result)) == hipSuccess &&
+              hipMalloc(&c->d_bcfound, sizeof(unsigned) * kCountReplicas * SPH_MAX_BUFFERS) == hipSuccess &&
+              hipHostMalloc(&c->h_bc_status, sizeof(unsigned), hipHostMallocDefault) == hipSuccess &&
               hipHostMalloc(&c->h_result, sizeof(sph_result), hipHostMallocDefault) == hipSuccess;
     if (ok) {
         Ctl init{};
@@ -2161,6 +2363,8 @@ extern "C" sph_status sph_create(const sph_config *cfg, sph_ctx **out) {
              hipMemsetAsync(c->d_part, 0, sizeof(unsigned) * 2 * SPH_MAX_BUFFERS * kMaxPartBlocks, c->stream) ==
                  hipSuccess &&
              hipMemcpyAsync(c->d_ctl, &init, sizeof(Ctl), hipMemcpyHostToDevice, c->stream) == hipSuccess &&
+             hipMemsetAsync(c->d_bcfound, 0, sizeof(unsigned) * kCountReplicas * SPH_MAX_BUFFERS, c->stream) ==
+                 hipSuccess &&
              (blog2 == 0 || hipMemsetAsync(c->d_brick_slot, 0xff, sizeof(int32_t) * c->n_bricks, c->stream) ==
                                 hipSuccess) &&
              hipMemcpyAsync(c->d_result, &r0, sizeof(r0), hipMemcpyHostToDevice, c->stream) == hipSuccess &&
@@ -2230,26 +2434,7 @@ extern "C" sph_status sph_buffer_define(sph_ctx *ctx, sph_kind kind, const doubl
     }
 
     const int k = ctx->nb;
-    BufDev b{};
-    for (int i = 0; i < 9; ++i) {
-        b.q[i] = q[i];
-        b.qf[i] = (float)q[i];
-    }
-    for (int c = 0; c < 3; ++c) {
-        b.o[c] = o[c];
-        b.ohi[c] = (float)o[c];
-        b.olo[c] = (float)(o[c] - (double)b.ohi[c]);
-        b.thr[c] = h[c];
-        b.thr[3 + c] = h[c] + margin;
-        b.thrf[c] = (float)b.thr[c];
-        b.thrf[3 + c] = (float)b.thr[3 + c];
-    }
-    const double a = 2.0 * h[0];
-    for (int c = 0; c < 3; ++c) b.shift[c] = c < dim ? a * q[c] : 0.0;
-    b.guard = (float)sphbuf::guard_band(dim, o, h, margin, ctx->cs, ctx->dp);
-    const double R = sphbuf::sphere_radius(dim, h, margin);
-    b.rsq = (float)(R * R);
-    b.kind = (int32_t)kind;
+    const BufDev b = frame_record(ctx, kind, o, q, h, margin);
 
     // rebuild the device run list with the new buffer's runs appended
     std::vector<int32_t> rf = ctx->h_run_first, rl = ctx->h_run_len;
@@ -2335,6 +2520,7 @@ extern "C" sph_status sph_buffer_update_async(sph_ctx *ctx, sph_particles *p) {
     Parts pp;
     const sph_status st = parts_of(ctx, p, pp);
     if (st != SPH_OK) return st;
+    if (ctx->fields.rho >= pp.nc) return SPH_ERR_ARG;
     int n_part = 0;
     if (ctx->n_runs > 0) {
         const LocalArgs la = local_args(ctx, pp);
@@ -2353,6 +2539,7 @@ static sph_status fullscan_enqueue(sph_ctx *ctx, sph_particles *p) {
     Parts pp;
     const sph_status st = parts_of(ctx, p, pp);
     if (st != SPH_OK) return st;
+    if (ctx->fields.rho >= pp.nc) return SPH_ERR_ARG;
     FullArgs fa{};
     fa.p = pp;
     fa.bufs = ctx->d_bufs;
@@ -2433,6 +2620,168 @@ extern "C" sph_status sph_celllist_view(sph_ctx *ctx, const int32_t **cell_start
     if (dims)
         for (int c = 0; c < 3; ++c) dims[c] = ctx->dims[c];
     return SPH_OK;
+}
+
+// ------------------------------------- boundary conditions, rotating buffers --
+
+extern "C" sph_status sph_set_fields(sph_ctx *ctx, const sph_fields *fields) {
+    if (!ctx || !fields) return SPH_ERR_ARG;
+    for (int c = 0; c < 3; ++c)
+        if (fields->vel[c] < -1 || fields->vel[c] >= SPH_MAX_CARRIED) return SPH_ERR_ARG;
+    if (fields->rho < -1 || fields->rho >= SPH_MAX_CARRIED) return SPH_ERR_ARG;
+    ctx->fields = *fields;
+    return SPH_OK;
+}
+
+extern "C" sph_status sph_buffer_set_bc(sph_ctx *ctx, int32_t buffer_id, const sph_bc *bc) {
+    if (!ctx || !bc || buffer_id < 1 || buffer_id > ctx->nb) return SPH_ERR_ARG;
+    if (bc->kind < SPH_BC_NONE || bc->kind > SPH_BC_PRESSURE) return SPH_ERR_ARG;
+    if (bc->profile < SPH_PROFILE_PLUG || bc->profile > SPH_PROFILE_PARABOLIC_R) return SPH_ERR_ARG;
+    if (!std::isfinite(bc->u) || !std::isfinite(bc->radius) || !std::isfinite(bc->p_b) || !std::isfinite(bc->rho0) ||
+        !std::isfinite(bc->c0))
+        return SPH_ERR_ARG;
+    if (bc->kind == SPH_BC_VELOCITY && bc->profile != SPH_PROFILE_PLUG && !(bc->radius > 0.0)) return SPH_ERR_ARG;
+    if (bc->kind == SPH_BC_PRESSURE && !(bc->c0 > 0.0)) return SPH_ERR_ARG;
+    BufDev &b = ctx->hb[buffer_id - 1];
+    b.bc_kind = bc->kind;
+    b.profile = bc->profile;
+    b.bc_u = bc->u;
+    b.bc_radius = bc->radius;
+    // Eq. (postulate-density) with the EoS p = c0^2 (rho - rho0)
+    b.rho_rec = bc->kind == SPH_BC_PRESSURE ? (float)(bc->rho0 + bc->p_b / (bc->c0 * bc->c0)) : 0.0f;
+    HIP_TRY(hipMemcpyAsync(ctx->d_bufs + (buffer_id - 1), &b, sizeof(BufDev), hipMemcpyHostToDevice, ctx->stream));
+    return SPH_OK;
+}
+
+// Velocity fields of a call: every component present and inside the carried arrays.
+static bool velocity_fields_ok(const sph_ctx *ctx, const Parts &pp) {
+    for (int c = 0; c < ctx->dim; ++c)
+        if (ctx->fields.vel[c] < 0 || ctx->fields.vel[c] >= pp.nc) return false;
+    return true;
+}
+
+static sph_status launch_buffer_pass(sph_ctx *ctx, const Parts &pp, int which, const double center[3],
+                                     const double m[9]) {
+    BcArgs a{};
+    a.p = pp;
+    a.bufs = ctx->d_bufs;
+    a.nb = ctx->nb;
+    a.run_first = ctx->d_run_first;
+    a.run_len = ctx->d_run_len;
+    a.run_buf = ctx->d_run_buf;
+    a.n_runs = ctx->n_runs;
+    a.cell_start = ctx->d_cell_start;
+    a.cell_idx = ctx->d_cell_idx;
+    for (int c = 0; c < 3; ++c) a.vel[c] = c < ctx->dim ? ctx->fields.vel[c] : -1;
+    a.which = which;
+    if (center)
+        for (int c = 0; c < 3; ++c) a.center[c] = center[c];
+    if (m)
+        for (int i = 0; i < 9; ++i) a.m[i] = m[i];
+    a.found = ctx->d_bcfound;
+    if (ctx->n_runs > 0) {
+        const int wpb = kClassifyBlock / kWave;
+        const int blocks = std::max(1, std::min(kMaxPartBlocks, (ctx->n_runs + wpb - 1) / wpb));
+        ProfScope ps(ctx, which < 0 ? SPH_PHASE_BC : SPH_PHASE_ROTATE);
+        hipLaunchKernelGGL(k_buffer_bc, dim3(blocks), dim3(kClassifyBlock), 0, ctx->stream, a);
+    }
+    hipLaunchKernelGGL(k_bc_finish, dim3(1), dim3(64), 0, ctx->stream, ctx->d_bcfound, ctx->d_bufs, ctx->nb, which,
+                       ctx->d_ctl);
+    HIP_TRY(hipGetLastError());
+    return SPH_OK;
+}
+
+static sph_status read_bc_status(sph_ctx *ctx) {
+    HIP_TRY(hipMemcpyAsync(ctx->h_bc_status, &ctx->d_ctl->bc_status, sizeof(unsigned), hipMemcpyDeviceToHost,
+                           ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return (sph_status)*ctx->h_bc_status;
+}
+
+extern "C" sph_status sph_buffer_apply_bc(sph_ctx *ctx, sph_particles *p) {
+    if (!ctx) return SPH_ERR_ARG;
+    Parts pp;
+    const sph_status st = parts_of(ctx, p, pp);
+    if (st != SPH_OK) return st;
+    if (!velocity_fields_ok(ctx, pp)) return SPH_ERR_ARG;
+    if (!ctx->built) return SPH_ERR_STATE;
+    const sph_status ls = launch_buffer_pass(ctx, pp, -1, nullptr, nullptr);
+    if (ls != SPH_OK) return ls;
+    return read_bc_status(ctx);
+}
+
+// y = m x with rows summed left to right (two terms in 2-D), FP64 on the host.
+static void mat_vec_host(int dim, const double m[9], const double x[3], double y[3]) {
+    for (int r = 0; r < 3; ++r) {
+        double acc = m[3 * r] * x[0] + m[3 * r + 1] * x[1];
+        if (dim == 3) acc = acc + m[3 * r + 2] * x[2];
+        y[r] = acc;
+    }
+}
+
+extern "C" sph_status sph_buffer_rotate(sph_ctx *ctx, sph_particles *p, int32_t buffer_id, const double center[3],
+                                        const double m[9]) {
+    if (!ctx || !center || !m || buffer_id < 1 || buffer_id > ctx->nb) return SPH_ERR_ARG;
+    const int dim = ctx->dim;
+    for (int c = 0; c < dim; ++c)
+        if (!std::isfinite(center[c])) return SPH_ERR_ARG;
+    const sph_status rs = sph_check_rotation(dim, m);
+    if (rs != SPH_OK) return rs;
+    Parts pp;
+    const sph_status st = parts_of(ctx, p, pp);
+    if (st != SPH_OK) return st;
+    for (int c = 0; c < dim; ++c)
+        if (ctx->fields.vel[c] >= pp.nc) return SPH_ERR_ARG;
+    if (!ctx->built) return SPH_ERR_STATE;
+    const int k = buffer_id - 1;
+    // the frame follows the body: O' <- C + m (O' - C), rows of Q <- m (rows of Q)
+    double o[3], q[9];
+    {
+        const double d[3] = {ctx->b_origin[k][0] - center[0], ctx->b_origin[k][1] - center[1],
+                             dim == 3 ? ctx->b_origin[k][2] - center[2] : 0.0};
+        double e[3];
+        mat_vec_host(dim, m, d, e);
+        for (int c = 0; c < 3; ++c) o[c] = c < dim ? center[c] + e[c] : ctx->b_origin[k][c];
+        for (int r = 0; r < 3; ++r) {
+            const double row[3] = {ctx->b_rot[k][3 * r], ctx->b_rot[k][3 * r + 1], ctx->b_rot[k][3 * r + 2]};
+            double nr[3];
+            mat_vec_host(dim, m, row, nr);
+            for (int c = 0; c < 3; ++c) q[3 * r + c] = c < dim ? nr[c] : ctx->b_rot[k][3 * r + c];
+        }
+    }
+    for (int j = 0; j < ctx->nb; ++j)
+        if (j != k && sphbuf::check_regions_overlap(dim, o, q, ctx->b_half[k], ctx->b_margin[k], ctx->b_origin[j],
+                                                    ctx->b_rot[j], ctx->b_half[j], ctx->b_margin[j]))
+            return SPH_ERR_OVERLAP;
+    std::vector<int32_t> first, len;
+    {
+        const sph_status cs = cover_runs(ctx, o, q, ctx->b_half[k], ctx->b_margin[k], first, len);
+        if (cs != SPH_OK) return cs;
+    }
+    // turn the particles with the old frame and cover, then install the new ones
+    const sph_status ls = launch_buffer_pass(ctx, pp, k, center, m);
+    if (ls != SPH_OK) return ls;
+    BufDev b = frame_record(ctx, ctx->hb[k].kind, o, q, ctx->b_half[k], ctx->b_margin[k]);
+    copy_bc(b, ctx->hb[k]);
+    ctx->hb[k] = b;
+    HIP_TRY(hipMemcpyAsync(ctx->d_bufs + k, &ctx->hb[k], sizeof(BufDev), hipMemcpyHostToDevice, ctx->stream));
+    std::vector<int32_t> rf, rl;
+    std::vector<uint8_t> rb;
+    for (size_t r = 0; r < ctx->h_run_buf.size(); ++r)
+        if (ctx->h_run_buf[r] != (uint8_t)k) {
+            rf.push_back(ctx->h_run_first[r]);
+            rl.push_back(ctx->h_run_len[r]);
+            rb.push_back(ctx->h_run_buf[r]);
+        }
+    rf.insert(rf.end(), first.begin(), first.end());
+    rl.insert(rl.end(), len.begin(), len.end());
+    rb.insert(rb.end(), first.size(), (uint8_t)k);
+    const sph_status us = upload_runs(ctx, rf, rl, rb);  // waits for the stream
+    if (us != SPH_OK) return us;
+    for (int c = 0; c < 3; ++c) ctx->b_origin[k][c] = o[c];
+    std::copy(q, q + 9, ctx->b_rot[k]);
+    ctx->built = false;  // the buffer's particles moved
+    return read_bc_status(ctx);
 }
 
 extern "C" sph_status sph_buffer_identify(sph_ctx *ctx, sph_particles *p, int32_t buffer_id) {

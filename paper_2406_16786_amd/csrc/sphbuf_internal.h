@@ -32,6 +32,12 @@ struct BufDev {
     double o[3];      // origin, FP64
     double thr[6];    // FP64 thresholds, same order as thrf
     double shift[3];  // recycle shift a d = (2 * a/2) * q[0..2], FP64
+    int32_t bc_kind;  // SPH_BC_NONE / SPH_BC_VELOCITY / SPH_BC_PRESSURE
+    int32_t profile;  // velocity BC: SPH_PROFILE_*
+    float rho_rec;    // pressure BC: density of a recycled particle, fl32(rho0 + p_b / c0^2)
+    int32_t pad2_;
+    double bc_u;      // velocity BC: speed scale of the profile along X'
+    double bc_radius; // velocity BC: radius R of the parabolic profiles
 };
 
 }  // namespace sphbuf

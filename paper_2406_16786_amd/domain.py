@@ -88,6 +88,18 @@ class Domain:
     def update_fullscan_async(self) -> int:
         return S.sph_buffer_update_fullscan_async(self.ctx, self.p)
 
+    def set_fields(self, vel, rho: int = -1) -> None:
+        S.check(S.sph_set_fields(self.ctx, vel, rho), "sph_set_fields")
+
+    def set_bc(self, buffer_id: int, kind: int, **kw) -> None:
+        S.check(S.sph_buffer_set_bc(self.ctx, buffer_id, kind, **kw), "sph_buffer_set_bc")
+
+    def apply_bc(self) -> int:
+        return S.sph_buffer_apply_bc(self.ctx, self.p)
+
+    def rotate(self, buffer_id: int, center, m) -> int:
+        return S.sph_buffer_rotate(self.ctx, self.p, buffer_id, center, m)
+
     def result(self):
         return S.sph_last_result(self.ctx)
 

@@ -33,10 +33,13 @@ EXPORTED = (
     "sph_status_str", "sph_profile_enable", "sph_profile_read", "sph_grid_fit",
     "sph_batch_create", "sph_batch_destroy", "sph_batch_set_mode", "sph_batch_set_count_block",
     "sph_batch_step", "sph_batch_results", "sph_batch_tune",
+    "sph_set_fields", "sph_buffer_set_bc", "sph_buffer_apply_bc", "sph_buffer_rotate",
 )
 SPH_BATCH_KERNELS, SPH_BATCH_GRAPH = 0, 1
-SPH_NPHASE = 7
-PHASES = ("count", "scan", "scatter", "classify", "fullscan", "finalize", "build")
+SPH_NPHASE = 9
+PHASES = ("count", "scan", "scatter", "classify", "fullscan", "finalize", "build", "bc", "rotate")
+SPH_BC_NONE, SPH_BC_VELOCITY, SPH_BC_PRESSURE = 0, 1, 2
+SPH_PROFILE_PLUG, SPH_PROFILE_PARABOLIC_Y, SPH_PROFILE_PARABOLIC_R = 0, 1, 2
 
 
 class sph_particles(ctypes.Structure):
@@ -79,6 +82,22 @@ class sph_result(ctypes.Structure):
         ("n_after", ctypes.c_int64),
         ("next_id", ctypes.c_int64),
         ("n_labelled", ctypes.c_int64 * SPH_MAX_BUFFERS),
+    ]
+
+
+class sph_fields(ctypes.Structure):
+    _fields_ = [("vel", ctypes.c_int32 * 3), ("rho", ctypes.c_int32)]
+
+
+class sph_bc(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int32),
+        ("profile", ctypes.c_int32),
+        ("u", ctypes.c_double),
+        ("radius", ctypes.c_double),
+        ("p_b", ctypes.c_double),
+        ("rho0", ctypes.c_double),
+        ("c0", ctypes.c_double),
     ]
 
 
@@ -128,6 +147,10 @@ def lib() -> ctypes.CDLL:
                                ctypes.c_double),
             "sph_status_str": ([ctypes.c_int], ctypes.c_char_p),
             "sph_profile_enable": ([_VP, ctypes.c_int32], ctypes.c_int),
+            "sph_set_fields": ([_VP, ctypes.POINTER(sph_fields)], ctypes.c_int),
+            "sph_buffer_set_bc": ([_VP, ctypes.c_int32, ctypes.POINTER(sph_bc)], ctypes.c_int),
+            "sph_buffer_apply_bc": ([_VP, ctypes.POINTER(sph_particles)], ctypes.c_int),
+            "sph_buffer_rotate": ([_VP, ctypes.POINTER(sph_particles), ctypes.c_int32, _D, _D], ctypes.c_int),
             "sph_batch_create": ([ctypes.POINTER(_VP), ctypes.POINTER(sph_particles), ctypes.c_int32, _VP,
                                   ctypes.POINTER(_VP)], ctypes.c_int),
             "sph_batch_destroy": ([_VP], ctypes.c_int),
@@ -203,6 +226,34 @@ def sph_grid_fit(ctx: int, p: sph_particles) -> int:
 
 def sph_celllist_build(ctx: int, p: sph_particles) -> int:
     return lib().sph_celllist_build(ctx, ctypes.byref(p))
+
+
+def sph_set_fields(ctx: int, vel: Sequence[int], rho: int = -1) -> int:
+    f = sph_fields()
+    v = list(vel) + [-1] * (3 - len(vel))
+    for i in range(3):
+        f.vel[i] = int(v[i])
+    f.rho = int(rho)
+    return lib().sph_set_fields(ctx, ctypes.byref(f))
+
+
+def sph_buffer_set_bc(ctx: int, buffer_id: int, kind: int, profile: int = SPH_PROFILE_PLUG, u: float = 0.0,
+                      radius: float = 1.0, p_b: float = 0.0, rho0: float = 1.0, c0: float = 1.0) -> int:
+    b = sph_bc()
+    b.kind, b.profile = int(kind), int(profile)
+    b.u, b.radius, b.p_b, b.rho0, b.c0 = float(u), float(radius), float(p_b), float(rho0), float(c0)
+    return lib().sph_buffer_set_bc(ctx, int(buffer_id), ctypes.byref(b))
+
+
+def sph_buffer_apply_bc(ctx: int, p: sph_particles) -> int:
+    return lib().sph_buffer_apply_bc(ctx, ctypes.byref(p))
+
+
+def sph_buffer_rotate(ctx: int, p: sph_particles, buffer_id: int, center: Sequence[float], m) -> int:
+    c = np.zeros(3)
+    c[: len(center)] = center
+    mm = np.ascontiguousarray(m, dtype=np.float64).reshape(9)
+    return lib().sph_buffer_rotate(ctx, ctypes.byref(p), int(buffer_id), c.ctypes.data_as(_D), mm.ctypes.data_as(_D))
 
 
 def sph_buffer_identify(ctx: int, p: sph_particles, buffer_id: int = -1) -> int:

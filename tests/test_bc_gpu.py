@@ -1,0 +1,165 @@
+"""GPU parity of the in-/outlet boundary conditions (Section 4) and of rotating
+buffers (Section 5.3): the HIP library through its C ABI against the FP64 oracle,
+bit-exact on every array after every call."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from tests._gpu import assert_same_state, make_domain, upload_state
+from tests._support import make_state, oracle_buffers, oracle_state
+
+pytestmark = pytest.mark.gpu
+
+
+def _sph():
+    from paper_2406_16786_amd import sphbuf as S
+    return S
+
+
+def _set_bcs(d, bcs, fields):
+    S = _sph()
+    d.set_fields(list(fields.vel), fields.rho)
+    for k, bc in enumerate(bcs):
+        d.set_bc(k + 1, bc.kind, profile=bc.profile, u=bc.u, radius=bc.radius, p_b=bc.p_b, rho0=bc.rho0, c0=bc.c0)
+
+
+def _vipo_pipe():
+    wl = W.pipe3d(dp=0.004)
+    bcs = [oracle.BC(oracle.BC_VELOCITY, oracle.PROFILE_PARABOLIC_R, u=1.0, radius=0.05),
+           oracle.BC(oracle.BC_PRESSURE, p_b=25.0, rho0=1000.0, c0=10.0)]
+    return wl, bcs, oracle.Fields(vel=(0, 1, 2), rho=4)
+
+
+def _pivo_channel():
+    wl = W.channel2d()
+    bcs = [oracle.BC(oracle.BC_PRESSURE, p_b=50.0, rho0=1000.0, c0=10.0),
+           oracle.BC(oracle.BC_VELOCITY, oracle.PROFILE_PARABOLIC_Y, u=1.0, radius=0.2)]
+    return wl, bcs, oracle.Fields(vel=(0, 1), rho=3)
+
+
+@pytest.mark.parametrize("case", ["vipo_pipe3d", "pivo_channel2d"])
+def test_boundary_conditions_over_steps(case):
+    wl, bcs, fields = {"vipo_pipe3d": _vipo_pipe, "pivo_channel2d": _pivo_channel}[case]()
+    bufs = oracle_buffers(wl)
+    st = oracle_state(wl)
+    d = make_domain(wl, bufs, st)
+    _set_bcs(d, bcs, fields)
+    assert oracle.identify(bufs, st, -1)[0] == 0 and d.identify(-1) == 0
+    recycled_at_pressure = 0
+    for step in range(30):
+        W.advect_host(wl, st.pos, st.n, step)
+        upload_state(d, st)
+        d.build()
+        assert d.apply_bc() == oracle.apply_bc(bufs, bcs, fields, st) == 0
+        assert_same_state(d, st, f"step {step} boundary conditions")
+        gst, g, dl = d.update()
+        res = oracle.update(bufs, st, bcs, fields)
+        assert gst == res.status == 0, (step, gst, res.status)
+        eg, gg, dd = d.events()
+        np.testing.assert_array_equal(gg, res.gen)
+        np.testing.assert_array_equal(dd, res.dele)
+        assert_same_state(d, st, f"step {step} update")
+        if bcs[0].kind == oracle.BC_PRESSURE:
+            rho = np.float32(bcs[0].rho0 + bcs[0].p_b / (bcs[0].c0 * bcs[0].c0))
+            recycled_at_pressure += int(np.sum(st.carried[fields.rho][: st.n] == rho))
+    if bcs[0].kind == oracle.BC_PRESSURE:
+        assert recycled_at_pressure > 0
+    d.close()
+
+
+def test_sprinkler_rotating_inlet():
+    """Section 5.3: generate at the turning inlet, impose its velocity profile,
+    move every particle with its own velocity, turn the buffer by omega dt."""
+    wl = W.sprinkler2d(n_background=3000)
+    bufs = oracle_buffers(wl)
+    bcs = [oracle.BC(oracle.BC_VELOCITY, oracle.PROFILE_PARABOLIC_Y, u=wl.bc_u, radius=wl.bc_radius)]
+    fields = oracle.Fields(vel=(0, 1), rho=3)
+    st = oracle_state(wl)
+    d = make_domain(wl, bufs, st)
+    _set_bcs(d, bcs, fields)
+    assert oracle.identify(bufs, st, -1)[0] == 0 and d.identify(-1) == 0
+    m = W.rotation_z(wl.omega * wl.dt)
+    generated = 0
+    for step in range(120):
+        d.build()
+        gst, g, dl = d.update()
+        res = oracle.update(bufs, st, bcs, fields)
+        assert gst == res.status == 0, (step, gst, res.status)
+        np.testing.assert_array_equal(d.events()[1], res.gen)
+        generated += g
+        d.build()
+        assert d.apply_bc() == oracle.apply_bc(bufs, bcs, fields, st) == 0
+        W.advect_carried(wl, st.pos, st.carried, st.n)
+        upload_state(d, st)
+        d.build()
+        assert d.rotate(1, (0.0, 0.0), m) == oracle.rotate_buffer(bufs, 1, (0.0, 0.0), m, fields, st) == 0
+        if step % 10 == 0 or step == 119:
+            assert_same_state(d, st, f"step {step}")
+    assert generated > 200
+    # the inlet turned by omega * t: its axis now points at that angle
+    ang = math.atan2(bufs[0].rot[0][1], bufs[0].rot[0][0])
+    assert abs(ang - wl.omega * wl.dt * 120) < 1e-9
+    d.close()
+
+
+def test_apply_bc_reports_buffer_particles_outside_the_check_region():
+    I3 = np.eye(3)
+    bufs = [oracle.Buffer(oracle.INLET, (0.5, 0.5, 0), I3, (0.5, 0.5, 0), 0.25)]
+    bcs = [oracle.BC(oracle.BC_VELOCITY, oracle.PROFILE_PARABOLIC_Y, u=2.0, radius=0.5)]
+    fields = oracle.Fields(vel=(0, 1), rho=2)
+    st = make_state(2, [(0.25, 0.5), (0.75, 0.25), (2.5, 0.5), (3.0, 0.5)], labels=[1, 1, 1, 0], carried=3)
+    from tests.test_parity_gpu import _Raw, _identify_counts
+    d = make_domain(_Raw(), bufs, st)
+    _set_bcs(d, bcs, fields)
+    _identify_counts(d, bufs, st)
+    d.build()
+    S = _sph()
+    assert d.apply_bc() == oracle.apply_bc(bufs, bcs, fields, st) == S.SPH_ERR_CFL
+    assert_same_state(d, st, "cfl")
+    d.close()
+
+
+def test_rotation_into_another_buffer_is_refused():
+    I3 = np.eye(3)
+    bufs = [oracle.Buffer(oracle.INLET, (0.5, 0.5, 0), I3, (0.5, 0.5, 0), 0.25),
+            oracle.Buffer(oracle.OUTLET, (4.5, 0.5, 0), I3, (0.5, 0.5, 0), 0.25)]
+    st = make_state(2, [(0.25, 0.5), (4.5, 0.5)], labels=[1, 2], carried=3)
+    from tests.test_parity_gpu import _Raw, _identify_counts
+    d = make_domain(_Raw(), bufs, st)
+    d.set_fields([0, 1], 2)
+    _identify_counts(d, bufs, st)
+    d.build()
+    S = _sph()
+    half_turn = np.array([[-1.0, 0, 0], [0, -1.0, 0], [0, 0, 1.0]])
+    assert d.rotate(1, (2.5, 0.5), half_turn) == S.SPH_ERR_OVERLAP
+    assert_same_state(d, st, "refused turn")
+    # a turn that keeps clear of the outlet is fine, and a non-rotation is refused
+    assert d.rotate(1, (0.5, 0.5), W.rotation_z(0.3)) == 0
+    d.build()
+    assert d.rotate(1, (0.5, 0.5), np.diag([1.0, 2.0, 1.0])) == S.SPH_ERR_ROTATION
+    d.close()
+
+
+def test_boundary_calls_need_a_current_cell_list_and_fields():
+    wl, bcs, fields = _pivo_channel()
+    bufs = oracle_buffers(wl)
+    st = oracle_state(wl)
+    d = make_domain(wl, bufs, st)
+    S = _sph()
+    d.build()
+    assert d.apply_bc() == S.SPH_ERR_ARG            # no velocity fields yet
+    _set_bcs(d, bcs, fields)
+    assert d.identify(-1) == 0
+    d.build()
+    gst, _, _ = d.update()
+    assert gst == 0
+    assert d.apply_bc() == S.SPH_ERR_STATE           # positions changed since the build
+    assert d.rotate(1, (0.0, 0.0), np.eye(3)) == S.SPH_ERR_STATE
+    assert S.sph_buffer_set_bc(d.ctx, 1, S.SPH_BC_PRESSURE, c0=0.0) == S.SPH_ERR_ARG
+    assert S.sph_buffer_set_bc(d.ctx, 2, S.SPH_BC_VELOCITY, profile=S.SPH_PROFILE_PARABOLIC_Y, radius=-1.0) == \
+        S.SPH_ERR_ARG
+    assert S.sph_buffer_set_bc(d.ctx, 3, S.SPH_BC_NONE) == S.SPH_ERR_ARG
+    d.close()

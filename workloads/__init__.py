@@ -301,6 +301,55 @@ def pipe3d(seed: int = 3, dp: float = 0.001, capacity_extra: Optional[int] = Non
                     0.25 * dp, 500, 3000, velocity, 1.0)
 
 
+# ------------------------------------------------------------ sprinkler ---
+
+def sprinkler2d(seed: int = 8, dp: float = 0.002, arm: float = 0.1, radius: float = 0.02,
+                omega: float = 2.0, n_background: int = 0, capacity: int = 200_000) -> Workload:
+    """2-D rotating sprinkler (stand-in for the lawn sprinkler of Section 5.3): a
+    velocity inlet of half-width R = 0.02 (profile 2500 (0.02^2 - y'^2), i.e.
+    u = 1 m/s on the axis) at the end of an arm of length ``arm`` from the pivot
+    (0, 0), pointing radially outward and turning at omega = 2 rad/s.  The buffer
+    starts filled with a jittered lattice (4 layers); ``n_background`` optional
+    resting particles are scattered over the lawn.  Particles move with their own
+    (carried) velocity; dt = 0.25 dp / u."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    a = 4 * dp
+    ny = int(round(2 * radius / dp))
+    ii, jj = np.meshgrid(np.arange(4), np.arange(ny), indexing="xy")
+    idx = np.stack([ii.ravel(), jj.ravel()], axis=1)
+    loc = np.stack([-a / 2 + (idx[:, 0] + 0.5) * dp, -radius + (idx[:, 1] + 0.5) * dp], axis=1)
+    loc = loc + _jitter(rng, loc.shape[0], 2, dp, amp=0.2)
+    pts = loc + np.array([arm, 0.0])
+    extent = 0.6
+    if n_background:
+        bg = rng.uniform(-extent, extent, size=(n_background, 2))
+        bg = bg[np.hypot(bg[:, 0], bg[:, 1]) > arm + 3 * a]
+        pts = np.concatenate([pts, bg])
+    n = pts.shape[0]
+    pos, carried, names, label, ids = _alloc(2, n, capacity, pts, dp)
+    cs = 2.6 * dp
+    bufs = [BufferSpec(INLET, (arm, 0.0, 0.0), (1.0, 0.0, 0.0), (a / 2, radius, 0.0), cs, angle=0.0)]
+    m = 2 * cs
+    wl = Workload("sprinkler2d", 2, dp, cs, (-extent - m, -extent - m, 0.0), (extent + m, extent + m, 0.0),
+                  n, capacity, pos, carried, names, label, ids, bufs, 0.25 * dp / 1.0, 400, 8000, None, 0.0)
+    wl.omega = omega
+    wl.bc_u, wl.bc_radius = 1.0, radius
+    return wl
+
+
+def rotation_z(theta: float) -> np.ndarray:
+    """Anticlockwise turn by theta about the z axis (row-major 3x3)."""
+    c, s = math.cos(theta), math.sin(theta)
+    return np.array([[c, -s, 0.0], [s, c, 0.0], [0.0, 0.0, 1.0]])
+
+
+def advect_carried(wl: Workload, pos: Sequence[np.ndarray], carried: Sequence[np.ndarray], n: int) -> None:
+    """x <- fl32(x + fl32(v dt)) with each particle's own carried velocity."""
+    for c in range(wl.dim):
+        du = (carried[c][:n].astype(np.float64) * wl.dt).astype(np.float32)
+        pos[c][:n] = (pos[c][:n] + du).astype(np.float32)
+
+
 # -------------------------------------------------------------- helpers ---
 
 def noise_for_step(wl: Workload, step: int, n: int) -> np.ndarray:
