@@ -86,6 +86,53 @@ def phase_bytes(dim: int, n: int, n_cells: int, cand: int, g: int, d: int, n_car
     }
 
 
+def sprinkler_leg(torch, np, S, W, Domain, log, steps: int = 40):
+    """Rotating sprinkler (2-D) on a lawn of 2 M resting particles: per step the
+    cell list, the update at the turning inlet, its velocity profile, the move of
+    every particle with its own velocity and the turn of the buffer."""
+    wl = W.sprinkler2d(n_background=2_000_000, capacity=2_200_000)
+    d = Domain(wl.dim, wl.lo, wl.hi, wl.cell_size, wl.dp, wl.capacity, wl.pos, wl.carried, wl.label, wl.id,
+               wl.n, wl.n, max_events=S.SPH_MAX_EVENTS_LIMIT)
+    b = wl.buffers[0]
+    d.define(b.kind, b.origin, rotation_of(S, b, 2), b.half, b.margin)
+    d.set_fields([0, 1], 3)
+    d.set_bc(1, S.SPH_BC_VELOCITY, profile=S.SPH_PROFILE_PARABOLIC_Y, u=wl.bc_u, radius=wl.bc_radius)
+    S.check(d.identify(-1), "identify")
+    m = W.rotation_z(wl.omega * wl.dt)
+    stream = d.stream
+
+    def step():
+        d.build()
+        S.check(d.update_async(), "update")
+        d.build()
+        S.check(d.apply_bc(), "apply_bc")
+        n = d.n()
+        with torch.cuda.stream(stream):
+            for c in range(2):
+                d.pos[c][:n].add_(d.carried[c][:n] * wl.dt)
+        d.build()
+        S.check(d.rotate(1, (0.0, 0.0), m), "rotate")
+
+    for _ in range(5):
+        step()
+    torch.cuda.synchronize()
+    S.check(S.sph_profile_enable(d.ctx, True), "profile")
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    st, pms, pn = S.sph_profile_read(d.ctx, reset=True)
+    ph = {S.PHASES[i]: float(pms[i]) / max(1, int(pn[i])) * 1e3 for i in range(S.SPH_NPHASE) if pn[i] > 0}
+    n = d.n()
+    d.close()
+    log(f"sprinkler: N = {n}, rotate {ph.get('rotate', 0):.1f} us, bc {ph.get('bc', 0):.1f} us, "
+        f"wall {wall * 1e3:.2f} ms/step (with host syncs)")
+    return {"n_particles": n, "steps": steps, "rotate_us": round(ph.get("rotate", 0.0), 2),
+            "apply_bc_us": round(ph.get("bc", 0.0), 2), "phases_us": {k: round(v, 2) for k, v in ph.items()},
+            "wall_ms_per_step": round(wall * 1e3, 3)}
+
+
 def batch_leg(torch, np, S, W, Domain, steps: int, warmup: int, log):
     """64 hub-and-spoke domains: batched step (autotuned launch mode, graph replay)
     against a per-domain loop of plain launches, on the same prepared states."""
@@ -219,6 +266,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile-pass", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-domain batched leg")
+    ap.add_argument("--no-bc", action="store_true", help="skip the boundary-condition leg")
+    ap.add_argument("--no-sprinkler", action="store_true", help="skip the rotating-sprinkler leg")
     ap.add_argument("--build", default=None, choices=["split", "fused"],
                     help="cell-list build variant (default: the library's)")
     args = ap.parse_args()
@@ -434,6 +483,30 @@ def main() -> int:
         out["phases_us"] = {k: round(v[0] * 1e3, 2) for k, v in prof_local.items()}
     if prof_full:
         out["fullscan_phases_us"] = {k: round(v[0] * 1e3, 2) for k, v in prof_full.items()}
+
+    # ---- boundary conditions on the same states: velocity inlet, pressure outlet ----
+    if not args.no_bc and wl.dim == 3:
+        S.check(S.sph_set_fields(dom.ctx, [0, 1, 2], 4), "fields")
+        S.check(S.sph_buffer_set_bc(dom.ctx, 1, S.SPH_BC_VELOCITY, profile=S.SPH_PROFILE_PARABOLIC_R, u=1.0,
+                                    radius=0.05), "bc inlet")
+        S.check(S.sph_buffer_set_bc(dom.ctx, 2, S.SPH_BC_PRESSURE, p_b=0.0, rho0=1000.0, c0=10.0), "bc outlet")
+        reset_work()
+        S.check(S.sph_profile_enable(dom.ctx, True), "profile")
+        for s in range(Wm, Wm + K):
+            S.check(S.sph_state_set(dom.ctx, *states[s]), "state_set")
+            S.sph_celllist_build(dom.ctx, parts[s])
+            S.check(S.sph_buffer_apply_bc(dom.ctx, parts[s]), "apply_bc")
+        st_, pms, pn = S.sph_profile_read(dom.ctx, reset=True)
+        S.check(S.sph_profile_enable(dom.ctx, False), "profile")
+        bc_us = float(pms[S.PHASES.index("bc")]) / max(1, int(pn[S.PHASES.index("bc")])) * 1e3
+        n_buf = int(sum(states[Wm][1][:2]))
+        out["boundary_conditions"] = {
+            "apply_bc_us": round(bc_us, 2), "buffer_particles": n_buf,
+            "what": "velocity inlet (pipe profile) + pressure outlet (normal projection) on the labelled particles, "
+                    "one kernel over the local cells"}
+        log(f"apply_bc {bc_us:.1f} us on {n_buf} buffer particles")
+    if not args.no_sprinkler:
+        out["sprinkler"] = sprinkler_leg(torch, np, S, W, Domain, log)
 
     # ---- many domains: batched step against a per-domain launch loop ----
     if not args.no_batch:
