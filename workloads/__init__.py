@@ -322,7 +322,13 @@ def sprinkler2d(seed: int = 8, dp: float = 0.002, arm: float = 0.1, radius: floa
     pts = loc + np.array([arm, 0.0])
     extent = 0.6
     if n_background:
-        bg = rng.uniform(-extent, extent, size=(n_background, 2))
+        # resting particles on a jittered lattice over the lawn, in lattice order,
+        # clear of the circle the turning buffer sweeps
+        h = 2 * extent / math.sqrt(n_background)
+        m_ = int(2 * extent / h)
+        gi, gj = np.meshgrid(np.arange(m_), np.arange(m_), indexing="xy")
+        bg = np.stack([-extent + (gi.ravel() + 0.5) * h, -extent + (gj.ravel() + 0.5) * h], axis=1)
+        bg = bg + rng.uniform(-0.3 * h, 0.3 * h, size=bg.shape)
         bg = bg[np.hypot(bg[:, 0], bg[:, 1]) > arm + 3 * a]
         pts = np.concatenate([pts, bg])
     n = pts.shape[0]
