@@ -341,6 +341,52 @@ def test_clustered_event_indices(n, mode):
     d.close()
 
 
+def _misalign(d):
+    """Move the domain's coordinate and carried arrays 4 bytes off 16-byte alignment
+    (views into one-longer allocations): the kernels must take their scalar paths."""
+    import torch
+    from paper_2406_16786_amd import sphbuf as S
+    for name in ("pos", "carried"):
+        views = []
+        for t in getattr(d, name):
+            big = torch.zeros(t.shape[0] + 1, dtype=t.dtype, device=t.device)
+            v = big[1:]
+            v.copy_(t)
+            views.append(v)
+        setattr(d, name, views)
+    assert d.pos[0].data_ptr() % 16 != 0
+    d.p = S.particles_from_tensors(d.pos, d.carried, d.label, d.id, d.n_dev)
+
+
+@pytest.mark.parametrize("mode", ["local", "fullscan"])
+def test_unaligned_arrays_take_the_scalar_paths(mode):
+    wl = W.bent_channel2d()
+    bufs = oracle_buffers(wl)
+    st = oracle_state(wl)
+    d = make_domain(wl, bufs, st)
+    _misalign(d)
+    assert oracle.identify(bufs, st, -1)[0] == 0 and d.identify(-1) == 0
+    for step in range(12):
+        W.advect_host(wl, st.pos, st.n, step)
+        upload_state(d, st)
+        if mode == "local":
+            d.build()
+            if step == 0:
+                cs, ci, dims = _cell_list(d, st.n)
+                ocs, oci = oracle.cell_list(2, np.float32(wl.lo[:2]), np.float32(1.0 / wl.cell_size), dims[:2],
+                                            st.pos[0][: st.n], st.pos[1][: st.n], None)
+                np.testing.assert_array_equal(cs, ocs)
+            gst, g, dl = d.update()
+        else:
+            gst, g, dl = d.update_fullscan()
+        res = oracle.update(bufs, st)
+        assert gst == res.status == 0
+        np.testing.assert_array_equal(d.events()[1], res.gen)
+        np.testing.assert_array_equal(d.events()[2], res.dele)
+        assert_same_state(d, st, f"step {step}")
+    d.close()
+
+
 # ---------------------------------------------------------------- guard band ---
 
 @pytest.mark.parametrize("dim", [2, 3])
