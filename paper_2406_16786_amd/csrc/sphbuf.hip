@@ -299,9 +299,11 @@ __device__ __forceinline__ void block_counts_store(const EventArgs &e, const uns
 // recycled position r - a d (FP64, rounded to FP32): nothing of the caller's
 // arrays is written here, so a failed status check can still leave them
 // untouched, and the finalize step has no random reads left to do.
+template <bool kPrefetched>  // carried fields already in carv, or loaded here
 __device__ __forceinline__ void emit(const EventArgs &e, const Parts &p, const BufDev &b, int k, int seg,
                                      bool valid, int64_t i, int lab, const Outcome &o, float x, float y, float z,
-                                     unsigned long long &found, unsigned long long &post) {
+                                     const float (&carv)[SPH_MAX_CARRIED], unsigned long long &found,
+                                     unsigned long long &post) {
     const bool in = valid && o.newlab >= 0;
     if (in && o.mine) found++;
     if (in && o.ev != kEvDel && o.newlab == k + 1) post++;
@@ -330,11 +332,24 @@ __device__ __forceinline__ void emit(const EventArgs &e, const Parts &p, const B
                 d[c] = r[c];
                 e.gen_new[4 * ev + c] = (float)((double)r[c] - b.shift[c]);
             }
-            for (int f = 0; f < p.nc; ++f) d[3 + f] = p.car[f][i];
+            float rho = 0.0f;
+            if constexpr (kPrefetched) {
+#pragma unroll
+                for (int f = 0; f < SPH_MAX_CARRIED; ++f) {
+                    if (f >= p.nc) continue;
+                    d[3 + f] = carv[f];
+                    if (f == e.rho_field) rho = carv[f];
+                }
+            } else {
+                for (int f = 0; f < p.nc; ++f) {
+                    const float v = p.car[f][i];
+                    d[3 + f] = v;
+                    if (f == e.rho_field) rho = v;
+                }
+            }
             // density of the recycled particle: the boundary value at a pressure
             // boundary (Eq. postulate-density), otherwise unchanged
-            if (e.rho_field >= 0)
-                e.gen_new[4 * ev + 3] = b.bc_kind == SPH_BC_PRESSURE ? b.rho_rec : d[3 + e.rho_field];
+            if (e.rho_field >= 0) e.gen_new[4 * ev + 3] = b.bc_kind == SPH_BC_PRESSURE ? b.rho_rec : rho;
         }
     }
     if (pd) {
@@ -943,16 +958,24 @@ __device__ __forceinline__ void classify_body(const LocalArgs &a, const int vb, 
             const bool valid = j < j1 && i < N;  // a list older than the live count cannot index past it
             int lab = 0;
             float x = 0.0f, y = 0.0f, z = 0.0f;
+            float carv[SPH_MAX_CARRIED];
             Outcome o{kEvNone, -1, false};
             if (valid) {
                 x = a.p.pos[0][i];
                 y = a.p.pos[1][i];
                 z = dim == 3 ? a.p.pos[2][i] : 0.0f;
                 lab = a.p.label[i];  // loaded with the position: one dependent round trip less
+                // carried fields too, where a duplicate may be made: its payload is then
+                // in registers when the event slot comes back
+                if (b.kind != SPH_OUTLET) {
+#pragma unroll
+                    for (int f = 0; f < SPH_MAX_CARRIED; ++f)
+                        if (f < a.p.nc) carv[f] = a.p.car[f][i];
+                }
                 const unsigned bits = classify(b, dim, x, y, z);
                 if (bits & kIn) o = decide(b, k, dim, bits, lab, x, y, z);
             }
-            emit(a.e, a.p, b, k, seg, valid, i, lab, o, x, y, z, found, post);
+            emit<true>(a.e, a.p, b, k, seg, valid, i, lab, o, x, y, z, carv, found, post);
         }
         block_counts_add(s_cnt, k, found, post);
     }
@@ -1034,7 +1057,8 @@ __global__ __launch_bounds__(kClassifyBlock) void k_classify_full(FullArgs a) {
                     o = decide(sb[k], k, dim, bits, lab, x, y, z);
                 }
                 unsigned long long found = 0, post = 0;
-                emit(a.e, a.p, sb[k], k, seg, valid, i, lab, o, x, y, z, found, post);
+                const float none[SPH_MAX_CARRIED] = {};
+                emit<false>(a.e, a.p, sb[k], k, seg, valid, i, lab, o, x, y, z, none, found, post);
                 block_counts_add(s_cnt, k, found, post);
             }
         }
@@ -1301,6 +1325,7 @@ __device__ __forceinline__ void finalize_body(const FinArgs &a, const int fb, co
         unsigned g0, g1, r0, r1;
         share_of(G, fb, nfb, g0, g1);
         share_of(R, fb, nfb, r0, r1);
+        uint32_t mn0 = 0xffffffffu, mx0 = 0u, mn1 = 0xffffffffu, mx1 = 0u;  // key ranges, for the sort
         for (unsigned e = tid; e < G; e += bd) {
             const int g = seg_of(s_off[0], e);
             const unsigned ev = (unsigned)g * cap + (e - s_off[0][g]);
@@ -1312,6 +1337,8 @@ __device__ __forceinline__ void finalize_body(const FinArgs &a, const int fb, co
             const uint32_t i = a.e.gen_idx[ev];
             s_k[0][0][e] = i;
             s_v[0][e] = ev;
+            mn0 = min(mn0, i);
+            mx0 = max(mx0, i);
             if ((long long)i >= Np) {
                 atomicOr(&s_map[i - Np], ev + 1u);
             } else if (mine) {
@@ -1323,6 +1350,8 @@ __device__ __forceinline__ void finalize_body(const FinArgs &a, const int fb, co
             const int g = seg_of(s_off[1], e);
             const uint32_t i = a.e.del_idx[(size_t)g * cap + (e - s_off[1][g])];
             s_k[1][0][e] = i;
+            mn1 = min(mn1, i);
+            mx1 = max(mx1, i);
             if ((long long)i >= Np) atomicOr(&s_bits[(i - Np) >> 5], 1u << ((i - Np) & 31));
         }
         for (unsigned q = tid; q < R; q += bd) {
@@ -1331,7 +1360,23 @@ __device__ __forceinline__ void finalize_body(const FinArgs &a, const int fb, co
             const long long i = (long long)(v >> 32);
             const uint32_t lab = (uint32_t)(v & 0xffffffffull);
             if (i >= Np) atomicOr(&s_map[i - Np], (lab + 1u) << kMapRelShift);
-            else if (q >= r0 && q < r1) p.label[i] = (int32_t)lab;
+            else if (q >= r0 && q < r1) p.label[i] = (int32_t)lab;  // in place, this block's share
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            mn0 = min(mn0, (uint32_t)__shfl_xor(mn0, off));
+            mx0 = max(mx0, (uint32_t)__shfl_xor(mx0, off));
+            mn1 = min(mn1, (uint32_t)__shfl_xor(mn1, off));
+            mx1 = max(mx1, (uint32_t)__shfl_xor(mx1, off));
+        }
+        if ((tid & (kWave - 1)) == 0) {
+            if (mx0 >= mn0) {
+                atomicMin(&s_mm[0][0], mn0);
+                atomicMax(&s_mm[0][1], mx0);
+            }
+            if (mx1 >= mn1) {
+                atomicMin(&s_mm[1][0], mn1);
+                atomicMax(&s_mm[1][1], mx1);
+            }
         }
         __syncthreads();
         // ---- sort both lists.  Counting sort into kSortBuckets buckets over each
@@ -1354,32 +1399,6 @@ __device__ __forceinline__ void finalize_body(const FinArgs &a, const int fb, co
             if (w0 < nw) s_wpre[w0] = excl;
             if (w1 < nw) s_wpre[w1] = excl + c0;
         }
-        {   // key range of each list
-            uint32_t mn[2] = {0xffffffffu, 0xffffffffu}, mx[2] = {0u, 0u};
-#pragma unroll
-            for (int l = 0; l < 2; ++l)
-#pragma unroll
-                for (int q = 0; q < kPer; ++q) {
-                    const unsigned e = (unsigned)q * kFinBlock + tid;
-                    if (e < nl[l]) {
-                        const uint32_t k = s_k[l][0][e];
-                        mn[l] = min(mn[l], k);
-                        mx[l] = max(mx[l], k);
-                    }
-                }
-#pragma unroll
-            for (int l = 0; l < 2; ++l) {
-                for (int off = 32; off > 0; off >>= 1) {
-                    mn[l] = min(mn[l], (uint32_t)__shfl_xor(mn[l], off));
-                    mx[l] = max(mx[l], (uint32_t)__shfl_xor(mx[l], off));
-                }
-                if ((tid & (kWave - 1)) == 0 && nl[l] > 0) {
-                    atomicMin(&s_mm[l][0], mn[l]);
-                    atomicMax(&s_mm[l][1], mx[l]);
-                }
-            }
-        }
-        __syncthreads();
         unsigned shift[2];
 #pragma unroll
         for (int l = 0; l < 2; ++l) {
