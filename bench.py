@@ -478,13 +478,15 @@ def main() -> int:
         # the paper's framing: the solver rebuilds the cell list every step anyway, so the
         # update with local cells (classify + finalize) against the all-particle update
         # (full classify + finalize)
-        t_upd_full = prof_full["fullscan"][0] + prof_full["finalize"][0] if prof_full else None
+        t_upd_full = (prof_full["fullscan"][0] + prof_full.get("candidates", (0.0, 0))[0] + prof_full["finalize"][0]
+                      if prof_full else None)
         out["local_update_only"] = {
             "ms": round(t_upd_local, 5),
             "Mparticles_per_s": round(n_mean / (t_upd_local * 1e-3) / 1e6, 1),
             "fullscan_update_ms": round(t_upd_full, 5) if t_upd_full else None,
             "speedup_vs_fullscan": round(t_upd_full / t_upd_local, 2) if t_upd_full else None,
-            "speedup_classify_vs_fullscan": round(prof_full["fullscan"][0] / prof_local["classify"][0], 2)
+            "speedup_classify_vs_fullscan": round((prof_full["fullscan"][0] + prof_full.get("candidates", (0.0, 0))[0])
+                                                  / prof_local["classify"][0], 2)
             if prof_full and "classify" in prof_local else None}
     if prof_local:
         out["phases_us"] = {k: round(v[0] * 1e3, 2) for k, v in prof_local.items()}

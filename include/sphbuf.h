@@ -249,12 +249,13 @@ typedef enum {
     SPH_PHASE_SCAN = 1,       /* exclusive scan of the cell counts                */
     SPH_PHASE_SCATTER = 2,    /* particle indices into cell order                 */
     SPH_PHASE_CLASSIFY = 3,   /* local-cell candidates, frame, crossing tests     */
-    SPH_PHASE_FULLSCAN = 4,   /* every particle against every buffer (baseline)   */
+    SPH_PHASE_FULLSCAN = 4,   /* full scan: every particle, FP32 filter (baseline)*/
     SPH_PHASE_FINALIZE = 5,   /* status, sort, duplicate/recycle/relabel/compact  */
     SPH_PHASE_BUILD = 6,      /* count + scan + scatter in one cooperative launch */
     SPH_PHASE_BC = 7,         /* boundary conditions on buffer particles          */
     SPH_PHASE_ROTATE = 8,     /* rigid turn of a buffer's particles               */
-    SPH_NPHASE = 9
+    SPH_PHASE_CANDIDATES = 9, /* full scan: the filter's candidates, exact tests  */
+    SPH_NPHASE = 10
 } sph_phase;
 
 /* When on, every kernel launch of the context is bracketed by two HIP events on

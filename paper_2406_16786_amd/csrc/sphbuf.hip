@@ -98,6 +98,8 @@ struct Ctl {
     unsigned int bar_gen;          // grid barrier generation
     unsigned int fin_ticket;       // finalize blocks that have read the counters
     unsigned int bc_status;        // outcome of the last boundary-condition or rotation pass
+    unsigned int cand_overflow;    // the full scan's candidate list overflowed (consumed by its finalize)
+    unsigned long long cand_count; // candidates appended by the full scan's filter
     long long next_id;
     long long n_labelled[16];
     unsigned int ident_bad;
@@ -987,35 +989,59 @@ __global__ __launch_bounds__(kClassifyBlock) void k_classify_local(LocalArgs a) 
     classify_body(a, blockIdx.x, gridDim.x);
 }
 
-constexpr int kFullVec = 4;  // particles per thread per step of the full scan (a multiple of 4)
+// ----------------------------------------------------- K1f full scan (baseline) --
+//
+// Two launches.  The filter tests every particle against every buffer's check
+// region in FP32, widened by the guard band so that no member can be missed, and
+// appends the candidates (index, buffer) to one list (one atomic per block).
+// The candidate pass then takes each through the same exact test, decision and
+// emission as the local classify.
+
+constexpr int kFullVec = 4;  // particles per thread per step of the filter (a multiple of 4)
+constexpr int64_t kCandSlack = 4096;  // candidate list: capacity + this many entries
+constexpr int kCandBlocks = 2048;     // grid of the candidate pass (grid-stride over the list)
 
 struct FullArgs {
     Parts p;
     const BufDev *bufs;
     int nb;
     EventArgs e;
-    int vec;  // positions 16-byte aligned: vector loads allowed
+    unsigned long long *cand;  // (index << 4) | buffer
+    int64_t cap_cand;
+    int vec;                   // positions 16-byte aligned: vector loads allowed
 };
 
-__global__ __launch_bounds__(kClassifyBlock) void k_classify_full(FullArgs a) {
+// FP32 check-region test widened by the guard band: true for every member of C_k.
+__device__ __forceinline__ bool near_region(const BufDev &b, int dim, float x, float y, float z) {
+    const float d0 = (x - b.ohi[0]) - b.olo[0];
+    const float d1 = (y - b.ohi[1]) - b.olo[1];
+    const float d2 = dim == 3 ? (z - b.ohi[2]) - b.olo[2] : 0.0f;
+    if (d0 * d0 + d1 * d1 + d2 * d2 > b.rsq) return false;
+    const float l0 = b.qf[0] * d0 + b.qf[1] * d1 + b.qf[2] * d2;
+    const float l1 = b.qf[3] * d0 + b.qf[4] * d1 + b.qf[5] * d2;
+    const float l2 = b.qf[6] * d0 + b.qf[7] * d1 + b.qf[8] * d2;
+    const float g = b.guard;
+    return fabsf(l0) < b.thrf[3] + g && fabsf(l1) < b.thrf[4] + g && (dim == 2 || fabsf(l2) < b.thrf[5] + g);
+}
+
+__global__ __launch_bounds__(kClassifyBlock) void k_filter_full(FullArgs a) {
     __shared__ BufDev sb[SPH_MAX_BUFFERS];
-    __shared__ unsigned s_cnt[2 * SPH_MAX_BUFFERS];
+    __shared__ unsigned s_wtot[kClassifyBlock / kWave];
+    __shared__ unsigned long long s_base;
     for (int t = threadIdx.x; t < a.nb * (int)(sizeof(BufDev) / 4); t += blockDim.x)
         reinterpret_cast<uint32_t *>(sb)[t] = reinterpret_cast<const uint32_t *>(a.bufs)[t];
-    block_counts_init(s_cnt);
     __syncthreads();
     const int64_t N = live_count(a.p.n_dev, a.p.capacity);
-    const int lane = threadIdx.x & (kWave - 1);
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     const int dim = a.p.dim;
     const int lb = logical_block();
-    const int seg = (lb * (int)(blockDim.x / kWave) + (int)(threadIdx.x / kWave)) % kSeg;
-    constexpr int kVec = kFullVec;  // particles per thread per step: 16-byte loads per coordinate
+    constexpr int kVec = kFullVec;
     const int64_t quant = (int64_t)blockDim.x * kVec;
     const int64_t per = ((N + gridDim.x - 1) / gridDim.x + quant - 1) / quant * quant;
     const int64_t s0 = (int64_t)lb * per;
     const int64_t s1 = min(N, s0 + per);
     bool bad = false;
-    for (int64_t base = s0; base < s1; base += quant) {
+    for (int64_t base = s0; base < s1; base += quant) {  // block-uniform trip count
         const int64_t i0 = base + (int64_t)kVec * threadIdx.x;
         float px[kVec], py[kVec], pz[kVec];
         if (a.vec && i0 + kVec <= s1) {
@@ -1041,29 +1067,88 @@ __global__ __launch_bounds__(kClassifyBlock) void k_classify_full(FullArgs a) {
                 pz[c] = ok && dim == 3 ? a.p.pos[2][i0 + c] : 0.0f;
             }
         }
+        // candidate bits: bit c * 16 + k for particle c of this lane and buffer k
+        unsigned long long bits = 0ull;
+        unsigned mine = 0;
 #pragma unroll
         for (int c = 0; c < kVec; ++c) {
-            const int64_t i = i0 + c;
-            const bool valid = i < s1;
-            const float x = px[c], y = py[c], z = pz[c];
-            if (valid) bad |= !(isfinite(x) && isfinite(y) && isfinite(z));
-            for (int k = 0; k < a.nb; ++k) {
-                const unsigned bits = valid ? classify(sb[k], dim, x, y, z) : 0u;
-                if (__ballot(bits & kIn) == 0ull) continue;
-                int lab = 0;
-                Outcome o{kEvNone, -1, false};
-                if (bits & kIn) {
-                    lab = a.p.label[i];
-                    o = decide(sb[k], k, dim, bits, lab, x, y, z);
+            if (i0 + c >= s1) continue;
+            bad |= !(isfinite(px[c]) && isfinite(py[c]) && isfinite(pz[c]));
+            for (int k = 0; k < a.nb; ++k)
+                if (near_region(sb[k], dim, px[c], py[c], pz[c])) {
+                    bits |= 1ull << (16 * c + k);
+                    ++mine;
                 }
-                unsigned long long found = 0, post = 0;
-                const float none[SPH_MAX_CARRIED] = {};
-                emit<false>(a.e, a.p, sb[k], k, seg, valid, i, lab, o, x, y, z, none, found, post);
-                block_counts_add(s_cnt, k, found, post);
-            }
         }
+        unsigned incl = mine;  // lane prefix of the candidate counts
+        for (int off = 1; off < kWave; off <<= 1) {
+            const unsigned t = __shfl_up(incl, off);
+            if (lane >= off) incl += t;
+        }
+        if (lane == kWave - 1) s_wtot[wave] = incl;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned tot = 0;
+            for (int w = 0; w < (int)(blockDim.x / kWave); ++w) tot += s_wtot[w];
+            s_base = tot ? atomicAdd(&a.e.ctl->cand_count, (unsigned long long)tot) : 0ull;
+        }
+        __syncthreads();
+        unsigned long long at = s_base + (incl - mine);
+        for (int w = 0; w < wave; ++w) at += s_wtot[w];
+        while (bits) {
+            const int bit = __ffsll((long long)bits) - 1;
+            bits &= bits - 1ull;
+            if (at < (unsigned long long)a.cap_cand)
+                a.cand[at] = ((unsigned long long)(i0 + bit / 16) << 4) | (unsigned long long)(bit % 16);
+            else
+                a.e.ctl->cand_overflow = 1u;
+            ++at;
+        }
+        __syncthreads();  // s_wtot and s_base are reused by the next step
     }
     if (__ballot(bad) != 0ull && lane == 0) atomicOr(&a.e.ctl->nonfinite_full, 1u);
+}
+
+__global__ __launch_bounds__(kClassifyBlock) void k_classify_cand(FullArgs a) {
+    __shared__ BufDev sb[SPH_MAX_BUFFERS];
+    __shared__ unsigned s_cnt[2 * SPH_MAX_BUFFERS];
+    for (int t = threadIdx.x; t < a.nb * (int)(sizeof(BufDev) / 4); t += blockDim.x)
+        reinterpret_cast<uint32_t *>(sb)[t] = reinterpret_cast<const uint32_t *>(a.bufs)[t];
+    block_counts_init(s_cnt);
+    __syncthreads();
+    const unsigned long long cc = a.e.ctl->cand_count;
+    const int64_t n_cand = cc < (unsigned long long)a.cap_cand ? (int64_t)cc : a.cap_cand;
+    const int dim = a.p.dim;
+    const int seg = (int)((blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave) % kSeg);
+    for (int64_t t0 = (int64_t)blockIdx.x * blockDim.x; t0 < n_cand; t0 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t = t0 + threadIdx.x;
+        const bool valid = t < n_cand;
+        const unsigned long long ent = valid ? a.cand[t] : 0ull;
+        const int64_t i = (int64_t)(ent >> 4);
+        const int k = valid ? (int)(ent & 15ull) : 0;
+        const BufDev &b = sb[k];
+        int lab = 0;
+        float x = 0.0f, y = 0.0f, z = 0.0f;
+        float carv[SPH_MAX_CARRIED];
+        Outcome o{kEvNone, -1, false};
+        if (valid) {
+            x = a.p.pos[0][i];
+            y = a.p.pos[1][i];
+            z = dim == 3 ? a.p.pos[2][i] : 0.0f;
+            lab = a.p.label[i];
+            if (b.kind != SPH_OUTLET) {
+#pragma unroll
+                for (int f = 0; f < SPH_MAX_CARRIED; ++f)
+                    if (f < a.p.nc) carv[f] = a.p.car[f][i];
+            }
+            const unsigned bits = classify(b, dim, x, y, z);
+            if (bits & kIn) o = decide(b, k, dim, bits, lab, x, y, z);
+        }
+        unsigned long long found = 0, post = 0;
+        emit<true>(a.e, a.p, b, k, seg, valid, i, lab, o, x, y, z, carv, found, post);
+        if (found) atomicAdd(&s_cnt[2 * k], 1u);  // the buffer differs from lane to lane
+        if (post) atomicAdd(&s_cnt[2 * k + 1], 1u);
+    }
     __syncthreads();
     block_counts_store(a.e, s_cnt, a.nb);
 }
@@ -1230,7 +1315,7 @@ __device__ __forceinline__ void finalize_body(const FinArgs &a, const int fb, co
     __shared__ long long s_N, s_next;
     __shared__ unsigned s_found[SPH_MAX_BUFFERS], s_post[SPH_MAX_BUFFERS];
     __shared__ long long s_nl[SPH_MAX_BUFFERS];
-    __shared__ unsigned s_flags[2];
+    __shared__ unsigned s_flags[3];
     __shared__ uint32_t s_hist[kSortBuckets];      // per list, two buckets per word: counts, then starts
     __shared__ uint32_t s_mm[2][2];                // per list: min and max key
     __shared__ unsigned s_fat[2];                  // per list: keys in the fullest bucket
@@ -1256,6 +1341,7 @@ __device__ __forceinline__ void finalize_body(const FinArgs &a, const int fb, co
         s_N = *a.p.n_dev;
         s_flags[0] = c->scan_fault;
         s_flags[1] = a.local ? c->nonfinite_seen : c->nonfinite_full;
+        s_flags[2] = c->cand_overflow;
     }
     unsigned pv[(kCountReplicas * 2 * SPH_MAX_BUFFERS + 1023) / 1024];
 #pragma unroll
@@ -1304,6 +1390,7 @@ __device__ __forceinline__ void finalize_body(const FinArgs &a, const int fb, co
             for (int k = 0; k < a.nb && st == SPH_OK; ++k)
                 if ((long long)s_found[k] < s_nl[k]) st = SPH_ERR_CFL;
             if (st == SPH_OK && (tot0 > a.e.cap_ev || tot1 > a.e.cap_ev || tot2 > a.e.cap_rel)) st = SPH_ERR_EVENTS;
+        if (st == SPH_OK && !a.local && s_flags[2]) st = SPH_ERR_EVENTS;  // the full scan's candidate list overflowed
             if (st == SPH_OK && N - (long long)tot1 + (long long)tot0 > a.p.capacity) st = SPH_ERR_CAPACITY;
             s_status = st;
             s_N = N;
@@ -1634,6 +1721,8 @@ __device__ __forceinline__ void finalize_body(const FinArgs &a, const int fb, co
             r->n_after = st == SPH_OK ? N - (long long)D + (long long)G : N;
             r->next_id = st == SPH_OK ? s_next + G : s_next;
             if (!a.local) c->nonfinite_full = 0u;
+            c->cand_count = 0ull;
+            c->cand_overflow = 0u;
             c->fin_ticket = 0u;
             if (st == SPH_OK) {
                 c->next_id = s_next + G;
@@ -1828,25 +1917,33 @@ __global__ __launch_bounds__(kClassifyBlock) void k_buffer_bc(BcArgs a) {
         atomicAdd(&a.found[(size_t)(blockIdx.x % kCountReplicas) * SPH_MAX_BUFFERS + threadIdx.x], s_cnt[threadIdx.x]);
 }
 
-// Sum the per-buffer counts, clear them, and compare with the labelled counts of
-// the buffers the pass was meant to handle.
-__global__ void k_bc_finish(unsigned *found, const BufDev *bufs, int nb, int which, Ctl *ctl) {
-    __shared__ unsigned s_bad;
-    if (threadIdx.x == 0) s_bad = 0u;
+// Sum the per-buffer counts (one thread per copy and buffer), clear them, and
+// compare with the labelled counts of the buffers the pass was meant to handle.
+constexpr int kBcFinishBlock = kCountReplicas * 16;
+
+__global__ __launch_bounds__(kBcFinishBlock) void k_bc_finish(unsigned *found, const BufDev *bufs, int nb, int which,
+                                                              Ctl *ctl) {
+    __shared__ unsigned s_tot[SPH_MAX_BUFFERS];
+    if (threadIdx.x < SPH_MAX_BUFFERS) s_tot[threadIdx.x] = 0u;
     __syncthreads();
-    if ((int)threadIdx.x < nb) {
-        const int k = threadIdx.x;
-        unsigned long long tot = 0;
-        for (int r = 0; r < kCountReplicas; ++r) {
-            unsigned *w = &found[(size_t)r * SPH_MAX_BUFFERS + k];
-            tot += *w;
+    const int r = threadIdx.x / 16, k = threadIdx.x % 16;
+    if (k < nb) {
+        unsigned *w = &found[(size_t)r * SPH_MAX_BUFFERS + k];
+        const unsigned v = *w;
+        if (v) {
             *w = 0u;
+            atomicAdd(&s_tot[k], v);
         }
-        const bool involved = which < 0 ? bufs[k].bc_kind != SPH_BC_NONE : k == which;
-        if (involved && (long long)tot != ctl->n_labelled[k]) atomicOr(&s_bad, 1u);
     }
     __syncthreads();
-    if (threadIdx.x == 0) ctl->bc_status = s_bad ? (unsigned)SPH_ERR_CFL : (unsigned)SPH_OK;
+    if (threadIdx.x == 0) {
+        unsigned bad = 0;
+        for (int j = 0; j < nb; ++j) {
+            const bool involved = which < 0 ? bufs[j].bc_kind != SPH_BC_NONE : j == which;
+            if (involved && (long long)s_tot[j] != ctl->n_labelled[j]) bad = 1;
+        }
+        ctl->bc_status = bad ? (unsigned)SPH_ERR_CFL : (unsigned)SPH_OK;
+    }
 }
 
 // ----------------------------------------------------------------- batches --
@@ -1924,6 +2021,7 @@ struct sph_ctx {
     int n_runs = 0;
 
     int32_t *d_count = nullptr, *d_cell_start = nullptr, *d_cell_idx = nullptr;
+    unsigned long long *d_cand = nullptr;        // candidate list of the full scan
     uint32_t *d_keys = nullptr;                  // packed (key, rank) of each particle (three-kernel build)
     unsigned long long *d_keyrank = nullptr;     // full (key, rank) of the particles that do not fit
     int32_t rbits = 1;                           // rank bits of the packed form
@@ -2146,6 +2244,7 @@ void free_ctx(sph_ctx *c) {
     (void)hipFree(c->d_cell_idx);
     (void)hipFree(c->d_keyrank);
     (void)hipFree(c->d_keys);
+    (void)hipFree(c->d_cand);
     (void)hipFree(c->d_tile_state);
     (void)hipFree(c->d_gen_idx);
     (void)hipFree(c->d_del_idx);
@@ -2356,6 +2455,7 @@ extern "C" sph_status sph_create(const sph_config *cfg, sph_ctx **out) {
               hipMalloc(&c->d_cell_idx, sizeof(int32_t) * c->capacity) == hipSuccess &&
               hipMalloc(&c->d_keyrank, sizeof(unsigned long long) * c->capacity) == hipSuccess &&
               hipMalloc(&c->d_keys, sizeof(uint32_t) * c->capacity) == hipSuccess &&
+              hipMalloc(&c->d_cand, sizeof(unsigned long long) * (c->capacity + kCandSlack)) == hipSuccess &&
               hipMalloc(&c->d_tile_state, sizeof(unsigned long long) * c->n_tiles) == hipSuccess &&
               hipMalloc(&c->d_gen_idx, sizeof(uint32_t) * ev * kSeg) == hipSuccess &&
               hipMalloc(&c->d_del_idx, sizeof(uint32_t) * ev * kSeg) == hipSuccess &&
@@ -2565,9 +2665,16 @@ static sph_status fullscan_enqueue(sph_ctx *ctx, sph_particles *p) {
     fa.nb = ctx->nb;
     fa.e = events_of(ctx);
     fa.vec = aligned16(pp.pos[0]) && aligned16(pp.pos[1]) && aligned16(pp.pos[2]) ? 1 : 0;
+    fa.cand = ctx->d_cand;
+    fa.cap_cand = ctx->capacity + kCandSlack;
     {
         ProfScope ps(ctx, SPH_PHASE_FULLSCAN);
-        hipLaunchKernelGGL(k_classify_full, dim3(ctx->full_blocks), dim3(kClassifyBlock), 0, ctx->stream, fa);
+        hipLaunchKernelGGL(k_filter_full, dim3(ctx->full_blocks), dim3(kClassifyBlock), 0, ctx->stream, fa);
+    }
+    HIP_TRY(hipGetLastError());
+    {
+        ProfScope ps(ctx, SPH_PHASE_CANDIDATES);
+        hipLaunchKernelGGL(k_classify_cand, dim3(kCandBlocks), dim3(kClassifyBlock), 0, ctx->stream, fa);
     }
     HIP_TRY(hipGetLastError());
     ctx->built = false;
@@ -2704,8 +2811,8 @@ static sph_status launch_buffer_pass(sph_ctx *ctx, const Parts &pp, int which, c
         ProfScope ps(ctx, which < 0 ? SPH_PHASE_BC : SPH_PHASE_ROTATE);
         hipLaunchKernelGGL(k_buffer_bc, dim3(blocks), dim3(kClassifyBlock), 0, ctx->stream, a);
     }
-    hipLaunchKernelGGL(k_bc_finish, dim3(1), dim3(64), 0, ctx->stream, ctx->d_bcfound, ctx->d_bufs, ctx->nb, which,
-                       ctx->d_ctl);
+    hipLaunchKernelGGL(k_bc_finish, dim3(1), dim3(kBcFinishBlock), 0, ctx->stream, ctx->d_bcfound, ctx->d_bufs, ctx->nb,
+                       which, ctx->d_ctl);
     HIP_TRY(hipGetLastError());
     return SPH_OK;
 }

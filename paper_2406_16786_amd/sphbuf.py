@@ -36,8 +36,8 @@ EXPORTED = (
     "sph_set_fields", "sph_buffer_set_bc", "sph_buffer_apply_bc", "sph_buffer_rotate",
 )
 SPH_BATCH_KERNELS, SPH_BATCH_GRAPH = 0, 1
-SPH_NPHASE = 9
-PHASES = ("count", "scan", "scatter", "classify", "fullscan", "finalize", "build", "bc", "rotate")
+SPH_NPHASE = 10
+PHASES = ("count", "scan", "scatter", "classify", "fullscan", "finalize", "build", "bc", "rotate", "candidates")
 SPH_BC_NONE, SPH_BC_VELOCITY, SPH_BC_PRESSURE = 0, 1, 2
 SPH_PROFILE_PLUG, SPH_PROFILE_PARABOLIC_Y, SPH_PROFILE_PARABOLIC_R = 0, 1, 2
 

@@ -387,6 +387,49 @@ def test_unaligned_arrays_take_the_scalar_paths(mode):
     d.close()
 
 
+def test_checkpoint_and_restore_continue_identically():
+    """Library state outside the particle arrays (next id, labelled counts) saved
+    mid-run and restored into a fresh context gives the same continuation."""
+    from paper_2406_16786_amd import sphbuf as S
+    wl = W.bent_channel2d()
+    bufs = oracle_buffers(wl)
+    st = oracle_state(wl)
+    d = make_domain(wl, bufs, st)
+    assert d.identify(-1) == 0
+
+    def run(dom, steps, first):
+        pos, car, lab, ids, n = dom.download()
+        events = []
+        for step in range(first, first + steps):
+            W.advect_host(wl, pos, n, step)
+            dom.upload(pos, car, lab, ids, n)
+            dom.build()
+            gst, g, dl = dom.update()
+            assert gst == 0
+            events.append((dom.events()[1].copy(), dom.events()[2].copy()))
+            pos, car, lab, ids, n = dom.download()
+        return events, (pos, car, lab, ids, n)
+
+    run(d, 10, 0)
+    snap = d.download()
+    st_, nid, nl = S.sph_state_get(d.ctx)
+    assert st_ == 0
+    ev1, end1 = run(d, 10, 10)
+    pos, car, lab, ids, n = snap
+    st2 = oracle.State(wl.dim, [p.copy() for p in pos], [c.copy() for c in car], lab.copy(), ids.copy(), n, nid)
+    d2 = make_domain(wl, bufs, st2)
+    assert S.sph_state_set(d2.ctx, nid, nl) == 0
+    ev2, end2 = run(d2, 10, 10)
+    for (g1, d1_), (g2, d2_) in zip(ev1, ev2):
+        np.testing.assert_array_equal(g1, g2)
+        np.testing.assert_array_equal(d1_, d2_)
+    assert end1[4] == end2[4]
+    for a1, a2 in zip(end1[0] + end1[1] + [end1[2], end1[3]], end2[0] + end2[1] + [end2[2], end2[3]]):
+        np.testing.assert_array_equal(a1[: end1[4]], a2[: end1[4]])
+    d.close()
+    d2.close()
+
+
 # ---------------------------------------------------------------- guard band ---
 
 @pytest.mark.parametrize("dim", [2, 3])
