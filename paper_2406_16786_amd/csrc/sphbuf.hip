@@ -428,6 +428,7 @@ __device__ __forceinline__ void key_rank_batch(const Grid &g, const float *__res
 }
 
 constexpr int kCountBatch = 2;
+constexpr int64_t kCountPer = 2048;  // particles per count workgroup (single domain)
 
 struct CountArgs {
     const float *x, *y, *z;
@@ -453,24 +454,28 @@ __device__ __forceinline__ void count_body(const CountArgs &a, const int lb, con
         a.ctl->tile_counter = 0u;
         a.ctl->scan_fault = 0u;
     }
-    // each logical block walks one contiguous segment
-    const int64_t per = ((N + G - 1) / G + blockDim.x - 1) / blockDim.x * blockDim.x;
+    // each logical block walks one contiguous segment, cut into one slice per wave
+    // and row (kCountBatch rows per wave): at every step the block's waves take the
+    // next 64 particles of each of their slices, so the particles whose atomics are
+    // in flight together lie a slice apart -- beyond the few lattice rows that share
+    // a cell -- and rarely meet on one counter (same-address atomics queue at the
+    // memory side)
+    const int W = (int)(blockDim.x / kWave), w = (int)(threadIdx.x / kWave);
+    const int64_t slices = (int64_t)W * kCountBatch;
+    const int64_t per = ((N + G - 1) / G + slices * kWave - 1) / (slices * kWave) * (slices * kWave);
+    const int64_t L = per / slices;
     const int64_t s0 = (int64_t)lb * per;
     const int64_t s1 = min(N, s0 + per);
     bool bad = false;
-    const int64_t B = blockDim.x;
     const uint32_t rmask = (1u << a.rbits) - 1u;
-    // the kCountBatch rows of one step lie in different parts of the segment, so a
-    // wave's atomics of one step rarely meet on one cell (same-address atomics
-    // queue at the memory side)
-    const int64_t sub = ((s1 - s0 + kCountBatch - 1) / kCountBatch + B - 1) / B * B;
-    for (int64_t base = s0; base < s0 + sub; base += B) {
+    for (int64_t it = 0; it < L && s0 + it < s1; it += kWave) {
+        const int64_t i0 = s0 + (int64_t)w * L + it + lane;
         uint32_t key[kCountBatch];
         int32_t rank[kCountBatch];
-        key_rank_batch<kCountBatch>(a.g, a.x, a.y, a.z, a.count, base + threadIdx.x, sub, s1, lane, key, rank, bad);
+        key_rank_batch<kCountBatch>(a.g, a.x, a.y, a.z, a.count, i0, (int64_t)W * L, s1, lane, key, rank, bad);
 #pragma unroll
         for (int j = 0; j < kCountBatch; ++j) {
-            const int64_t i = base + threadIdx.x + j * sub;
+            const int64_t i = i0 + (int64_t)j * W * L;
             if (i >= s1) continue;
             if ((uint32_t)rank[j] < rmask) {
                 a.packed[i] = (key[j] << a.rbits) | (uint32_t)rank[j];
@@ -2146,6 +2151,13 @@ EventArgs events_of(const sph_ctx *ctx) {
     return e;
 }
 
+// Count workgroups for a particle array of this capacity (a multiple of 8, so the
+// XCD renumbering applies).
+int count_blocks(int64_t capacity) {
+    const int64_t want = (capacity + kCountPer - 1) / kCountPer;
+    return (int)std::max<int64_t>(8, std::min<int64_t>(16384, (want + 7) / 8 * 8));
+}
+
 CountArgs count_args(const sph_ctx *ctx, const Parts &pp) {
     CountArgs ca{};
     ca.x = pp.pos[0];
@@ -2614,7 +2626,7 @@ extern "C" sph_status sph_celllist_build(sph_ctx *ctx, const sph_particles *p) {
     const CountArgs ca = count_args(ctx, pp);
     {
         ProfScope ps(ctx, SPH_PHASE_COUNT);
-        hipLaunchKernelGGL(k_count, dim3(ctx->build_blocks), dim3(kBuildBlock), 0, ctx->stream, ca);
+        hipLaunchKernelGGL(k_count, dim3(count_blocks(pp.capacity)), dim3(kBuildBlock), 0, ctx->stream, ca);
     }
     HIP_TRY(hipGetLastError());
     const ScanArgs sa = scan_args(ctx);
