@@ -378,53 +378,98 @@ __device__ __forceinline__ void emit(const EventArgs &e, const Parts &p, const B
 // The order inside a cell is whatever the atomics make it; nothing downstream
 // depends on it.
 
-// Cell keys and per-cell ranks of J particles per thread at once: all position
-// loads are issued first, then the wave-level run detection, then all atomics,
-// and only then are the returned bases read -- so J load and J atomic round
-// trips overlap instead of queueing.  Particle of slot j: i0 + j * stride;
-// lanes past s1 take no part.  Wave-uniform call.
+// Cell keys and per-cell ranks of J particles per lane whose positions are already
+// in registers (slot j of lane l is the l-th particle of group j; the particles of
+// one group are consecutive): wave-level run detection for every group first, then
+// all atomics, and only then are the returned bases read -- so the J atomic round
+// trips overlap instead of queueing.  Invalid slots take no part.  Wave-uniform call.
+template <int J>
+__device__ __forceinline__ void rank_groups(const Grid &g, int32_t *count, const float (&px)[J], const float (&py)[J],
+                                            const float (&pz)[J], const bool (&valid)[J], int lane,
+                                            uint32_t (&key)[J], int32_t (&rank)[J], bool &bad) {
+    int my_head[J], len[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        key[j] = 0xffffffffu;
+        if (valid[j]) {
+            bad |= !(isfinite(px[j]) && isfinite(py[j]) && isfinite(pz[j]));
+            key[j] = cell_key(g, px[j], py[j], pz[j]);
+        }
+        const uint32_t prev = __shfl_up(key[j], 1);
+        const bool head = !valid[j] || lane == 0 || key[j] != prev;
+        const unsigned long long heads = __ballot(head);
+        const unsigned long long le = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+        my_head[j] = 63 - __clzll((long long)(heads & le));
+        const unsigned long long gt = heads & ~le;
+        len[j] = (gt ? __ffsll((long long)gt) - 1 : 64) - my_head[j];
+        if (!valid[j]) len[j] = 0;
+    }
+    int old[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        old[j] = len[j];  // any value already in the register: no copy that would wait on the atomic before
+        if (len[j] > 0 && lane == my_head[j]) old[j] = atomicAdd(&count[key[j]], len[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < J; ++j) rank[j] = __shfl(old[j], my_head[j]) + (lane - my_head[j]);
+}
+
+// The same with the positions loaded here: particle of slot j is i0 + j * stride;
+// lanes past s1 take no part.  All loads are issued before any key is formed.
 template <int J>
 __device__ __forceinline__ void key_rank_batch(const Grid &g, const float *__restrict__ x,
                                                const float *__restrict__ y, const float *__restrict__ z,
                                                int32_t *count, int64_t i0, int64_t stride, int64_t s1, int lane,
                                                uint32_t (&key)[J], int32_t (&rank)[J], bool &bad) {
     float px[J], py[J], pz[J];
+    bool valid[J];
 #pragma unroll
     for (int j = 0; j < J; ++j) {
         const int64_t i = i0 + (int64_t)j * stride;
+        valid[j] = i < s1;
         px[j] = py[j] = pz[j] = 0.0f;
-        if (i < s1) {
+        if (valid[j]) {
             px[j] = x[i];
             py[j] = y[i];
             if (g.dim == 3) pz[j] = z[i];
         }
     }
-    int my_head[J], len[J];
+    rank_groups<J>(g, count, px, py, pz, valid, lane, key, rank, bad);
+}
+
+// Element o of an array whose base is uniform, addressed by a 32-bit byte offset
+// (o * sizeof(T) < 2^32): the address is base + offset in one memory instruction,
+// no 64-bit address arithmetic per lane.
+template <class T>
+__device__ __forceinline__ const T &at32(const T *base, uint32_t o) {
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + (size_t)(uint32_t)(o * (uint32_t)sizeof(T)));
+}
+template <class T>
+__device__ __forceinline__ T &at32(T *base, uint32_t o) {
+    return *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + (size_t)(uint32_t)(o * (uint32_t)sizeof(T)));
+}
+
+// key_rank_batch on one segment: positions at 32-bit offsets from the segment's
+// base pointers; slot j is offset o0 + j * stride, live below n.
+template <int J>
+__device__ __forceinline__ void key_rank_seg(const Grid &g, const float *__restrict__ x, const float *__restrict__ y,
+                                             const float *__restrict__ z, int32_t *count, uint32_t o0, uint32_t stride,
+                                             uint32_t n, int lane, uint32_t (&key)[J], int32_t (&rank)[J],
+                                             bool &bad) {
+    float px[J], py[J], pz[J];
+    bool valid[J];
 #pragma unroll
     for (int j = 0; j < J; ++j) {
-        const bool valid = i0 + (int64_t)j * stride < s1;
-        key[j] = 0xffffffffu;
-        if (valid) {
-            bad |= !(isfinite(px[j]) && isfinite(py[j]) && isfinite(pz[j]));
-            key[j] = cell_key(g, px[j], py[j], pz[j]);
+        const uint32_t o = o0 + (uint32_t)j * stride;
+        valid[j] = o < n;
+        px[j] = py[j] = pz[j] = 0.0f;
+        if (valid[j]) {
+            px[j] = at32(x, o);
+            py[j] = at32(y, o);
+            if (g.dim == 3) pz[j] = at32(z, o);
         }
-        const uint32_t prev = __shfl_up(key[j], 1);
-        const bool head = !valid || lane == 0 || key[j] != prev;
-        const unsigned long long heads = __ballot(head);
-        const unsigned long long le = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
-        my_head[j] = 63 - __clzll((long long)(heads & le));
-        const unsigned long long gt = heads & ~le;
-        len[j] = (gt ? __ffsll((long long)gt) - 1 : 64) - my_head[j];
-        if (!valid) len[j] = 0;
     }
-    int old[J];
-#pragma unroll
-    for (int j = 0; j < J; ++j) {
-        old[j] = 0;
-        if (len[j] > 0 && lane == my_head[j]) old[j] = atomicAdd(&count[key[j]], len[j]);
-    }
-#pragma unroll
-    for (int j = 0; j < J; ++j) rank[j] = __shfl(old[j], my_head[j]) + (lane - my_head[j]);
+    rank_groups<J>(g, count, px, py, pz, valid, lane, key, rank, bad);
 }
 
 constexpr int kCountBatch = 2;
@@ -468,20 +513,26 @@ __device__ __forceinline__ void count_body(const CountArgs &a, const int lb, con
     const int64_t s1 = min(N, s0 + per);
     bool bad = false;
     const uint32_t rmask = (1u << a.rbits) - 1u;
-    for (int64_t it = 0; it < L && s0 + it < s1; it += kWave) {
-        const int64_t i0 = s0 + (int64_t)w * L + it + lane;
+    if (s0 >= s1) return;
+    // segment-relative 32-bit offsets (a segment is far below 2^29 particles)
+    const uint32_t n = (uint32_t)(s1 - s0), L32 = (uint32_t)L, stride = (uint32_t)W * L32;
+    const float *xs = a.x + s0, *ys = a.y + s0, *zs = a.g.dim == 3 ? a.z + s0 : a.x + s0;
+    uint32_t *ps = a.packed + s0;
+    unsigned long long *ss = a.spill + s0;
+    for (uint32_t it = 0; it < L32 && it < n; it += kWave) {
+        const uint32_t o0 = (uint32_t)w * L32 + it + (uint32_t)lane;
         uint32_t key[kCountBatch];
         int32_t rank[kCountBatch];
-        key_rank_batch<kCountBatch>(a.g, a.x, a.y, a.z, a.count, i0, (int64_t)W * L, s1, lane, key, rank, bad);
+        key_rank_seg<kCountBatch>(a.g, xs, ys, zs, a.count, o0, stride, n, lane, key, rank, bad);
 #pragma unroll
         for (int j = 0; j < kCountBatch; ++j) {
-            const int64_t i = i0 + (int64_t)j * W * L;
-            if (i >= s1) continue;
+            const uint32_t o = o0 + (uint32_t)j * stride;
+            if (o >= n) continue;
             if ((uint32_t)rank[j] < rmask) {
-                a.packed[i] = (key[j] << a.rbits) | (uint32_t)rank[j];
+                at32(ps, o) = (key[j] << a.rbits) | (uint32_t)rank[j];
             } else {
-                a.packed[i] = 0xffffffffu;
-                a.spill[i] = ((unsigned long long)key[j] << 32) | (unsigned)rank[j];
+                at32(ps, o) = 0xffffffffu;
+                at32(ss, o) = ((unsigned long long)key[j] << 32) | (unsigned)rank[j];
             }
         }
     }
@@ -777,7 +828,7 @@ __device__ __forceinline__ void rank_batch(int32_t *count, const uint32_t (&key)
     int old[J];
 #pragma unroll
     for (int j = 0; j < J; ++j) {
-        old[j] = 0;
+        old[j] = len[j];  // any value already in the register: no copy that would wait on the atomic before
         if (len[j] > 0 && lane == my_head[j]) old[j] = atomicAdd(&count[key[j]], len[j]);
     }
 #pragma unroll
