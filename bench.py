@@ -268,6 +268,7 @@ def main() -> int:
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-domain batched leg")
     ap.add_argument("--no-bc", action="store_true", help="skip the boundary-condition leg")
     ap.add_argument("--no-sprinkler", action="store_true", help="skip the rotating-sprinkler leg")
+    ap.add_argument("--no-neighbor", action="store_true", help="skip the neighbour-search leg")
     ap.add_argument("--build", default=None, choices=["split", "fused"],
                     help="cell-list build variant (default: the library's)")
     args = ap.parse_args()
@@ -514,6 +515,26 @@ def main() -> int:
             "what": "velocity inlet (pipe profile) + pressure outlet (normal projection) on the labelled particles, "
                     "one kernel over the local cells"}
         log(f"apply_bc {bc_us:.1f} us on {n_buf} buffer particles")
+    # ---- the cell list reused by the solver's neighbour search (radius = cell size = 2h) ----
+    if not args.no_neighbor:
+        counts = torch.empty(wl.capacity, dtype=torch.int32, device=dev)
+        reset_work()
+        S.check(S.sph_profile_enable(dom.ctx, True), "profile")
+        n_nb = min(K, 5)
+        for s in range(Wm, Wm + n_nb):
+            S.check(S.sph_state_set(dom.ctx, *states[s]), "state_set")
+            S.sph_celllist_build(dom.ctx, parts[s])
+            S.check(S.sph_neighbor_count(dom.ctx, parts[s], wl.cell_size, counts.data_ptr()), "neighbor_count")
+        st_, pms, pn = S.sph_profile_read(dom.ctx, reset=True)
+        S.check(S.sph_profile_enable(dom.ctx, False), "profile")
+        nb_us = float(pms[S.PHASES.index("neighbor")]) / max(1, int(pn[S.PHASES.index("neighbor")])) * 1e3
+        n_last = int(snaps[Wm + n_nb - 1].n_dev.item())
+        mean_nb = float(counts[:n_last].double().mean().item())
+        out["neighbor_search"] = {
+            "us": round(nb_us, 1), "radius": "cell size (2h = 2.6 dp)", "mean_neighbors": round(mean_nb, 2),
+            "Mparticles_per_s": round(n_last / (nb_us * 1e-6) / 1e6, 1),
+            "what": "neighbour counts over the library's cell list (FP32 distances, FP64 in the 2^-16 band)"}
+        log(f"neighbor_count {nb_us:.1f} us, {mean_nb:.1f} neighbours per particle")
     if not args.no_sprinkler:
         out["sprinkler"] = sprinkler_leg(torch, np, S, W, Domain, log)
 

@@ -173,6 +173,22 @@ sph_status sph_last_events(sph_ctx *ctx, int64_t *gen_src, int64_t *del_idx, int
 sph_status sph_celllist_view(sph_ctx *ctx, const int32_t **cell_start, const int32_t **cell_idx,
                              int64_t *n_cells, int32_t dims[3]);
 
+/* Async: neighbour search on the cell list of the last build, the use a solver
+ * makes of the same list (the kernel support 2h of Section 3, h = 1.3 dp, is the
+ * cell size).  For every live particle i (i < N):
+ *   counts[i] = #{ j != i live : |r_i - r_j| < radius },
+ * the distance decided as in FP64 by ((dx*dx + dy*dy) + dz*dz) < radius*radius with
+ * dx = (double)x_i - (double)x_j (dz = 0 in 2-D), every operation rounded to
+ * nearest.  counts: caller-owned device int32 array of at least N entries; entries
+ * past N are left alone; valid once the context's stream has reached this call.
+ * The particle arrays must be those of the last sph_celllist_build, unchanged.
+ * Allocates nothing: the positions are copied into cell order in the build's own
+ * key scratch (the cell list itself stays as it is).
+ * Errors: SPH_ERR_ARG (NULL, radius not in (0, cell size], or a grid too large for
+ * FP32 cell coordinates), SPH_ERR_STATE (no current cell list).  Nothing is
+ * written on error. */
+sph_status sph_neighbor_count(sph_ctx *ctx, const sph_particles *p, double radius, int32_t *counts);
+
 /* ---------------------------------- boundary conditions and moving buffers -- */
 
 /* Roles of the caller's carried arrays: indices into sph_particles.carried of the
@@ -255,7 +271,8 @@ typedef enum {
     SPH_PHASE_BC = 7,         /* boundary conditions on buffer particles          */
     SPH_PHASE_ROTATE = 8,     /* rigid turn of a buffer's particles               */
     SPH_PHASE_CANDIDATES = 9, /* full scan: the filter's candidates, exact tests  */
-    SPH_NPHASE = 10
+    SPH_PHASE_NEIGHBOR = 10,  /* neighbour counts over the cell list              */
+    SPH_NPHASE = 11
 } sph_phase;
 
 /* When on, every kernel launch of the context is bracketed by two HIP events on

@@ -133,6 +133,10 @@ def lib():
                                            ctypes.c_int, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         L.orc_cell_list_sparse.restype = ctypes.c_int
+        L.orc_neighbor_count.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_int64,
+                                         ctypes.c_void_p]
+        L.orc_neighbor_count.restype = None
         _lib = L
     return _lib
 
@@ -444,3 +448,22 @@ def cell_list_sparse(dim: int, lo, inv_cs: float, dims, blog2: int, active: np.n
     if rc != OK:
         raise ValueError("bad sparse-grid arguments")
     return start, idx[:n]
+
+
+def neighbor_count(dim: int, x, y, z=None, radius: float = 1.0, query=None) -> np.ndarray:
+    """Brute-force neighbour counts (int32) of the query particles (all if None):
+    other particles with FP64 squared distance ((dx*dx + dy*dy) + dz*dz) < radius^2."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    y = np.ascontiguousarray(y, dtype=np.float32)
+    n = x.size
+    zz = np.ascontiguousarray(z if z is not None else np.zeros(n), dtype=np.float32)
+    if query is None:
+        q = None
+        nq = n
+    else:
+        q = np.ascontiguousarray(query, dtype=np.int64)
+        nq = q.size
+    out = np.zeros(max(1, nq), np.int32)
+    lib().orc_neighbor_count(dim, n, x.ctypes.data, y.ctypes.data, zz.ctypes.data, float(radius),
+                             None if q is None else q.ctypes.data, nq, out.ctypes.data)
+    return out[:nq]

@@ -586,3 +586,26 @@ int orc_cell_list_sparse(int dim, const float lo[3], float inv_cs, const int32_t
     free(slot);
     return ORC_OK;
 }
+
+/* ------------------------------------------------------ neighbour search -- */
+
+void orc_neighbor_count(int dim, int64_t n, const float *x, const float *y, const float *z, double radius,
+                        const int64_t *query, int64_t nq, int32_t *counts) {
+    const double r2 = radius * radius;
+    for (int64_t k = 0; k < nq; k++) {
+        const int64_t q = query ? query[k] : k;
+        int32_t c = 0;
+        for (int64_t j = 0; j < n; j++) {
+            if (j == q) continue;
+            const double dx = (double)x[q] - (double)x[j];
+            const double dy = (double)y[q] - (double)y[j];
+            double d2 = dx * dx + dy * dy;
+            if (dim == 3) {
+                const double dz = (double)z[q] - (double)z[j];
+                d2 = d2 + dz * dz;
+            }
+            if (d2 < r2) c++;
+        }
+        counts[k] = c;
+    }
+}

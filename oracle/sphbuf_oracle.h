@@ -160,6 +160,15 @@ int orc_apply_bc(const orc_buffer *bufs, const orc_bc *bcs, const orc_fields *fi
 int orc_rotate_buffer(orc_buffer *bufs, int nb, int which, const double center[3], const double m[9],
                       const orc_fields *fields, orc_state *s);
 
+/* Neighbour search by its definition, brute force over all particles (the solver's
+ * search for neighbours within the kernel support 2h, Section 3): for each query
+ * particle q = query[k], counts[k] = number of j != q, 0 <= j < n, with
+ * ((dx*dx + dy*dy) + dz*dz) < radius*radius, dx = (double)x_q - (double)x_j,
+ * every operation rounded in FP64 (no contraction), dz = 0 in 2-D.  query = NULL
+ * queries every particle (nq = n).  O(n) per query. */
+void orc_neighbor_count(int dim, int64_t n, const float *x, const float *y, const float *z, double radius,
+                        const int64_t *query, int64_t nq, int32_t *counts);
+
 #ifdef __cplusplus
 }
 #endif

@@ -148,9 +148,10 @@ __device__ __forceinline__ void cell_coords(const Grid &g, float x, float y, flo
     }
 }
 
-__device__ __forceinline__ uint32_t cell_key(const Grid &g, float x, float y, float z) {
-    uint32_t ix, iy, iz;
-    cell_coords(g, x, y, z, ix, iy, iz);
+// Key of the cell with (in-range) coordinates ix, iy, iz: dense row-major, or the
+// brick slot and the position inside the brick (cells of inactive bricks share the
+// overflow key).
+__device__ __forceinline__ uint32_t key_of_cell(const Grid &g, uint32_t ix, uint32_t iy, uint32_t iz) {
     if (g.blog2 == 0) return ix + (uint32_t)g.dims[0] * (iy + (uint32_t)g.dims[1] * iz);
     const uint32_t b = (uint32_t)g.blog2, m = (1u << b) - 1u;
     const uint32_t brick = (ix >> b) + (uint32_t)g.bdims[0] * ((iy >> b) + (uint32_t)g.bdims[1] * (iz >> b));
@@ -158,6 +159,12 @@ __device__ __forceinline__ uint32_t cell_key(const Grid &g, float x, float y, fl
     if (slot < 0) return g.overflow_key;
     const uint32_t local = (ix & m) + ((iy & m) << b) + (g.dim == 3 ? ((iz & m) << (2 * b)) : 0u);
     return ((uint32_t)slot << (g.dim * b)) + local;
+}
+
+__device__ __forceinline__ uint32_t cell_key(const Grid &g, float x, float y, float z) {
+    uint32_t ix, iy, iz;
+    cell_coords(g, x, y, z, ix, iy, iz);
+    return key_of_cell(g, ix, iy, iz);
 }
 
 // Exact FP64 decision: local coordinates r' = Q (r - O') evaluated as
@@ -2002,6 +2009,112 @@ __global__ __launch_bounds__(kBcFinishBlock) void k_bc_finish(unsigned *found, c
     }
 }
 
+// ------------------------------------------------------ neighbour search --
+//
+// The cell list also serves the solver's neighbour search: with the cell size at
+// least the search radius (the kernel support 2h of Section 3 is the cell size,
+// 2.6 dp), every particle closer than the radius lies in the 3^d cells around the
+// particle's own.  Binning is FP32, so two particles less than one cell apart can
+// land two cells apart when one of them lies within `band` (cell units, from the
+// binning error bound) of its cell's face; on such a side the block is widened by
+// one cell.  Distances: FP32 first; within a relative 2^-16 of the squared radius
+// the decision is taken in FP64 as ((dx*dx + dy*dy) + dz*dz), dx = (double)x_i -
+// (double)x_j, each operation rounded separately.
+//
+// The positions are first copied into cell order (slot k of cell_idx), so one
+// thread per slot reads its own position coalesced, the threads of one cell walk
+// identical loops over the same contiguous slots, and on the dense grid the three
+// cells of a stencil row are one contiguous slot range.
+
+struct NbrArgs {
+    Parts p;
+    Grid g;
+    const int32_t *cell_start;
+    const int32_t *cell_idx;
+    float *xs, *ys, *zs;  // positions in cell order (build scratch)
+    double r2;            // radius^2
+    float r2_in, r2_out;  // FP32 squared distances surely inside / outside
+    float band;           // cell units
+    int32_t *counts;
+};
+
+constexpr int kNbrBlock = 256;
+
+__global__ __launch_bounds__(kNbrBlock) void k_nbr_order(NbrArgs a) {
+    const int64_t N = live_count(a.p.n_dev, a.p.capacity);
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < N; k += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t j = a.cell_idx[k];
+        a.xs[k] = a.p.pos[0][j];
+        a.ys[k] = a.p.pos[1][j];
+        if (a.g.dim == 3) a.zs[k] = a.p.pos[2][j];
+    }
+}
+
+// Pairs of slot k with the slots [m0, m1): FP32 test, FP64 in the band.
+__device__ __forceinline__ int nbr_range(const NbrArgs &a, int64_t k, const float (&pi)[3], int32_t m0, int32_t m1) {
+    int cnt = 0;
+    const bool d3 = a.g.dim == 3;
+    for (int32_t m = m0; m < m1; ++m) {
+        if (m == k) continue;
+        const float xj = a.xs[m], yj = a.ys[m], zj = d3 ? a.zs[m] : 0.0f;
+        const float dx = pi[0] - xj, dy = pi[1] - yj, dz = pi[2] - zj;
+        const float d2 = (dx * dx + dy * dy) + dz * dz;
+        if (d2 < a.r2_in) {
+            ++cnt;
+        } else if (!(d2 > a.r2_out)) {
+            const double ex = __dadd_rn((double)pi[0], -(double)xj);
+            const double ey = __dadd_rn((double)pi[1], -(double)yj);
+            const double ez = __dadd_rn((double)pi[2], -(double)zj);
+            const double e2 = __dadd_rn(__dadd_rn(__dmul_rn(ex, ex), __dmul_rn(ey, ey)), __dmul_rn(ez, ez));
+            if (e2 < a.r2) ++cnt;
+        }
+    }
+    return cnt;
+}
+
+__global__ __launch_bounds__(kNbrBlock) void k_neighbor_count(NbrArgs a) {
+    const int64_t N = live_count(a.p.n_dev, a.p.capacity);
+    const Grid &g = a.g;
+    const int dim = g.dim;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < N; k += (int64_t)gridDim.x * blockDim.x) {
+        const float pi[3] = {a.xs[k], a.ys[k], dim == 3 ? a.zs[k] : 0.0f};
+        int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+        for (int ax = 0; ax < dim; ++ax) {
+            const float t = (pi[ax] - g.lo[ax]) * g.inv_cs;  // as in cell_coords
+            const float f = floorf(t);
+            const float cl = fminf(fmaxf(f, 0.0f), (float)(g.dims[ax] - 1));
+            const int c = (int)cl;
+            const bool inside = f == cl;  // not clamped to an edge cell (and not NaN)
+            const float fr = t - f;       // exact
+            lo[ax] = max(0, c - 1 - ((inside && fr < a.band) ? 1 : 0));
+            hi[ax] = min(g.dims[ax] - 1, c + 1 + ((inside && fr > 1.0f - a.band) ? 1 : 0));
+        }
+        int cnt = 0;
+        if (g.blog2 == 0) {
+            // dense: the cells lo[0]..hi[0] of a row are consecutive keys, one slot range
+            for (int iz = lo[2]; iz <= hi[2]; ++iz)
+                for (int iy = lo[1]; iy <= hi[1]; ++iy) {
+                    const uint32_t k0 = key_of_cell(g, (uint32_t)lo[0], (uint32_t)iy, (uint32_t)iz);
+                    const uint32_t k1 = k0 + (uint32_t)(hi[0] - lo[0]);
+                    cnt += nbr_range(a, k, pi, a.cell_start[k0], a.cell_start[k1 + 1]);
+                }
+        } else {
+            bool overflow_seen = false;
+            for (int iz = lo[2]; iz <= hi[2]; ++iz)
+                for (int iy = lo[1]; iy <= hi[1]; ++iy)
+                    for (int ix = lo[0]; ix <= hi[0]; ++ix) {
+                        const uint32_t key = key_of_cell(g, (uint32_t)ix, (uint32_t)iy, (uint32_t)iz);
+                        if (key == g.overflow_key) {  // one cell for all inactive bricks
+                            if (overflow_seen) continue;
+                            overflow_seen = true;
+                        }
+                        cnt += nbr_range(a, k, pi, a.cell_start[key], a.cell_start[key + 1]);
+                    }
+        }
+        a.counts[a.cell_idx[k]] = cnt;
+    }
+}
+
 // ----------------------------------------------------------------- batches --
 //
 // Every phase of every domain of a batch in one launch: a static table maps each
@@ -2808,6 +2921,47 @@ extern "C" sph_status sph_celllist_view(sph_ctx *ctx, const int32_t **cell_start
     if (n_cells) *n_cells = ctx->n_cells;
     if (dims)
         for (int c = 0; c < 3; ++c) dims[c] = ctx->dims[c];
+    return SPH_OK;
+}
+
+extern "C" sph_status sph_neighbor_count(sph_ctx *ctx, const sph_particles *p, double radius, int32_t *counts) {
+    if (!ctx || !counts) return SPH_ERR_ARG;
+    Parts pp;
+    const sph_status st = parts_of(ctx, p, pp);
+    if (st != SPH_OK) return st;
+    const double r2 = radius * radius;
+    if (!(radius > 0.0) || !(radius <= ctx->cs) || !(r2 >= 1e-30)) return SPH_ERR_ARG;
+    int max_dim = 1;
+    for (int c = 0; c < ctx->dim; ++c) max_dim = std::max(max_dim, ctx->dims[c]);
+    // FP32 cell coordinate t = fl(fl(x - lo) * inv_cs) is within 2u(t + 1) of the
+    // exact one and the cell size times inv_cs within u of 1 (u = 2^-24): a pair
+    // less than one cell apart is two cells apart only if one of them lies within
+    // 2 * 2u(t + 1) + u of its cell's face
+    const double band = 8.0 * 0x1p-24 * (double)(max_dim + 2);
+    if (band >= 0.25) return SPH_ERR_ARG;
+    if (!ctx->built) return SPH_ERR_STATE;
+    NbrArgs a{};
+    a.p = pp;
+    a.g = grid_of(ctx);
+    a.cell_start = ctx->d_cell_start;
+    a.cell_idx = ctx->d_cell_idx;
+    // the build's key scratch (4 + 8 bytes per particle) holds the ordered positions
+    a.xs = reinterpret_cast<float *>(ctx->d_keys);
+    a.ys = reinterpret_cast<float *>(ctx->d_keyrank);
+    a.zs = a.ys + ctx->capacity;
+    a.r2 = r2;
+    // the FP32 squared distance is within 2^-21 (relative) of the exact one
+    a.r2_in = (float)(r2 * (1.0 - 0x1p-16));
+    a.r2_out = (float)(r2 * (1.0 + 0x1p-16));
+    a.band = (float)band;
+    a.counts = counts;
+    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(65536, (pp.capacity + kNbrBlock - 1) / kNbrBlock));
+    {
+        ProfScope ps(ctx, SPH_PHASE_NEIGHBOR);
+        hipLaunchKernelGGL(k_nbr_order, dim3(blocks), dim3(kNbrBlock), 0, ctx->stream, a);
+        hipLaunchKernelGGL(k_neighbor_count, dim3(blocks), dim3(kNbrBlock), 0, ctx->stream, a);
+    }
+    HIP_TRY(hipGetLastError());
     return SPH_OK;
 }
 

@@ -100,6 +100,13 @@ class Domain:
     def rotate(self, buffer_id: int, center, m) -> int:
         return S.sph_buffer_rotate(self.ctx, self.p, buffer_id, center, m)
 
+    def neighbor_count(self, radius: float):
+        """(status, int32 device tensor of the capacity; entries below N hold the counts)."""
+        counts = torch.full((self.capacity,), -1, dtype=torch.int32, device=self.device)
+        st = S.sph_neighbor_count(self.ctx, self.p, radius, counts.data_ptr())
+        self.stream.synchronize()
+        return st, counts
+
     def result(self):
         return S.sph_last_result(self.ctx)
 

@@ -33,11 +33,12 @@ EXPORTED = (
     "sph_status_str", "sph_profile_enable", "sph_profile_read", "sph_grid_fit",
     "sph_batch_create", "sph_batch_destroy", "sph_batch_set_mode", "sph_batch_set_count_block",
     "sph_batch_step", "sph_batch_results", "sph_batch_tune",
-    "sph_set_fields", "sph_buffer_set_bc", "sph_buffer_apply_bc", "sph_buffer_rotate",
+    "sph_set_fields", "sph_buffer_set_bc", "sph_buffer_apply_bc", "sph_buffer_rotate", "sph_neighbor_count",
 )
 SPH_BATCH_KERNELS, SPH_BATCH_GRAPH = 0, 1
-SPH_NPHASE = 10
-PHASES = ("count", "scan", "scatter", "classify", "fullscan", "finalize", "build", "bc", "rotate", "candidates")
+SPH_NPHASE = 11
+PHASES = ("count", "scan", "scatter", "classify", "fullscan", "finalize", "build", "bc", "rotate", "candidates",
+          "neighbor")
 SPH_BC_NONE, SPH_BC_VELOCITY, SPH_BC_PRESSURE = 0, 1, 2
 SPH_PROFILE_PLUG, SPH_PROFILE_PARABOLIC_Y, SPH_PROFILE_PARABOLIC_R = 0, 1, 2
 
@@ -151,6 +152,7 @@ def lib() -> ctypes.CDLL:
             "sph_buffer_set_bc": ([_VP, ctypes.c_int32, ctypes.POINTER(sph_bc)], ctypes.c_int),
             "sph_buffer_apply_bc": ([_VP, ctypes.POINTER(sph_particles)], ctypes.c_int),
             "sph_buffer_rotate": ([_VP, ctypes.POINTER(sph_particles), ctypes.c_int32, _D, _D], ctypes.c_int),
+            "sph_neighbor_count": ([_VP, ctypes.POINTER(sph_particles), ctypes.c_double, _VP], ctypes.c_int),
             "sph_batch_create": ([ctypes.POINTER(_VP), ctypes.POINTER(sph_particles), ctypes.c_int32, _VP,
                                   ctypes.POINTER(_VP)], ctypes.c_int),
             "sph_batch_destroy": ([_VP], ctypes.c_int),
@@ -247,6 +249,11 @@ def sph_buffer_set_bc(ctx: int, buffer_id: int, kind: int, profile: int = SPH_PR
 
 def sph_buffer_apply_bc(ctx: int, p: sph_particles) -> int:
     return lib().sph_buffer_apply_bc(ctx, ctypes.byref(p))
+
+
+def sph_neighbor_count(ctx: int, p: sph_particles, radius: float, counts_ptr: int) -> int:
+    """counts_ptr: device int32 array of at least N entries (async, on the context's stream)."""
+    return lib().sph_neighbor_count(ctx, ctypes.byref(p), float(radius), _VP(counts_ptr))
 
 
 def sph_buffer_rotate(ctx: int, p: sph_particles, buffer_id: int, center: Sequence[float], m) -> int:
