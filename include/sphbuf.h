@@ -136,7 +136,11 @@ sph_status sph_buffer_define(sph_ctx *ctx, sph_kind kind, const double origin[3]
 sph_status sph_grid_fit(sph_ctx *ctx, const sph_particles *p);
 
 /* Step 1: counting-sort cell list of the live particles on the context stream
- * (async).  Flags non-finite positions for the next update. */
+ * (async).  Flags non-finite positions for the next update.
+ * With SPHBUF_UPDATE=overlap in the environment at sph_create, the count pass also
+ * gathers the particles of every buffer's cover cells, and the scan and scatter run
+ * on a library-owned side stream that the next update (or any call that reads the
+ * cell list) joins to the context stream; results are the same either way. */
 sph_status sph_celllist_build(sph_ctx *ctx, const sph_particles *p);
 
 /* Algorithm 1, identification ("execute only once"): label k for every live
