@@ -2204,25 +2204,33 @@ struct BlockMap {
     int32_t vb;  // block within the domain
 };
 
+// The tables are padded to a multiple of 8 entries (padding: d = -1) and read in
+// the XCD-renumbered order, so each XCD takes a contiguous range of the table (and
+// so of each domain's particles, as in the single-domain launches).
 __global__ __launch_bounds__(kBuildBlock) void kb_count(const CountArgs *args, const BlockMap *map,
                                                         const int32_t *vg) {
-    const BlockMap m = map[blockIdx.x];
+    const BlockMap m = map[logical_block()];
+    if (m.d < 0) return;
     count_body(args[m.d], m.vb, vg[m.d]);
 }
 
 __global__ __launch_bounds__(kScanBlock) void kb_scan(const ScanArgs *args, const BlockMap *map) {
-    scan_body(args[map[blockIdx.x].d]);
+    const BlockMap m = map[logical_block()];
+    if (m.d < 0) return;
+    scan_body(args[m.d]);
 }
 
 __global__ __launch_bounds__(kBuildBlock) void kb_scatter(const ScatterArgs *args, const BlockMap *map,
                                                           const int32_t *vg) {
-    const BlockMap m = map[blockIdx.x];
+    const BlockMap m = map[logical_block()];
+    if (m.d < 0) return;
     scatter_body(args[m.d], m.vb, vg[m.d]);
 }
 
 __global__ __launch_bounds__(kClassifyBlock) void kb_classify(const LocalArgs *args, const BlockMap *map,
                                                               const int32_t *vg) {
-    const BlockMap m = map[blockIdx.x];
+    const BlockMap m = map[logical_block()];
+    if (m.d < 0) return;
     classify_body(args[m.d], m.vb, vg[m.d]);
 }
 
@@ -3574,6 +3582,8 @@ sph_status batch_layout(sph_batch *b) {
         vgl.push_back(vl);
         for (int v = 0; v < vl; ++v) ml.push_back({(int32_t)d, v});
     }
+    for (auto *t : {&mc, &ms, &ml})  // padding for the XCD renumbering (a multiple of 8 blocks)
+        while (!t->empty() && t->size() % 8) t->push_back({-1, 0});
     sph_status st;
     if ((st = upload_table(b->d_map_count, mc, b->stream)) != SPH_OK) return st;
     if ((st = upload_table(b->d_map_scan, ms, b->stream)) != SPH_OK) return st;
