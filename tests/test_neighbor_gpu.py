@@ -134,6 +134,15 @@ def test_pairs_two_fp32_cells_apart_are_found():
     d.close()
 
 
+def test_empty_domain():
+    st = make_state(3, np.zeros((0, 3)))
+    d = make_domain_raw(3, (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), 0.1, 0.04, [], st)
+    d.build()
+    c = _gpu_counts(d, 0.1)
+    assert np.all(c == -1)
+    d.close()
+
+
 def test_neighbor_count_arguments_and_state():
     S = _S()
     wl = W.channel2d()
