@@ -386,16 +386,10 @@ __device__ __forceinline__ void emit(const EventArgs &e, const Parts &p, const B
 // The order inside a cell is whatever the atomics make it; nothing downstream
 // depends on it.
 
-// Cell keys and per-cell ranks of J particles per lane whose positions are already
-// in registers (slot j of lane l is the l-th particle of group j; the particles of
-// one group are consecutive): wave-level run detection for every group first, then
-// all atomics, and only then are the returned bases read -- so the J atomic round
-// trips overlap instead of queueing.  Invalid slots take no part.  Wave-uniform call.
 template <int J>
-__device__ __forceinline__ void rank_groups(const Grid &g, int32_t *count, const float (&px)[J], const float (&py)[J],
-                                            const float (&pz)[J], const bool (&valid)[J], int lane,
-                                            uint32_t (&key)[J], int32_t (&rank)[J], bool &bad) {
-    int my_head[J], len[J];
+__device__ __forceinline__ void group_keys(const Grid &g, const float (&px)[J], const float (&py)[J],
+                                           const float (&pz)[J], const bool (&valid)[J], uint32_t (&key)[J],
+                                           bool &bad) {
 #pragma unroll
     for (int j = 0; j < J; ++j) {
         key[j] = 0xffffffffu;
@@ -403,6 +397,17 @@ __device__ __forceinline__ void rank_groups(const Grid &g, int32_t *count, const
             bad |= !(isfinite(px[j]) && isfinite(py[j]) && isfinite(pz[j]));
             key[j] = cell_key(g, px[j], py[j], pz[j]);
         }
+    }
+}
+
+// Runs of equal keys in consecutive lanes: the run's first lane (head) issues one
+// returning atomic for the run's length; old[j] is then in flight.
+template <int J>
+__device__ __forceinline__ void group_runs_issue(int32_t *count, const uint32_t (&key)[J], const bool (&valid)[J],
+                                                 int lane, int (&my_head)[J], int (&old)[J]) {
+    int len[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
         const uint32_t prev = __shfl_up(key[j], 1);
         const bool head = !valid[j] || lane == 0 || key[j] != prev;
         const unsigned long long heads = __ballot(head);
@@ -412,14 +417,34 @@ __device__ __forceinline__ void rank_groups(const Grid &g, int32_t *count, const
         len[j] = (gt ? __ffsll((long long)gt) - 1 : 64) - my_head[j];
         if (!valid[j]) len[j] = 0;
     }
-    int old[J];
 #pragma unroll
     for (int j = 0; j < J; ++j) {
         old[j] = len[j];  // any value already in the register: no copy that would wait on the atomic before
         if (len[j] > 0 && lane == my_head[j]) old[j] = atomicAdd(&count[key[j]], len[j]);
     }
+}
+
+// Rank of each lane in its cell: the run's base from its head plus the offset in the run.
+template <int J>
+__device__ __forceinline__ void group_ranks(const int (&my_head)[J], const int (&old)[J], int lane,
+                                            int32_t (&rank)[J]) {
 #pragma unroll
     for (int j = 0; j < J; ++j) rank[j] = __shfl(old[j], my_head[j]) + (lane - my_head[j]);
+}
+
+// Cell keys and per-cell ranks of J particles per lane whose positions are already
+// in registers (slot j of lane l is the l-th particle of group j; the particles of
+// one group are consecutive): keys and run detection for every group first, then
+// all atomics, and only then are the returned bases read -- so the J atomic round
+// trips overlap instead of queueing.  Invalid slots take no part.  Wave-uniform call.
+template <int J>
+__device__ __forceinline__ void rank_groups(const Grid &g, int32_t *count, const float (&px)[J], const float (&py)[J],
+                                            const float (&pz)[J], const bool (&valid)[J], int lane,
+                                            uint32_t (&key)[J], int32_t (&rank)[J], bool &bad) {
+    int my_head[J], old[J];
+    group_keys<J>(g, px, py, pz, valid, key, bad);
+    group_runs_issue<J>(count, key, valid, lane, my_head, old);
+    group_ranks<J>(my_head, old, lane, rank);
 }
 
 // The same with the positions loaded here: particle of slot j is i0 + j * stride;
@@ -455,29 +480,6 @@ __device__ __forceinline__ const T &at32(const T *base, uint32_t o) {
 template <class T>
 __device__ __forceinline__ T &at32(T *base, uint32_t o) {
     return *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + (size_t)(uint32_t)(o * (uint32_t)sizeof(T)));
-}
-
-// key_rank_batch on one segment: positions at 32-bit offsets from the segment's
-// base pointers; slot j is offset o0 + j * stride, live below n.
-template <int J>
-__device__ __forceinline__ void key_rank_seg(const Grid &g, const float *__restrict__ x, const float *__restrict__ y,
-                                             const float *__restrict__ z, int32_t *count, uint32_t o0, uint32_t stride,
-                                             uint32_t n, int lane, uint32_t (&key)[J], int32_t (&rank)[J],
-                                             bool &bad) {
-    float px[J], py[J], pz[J];
-    bool valid[J];
-#pragma unroll
-    for (int j = 0; j < J; ++j) {
-        const uint32_t o = o0 + (uint32_t)j * stride;
-        valid[j] = o < n;
-        px[j] = py[j] = pz[j] = 0.0f;
-        if (valid[j]) {
-            px[j] = at32(x, o);
-            py[j] = at32(y, o);
-            if (g.dim == 3) pz[j] = at32(z, o);
-        }
-    }
-    rank_groups<J>(g, count, px, py, pz, valid, lane, key, rank, bad);
 }
 
 constexpr int kCountBatch = 2;
@@ -534,11 +536,38 @@ __device__ __forceinline__ void count_body(const CountArgs &a, const int lb, con
     const float *xs = a.x + s0, *ys = a.y + s0, *zs = a.g.dim == 3 ? a.z + s0 : a.x + s0;
     uint32_t *ps = a.packed + s0;
     unsigned long long *ss = a.spill + s0;
+    // Software pipelined: once a step has its keys it issues the next step's position
+    // loads, then its run detection and atomics, so the two round trips overlap.
+    constexpr int J = kCountBatch;
+    const bool d3 = a.g.dim == 3;
+    float px[J], py[J], pz[J];
+    auto load = [&](uint32_t it) {
+        const uint32_t o0 = (uint32_t)w * L32 + it + (uint32_t)lane;
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const uint32_t o = o0 + (uint32_t)j * stride;
+            px[j] = py[j] = pz[j] = 0.0f;
+            if (o < n) {
+                px[j] = at32(xs, o);
+                py[j] = at32(ys, o);
+                if (d3) pz[j] = at32(zs, o);
+            }
+        }
+    };
+    load(0);
     for (uint32_t it = 0; it < L32 && it < n; it += kWave) {
         const uint32_t o0 = (uint32_t)w * L32 + it + (uint32_t)lane;
-        uint32_t key[kCountBatch];
-        int32_t rank[kCountBatch];
-        key_rank_seg<kCountBatch>(a.g, xs, ys, zs, a.count, o0, stride, n, lane, key, rank, bad);
+        uint32_t key[J];
+        int32_t rank[J];
+        bool valid[J];
+#pragma unroll
+        for (int j = 0; j < J; ++j) valid[j] = o0 + (uint32_t)j * stride < n;
+        group_keys<J>(a.g, px, py, pz, valid, key, bad);
+        const uint32_t nx = it + kWave;
+        if (nx < L32 && nx < n) load(nx);  // block-uniform; the positions are consumed
+        int my_head[J], old[J];
+        group_runs_issue<J>(a.count, key, valid, lane, my_head, old);
+        group_ranks<J>(my_head, old, lane, rank);
         if (a.cover) {
             uint32_t m[kCountBatch];
             unsigned mine = 0;
