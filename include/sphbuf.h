@@ -28,8 +28,10 @@
  *     an update leaves every particle array and the library's own counters as
  *     they were (checks run on the GPU before the first write).
  *   - A context is bound to one HIP stream and is not thread-safe.  All device
- *     work of a context is enqueued on that stream.  Calls marked "sync" wait for
- *     the stream; the others only enqueue.
+ *     work of a context is ordered on that stream (with SPHBUF_UPDATE=overlap a
+ *     build's scan and scatter run on a library-owned side stream that later calls
+ *     join back with an event).  Calls marked "sync" wait for the stream; the
+ *     others only enqueue.
  *   - The library allocates its device scratch in sph_create and
  *     sph_buffer_define; build and update calls allocate nothing.
  */
@@ -120,7 +122,8 @@ sph_status sph_destroy(sph_ctx *ctx);
  * cell cover of the check region, guard band), then one small upload.
  * Errors: SPH_ERR_ARG (kind, non-positive or non-finite extents, a check region
  * wider than 2^20 cells), SPH_ERR_ROTATION, SPH_ERR_OVERLAP (check regions of two
- * buffers intersect), SPH_ERR_TOO_MANY_BUFFERS.  *buffer_id receives 1..15. */
+ * buffers intersect), SPH_ERR_TOO_MANY_BUFFERS.  *buffer_id receives 1..15.
+ * The next update needs a cell list built after this call. */
 sph_status sph_buffer_define(sph_ctx *ctx, sph_kind kind, const double origin[3], const double rot[9],
                              const double half[3], double margin, int32_t *buffer_id);
 
