@@ -1150,11 +1150,12 @@ struct FullArgs {
 };
 
 // FP32 check-region test widened by the guard band: true for every member of C_k.
+// (The caller first tests the axis-aligned box bmin..bmax, rounded outward: it
+// never drops a member, and a NaN coordinate fails it.)
 __device__ __forceinline__ bool near_region(const BufDev &b, int dim, float x, float y, float z) {
     const float d0 = (x - b.ohi[0]) - b.olo[0];
     const float d1 = (y - b.ohi[1]) - b.olo[1];
     const float d2 = dim == 3 ? (z - b.ohi[2]) - b.olo[2] : 0.0f;
-    if (d0 * d0 + d1 * d1 + d2 * d2 > b.rsq) return false;
     const float l0 = b.qf[0] * d0 + b.qf[1] * d1 + b.qf[2] * d2;
     const float l1 = b.qf[3] * d0 + b.qf[4] * d1 + b.qf[5] * d2;
     const float l2 = b.qf[6] * d0 + b.qf[7] * d1 + b.qf[8] * d2;
@@ -1209,14 +1210,21 @@ __global__ __launch_bounds__(kClassifyBlock) void k_filter_full(FullArgs a) {
         unsigned long long bits = 0ull;
         unsigned mine = 0;
 #pragma unroll
-        for (int c = 0; c < kVec; ++c) {
-            if (i0 + c >= s1) continue;
-            bad |= !(isfinite(px[c]) && isfinite(py[c]) && isfinite(pz[c]));
-            for (int k = 0; k < a.nb; ++k)
-                if (near_region(sb[k], dim, px[c], py[c], pz[c])) {
+        for (int c = 0; c < kVec; ++c)
+            if (i0 + c < s1) bad |= !(isfinite(px[c]) && isfinite(py[c]) && isfinite(pz[c]));
+        for (int k = 0; k < a.nb; ++k) {  // buffer outer: its box is read once for all kVec particles
+            const BufDev &b = sb[k];
+            const float x0 = b.bmin[0], x1 = b.bmax[0], y0 = b.bmin[1], y1 = b.bmax[1], z0 = b.bmin[2],
+                        z1 = b.bmax[2];
+#pragma unroll
+            for (int c = 0; c < kVec; ++c) {
+                const bool in_box = i0 + c < s1 && px[c] > x0 && px[c] < x1 && py[c] > y0 && py[c] < y1 &&
+                                    pz[c] > z0 && pz[c] < z1;
+                if (in_box && near_region(b, dim, px[c], py[c], pz[c])) {
                     bits |= 1ull << (16 * c + k);
                     ++mine;
                 }
+            }
         }
         unsigned incl = mine;  // lane prefix of the candidate counts
         for (int off = 1; off < kWave; off <<= 1) {
@@ -2624,6 +2632,20 @@ static BufDev frame_record(const sph_ctx *ctx, int kind, const double o[3], cons
     b.guard = (float)sphbuf::guard_band(dim, o, h, margin, ctx->cs, ctx->dp);
     const double R = sphbuf::sphere_radius(dim, h, margin);
     b.rsq = (float)(R * R);
+    // x - O' = Q^T r': a member's global offset along axis g is below
+    // sum_i |Q_ig| (h_i + margin); the guard band and a relative 1e-6 on top
+    for (int g = 0; g < 3; ++g) {
+        if (g >= dim) {
+            b.bmin[g] = -INFINITY;
+            b.bmax[g] = INFINITY;
+            continue;
+        }
+        double ext = 0.0;
+        for (int i = 0; i < dim; ++i) ext += std::fabs(q[3 * i + g]) * (h[i] + margin);
+        ext = (ext + dim * (double)b.guard) * (1.0 + 1e-6);
+        b.bmin[g] = std::nextafter((float)(o[g] - ext), -INFINITY);
+        b.bmax[g] = std::nextafter((float)(o[g] + ext), INFINITY);
+    }
     b.kind = (int32_t)kind;
     return b;
 }

@@ -38,6 +38,8 @@ struct BufDev {
     int32_t pad2_;
     double bc_u;      // velocity BC: speed scale of the profile along X'
     double bc_radius; // velocity BC: radius R of the parabolic profiles
+    float bmin[3];    // axis-aligned box holding the check region, rounded outward in FP32
+    float bmax[3];    // (+-inf on the axes a 2-D domain does not have)
 };
 
 }  // namespace sphbuf
