@@ -105,6 +105,46 @@ def test_sprinkler_rotating_inlet():
     d.close()
 
 
+def _turn(axis, theta):
+    """Rotation by theta about the unit vector axis (input matrix handed to both sides)."""
+    n = np.asarray(axis, dtype=np.float64)
+    n = n / np.linalg.norm(n)
+    k = np.array([[0.0, -n[2], n[1]], [n[2], 0.0, -n[0]], [-n[1], n[0], 0.0]])
+    return math.cos(theta) * np.eye(3) + math.sin(theta) * k + (1.0 - math.cos(theta)) * np.outer(n, n)
+
+
+def test_pipe_inlet_turning_in_3d():
+    """Section 5.3's rigid turn of a buffer, in 3-D about an oblique axis through the
+    inlet's origin, every step of a VIPO pipe: update, boundary conditions, advection,
+    turn -- each against the oracle."""
+    wl, bcs, fields = _vipo_pipe()
+    bufs = oracle_buffers(wl)
+    st = oracle_state(wl)
+    d = make_domain(wl, bufs, st)
+    _set_bcs(d, bcs, fields)
+    assert oracle.identify(bufs, st, -1)[0] == 0 and d.identify(-1) == 0
+    m = _turn((1.0, 1.0, 0.3), math.radians(0.25))
+    center = tuple(bufs[0].origin)
+    for step in range(24):
+        W.advect_host(wl, st.pos, st.n, step)
+        upload_state(d, st)
+        d.build()
+        gst, g, dl = d.update()
+        res = oracle.update(bufs, st, bcs, fields)
+        assert gst == res.status == 0, (step, gst, res.status)
+        np.testing.assert_array_equal(d.events()[1], res.gen)
+        np.testing.assert_array_equal(d.events()[2], res.dele)
+        d.build()
+        assert d.apply_bc() == oracle.apply_bc(bufs, bcs, fields, st) == 0
+        d.build()
+        assert d.rotate(1, center, m) == oracle.rotate_buffer(bufs, 1, center, m, fields, st) == 0
+        assert_same_state(d, st, f"step {step} turn")
+    # the inlet's axis turned by up to 24 times the step angle about the oblique axis
+    ang = math.degrees(math.acos(np.clip(np.dot(bufs[0].rot[0], oracle_buffers(wl)[0].rot[0]), -1.0, 1.0)))
+    assert 0.5 < ang < 6.5
+    d.close()
+
+
 def test_apply_bc_reports_buffer_particles_outside_the_check_region():
     I3 = np.eye(3)
     bufs = [oracle.Buffer(oracle.INLET, (0.5, 0.5, 0), I3, (0.5, 0.5, 0), 0.25)]
