@@ -145,6 +145,32 @@ def test_pipe_inlet_turning_in_3d():
     d.close()
 
 
+def test_pipe3d_full_size_boundary_conditions():
+    """The benchmark's pipe (dp = 0.001, 7.86 M particles, its launch configuration):
+    velocity inlet with the pipe profile and pressure outlet, two steps of update +
+    boundary conditions, every array against the oracle."""
+    wl = W.pipe3d()
+    bcs = [oracle.BC(oracle.BC_VELOCITY, oracle.PROFILE_PARABOLIC_R, u=1.0, radius=0.05),
+           oracle.BC(oracle.BC_PRESSURE, p_b=0.0, rho0=1000.0, c0=10.0)]
+    fields = oracle.Fields(vel=(0, 1, 2), rho=4)
+    bufs = oracle_buffers(wl)
+    st = oracle_state(wl)
+    d = make_domain(wl, bufs, st)
+    _set_bcs(d, bcs, fields)
+    assert oracle.identify(bufs, st, -1)[0] == 0 and d.identify(-1) == 0
+    for step in range(2):
+        W.advect_host(wl, st.pos, st.n, step)
+        upload_state(d, st)
+        d.build()
+        gst, g, dl = d.update()
+        res = oracle.update(bufs, st, bcs, fields)
+        assert gst == res.status == 0, (step, gst, res.status)
+        d.build()
+        assert d.apply_bc() == oracle.apply_bc(bufs, bcs, fields, st) == 0
+        assert_same_state(d, st, f"step {step}")
+    d.close()
+
+
 def test_apply_bc_reports_buffer_particles_outside_the_check_region():
     I3 = np.eye(3)
     bufs = [oracle.Buffer(oracle.INLET, (0.5, 0.5, 0), I3, (0.5, 0.5, 0), 0.25)]

@@ -94,3 +94,9 @@ def test_unconsumed_builds_and_interleaved_calls(monkeypatch):
             np.testing.assert_array_equal(cs, ref_s)
             _check_update(d, bufs, st, f"step {step}: cell-list view before the update")
     d.close()
+
+
+def test_overlapped_step_full_size(monkeypatch):
+    """The overlapped step on the benchmark's pipe (7.86 M particles), two steps."""
+    _mode(monkeypatch, "overlap")
+    _run_steps(W.pipe3d(), 2)
