@@ -166,6 +166,14 @@ def test_bent_channel_40_steps(mode):
     assert g > 0
 
 
+def test_bent_channel_1000_steps():
+    """The non-orthogonal channel (inlet at +30 deg, outlet at -45 deg, 206 k
+    particles) for 1,000 steps of the local-cell path: events every step, every
+    array every 100 steps."""
+    g, dl = _run_steps(W.bent_channel2d(), 1000, check_every=100)
+    assert g > 1000 and dl > 1000
+
+
 @pytest.mark.parametrize("mode", ["local", "fullscan"])
 def test_pipe3d_small_40_steps(mode):
     # dp = 0.004 (about 122k particles): several cells across, ragged tails
