@@ -181,6 +181,13 @@ def test_pipe3d_small_40_steps(mode):
     assert g > 0
 
 
+def test_pipe3d_small_500_steps():
+    """The 3-D pipe scaled to dp = 0.004 (122 k particles) for 500 steps of the
+    local-cell path: events every step, every array every 50 steps."""
+    g, dl = _run_steps(W.pipe3d(dp=0.004), 500, check_every=50)
+    assert g > 1000 and dl > 1000
+
+
 def test_grid_independence_of_local_path():
     # cell size 1.3 dp and 5.2 dp give the same events as the oracle (no grid)
     wl = W.channel2d()
