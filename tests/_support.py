@@ -57,3 +57,27 @@ def make_state(dim: int, pts: np.ndarray, capacity: int = None, carried: int = 2
 def local(dim: int, buf: oracle.Buffer, st: oracle.State) -> np.ndarray:
     n = st.n
     return oracle.local_coords(dim, buf, st.pos[0][:n], st.pos[1][:n], st.pos[2][:n] if dim == 3 else None)
+
+
+_KINDS = {"inlet": oracle.INLET, "outlet": oracle.OUTLET, "bidir": oracle.BIDIR}
+
+
+def golden_cases(name: str = "hand_examples.json"):
+    """Cases of a golden fixture under tests/golden/: (case dict, oracle buffers,
+    fresh host state).  Frames come from the oracle's own constructions of the
+    printed angle or direction."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
+    data = json.load(open(path))
+    out = []
+    for c in data["cases"]:
+        bufs = []
+        for b in c["buffers"]:
+            rot = oracle.rotation_2d(b["angle"]) if "angle" in b else oracle.rotation_from_direction(b["direction"])
+            bufs.append(oracle.Buffer(_KINDS[b["kind"]], tuple(b["origin"]), rot, tuple(b["half"]), b["margin"]))
+        pts = [p["pos"] for p in c["particles"]]
+        labels = [p["label"] for p in c["particles"]]
+        st = make_state(c["dim"], pts, capacity=c["capacity"], labels=labels, next_id=c["next_id"], carried=3)
+        out.append((c, bufs, st))
+    return out

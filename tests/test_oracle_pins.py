@@ -21,7 +21,7 @@ from scipy.spatial.transform import Rotation
 
 import oracle
 import workloads as W
-from tests._support import local, make_state, oracle_buffers, oracle_state
+from tests._support import golden_cases, local, make_state, oracle_buffers, oracle_state
 
 I3 = np.eye(3)
 
@@ -120,68 +120,25 @@ def _inlet_outlet_2d():
     return [inlet, outlet]
 
 
-def test_hand_example_inlet_outlet_2d():
-    # inlet box x in (0,1), check region x in (-.25, 1.25); outlet box x in (4,5),
-    # check region x in (3.75, 5.25); all with |y - .5| small.
-    pts = [(0.25, 0.5),   # 0 inlet particle, X' = -.25: nothing
-           (1.125, 0.5),  # 1 inlet particle, X' = .625 > a/2: duplicate + recycle to .125
-           (2.0, 0.5),    # 2 fluid in between: nothing
-           (4.25, 0.5),   # 3 fluid inside the outlet box: relabelled 2
-           (5.125, 0.5),  # 4 X' = .625 > a/2 at the outlet: deleted
-           (5.5, 0.5),    # 5 beyond the check region: not a candidate
-           (3.875, 0.5),  # 6 labelled 2 but outside the outlet box: back to 0
-           (0.75, 0.5)]   # 7 inlet particle, X' = .25: nothing
-    st = make_state(2, pts, capacity=12, labels=[1, 1, 0, 0, 2, 0, 2, 1], next_id=100)
-    res = oracle.update(_inlet_outlet_2d(), st)
+@pytest.mark.parametrize("case", range(3))
+def test_hand_examples(case):
+    """tests/golden/hand_examples.json: three updates worked out by hand (an inlet and
+    an outlet in 2-D, a bidirectional buffer under a quarter turn, a 3-D frame along
+    e_z), every particle's fate, layout and id against the oracle."""
+    c, bufs, st = golden_cases()[case]
+    e = c["expect"]
+    res = oracle.update(bufs, st)
     assert res.status == oracle.OK
-    assert list(res.gen) == [1] and list(res.dele) == [4]
-    assert st.n == 8 and st.next_id == 101
-    # slot 4 (deleted) is refilled from slot 7; the duplicate of 1 is appended at 7
-    exp_x = [0.25, 0.125, 2.0, 4.25, 0.75, 5.5, 3.875, 1.125]
-    np.testing.assert_array_equal(st.pos[0][:8], np.float32(exp_x))
-    np.testing.assert_array_equal(st.pos[1][:8], np.float32([0.5] * 8))
-    assert list(st.label[:8]) == [1, 1, 0, 2, 1, 0, 0, 0]
-    assert list(st.id[:8]) == [0, 1, 2, 3, 7, 5, 6, 100]
-    np.testing.assert_array_equal(st.carried[0][:8], np.float32([0, 10, 20, 30, 70, 50, 60, 10]))
-    np.testing.assert_array_equal(st.carried[1][:8], np.float32([1, 11, 21, 31, 71, 51, 61, 11]))
-    assert list(res.n_labelled) == [3, 1]
-
-
-def test_hand_example_bidirectional_quarter_turn_2d():
-    # X' = y, Y' = -x (theta = 90 deg); box |y| < .5, |x| < 1; check |y| < .75, |x| < 1.25
-    b = oracle.Buffer(oracle.BIDIR, (0, 0, 0), oracle.rotation_2d(math.pi / 2), (0.5, 1.0, 0), 0.25)
-    pts = [(0.5, 0.625),   # 0 buffer particle, X' > a/2: duplicate, recycle y -> -.375
-           (0.25, -0.625),  # 1 buffer particle, X' < -a/2: deleted
-           (-0.5, 0.25),   # 2 fluid inside the box: relabelled 1
-           (1.125, 0.0),   # 3 buffer particle laterally outside the box: back to 0
-           (0.0, 2.0),     # 4 far away: untouched
-           (0.5, 0.7)]     # 5 fluid past the threshold but not a buffer particle: untouched
-    st = make_state(2, pts, capacity=8, labels=[1, 1, 0, 1, 0, 0], next_id=50)
-    res = oracle.update([b], st)
-    assert res.status == oracle.OK
-    assert list(res.gen) == [0] and list(res.dele) == [1]
-    assert st.n == 6
-    np.testing.assert_array_equal(st.pos[0][:6], np.float32([0.5, 0.5, -0.5, 1.125, 0.0, 0.5]))
-    np.testing.assert_array_equal(st.pos[1][:6], np.float32([-0.375, 0.7, 0.25, 0.0, 2.0, 0.625]))
-    assert list(st.label[:6]) == [1, 0, 1, 0, 0, 0]
-    assert list(st.id[:6]) == [0, 5, 2, 3, 4, 50]
-    assert list(res.n_labelled) == [2]
-
-
-def test_hand_example_3d_frame_along_z():
-    # d = e_z: X' = z, Y' = y, Z' = -x.  Box |z| < .5, |y| < 1, |x| < 2.
-    q = oracle.rotation_from_direction([0, 0, 1])
-    b = oracle.Buffer(oracle.INLET, (0, 0, 0), q, (0.5, 1.0, 2.0), 0.25)
-    pts = [(1.5, 0.5, 0.625),   # 0 X' = .625: duplicate, recycle z -> -.375
-           (2.125, 0.0, 0.0),   # 1 |Z'| = 2.125 in the check region only: nothing
-           (0.0, 1.125, 0.0),   # 2 |Y'| = 1.125 in the check region only: nothing
-           (0.0, 0.0, 0.75)]    # 3 fluid with X' = .75 (outside the check region)
-    st = make_state(3, pts, capacity=6, labels=[1, 1, 1, 0], next_id=9)
-    res = oracle.update([b], st)
-    assert res.status == oracle.OK and list(res.gen) == [0] and list(res.dele) == []
-    np.testing.assert_array_equal(st.pos[2][:5], np.float32([-0.375, 0, 0, 0.75, 0.625]))
-    np.testing.assert_array_equal(st.pos[0][:5], np.float32([1.5, 2.125, 0, 0, 1.5]))
-    assert list(st.label[:5]) == [1, 1, 1, 0, 0] and list(st.id[:5]) == [0, 1, 2, 3, 9]
+    assert list(res.gen) == e["gen"] and list(res.dele) == e["del"]
+    assert st.n == e["n"] and st.next_id == e["next_id"]
+    n = st.n
+    for ax in range(c["dim"]):
+        np.testing.assert_array_equal(st.pos[ax][:n], np.float32(e["pos"][ax]))
+    assert list(st.label[:n]) == e["label"]
+    assert list(st.id[:n]) == e["id"]
+    for f in range(3):
+        np.testing.assert_array_equal(st.carried[f][:n], np.float32([10 * s_ + f for s_ in e["source"]]))
+    assert list(res.n_labelled) == e["n_labelled"]
 
 
 def test_identification_labels_box_particles_only():

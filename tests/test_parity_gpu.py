@@ -15,7 +15,7 @@ import pytest
 import oracle
 import workloads as W
 from tests._gpu import assert_same_state, make_domain, make_domain_raw, upload_state
-from tests._support import local, make_state, oracle_buffers, oracle_state
+from tests._support import golden_cases, local, make_state, oracle_buffers, oracle_state
 
 pytestmark = pytest.mark.gpu
 
@@ -230,16 +230,36 @@ def _identify_counts(d, bufs, st):
     assert S.sph_state_set(d.ctx, st.next_id, nl) == 0
 
 
-def test_hand_example_on_gpu():
-    pts = [(0.25, 0.5), (1.125, 0.5), (2.0, 0.5), (4.25, 0.5), (5.125, 0.5), (5.5, 0.5), (3.875, 0.5), (0.75, 0.5)]
-    wl, bufs, st = _two_buffer_case(pts, [1, 1, 0, 0, 2, 0, 2, 1], capacity=12)
-    d = make_domain(wl, bufs, st)
+@pytest.mark.parametrize("mode", ["local", "fullscan"])
+@pytest.mark.parametrize("case", range(3))
+def test_hand_examples_on_gpu(case, mode):
+    """tests/golden/hand_examples.json through the library: the hand-worked events,
+    layout, ids and carried fields, both update paths."""
+    c, bufs, st = golden_cases()[case]
+    e = c["expect"]
+    dim = c["dim"]
+    pts = np.array([p["pos"] for p in c["particles"]])
+    lo = [float(pts[:, a].min()) - 1.5 for a in range(dim)] + [0.0] * (3 - dim)
+    hi = [float(pts[:, a].max()) + 1.5 for a in range(dim)] + [0.0] * (3 - dim)
+    d = make_domain_raw(dim, tuple(lo), tuple(hi), 0.3, 0.1, bufs, st)
     _identify_counts(d, bufs, st)
-    d.build()
-    gst, g, dl = d.update()
-    res = oracle.update(bufs, st)
-    assert gst == 0 and list(res.gen) == [1] and list(res.dele) == [4]
-    assert_same_state(d, st, "hand example")
+    if mode == "local":
+        d.build()
+        gst, g, dl = d.update()
+    else:
+        gst, g, dl = d.update_fullscan()
+    assert gst == 0
+    _, gg, dd = d.events()
+    assert list(gg) == e["gen"] and list(dd) == e["del"]
+    pos, car, lab, ids, n = d.download()
+    assert n == e["n"]
+    for ax in range(dim):
+        np.testing.assert_array_equal(pos[ax][:n], np.float32(e["pos"][ax]))
+    assert list(lab[:n]) == e["label"] and list(ids[:n]) == e["id"]
+    for f in range(3):
+        np.testing.assert_array_equal(car[f][:n], np.float32([10 * s_ + f for s_ in e["source"]]))
+    rs, r = d.result()
+    assert r.next_id == e["next_id"] and list(r.n_labelled[: len(bufs)]) == e["n_labelled"]
     d.close()
 
 
