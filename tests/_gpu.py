@@ -2,13 +2,12 @@
 inputs (and the oracle's own frames) as the FP64 oracle, plus comparisons."""
 from __future__ import annotations
 
-from typing import List, Sequence
+from typing import Sequence
 
 import numpy as np
 
 import oracle
-import workloads as W
-from tests._support import oracle_buffers, oracle_state
+from tests._support import oracle_state
 
 
 def make_domain_raw(dim, lo, hi, cell_size, dp, bufs: Sequence[oracle.Buffer], st: oracle.State,
@@ -44,15 +43,3 @@ def assert_same_state(d, st: oracle.State, what: str = "") -> None:
         np.testing.assert_array_equal(car[f][:n], st.carried[f][:n], err_msg=f"{what}: carried[{f}]")
     np.testing.assert_array_equal(lab[:n], st.label[:n], err_msg=f"{what}: label")
     np.testing.assert_array_equal(ids[:n], st.id[:n], err_msg=f"{what}: id")
-
-
-def step_both(d, bufs, st: oracle.State, mode: str = "local"):
-    """One update on the GPU (local or full scan) and on the oracle; returns both."""
-    from paper_2406_16786_amd import sphbuf as S
-    if mode == "local":
-        d.build()
-        gst, g, dl = d.update()
-    else:
-        gst, g, dl = d.update_fullscan()
-    res = oracle.update(bufs, st)
-    return gst, g, dl, res

@@ -9,7 +9,6 @@ Rotating buffer: the rotation step of the sprinkler (Section 5.3).
 import math
 
 import numpy as np
-import pytest
 
 import oracle
 from tests._support import make_state

@@ -6,7 +6,6 @@ and the counts balance (N' = N - |D| + |G|, ids stay unique)."""
 import math
 
 import numpy as np
-import pytest
 from hypothesis import HealthCheck, given, settings
 from hypothesis import strategies as st
 
