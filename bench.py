@@ -71,6 +71,13 @@ class Snapshot:
         return self.pos + self.carried + [self.label, self.id, self.n_dev]
 
 
+PATHS = {
+    "cells": "cell-list build + local-cell update",
+    "overlap": "cell-list build gathering the cover cells' particles + their update beside the scan and scatter",
+    "merged": "cell-list build classifying the cover cells' particles in its count pass + finalize beside the scan",
+}
+
+
 def phase_bytes(dim: int, n: int, n_cells: int, cand: int, g: int, d: int, n_carried: int):
     """Algorithmic bytes per launch of each kernel phase (what the step must move)."""
     state = 4 * dim + 4 * n_carried + 4 + 8          # bytes of one particle's state
@@ -270,6 +277,8 @@ def main() -> int:
     ap.add_argument("--no-neighbor", action="store_true", help="skip the neighbour-search leg")
     ap.add_argument("--build", default=None, choices=["split", "fused"],
                     help="cell-list build variant (default: the library's)")
+    ap.add_argument("--update", default=None, choices=["cells", "overlap", "merged"],
+                    help="update path (default: the library's cover-cell walk)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
@@ -278,6 +287,10 @@ def main() -> int:
 
     if args.build:
         os.environ["SPHBUF_BUILD"] = args.build
+    if args.update in ("overlap", "merged"):
+        os.environ["SPHBUF_UPDATE"] = args.update
+    elif args.update == "cells":
+        os.environ.pop("SPHBUF_UPDATE", None)
     import numpy as np
     import torch
 
@@ -326,15 +339,14 @@ def main() -> int:
         f"G={np.mean([x[2] for x in n_list]):.0f} D={np.mean([x[3] for x in n_list]):.0f}")
 
     # ---- candidate count of the local path (for the classify bytes) ----
-    _, cs_ptr, _, n_cells, dims = S.sph_celllist_view(dom.ctx)
     cand = 0
-    start = torch.zeros(n_cells + 1, dtype=torch.int32, device=dev)
     # rebuild on the first state to read its cell starts
     work0 = Snapshot(dom, torch)
     for dst, src in zip(work0.tensors(), snaps[0].tensors()):
         dst.copy_(src)
     p0 = S.particles_from_tensors(work0.pos, work0.carried, work0.label, work0.id, work0.n_dev)
     S.check(S.sph_celllist_build(dom.ctx, p0), "build")
+    _, cs_ptr, _, n_cells, dims = S.sph_celllist_view(dom.ctx)  # (completes a merged build's cell list)
     stream.synchronize()
     import ctypes
     hip = ctypes.CDLL("libamdhip64.so")
@@ -467,7 +479,7 @@ def main() -> int:
                    if wl.name == "pipe3d" else wl.name,
                    "n_particles": int(n_mean), "dim": wl.dim, "buffers": len(wl.buffers), "cells": int(n_cells),
                    "candidates_per_update": cand, "events_per_step": {"generated": g_mean, "deleted": d_mean},
-                   "particle_order": args.order, "path": "cell-list build + local-cell update"},
+                   "particle_order": args.order, "path": PATHS[args.update or "cells"]},
         "pct_hbm_peak_step": round(step_bytes / (ms_local * 1e-3) / 1e9 / HBM_PEAK_GBS * 100, 2),
         "fullscan": {"ms_per_update": round(ms_full, 5),
                      "Mparticles_per_s": round(n_mean / (ms_full * 1e-3) / 1e6, 1)},

@@ -106,6 +106,7 @@ struct Ctl {
     unsigned int ident_bad;
     unsigned int pad1;
     unsigned long long ident_count[16];
+    int64_t n_built;               // particles of the latest count pass (what its scatter places)
 };
 
 // ------------------------------------------------------------ device utils --
@@ -484,6 +485,8 @@ __device__ __forceinline__ T &at32(T *base, uint32_t o) {
 
 constexpr int kCountBatch = 2;
 constexpr int64_t kCountPer = 2048;  // particles per count workgroup (single domain)
+constexpr int kClsList = 2048;       // classifying count pass: particles per workgroup at most
+constexpr int kClsStash = 384;       // ... of which keep their position and label in LDS
 
 struct CountArgs {
     const float *x, *y, *z;
@@ -504,8 +507,17 @@ struct CountArgs {
     const uint16_t *cover;
     unsigned long long *cand;
     int64_t seg_cap;
+    // classification during the count (cls != 0, cover set, cand null): every
+    // particle whose cell is in buffer k's cover is tested against buffer k here
+    // and its events emitted, so that the update only has to finalize them
+    int cls;
+    int nb;
+    Parts p;
+    const BufDev *bufs;
+    EventArgs e;
 };
 
+template <bool kCls>  // the merged step's classification compiled in (its own kernel: registers)
 __device__ __forceinline__ void count_body(const CountArgs &a, const int lb, const int G) {
     const int64_t N = live_count(a.n_dev, a.capacity);
     const int lane = threadIdx.x & (kWave - 1);
@@ -515,65 +527,139 @@ __device__ __forceinline__ void count_body(const CountArgs &a, const int lb, con
     if (lb == 0 && threadIdx.x == 0) {
         a.ctl->tile_counter = 0u;
         a.ctl->scan_fault = 0u;
+        a.ctl->n_built = N;
     }
-    // each logical block walks one contiguous segment, cut into one slice per wave
-    // and row (kCountBatch rows per wave): at every step the block's waves take the
-    // next 64 particles of each of their slices, so the particles whose atomics are
-    // in flight together lie a slice apart -- beyond the few lattice rows that share
-    // a cell -- and rarely meet on one counter (same-address atomics queue at the
-    // memory side)
-    const int W = (int)(blockDim.x / kWave), w = (int)(threadIdx.x / kWave);
+    // classification: the block's particles in cover cells, as (offset << 16 | cover
+    // bits), classified after the count loop (its registers are free by then); the
+    // first kClsStash of them keep their position and label here too
+    __shared__ uint32_t s_cl[kClsList];
+    __shared__ float s_px[kClsStash], s_py[kClsStash], s_pz[kClsStash];
+    __shared__ int32_t s_lab[kClsStash];
+    __shared__ unsigned s_ncl;
+    __shared__ unsigned s_cnt[2 * SPH_MAX_BUFFERS];  // label counts of the classification
+    __shared__ BufDev s_b[SPH_MAX_BUFFERS];
+    if constexpr (kCls) {
+        block_counts_init(s_cnt);
+        if (threadIdx.x == 0) s_ncl = 0u;
+        for (int t = threadIdx.x; t < a.nb * (int)(sizeof(BufDev) / 4); t += blockDim.x)
+            reinterpret_cast<uint32_t *>(s_b)[t] = reinterpret_cast<const uint32_t *>(a.bufs)[t];
+        __syncthreads();
+    }
+    // Each logical block walks kCountBatch * W slices of L particles, one per wave and
+    // row (kCountBatch rows per wave): at every step the block's waves take the next
+    // 64 particles of each of their slices, so the particles whose atomics are in
+    // flight together lie a slice apart -- beyond the few lattice rows that share a
+    // cell -- and rarely meet on one counter (same-address atomics queue at the
+    // memory side).  The plain pass cuts one contiguous segment of the block into
+    // its slices; the classifying pass takes slice q of block lb at (q * G + lb) * L,
+    // so the particles of a buffer's cover (a contiguous stretch of a spatially
+    // ordered array) spread over many workgroups instead of crowding a few.
+    const int W = (int)(blockDim.x / kWave);
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));  // uniform: scalar row bases
     const int64_t slices = (int64_t)W * kCountBatch;
     const int64_t per = ((N + G - 1) / G + slices * kWave - 1) / (slices * kWave) * (slices * kWave);
     const int64_t L = per / slices;
     const int64_t s0 = (int64_t)lb * per;
-    const int64_t s1 = min(N, s0 + per);
     bool bad = false;
     const uint32_t rmask = (1u << a.rbits) - 1u;
-    if (s0 >= s1) return;
-    // segment-relative 32-bit offsets (a segment is far below 2^29 particles)
-    const uint32_t n = (uint32_t)(s1 - s0), L32 = (uint32_t)L, stride = (uint32_t)W * L32;
-    const float *xs = a.x + s0, *ys = a.y + s0, *zs = a.g.dim == 3 ? a.z + s0 : a.x + s0;
-    uint32_t *ps = a.packed + s0;
-    unsigned long long *ss = a.spill + s0;
+    if ((kCls ? (int64_t)lb * L : s0) >= N) return;  // block-uniform: no particle here
+    constexpr int J = kCountBatch;
+    const uint32_t L32 = (uint32_t)L;
+    // per row: first particle, particles in it (slice-relative 32-bit offsets from
+    // uniform base pointers)
+    int64_t rb[J];
+    uint32_t nr[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const int64_t q = (int64_t)j * W + w;
+        rb[j] = kCls ? (q * G + lb) * L : s0 + q * L;
+        const int64_t left = N - rb[j];
+        nr[j] = left <= 0 ? 0u : (left >= L ? L32 : (uint32_t)left);
+    }
+    const bool d3 = a.g.dim == 3;
+    const float *xr[J], *yr[J], *zr[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        xr[j] = a.x + rb[j];
+        yr[j] = a.y + rb[j];
+        zr[j] = d3 ? a.z + rb[j] : a.x + rb[j];
+    }
     // Software pipelined: once a step has its keys it issues the next step's position
     // loads, then its run detection and atomics, so the two round trips overlap.
-    constexpr int J = kCountBatch;
-    const bool d3 = a.g.dim == 3;
     float px[J], py[J], pz[J];
     auto load = [&](uint32_t it) {
-        const uint32_t o0 = (uint32_t)w * L32 + it + (uint32_t)lane;
+        const uint32_t o = it + (uint32_t)lane;
 #pragma unroll
         for (int j = 0; j < J; ++j) {
-            const uint32_t o = o0 + (uint32_t)j * stride;
             px[j] = py[j] = pz[j] = 0.0f;
-            if (o < n) {
-                px[j] = at32(xs, o);
-                py[j] = at32(ys, o);
-                if (d3) pz[j] = at32(zs, o);
+            if (o < nr[j]) {
+                px[j] = at32(xr[j], o);
+                py[j] = at32(yr[j], o);
+                if (d3) pz[j] = at32(zr[j], o);
             }
         }
     };
     load(0);
-    for (uint32_t it = 0; it < L32 && it < n; it += kWave) {
-        const uint32_t o0 = (uint32_t)w * L32 + it + (uint32_t)lane;
+    for (uint32_t it = 0; it < L32; it += kWave) {
+        const uint32_t o = it + (uint32_t)lane;
         uint32_t key[J];
         int32_t rank[J];
         bool valid[J];
 #pragma unroll
-        for (int j = 0; j < J; ++j) valid[j] = o0 + (uint32_t)j * stride < n;
+        for (int j = 0; j < J; ++j) valid[j] = o < nr[j];
         group_keys<J>(a.g, px, py, pz, valid, key, bad);
+        // classification: the cover bits are loaded before the next positions and the
+        // atomics, so waiting for them waits for nothing else
+        uint32_t cm[J];
+        float cx[J], cy[J], cz[J];
+        if constexpr (kCls) {
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                cm[j] = valid[j] ? a.cover[key[j]] : 0u;
+                cx[j] = px[j];
+                cy[j] = py[j];
+                cz[j] = pz[j];
+            }
+        }
         const uint32_t nx = it + kWave;
-        if (nx < L32 && nx < n) load(nx);  // block-uniform; the positions are consumed
+        if (nx < L32) load(nx);  // block-uniform; the positions are consumed
         int my_head[J], old[J];
         group_runs_issue<J>(a.count, key, valid, lane, my_head, old);
+        if constexpr (kCls) {  // the particles in some cover cell join the block's list
+            bool has[J];
+            bool any = false;
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                has[j] = cm[j] != 0u;
+                any = any || has[j];
+            }
+            if (__ballot(any) != 0ull) {  // wave-uniform
+#pragma unroll
+                for (int j = 0; j < J; ++j) {
+                    const unsigned long long mj = __ballot(has[j]);
+                    if (mj == 0ull) continue;
+                    unsigned at = 0u;
+                    if (lane == 0) at = atomicAdd(&s_ncl, (unsigned)__popcll(mj));
+                    at = __shfl(at, 0) + mbcnt(mj);
+                    if (has[j]) {
+                        s_cl[at] = (((uint32_t)(j * W + w) * L32 + o) << 16) | cm[j];
+                        if (at < (unsigned)kClsStash) {  // label load in flight with the atomics
+                            s_px[at] = cx[j];
+                            s_py[at] = cy[j];
+                            s_pz[at] = cz[j];
+                            s_lab[at] = at32(a.p.label + rb[j], o);
+                        }
+                    }
+                }
+            }
+        }
         group_ranks<J>(my_head, old, lane, rank);
-        if (a.cover) {
+        if (!kCls && a.cand) {
             uint32_t m[kCountBatch];
             unsigned mine = 0;
 #pragma unroll
             for (int j = 0; j < kCountBatch; ++j) {
-                m[j] = o0 + (uint32_t)j * stride < n ? a.cover[key[j]] : 0u;
+                m[j] = valid[j] ? a.cover[key[j]] : 0u;
                 mine += (unsigned)__popc(m[j]);
             }
             if (__ballot(mine != 0u) != 0ull) {  // wave-uniform
@@ -591,7 +677,7 @@ __device__ __forceinline__ void count_body(const CountArgs &a, const int lb, con
                 unsigned long long *dst = a.cand + (int64_t)sg * a.seg_cap;
 #pragma unroll
                 for (int j = 0; j < kCountBatch; ++j) {
-                    const int64_t i = s0 + (int64_t)(o0 + (uint32_t)j * stride);
+                    const int64_t i = rb[j] + (int64_t)o;
                     uint32_t mm = m[j];
                     while (mm) {
                         const int k = __ffs(mm) - 1;
@@ -607,20 +693,69 @@ __device__ __forceinline__ void count_body(const CountArgs &a, const int lb, con
         }
 #pragma unroll
         for (int j = 0; j < kCountBatch; ++j) {
-            const uint32_t o = o0 + (uint32_t)j * stride;
-            if (o >= n) continue;
+            if (!valid[j]) continue;
             if ((uint32_t)rank[j] < rmask) {
-                at32(ps, o) = (key[j] << a.rbits) | (uint32_t)rank[j];
+                at32(a.packed + rb[j], o) = (key[j] << a.rbits) | (uint32_t)rank[j];
             } else {
-                at32(ps, o) = 0xffffffffu;
-                at32(ss, o) = ((unsigned long long)key[j] << 32) | (unsigned)rank[j];
+                at32(a.packed + rb[j], o) = 0xffffffffu;
+                at32(a.spill + rb[j], o) = ((unsigned long long)key[j] << 32) | (unsigned)rank[j];
             }
         }
     }
     if (__ballot(bad) != 0ull && lane == 0) atomicOr(a.nonfinite, 1u);
+    if constexpr (kCls) {
+        __syncthreads();
+        const unsigned ncl = s_ncl;
+        if (ncl == 0u) return;  // block-uniform
+        const int dim = a.g.dim;
+        const int sg = (int)(((unsigned)lb * (unsigned)W + (unsigned)w) % (unsigned)kSeg);
+        for (unsigned e0 = 0; e0 < ncl; e0 += blockDim.x) {  // block-uniform trip count
+            const unsigned e = e0 + threadIdx.x;
+            const uint32_t ent = e < ncl ? s_cl[e] : 0u;
+            const uint32_t vo = ent >> 16;  // slice * L + offset in the slice
+            uint32_t bm = ent & 0xffffu;
+            const int64_t i = ((int64_t)(vo / L32) * G + lb) * L + (int64_t)(vo % L32);
+            float x = 0.0f, y = 0.0f, z = 0.0f;
+            int lab = 0;
+            if (bm && e < (unsigned)kClsStash) {
+                x = s_px[e];
+                y = s_py[e];
+                z = s_pz[e];
+                lab = s_lab[e];
+            } else if (bm) {
+                x = a.x[i];
+                y = a.y[i];
+                z = d3 ? a.z[i] : 0.0f;
+                lab = a.p.label[i];
+            }
+            while (__ballot(bm != 0u) != 0ull) {  // each lane's buffers in turn (the buffer varies per lane)
+                const bool c = bm != 0u;
+                const int k = c ? __ffs(bm) - 1 : 0;
+                bm &= bm - 1u;
+                const BufDev &b = s_b[k];
+                Outcome oc{kEvNone, -1, false};
+                if (c) {
+                    const unsigned bits = classify(b, dim, x, y, z);
+                    if (bits & kIn) oc = decide(b, k, dim, bits, lab, x, y, z);
+                }
+                unsigned long long found = 0, post = 0;
+                const float carv[SPH_MAX_CARRIED] = {};
+                emit<false>(a.e, a.p, b, k, sg, c, i, lab, oc, x, y, z, carv, found, post);
+                if (found) atomicAdd(&s_cnt[2 * k], 1u);
+                if (post) atomicAdd(&s_cnt[2 * k + 1], 1u);
+            }
+        }
+        __syncthreads();
+        block_counts_store(a.e, s_cnt, a.nb);
+    }
 }
 
-__global__ __launch_bounds__(kBuildBlock) void k_count(CountArgs a) { count_body(a, logical_block(), gridDim.x); }
+__global__ __launch_bounds__(kBuildBlock) void k_count(CountArgs a) { count_body<false>(a, logical_block(), gridDim.x); }
+
+// The count pass of the merged step (classification of the cover cells' particles).
+__global__ __launch_bounds__(kBuildBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_count_cls(CountArgs a) {
+    count_body<true>(a, logical_block(), gridDim.x);
+}
 
 // Decoupled look-back scan state: bits 62..63 = flag (1 aggregate, 2 prefix),
 // low 32 bits = value.
@@ -645,11 +780,18 @@ struct ScanArgs {
 // per-thread runs of kScanItems, wave and block scans, a decoupled look-back
 // over the preceding tiles (tile order from an atomic ticket, so a tile only
 // ever waits on tiles that started before it), and coalesced stores.
-__device__ __forceinline__ void scan_body(const ScanArgs &a) {
-    __shared__ unsigned s_tile;
-    __shared__ int s_wave[kScanBlock / kWave];
-    __shared__ int s_excl;
-    __shared__ int s_buf[kScanTile + kScanTile / 32];  // padded: index j at j + j / 32
+struct ScanLds {
+    unsigned tile;
+    int wave[kScanBlock / kWave];
+    int excl;
+    int buf[kScanTile + kScanTile / 32];  // padded: index j at j + j / 32
+};
+
+__device__ __forceinline__ void scan_body(const ScanArgs &a, ScanLds &L) {
+    unsigned &s_tile = L.tile;
+    auto &s_wave = L.wave;
+    int &s_excl = L.excl;
+    auto &s_buf = L.buf;
     if (threadIdx.x == 0) {
         s_tile = atomicAdd(&a.ctl->tile_counter, 1u);
         if (s_tile == 0u) {  // the count phase is complete: keep its verdict for the next update
@@ -740,7 +882,10 @@ __device__ __forceinline__ void scan_body(const ScanArgs &a) {
     }
 }
 
-__global__ __launch_bounds__(kScanBlock) void k_scan(ScanArgs a) { scan_body(a); }
+__global__ __launch_bounds__(kScanBlock) void k_scan(ScanArgs a) {
+    __shared__ ScanLds L;
+    scan_body(a, L);
+}
 
 struct ScatterArgs {
     const int64_t *n_dev;
@@ -1266,6 +1411,19 @@ __global__ void k_reset_cand(Ctl *ctl) {
     }
 }
 
+// Clears the events and label counts a classifying count pass emitted for an update
+// that will not finalize them (the state changed since, or a new build or a full
+// scan replaces them).  clear_nf: also its non-finite flag.
+__global__ void k_reset_events(Ctl *ctl, unsigned *part, int clear_nf) {
+    if (threadIdx.x < kSeg) {
+        ctl->seg[threadIdx.x].n_gen = 0u;
+        ctl->seg[threadIdx.x].n_del = 0u;
+        ctl->seg[threadIdx.x].n_rel = 0u;
+    }
+    if (threadIdx.x == 0 && clear_nf) ctl->nonfinite_full = 0u;
+    for (int w = threadIdx.x; w < kCountReplicas * 2 * SPH_MAX_BUFFERS; w += blockDim.x) part[w] = 0u;
+}
+
 __global__ __launch_bounds__(kClassifyBlock) void k_classify_cand(FullArgs a) {
     __shared__ BufDev sb[SPH_MAX_BUFFERS];
     __shared__ unsigned s_cnt[2 * SPH_MAX_BUFFERS];
@@ -1354,6 +1512,7 @@ struct FinArgs {
     Parts p;
     int nb;
     int local;
+    int nf_full;  // the non-finite flag is the one a full scan or a classifying count pass raises
     EventArgs e;
     uint32_t *gen_sorted;  // [cap_ev] sources in ascending order (for sph_last_events)
     uint32_t *del_sorted;  // [cap_ev] deleted indices in ascending order
@@ -1482,22 +1641,44 @@ constexpr int kSortBuckets = 8192;   // buckets per list of the finalize's count
 constexpr int kSortBucketMax = 64;   // fuller buckets: comparison sort instead
 static_assert(kMaxEv % kFinBlock == 0 && kSortBuckets % kFinBlock == 0 && kMaxEv < 65536, "finalize sort layout");
 
-__device__ __forceinline__ void finalize_body(const FinArgs &a, const int fb, const int nfb) {
-    __shared__ uint32_t s_k[2][2][kMaxEv];  // [list: 0 sources, 1 deleted][ping-pong] keys
-    __shared__ uint32_t s_v[2][kMaxEv];     // [ping-pong] event entry of each source
-    __shared__ uint32_t s_map[kMaxEv];      // tail position t = p - N': recycle entry and new label
-    __shared__ unsigned s_bits[kMaxEv / 32], s_wpre[kMaxEv / 32];  // deleted tail positions, prefix per word
-    __shared__ unsigned s_off[3][kSeg + 1];  // per list: segment counts, then exclusive offsets; [kSeg] = total
-    __shared__ int s_status;
-    __shared__ unsigned s_last;
-    __shared__ long long s_N, s_next;
-    __shared__ unsigned s_found[SPH_MAX_BUFFERS], s_post[SPH_MAX_BUFFERS];
-    __shared__ long long s_nl[SPH_MAX_BUFFERS];
-    __shared__ unsigned s_flags[3];
-    __shared__ uint32_t s_hist[kSortBuckets];      // per list, two buckets per word: counts, then starts
-    __shared__ uint32_t s_mm[2][2];                // per list: min and max key
-    __shared__ unsigned s_fat[2];                  // per list: keys in the fullest bucket
-    __shared__ unsigned s_wsum[kFinBlock / kWave];
+// LDS of one finalize workgroup (declared by the kernel, so that a launch that
+// also runs scan tiles can overlay both in one allocation).
+struct FinLds {
+    uint32_t k[2][2][kMaxEv];          // [list: 0 sources, 1 deleted][ping-pong] keys
+    uint32_t v[2][kMaxEv];             // [ping-pong] event entry of each source
+    uint32_t map[kMaxEv];              // tail position t = p - N': recycle entry and new label
+    unsigned bits[kMaxEv / 32], wpre[kMaxEv / 32];  // deleted tail positions, prefix per word
+    unsigned off[3][kSeg + 1];         // per list: segment counts, then exclusive offsets; [kSeg] = total
+    int status;
+    unsigned last;
+    long long N, next;
+    unsigned found[SPH_MAX_BUFFERS], post[SPH_MAX_BUFFERS];
+    long long nl[SPH_MAX_BUFFERS];
+    unsigned flags[3];
+    uint32_t hist[kSortBuckets];       // per list, two buckets per word: counts, then starts
+    uint32_t mm[2][2];                 // per list: min and max key
+    unsigned fat[2];                   // per list: keys in the fullest bucket
+    unsigned wsum[kFinBlock / kWave];
+};
+
+__device__ __forceinline__ void finalize_body(const FinArgs &a, const int fb, const int nfb, FinLds &L) {
+    auto &s_k = L.k;
+    auto &s_v = L.v;
+    auto &s_map = L.map;
+    auto &s_bits = L.bits;
+    auto &s_wpre = L.wpre;
+    auto &s_off = L.off;
+    int &s_status = L.status;
+    unsigned &s_last = L.last;
+    long long &s_N = L.N, &s_next = L.next;
+    auto &s_found = L.found;
+    auto &s_post = L.post;
+    auto &s_nl = L.nl;
+    auto &s_flags = L.flags;
+    auto &s_hist = L.hist;
+    auto &s_mm = L.mm;
+    auto &s_fat = L.fat;
+    auto &s_wsum = L.wsum;
     Ctl *c = a.e.ctl;
     const int tid = threadIdx.x;
     const unsigned bd = blockDim.x;
@@ -1518,7 +1699,7 @@ __device__ __forceinline__ void finalize_body(const FinArgs &a, const int fb, co
         s_next = c->next_id;
         s_N = *a.p.n_dev;
         s_flags[0] = c->scan_fault;
-        s_flags[1] = a.local ? c->nonfinite_seen : c->nonfinite_full;
+        s_flags[1] = a.nf_full ? c->nonfinite_full : c->nonfinite_seen;
         s_flags[2] = c->cand_overflow;
     }
     unsigned pv[(kCountReplicas * 2 * SPH_MAX_BUFFERS + 1023) / 1024];
@@ -1899,7 +2080,7 @@ __device__ __forceinline__ void finalize_body(const FinArgs &a, const int fb, co
             r->n_before = N;
             r->n_after = st == SPH_OK ? N - (long long)D + (long long)G : N;
             r->next_id = st == SPH_OK ? s_next + G : s_next;
-            if (!a.local) c->nonfinite_full = 0u;
+            if (a.nf_full) c->nonfinite_full = 0u;
             c->cand_count = 0ull;
             c->cand_overflow = 0u;
             c->fin_ticket = 0u;
@@ -1912,7 +2093,34 @@ __device__ __forceinline__ void finalize_body(const FinArgs &a, const int fb, co
     }
 }
 
-__global__ __launch_bounds__(kFinBlock) void k_finalize(FinArgs a) { finalize_body(a, blockIdx.x, gridDim.x); }
+__global__ __launch_bounds__(kFinBlock) void k_finalize(FinArgs a) {
+    __shared__ FinLds L;
+    finalize_body(a, blockIdx.x, gridDim.x, L);
+}
+
+// Update of the merged step: the finalize workgroups (the first nfin) and the scan
+// tiles of the cell list side by side in one launch.  They touch disjoint state
+// (event lists and particle arrays; cell counts, tile states and cell starts); the
+// scatter that follows places the particles the count pass saw (its own count of
+// them, not the updated one).
+struct ScanFinArgs {
+    ScanArgs s;
+    FinArgs f;
+    int nfin;
+};
+
+static_assert(kFinBlock == kScanBlock, "finalize and scan workgroups share one launch");
+
+__global__ __launch_bounds__(kFinBlock) void k_scan_finalize(ScanFinArgs a) {
+    __shared__ union {
+        FinLds f;
+        ScanLds s;
+    } L;
+    if ((int)blockIdx.x < a.nfin)
+        finalize_body(a.f, (int)blockIdx.x, a.nfin, L.f);
+    else
+        scan_body(a.s, L.s);
+}
 
 // ------------------------------------------------------------- identify --
 
@@ -2248,13 +2456,14 @@ __global__ __launch_bounds__(kBuildBlock) void kb_count(const CountArgs *args, c
                                                         const int32_t *vg) {
     const BlockMap m = map[logical_block()];
     if (m.d < 0) return;
-    count_body(args[m.d], m.vb, vg[m.d]);
+    count_body<false>(args[m.d], m.vb, vg[m.d]);
 }
 
 __global__ __launch_bounds__(kScanBlock) void kb_scan(const ScanArgs *args, const BlockMap *map) {
     const BlockMap m = map[logical_block()];
     if (m.d < 0) return;
-    scan_body(args[m.d]);
+    __shared__ ScanLds L;
+    scan_body(args[m.d], L);
 }
 
 __global__ __launch_bounds__(kBuildBlock) void kb_scatter(const ScatterArgs *args, const BlockMap *map,
@@ -2272,7 +2481,8 @@ __global__ __launch_bounds__(kClassifyBlock) void kb_classify(const LocalArgs *a
 }
 
 __global__ __launch_bounds__(kFinBlock) void kb_finalize(const FinArgs *args, int nfb) {
-    finalize_body(args[blockIdx.x / nfb], blockIdx.x % nfb, nfb);
+    __shared__ FinLds L;
+    finalize_body(args[blockIdx.x / nfb], blockIdx.x % nfb, nfb, L);
 }
 
 }  // namespace
@@ -2322,6 +2532,13 @@ struct sph_ctx {
     hipEvent_t ev_count = nullptr, ev_built = nullptr;
     bool pending_join = false;   // the side stream's build work is not yet ordered before ctx->stream
     bool cand_pending = false;   // the count pass left candidates no update has consumed
+    // merged step (opt-in): the count pass also classifies the cover cells' particles
+    // and emits their events; the update runs the finalize beside the scan, then the
+    // scatter
+    bool merged = false;
+    bool scan_pending = false;   // a merged build's scan and scatter are not enqueued yet
+    bool ev_pending = false;     // a merged build's events are not finalized yet
+    bool nf_full_next = false;   // the next cover-walk finalize reads the count pass's non-finite flag
     uint16_t *d_cover = nullptr; // per cell: bit k set if the cell is in buffer k's cover
     int64_t cover_cells = 0;
     uint32_t *d_keys = nullptr;                  // packed (key, rank) of each particle (three-kernel build)
@@ -2510,10 +2727,10 @@ ScanArgs scan_args(const sph_ctx *ctx) {
     return sa;
 }
 
-ScatterArgs scatter_args(const sph_ctx *ctx, const Parts &pp) {
+ScatterArgs scatter_args(const sph_ctx *ctx, int64_t capacity) {
     ScatterArgs xa{};
-    xa.n_dev = pp.n_dev;
-    xa.capacity = pp.capacity;
+    xa.n_dev = &ctx->d_ctl->n_built;  // the particles the count pass saw, whatever an update did since
+    xa.capacity = capacity;
     xa.ctl = ctx->d_ctl;
     xa.packed = ctx->d_keys;
     xa.spill = ctx->d_keyrank;
@@ -2542,6 +2759,7 @@ FinArgs fin_args(const sph_ctx *ctx, const Parts &pp, bool local) {
     FinArgs f{};
     f.p = pp;
     f.local = local ? 1 : 0;
+    f.nf_full = local ? 0 : 1;
     f.nb = ctx->nb;
     f.e = events_of(ctx);
     f.gen_sorted = ctx->d_gen_sorted;
@@ -2552,13 +2770,48 @@ FinArgs fin_args(const sph_ctx *ctx, const Parts &pp, bool local) {
 
 sph_status launch_finalize(sph_ctx *ctx, const Parts &pp, bool local, int n_part) {
     (void)n_part;
-    const FinArgs f = fin_args(ctx, pp, local);
+    FinArgs f = fin_args(ctx, pp, local);
+    if (local && ctx->nf_full_next) f.nf_full = 1;  // a merged build raised its flag there
+    ctx->nf_full_next = false;
     {
         ProfScope ps(ctx, SPH_PHASE_FINALIZE);
         hipLaunchKernelGGL(k_finalize, dim3(kFinBlocksMax), dim3(kFinBlock), 0, ctx->stream, f);
     }
     HIP_TRY(hipGetLastError());
     ctx->any_update = true;
+    return SPH_OK;
+}
+
+// Merged step: enqueue the scan and the scatter a merged build left for its update
+// (every call that reads the cell list needs them first).
+sph_status merged_cells(sph_ctx *c) {
+    if (!c->scan_pending) return SPH_OK;
+    c->scan_pending = false;
+    const ScanArgs sa = scan_args(c);
+    {
+        ProfScope ps(c, SPH_PHASE_SCAN);
+        hipLaunchKernelGGL(k_scan, dim3((unsigned)c->n_tiles), dim3(kScanBlock), 0, c->stream, sa);
+    }
+    HIP_TRY(hipGetLastError());
+    const ScatterArgs xa = scatter_args(c, c->built_capacity);
+    {
+        ProfScope ps(c, SPH_PHASE_SCATTER);
+        hipLaunchKernelGGL(k_scatter, dim3(c->build_blocks), dim3(kBuildBlock), 0, c->stream, xa);
+    }
+    HIP_TRY(hipGetLastError());
+    return SPH_OK;
+}
+
+// Merged step: drop the events of a merged build once a call changes what they were
+// decided on (the update then walks the cover cells instead), or before a new build
+// or a full scan fills the event lists again (rebuild: its non-finite flag too).
+sph_status merged_drop(sph_ctx *c, bool rebuild) {
+    HIP_CHECKED(merged_cells(c));
+    if (rebuild) c->nf_full_next = false;
+    if (!c->ev_pending) return SPH_OK;
+    hipLaunchKernelGGL(k_reset_events, dim3(1), dim3(256), 0, c->stream, c->d_ctl, c->d_part, rebuild ? 1 : 0);
+    HIP_TRY(hipGetLastError());
+    c->ev_pending = false;
     return SPH_OK;
 }
 
@@ -2728,9 +2981,10 @@ static sph_status upload_runs(sph_ctx *ctx, std::vector<int32_t> &rf, std::vecto
             hipMemcpyAsync(nbuf, rb.data(), nr, hipMemcpyHostToDevice, ctx->stream) != hipSuccess)
             return SPH_ERR_HIP;
     }
-    // per-cell cover mask for the overlapped step's candidate gathering
+    // per-cell cover mask for the candidate gathering of the overlapped step and the
+    // classification of the merged step
     std::vector<uint16_t> mask;
-    if (ctx->overlap) {
+    if (ctx->overlap || ctx->merged) {
         if (ctx->cover_cells != ctx->n_cells) {
             HIP_TRY(hipStreamSynchronize(ctx->stream));
             (void)hipFree(ctx->d_cover);
@@ -2892,9 +3146,17 @@ extern "C" sph_status sph_create(const sph_config *cfg, sph_ctx **out) {
     // cover cells and the update runs on them while the scan and the scatter finish on
     // a side stream (not with the one-launch build).  On the 3-D pipe it is about 1 %
     // faster: the finalize and the scatter slow each other down when they share the GPU.
+    // SPHBUF_UPDATE=merged selects the merged step: the count pass classifies the
+    // particles of the cover cells as it bins them and emits their events, and the
+    // update runs the finalize beside the scan tiles in one launch, then the scatter
+    // (not with the one-launch build).  The events and duplicate payloads are those
+    // of the state the build saw; the library's own calls that change that state
+    // (boundary conditions, turns, identification, fields, buffer definitions) drop
+    // them, and the update then walks the cover cells.
     {
         const char *upd = std::getenv("SPHBUF_UPDATE");
         c->overlap = c->fused_blocks == 0 && upd && std::strcmp(upd, "overlap") == 0;
+        c->merged = c->fused_blocks == 0 && upd && std::strcmp(upd, "merged") == 0;
         if (c->overlap && (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
                            hipEventCreateWithFlags(&c->ev_count, hipEventDisableTiming) != hipSuccess ||
                            hipEventCreateWithFlags(&c->ev_built, hipEventDisableTiming) != hipSuccess)) {
@@ -2918,6 +3180,7 @@ extern "C" sph_status sph_buffer_define(sph_ctx *ctx, sph_kind kind, const doubl
                                         const double half[3], double margin, int32_t *buffer_id) {
     if (!ctx || !origin || !rot || !half) return SPH_ERR_ARG;
     HIP_CHECKED(join_side(ctx));
+    HIP_CHECKED(merged_drop(ctx, true));
     if (kind != SPH_INLET && kind != SPH_OUTLET && kind != SPH_BIDIR) return SPH_ERR_ARG;
     const int dim = ctx->dim;
     double o[3] = {origin[0], origin[1], dim == 3 ? origin[2] : 0.0};
@@ -2976,6 +3239,33 @@ extern "C" sph_status sph_celllist_build(sph_ctx *ctx, const sph_particles *p) {
     if (st != SPH_OK) return st;
     HIP_CHECKED(join_side(ctx));  // the previous build's scan must have cleared the counts
     HIP_CHECKED(drop_candidates(ctx));
+    HIP_CHECKED(merged_drop(ctx, true));
+    ctx->built_capacity = pp.capacity;
+    // merged step: a workgroup's list holds at most kClsList particles (capacities
+    // beyond 2^25 particles, and domains without buffers, take the plain build)
+    if (ctx->merged && ctx->d_cover && ctx->nb > 0 &&
+        (int64_t)count_blocks(pp.capacity) * kClsList >= pp.capacity) {
+        // count + classification of the cover cells' particles here; the scan and the
+        // scatter are left for the update (or the next call that needs the cell list)
+        CountArgs ca = count_args(ctx, pp);
+        ca.nonfinite = &ctx->d_ctl->nonfinite_full;
+        ca.cover = ctx->d_cover;
+        ca.cls = 1;
+        ca.nb = ctx->nb;
+        ca.p = pp;
+        ca.bufs = ctx->d_bufs;
+        ca.e = events_of(ctx);
+        {
+            ProfScope ps(ctx, SPH_PHASE_COUNT);
+            hipLaunchKernelGGL(k_count_cls, dim3(count_blocks(pp.capacity)), dim3(kBuildBlock), 0, ctx->stream, ca);
+        }
+        HIP_TRY(hipGetLastError());
+        ctx->scan_pending = true;
+        ctx->ev_pending = true;
+        ctx->nf_full_next = true;
+        ctx->built = true;
+        return SPH_OK;
+    }
     if (ctx->fused_blocks > 0) {
         FusedArgs fa{};
         fa.x = pp.pos[0];
@@ -3027,7 +3317,7 @@ extern "C" sph_status sph_celllist_build(sph_ctx *ctx, const sph_particles *p) {
             hipLaunchKernelGGL(k_scan, dim3((unsigned)ctx->n_tiles), dim3(kScanBlock), 0, ctx->side, sa);
         }
         HIP_TRY(hipGetLastError());
-        const ScatterArgs xa = scatter_args(ctx, pp);
+        const ScatterArgs xa = scatter_args(ctx, pp.capacity);
         {
             ProfScope ps(ctx, SPH_PHASE_SCATTER, ctx->side);
             hipLaunchKernelGGL(k_scatter, dim3(ctx->build_blocks), dim3(kBuildBlock), 0, ctx->side, xa);
@@ -3051,7 +3341,7 @@ extern "C" sph_status sph_celllist_build(sph_ctx *ctx, const sph_particles *p) {
         hipLaunchKernelGGL(k_scan, dim3((unsigned)ctx->n_tiles), dim3(kScanBlock), 0, ctx->stream, sa);
     }
     HIP_TRY(hipGetLastError());
-    const ScatterArgs xa = scatter_args(ctx, pp);
+    const ScatterArgs xa = scatter_args(ctx, pp.capacity);
     {
         ProfScope ps(ctx, SPH_PHASE_SCATTER);
         hipLaunchKernelGGL(k_scatter, dim3(ctx->build_blocks), dim3(kBuildBlock), 0, ctx->stream, xa);
@@ -3068,6 +3358,42 @@ extern "C" sph_status sph_buffer_update_async(sph_ctx *ctx, sph_particles *p) {
     const sph_status st = parts_of(ctx, p, pp);
     if (st != SPH_OK) return st;
     if (ctx->fields.rho >= pp.nc) return SPH_ERR_ARG;
+    if (ctx->merged && ctx->ev_pending) {
+        // the events are already emitted: the finalize runs beside the scan tiles,
+        // then the scatter (or the finalize alone if a call needed the cell list first)
+        FinArgs f = fin_args(ctx, pp, false);
+        if (ctx->scan_pending) {
+            ScanFinArgs sf{};
+            sf.s = scan_args(ctx);
+            sf.f = f;
+            sf.nfin = kFinBlocksMax;
+            {
+                ProfScope ps(ctx, SPH_PHASE_FINALIZE);
+                hipLaunchKernelGGL(k_scan_finalize, dim3((unsigned)(kFinBlocksMax + ctx->n_tiles)), dim3(kFinBlock), 0,
+                                   ctx->stream, sf);
+            }
+            HIP_TRY(hipGetLastError());
+            const ScatterArgs xa = scatter_args(ctx, ctx->built_capacity);
+            {
+                ProfScope ps(ctx, SPH_PHASE_SCATTER);
+                hipLaunchKernelGGL(k_scatter, dim3(ctx->build_blocks), dim3(kBuildBlock), 0, ctx->stream, xa);
+            }
+            HIP_TRY(hipGetLastError());
+            ctx->scan_pending = false;
+        } else {
+            {
+                ProfScope ps(ctx, SPH_PHASE_FINALIZE);
+                hipLaunchKernelGGL(k_finalize, dim3(kFinBlocksMax), dim3(kFinBlock), 0, ctx->stream, f);
+            }
+            HIP_TRY(hipGetLastError());
+        }
+        ctx->ev_pending = false;
+        ctx->nf_full_next = false;
+        ctx->built = false;
+        ctx->any_update = true;
+        return SPH_OK;
+    }
+    HIP_CHECKED(merged_cells(ctx));  // a merged build whose events were dropped: walk the cover cells
     if (ctx->overlap) {
         // the count pass's candidates: exact tests and emission, then the finalize, while
         // the scan and scatter may still run on the side stream (they touch neither the
@@ -3107,6 +3433,7 @@ extern "C" sph_status sph_buffer_update_async(sph_ctx *ctx, sph_particles *p) {
 static sph_status fullscan_enqueue(sph_ctx *ctx, sph_particles *p) {
     if (!ctx) return SPH_ERR_ARG;
     HIP_CHECKED(join_side(ctx));
+    HIP_CHECKED(merged_drop(ctx, true));
     HIP_CHECKED(drop_candidates(ctx));
     Parts pp;
     const sph_status st = parts_of(ctx, p, pp);
@@ -3196,6 +3523,7 @@ extern "C" sph_status sph_celllist_view(sph_ctx *ctx, const int32_t **cell_start
                                         int64_t *n_cells, int32_t dims[3]) {
     if (!ctx) return SPH_ERR_ARG;
     HIP_CHECKED(join_side(ctx));
+    HIP_CHECKED(merged_cells(ctx));
     if (cell_start) *cell_start = ctx->d_cell_start;
     if (cell_idx) *cell_idx = ctx->d_cell_idx;
     if (n_cells) *n_cells = ctx->n_cells;
@@ -3207,6 +3535,7 @@ extern "C" sph_status sph_celllist_view(sph_ctx *ctx, const int32_t **cell_start
 extern "C" sph_status sph_neighbor_count(sph_ctx *ctx, const sph_particles *p, double radius, int32_t *counts) {
     if (!ctx || !counts) return SPH_ERR_ARG;
     HIP_CHECKED(join_side(ctx));
+    HIP_CHECKED(merged_cells(ctx));
     Parts pp;
     const sph_status st = parts_of(ctx, p, pp);
     if (st != SPH_OK) return st;
@@ -3253,6 +3582,7 @@ extern "C" sph_status sph_set_fields(sph_ctx *ctx, const sph_fields *fields) {
     for (int c = 0; c < 3; ++c)
         if (fields->vel[c] < -1 || fields->vel[c] >= SPH_MAX_CARRIED) return SPH_ERR_ARG;
     if (fields->rho < -1 || fields->rho >= SPH_MAX_CARRIED) return SPH_ERR_ARG;
+    HIP_CHECKED(merged_drop(ctx, false));  // a merged build's duplicates were captured with the old fields
     ctx->fields = *fields;
     return SPH_OK;
 }
@@ -3266,6 +3596,7 @@ extern "C" sph_status sph_buffer_set_bc(sph_ctx *ctx, int32_t buffer_id, const s
         return SPH_ERR_ARG;
     if (bc->kind == SPH_BC_VELOCITY && bc->profile != SPH_PROFILE_PLUG && !(bc->radius > 0.0)) return SPH_ERR_ARG;
     if (bc->kind == SPH_BC_PRESSURE && !(bc->c0 > 0.0)) return SPH_ERR_ARG;
+    HIP_CHECKED(merged_drop(ctx, false));  // a merged build emitted with the old boundary values
     BufDev &b = ctx->hb[buffer_id - 1];
     b.bc_kind = bc->kind;
     b.profile = bc->profile;
@@ -3325,6 +3656,7 @@ static sph_status read_bc_status(sph_ctx *ctx) {
 extern "C" sph_status sph_buffer_apply_bc(sph_ctx *ctx, sph_particles *p) {
     if (!ctx) return SPH_ERR_ARG;
     HIP_CHECKED(join_side(ctx));
+    HIP_CHECKED(merged_drop(ctx, false));
     Parts pp;
     const sph_status st = parts_of(ctx, p, pp);
     if (st != SPH_OK) return st;
@@ -3348,6 +3680,7 @@ extern "C" sph_status sph_buffer_rotate(sph_ctx *ctx, sph_particles *p, int32_t 
                                         const double m[9]) {
     if (!ctx || !center || !m || buffer_id < 1 || buffer_id > ctx->nb) return SPH_ERR_ARG;
     HIP_CHECKED(join_side(ctx));
+    HIP_CHECKED(merged_drop(ctx, false));
     const int dim = ctx->dim;
     for (int c = 0; c < dim; ++c)
         if (!std::isfinite(center[c])) return SPH_ERR_ARG;
@@ -3413,6 +3746,7 @@ extern "C" sph_status sph_buffer_rotate(sph_ctx *ctx, sph_particles *p, int32_t 
 extern "C" sph_status sph_buffer_identify(sph_ctx *ctx, sph_particles *p, int32_t buffer_id) {
     if (!ctx) return SPH_ERR_ARG;
     HIP_CHECKED(join_side(ctx));
+    HIP_CHECKED(merged_drop(ctx, false));
     if (buffer_id != -1 && (buffer_id < 1 || buffer_id > ctx->nb)) return SPH_ERR_ARG;
     Parts pp;
     const sph_status st = parts_of(ctx, p, pp);
@@ -3452,6 +3786,7 @@ extern "C" sph_status sph_state_get(sph_ctx *ctx, int64_t *next_id, int64_t n_la
 extern "C" sph_status sph_state_set(sph_ctx *ctx, int64_t next_id, const int64_t n_labelled[SPH_MAX_BUFFERS]) {
     if (!ctx) return SPH_ERR_ARG;
     HIP_CHECKED(join_side(ctx));
+    HIP_CHECKED(merged_drop(ctx, false));
     HIP_TRY(hipMemcpyAsync(&ctx->d_ctl->next_id, &next_id, sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
     if (n_labelled)
         HIP_TRY(hipMemcpyAsync(ctx->d_ctl->n_labelled, n_labelled, sizeof(int64_t) * SPH_MAX_BUFFERS,
@@ -3496,6 +3831,7 @@ extern "C" sph_status sph_profile_read(sph_ctx *ctx, double ms[SPH_NPHASE], int6
 extern "C" sph_status sph_grid_fit(sph_ctx *ctx, const sph_particles *p) {
     if (!ctx) return SPH_ERR_ARG;
     HIP_CHECKED(join_side(ctx));
+    HIP_CHECKED(merged_drop(ctx, false));
     if (ctx->blog2 == 0) return SPH_OK;
     Parts pp;
     const sph_status st = parts_of(ctx, p, pp);
@@ -3692,6 +4028,7 @@ extern "C" sph_status sph_batch_create(sph_ctx *const *domains, const sph_partic
     for (int d = 0; d < n_domains; ++d) {  // no build work of a domain left in flight
         if (!domains[d]) return SPH_ERR_ARG;
         HIP_CHECKED(join_side(domains[d]));
+        HIP_CHECKED(merged_drop(domains[d], true));
         HIP_TRY(hipStreamSynchronize(domains[d]->stream));
     }
     sph_batch *b = new (std::nothrow) sph_batch();
@@ -3722,7 +4059,7 @@ extern "C" sph_status sph_batch_create(sph_ctx *const *domains, const sph_partic
         b->parts.push_back(pp);
         ca.push_back(count_args(c, pp));
         sa.push_back(scan_args(c));
-        xa.push_back(scatter_args(c, pp));
+        xa.push_back(scatter_args(c, pp.capacity));
         la.push_back(local_args(c, pp));
         fa.push_back(fin_args(c, pp, true));
     }

@@ -1,8 +1,10 @@
-"""The two update paths behind the same C ABI against the FP64 oracle: the update
-that walks the cover cells of the finished cell list (the default) and the
-overlapped step (SPHBUF_UPDATE=overlap: the count pass gathers the particles of the
-buffers' cover cells, the update runs on them while the scan and scatter finish on a
-side stream); plus the call orders the overlapped step has to survive."""
+"""The update paths behind the same C ABI against the FP64 oracle: the update that
+walks the cover cells of the finished cell list (the default), the overlapped step
+(SPHBUF_UPDATE=overlap: the count pass gathers the particles of the buffers' cover
+cells, the update runs on them while the scan and scatter finish on a side stream)
+and the merged step (SPHBUF_UPDATE=merged: the count pass classifies those
+particles and emits their events, the update runs the finalize beside the scan
+tiles, then the scatter); plus the call orders the two have to survive."""
 import numpy as np
 import pytest
 
@@ -16,13 +18,13 @@ pytestmark = pytest.mark.gpu
 
 
 def _mode(monkeypatch, mode):
-    if mode == "overlap":
-        monkeypatch.setenv("SPHBUF_UPDATE", "overlap")
+    if mode in ("overlap", "merged"):
+        monkeypatch.setenv("SPHBUF_UPDATE", mode)
     else:
         monkeypatch.delenv("SPHBUF_UPDATE", raising=False)
 
 
-@pytest.mark.parametrize("mode", ["overlap", "cells"])
+@pytest.mark.parametrize("mode", ["overlap", "merged", "cells"])
 def test_channel_and_pipe(mode, monkeypatch):
     _mode(monkeypatch, mode)
     g, dl = _run_steps(W.channel2d(), 120)
@@ -31,7 +33,7 @@ def test_channel_and_pipe(mode, monkeypatch):
     assert g > 0
 
 
-@pytest.mark.parametrize("mode", ["overlap", "cells"])
+@pytest.mark.parametrize("mode", ["overlap", "merged", "cells"])
 def test_tree_bidirectional_sparse_grid(mode, monkeypatch):
     _mode(monkeypatch, mode)
     g, dl = _run_steps(W.tree3d(dp=0.004), 60, check_every=20, brick_log2=3)
@@ -56,11 +58,12 @@ def _check_update(d, bufs, st, what):
     assert_same_state(d, st, what)
 
 
-def test_unconsumed_builds_and_interleaved_calls(monkeypatch):
-    """Overlapped step: a build no update consumed (its candidates must not count
-    twice), a full-scan update after such a build, a neighbour search and a
-    cell-list view between the build and the update."""
-    _mode(monkeypatch, "overlap")
+@pytest.mark.parametrize("mode", ["overlap", "merged"])
+def test_unconsumed_builds_and_interleaved_calls(mode, monkeypatch):
+    """A build no update consumed (its candidates or events must not count twice),
+    a full-scan update after such a build, a neighbour search and a cell-list view
+    between the build and the update."""
+    _mode(monkeypatch, mode)
     wl = W.channel2d()
     bufs, st, d = _setup(wl)
     for step in range(40):
@@ -100,3 +103,74 @@ def test_overlapped_step_full_size(monkeypatch):
     """The overlapped step on the benchmark's pipe (7.86 M particles), two steps."""
     _mode(monkeypatch, "overlap")
     _run_steps(W.pipe3d(), 2)
+
+
+def test_merged_step_full_size(monkeypatch):
+    """The merged step on the benchmark's pipe (7.86 M particles), two steps."""
+    _mode(monkeypatch, "merged")
+    _run_steps(W.pipe3d(), 2)
+
+
+def test_merged_step_cell_list_after_the_update(monkeypatch):
+    """The scatter of a merged step runs after the finalize has changed the live
+    count: the cell list it leaves is that of the state the build saw."""
+    _mode(monkeypatch, "merged")
+    wl = W.channel2d()
+    bufs, st, d = _setup(wl)
+    dims = _cell_list(d, 0)[2]
+    for step in range(30):
+        W.advect_host(wl, st.pos, st.n, step)
+        upload_state(d, st)
+        n = st.n
+        ref_s, ref_i = oracle.cell_list(2, np.float32(wl.lo[:2]), np.float32(1.0 / wl.cell_size), dims[:2],
+                                        st.pos[0][:n].copy(), st.pos[1][:n].copy())
+        d.build()
+        _check_update(d, bufs, st, f"step {step}")
+        cs, ci, _ = _cell_list(d, n)
+        np.testing.assert_array_equal(cs, ref_s, err_msg=f"step {step}")
+        for c in np.flatnonzero(np.diff(ref_s)):  # each cell's set (the order inside a cell is free)
+            np.testing.assert_array_equal(np.sort(ci[ref_s[c]:ref_s[c + 1]]), np.sort(ref_i[ref_s[c]:ref_s[c + 1]]))
+    d.close()
+
+
+@pytest.mark.parametrize("case", ["vipo_pipe3d", "pivo_channel2d"])
+def test_merged_step_with_boundary_conditions(case, monkeypatch):
+    """Boundary conditions applied between the build and the update change the
+    state the merged build classified: its events are dropped and the update walks
+    the cover cells (the duplicates carry the new velocities)."""
+    from tests.test_bc_gpu import test_boundary_conditions_over_steps
+    _mode(monkeypatch, "merged")
+    test_boundary_conditions_over_steps(case)
+
+
+def test_merged_step_sprinkler(monkeypatch):
+    from tests.test_bc_gpu import test_sprinkler_rotating_inlet
+    _mode(monkeypatch, "merged")
+    test_sprinkler_rotating_inlet()
+
+
+@pytest.mark.parametrize("what", ["cfl", "capacity", "nonfinite", "empty", "all_deleted", "hand", "unaligned",
+                                  "clustered", "guard"])
+def test_merged_step_edge_cases(what, monkeypatch):
+    import tests.test_parity_gpu as P
+    _mode(monkeypatch, "merged")
+    if what == "cfl":
+        P.test_cfl_violation_leaves_state_untouched("local")
+    elif what == "capacity":
+        P.test_capacity_exhaustion_leaves_state_untouched("local")
+    elif what == "nonfinite":
+        P.test_nonfinite_position_leaves_state_untouched("local")
+    elif what == "empty":
+        P.test_empty_domain()
+    elif what == "all_deleted":
+        P.test_every_particle_deleted()
+    elif what == "hand":
+        for case in range(3):
+            P.test_hand_examples_on_gpu(case, "local")
+    elif what == "unaligned":
+        P.test_unaligned_arrays_take_the_scalar_paths("local")
+    elif what == "clustered":
+        P.test_clustered_event_indices(200_000, "local")
+    else:
+        for dim in (2, 3):
+            P.test_guard_band_decisions_equal_fp64(dim, 0)
