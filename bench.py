@@ -277,8 +277,8 @@ def main() -> int:
     ap.add_argument("--no-neighbor", action="store_true", help="skip the neighbour-search leg")
     ap.add_argument("--build", default=None, choices=["split", "fused"],
                     help="cell-list build variant (default: the library's)")
-    ap.add_argument("--update", default=None, choices=["cells", "overlap", "merged"],
-                    help="update path (default: the library's cover-cell walk)")
+    ap.add_argument("--update", default="merged", choices=["cells", "overlap", "merged"],
+                    help="update path of the timed step (the cover-cell walk is timed beside it as well)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
@@ -312,6 +312,19 @@ def main() -> int:
         dom.define(b.kind, b.origin, q, b.half, b.margin)
     S.check(dom.identify(-1), "identify")
     stream = dom.stream
+    # the cover-cell walk (the library's default update) replays the same states
+    # through a context of its own, on the same stream
+    ctx_cells = None
+    if args.update != "cells":
+        saved = os.environ.pop("SPHBUF_UPDATE", None)
+        st_c, ctx_cells = S.sph_create(wl.dim, wl.lo, wl.hi, wl.cell_size, wl.dp, wl.capacity,
+                                       max_events=S.SPH_MAX_EVENTS_LIMIT, next_id=wl.n, stream=stream.cuda_stream)
+        S.check(st_c, "create (cover-cell walk)")
+        if saved is not None:
+            os.environ["SPHBUF_UPDATE"] = saved
+        for b, q in zip(wl.buffers, rots):
+            st_c, _ = S.sph_buffer_define(ctx_cells, b.kind, b.origin, q, b.half, b.margin)
+            S.check(st_c, "define (cover-cell walk)")
 
     # ---- prepare the states the timed steps consume (the real loop, untimed) ----
     n_snap = Wm + K
@@ -363,7 +376,8 @@ def main() -> int:
     parts = [S.particles_from_tensors(w.pos, w.carried, w.label, w.id, w.n_dev) for w in work]
     flush = torch.ones(1 << 28, dtype=torch.float32, device=dev)       # 1 GB, read-only flush
 
-    def reset_work():
+    def reset_work(ctx=None):
+        ctx = ctx or dom.ctx
         with torch.cuda.stream(stream):
             for w, s in zip(work, snaps):
                 for dst, src in zip(w.tensors(), s.tensors()):
@@ -373,20 +387,21 @@ def main() -> int:
             float(flush.sum())
         stream.synchronize()
         nid, nl = states[0]
-        S.check(S.sph_state_set(dom.ctx, nid, nl), "state_set")
+        S.check(S.sph_state_set(ctx, nid, nl), "state_set")
 
-    def replay(mode: str, profile: bool):
-        reset_work()
-        S.check(S.sph_profile_enable(dom.ctx, False), "profile")
+    def replay(mode: str, profile: bool, ctx=None):
+        ctx = ctx or dom.ctx
+        reset_work(ctx)
+        S.check(S.sph_profile_enable(ctx, False), "profile")
         for s in range(Wm):
             if mode == "local":
-                S.check(S.sph_celllist_build(dom.ctx, parts[s]), "build")
-                S.check(S.sph_buffer_update_async(dom.ctx, parts[s]), "update")
+                S.check(S.sph_celllist_build(ctx, parts[s]), "build")
+                S.check(S.sph_buffer_update_async(ctx, parts[s]), "update")
             else:
-                S.check(S.sph_buffer_update_fullscan_async(dom.ctx, parts[s]), "fullscan")
+                S.check(S.sph_buffer_update_fullscan_async(ctx, parts[s]), "fullscan")
         stream.synchronize()
         if profile:
-            S.check(S.sph_profile_enable(dom.ctx, True), "profile")
+            S.check(S.sph_profile_enable(ctx, True), "profile")
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
@@ -394,32 +409,42 @@ def main() -> int:
         e0.record(stream)
         for s in range(Wm, Wm + K):
             if mode == "local":
-                S.sph_celllist_build(dom.ctx, parts[s])
-                S.sph_buffer_update_async(dom.ctx, parts[s])
+                S.sph_celllist_build(ctx, parts[s])
+                S.sph_buffer_update_async(ctx, parts[s])
             else:
-                S.sph_buffer_update_fullscan_async(dom.ctx, parts[s])
+                S.sph_buffer_update_fullscan_async(ctx, parts[s])
         e1.record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         ms = e0.elapsed_time(e1) / K
-        rs, r = S.sph_last_result(dom.ctx)
+        rs, r = S.sph_last_result(ctx)
         S.check(r.status, f"{mode} replay")
         expect = n_list[Wm + K - 1]
         assert (r.n_before, r.n_after, r.n_generated, r.n_deleted) == expect, (mode, expect, r.n_after)
         prof = None
         if profile:
-            st, pms, pn = S.sph_profile_read(dom.ctx, reset=True)
-            S.check(S.sph_profile_enable(dom.ctx, False), "profile")
+            st, pms, pn = S.sph_profile_read(ctx, reset=True)
+            S.check(S.sph_profile_enable(ctx, False), "profile")
             prof = {S.PHASES[i]: (float(pms[i]) / max(1, int(pn[i])), int(pn[i])) for i in range(S.SPH_NPHASE)
                     if pn[i] > 0}
         return ms, wall / K * 1e3, prof
 
     ms_local, wall_local, _ = replay("local", False)
     ms_full, wall_full, _ = replay("fullscan", False)
+    ms_cells = prof_cells = None
+    if ctx_cells is not None:
+        ms_cells, _, _ = replay("local", False, ctx_cells)
     prof_local = prof_full = None
     if not args.no_profile_pass:
         _, _, prof_local = replay("local", True)
         _, _, prof_full = replay("fullscan", True)
+        if ctx_cells is not None:
+            _, _, prof_cells = replay("local", True, ctx_cells)
+    if ctx_cells is None:
+        ms_cells, prof_cells = ms_local, prof_local
+    else:
+        log(f"cover-cell walk step {ms_cells * 1e3:.1f} us; phases (us): "
+            + ", ".join(f"{k} {v[0] * 1e3:.1f}" for k, v in (prof_cells or {}).items()))
     log(f"local step {ms_local * 1e3:.1f} us (wall {wall_local * 1e3:.1f} us); "
         f"full-scan update {ms_full * 1e3:.1f} us")
     log(f"local phases (us): " + ", ".join(f"{k} {v[0] * 1e3:.1f}" for k, v in (prof_local or {}).items()))
@@ -429,6 +454,12 @@ def main() -> int:
     g_mean = float(np.mean([x[2] for x in n_list[Wm:]]))
     d_mean = float(np.mean([x[3] for x in n_list[Wm:]]))
     pb = phase_bytes(wl.dim, int(n_mean), int(n_cells), cand, int(g_mean), int(d_mean), len(wl.carried))
+    merged = args.update == "merged"
+    if merged:
+        # the classifying count pass also reads the label of each candidate (its
+        # position is the one the count already read)
+        pb["count"] += 4 * cand
+    kernel_of = {"count": "count_cls" if merged else "count", "finalize": "scan_finalize" if merged else "finalize"}
     step_bytes = pb["build"] + pb["classify"] + pb["finalize"]
     upd_local_bytes = pb["classify"] + pb["finalize"]
 
@@ -454,13 +485,14 @@ def main() -> int:
         dom_phase = max((k for k in prof_local if k != "fullscan"), key=lambda k: prof_local[k][0])
         avg_ms = prof_local[dom_phase][0]
         achieved = pb[dom_phase] / (avg_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "kernel": dom_phase, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom_phase),
+        kname = kernel_of.get(dom_phase, dom_phase)
+        roof = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kname),
                 "avg_launch_us": round(avg_ms * 1e3, 2), "algorithmic_bytes_per_launch": int(pb[dom_phase])}
 
     t_upd_local = None
-    if prof_local:
-        t_upd_local = (prof_local.get("classify", (0, 0))[0] + prof_local.get("finalize", (0, 0))[0])
+    if prof_cells:  # the update of the cover-cell walk: classify + finalize
+        t_upd_local = (prof_cells.get("classify", (0, 0))[0] + prof_cells.get("finalize", (0, 0))[0])
     value = n_mean / (ms_local * 1e-3) / 1e6
     out = {
         "metric": METRIC,
@@ -498,10 +530,19 @@ def main() -> int:
             "fullscan_update_ms": round(t_upd_full, 5) if t_upd_full else None,
             "speedup_vs_fullscan": round(t_upd_full / t_upd_local, 2) if t_upd_full else None,
             "speedup_classify_vs_fullscan": round((prof_full["fullscan"][0] + prof_full.get("candidates", (0.0, 0))[0])
-                                                  / prof_local["classify"][0], 2)
-            if prof_full and "classify" in prof_local else None}
+                                                  / prof_cells["classify"][0], 2)
+            if prof_full and "classify" in prof_cells else None}
     if prof_local:
         out["phases_us"] = {k: round(v[0] * 1e3, 2) for k, v in prof_local.items()}
+        if merged:
+            out["phases_note"] = ("merged step: count = the classifying count pass, finalize = the finalize "
+                                  "workgroups beside the scan tiles in one launch")
+    if ctx_cells is not None:
+        out["cover_cell_walk"] = {
+            "ms_per_step": round(ms_cells, 5), "Mparticles_per_s": round(n_mean / (ms_cells * 1e-3) / 1e6, 1),
+            "path": PATHS["cells"],
+            "phases_us": {k: round(v[0] * 1e3, 2) for k, v in prof_cells.items()} if prof_cells else None,
+            "speedup_of_timed_step": round(ms_cells / ms_local, 3)}
     if prof_full:
         out["fullscan_phases_us"] = {k: round(v[0] * 1e3, 2) for k, v in prof_full.items()}
 
@@ -582,6 +623,8 @@ def main() -> int:
         log(f"cpu oracle: {len(times)} updates, median {t_o * 1e3:.1f} ms")
     log(f"total {time.perf_counter() - t_all:.1f} s")
     print(json.dumps(out), flush=True)
+    if ctx_cells is not None:
+        S.sph_destroy(ctx_cells)
     dom.close()
     return 0
 

@@ -741,8 +741,19 @@ __device__ __forceinline__ void count_body(const CountArgs &a, const int lb, con
                 unsigned long long found = 0, post = 0;
                 const float carv[SPH_MAX_CARRIED] = {};
                 emit<false>(a.e, a.p, b, k, sg, c, i, lab, oc, x, y, z, carv, found, post);
-                if (found) atomicAdd(&s_cnt[2 * k], 1u);
-                if (post) atomicAdd(&s_cnt[2 * k + 1], 1u);
+                // label counts: one LDS atomic per wave and buffer, not per lane
+                unsigned ks = c ? 1u << k : 0u;
+                for (int off = 32; off > 0; off >>= 1) ks |= (unsigned)__shfl_xor((int)ks, off);
+                while (ks) {  // wave-uniform
+                    const int kk = __ffs(ks) - 1;
+                    ks &= ks - 1u;
+                    const unsigned nf = (unsigned)__popcll(__ballot(c && k == kk && found));
+                    const unsigned np = (unsigned)__popcll(__ballot(c && k == kk && post));
+                    if (lane == 0 && (nf | np)) {
+                        atomicAdd(&s_cnt[2 * kk], nf);
+                        atomicAdd(&s_cnt[2 * kk + 1], np);
+                    }
+                }
             }
         }
         __syncthreads();
