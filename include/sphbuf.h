@@ -31,7 +31,9 @@
  *     work of a context is ordered on that stream (with SPHBUF_UPDATE=overlap a
  *     build's scan and scatter run on a library-owned side stream that later calls
  *     join back with an event).  Calls marked "sync" wait for the stream; the
- *     others only enqueue.
+ *     others only enqueue.  SPHBUF_UPDATE (read at sph_create) picks the update
+ *     path: unset, the update walks the cover cells of the finished cell list;
+ *     "overlap" and "merged" are described at sph_celllist_build.
  *   - The library allocates its device scratch in sph_create and
  *     sph_buffer_define; build and update calls allocate nothing.
  */
@@ -143,7 +145,17 @@ sph_status sph_grid_fit(sph_ctx *ctx, const sph_particles *p);
  * With SPHBUF_UPDATE=overlap in the environment at sph_create, the count pass also
  * gathers the particles of every buffer's cover cells, and the scan and scatter run
  * on a library-owned side stream that the next update (or any call that reads the
- * cell list) joins to the context stream; results are the same either way. */
+ * cell list) joins to the context stream; results are the same either way.
+ * With SPHBUF_UPDATE=merged, the count pass also classifies the particles of every
+ * buffer's cover cells and emits their events (steps 2-5 decided here, on these
+ * positions and carried fields; the caller must not change the arrays before the
+ * update), and the scan and scatter are left for the update, which runs the
+ * finalize beside the scan in one launch and then the scatter; a call that reads
+ * the cell list first enqueues them itself.  Library calls that change the state
+ * the events were decided on (apply_bc, rotate, identify, set_fields, set_bc,
+ * buffer_define, grid_fit, state_set) drop them, and the update then walks the
+ * cover cells; results are the same either way.  Capacities above 2^25 particles
+ * take the plain build. */
 sph_status sph_celllist_build(sph_ctx *ctx, const sph_particles *p);
 
 /* Algorithm 1, identification ("execute only once"): label k for every live
