@@ -139,9 +139,10 @@ def sprinkler_leg(torch, np, S, W, Domain, log, steps: int = 40):
             "wall_ms_per_step": round(wall * 1e3, 3)}
 
 
-def batch_leg(torch, np, S, W, Domain, steps: int, warmup: int, log):
+def batch_leg(torch, np, S, W, Domain, steps: int, warmup: int, log, fixed=None):
     """64 hub-and-spoke domains: batched step (autotuned launch mode, graph replay)
-    against a per-domain loop of plain launches, on the same prepared states."""
+    against a per-domain loop of plain launches, on the same prepared states.
+    fixed = (mode, particles per count block) skips the autotuner."""
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
     wls = W.hub_batch()
@@ -226,8 +227,11 @@ def batch_leg(torch, np, S, W, Domain, steps: int, warmup: int, log):
         S.check(st, "batch_create")
         batches.append(b)
     reset()
-    st, mode, ppb, ms_tuned = S.sph_batch_tune(batches[0], 3, None)
-    S.check(st, "tune")
+    if fixed:
+        mode, ppb = fixed
+    else:
+        st, mode, ppb, ms_tuned = S.sph_batch_tune(batches[0], 3, None)
+        S.check(st, "tune")
     for b in batches:
         S.check(S.sph_batch_set_mode(b, mode), "mode")
         S.check(S.sph_batch_set_count_block(b, ppb), "ppb")

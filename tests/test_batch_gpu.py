@@ -1,7 +1,8 @@
 """GPU parity of the batched path: many independent hub-and-spoke domains (2-D
 and 3-D, 1-6 buffers each) stepped together -- five launches per step for all
 domains, directly or as a replayed HIP graph -- against the FP64 oracle run
-domain by domain."""
+domain by domain; with the domains' contexts created for the cover-cell walk and
+for the merged step (the batch runs its own launches either way)."""
 import numpy as np
 import pytest
 
@@ -74,15 +75,25 @@ def _run(wls, steps, mode, tune=False):
         d.close()
 
 
+@pytest.fixture(params=["cells", "merged"])
+def path(request, monkeypatch):
+    """The update path of the domains (read when each domain is created)."""
+    if request.param == "merged":
+        monkeypatch.setenv("SPHBUF_UPDATE", "merged")
+    else:
+        monkeypatch.delenv("SPHBUF_UPDATE", raising=False)
+    return request.param
+
+
 @pytest.mark.parametrize("mode", [0, 1])
-def test_small_batch_matches_oracle(mode):
+def test_small_batch_matches_oracle(mode, path):
     _run(W.hub_batch(8, 2e3, 4e4), 12, mode)
 
 
-def test_batch_after_autotuning():
+def test_batch_after_autotuning(path):
     _run(W.hub_batch(6, 2e3, 2e4, seed=11), 4, 1, tune=True)
 
 
-def test_full_batch_two_steps():
+def test_full_batch_two_steps(path):
     """64 domains, particle counts log-uniform over 10k-2M (about 27.6 M in all)."""
     _run(W.hub_batch(), 2, 1)
