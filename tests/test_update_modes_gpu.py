@@ -174,3 +174,18 @@ def test_merged_step_edge_cases(what, monkeypatch):
     else:
         for dim in (2, 3):
             P.test_guard_band_decisions_equal_fp64(dim, 0)
+
+
+def test_merged_step_tree_full_size(monkeypatch):
+    """The merged step on the branching network at full size (16.1 M particles,
+    brick-sparse grid, four bidirectional buffers), two steps."""
+    _mode(monkeypatch, "merged")
+    _run_steps(W.tree3d(), 2, brick_log2=3)
+
+
+def test_merged_step_bent_channel_1000_steps(monkeypatch):
+    """The merged step on the bent 2-D channel for its full 1,000 steps (events every
+    step, every array every 100 steps)."""
+    _mode(monkeypatch, "merged")
+    g, dl = _run_steps(W.bent_channel2d(), 1000, check_every=100)
+    assert g > 0 and dl > 0
