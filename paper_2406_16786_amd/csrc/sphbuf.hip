@@ -587,15 +587,34 @@ __device__ __forceinline__ void count_body(const CountArgs &a, const int lb, con
     // Software pipelined: once a step has its keys it issues the next step's position
     // loads, then its run detection and atomics, so the two round trips overlap.
     float px[J], py[J], pz[J];
+    // The plain pass loads without a branch (lanes past a row's end re-read its first
+    // particle, rows with none the array's first; a 2-D z is a copy of x, unused):
+    // behind a branch the compiler waits for every outstanding access, the previous
+    // step's stores included, before the next loads.  The classifying pass keeps the
+    // branch (its register budget).
+    const float *xl[J], *yl[J], *zl[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        xl[j] = nr[j] ? xr[j] : a.x;
+        yl[j] = nr[j] ? yr[j] : a.y;
+        zl[j] = nr[j] ? zr[j] : (d3 ? a.z : a.x);
+    }
     auto load = [&](uint32_t it) {
         const uint32_t o = it + (uint32_t)lane;
 #pragma unroll
         for (int j = 0; j < J; ++j) {
-            px[j] = py[j] = pz[j] = 0.0f;
-            if (o < nr[j]) {
-                px[j] = at32(xr[j], o);
-                py[j] = at32(yr[j], o);
-                if (d3) pz[j] = at32(zr[j], o);
+            if constexpr (kCls) {
+                px[j] = py[j] = pz[j] = 0.0f;
+                if (o < nr[j]) {
+                    px[j] = at32(xr[j], o);
+                    py[j] = at32(yr[j], o);
+                    if (d3) pz[j] = at32(zr[j], o);
+                }
+            } else {
+                const uint32_t oc = o < nr[j] ? o : 0u;
+                px[j] = at32(xl[j], oc);
+                py[j] = at32(yl[j], oc);
+                pz[j] = at32(zl[j], oc);
             }
         }
     };
