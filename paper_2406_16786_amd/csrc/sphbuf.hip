@@ -507,18 +507,21 @@ struct CountArgs {
     const uint16_t *cover;
     unsigned long long *cand;
     int64_t seg_cap;
-    // classification during the count (cls != 0, cover set, cand null): every
-    // particle whose cell is in buffer k's cover is tested against buffer k here
-    // and its events emitted, so that the update only has to finalize them
-    int cls;
+};
+
+// The classifying count pass of the merged step (cover set, cand null): every
+// particle whose cell is in buffer k's cover is tested against buffer k there and
+// its events emitted, so that the update only has to finalize them.  (Its own
+// argument block: the plain pass keeps a small one.)
+struct ClsArgs : CountArgs {
     int nb;
     Parts p;
     const BufDev *bufs;
     EventArgs e;
 };
 
-template <bool kCls>  // the merged step's classification compiled in (its own kernel: registers)
-__device__ __forceinline__ void count_body(const CountArgs &a, const int lb, const int G) {
+template <bool kCls, class A>  // the merged step's classification compiled in (A = ClsArgs; its own kernel: registers)
+__device__ __forceinline__ void count_body(const A &a, const int lb, const int G) {
     const int64_t N = live_count(a.n_dev, a.capacity);
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t nthreads = (int64_t)G * blockDim.x;
@@ -783,7 +786,7 @@ __device__ __forceinline__ void count_body(const CountArgs &a, const int lb, con
 __global__ __launch_bounds__(kBuildBlock) void k_count(CountArgs a) { count_body<false>(a, logical_block(), gridDim.x); }
 
 // The count pass of the merged step (classification of the cover cells' particles).
-__global__ __launch_bounds__(kBuildBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_count_cls(CountArgs a) {
+__global__ __launch_bounds__(kBuildBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_count_cls(ClsArgs a) {
     count_body<true>(a, logical_block(), gridDim.x);
 }
 
@@ -3277,10 +3280,10 @@ extern "C" sph_status sph_celllist_build(sph_ctx *ctx, const sph_particles *p) {
         (int64_t)count_blocks(pp.capacity) * kClsList >= pp.capacity) {
         // count + classification of the cover cells' particles here; the scan and the
         // scatter are left for the update (or the next call that needs the cell list)
-        CountArgs ca = count_args(ctx, pp);
+        ClsArgs ca{};
+        static_cast<CountArgs &>(ca) = count_args(ctx, pp);
         ca.nonfinite = &ctx->d_ctl->nonfinite_full;
         ca.cover = ctx->d_cover;
-        ca.cls = 1;
         ca.nb = ctx->nb;
         ca.p = pp;
         ca.bufs = ctx->d_bufs;
