@@ -1664,8 +1664,13 @@ __device__ __forceinline__ void share_of(unsigned n, int q, int nparts, unsigned
 
 // Segment of a flat event number e, given the exclusive segment offsets.
 __device__ __forceinline__ int seg_of(const unsigned *off, unsigned e) {
+    // the last segment g with off[g] <= e (off is non-decreasing, off[0] = 0):
+    // four dependent LDS reads
+    static_assert(kSeg == 16, "segment search");
     int g = 0;
-    while (g + 1 < kSeg && off[g + 1] <= e) ++g;
+#pragma unroll
+    for (int step = kSeg / 2; step > 0; step >>= 1)
+        if (off[g + step] <= e) g += step;
     return g;
 }
 
@@ -1805,41 +1810,60 @@ __device__ __forceinline__ void finalize_body(const FinArgs &a, const int fb, co
         share_of(G, fb, nfb, g0, g1);
         share_of(R, fb, nfb, r0, r1);
         uint32_t mn0 = 0xffffffffu, mx0 = 0u, mn1 = 0xffffffffu, mx1 = 0u;  // key ranges, for the sort
-        for (unsigned e = tid; e < G; e += bd) {
-            const int g = seg_of(s_off[0], e);
-            const unsigned ev = (unsigned)g * cap + (e - s_off[0][g]);
-            const bool mine = e >= g0 && e < g1;
+        // One round per bd entries of the longest list: the generation, deletion and
+        // relabel entries of index e are all loaded before any is used (one round trip
+        // for the three lists).
+        const unsigned nround = max(G, max(D, R));
+        for (unsigned base = 0; base < nround; base += bd) {  // block-uniform
+            const unsigned e = base + (unsigned)tid;
+            const bool hg = e < G, hd = e < D, hr = e < R;
+            const bool mine = hg && e >= g0 && e < g1;
+            unsigned ev = 0u;
+            uint32_t gi = 0u, di = 0u;
+            unsigned long long rv = 0ull;
             float rn[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-            if (mine)
-                for (int q = 0; q < 4; ++q)
-                    if (q < dim || (q == 3 && a.e.rho_field >= 0)) rn[q] = a.e.gen_new[4 * (size_t)ev + q];
-            const uint32_t i = a.e.gen_idx[ev];
-            s_k[0][0][e] = i;
-            s_v[0][e] = ev;
-            mn0 = min(mn0, i);
-            mx0 = max(mx0, i);
-            if ((long long)i >= Np) {
-                atomicOr(&s_map[i - Np], ev + 1u);
-            } else if (mine) {
-                for (int q = 0; q < dim; ++q) p.pos[q][i] = rn[q];
-                if (a.e.rho_field >= 0) p.car[a.e.rho_field][i] = rn[3];
+            if (hg) {
+                const int g = seg_of(s_off[0], e);
+                ev = (unsigned)g * cap + (e - s_off[0][g]);
+                if (mine)
+                    for (int q = 0; q < 4; ++q)
+                        if (q < dim || (q == 3 && a.e.rho_field >= 0)) rn[q] = a.e.gen_new[4 * (size_t)ev + q];
+                gi = a.e.gen_idx[ev];
             }
-        }
-        for (unsigned e = tid; e < D; e += bd) {
-            const int g = seg_of(s_off[1], e);
-            const uint32_t i = a.e.del_idx[(size_t)g * cap + (e - s_off[1][g])];
-            s_k[1][0][e] = i;
-            mn1 = min(mn1, i);
-            mx1 = max(mx1, i);
-            if ((long long)i >= Np) atomicOr(&s_bits[(i - Np) >> 5], 1u << ((i - Np) & 31));
-        }
-        for (unsigned q = tid; q < R; q += bd) {
-            const int g = seg_of(s_off[2], q);
-            const unsigned long long v = a.e.rel[(size_t)g * a.e.cap_rel + (q - s_off[2][g])];
-            const long long i = (long long)(v >> 32);
-            const uint32_t lab = (uint32_t)(v & 0xffffffffull);
-            if (i >= Np) atomicOr(&s_map[i - Np], (lab + 1u) << kMapRelShift);
-            else if (q >= r0 && q < r1) p.label[i] = (int32_t)lab;  // in place, this block's share
+            if (hd) {
+                const int g = seg_of(s_off[1], e);
+                di = a.e.del_idx[(size_t)g * cap + (e - s_off[1][g])];
+            }
+            if (hr) {
+                const int g = seg_of(s_off[2], e);
+                rv = a.e.rel[(size_t)g * a.e.cap_rel + (e - s_off[2][g])];
+            }
+            if (hg) {
+                const uint32_t i = gi;
+                s_k[0][0][e] = i;
+                s_v[0][e] = ev;
+                mn0 = min(mn0, i);
+                mx0 = max(mx0, i);
+                if ((long long)i >= Np) {
+                    atomicOr(&s_map[i - Np], ev + 1u);
+                } else if (mine) {
+                    for (int q = 0; q < dim; ++q) p.pos[q][i] = rn[q];
+                    if (a.e.rho_field >= 0) p.car[a.e.rho_field][i] = rn[3];
+                }
+            }
+            if (hd) {
+                const uint32_t i = di;
+                s_k[1][0][e] = i;
+                mn1 = min(mn1, i);
+                mx1 = max(mx1, i);
+                if ((long long)i >= Np) atomicOr(&s_bits[(i - Np) >> 5], 1u << ((i - Np) & 31));
+            }
+            if (hr) {
+                const long long i = (long long)(rv >> 32);
+                const uint32_t lab = (uint32_t)(rv & 0xffffffffull);
+                if (i >= Np) atomicOr(&s_map[i - Np], (lab + 1u) << kMapRelShift);
+                else if (e >= r0 && e < r1) p.label[i] = (int32_t)lab;  // in place, this block's share
+            }
         }
         for (int off = 32; off > 0; off >>= 1) {
             mn0 = min(mn0, (uint32_t)__shfl_xor(mn0, off));
