@@ -1677,6 +1677,10 @@ __device__ __forceinline__ int seg_of(const unsigned *off, unsigned e) {
 constexpr uint32_t kMapRelShift = 20;  // tail map: bits 0..19 recycle entry + 1, bits 20.. new label + 1
 constexpr int kSortBuckets = 8192;   // buckets per list of the finalize's counting sort (16-bit counters)
 constexpr int kSortBucketMax = 64;   // fuller buckets: comparison sort instead
+// LDS position of word w of the bucket counters: one pad word per 32, so that the
+// bucket scan's per-thread runs of kSortBuckets / kFinBlock words do not pile up
+// on a few banks
+__device__ __forceinline__ unsigned hx(unsigned w) { return w + (w >> 5); }
 static_assert(kMaxEv % kFinBlock == 0 && kSortBuckets % kFinBlock == 0 && kMaxEv < 65536, "finalize sort layout");
 
 // LDS of one finalize workgroup (declared by the kernel, so that a launch that
@@ -1693,7 +1697,7 @@ struct FinLds {
     unsigned found[SPH_MAX_BUFFERS], post[SPH_MAX_BUFFERS];
     long long nl[SPH_MAX_BUFFERS];
     unsigned flags[3];
-    uint32_t hist[kSortBuckets];       // per list, two buckets per word: counts, then starts
+    uint32_t hist[kSortBuckets + kSortBuckets / 32];  // per list, two buckets per word: counts, then starts (padded, hx)
     uint32_t mm[2][2];                 // per list: min and max key
     unsigned fat[2];                   // per list: keys in the fullest bucket
     unsigned wsum[kFinBlock / kWave];
@@ -1748,7 +1752,7 @@ __device__ __forceinline__ void finalize_body(const FinArgs &a, const int fb, co
     }
     for (unsigned t = tid; t < kMaxEv; t += bd) s_map[t] = 0u;
     for (unsigned w = tid; w < kMaxEv / 32; w += bd) s_bits[w] = 0u;
-    for (unsigned t = tid; t < kSortBuckets; t += bd) s_hist[t] = 0u;
+    for (unsigned t = tid; t < kSortBuckets + kSortBuckets / 32; t += bd) s_hist[t] = 0u;
     if (tid < 2) {
         s_mm[tid][0] = 0xffffffffu;
         s_mm[tid][1] = 0u;
@@ -1919,7 +1923,7 @@ __device__ __forceinline__ void finalize_body(const FinArgs &a, const int fb, co
                 slot[l][q] = 0u;
                 if (e < nl[l]) {
                     const uint32_t b = (s_k[l][0][e] - s_mm[l][0]) >> shift[l], sh = (b & 1u) * 16u;
-                    slot[l][q] = (atomicAdd(&s_hist[l * (kSortBuckets / 2) + (b >> 1)], 1u << sh) >> sh) & 0xffffu;
+                    slot[l][q] = (atomicAdd(&s_hist[hx(l * (kSortBuckets / 2) + (b >> 1))], 1u << sh) >> sh) & 0xffffu;
                 }
             }
         __syncthreads();
@@ -1929,7 +1933,7 @@ __device__ __forceinline__ void finalize_body(const FinArgs &a, const int fb, co
             uint32_t v[kWords], sum = 0, fat = 0;
 #pragma unroll
             for (int q = 0; q < kWords; ++q) {
-                v[q] = s_hist[kWords * tid + q];
+                v[q] = s_hist[hx(kWords * tid + q)];
                 const uint32_t lo = v[q] & 0xffffu, hi = v[q] >> 16;
                 sum += lo + hi;
                 fat = max(fat, max(lo, hi));
@@ -1949,7 +1953,7 @@ __device__ __forceinline__ void finalize_body(const FinArgs &a, const int fb, co
             for (int q = 0; q < kWords; ++q) {
                 const uint32_t lo = run;
                 run += v[q] & 0xffffu;
-                s_hist[kWords * tid + q] = lo | (run << 16);
+                s_hist[hx(kWords * tid + q)] = lo | (run << 16);
                 run += v[q] >> 16;
             }
         }
@@ -1966,7 +1970,7 @@ __device__ __forceinline__ void finalize_body(const FinArgs &a, const int fb, co
                         const uint32_t k = s_k[l][0][e];
                         const uint32_t b = (k - s_mm[l][0]) >> shift[l];
                         const uint32_t pos =
-                            ((s_hist[l * (kSortBuckets / 2) + (b >> 1)] >> ((b & 1u) * 16u)) & 0xffffu) + slot[l][q];
+                            ((s_hist[hx(l * (kSortBuckets / 2) + (b >> 1))] >> ((b & 1u) * 16u)) & 0xffffu) + slot[l][q];
                         s_k[l][1][pos] = k;
                         if (l == 0) s_v[1][pos] = s_v[0][e];
                     }
@@ -1980,10 +1984,11 @@ __device__ __forceinline__ void finalize_body(const FinArgs &a, const int fb, co
                     if (t < nl[l]) {
                         const uint32_t k = s_k[l][1][t];
                         const uint32_t b = (k - s_mm[l][0]) >> shift[l];
-                        const uint32_t *hs = s_hist + l * (kSortBuckets / 2);
-                        const uint32_t b0 = (hs[b >> 1] >> ((b & 1u) * 16u)) & 0xffffu;
-                        const uint32_t b1 =
-                            b + 1 < (uint32_t)kSortBuckets ? (hs[(b + 1) >> 1] >> (((b + 1) & 1u) * 16u)) & 0xffffu : nl[l];
+                        const unsigned hb = l * (kSortBuckets / 2);
+                        const uint32_t b0 = (s_hist[hx(hb + (b >> 1))] >> ((b & 1u) * 16u)) & 0xffffu;
+                        const uint32_t b1 = b + 1 < (uint32_t)kSortBuckets
+                                                ? (s_hist[hx(hb + ((b + 1) >> 1))] >> (((b + 1) & 1u) * 16u)) & 0xffffu
+                                                : nl[l];
                         uint32_t rank = b0;
                         for (uint32_t j = b0; j < b1; ++j) rank += s_k[l][1][j] < k ? 1u : 0u;
                         s_k[l][0][rank] = k;
