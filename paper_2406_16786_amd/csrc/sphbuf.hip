@@ -1796,8 +1796,11 @@ __device__ __forceinline__ void finalize_body(const FinArgs &a, const int fb, co
             s_status = st;
             s_N = N;
             // Every counter this block reads has been read (the values are used
-            // above); the ticket's result is only needed at the end.
-            ticket = __hip_atomic_fetch_add(&c->fin_ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // above); the ticket's result is only needed at the end.  With no error
+            // it is taken after the event lists are loaded: a wave waiting for its
+            // loads also waits for every access it issued before them.
+            if (st != SPH_OK)
+                ticket = __hip_atomic_fetch_add(&c->fin_ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
     __syncthreads();
@@ -1869,6 +1872,7 @@ __device__ __forceinline__ void finalize_body(const FinArgs &a, const int fb, co
                 else if (e >= r0 && e < r1) p.label[i] = (int32_t)lab;  // in place, this block's share
             }
         }
+        if (tid == 0) ticket = __hip_atomic_fetch_add(&c->fin_ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         for (int off = 32; off > 0; off >>= 1) {
             mn0 = min(mn0, (uint32_t)__shfl_xor(mn0, off));
             mx0 = max(mx0, (uint32_t)__shfl_xor(mx0, off));
