@@ -836,16 +836,20 @@ __device__ __forceinline__ void scan_body(const ScanArgs &a, ScanLds &L) {
     const unsigned tile = s_tile;
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     const int64_t t0 = (int64_t)tile * kScanTile;
+    // every count of the tile is loaded before any is cleared: a wave waiting for a
+    // load also waits for the stores it issued before it
+    int vq[kScanItems];
+#pragma unroll
+    for (int q = 0; q < kScanItems; ++q) {
+        const int64_t gj = t0 + q * kScanBlock + (int)threadIdx.x;
+        vq[q] = gj < a.m ? a.count[gj] : 0;
+    }
 #pragma unroll
     for (int q = 0; q < kScanItems; ++q) {
         const int j = q * kScanBlock + (int)threadIdx.x;
         const int64_t gj = t0 + j;
-        int v = 0;
-        if (gj < a.m) {
-            v = a.count[gj];
-            a.count[gj] = 0;
-        }
-        s_buf[j + j / 32] = v;
+        if (gj < a.m) a.count[gj] = 0;
+        s_buf[j + j / 32] = vq[q];
     }
     __syncthreads();
     int v[kScanItems];
