@@ -590,11 +590,10 @@ __device__ __forceinline__ void count_body(const A &a, const int lb, const int G
     // Software pipelined: once a step has its keys it issues the next step's position
     // loads, then its run detection and atomics, so the two round trips overlap.
     float px[J], py[J], pz[J];
-    // The plain pass loads without a branch (lanes past a row's end re-read its first
-    // particle, rows with none the array's first; a 2-D z is a copy of x, unused):
-    // behind a branch the compiler waits for every outstanding access, the previous
-    // step's stores included, before the next loads.  The classifying pass keeps the
-    // branch (its register budget).
+    // The positions are loaded without a branch (lanes past a row's end re-read its
+    // first particle, rows with none the array's first; a 2-D z is a copy of x,
+    // unused): behind a branch the compiler waits for every outstanding access, the
+    // previous step's stores included, before the next loads.
     const float *xl[J], *yl[J], *zl[J];
 #pragma unroll
     for (int j = 0; j < J; ++j) {
@@ -606,19 +605,10 @@ __device__ __forceinline__ void count_body(const A &a, const int lb, const int G
         const uint32_t o = it + (uint32_t)lane;
 #pragma unroll
         for (int j = 0; j < J; ++j) {
-            if constexpr (kCls) {
-                px[j] = py[j] = pz[j] = 0.0f;
-                if (o < nr[j]) {
-                    px[j] = at32(xr[j], o);
-                    py[j] = at32(yr[j], o);
-                    if (d3) pz[j] = at32(zr[j], o);
-                }
-            } else {
-                const uint32_t oc = o < nr[j] ? o : 0u;
-                px[j] = at32(xl[j], oc);
-                py[j] = at32(yl[j], oc);
-                pz[j] = at32(zl[j], oc);
-            }
+            const uint32_t oc = o < nr[j] ? o : 0u;
+            px[j] = at32(xl[j], oc);
+            py[j] = at32(yl[j], oc);
+            pz[j] = at32(zl[j], oc);
         }
     };
     load(0);
@@ -2068,10 +2058,6 @@ __device__ __forceinline__ void finalize_body(const FinArgs &a, const int fb, co
             }
         }
         const uint32_t *gsrc = s_k[0][cur], *gslot = s_v[cur], *del = s_k[1][cur];
-        if (fb == 0) {
-            for (unsigned j = tid; j < G; j += bd) a.gen_sorted[j] = gsrc[j];
-            for (unsigned j = tid; j < D; j += bd) a.del_sorted[j] = del[j];
-        }
         // ---- tail positions: move the survivor at p into its hole, then append at p ----
         unsigned t0, t1;
         share_of(G > D ? G : D, fb, nfb, t0, t1);
@@ -2123,6 +2109,12 @@ __device__ __forceinline__ void finalize_body(const FinArgs &a, const int fb, co
                 p.label[pi] = 0;
                 p.id[pi] = s_next + (long long)t;
             }
+        }
+        // the sorted lists for sph_last_events, after the tail loads (a wave waiting
+        // for a load also waits for the stores it issued before it)
+        if (fb == 0) {
+            for (unsigned j = tid; j < G; j += bd) a.gen_sorted[j] = gsrc[j];
+            for (unsigned j = tid; j < D; j += bd) a.del_sorted[j] = del[j];
         }
     }
     // ---- the last block to take a ticket publishes the result and clears the counters ----
