@@ -2869,9 +2869,12 @@ sph_status merged_cells(sph_ctx *c) {
 // or a full scan fills the event lists again (rebuild: its non-finite flag too).
 sph_status merged_drop(sph_ctx *c, bool rebuild) {
     HIP_CHECKED(merged_cells(c));
+    // a merged build's non-finite flag no finalize consumed (its events may have
+    // been dropped earlier) must not reach the next build's or full scan's finalize
+    const bool clear_nf = rebuild && c->nf_full_next;
     if (rebuild) c->nf_full_next = false;
-    if (!c->ev_pending) return SPH_OK;
-    hipLaunchKernelGGL(k_reset_events, dim3(1), dim3(256), 0, c->stream, c->d_ctl, c->d_part, rebuild ? 1 : 0);
+    if (!c->ev_pending && !clear_nf) return SPH_OK;
+    hipLaunchKernelGGL(k_reset_events, dim3(1), dim3(256), 0, c->stream, c->d_ctl, c->d_part, clear_nf ? 1 : 0);
     HIP_TRY(hipGetLastError());
     c->ev_pending = false;
     return SPH_OK;

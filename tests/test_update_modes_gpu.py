@@ -189,3 +189,28 @@ def test_merged_step_bent_channel_1000_steps(monkeypatch):
     _mode(monkeypatch, "merged")
     g, dl = _run_steps(W.bent_channel2d(), 1000, check_every=100)
     assert g > 0 and dl > 0
+
+
+@pytest.mark.parametrize("then", ["build", "fullscan"])
+def test_merged_dropped_events_leave_no_nonfinite_flag(then, monkeypatch):
+    """A merged build that met a non-finite position and whose events a library call
+    dropped before any update: once the position is finite again, the next build's
+    update (or a full-scan update) must not report it."""
+    import tests.test_parity_gpu as P
+    _mode(monkeypatch, "merged")
+    wl, bufs, st = P._two_buffer_case([(1.125, 0.5), (np.nan, 0.4), (0.3, 0.3)], [1, 0, 1])
+    d = make_domain(wl, bufs, st)
+    P._identify_counts(d, bufs, st)
+    d.build()                        # classifies, raises the non-finite flag
+    d.set_fields([0, 1], -1)         # drops the build's events
+    st.pos[0][1] = np.float32(0.4)   # finite again
+    upload_state(d, st)
+    if then == "build":
+        d.build()
+        gst, g, dl = d.update()
+    else:
+        gst, g, dl = d.update_fullscan()
+    res = oracle.update(bufs, st)
+    assert gst == res.status == 0, (gst, res.status)
+    assert_same_state(d, st, "after the dropped build")
+    d.close()
