@@ -33,9 +33,11 @@ MAX_CARRIED = 16
 
 
 def build(verbose: bool = False) -> str:
-    """Compile the oracle with gcc (FP64, no FMA contraction); returns the .so path."""
+    """Compile the oracle with gcc (FP64, no FMA contraction; OpenMP over the
+    per-particle loops, whose arithmetic does not depend on it); returns the .so
+    path."""
     cmd = [
-        "gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+        "gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
         "-Wall", "-Wextra", "-o", _LIB + ".tmp", _SRC, "-lm",
     ]
     if verbose:
@@ -137,6 +139,14 @@ def lib():
                                          ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p, ctypes.c_int64,
                                          ctypes.c_void_p]
         L.orc_neighbor_count.restype = None
+        L.orc_update_local.argtypes = [ctypes.POINTER(_CBuffer), ctypes.c_int, ctypes.POINTER(_CState),
+                                       ctypes.c_void_p, ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p,
+                                       ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]
+        L.orc_update_local.restype = ctypes.c_int
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_set_threads.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -350,6 +360,40 @@ def update(bufs: Sequence[Buffer], st: State, bcs: Optional[Sequence[BC]] = None
                              ctypes.cast(ctypes.pointer(cf), ctypes.c_void_p) if cf is not None else None,
                              len(bufs), ctypes.byref(cs), gen.ctypes.data, ctypes.byref(ng),
                              dele.ctypes.data, ctypes.byref(nd), nl.ctypes.data)
+    if rc == OK:
+        st.n = int(cs.n)
+        st.next_id = int(cs.next_id)
+        return UpdateResult(rc, gen[: ng.value].copy(), dele[: nd.value].copy(), nl[: len(bufs)].copy())
+    return UpdateResult(rc, np.zeros(0, np.int64), np.zeros(0, np.int64), np.zeros(len(bufs), np.int64))
+
+
+def set_threads(n: int = 0) -> int:
+    """Threads of the oracle's per-particle loops (n <= 0 leaves the setting);
+    returns the number the next call uses."""
+    return int(lib().orc_set_threads(int(n)))
+
+
+def update_local(bufs: Sequence[Buffer], st: State, lo, inv_cs: float, dims, cell_start: np.ndarray,
+                 cell_idx: np.ndarray, n_labelled_in: Sequence[int]) -> UpdateResult:
+    """The update with candidates only from the cells of a cell list (from
+    cell_list on the dense grid lo, inv_cs, dims) near each check region: the
+    paper's method on the CPU, for the CPU baseline.  Same results as update()."""
+    cs = st.c()
+    cb = _cbufs(bufs)
+    lo32, d = _grid_args(st.dim, lo, dims)
+    cap = max(1, st.n)
+    gen = np.zeros(cap, dtype=np.int64)
+    dele = np.zeros(cap, dtype=np.int64)
+    ng, nd = ctypes.c_int64(0), ctypes.c_int64(0)
+    nl = np.zeros(max(1, len(bufs)), dtype=np.int64)
+    nl_in = np.zeros(max(1, len(bufs)), dtype=np.int64)
+    nl_in[: len(bufs)] = n_labelled_in
+    cell_start = np.ascontiguousarray(cell_start, dtype=np.int32)
+    cell_idx = np.ascontiguousarray(cell_idx, dtype=np.int32)
+    rc = lib().orc_update_local(cb, len(bufs), ctypes.byref(cs), lo32.ctypes.data, float(np.float32(inv_cs)),
+                                d.ctypes.data, cell_start.ctypes.data, cell_idx.ctypes.data, nl_in.ctypes.data,
+                                gen.ctypes.data, ctypes.byref(ng), dele.ctypes.data, ctypes.byref(nd),
+                                nl.ctypes.data)
     if rc == OK:
         st.n = int(cs.n)
         st.next_id = int(cs.next_id)

@@ -18,6 +18,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* ---------------------------------------------------------------- frames --- */
 
@@ -192,6 +195,11 @@ int orc_identify(const orc_buffer *bufs, int nb, int which, orc_state *s, int64_
 
 enum { EV_NONE = 0, EV_GEN = 1, EV_DEL = 2 };
 
+static int cmp_i64(const void *a, const void *b) {
+    const int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+    return (x > y) - (x < y);
+}
+
 static void copy_particle(orc_state *s, int64_t dst, int64_t src) {
     for (int c = 0; c < s->dim; c++) s->pos[c][dst] = s->pos[c][src];
     for (int f = 0; f < s->n_carried; f++) s->carried[f][dst] = s->carried[f][src];
@@ -238,73 +246,83 @@ static float recycled_density(const orc_bc *bc) {
     return (float)(bc->rho0 + bc->p_b / (bc->c0 * bc->c0));
 }
 
-int orc_update_bc(const orc_buffer *bufs, const orc_bc *bcs, const orc_fields *fields, int nb, orc_state *s,
-                  int64_t *gen_src, int64_t *n_gen, int64_t *del_idx, int64_t *n_del, int64_t *n_labelled) {
-    if (!valid_args(bufs, nb, s) || !valid_fields(fields, s)) return ORC_ERR_ARG;
+/* Event of a particle in the check region of buffer b (local coordinates lc,
+ * mine: it carries the buffer's label): Algorithm 1 (inlet generation),
+ * Algorithm 2 (outlet deletion), Algorithm 3 (bidirectional: both). */
+static unsigned char event_of(const orc_buffer *b, int mine, const double lc[3]) {
+    if (b->kind == ORC_INLET) return (mine && lc[0] > b->half[0]) ? EV_GEN : EV_NONE;
+    if (b->kind == ORC_OUTLET) return lc[0] > b->half[0] ? EV_DEL : EV_NONE;
+    if (mine && lc[0] > b->half[0]) return EV_GEN;
+    if (mine && lc[0] < -b->half[0]) return EV_DEL;
+    return EV_NONE;
+}
+
+/* Particle i against every buffer on the input state: its event and owning
+ * buffer (written only when it is in order), ORC_ERR_CFL if it carries label k
+ * but lies outside C_k, ORC_ERR_ARG if two check regions hold it. */
+static int classify_particle(const orc_buffer *bufs, int nb, const orc_state *s, int64_t i, unsigned char *ev,
+                             unsigned char *owner) {
+    double r[3], lc[3];
+    position_of(s, i, r);
+    unsigned char e = EV_NONE, own = 0;
+    for (int k = 0; k < nb; k++) {
+        const orc_buffer *b = &bufs[k];
+        local_of(s->dim, b, r[0], r[1], r[2], lc);
+        if (!in_check(s->dim, b, lc)) {
+            if (s->label[i] == k + 1) return ORC_ERR_CFL;
+            continue;
+        }
+        if (own != 0) return ORC_ERR_ARG; /* overlapping regions */
+        own = (unsigned char)(k + 1);
+        e = event_of(b, s->label[i] == k + 1, lc);
+    }
+    ev[i] = e;
+    owner[i] = own;
+    return ORC_OK;
+}
+
+/* Relabel of outlets / bidirectional buffers (Algorithms 2 and 3, second
+ * procedure) for one surviving particle, on its post-recycle position. */
+static void relabel_particle(const orc_buffer *bufs, int nb, orc_state *s, int64_t i) {
+    double r[3], lc[3];
+    position_of(s, i, r);
+    for (int k = 0; k < nb; k++) {
+        const orc_buffer *b = &bufs[k];
+        if (b->kind == ORC_INLET) continue;
+        local_of(s->dim, b, r[0], r[1], r[2], lc);
+        if (!in_check(s->dim, b, lc)) continue;
+        if (in_box(s->dim, b, lc)) s->label[i] = k + 1;
+        else if (s->label[i] == k + 1) s->label[i] = 0;
+    }
+}
+
+/* Everything after the classification: index sets (ascending), capacity check,
+ * duplicates (pre-recycle state), recycle, relabel of the survivors (cand: the
+ * particles to relabel, NULL for all), hole refill and append. */
+static int apply_events(const orc_buffer *bufs, const orc_bc *bcs, const orc_fields *fields, int nb, orc_state *s,
+                        unsigned char *ev, const unsigned char *owner, const int64_t *cand, int64_t n_cand,
+                        int64_t *gen_src, int64_t *n_gen, int64_t *del_idx, int64_t *n_del, int64_t *n_labelled) {
     const int dim = s->dim;
     const int64_t N = s->n;
-
-    for (int64_t i = 0; i < N; i++)
-        for (int c = 0; c < dim; c++)
-            if (!isfinite(s->pos[c][i])) return ORC_ERR_NONFINITE;
-
-    unsigned char *ev = (unsigned char *)calloc((size_t)(N > 0 ? N : 1), 1);
-    unsigned char *owner = (unsigned char *)calloc((size_t)(N > 0 ? N : 1), 1);
-    if (!ev || !owner) {
-        free(ev);
-        free(owner);
-        return ORC_ERR_ARG;
-    }
-    int status = ORC_OK;
-
-    /* ---- classification on the input state ---- */
-    for (int64_t i = 0; i < N && status == ORC_OK; i++) {
-        double r[3], lc[3];
-        position_of(s, i, r);
-        for (int k = 0; k < nb; k++) {
-            const orc_buffer *b = &bufs[k];
-            local_of(dim, b, r[0], r[1], r[2], lc);
-            if (!in_check(dim, b, lc)) {
-                if (s->label[i] == k + 1) { status = ORC_ERR_CFL; break; }
-                continue;
-            }
-            if (owner[i] != 0) { status = ORC_ERR_ARG; break; } /* overlapping regions */
-            owner[i] = (unsigned char)(k + 1);
-            const int mine = (s->label[i] == k + 1);
-            if (b->kind == ORC_INLET) {
-                if (mine && lc[0] > b->half[0]) ev[i] = EV_GEN;
-            } else if (b->kind == ORC_OUTLET) {
-                if (lc[0] > b->half[0]) ev[i] = EV_DEL;
-            } else {
-                if (mine && lc[0] > b->half[0]) ev[i] = EV_GEN;
-                else if (mine && lc[0] < -b->half[0]) ev[i] = EV_DEL;
-            }
+    int64_t G = 0, D = 0;
+    if (cand) {
+        /* index sets from the candidates, then sorted */
+        for (int64_t j = 0; j < n_cand; j++) {
+            const int64_t i = cand[j];
+            if (ev[i] == EV_GEN) gen_src[G++] = i;
+            if (ev[i] == EV_DEL) del_idx[D++] = i;
+        }
+        qsort(gen_src, (size_t)G, sizeof(int64_t), cmp_i64);
+        qsort(del_idx, (size_t)D, sizeof(int64_t), cmp_i64);
+    } else {
+        /* index sets, ascending because i runs upwards */
+        for (int64_t i = 0; i < N; i++) {
+            if (ev[i] == EV_GEN) gen_src[G++] = i;
+            if (ev[i] == EV_DEL) del_idx[D++] = i;
         }
     }
-    if (status != ORC_OK) {
-        free(ev);
-        free(owner);
-        return status;
-    }
-
-    int64_t G = 0, D = 0;
-    for (int64_t i = 0; i < N; i++) {
-        if (ev[i] == EV_GEN) G++;
-        if (ev[i] == EV_DEL) D++;
-    }
     const int64_t Np = N - D;
-    if (Np + G > s->capacity) {
-        free(ev);
-        free(owner);
-        return ORC_ERR_CAPACITY;
-    }
-
-    /* index sets, ascending because i runs upwards */
-    int64_t g = 0, d = 0;
-    for (int64_t i = 0; i < N; i++) {
-        if (ev[i] == EV_GEN) gen_src[g++] = i;
-        if (ev[i] == EV_DEL) del_idx[d++] = i;
-    }
+    if (Np + G > s->capacity) return ORC_ERR_CAPACITY;
 
     /* ---- duplicates: a copy of the crossing particle's state, before recycling ---- */
     const int nf = s->n_carried;
@@ -331,32 +349,32 @@ int orc_update_bc(const orc_buffer *bufs, const orc_bc *bcs, const orc_fields *f
     }
 
     /* ---- relabel outlets / bidirectional buffers on post-recycle positions ---- */
-    for (int64_t i = 0; i < N; i++) {
-        if (ev[i] == EV_DEL) continue;
-        double r[3], lc[3];
-        position_of(s, i, r);
-        for (int k = 0; k < nb; k++) {
-            const orc_buffer *b = &bufs[k];
-            if (b->kind == ORC_INLET) continue;
-            local_of(dim, b, r[0], r[1], r[2], lc);
-            if (!in_check(dim, b, lc)) continue;
-            if (in_box(dim, b, lc)) s->label[i] = k + 1;
-            else if (s->label[i] == k + 1) s->label[i] = 0;
+    int64_t nl_cand[ORC_MAX_BUFFERS] = {0};
+    if (cand) {
+        /* every particle of a buffer is one of its candidates: the labelled counts
+         * after the update are those of the surviving candidates */
+        for (int64_t j = 0; j < n_cand; j++) {
+            const int64_t i = cand[j];
+            if (ev[i] == EV_DEL) continue;
+            relabel_particle(bufs, nb, s, i);
+            if (s->label[i] == owner[i]) nl_cand[owner[i] - 1]++;
         }
+    } else {
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < N; i++)
+            if (ev[i] != EV_DEL) relabel_particle(bufs, nb, s, i);
     }
 
     /* ---- layout: refill holes below Np from the surviving tail, ascending ---- */
     {
-        int64_t h = 0, t = Np;
+        int64_t t = Np;
         for (int64_t j = 0; j < D; j++) {
             int64_t hole = del_idx[j];
             if (hole >= Np) break;
             while (t < N && ev[t] == EV_DEL) t++;
             copy_particle(s, hole, t);
             t++;
-            h++;
         }
-        (void)h;
     }
 
     /* ---- append duplicates: label 0, fresh ids ---- */
@@ -372,13 +390,130 @@ int orc_update_bc(const orc_buffer *bufs, const orc_bc *bcs, const orc_fields *f
 
     free(dup_pos);
     free(dup_car);
-    free(ev);
-    free(owner);
 
     *n_gen = G;
     *n_del = D;
-    count_labels(nb, s, n_labelled);
+    if (!cand) count_labels(nb, s, n_labelled);
+    else if (n_labelled)
+        for (int k = 0; k < nb; k++) n_labelled[k] = nl_cand[k];
     return ORC_OK;
+}
+
+int orc_update_bc(const orc_buffer *bufs, const orc_bc *bcs, const orc_fields *fields, int nb, orc_state *s,
+                  int64_t *gen_src, int64_t *n_gen, int64_t *del_idx, int64_t *n_del, int64_t *n_labelled) {
+    if (!valid_args(bufs, nb, s) || !valid_fields(fields, s)) return ORC_ERR_ARG;
+    const int dim = s->dim;
+    const int64_t N = s->n;
+
+    for (int64_t i = 0; i < N; i++)
+        for (int c = 0; c < dim; c++)
+            if (!isfinite(s->pos[c][i])) return ORC_ERR_NONFINITE;
+
+    unsigned char *ev = (unsigned char *)calloc((size_t)(N > 0 ? N : 1), 1);
+    unsigned char *owner = (unsigned char *)calloc((size_t)(N > 0 ? N : 1), 1);
+    if (!ev || !owner) {
+        free(ev);
+        free(owner);
+        return ORC_ERR_ARG;
+    }
+
+    /* ---- classification on the input state: every particle against every
+     *      buffer; the error reported is that of the lowest index ---- */
+    int64_t first_bad = N;
+#pragma omp parallel for schedule(static) reduction(min : first_bad)
+    for (int64_t i = 0; i < N; i++)
+        if (classify_particle(bufs, nb, s, i, ev, owner) != ORC_OK && i < first_bad) first_bad = i;
+    int status = first_bad < N ? classify_particle(bufs, nb, s, first_bad, ev, owner) : ORC_OK;
+    if (status == ORC_OK)
+        status = apply_events(bufs, bcs, fields, nb, s, ev, owner, NULL, 0, gen_src, n_gen, del_idx, n_del,
+                              n_labelled);
+    free(ev);
+    free(owner);
+    return status;
+}
+
+/* The paper's own method on the CPU (Section 3.1): candidates come only from
+ * the cells of a cell list (cell_start, cell_idx: cell keys as in orc_cell_list
+ * on a dense grid lo, inv_cs, dims) that meet the axis-aligned box around each
+ * buffer's check region, widened by one cell on every side (more than the FP32
+ * binning error).  A buffer particle outside its check region is caught by
+ * counting: n_labelled_in[k] particles carry label k.  Same decisions, index
+ * sets and layout as orc_update_bc. */
+int orc_update_local(const orc_buffer *bufs, int nb, orc_state *s, const float lo[3], float inv_cs,
+                     const int32_t dims[3], const int32_t *cell_start, const int32_t *cell_idx,
+                     const int64_t *n_labelled_in, int64_t *gen_src, int64_t *n_gen, int64_t *del_idx,
+                     int64_t *n_del, int64_t *n_labelled) {
+    if (!valid_args(bufs, nb, s) || !n_labelled_in) return ORC_ERR_ARG;
+    const int dim = s->dim;
+    const int64_t N = s->n;
+    const double cs = 1.0 / (double)inv_cs;
+    unsigned char *ev = (unsigned char *)calloc((size_t)(N > 0 ? N : 1), 1);
+    unsigned char *owner = (unsigned char *)calloc((size_t)(N > 0 ? N : 1), 1);
+    int64_t n_cand = 0, cap = 1024;
+    int64_t *cand = (int64_t *)malloc(sizeof(int64_t) * (size_t)cap);
+    int status = (ev && owner && cand) ? ORC_OK : ORC_ERR_ARG;
+    for (int k = 0; k < nb && status == ORC_OK; k++) {
+        const orc_buffer *b = &bufs[k];
+        int64_t c0[3] = {0, 0, 0}, c1[3] = {0, 0, 0}, found = 0;
+        for (int j = 0; j < dim; j++) {
+            double ext = 0.0;
+            for (int i = 0; i < dim; i++) ext += fabs(b->rot[3 * i + j]) * (b->half[i] + b->margin);
+            double a = floor((b->origin[j] - ext - (double)lo[j]) / cs) - 1.0;
+            double z = floor((b->origin[j] + ext - (double)lo[j]) / cs) + 1.0;
+            a = a < 0.0 ? 0.0 : (a > dims[j] - 1 ? dims[j] - 1 : a);
+            z = z < 0.0 ? 0.0 : (z > dims[j] - 1 ? dims[j] - 1 : z);
+            c0[j] = (int64_t)a;
+            c1[j] = (int64_t)z;
+        }
+        for (int64_t iz = c0[2]; iz <= c1[2] && status == ORC_OK; iz++)
+            for (int64_t iy = c0[1]; iy <= c1[1] && status == ORC_OK; iy++)
+                for (int64_t ix = c0[0]; ix <= c1[0] && status == ORC_OK; ix++) {
+                    const int64_t key = ix + (int64_t)dims[0] * (iy + (int64_t)dims[1] * iz);
+                    for (int32_t t = cell_start[key]; t < cell_start[key + 1]; t++) {
+                        const int64_t i = cell_idx[t];
+                        double r[3], lc[3];
+                        position_of(s, i, r);
+                        if (!(isfinite(r[0]) && isfinite(r[1]) && isfinite(r[2]))) {
+                            status = ORC_ERR_NONFINITE;
+                            break;
+                        }
+                        local_of(dim, b, r[0], r[1], r[2], lc);
+                        if (!in_check(dim, b, lc)) continue;
+                        if (owner[i] != 0) {
+                            status = ORC_ERR_ARG;
+                            break;
+                        }
+                        owner[i] = (unsigned char)(k + 1);
+                        found += s->label[i] == k + 1;
+                        ev[i] = event_of(b, s->label[i] == k + 1, lc);
+                        if (n_cand == cap) {
+                            cap *= 2;
+                            cand = (int64_t *)realloc(cand, sizeof(int64_t) * (size_t)cap);
+                        }
+                        cand[n_cand++] = i;
+                    }
+                }
+        if (status == ORC_OK && found != n_labelled_in[k]) status = ORC_ERR_CFL;
+    }
+    if (status == ORC_OK)
+        status = apply_events(bufs, NULL, NULL, nb, s, ev, owner, cand, n_cand, gen_src, n_gen, del_idx, n_del,
+                              n_labelled);
+    free(cand);
+    free(ev);
+    free(owner);
+    return status;
+}
+
+/* Threads of the parallel loops (OpenMP; 1 when built without it); returns the
+ * number the next call will use. */
+int orc_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }
 
 /* ------------------------------------------------- boundary conditions --- */

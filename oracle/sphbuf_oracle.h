@@ -166,6 +166,19 @@ int orc_rotate_buffer(orc_buffer *bufs, int nb, int which, const double center[3
  * ((dx*dx + dy*dy) + dz*dz) < radius*radius, dx = (double)x_q - (double)x_j,
  * every operation rounded in FP64 (no contraction), dz = 0 in 2-D.  query = NULL
  * queries every particle (nq = n).  O(n) per query. */
+/* The paper's method on the CPU: one update with candidates gathered only from
+ * the cells of a cell list (orc_cell_list on the dense grid lo, inv_cs, dims)
+ * near each buffer's check region; n_labelled_in[k] is the number of particles
+ * carrying label k.  Same results as orc_update.  CPU-baseline mode. */
+int orc_update_local(const orc_buffer *bufs, int nb, orc_state *s, const float lo[3], float inv_cs,
+                     const int32_t dims[3], const int32_t *cell_start, const int32_t *cell_idx,
+                     const int64_t *n_labelled_in, int64_t *gen_src, int64_t *n_gen, int64_t *del_idx,
+                     int64_t *n_del, int64_t *n_labelled);
+
+/* Threads of the oracle's parallel loops (OpenMP over particles; the arithmetic
+ * of each particle is unchanged); returns the count the next call uses. */
+int orc_set_threads(int n);
+
 void orc_neighbor_count(int dim, int64_t n, const float *x, const float *y, const float *z, double radius,
                         const int64_t *query, int64_t nq, int32_t *counts);
 
