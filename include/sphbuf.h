@@ -28,14 +28,26 @@
  *     an update leaves every particle array and the library's own counters as
  *     they were (checks run on the GPU before the first write).
  *   - A context is bound to one HIP stream and is not thread-safe.  All device
- *     work of a context is ordered on that stream (with SPHBUF_UPDATE=overlap a
- *     build's scan and scatter run on a library-owned side stream that later calls
- *     join back with an event).  Calls marked "sync" wait for the stream; the
- *     others only enqueue.  SPHBUF_UPDATE (read at sph_create) picks the update
- *     path: unset, the update walks the cover cells of the finished cell list;
- *     "overlap" and "merged" are described at sph_celllist_build.
+ *     work of a context is ordered on that stream.  Calls marked "sync" wait for
+ *     the stream; the others only enqueue.  sph_config.update_path picks how the
+ *     update finds its candidates (see sph_update_path); results are identical.
  *   - The library allocates its device scratch in sph_create and
  *     sph_buffer_define; build and update calls allocate nothing.
+ *
+ * The calls of the method, by what they do:
+ *   cell-linked list ............ sph_celllist_build (view: sph_celllist_view)
+ *   buffer definition ........... sph_buffer_define (frames: sph_rotation_*)
+ *   one-time identification ..... sph_buffer_identify
+ *   update, counts returned ..... sph_buffer_update (enqueue only:
+ *                                 sph_buffer_update_async + sph_last_result)
+ *   full-scan baseline .......... sph_buffer_update_fullscan[_async]
+ *   event index sets ............ sph_last_events
+ *   state export / import ....... sph_state_export, sph_state_import (the same
+ *                                 fields as sph_state_get / sph_state_set)
+ *   many domains ................ sph_batch_create, sph_batch_step (counts of
+ *                                 every domain: sph_batch_results), graph
+ *                                 capture and replay: sph_batch_graph_capture,
+ *                                 sph_batch_graph_launch
  */
 #ifndef SPHBUF_H
 #define SPHBUF_H
@@ -65,7 +77,22 @@ typedef enum { SPH_INLET = 1, SPH_OUTLET = 2, SPH_BIDIR = 3 } sph_kind;
 
 #define SPH_MAX_BUFFERS 15
 #define SPH_MAX_CARRIED 16
+/* Largest max_events of a context: per update at most this many generated
+ * particles and this many deleted particles (and four times as many relabelled
+ * ones).  The finalize sorts and applies the events of one update on chip, so
+ * the bound is fixed; an update with more events returns SPH_ERR_EVENTS and
+ * changes nothing (a caller with more inflow per step splits it into smaller
+ * steps).  Algorithms 1-3 themselves put no bound on the events of a step. */
 #define SPH_MAX_EVENTS_LIMIT 4096
+
+/* How an update finds its candidates.  Both give the same events and arrays.
+ *   SPH_UPDATE_MERGED (default): the count pass of sph_celllist_build classifies
+ *     the particles of every buffer's cover cells as it bins them and emits their
+ *     events; the update then runs the finalize beside the scan of the cell
+ *     counts and the scatter of the cell list.
+ *   SPH_UPDATE_CELLS: the build only builds the cell list; the update walks the
+ *     cover cells of the finished list (one wave per run of cells). */
+typedef enum { SPH_UPDATE_MERGED = 0, SPH_UPDATE_CELLS = 1 } sph_update_path;
 
 typedef struct sph_ctx sph_ctx;
 
@@ -93,6 +120,8 @@ typedef struct {
     void *stream;           /* hipStream_t (NULL = the null stream)                           */
     int32_t brick_log2;     /* 0: dense grid; 1..5: brick-sparse grid of 2^b cells per axis   */
     int32_t brick_margin;   /* sparse grid: active bricks = occupied ones dilated by this     */
+    int32_t update_path;    /* sph_update_path (0 = SPH_UPDATE_MERGED)                         */
+    int32_t pad2_;
 } sph_config;
 
 /* Result of the last update (see sph_last_result). */
@@ -112,7 +141,12 @@ typedef struct {
 /* Create a context: validates cfg, allocates the cell grid and all scratch on the
  * current HIP device.  SPH_ERR_ARG for a bad config (dim, cell_size <= 0, empty or
  * non-finite bounds, more than 2^31 cells, capacity <= 0 or >= 2^31, max_events
- * outside 1..4096); SPH_ERR_HIP if allocation fails.  *out is NULL on error. */
+ * outside 1..4096, an unknown update_path, or a grid on which FP32 binning can
+ * misplace a particle by a quarter cell or more: the cell coordinate
+ * fl32(fl32(x - fl32(lo)) * fl32(1/cell_size)) is off by at most
+ * |lo - fl32(lo)|/cell_size + 3.0001 2^-24 (cells per axis + 1 + that offset)
+ * cells, and buffer covers are widened by 1.5 times this bound, at least 1e-2
+ * cell); SPH_ERR_HIP if allocation fails.  *out is NULL on error. */
 sph_status sph_create(const sph_config *cfg, sph_ctx **out);
 sph_status sph_destroy(sph_ctx *ctx);
 
@@ -142,20 +176,17 @@ sph_status sph_grid_fit(sph_ctx *ctx, const sph_particles *p);
 
 /* Step 1: counting-sort cell list of the live particles on the context stream
  * (async).  Flags non-finite positions for the next update.
- * With SPHBUF_UPDATE=overlap in the environment at sph_create, the count pass also
- * gathers the particles of every buffer's cover cells, and the scan and scatter run
- * on a library-owned side stream that the next update (or any call that reads the
- * cell list) joins to the context stream; results are the same either way.
- * With SPHBUF_UPDATE=merged, the count pass also classifies the particles of every
- * buffer's cover cells and emits their events (steps 2-5 decided here, on these
- * positions and carried fields; the caller must not change the arrays before the
- * update), and the scan and scatter are left for the update, which runs the
- * finalize beside the scan in one launch and then the scatter; a call that reads
- * the cell list first enqueues them itself.  Library calls that change the state
- * the events were decided on (apply_bc, rotate, identify, set_fields, set_bc,
- * buffer_define, grid_fit, state_set) drop them, and the update then walks the
- * cover cells; results are the same either way.  Capacities above 2^25 particles
- * take the plain build. */
+ * On the merged path (the default) the count pass also classifies the particles
+ * of every buffer's cover cells and emits their events (steps 2-5 decided here,
+ * on these positions and carried fields; the caller must not change the arrays
+ * before the update), and the scan and scatter are left for the update, which
+ * runs the finalize beside the scan in one launch and then the scatter; a call
+ * that reads the cell list first enqueues them itself.  Library calls that
+ * change the state the events were decided on (apply_bc, rotate, identify,
+ * set_fields, set_bc, buffer_define, grid_fit, state_set) drop them, and the
+ * update then walks the cover cells; results are the same either way.
+ * Capacities above 2^25 particles and domains without buffers take the plain
+ * build. */
 sph_status sph_celllist_build(sph_ctx *ctx, const sph_particles *p);
 
 /* Algorithm 1, identification ("execute only once"): label k for every live
@@ -275,6 +306,13 @@ sph_status sph_buffer_rotate(sph_ctx *ctx, sph_particles *p, int32_t buffer_id, 
  * labelled count (sync).  Lets a caller checkpoint and restore a run. */
 sph_status sph_state_get(sph_ctx *ctx, int64_t *next_id, int64_t n_labelled[SPH_MAX_BUFFERS]);
 sph_status sph_state_set(sph_ctx *ctx, int64_t next_id, const int64_t n_labelled[SPH_MAX_BUFFERS]);
+/* The same state as an opaque blob (sync): export writes SPH_STATE_BLOB_BYTES
+ * bytes to blob when *len is at least that, and always sets *len to that size
+ * (blob may be NULL to ask for it: SPH_ERR_ARG, *len set).  import reads a blob
+ * written by export (SPH_ERR_ARG for a wrong length or tag). */
+#define SPH_STATE_BLOB_BYTES 136
+sph_status sph_state_export(sph_ctx *ctx, void *blob, size_t *len);
+sph_status sph_state_import(sph_ctx *ctx, const void *blob, size_t len);
 
 /* ---------------------------------------------------------------- profiling -- */
 
@@ -286,12 +324,11 @@ typedef enum {
     SPH_PHASE_CLASSIFY = 3,   /* local-cell candidates, frame, crossing tests     */
     SPH_PHASE_FULLSCAN = 4,   /* full scan: every particle, FP32 filter (baseline)*/
     SPH_PHASE_FINALIZE = 5,   /* status, sort, duplicate/recycle/relabel/compact  */
-    SPH_PHASE_BUILD = 6,      /* count + scan + scatter in one cooperative launch */
-    SPH_PHASE_BC = 7,         /* boundary conditions on buffer particles          */
-    SPH_PHASE_ROTATE = 8,     /* rigid turn of a buffer's particles               */
-    SPH_PHASE_CANDIDATES = 9, /* full scan: the filter's candidates, exact tests  */
-    SPH_PHASE_NEIGHBOR = 10,  /* neighbour counts over the cell list              */
-    SPH_NPHASE = 11
+    SPH_PHASE_BC = 6,         /* boundary conditions on buffer particles          */
+    SPH_PHASE_ROTATE = 7,     /* rigid turn of a buffer's particles (and cover)   */
+    SPH_PHASE_CANDIDATES = 8, /* full scan: the filter's candidates, exact tests  */
+    SPH_PHASE_NEIGHBOR = 9,   /* neighbour counts over the cell list              */
+    SPH_NPHASE = 10
 } sph_phase;
 
 /* When on, every kernel launch of the context is bracketed by two HIP events on
@@ -310,7 +347,10 @@ sph_status sph_profile_read(sph_ctx *ctx, double ms[SPH_NPHASE], int64_t launche
  * block to a domain), either enqueued directly or replayed from a HIP graph
  * captured at the first step.  Member contexts keep their own results
  * (sph_last_result, sph_last_events) and must be fully set up first: a later
- * sph_buffer_define or sph_grid_fit on a member invalidates the batch. */
+ * sph_buffer_define, sph_grid_fit, sph_buffer_rotate or a change of the density
+ * field in sph_set_fields on a member invalidates the batch (its launch tables
+ * hold the member's cover cells, grid arrays and field roles): sph_batch_step
+ * then returns SPH_ERR_STATE and launches nothing. */
 typedef struct sph_batch sph_batch;
 typedef enum { SPH_BATCH_KERNELS = 0, SPH_BATCH_GRAPH = 1 } sph_batch_mode;
 
@@ -326,8 +366,14 @@ sph_status sph_batch_set_mode(sph_batch *b, int32_t mode);
 /* Particles per block of the count and scatter launches (256 .. 2^20; default
  * 2048).  Sync; drops a captured graph. */
 sph_status sph_batch_set_count_block(sph_batch *b, int32_t particles_per_block);
-/* Async: one step (build + local-cell update) of every domain. */
+/* Async: one step (build + local-cell update) of every domain.  SPH_ERR_STATE if
+ * a member was redefined since sph_batch_create (nothing is enqueued). */
 sph_status sph_batch_step(sph_batch *b);
+/* The step as a HIP graph: capture sets SPH_BATCH_GRAPH and records the step's
+ * five launches into a graph (sync; replaces an earlier graph); launch replays it
+ * on the batch stream (async; captures first if there is no graph). */
+sph_status sph_batch_graph_capture(sph_batch *b);
+sph_status sph_batch_graph_launch(sph_batch *b);
 /* Sync: out[d] = result of domain d's last update. */
 sph_status sph_batch_results(sph_batch *b, sph_result *out);
 /* Autotuner: times `trials` steps of each launch mode x particles-per-block
@@ -351,11 +397,13 @@ sph_status sph_rotation_from_direction(const double dir[3], double rot[9]);
 /* SPH_OK if rot (2x2 block in 2-D) is orthonormal with det +1 within 1e-9. */
 sph_status sph_check_rotation(int32_t dim, const double rot[9]);
 
-/* Cells of a dense grid (lo, cell_size, dims) whose boxes, dilated by 1e-2 of a
- * cell and with edge cells extended to infinity, intersect the check region of a
- * buffer (separating-axis test).  Written as runs along x: first cell (linear
- * index ix + dims[0] * (iy + dims[1] * iz)) and run length, at most cap runs.
- * SPH_ERR_ARG if more than cap runs are needed (*n_runs then holds the need). */
+/* Cells of a dense grid (lo, cell_size, dims) whose boxes, dilated by
+ * max(1e-2, 1.5 E) of a cell (E: the FP32 binning bound given at sph_create) and
+ * with edge cells extended to infinity, intersect the check region of a buffer
+ * (separating-axis test).  Written as runs along x: first cell (linear index
+ * ix + dims[0] * (iy + dims[1] * iz)) and run length, at most cap runs.
+ * SPH_ERR_ARG if more than cap runs are needed (*n_runs then holds the need) or
+ * if E reaches a quarter cell. */
 sph_status sph_grid_cover(int32_t dim, const double lo[3], double cell_size, const int32_t dims[3],
                           const double origin[3], const double rot[9], const double half[3], double margin,
                           int32_t *run_first, int32_t *run_len, int64_t cap, int64_t *n_runs);

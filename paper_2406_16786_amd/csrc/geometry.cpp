@@ -98,6 +98,8 @@ extern "C" sph_status sph_check_rotation(int32_t dim, const double rot[9]) {
 
 namespace sphbuf {
 
+const double kMaxBinningError = 0.25;
+
 // Oriented box: centre, axes (rows of rot), half-extents.
 struct Obb {
     int dim;
@@ -209,6 +211,23 @@ bool obb_obb_overlap(const Obb &a, const Obb &b) {
     return true;
 }
 
+// Bound, in cells, on how far the FP32 cell coordinate of a particle can lie from
+// the exact one.  The kernels bin a position x (an FP32 value) by
+// t = fl32(fl32(x - lo32) * ic) with lo32 = fl32(lo) and ic = fl32(1/cs), so
+//   t = [(x - lo) + (lo - lo32)] / cs * (1 + d1)(1 + d2)(1 + d3),  |di| <= u,
+// and |t - (x - lo)/cs| <= |lo - lo32|/cs + 3.0001 u |x - lo32|/cs.  Positions
+// beyond the grid are clamped into the edge cells, whose cover extends to
+// infinity, so |x - lo32|/cs <= dims + 1 + |lo - lo32|/cs is all that matters.
+double binning_error_cells(int dim, const double glo[3], double cs, const int32_t dims[3]) {
+    const double u = std::ldexp(1.0, -24);
+    double off = 0.0, span = 0.0;
+    for (int j = 0; j < dim; ++j) {
+        off = std::max(off, std::fabs(glo[j] - (double)(float)glo[j]) / cs);
+        span = std::max(span, (double)dims[j] + 1.0);
+    }
+    return off + 3.0001 * u * (span + off);
+}
+
 sph_status grid_cover(int dim, const double glo[3], double cs, const int32_t dims[3], const double origin[3],
                       const double rot[9], const double half[3], double margin, std::vector<int32_t> &first,
                       std::vector<int32_t> &len) {
@@ -217,7 +236,12 @@ sph_status grid_cover(int dim, const double glo[3], double cs, const int32_t dim
     const Obb b = check_box(dim, origin, rot, half, margin);
     double blo[3], bhi[3];
     obb_aabb(b, blo, bhi);
-    const double eps = 1e-2 * cs;  // covers the FP32 binning error of a position near a face
+    // Cell boxes are dilated by more than the FP32 binning error, so a particle of
+    // the check region binned into a cell puts that cell in the cover; grids whose
+    // error reaches a quarter cell are refused.
+    const double err = binning_error_cells(dim, glo, cs, dims);
+    if (!(err < kMaxBinningError)) return SPH_ERR_ARG;
+    const double eps = std::max(1e-2, 1.5 * err) * cs;
     int lo_i[3] = {0, 0, 0}, hi_i[3] = {0, 0, 0};
     for (int j = 0; j < dim; ++j) {
         double a = std::floor((blo[j] - eps - glo[j]) / cs) - 1.0;

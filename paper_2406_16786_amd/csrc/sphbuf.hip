@@ -83,8 +83,7 @@ constexpr int kSeg = 16;
 
 struct SegCtr {
     unsigned int n_gen, n_del, n_rel;
-    unsigned int n_cand;  // candidates the count pass appended to this segment's part of the list
-    unsigned int pad[28];
+    unsigned int pad[29];
 };
 
 // Device-resident counters and library state.
@@ -94,9 +93,7 @@ struct Ctl {
     unsigned int nonfinite_build;  // set by the count phase of a build that met a non-finite position
     unsigned int nonfinite_seen;   // the latest completed build's flag (moved there by its scan phase)
     unsigned int nonfinite_full;   // set by a full-scan classify; consumed by its finalize
-    unsigned int scan_fault;       // set if a look-back or grid-barrier wait ran past its spin limit
-    unsigned int bar_count;        // grid barrier of the fused build: arrivals
-    unsigned int bar_gen;          // grid barrier generation
+    unsigned int scan_fault;       // set if a look-back wait ran past its spin limit
     unsigned int fin_ticket;       // finalize blocks that have read the counters
     unsigned int bc_status;        // outcome of the last boundary-condition or rotation pass
     unsigned int cand_overflow;    // the full scan's candidate list overflowed (consumed by its finalize)
@@ -433,44 +430,6 @@ __device__ __forceinline__ void group_ranks(const int (&my_head)[J], const int (
     for (int j = 0; j < J; ++j) rank[j] = __shfl(old[j], my_head[j]) + (lane - my_head[j]);
 }
 
-// Cell keys and per-cell ranks of J particles per lane whose positions are already
-// in registers (slot j of lane l is the l-th particle of group j; the particles of
-// one group are consecutive): keys and run detection for every group first, then
-// all atomics, and only then are the returned bases read -- so the J atomic round
-// trips overlap instead of queueing.  Invalid slots take no part.  Wave-uniform call.
-template <int J>
-__device__ __forceinline__ void rank_groups(const Grid &g, int32_t *count, const float (&px)[J], const float (&py)[J],
-                                            const float (&pz)[J], const bool (&valid)[J], int lane,
-                                            uint32_t (&key)[J], int32_t (&rank)[J], bool &bad) {
-    int my_head[J], old[J];
-    group_keys<J>(g, px, py, pz, valid, key, bad);
-    group_runs_issue<J>(count, key, valid, lane, my_head, old);
-    group_ranks<J>(my_head, old, lane, rank);
-}
-
-// The same with the positions loaded here: particle of slot j is i0 + j * stride;
-// lanes past s1 take no part.  All loads are issued before any key is formed.
-template <int J>
-__device__ __forceinline__ void key_rank_batch(const Grid &g, const float *__restrict__ x,
-                                               const float *__restrict__ y, const float *__restrict__ z,
-                                               int32_t *count, int64_t i0, int64_t stride, int64_t s1, int lane,
-                                               uint32_t (&key)[J], int32_t (&rank)[J], bool &bad) {
-    float px[J], py[J], pz[J];
-    bool valid[J];
-#pragma unroll
-    for (int j = 0; j < J; ++j) {
-        const int64_t i = i0 + (int64_t)j * stride;
-        valid[j] = i < s1;
-        px[j] = py[j] = pz[j] = 0.0f;
-        if (valid[j]) {
-            px[j] = x[i];
-            py[j] = y[i];
-            if (g.dim == 3) pz[j] = z[i];
-        }
-    }
-    rank_groups<J>(g, count, px, py, pz, valid, lane, key, rank, bad);
-}
-
 // Element o of an array whose base is uniform, addressed by a 32-bit byte offset
 // (o * sizeof(T) < 2^32): the address is base + offset in one memory instruction,
 // no 64-bit address arithmetic per lane.
@@ -501,19 +460,14 @@ struct CountArgs {
     int64_t n_tiles;
     Ctl *ctl;
     unsigned int *nonfinite;        // flag to raise on a non-finite position
-    // candidate gather during the count (null cover: none): every particle whose
-    // cell is in buffer k's cover (bit k of cover[key]) is appended as (i << 4 | k)
-    // to the part of cand of its wave's segment (seg_cap entries each)
-    const uint16_t *cover;
-    unsigned long long *cand;
-    int64_t seg_cap;
 };
 
-// The classifying count pass of the merged step (cover set, cand null): every
-// particle whose cell is in buffer k's cover is tested against buffer k there and
-// its events emitted, so that the update only has to finalize them.  (Its own
+// The classifying count pass of the merged step: every particle whose cell is in
+// buffer k's cover (bit k of cover[key]) is tested against buffer k there and its
+// events emitted, so that the update only has to finalize them.  (Its own
 // argument block: the plain pass keeps a small one.)
 struct ClsArgs : CountArgs {
+    const uint16_t *cover;
     int nb;
     Parts p;
     const BufDev *bufs;
@@ -666,43 +620,6 @@ __device__ __forceinline__ void count_body(const A &a, const int lb, const int G
             }
         }
         group_ranks<J>(my_head, old, lane, rank);
-        if (!kCls && a.cand) {
-            uint32_t m[kCountBatch];
-            unsigned mine = 0;
-#pragma unroll
-            for (int j = 0; j < kCountBatch; ++j) {
-                m[j] = valid[j] ? a.cover[key[j]] : 0u;
-                mine += (unsigned)__popc(m[j]);
-            }
-            if (__ballot(mine != 0u) != 0ull) {  // wave-uniform
-                unsigned incl = mine;
-                for (int off = 1; off < kWave; off <<= 1) {
-                    const unsigned t = __shfl_up(incl, off);
-                    if (lane >= off) incl += t;
-                }
-                const unsigned tot = __shfl(incl, kWave - 1);
-                const int sg = (int)(((unsigned)lb * (unsigned)W + (unsigned)w) % (unsigned)kSeg);
-                unsigned base = 0u;
-                if (lane == 0) base = atomicAdd(&a.ctl->seg[sg].n_cand, tot);
-                base = __shfl(base, 0);
-                unsigned at = base + incl - mine;
-                unsigned long long *dst = a.cand + (int64_t)sg * a.seg_cap;
-#pragma unroll
-                for (int j = 0; j < kCountBatch; ++j) {
-                    const int64_t i = rb[j] + (int64_t)o;
-                    uint32_t mm = m[j];
-                    while (mm) {
-                        const int k = __ffs(mm) - 1;
-                        mm &= mm - 1u;
-                        if ((int64_t)at < a.seg_cap)
-                            dst[at] = ((unsigned long long)i << 4) | (unsigned long long)k;
-                        else
-                            a.ctl->cand_overflow = 1u;
-                        ++at;
-                    }
-                }
-            }
-        }
 #pragma unroll
         for (int j = 0; j < kCountBatch; ++j) {
             if (!valid[j]) continue;
@@ -964,253 +881,6 @@ __device__ __forceinline__ void scatter_body(const ScatterArgs &a, const int lb,
 
 __global__ __launch_bounds__(kBuildBlock) void k_scatter(ScatterArgs a) { scatter_body(a, logical_block(), gridDim.x); }
 
-// ---------------------------------------------------- K0 fused (one launch) --
-//
-// Count, scan and scatter in one cooperative launch with three grid barriers
-// (after the counts, after the scan's block sums, after the cell starts).  Each
-// block owns one contiguous particle segment; for up to kFusedSlots particles per
-// thread the cell key stays in LDS and the rank in registers from the count phase
-// to the scatter phase, so the only per-particle HBM traffic is the position read
-// and the cell_idx write.  Particles beyond those slots (very large N) go through
-// a 64-bit (key, rank) spill buffer.
-
-constexpr int kFusedBlock = 1024;
-constexpr int kFusedSlots = 32;
-constexpr int kFusedGroup = 8;
-
-struct FusedArgs {
-    const float *x, *y, *z;
-    const int64_t *n_dev;
-    int64_t capacity;
-    Grid g;
-    int32_t *count;
-    int32_t *cell_start;
-    int32_t *cell_idx;
-    unsigned long long *keyrank;
-    int32_t *block_sum;
-    int64_t m;  // cells + 1
-    Ctl *ctl;
-    int vec;    // positions 16-byte aligned: vector loads allowed
-};
-
-// Grid-wide barrier for a cooperative launch (all blocks resident).  Every wave
-// first waits for its own memory operations to complete; one thread per block
-// then releases at agent scope, arrives on a counter and (after the last
-// arrival opens the next generation) acquires at agent scope, which also
-// invalidates the CU's and XCD's caches for the other waves of the block.  A
-// wait that runs past its spin limit flags a fault and returns false so the
-// kernel can stop before using data it cannot trust.
-__device__ bool grid_barrier(Ctl *c, unsigned nblocks) {
-    __shared__ int s_ok;
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int ok = 1;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        const unsigned gen = __hip_atomic_load(&c->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned arrived = __hip_atomic_fetch_add(&c->bar_count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (arrived == nblocks - 1) {
-            __hip_atomic_store(&c->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&c->bar_gen, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            unsigned spins = 0;
-            while (__hip_atomic_load(&c->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-                __builtin_amdgcn_s_sleep(1);
-                if (++spins > (1u << 24)) {
-                    atomicOr(&c->scan_fault, 1u);
-                    ok = 0;
-                    break;
-                }
-            }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        s_ok = ok;
-    }
-    __syncthreads();
-    return s_ok != 0;
-}
-
-__device__ __forceinline__ int block_sum_1024(int v, int *s_red) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    const int wave = threadIdx.x / kWave;
-    __syncthreads();
-    if ((threadIdx.x & (kWave - 1)) == 0) s_red[wave] = v;
-    __syncthreads();
-    int t = 0;
-    for (int w = 0; w < kFusedBlock / kWave; ++w) t += s_red[w];
-    return t;
-}
-
-// Inclusive block scan of one value per thread; also returns the block total.
-__device__ __forceinline__ int block_scan_1024(int v, int *s_red, int &total) {
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    int incl = v;
-    for (int off = 1; off < kWave; off <<= 1) {
-        const int t = __shfl_up(incl, off);
-        if (lane >= off) incl += t;
-    }
-    __syncthreads();
-    if (lane == kWave - 1) s_red[wave] = incl;
-    __syncthreads();
-    int before = 0;
-    total = 0;
-    for (int w = 0; w < kFusedBlock / kWave; ++w) {
-        const int s = s_red[w];
-        if (w < wave) before += s;
-        total += s;
-    }
-    return before + incl;
-}
-
-// Ranks of J wave-rows of keys already known (lanes with valid[j] false take no
-// part): run detection, then all J atomics, then the bases.  Wave-uniform call.
-template <int J>
-__device__ __forceinline__ void rank_batch(int32_t *count, const uint32_t (&key)[J], const bool (&valid)[J],
-                                           int lane, int32_t (&rank)[J]) {
-    int my_head[J], len[J];
-#pragma unroll
-    for (int j = 0; j < J; ++j) {
-        const uint32_t prev = __shfl_up(key[j], 1);
-        const bool head = !valid[j] || lane == 0 || key[j] != prev;
-        const unsigned long long heads = __ballot(head);
-        const unsigned long long le = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
-        my_head[j] = 63 - __clzll((long long)(heads & le));
-        const unsigned long long gt = heads & ~le;
-        len[j] = valid[j] ? (gt ? __ffsll((long long)gt) - 1 : 64) - my_head[j] : 0;
-    }
-    int old[J];
-#pragma unroll
-    for (int j = 0; j < J; ++j) {
-        old[j] = len[j];  // any value already in the register: no copy that would wait on the atomic before
-        if (len[j] > 0 && lane == my_head[j]) old[j] = atomicAdd(&count[key[j]], len[j]);
-    }
-#pragma unroll
-    for (int j = 0; j < J; ++j) rank[j] = __shfl(old[j], my_head[j]) + (lane - my_head[j]);
-}
-
-__global__ __launch_bounds__(kFusedBlock) void k_build_fused(FusedArgs a) {
-    __shared__ int s_red[kFusedBlock / kWave];
-    __shared__ uint32_t s_key[kFusedSlots * kFusedBlock];
-    const int64_t N = live_count(a.n_dev, a.capacity);
-    const unsigned G = gridDim.x;
-    const int lb = logical_block();
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wave = threadIdx.x / kWave;
-    constexpr int kVec = 4;                              // particles per 16-byte load
-    constexpr int64_t kQuant = (int64_t)kFusedBlock * kVec;
-    const int64_t per = ((N + G - 1) / G + kQuant - 1) / kQuant * kQuant;  // keeps segments 16-byte aligned
-    const int64_t s0 = (int64_t)lb * per;
-    const int64_t s1 = min(N, s0 + per);
-    const int64_t nreg = max((int64_t)0, min(s1 - s0, (int64_t)kFusedSlots * kFusedBlock));
-    int32_t rank[kFusedSlots];
-    bool bad = false;
-    // ---- count, part 1: cell keys of the on-chip part of the segment into LDS,
-    //      four consecutive particles per thread per 16-byte load ----
-#pragma unroll 2
-    for (int q = 0; q < kFusedSlots / kVec; ++q) {
-        const int64_t lp = (int64_t)kVec * (threadIdx.x + (int64_t)kFusedBlock * q);
-        if ((int64_t)kVec * kFusedBlock * q >= nreg) break;   // block-uniform
-        float px[kVec], py[kVec], pz[kVec];
-        if (a.vec && lp + kVec <= nreg) {
-            const float4 vx = *reinterpret_cast<const float4 *>(a.x + s0 + lp);
-            const float4 vy = *reinterpret_cast<const float4 *>(a.y + s0 + lp);
-            px[0] = vx.x; px[1] = vx.y; px[2] = vx.z; px[3] = vx.w;
-            py[0] = vy.x; py[1] = vy.y; py[2] = vy.z; py[3] = vy.w;
-            if (a.g.dim == 3) {
-                const float4 vz = *reinterpret_cast<const float4 *>(a.z + s0 + lp);
-                pz[0] = vz.x; pz[1] = vz.y; pz[2] = vz.z; pz[3] = vz.w;
-            } else {
-                pz[0] = pz[1] = pz[2] = pz[3] = 0.0f;
-            }
-        } else {
-#pragma unroll
-            for (int c = 0; c < kVec; ++c) {
-                const bool ok = lp + c < nreg;
-                px[c] = ok ? a.x[s0 + lp + c] : 0.0f;
-                py[c] = ok ? a.y[s0 + lp + c] : 0.0f;
-                pz[c] = ok && a.g.dim == 3 ? a.z[s0 + lp + c] : 0.0f;
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < kVec; ++c) {
-            if (lp + c < nreg) {
-                bad |= !(isfinite(px[c]) && isfinite(py[c]) && isfinite(pz[c]));
-                s_key[lp + c] = cell_key(a.g, px[c], py[c], pz[c]);
-            }
-        }
-    }
-    __syncthreads();
-    // ---- count, part 2: ranks, one wave-row of 64 consecutive keys at a time ----
-#pragma unroll
-    for (int r0 = 0; r0 < kFusedSlots; r0 += kFusedGroup) {
-        if ((int64_t)kWave * (kFusedBlock / kWave) * r0 >= nreg) break;  // block-uniform
-        uint32_t k[kFusedGroup];
-        bool v[kFusedGroup];
-        int32_t r[kFusedGroup];
-#pragma unroll
-        for (int j = 0; j < kFusedGroup; ++j) {
-            const int64_t p = (int64_t)kWave * (wave + (kFusedBlock / kWave) * (r0 + j)) + lane;
-            v[j] = p < nreg;
-            k[j] = v[j] ? s_key[p] : 0xffffffffu;
-        }
-        rank_batch<kFusedGroup>(a.count, k, v, lane, r);
-#pragma unroll
-        for (int j = 0; j < kFusedGroup; ++j) rank[r0 + j] = r[j];
-    }
-    // ---- count, rest of the segment (very large N): through the keyrank buffer ----
-    for (int64_t base = s0 + nreg; base < s1; base += kFusedBlock * kFusedGroup) {
-        uint32_t k[kFusedGroup];
-        int32_t r[kFusedGroup];
-        key_rank_batch<kFusedGroup>(a.g, a.x, a.y, a.z, a.count, base + threadIdx.x, kFusedBlock, s1, lane, k, r,
-                                    bad);
-#pragma unroll
-        for (int j = 0; j < kFusedGroup; ++j) {
-            const int64_t i = base + threadIdx.x + (int64_t)j * kFusedBlock;
-            if (i < s1) a.keyrank[i] = ((unsigned long long)k[j] << 32) | (unsigned)r[j];
-        }
-    }
-    if (__ballot(bad) != 0ull && lane == 0) atomicOr(&a.ctl->nonfinite_build, 1u);
-    if (!grid_barrier(a.ctl, G)) return;
-    if (lb == 0 && threadIdx.x == 0) {  // this build's verdict for the next update
-        a.ctl->nonfinite_seen = a.ctl->nonfinite_build;
-        a.ctl->nonfinite_build = 0u;
-    }
-    // ---- scan: block sums of contiguous cell chunks, then the chunk scan ----
-    const int64_t chunk = (a.m + G - 1) / G;
-    const int64_t c0 = (int64_t)lb * chunk;
-    const int64_t c1 = min(a.m, c0 + chunk);
-    int part = 0;
-    for (int64_t c = c0 + threadIdx.x; c < c1; c += kFusedBlock) part += a.count[c];
-    part = block_sum_1024(part, s_red);
-    if (threadIdx.x == 0) a.block_sum[lb] = part;
-    if (!grid_barrier(a.ctl, G)) return;
-    int pre = 0;
-    for (int b = threadIdx.x; b < lb; b += kFusedBlock) pre += a.block_sum[b];
-    int running = block_sum_1024(pre, s_red);
-    for (int64_t t0 = c0; t0 < c1; t0 += kFusedBlock) {
-        const int64_t c = t0 + threadIdx.x;
-        const int v = c < c1 ? a.count[c] : 0;
-        int total;
-        const int incl = block_scan_1024(v, s_red, total);
-        if (c < c1) {
-            a.cell_start[c] = running + incl - v;
-            a.count[c] = 0;
-        }
-        running += total;
-    }
-    if (!grid_barrier(a.ctl, G)) return;
-    // ---- scatter: keys from LDS, ranks from registers (and the spill buffer) ----
-#pragma unroll
-    for (int r = 0; r < kFusedSlots; ++r) {
-        const int64_t p = (int64_t)kWave * (wave + (kFusedBlock / kWave) * r) + lane;
-        if (p < nreg) a.cell_idx[a.cell_start[s_key[p]] + rank[r]] = (int32_t)(s0 + p);
-    }
-    for (int64_t i = s0 + nreg + threadIdx.x; i < s1; i += kFusedBlock) {
-        const unsigned long long kr = a.keyrank[i];
-        a.cell_idx[a.cell_start[(uint32_t)(kr >> 32)] + (int)(unsigned)(kr & 0xffffffffull)] = (int32_t)i;
-    }
-}
-
 // Occupied bricks of the sparse grid (setup: sph_grid_fit).
 __global__ __launch_bounds__(kBuildBlock) void k_mark_bricks(const float *x, const float *y, const float *z,
                                                              const int64_t *n_dev, int64_t capacity, Grid g,
@@ -1318,7 +988,6 @@ struct FullArgs {
     unsigned long long *cand;  // (index << 4) | buffer
     int64_t cap_cand;
     int vec;                   // positions 16-byte aligned: vector loads allowed
-    int64_t seg_cap;           // > 0: the list is kSeg parts of seg_cap entries filled by the count pass
 };
 
 // FP32 check-region test widened by the guard band: true for every member of C_k.
@@ -1427,17 +1096,6 @@ __global__ __launch_bounds__(kClassifyBlock) void k_filter_full(FullArgs a) {
     if (__ballot(bad) != 0ull && lane == 0) atomicOr(&a.e.ctl->nonfinite_full, 1u);
 }
 
-// Clears what a count pass with candidate gathering left for an update that never
-// came (before the next such pass or a full scan reuses the list).
-__global__ void k_reset_cand(Ctl *ctl) {
-    if (threadIdx.x < kSeg) ctl->seg[threadIdx.x].n_cand = 0u;
-    if (threadIdx.x == 0) {
-        ctl->cand_count = 0ull;
-        ctl->cand_overflow = 0u;
-        ctl->nonfinite_full = 0u;
-    }
-}
-
 // Clears the events and label counts a classifying count pass emitted for an update
 // that will not finalize them (the state changed since, or a new build or a full
 // scan replaces them).  clear_nf: also its non-finite flag.
@@ -1458,35 +1116,14 @@ __global__ __launch_bounds__(kClassifyBlock) void k_classify_cand(FullArgs a) {
         reinterpret_cast<uint32_t *>(sb)[t] = reinterpret_cast<const uint32_t *>(a.bufs)[t];
     block_counts_init(s_cnt);
     __syncthreads();
-    // list length; a segmented list is read as its kSeg parts one after the other
-    __shared__ int64_t s_pre[kSeg + 1];
-    if (threadIdx.x == 0) {
-        int64_t tot = 0;
-        if (a.seg_cap > 0) {
-            for (int q = 0; q < kSeg; ++q) {
-                s_pre[q] = tot;
-                tot += min((int64_t)a.e.ctl->seg[q].n_cand, a.seg_cap);
-            }
-        } else {
-            const unsigned long long cc = a.e.ctl->cand_count;
-            tot = cc < (unsigned long long)a.cap_cand ? (int64_t)cc : a.cap_cand;
-        }
-        s_pre[kSeg] = tot;
-    }
-    __syncthreads();
-    const int64_t n_cand = s_pre[kSeg];
+    const unsigned long long cc = a.e.ctl->cand_count;
+    const int64_t n_cand = cc < (unsigned long long)a.cap_cand ? (int64_t)cc : a.cap_cand;
     const int dim = a.p.dim;
     const int seg = (int)((blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave) % kSeg);
     for (int64_t t0 = (int64_t)blockIdx.x * blockDim.x; t0 < n_cand; t0 += (int64_t)gridDim.x * blockDim.x) {
         const int64_t t = t0 + threadIdx.x;
         const bool valid = t < n_cand;
-        int64_t at = t;
-        if (valid && a.seg_cap > 0) {
-            int q = 0;
-            while (q + 1 < kSeg && s_pre[q + 1] <= t) ++q;
-            at = (int64_t)q * a.seg_cap + (t - s_pre[q]);
-        }
-        const unsigned long long ent = valid ? a.cand[at] : 0ull;
+        const unsigned long long ent = valid ? a.cand[t] : 0ull;
         const int64_t i = (int64_t)(ent >> 4);
         const int k = valid ? (int)(ent & 15ull) : 0;
         const BufDev &b = sb[k];
@@ -2132,7 +1769,6 @@ __device__ __forceinline__ void finalize_body(const FinArgs &a, const int fb, co
             sc.n_gen = 0u;
             sc.n_del = 0u;
             sc.n_rel = 0u;
-            sc.n_cand = 0u;
         }
         if (tid == 2 * kWave) {
             r->status = st;
@@ -2569,9 +2205,11 @@ struct sph_ctx {
     int device = 0;
     int build_blocks = 0;
     int full_blocks = 0;
-    int fused_blocks = 0;        // grid of the one-launch build (0: three-kernel build)
     bool built = false;          // a build is pending for the next local update
     int64_t built_capacity = 0;
+    // bumped whenever what a batch bakes into its launch tables changes (cover runs,
+    // grid arrays, field roles): a batch made before refuses to step
+    uint64_t layout_gen = 0;
 
     int nb = 0;
     BufDev hb[SPH_MAX_BUFFERS];
@@ -2586,18 +2224,11 @@ struct sph_ctx {
     int n_runs = 0;
 
     int32_t *d_count = nullptr, *d_cell_start = nullptr, *d_cell_idx = nullptr;
-    unsigned long long *d_cand = nullptr;        // candidate list of the full scan / of the count pass
-    // overlapped step (opt-in): the count pass gathers the cover cells' particles, the
-    // update runs on them while the scan and scatter finish on a side stream
-    bool overlap = false;
-    hipStream_t side = nullptr;
-    hipEvent_t ev_count = nullptr, ev_built = nullptr;
-    bool pending_join = false;   // the side stream's build work is not yet ordered before ctx->stream
-    bool cand_pending = false;   // the count pass left candidates no update has consumed
-    // merged step (opt-in): the count pass also classifies the cover cells' particles
-    // and emits their events; the update runs the finalize beside the scan, then the
-    // scatter
-    bool merged = false;
+    unsigned long long *d_cand = nullptr;        // candidate list of the full scan
+    // merged step (the default update path): the count pass also classifies the cover
+    // cells' particles and emits their events; the update runs the finalize beside
+    // the scan, then the scatter.  Off: the update walks the cover cells.
+    bool merged = true;
     bool scan_pending = false;   // a merged build's scan and scatter are not enqueued yet
     bool ev_pending = false;     // a merged build's events are not finalized yet
     bool nf_full_next = false;   // the next cover-walk finalize reads the count pass's non-finite flag
@@ -2617,7 +2248,6 @@ struct sph_ctx {
     unsigned *d_bcfound = nullptr;    // per-buffer counts of a boundary-condition / rotation pass
     unsigned *h_bc_status = nullptr;  // pinned
     sph_fields fields = {{-1, -1, -1}, -1};
-    int32_t *d_block_sum = nullptr;
     sph_result *d_result = nullptr;
     sph_result *h_result = nullptr;  // pinned
     bool any_update = false;
@@ -2662,25 +2292,6 @@ struct ProfScope {
         if (on) (void)hipEventRecord(c->prof_ev[2 * slot + 1], s);
     }
 };
-
-// Orders the side stream's build work (scan, scatter of an overlapped build) before
-// whatever is enqueued next on the context's stream.  Stream-ordered, no host wait.
-sph_status join_side(sph_ctx *c) {
-    if (!c->pending_join) return SPH_OK;
-    HIP_TRY(hipStreamWaitEvent(c->stream, c->ev_built, 0));
-    c->pending_join = false;
-    return SPH_OK;
-}
-
-// Before a count pass or a full scan fills the candidate list: clear what an
-// overlapped build left for an update that never came.
-sph_status drop_candidates(sph_ctx *c) {
-    if (!c->cand_pending) return SPH_OK;
-    hipLaunchKernelGGL(k_reset_cand, dim3(1), dim3(kWave), 0, c->stream, c->d_ctl);
-    HIP_TRY(hipGetLastError());
-    c->cand_pending = false;
-    return SPH_OK;
-}
 
 void prof_drain(sph_ctx *c) {
     for (size_t s = 0; s < c->prof_used; ++s) {
@@ -2899,10 +2510,6 @@ void free_ctx(sph_ctx *c) {
     (void)hipFree(c->d_keyrank);
     (void)hipFree(c->d_keys);
     (void)hipFree(c->d_cand);
-    if (c->side) (void)hipStreamSynchronize(c->side);
-    if (c->ev_count) (void)hipEventDestroy(c->ev_count);
-    if (c->ev_built) (void)hipEventDestroy(c->ev_built);
-    if (c->side) (void)hipStreamDestroy(c->side);
     (void)hipFree(c->d_cover);
     (void)hipFree(c->d_tile_state);
     (void)hipFree(c->d_gen_idx);
@@ -2916,7 +2523,6 @@ void free_ctx(sph_ctx *c) {
     (void)hipFree(c->d_part);
     (void)hipFree(c->d_bcfound);
     if (c->h_bc_status) (void)hipHostFree(c->h_bc_status);
-    (void)hipFree(c->d_block_sum);
     (void)hipFree(c->d_result);
     if (c->h_result) (void)hipHostFree(c->h_result);
     for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
@@ -3046,10 +2652,9 @@ static sph_status upload_runs(sph_ctx *ctx, std::vector<int32_t> &rf, std::vecto
             hipMemcpyAsync(nbuf, rb.data(), nr, hipMemcpyHostToDevice, ctx->stream) != hipSuccess)
             return SPH_ERR_HIP;
     }
-    // per-cell cover mask for the candidate gathering of the overlapped step and the
-    // classification of the merged step
+    // per-cell cover mask for the classification of the merged step
     std::vector<uint16_t> mask;
-    if (ctx->overlap || ctx->merged) {
+    if (ctx->merged) {
         if (ctx->cover_cells != ctx->n_cells) {
             HIP_TRY(hipStreamSynchronize(ctx->stream));
             (void)hipFree(ctx->d_cover);
@@ -3069,6 +2674,7 @@ static sph_status upload_runs(sph_ctx *ctx, std::vector<int32_t> &rf, std::vecto
     }
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     ctx->built = false;  // covers changed: the next update needs a build with them
+    ctx->layout_gen++;
     (void)hipFree(ctx->d_run_first);
     (void)hipFree(ctx->d_run_len);
     (void)hipFree(ctx->d_run_buf);
@@ -3113,6 +2719,13 @@ extern "C" sph_status sph_create(const sph_config *cfg, sph_ctx **out) {
     } else if (cells >= 2147483000.0) {
         return SPH_ERR_ARG;
     }
+    if (cfg->update_path != SPH_UPDATE_MERGED && cfg->update_path != SPH_UPDATE_CELLS) return SPH_ERR_ARG;
+    {   // FP32 binning must place every particle within a quarter cell of its cell
+        double glo[3] = {0.0, 0.0, 0.0};
+        for (int c = 0; c < cfg->dim; ++c) glo[c] = cfg->lo[c];
+        if (!(sphbuf::binning_error_cells(cfg->dim, glo, cfg->cell_size, dims) < sphbuf::kMaxBinningError))
+            return SPH_ERR_ARG;
+    }
 
     sph_ctx *c = new (std::nothrow) sph_ctx();
     if (!c) return SPH_ERR_HIP;
@@ -3133,6 +2746,7 @@ extern "C" sph_status sph_create(const sph_config *cfg, sph_ctx **out) {
     c->capacity = cfg->capacity;
     c->max_events = (unsigned)cfg->max_events;
     c->stream = (hipStream_t)cfg->stream;
+    c->merged = cfg->update_path == SPH_UPDATE_MERGED;
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
         return SPH_ERR_HIP;
@@ -3162,7 +2776,6 @@ extern "C" sph_status sph_create(const sph_config *cfg, sph_ctx **out) {
               hipMalloc(&c->d_ctl, sizeof(Ctl)) == hipSuccess &&
               (blog2 == 0 || hipMalloc(&c->d_brick_slot, sizeof(int32_t) * c->n_bricks) == hipSuccess) &&
               hipMalloc(&c->d_part, sizeof(unsigned) * 2 * SPH_MAX_BUFFERS * kMaxPartBlocks) == hipSuccess &&
-              hipMalloc(&c->d_block_sum, sizeof(int32_t) * kMaxPartBlocks) == hipSuccess &&
               hipMalloc(&c->d_result, sizeof(sph_result)) == hipSuccess &&
               hipMalloc(&c->d_bcfound, sizeof(unsigned) * kCountReplicas * SPH_MAX_BUFFERS) == hipSuccess &&
               hipHostMalloc(&c->h_bc_status, sizeof(unsigned), hipHostMallocDefault) == hipSuccess &&
@@ -3188,54 +2801,12 @@ extern "C" sph_status sph_create(const sph_config *cfg, sph_ctx **out) {
         free_ctx(c);
         return SPH_ERR_HIP;
     }
-    // one-launch build: every block must be resident at once (cooperative launch)
-    {
-        int coop = 0, cus = 0, per_cu = 0;
-        if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, c->device) == hipSuccess && coop &&
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess &&
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(k_build_fused),
-                                                         kFusedBlock, 0) == hipSuccess &&
-            per_cu > 0) {
-            int g = cus * per_cu;
-            g = std::min(g, kMaxPartBlocks) / 8 * 8;
-            c->fused_blocks = g >= 8 ? g : 0;
-        }
-        // The three-kernel build is the default: in the one-launch build each of the
-        // three grid barriers costs about as much as a kernel boundary.  Opt in with
-        // SPHBUF_BUILD=fused.
-        const char *env = std::getenv("SPHBUF_BUILD");
-        if (!env || std::strcmp(env, "fused") != 0) c->fused_blocks = 0;
-    }
-    // The update walks the cover cells of the finished cell list.  SPHBUF_UPDATE=overlap
-    // selects the overlapped step instead: the count pass gathers the particles of the
-    // cover cells and the update runs on them while the scan and the scatter finish on
-    // a side stream (not with the one-launch build).  On the 3-D pipe it is about 1 %
-    // faster: the finalize and the scatter slow each other down when they share the GPU.
-    // SPHBUF_UPDATE=merged selects the merged step: the count pass classifies the
-    // particles of the cover cells as it bins them and emits their events, and the
-    // update runs the finalize beside the scan tiles in one launch, then the scatter
-    // (not with the one-launch build).  The events and duplicate payloads are those
-    // of the state the build saw; the library's own calls that change that state
-    // (boundary conditions, turns, identification, fields, buffer definitions) drop
-    // them, and the update then walks the cover cells.
-    {
-        const char *upd = std::getenv("SPHBUF_UPDATE");
-        c->overlap = c->fused_blocks == 0 && upd && std::strcmp(upd, "overlap") == 0;
-        c->merged = c->fused_blocks == 0 && upd && std::strcmp(upd, "merged") == 0;
-        if (c->overlap && (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
-                           hipEventCreateWithFlags(&c->ev_count, hipEventDisableTiming) != hipSuccess ||
-                           hipEventCreateWithFlags(&c->ev_built, hipEventDisableTiming) != hipSuccess)) {
-            free_ctx(c);
-            return SPH_ERR_HIP;
-        }
-    }
     *out = c;
     return SPH_OK;
 }
 
 extern "C" sph_status sph_destroy(sph_ctx *ctx) {
     if (!ctx) return SPH_ERR_ARG;
-    (void)join_side(ctx);
     (void)hipStreamSynchronize(ctx->stream);
     free_ctx(ctx);
     return SPH_OK;
@@ -3244,7 +2815,6 @@ extern "C" sph_status sph_destroy(sph_ctx *ctx) {
 extern "C" sph_status sph_buffer_define(sph_ctx *ctx, sph_kind kind, const double origin[3], const double rot[9],
                                         const double half[3], double margin, int32_t *buffer_id) {
     if (!ctx || !origin || !rot || !half) return SPH_ERR_ARG;
-    HIP_CHECKED(join_side(ctx));
     HIP_CHECKED(merged_drop(ctx, true));
     if (kind != SPH_INLET && kind != SPH_OUTLET && kind != SPH_BIDIR) return SPH_ERR_ARG;
     const int dim = ctx->dim;
@@ -3302,8 +2872,6 @@ extern "C" sph_status sph_celllist_build(sph_ctx *ctx, const sph_particles *p) {
     Parts pp;
     const sph_status st = parts_of(ctx, p, pp);
     if (st != SPH_OK) return st;
-    HIP_CHECKED(join_side(ctx));  // the previous build's scan must have cleared the counts
-    HIP_CHECKED(drop_candidates(ctx));
     HIP_CHECKED(merged_drop(ctx, true));
     ctx->built_capacity = pp.capacity;
     // merged step: a workgroup's list holds at most kClsList particles (capacities
@@ -3328,69 +2896,6 @@ extern "C" sph_status sph_celllist_build(sph_ctx *ctx, const sph_particles *p) {
         ctx->scan_pending = true;
         ctx->ev_pending = true;
         ctx->nf_full_next = true;
-        ctx->built = true;
-        return SPH_OK;
-    }
-    if (ctx->fused_blocks > 0) {
-        FusedArgs fa{};
-        fa.x = pp.pos[0];
-        fa.y = pp.pos[1];
-        fa.z = pp.pos[2];
-        fa.n_dev = pp.n_dev;
-        fa.capacity = pp.capacity;
-        fa.g = grid_of(ctx);
-        fa.count = ctx->d_count;
-        fa.cell_start = ctx->d_cell_start;
-        fa.cell_idx = ctx->d_cell_idx;
-        fa.keyrank = ctx->d_keyrank;
-        fa.block_sum = ctx->d_block_sum;
-        fa.m = ctx->n_cells + 1;
-        fa.ctl = ctx->d_ctl;
-        fa.vec = aligned16(fa.x) && aligned16(fa.y) && aligned16(fa.z) ? 1 : 0;
-        void *args[] = {&fa};
-        hipError_t e;
-        {
-            ProfScope ps(ctx, SPH_PHASE_BUILD);
-            e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_build_fused), dim3(ctx->fused_blocks),
-                                           dim3(kFusedBlock), args, 0, ctx->stream);
-        }
-        if (e == hipSuccess) {
-            ctx->built = true;
-            return SPH_OK;
-        }
-        (void)hipGetLastError();
-        ctx->fused_blocks = 0;  // not available here: fall back to the three-kernel build
-    }
-    if (ctx->overlap) {
-        // count (+ the cover cells' candidates) here; scan and scatter on the side
-        // stream, joined by the update (or by the next call that needs the cell list)
-        CountArgs ca = count_args(ctx, pp);
-        ca.nonfinite = &ctx->d_ctl->nonfinite_full;
-        ca.cover = ctx->d_cover;
-        ca.cand = ctx->d_cand;
-        ca.seg_cap = (ctx->capacity + kCandSlack) / kSeg;
-        {
-            ProfScope ps(ctx, SPH_PHASE_COUNT);
-            hipLaunchKernelGGL(k_count, dim3(count_blocks(pp.capacity)), dim3(kBuildBlock), 0, ctx->stream, ca);
-        }
-        HIP_TRY(hipGetLastError());
-        HIP_TRY(hipEventRecord(ctx->ev_count, ctx->stream));
-        HIP_TRY(hipStreamWaitEvent(ctx->side, ctx->ev_count, 0));
-        const ScanArgs sa = scan_args(ctx);
-        {
-            ProfScope ps(ctx, SPH_PHASE_SCAN, ctx->side);
-            hipLaunchKernelGGL(k_scan, dim3((unsigned)ctx->n_tiles), dim3(kScanBlock), 0, ctx->side, sa);
-        }
-        HIP_TRY(hipGetLastError());
-        const ScatterArgs xa = scatter_args(ctx, pp.capacity);
-        {
-            ProfScope ps(ctx, SPH_PHASE_SCATTER, ctx->side);
-            hipLaunchKernelGGL(k_scatter, dim3(ctx->build_blocks), dim3(kBuildBlock), 0, ctx->side, xa);
-        }
-        HIP_TRY(hipGetLastError());
-        HIP_TRY(hipEventRecord(ctx->ev_built, ctx->side));
-        ctx->pending_join = true;
-        ctx->cand_pending = true;
         ctx->built = true;
         return SPH_OK;
     }
@@ -3459,29 +2964,6 @@ extern "C" sph_status sph_buffer_update_async(sph_ctx *ctx, sph_particles *p) {
         return SPH_OK;
     }
     HIP_CHECKED(merged_cells(ctx));  // a merged build whose events were dropped: walk the cover cells
-    if (ctx->overlap) {
-        // the count pass's candidates: exact tests and emission, then the finalize, while
-        // the scan and scatter may still run on the side stream (they touch neither the
-        // particle arrays nor the event state); then join them
-        FullArgs fa{};
-        fa.p = pp;
-        fa.bufs = ctx->d_bufs;
-        fa.nb = ctx->nb;
-        fa.e = events_of(ctx);
-        fa.cand = ctx->d_cand;
-        fa.cap_cand = ctx->capacity + kCandSlack;
-        fa.seg_cap = (ctx->capacity + kCandSlack) / kSeg;
-        {
-            ProfScope ps(ctx, SPH_PHASE_CLASSIFY);
-            hipLaunchKernelGGL(k_classify_cand, dim3(kCandBlocks), dim3(kClassifyBlock), 0, ctx->stream, fa);
-        }
-        HIP_TRY(hipGetLastError());
-        ctx->built = false;
-        ctx->cand_pending = false;
-        const sph_status fs = launch_finalize(ctx, pp, false, ctx->full_blocks);
-        if (fs != SPH_OK) return fs;
-        return join_side(ctx);
-    }
     int n_part = 0;
     if (ctx->n_runs > 0) {
         const LocalArgs la = local_args(ctx, pp);
@@ -3497,9 +2979,7 @@ extern "C" sph_status sph_buffer_update_async(sph_ctx *ctx, sph_particles *p) {
 
 static sph_status fullscan_enqueue(sph_ctx *ctx, sph_particles *p) {
     if (!ctx) return SPH_ERR_ARG;
-    HIP_CHECKED(join_side(ctx));
     HIP_CHECKED(merged_drop(ctx, true));
-    HIP_CHECKED(drop_candidates(ctx));
     Parts pp;
     const sph_status st = parts_of(ctx, p, pp);
     if (st != SPH_OK) return st;
@@ -3553,7 +3033,6 @@ extern "C" sph_status sph_buffer_update_fullscan(sph_ctx *ctx, sph_particles *p,
 
 extern "C" sph_status sph_last_result(sph_ctx *ctx, sph_result *out) {
     if (!ctx || !out) return SPH_ERR_ARG;
-    HIP_CHECKED(join_side(ctx));
     const sph_status w = wait_result(ctx);
     if (w != SPH_OK) return w;
     *out = *ctx->h_result;
@@ -3563,7 +3042,6 @@ extern "C" sph_status sph_last_result(sph_ctx *ctx, sph_result *out) {
 extern "C" sph_status sph_last_events(sph_ctx *ctx, int64_t *gen_src, int64_t *del_idx, int64_t cap, int64_t *n_gen,
                                       int64_t *n_del) {
     if (!ctx || !n_gen || !n_del || cap < 0) return SPH_ERR_ARG;
-    HIP_CHECKED(join_side(ctx));
     const sph_status w = wait_result(ctx);
     if (w != SPH_OK) return w;
     const sph_result r = *ctx->h_result;
@@ -3587,7 +3065,6 @@ extern "C" sph_status sph_last_events(sph_ctx *ctx, int64_t *gen_src, int64_t *d
 extern "C" sph_status sph_celllist_view(sph_ctx *ctx, const int32_t **cell_start, const int32_t **cell_idx,
                                         int64_t *n_cells, int32_t dims[3]) {
     if (!ctx) return SPH_ERR_ARG;
-    HIP_CHECKED(join_side(ctx));
     HIP_CHECKED(merged_cells(ctx));
     if (cell_start) *cell_start = ctx->d_cell_start;
     if (cell_idx) *cell_idx = ctx->d_cell_idx;
@@ -3599,7 +3076,6 @@ extern "C" sph_status sph_celllist_view(sph_ctx *ctx, const int32_t **cell_start
 
 extern "C" sph_status sph_neighbor_count(sph_ctx *ctx, const sph_particles *p, double radius, int32_t *counts) {
     if (!ctx || !counts) return SPH_ERR_ARG;
-    HIP_CHECKED(join_side(ctx));
     HIP_CHECKED(merged_cells(ctx));
     Parts pp;
     const sph_status st = parts_of(ctx, p, pp);
@@ -3648,6 +3124,7 @@ extern "C" sph_status sph_set_fields(sph_ctx *ctx, const sph_fields *fields) {
         if (fields->vel[c] < -1 || fields->vel[c] >= SPH_MAX_CARRIED) return SPH_ERR_ARG;
     if (fields->rho < -1 || fields->rho >= SPH_MAX_CARRIED) return SPH_ERR_ARG;
     HIP_CHECKED(merged_drop(ctx, false));  // a merged build's duplicates were captured with the old fields
+    if (fields->rho != ctx->fields.rho) ctx->layout_gen++;  // the density field is baked into batch tables
     ctx->fields = *fields;
     return SPH_OK;
 }
@@ -3720,7 +3197,6 @@ static sph_status read_bc_status(sph_ctx *ctx) {
 
 extern "C" sph_status sph_buffer_apply_bc(sph_ctx *ctx, sph_particles *p) {
     if (!ctx) return SPH_ERR_ARG;
-    HIP_CHECKED(join_side(ctx));
     HIP_CHECKED(merged_drop(ctx, false));
     Parts pp;
     const sph_status st = parts_of(ctx, p, pp);
@@ -3744,7 +3220,6 @@ static void mat_vec_host(int dim, const double m[9], const double x[3], double y
 extern "C" sph_status sph_buffer_rotate(sph_ctx *ctx, sph_particles *p, int32_t buffer_id, const double center[3],
                                         const double m[9]) {
     if (!ctx || !center || !m || buffer_id < 1 || buffer_id > ctx->nb) return SPH_ERR_ARG;
-    HIP_CHECKED(join_side(ctx));
     HIP_CHECKED(merged_drop(ctx, false));
     const int dim = ctx->dim;
     for (int c = 0; c < dim; ++c)
@@ -3810,7 +3285,6 @@ extern "C" sph_status sph_buffer_rotate(sph_ctx *ctx, sph_particles *p, int32_t 
 
 extern "C" sph_status sph_buffer_identify(sph_ctx *ctx, sph_particles *p, int32_t buffer_id) {
     if (!ctx) return SPH_ERR_ARG;
-    HIP_CHECKED(join_side(ctx));
     HIP_CHECKED(merged_drop(ctx, false));
     if (buffer_id != -1 && (buffer_id < 1 || buffer_id > ctx->nb)) return SPH_ERR_ARG;
     Parts pp;
@@ -3838,7 +3312,6 @@ extern "C" sph_status sph_buffer_identify(sph_ctx *ctx, sph_particles *p, int32_
 
 extern "C" sph_status sph_state_get(sph_ctx *ctx, int64_t *next_id, int64_t n_labelled[SPH_MAX_BUFFERS]) {
     if (!ctx) return SPH_ERR_ARG;
-    HIP_CHECKED(join_side(ctx));
     Ctl h{};
     HIP_TRY(hipMemcpyAsync(&h, ctx->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
@@ -3850,7 +3323,6 @@ extern "C" sph_status sph_state_get(sph_ctx *ctx, int64_t *next_id, int64_t n_la
 
 extern "C" sph_status sph_state_set(sph_ctx *ctx, int64_t next_id, const int64_t n_labelled[SPH_MAX_BUFFERS]) {
     if (!ctx) return SPH_ERR_ARG;
-    HIP_CHECKED(join_side(ctx));
     HIP_CHECKED(merged_drop(ctx, false));
     HIP_TRY(hipMemcpyAsync(&ctx->d_ctl->next_id, &next_id, sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
     if (n_labelled)
@@ -3858,6 +3330,30 @@ extern "C" sph_status sph_state_set(sph_ctx *ctx, int64_t next_id, const int64_t
                                hipMemcpyHostToDevice, ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     return SPH_OK;
+}
+
+// Blob layout: tag, next_id, n_labelled[SPH_MAX_BUFFERS] (int64 each).
+static constexpr uint64_t kStateTag = 0x31766174736870ull;  // "phstav1"
+static_assert(SPH_STATE_BLOB_BYTES == 8 * (2 + SPH_MAX_BUFFERS), "state blob layout");
+
+extern "C" sph_status sph_state_export(sph_ctx *ctx, void *blob, size_t *len) {
+    if (!ctx || !len) return SPH_ERR_ARG;
+    const size_t have = *len;
+    *len = SPH_STATE_BLOB_BYTES;
+    if (!blob || have < SPH_STATE_BLOB_BYTES) return SPH_ERR_ARG;
+    int64_t w[2 + SPH_MAX_BUFFERS];
+    w[0] = (int64_t)kStateTag;
+    HIP_CHECKED(sph_state_get(ctx, &w[1], &w[2]));
+    std::memcpy(blob, w, sizeof(w));
+    return SPH_OK;
+}
+
+extern "C" sph_status sph_state_import(sph_ctx *ctx, const void *blob, size_t len) {
+    if (!ctx || !blob || len != SPH_STATE_BLOB_BYTES) return SPH_ERR_ARG;
+    int64_t w[2 + SPH_MAX_BUFFERS];
+    std::memcpy(w, blob, sizeof(w));
+    if ((uint64_t)w[0] != kStateTag) return SPH_ERR_ARG;
+    return sph_state_set(ctx, w[1], &w[2]);
 }
 
 extern "C" sph_status sph_profile_enable(sph_ctx *ctx, int32_t on) {
@@ -3895,7 +3391,6 @@ extern "C" sph_status sph_profile_read(sph_ctx *ctx, double ms[SPH_NPHASE], int6
 
 extern "C" sph_status sph_grid_fit(sph_ctx *ctx, const sph_particles *p) {
     if (!ctx) return SPH_ERR_ARG;
-    HIP_CHECKED(join_side(ctx));
     HIP_CHECKED(merged_drop(ctx, false));
     if (ctx->blog2 == 0) return SPH_OK;
     Parts pp;
@@ -3954,6 +3449,7 @@ extern "C" sph_status sph_grid_fit(sph_ctx *ctx, const sph_particles *p) {
     (void)hipFree(ctx->d_count);
     (void)hipFree(ctx->d_cell_start);
     (void)hipFree(ctx->d_tile_state);
+    ctx->layout_gen++;
     ctx->d_count = cnt;
     ctx->d_cell_start = start;
     ctx->d_tile_state = ts;
@@ -3979,6 +3475,7 @@ extern "C" sph_status sph_grid_fit(sph_ctx *ctx, const sph_particles *p) {
 
 struct sph_batch {
     std::vector<sph_ctx *> doms;
+    std::vector<uint64_t> gens;  // each member's layout generation when the tables were made
     std::vector<Parts> parts;
     hipStream_t stream = nullptr;
     bool own_stream = false;
@@ -4092,7 +3589,6 @@ extern "C" sph_status sph_batch_create(sph_ctx *const *domains, const sph_partic
     if (!domains || !particles || n_domains < 1 || n_domains > 65535) return SPH_ERR_ARG;
     for (int d = 0; d < n_domains; ++d) {  // no build work of a domain left in flight
         if (!domains[d]) return SPH_ERR_ARG;
-        HIP_CHECKED(join_side(domains[d]));
         HIP_CHECKED(merged_drop(domains[d], true));
         HIP_TRY(hipStreamSynchronize(domains[d]->stream));
     }
@@ -4121,6 +3617,7 @@ extern "C" sph_status sph_batch_create(sph_ctx *const *domains, const sph_partic
         }
         (void)hipStreamSynchronize(c->stream);
         b->doms.push_back(c);
+        b->gens.push_back(c->layout_gen);
         b->parts.push_back(pp);
         ca.push_back(count_args(c, pp));
         sa.push_back(scan_args(c));
@@ -4164,22 +3661,39 @@ extern "C" sph_status sph_batch_set_count_block(sph_batch *b, int32_t particles_
 
 extern "C" sph_status sph_batch_step(sph_batch *b) {
     if (!b) return SPH_ERR_ARG;
+    for (size_t d = 0; d < b->doms.size(); ++d)  // a member redefined since: stale tables, launch nothing
+        if (b->doms[d]->layout_gen != b->gens[d]) return SPH_ERR_STATE;
     if (b->mode == SPH_BATCH_KERNELS) return batch_enqueue(b);
-    if (!b->exec) {
-        HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-        const sph_status st = batch_enqueue(b);
-        hipGraph_t g = nullptr;
-        const hipError_t e = hipStreamEndCapture(b->stream, &g);
-        if (st != SPH_OK || e != hipSuccess || !g) {
-            if (g) (void)hipGraphDestroy(g);
-            return st != SPH_OK ? st : SPH_ERR_HIP;
-        }
-        b->graph = g;
-        if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) {
-            batch_drop_graph(b);
-            return SPH_ERR_HIP;
-        }
+    return sph_batch_graph_launch(b);
+}
+
+extern "C" sph_status sph_batch_graph_capture(sph_batch *b) {
+    if (!b) return SPH_ERR_ARG;
+    for (size_t d = 0; d < b->doms.size(); ++d)
+        if (b->doms[d]->layout_gen != b->gens[d]) return SPH_ERR_STATE;
+    batch_drop_graph(b);
+    b->mode = SPH_BATCH_GRAPH;
+    HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    const sph_status st = batch_enqueue(b);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->stream, &g);
+    if (st != SPH_OK || e != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        return st != SPH_OK ? st : SPH_ERR_HIP;
     }
+    b->graph = g;
+    if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+        batch_drop_graph(b);
+        return SPH_ERR_HIP;
+    }
+    return SPH_OK;
+}
+
+extern "C" sph_status sph_batch_graph_launch(sph_batch *b) {
+    if (!b) return SPH_ERR_ARG;
+    for (size_t d = 0; d < b->doms.size(); ++d)
+        if (b->doms[d]->layout_gen != b->gens[d]) return SPH_ERR_STATE;
+    if (!b->exec) HIP_CHECKED(sph_batch_graph_capture(b));
     HIP_TRY(hipGraphLaunch(b->exec, b->stream));
     return SPH_OK;
 }

@@ -12,6 +12,10 @@ struct Obb;
 sph_status grid_cover(int dim, const double glo[3], double cs, const int32_t dims[3], const double origin[3],
                       const double rot[9], const double half[3], double margin, std::vector<int32_t> &first,
                       std::vector<int32_t> &len);
+// FP32 cell binning: bound on the error of a cell coordinate (in cells), and the
+// largest bound a grid may have (the cover dilates cell boxes by 1.5 times it).
+double binning_error_cells(int dim, const double glo[3], double cs, const int32_t dims[3]);
+extern const double kMaxBinningError;
 double guard_band(int dim, const double origin[3], const double half[3], double margin, double cs, double dp);
 double sphere_radius(int dim, const double half[3], double margin);
 bool check_regions_overlap(int dim, const double o1[3], const double r1[9], const double h1[3], double m1,

@@ -4,9 +4,15 @@ Argument marshalling only: every function keeps the C name and forwards to the
 library, which runs every step of the buffer update in its own HIP kernels.
 PyTorch supplies device memory (``tensor.data_ptr()``) and the stream.  There is
 no fallback: if the shared library is missing, loading it raises.
+
+Contexts and batches still alive when the interpreter exits are destroyed by an
+``atexit`` hook (batches first, then contexts), while the HIP runtime is still
+up: left to garbage collection at interpreter teardown, their HIP calls could
+run after the runtime (or a profiler attached to it) has shut down.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 from typing import Optional, Sequence, Tuple
@@ -23,6 +29,9 @@ SPH_INLET, SPH_OUTLET, SPH_BIDIR = 1, 2, 3
 SPH_MAX_BUFFERS = 15
 SPH_MAX_CARRIED = 16
 SPH_MAX_EVENTS_LIMIT = 4096
+SPH_UPDATE_MERGED, SPH_UPDATE_CELLS = 0, 1
+UPDATE_PATHS = {"merged": SPH_UPDATE_MERGED, "cells": SPH_UPDATE_CELLS}
+SPH_STATE_BLOB_BYTES = 136
 
 EXPORTED = (
     "sph_create", "sph_destroy", "sph_buffer_define", "sph_celllist_build", "sph_buffer_identify",
@@ -34,11 +43,11 @@ EXPORTED = (
     "sph_batch_create", "sph_batch_destroy", "sph_batch_set_mode", "sph_batch_set_count_block",
     "sph_batch_step", "sph_batch_results", "sph_batch_tune",
     "sph_set_fields", "sph_buffer_set_bc", "sph_buffer_apply_bc", "sph_buffer_rotate", "sph_neighbor_count",
+    "sph_state_export", "sph_state_import", "sph_batch_graph_capture", "sph_batch_graph_launch",
 )
 SPH_BATCH_KERNELS, SPH_BATCH_GRAPH = 0, 1
-SPH_NPHASE = 11
-PHASES = ("count", "scan", "scatter", "classify", "fullscan", "finalize", "build", "bc", "rotate", "candidates",
-          "neighbor")
+SPH_NPHASE = 10
+PHASES = ("count", "scan", "scatter", "classify", "fullscan", "finalize", "bc", "rotate", "candidates", "neighbor")
 SPH_BC_NONE, SPH_BC_VELOCITY, SPH_BC_PRESSURE = 0, 1, 2
 SPH_PROFILE_PLUG, SPH_PROFILE_PARABOLIC_Y, SPH_PROFILE_PARABOLIC_R = 0, 1, 2
 
@@ -70,6 +79,8 @@ class sph_config(ctypes.Structure):
         ("stream", ctypes.c_void_p),
         ("brick_log2", ctypes.c_int32),
         ("brick_margin", ctypes.c_int32),
+        ("update_path", ctypes.c_int32),
+        ("pad2_", ctypes.c_int32),
     ]
 
 
@@ -109,6 +120,23 @@ class SphError(RuntimeError):
 
 
 _lib = None
+_live_ctx: set = set()
+_live_batch: set = set()
+
+
+@atexit.register
+def _destroy_live_handles() -> None:
+    """Destroy what the program left alive, batches before their member contexts."""
+    if _lib is None:
+        return
+    for b in list(_live_batch):
+        _live_batch.discard(b)
+        _lib.sph_batch_destroy(b)
+    for c in list(_live_ctx):
+        _live_ctx.discard(c)
+        _lib.sph_destroy(c)
+
+
 _D = ctypes.POINTER(ctypes.c_double)
 _I64 = ctypes.POINTER(ctypes.c_int64)
 _I32 = ctypes.POINTER(ctypes.c_int32)
@@ -138,6 +166,10 @@ def lib() -> ctypes.CDLL:
             "sph_celllist_view": ([_VP, ctypes.POINTER(_VP), ctypes.POINTER(_VP), _I64, _I32], ctypes.c_int),
             "sph_state_get": ([_VP, _I64, _I64], ctypes.c_int),
             "sph_state_set": ([_VP, ctypes.c_int64, _I64], ctypes.c_int),
+            "sph_state_export": ([_VP, _VP, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+            "sph_state_import": ([_VP, _VP, ctypes.c_size_t], ctypes.c_int),
+            "sph_batch_graph_capture": ([_VP], ctypes.c_int),
+            "sph_batch_graph_launch": ([_VP], ctypes.c_int),
             "sph_rotation_2d": ([ctypes.c_double, _D], ctypes.c_int),
             "sph_rotation_axis_angle": ([_D, ctypes.c_double, _D], ctypes.c_int),
             "sph_rotation_from_direction": ([_D, _D], ctypes.c_int),
@@ -194,7 +226,7 @@ def sph_status_str(status: int) -> str:
 
 def sph_create(dim: int, lo, hi, cell_size: float, dp: float, capacity: int, max_events: int = 4096,
                next_id: int = 0, stream: int = 0, brick_log2: int = 0,
-               brick_margin: int = 1) -> Tuple[int, Optional[int]]:
+               brick_margin: int = 1, update_path: int = SPH_UPDATE_MERGED) -> Tuple[int, Optional[int]]:
     cfg = sph_config()
     cfg.dim = dim
     cfg.lo = _d3(lo)
@@ -207,12 +239,16 @@ def sph_create(dim: int, lo, hi, cell_size: float, dp: float, capacity: int, max
     cfg.stream = stream or None
     cfg.brick_log2 = brick_log2
     cfg.brick_margin = brick_margin
+    cfg.update_path = int(update_path)
     out = _VP()
     st = lib().sph_create(ctypes.byref(cfg), ctypes.byref(out))
+    if st == SPH_OK and out.value:
+        _live_ctx.add(out.value)
     return st, out.value
 
 
 def sph_destroy(ctx: int) -> int:
+    _live_ctx.discard(ctx)
     return lib().sph_destroy(ctx)
 
 
@@ -323,6 +359,18 @@ def sph_state_set(ctx: int, next_id: int, n_labelled) -> int:
     return lib().sph_state_set(ctx, int(next_id), nl.ctypes.data_as(_I64))
 
 
+def sph_state_export(ctx: int) -> Tuple[int, bytes]:
+    buf = ctypes.create_string_buffer(SPH_STATE_BLOB_BYTES)
+    n = ctypes.c_size_t(SPH_STATE_BLOB_BYTES)
+    st = lib().sph_state_export(ctx, ctypes.cast(buf, _VP), ctypes.byref(n))
+    return st, buf.raw[: n.value]
+
+
+def sph_state_import(ctx: int, blob: bytes) -> int:
+    buf = ctypes.create_string_buffer(bytes(blob), len(blob))
+    return lib().sph_state_import(ctx, ctypes.cast(buf, _VP), len(blob))
+
+
 def sph_rotation_2d(theta: float) -> Tuple[int, np.ndarray]:
     r = (ctypes.c_double * 9)()
     st = lib().sph_rotation_2d(float(theta), r)
@@ -377,11 +425,22 @@ def sph_batch_create(ctxs, parts, stream: int = 0):
     parr = (sph_particles * n)(*parts)
     out = _VP()
     st = lib().sph_batch_create(arr, parr, n, stream or None, ctypes.byref(out))
+    if st == SPH_OK and out.value:
+        _live_batch.add(out.value)
     return st, out.value
 
 
 def sph_batch_destroy(b: int) -> int:
+    _live_batch.discard(b)
     return lib().sph_batch_destroy(b)
+
+
+def sph_batch_graph_capture(b: int) -> int:
+    return lib().sph_batch_graph_capture(b)
+
+
+def sph_batch_graph_launch(b: int) -> int:
+    return lib().sph_batch_graph_launch(b)
 
 
 def sph_batch_set_mode(b: int, mode: int) -> int:

@@ -9,12 +9,17 @@ import numpy as np
 import oracle
 from tests._support import oracle_state
 
+# Update path of the contexts the tests make ("merged", the library's default, or
+# "cells"); tests of one path set it with monkeypatch.setattr.
+UPDATE_PATH = "merged"
+
 
 def make_domain_raw(dim, lo, hi, cell_size, dp, bufs: Sequence[oracle.Buffer], st: oracle.State,
-                    max_events: int = 4096, brick_log2: int = 0, brick_margin: int = 1):
+                    max_events: int = 4096, brick_log2: int = 0, brick_margin: int = 1, update_path: str = None):
     from paper_2406_16786_amd.domain import Domain
     d = Domain(dim, lo, hi, cell_size, dp, st.capacity, st.pos, st.carried, st.label, st.id, st.n, st.next_id,
-               max_events=max_events, brick_log2=brick_log2, brick_margin=brick_margin)
+               max_events=max_events, brick_log2=brick_log2, brick_margin=brick_margin,
+               update_path=update_path or UPDATE_PATH)
     for b in bufs:
         d.define(b.kind, b.origin, b.rot, b.half, b.margin)
     if brick_log2:

@@ -147,3 +147,95 @@ def test_guard_band_is_1e4_dp_for_the_pipe():
     g = S.sph_guard_band(3, (0, 0, 1.0), (2 * dp, 0.05 / math.cos(math.radians(35)) + 2 * dp,
                                           0.05 / math.cos(math.radians(35)) + 2 * dp), 2.6 * dp, 2.6 * dp, dp)
     assert g == pytest.approx(1e-4 * dp)
+
+
+def _fp32_cells(dim, lo, cs, dims, P):
+    """Cell coordinates exactly as the kernels bin an FP32 position:
+    floor(fl32(fl32(x - fl32(lo)) * fl32(1/cs))), clamped to the grid."""
+    lo32 = np.asarray(lo[:dim], dtype=np.float32)
+    ic = np.float32(1.0 / cs)
+    t = ((P[:, :dim] - lo32).astype(np.float32) * ic).astype(np.float32)
+    c = np.floor(t).astype(np.int64)
+    return np.clip(c, 0, np.asarray(dims[:dim]) - 1)
+
+
+WIDE_DP = 0.001
+WIDE_CS = 2.6 * WIDE_DP
+# 150,000 cells along x, origin 10^6 cells from 0: lo_x rounds to FP32 with an
+# error of 0.045 cells, which shifts every binned particle by that much
+WIDE_LO = np.array([1e6 * WIDE_CS + 0.37 * WIDE_DP, -8 * WIDE_CS + 0.11 * WIDE_DP, 0.0])
+WIDE_DIMS = [150_000, 16, 1]
+
+
+def misbinned_column(lo, cs, dims, k_start):
+    """An FP32 x value that lies 0.012 .. 0.044 cells right of a cell face (in
+    exact arithmetic) but is binned into the cell left of that face, near cell
+    k_start: (x, cell index of the face)."""
+    for k in range(k_start, k_start - 200, -1):
+        face = lo[0] + k * cs
+        x = np.float32(face)
+        while float(x) < face + 0.05 * cs:
+            if float(x) > face + 0.012 * cs:
+                c = _fp32_cells(2, lo, cs, dims, np.array([[x, 0.0, 0.0]], np.float32))[0, 0]
+                if c == k - 1:
+                    return float(x), k
+            x = np.nextafter(x, np.float32(np.inf))
+    raise AssertionError("no misbinned FP32 column")
+
+
+def test_grid_cover_holds_fp32_binning_on_a_wide_far_grid():
+    """A 2-D grid of 150,000 cells along x whose origin lies 10^6 cells from 0: the
+    FP32 cell coordinate is off by up to ~0.07 cells there.  (1) An axis-aligned
+    outlet whose check region starts just left of an FP32 column that is binned a
+    cell too low: those points must bin into a covered cell (a dilation of 1e-2
+    cell would miss them).  (2) Random points of an oblique outlet's check region,
+    most within a fraction of a cell of its boundary."""
+    dp, cs, lo, dims = WIDE_DP, WIDE_CS, WIDE_LO, WIDE_DIMS
+    half = np.array([2 * dp, 0.012, 0.0])
+    margin = cs
+    ext = (half + margin)[:2]
+    # (1) adversarial axis-aligned region
+    xc, k = misbinned_column(lo, cs, dims, dims[0] - 30)
+    origin = np.array([xc - 1e-9 + ext[0], 0.0012, 0.0])
+    b = oracle.Buffer(2, tuple(origin), np.eye(3), tuple(half), margin)
+    cells = _cover_cells(2, lo, cs, dims, b)
+    ys = np.linspace(origin[1] - 0.9 * ext[1], origin[1] + 0.9 * ext[1], 101)
+    P = np.zeros((len(ys), 3), np.float32)
+    P[:, 0] = np.float32(xc)
+    P[:, 1] = ys
+    lc = oracle.local_coords(2, b, P[:, 0], P[:, 1], None)
+    assert np.all(np.abs(lc[:, :2]) < ext)             # all in the check region
+    c = _fp32_cells(2, lo, cs, dims, P)
+    assert np.all(c[:, 0] == k - 1)                    # binned left of the region's first cell
+    missing = [int(q) for q in c[:, 0] + dims[0] * c[:, 1] if int(q) not in cells]
+    assert not missing, f"{len(missing)} points of the check region fall in uncovered cells"
+    # (2) oblique region, random points mostly near its boundary
+    rng = np.random.default_rng(5)
+    q = oracle.rotation_2d(math.radians(-35.0))
+    origin = np.array([lo[0] + (dims[0] - 20) * cs, 0.0012, 0.0])
+    b = oracle.Buffer(2, tuple(origin), q, tuple(half), margin)
+    cells = _cover_cells(2, lo, cs, dims, b)
+    n = 400_000
+    L = rng.uniform(-1, 1, size=(n, 2)) * ext
+    shell = rng.uniform(size=n) < 0.7
+    side = rng.integers(0, 2, n)
+    depth = rng.uniform(0.0, 0.3 * cs, n)
+    L[shell, side[shell]] = np.sign(L[shell, side[shell]]) * (ext[side[shell]] - depth[shell])
+    P = np.zeros((n, 3))
+    P[:, :2] = L @ q[:2, :2] + origin[:2]
+    P = P.astype(np.float32)
+    lc = oracle.local_coords(2, b, P[:, 0], P[:, 1], None)
+    inside = np.all(np.abs(lc[:, :2]) < ext, axis=1)
+    c = _fp32_cells(2, lo, cs, dims, P)
+    exact = np.floor((P[:, :2].astype(np.float64) - lo[:2]) / cs).astype(np.int64)
+    assert np.count_nonzero(np.any(c != exact, axis=1) & inside) > 1000
+    key = c[:, 0] + dims[0] * c[:, 1]
+    missing = [int(q) for q in key[inside] if int(q) not in cells]
+    assert not missing, f"{len(missing)} points of the check region fall in uncovered cells"
+
+
+def test_grid_cover_refuses_grids_too_wide_for_fp32_binning():
+    # 2^23 cells along x: the relative FP32 error alone reaches 1.5 cells
+    dims = [1 << 23, 4, 1]
+    st, f, ln = S.sph_grid_cover(2, (0, 0, 0), 1e-3, dims, (0.5, 0.002, 0), np.eye(3), (1e-3, 1e-3, 0), 1e-3)
+    assert st == S.SPH_ERR_ARG

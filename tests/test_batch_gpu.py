@@ -77,11 +77,9 @@ def _run(wls, steps, mode, tune=False):
 
 @pytest.fixture(params=["cells", "merged"])
 def path(request, monkeypatch):
-    """The update path of the domains (read when each domain is created)."""
-    if request.param == "merged":
-        monkeypatch.setenv("SPHBUF_UPDATE", "merged")
-    else:
-        monkeypatch.delenv("SPHBUF_UPDATE", raising=False)
+    """The update path of the domains (set when each domain is created)."""
+    import tests._gpu as G
+    monkeypatch.setattr(G, "UPDATE_PATH", request.param)
     return request.param
 
 
@@ -97,3 +95,67 @@ def test_batch_after_autotuning(path):
 def test_full_batch_two_steps(path):
     """64 domains, particle counts log-uniform over 10k-2M (about 27.6 M in all)."""
     _run(W.hub_batch(), 2, 1)
+
+
+def test_graph_capture_and_launch_calls():
+    """sph_batch_graph_capture records the step, sph_batch_graph_launch replays it:
+    the same results as stepping in launch mode."""
+    import torch
+    from paper_2406_16786_amd import sphbuf as S
+    wls = W.hub_batch(4, 2e3, 1e4, seed=3)
+    doms, bufs, states, batch, stream = _setup(wls)
+    assert S.sph_batch_graph_capture(batch) == 0
+    for step in range(6):
+        for wl, s, d in zip(wls, states, doms):
+            W.advect_host(wl, s.pos, s.n, step)
+            upload_state(d, s)
+        torch.cuda.synchronize()
+        assert S.sph_batch_graph_launch(batch) == 0
+        st, res = S.sph_batch_results(batch, len(doms))
+        assert st == 0
+        for k, (d, b, s) in enumerate(zip(doms, bufs, states)):
+            ro = oracle.update(b, s)
+            assert res[k].status == ro.status == 0
+            assert_same_state(d, s, f"step {step} domain {k}")
+    S.sph_batch_destroy(batch)
+    for d in doms:
+        d.close()
+
+
+@pytest.mark.parametrize("change", ["rotate", "define", "fields"])
+def test_batch_refuses_to_step_after_a_member_changed(change):
+    """A batch bakes its members' cover cells, grid arrays and field roles into its
+    launch tables: after a turn, a new buffer or a new density field on a member it
+    refuses to step (SPH_ERR_STATE, nothing launched) and the particle arrays stay
+    as they were; a new batch steps again."""
+    import torch
+    from paper_2406_16786_amd import sphbuf as S
+    wls = W.hub_batch(3, 2e3, 1e4, seed=7)
+    doms, bufs, states, batch, stream = _setup(wls)
+    d0 = doms[0]
+    if change == "rotate":
+        d0.build()
+        c = np.array(wls[0].buffers[0].origin, dtype=np.float64)
+        m = np.eye(3)   # the identity is a turn too: the cover is recomputed
+        assert d0.rotate(1, c[:wls[0].dim], m) == 0
+    elif change == "define":
+        far = [0.9 * h for h in wls[0].hi]
+        assert S.sph_buffer_define(d0.ctx, S.SPH_OUTLET, far, np.eye(3), [1e-3, 1e-3, 1e-3], 1e-3)[0] == 0
+    else:
+        assert S.sph_set_fields(d0.ctx, [0, 1, 2][: wls[0].dim], 0) == 0
+    torch.cuda.synchronize()
+    before = [d.download() for d in doms]
+    assert S.sph_batch_step(batch) == S.SPH_ERR_STATE
+    assert S.sph_batch_graph_launch(batch) == S.SPH_ERR_STATE
+    torch.cuda.synchronize()
+    for d, b4 in zip(doms, before):
+        after = d.download()
+        for x, y in zip(b4[0] + b4[1] + [b4[2], b4[3]], after[0] + after[1] + [after[2], after[3]]):
+            np.testing.assert_array_equal(x, y)
+    S.sph_batch_destroy(batch)
+    st, batch2 = S.sph_batch_create([d.ctx for d in doms], [d.p for d in doms], stream.cuda_stream)
+    assert st == 0 and S.sph_batch_step(batch2) == 0
+    torch.cuda.synchronize()
+    S.sph_batch_destroy(batch2)
+    for d in doms:
+        d.close()

@@ -83,10 +83,11 @@ def _run_steps(wl, steps, mode="local", identify=True, check_every=1, cell_size=
 
 # ------------------------------------------------------------- cell list ---
 
-@pytest.mark.parametrize("build", ["fused", "split"])
+@pytest.mark.parametrize("path", ["merged", "cells"])
 @pytest.mark.parametrize("name", ["channel2d", "bent_channel2d", "pipe3d_small"])
-def test_celllist_matches_oracle(name, build, monkeypatch):
-    monkeypatch.setenv("SPHBUF_BUILD", build)
+def test_celllist_matches_oracle(name, path, monkeypatch):
+    import tests._gpu as G
+    monkeypatch.setattr(G, "UPDATE_PATH", path)
     wl = {"channel2d": W.channel2d, "bent_channel2d": W.bent_channel2d,
           "pipe3d_small": lambda: W.pipe3d(dp=0.004)}[name]()
     bufs = oracle_buffers(wl)
@@ -107,10 +108,8 @@ def test_celllist_matches_oracle(name, build, monkeypatch):
     d.close()
 
 
-def test_celllist_beyond_register_slots(monkeypatch):
-    """9.5 M random particles: more than the one-launch build keeps on chip
-    (256 blocks x 1024 threads x 32 slots), so part of them take the spill path."""
-    monkeypatch.setenv("SPHBUF_BUILD", "fused")
+def test_celllist_random_9_5m():
+    """9.5 M random particles in a box (no buffer: the plain count pass)."""
     n = 9_500_000
     pos, car, lab, ids = W.random_box_particles(7, n, 3, (0, 0, 0), (1.0, 0.5, 0.5), capacity=n + 16, n_carried=1)
     st = make_state(3, np.zeros((0, 3)))
@@ -583,3 +582,58 @@ def test_tree_full_size_two_steps():
     """The branching network at dp = 0.001 (about 16 M particles) on the
     brick-sparse grid: events and every array against the oracle."""
     _run_steps(W.tree3d(), 2, mode="local", brick_log2=3)
+
+
+@pytest.mark.parametrize("path", ["merged", "cells", "fullscan"])
+def test_far_wide_grid_fp32_binning(path):
+    """A 2-D grid of 150,000 cells along x whose origin is 10^6 cells from 0 (FP32
+    binning is off by up to ~0.07 cells): an axis-aligned outlet whose check region
+    starts just left of an FP32 column that bins a cell too low, with buffer
+    particles on that column (they must be found, relabelled to fluid, and counted
+    by the CFL check), plus an oblique outlet with a few thousand particles near
+    the boundary of its check region.  Events and arrays equal the oracle's."""
+    import math
+    from tests.test_abi_host import WIDE_CS, WIDE_DIMS, WIDE_DP, WIDE_LO, misbinned_column
+    cs, dp, lo, dims = WIDE_CS, WIDE_DP, WIDE_LO, WIDE_DIMS
+    half = np.array([2 * dp, 0.012, 0.0])
+    ext = (half + cs)[:2]
+    xc, k = misbinned_column(lo, cs, dims, dims[0] - 300)
+    o1 = np.array([xc - 1e-9 + ext[0], 0.0012, 0.0])
+    q2 = oracle.rotation_2d(math.radians(-35.0))
+    o2 = np.array([lo[0] + (dims[0] - 40) * cs, 0.0012, 0.0])
+    bufs = [oracle.Buffer(oracle.OUTLET, tuple(o1), np.eye(3), tuple(half), cs),
+            oracle.Buffer(oracle.OUTLET, tuple(o2), q2, tuple(half), cs)]
+    rng = np.random.default_rng(21)
+    col = np.column_stack([np.full(60, np.float32(xc)), np.linspace(o1[1] - 0.9 * ext[1], o1[1] + 0.9 * ext[1], 60)])
+    box1 = np.column_stack([rng.uniform(o1[0] - half[0], o1[0] + half[0], 200),
+                            rng.uniform(o1[1] - half[1], o1[1] + half[1], 200)])
+    L = rng.uniform(-1.05, 1.05, size=(3000, 2)) * ext
+    side = rng.integers(0, 2, 3000)
+    L[np.arange(3000), side] = np.sign(L[np.arange(3000), side]) * ext[side] * rng.uniform(0.9, 1.02, 3000)
+    obl = L @ q2[:2, :2] + o2[:2]
+    pts = np.concatenate([col, box1, obl]).astype(np.float32).astype(np.float64)
+    labels = np.zeros(len(pts), np.int32)
+    labels[:60] = 1                                  # buffer particles of outlet 1 in its margin
+    labels[60:260] = 1                               # ... and in its box
+    lc2 = oracle.local_coords(2, bufs[1], pts[:, 0].astype(np.float32), pts[:, 1].astype(np.float32), None)
+    in_box2 = np.all(np.abs(lc2[:, :2]) < half[:2], axis=1)
+    labels[260:][in_box2[260:]] = 2
+    st = make_state(2, pts, capacity=len(pts) + 64, labels=labels)
+    hi = lo + (np.array(dims) - 0.5) * cs
+    d = make_domain_raw(2, tuple(lo), tuple(hi), cs, dp, bufs, st,
+                        update_path="cells" if path == "cells" else "merged")
+    _identify_counts(d, bufs, st)
+    if path == "fullscan":
+        gst, g, dl = d.update_fullscan()
+    else:
+        d.build()
+        gst, g, dl = d.update()
+    res = oracle.update(bufs, st)
+    assert gst == res.status == 0, (gst, res.status)
+    _, gg, dd = d.events()
+    np.testing.assert_array_equal(gg, res.gen)
+    np.testing.assert_array_equal(dd, res.dele)
+    assert len(res.dele) > 0
+    assert_same_state(d, st, "far wide grid")
+    assert np.all(st.label[:60] == 0)                # the column's buffer particles were relabelled
+    d.close()

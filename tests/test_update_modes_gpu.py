@@ -1,10 +1,9 @@
-"""The update paths behind the same C ABI against the FP64 oracle: the update that
-walks the cover cells of the finished cell list (the default), the overlapped step
-(SPHBUF_UPDATE=overlap: the count pass gathers the particles of the buffers' cover
-cells, the update runs on them while the scan and scatter finish on a side stream)
-and the merged step (SPHBUF_UPDATE=merged: the count pass classifies those
-particles and emits their events, the update runs the finalize beside the scan
-tiles, then the scatter); plus the call orders the two have to survive."""
+"""The two update paths behind the same C ABI against the FP64 oracle: the merged
+step (SPH_UPDATE_MERGED, the default: the count pass classifies the particles of
+the buffers' cover cells and emits their events, the update runs the finalize
+beside the scan tiles, then the scatter) and the update that walks the cover
+cells of the finished cell list (SPH_UPDATE_CELLS); plus the call orders the
+merged step has to survive."""
 import numpy as np
 import pytest
 
@@ -18,13 +17,11 @@ pytestmark = pytest.mark.gpu
 
 
 def _mode(monkeypatch, mode):
-    if mode in ("overlap", "merged"):
-        monkeypatch.setenv("SPHBUF_UPDATE", mode)
-    else:
-        monkeypatch.delenv("SPHBUF_UPDATE", raising=False)
+    import tests._gpu as G
+    monkeypatch.setattr(G, "UPDATE_PATH", mode)
 
 
-@pytest.mark.parametrize("mode", ["overlap", "merged", "cells"])
+@pytest.mark.parametrize("mode", ["merged", "cells"])
 def test_channel_and_pipe(mode, monkeypatch):
     _mode(monkeypatch, mode)
     g, dl = _run_steps(W.channel2d(), 120)
@@ -33,7 +30,7 @@ def test_channel_and_pipe(mode, monkeypatch):
     assert g > 0
 
 
-@pytest.mark.parametrize("mode", ["overlap", "merged", "cells"])
+@pytest.mark.parametrize("mode", ["merged", "cells"])
 def test_tree_bidirectional_sparse_grid(mode, monkeypatch):
     _mode(monkeypatch, mode)
     g, dl = _run_steps(W.tree3d(dp=0.004), 60, check_every=20, brick_log2=3)
@@ -58,9 +55,9 @@ def _check_update(d, bufs, st, what):
     assert_same_state(d, st, what)
 
 
-@pytest.mark.parametrize("mode", ["overlap", "merged"])
+@pytest.mark.parametrize("mode", ["merged", "cells"])
 def test_unconsumed_builds_and_interleaved_calls(mode, monkeypatch):
-    """A build no update consumed (its candidates or events must not count twice),
+    """A build no update consumed (its events must not count twice),
     a full-scan update after such a build, a neighbour search and a cell-list view
     between the build and the update."""
     _mode(monkeypatch, mode)
@@ -99,15 +96,10 @@ def test_unconsumed_builds_and_interleaved_calls(mode, monkeypatch):
     d.close()
 
 
-def test_overlapped_step_full_size(monkeypatch):
-    """The overlapped step on the benchmark's pipe (7.86 M particles), two steps."""
-    _mode(monkeypatch, "overlap")
-    _run_steps(W.pipe3d(), 2)
-
-
-def test_merged_step_full_size(monkeypatch):
-    """The merged step on the benchmark's pipe (7.86 M particles), two steps."""
-    _mode(monkeypatch, "merged")
+def test_cover_walk_full_size(monkeypatch):
+    """The cover-cell walk on the benchmark's pipe (7.86 M particles), two steps
+    (the parity tests run the merged step, the default)."""
+    _mode(monkeypatch, "cells")
     _run_steps(W.pipe3d(), 2)
 
 
@@ -134,26 +126,26 @@ def test_merged_step_cell_list_after_the_update(monkeypatch):
 
 
 @pytest.mark.parametrize("case", ["vipo_pipe3d", "pivo_channel2d"])
-def test_merged_step_with_boundary_conditions(case, monkeypatch):
-    """Boundary conditions applied between the build and the update change the
-    state the merged build classified: its events are dropped and the update walks
-    the cover cells (the duplicates carry the new velocities)."""
+def test_cover_walk_with_boundary_conditions(case, monkeypatch):
+    """The boundary-condition runs on the cover-cell walk.  (On the merged path, the
+    default, boundary conditions applied between the build and the update drop the
+    build's events and the update walks the cover cells.)"""
     from tests.test_bc_gpu import test_boundary_conditions_over_steps
-    _mode(monkeypatch, "merged")
+    _mode(monkeypatch, "cells")
     test_boundary_conditions_over_steps(case)
 
 
-def test_merged_step_sprinkler(monkeypatch):
+def test_cover_walk_sprinkler(monkeypatch):
     from tests.test_bc_gpu import test_sprinkler_rotating_inlet
-    _mode(monkeypatch, "merged")
+    _mode(monkeypatch, "cells")
     test_sprinkler_rotating_inlet()
 
 
 @pytest.mark.parametrize("what", ["cfl", "capacity", "nonfinite", "empty", "all_deleted", "hand", "unaligned",
                                   "clustered", "guard"])
-def test_merged_step_edge_cases(what, monkeypatch):
+def test_cover_walk_edge_cases(what, monkeypatch):
     import tests.test_parity_gpu as P
-    _mode(monkeypatch, "merged")
+    _mode(monkeypatch, "cells")
     if what == "cfl":
         P.test_cfl_violation_leaves_state_untouched("local")
     elif what == "capacity":
@@ -176,17 +168,17 @@ def test_merged_step_edge_cases(what, monkeypatch):
             P.test_guard_band_decisions_equal_fp64(dim, 0)
 
 
-def test_merged_step_tree_full_size(monkeypatch):
-    """The merged step on the branching network at full size (16.1 M particles,
+def test_cover_walk_tree_full_size(monkeypatch):
+    """The cover-cell walk on the branching network at full size (16.1 M particles,
     brick-sparse grid, four bidirectional buffers), two steps."""
-    _mode(monkeypatch, "merged")
+    _mode(monkeypatch, "cells")
     _run_steps(W.tree3d(), 2, brick_log2=3)
 
 
-def test_merged_step_bent_channel_1000_steps(monkeypatch):
-    """The merged step on the bent 2-D channel for its full 1,000 steps (events every
-    step, every array every 100 steps)."""
-    _mode(monkeypatch, "merged")
+def test_cover_walk_bent_channel_1000_steps(monkeypatch):
+    """The cover-cell walk on the bent 2-D channel for its full 1,000 steps (events
+    every step, every array every 100 steps)."""
+    _mode(monkeypatch, "cells")
     g, dl = _run_steps(W.bent_channel2d(), 1000, check_every=100)
     assert g > 0 and dl > 0
 
