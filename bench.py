@@ -4,24 +4,36 @@
 One step = one pass of the whole path over one particle state: the cell-list
 build (count, scan, scatter) followed by the buffer update (local-cell
 candidates, frame rotation, crossing tests, generation/recycle, deletion by
-compaction, relabel).  The workload is the 3-D pipe (R = 0.05, L = 1, dp = 0.001,
-about 7.86 M particles, inlet and outlet planes tilted 20 and 35 degrees) unless
---workload says otherwise.
+compaction, relabel), on the library's default path (the merged step).
+
+Headline workload: the 3-D bifurcating pipe network (trunk, two daughters, two
+granddaughters; dp = 0.001, about 16.1 M particles on a brick-sparse grid; one
+bidirectional buffer at the trunk inlet and one at each of the three leaf
+outlets; reversing sinusoidal flow of period 200 steps).  The 3-D pipe (7.86 M
+particles, inlet and outlet tilted 20 and 35 degrees) is a second leg with the
+same measurements.
 
 The particle states the timed steps consume are prepared beforehand by running
-the real loop (update, then advection with the prescribed velocity) and keeping
-a device copy of each pre-update state; the timed region replays those states
-in order, so every timed step does the full work of a real step (events
-included) on inputs already resident in HBM, and nothing else.
+the real loop (update, then advection with the prescribed velocity) from the
+initial lattice and keeping a device copy of each pre-update state.  The timed
+window starts late in the run (step 445 of the network, at peak flow after two
+reversals; step 400 of the pipe), when the particles have left their initial
+lattice order; an early window (from step 5) is timed as well and reported as
+the drift.  The timed region replays the window's states in order, so every
+timed step does the full work of a real step (events included) on inputs
+already resident in HBM, and nothing else.
 
 Printed: one JSON line with the throughput, the roofline of the dominant
-kernel, the full-scan baseline and the FP64 CPU oracle timed on this host.
+kernel, the full-scan baseline, the legs, and the FP64 CPU oracle timed on this
+host (one thread and all threads; brute force and the local-cell method).
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
+import platform
 import sys
 import time
 
@@ -31,6 +43,17 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "buffer-update Mparticles/s, speedup vs full scan, % HBM peak; batched vs plain"
+
+DESCRIPTION = {
+    "tree3d": "3-D bifurcating pipe network (trunk R=0.05, daughters R=0.04, granddaughters R=0.03), dp=0.001, "
+              "4 bidirectional buffers (trunk inlet, 3 leaf outlets), reversing flow of period 200 steps, "
+              "brick-sparse grid",
+    "pipe3d": "3-D pipe R=0.05 L=1.0 dp=0.001, inlet tilted 20 deg about x, outlet 35 deg about y",
+    "bent_channel2d": "2-D bent channel W=0.2, dp=0.002, inlet at 30 deg, outlet at -45 deg",
+    "channel2d": "2-D straight channel 2.0 x 0.4, dp=0.02, axis-aligned inlet and outlet",
+}
+LATE_START = {"tree3d": 445, "pipe3d": 400, "bent_channel2d": 400, "channel2d": 100}
+BRICKS = {"tree3d": 3}
 
 
 def log(msg: str) -> None:
@@ -46,21 +69,16 @@ def rotation_of(S, spec, dim):
     return q
 
 
-def make_workload(name: str, order: str):
+def make_workload(name: str):
     import workloads as W
-    if name == "pipe3d":
-        return W.pipe3d(order=order)
-    if name == "bent_channel2d":
-        return W.bent_channel2d(order=order)
-    if name == "channel2d":
-        return W.channel2d(order=order)
-    raise SystemExit(f"unknown workload {name}")
+    return {"tree3d": W.tree3d, "pipe3d": W.pipe3d, "bent_channel2d": W.bent_channel2d,
+            "channel2d": W.channel2d}[name]()
 
 
 class Snapshot:
-    """Device copy of one pre-update state."""
+    """Device copy of one particle state."""
 
-    def __init__(self, dom, torch):
+    def __init__(self, dom):
         self.pos = [t.clone() for t in dom.pos]
         self.carried = [t.clone() for t in dom.carried]
         self.label = dom.label.clone()
@@ -69,13 +87,6 @@ class Snapshot:
 
     def tensors(self):
         return self.pos + self.carried + [self.label, self.id, self.n_dev]
-
-
-PATHS = {
-    "cells": "cell-list build + local-cell update",
-    "overlap": "cell-list build gathering the cover cells' particles + their update beside the scan and scatter",
-    "merged": "cell-list build classifying the cover cells' particles in its count pass + finalize beside the scan",
-}
 
 
 def phase_bytes(dim: int, n: int, n_cells: int, cand: int, g: int, d: int, n_carried: int):
@@ -92,7 +103,300 @@ def phase_bytes(dim: int, n: int, n_cells: int, cand: int, g: int, d: int, n_car
     }
 
 
-def sprinkler_leg(torch, np, S, W, Domain, log, steps: int = 40):
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    src_path = os.path.join(ROOT, "paper_2406_16786_amd", "csrc", "sphbuf.hip")
+    try:
+        t = json.load(open(path))
+        if t.get("source_sha256") != hashlib.sha256(open(src_path, "rb").read()).hexdigest():
+            return None
+        e = max(t["workloads"][workload]["kernels"][kernel], key=lambda r: r["grid"])
+        return int(e["fetch_bytes"] + e["write_bytes"])
+    except (OSError, KeyError, ValueError, TypeError):
+        return None
+
+
+def cover_candidates(np, S, wl, rots, pos, n):
+    """Particles of the buffers' cover cells (what the local path examines), from
+    the dense cover of each check region and the FP32 cell of every particle."""
+    dims = [int(math.ceil((wl.hi[c] - wl.lo[c]) / wl.cell_size)) for c in range(wl.dim)] + [1] * (3 - wl.dim)
+    lo32 = np.asarray(wl.lo[: wl.dim], dtype=np.float32)
+    ic = np.float32(1.0 / wl.cell_size)
+    key = np.zeros(n, dtype=np.int64)
+    mul = 1
+    for c in range(wl.dim):
+        t = ((pos[c][:n] - lo32[c]).astype(np.float32) * ic).astype(np.float32)
+        key += np.clip(np.floor(t), 0, dims[c] - 1).astype(np.int64) * mul
+        mul *= dims[c]
+    total = 0
+    for b, q in zip(wl.buffers, rots):
+        st, f, ln = S.sph_grid_cover(wl.dim, wl.lo, wl.cell_size, dims, b.origin, q, b.half, b.margin)
+        S.check(st, "grid_cover")
+        cells = np.concatenate([np.arange(a, a + l) for a, l in zip(f, ln)]) if len(f) else np.zeros(0, np.int64)
+        total += int(np.isin(key, cells).sum())
+    return total
+
+
+def single_leg(torch, np, S, W, Domain, wl, K, Wm, late, early, args):
+    """Prepare the run of one workload, then time its early and late windows
+    through the merged step (timed path), the cover-cell walk and the full scan."""
+    dev = torch.device("cuda:0")
+    t_leg = time.perf_counter()
+    rots = [rotation_of(S, b, wl.dim) for b in wl.buffers]
+    blog2 = BRICKS.get(wl.name, 0)
+    dom = Domain(wl.dim, wl.lo, wl.hi, wl.cell_size, wl.dp, wl.capacity, wl.pos, wl.carried, wl.label, wl.id,
+                 wl.n, wl.n, max_events=S.SPH_MAX_EVENTS_LIMIT, brick_log2=blog2, update_path="merged")
+    for b, q in zip(wl.buffers, rots):
+        dom.define(b.kind, b.origin, q, b.half, b.margin)
+    st_c, ctx_cells = S.sph_create(wl.dim, wl.lo, wl.hi, wl.cell_size, wl.dp, wl.capacity,
+                                   max_events=S.SPH_MAX_EVENTS_LIMIT, next_id=wl.n, stream=dom.stream.cuda_stream,
+                                   brick_log2=blog2, update_path=S.SPH_UPDATE_CELLS)
+    S.check(st_c, "create (cover-cell walk)")
+    for b, q in zip(wl.buffers, rots):
+        S.check(S.sph_buffer_define(ctx_cells, b.kind, b.origin, q, b.half, b.margin)[0], "define (cells)")
+    if blog2:  # both contexts fit their bricks to the same initial state
+        dom.fit()
+        S.check(S.sph_grid_fit(ctx_cells, dom.p), "grid_fit (cells)")
+    S.check(dom.identify(-1), "identify")
+    stream = dom.stream
+
+    # ---- the real loop, untimed: keep the states of both windows ----
+    windows = {"early": early, "late": late}
+    snaps = {k: [] for k in windows}
+    states = {k: [] for k in windows}
+    nlist = {k: [] for k in windows}
+    last = max(windows.values()) + Wm + K
+    gen = torch.Generator(device=dev)
+    for s in range(last):
+        keep = [k for k, s0 in windows.items() if s0 <= s < s0 + Wm + K]
+        for k in keep:
+            st, nid, nl = S.sph_state_get(dom.ctx)
+            states[k].append((nid, nl.copy()))
+            snaps[k].append(Snapshot(dom))
+        dom.build()
+        S.check(dom.update_async(), "update")
+        rs, r = dom.result()
+        S.check(r.status, f"update in preparation step {s}")
+        for k in keep:
+            nlist[k].append((r.n_before, r.n_after, r.n_generated, r.n_deleted))
+        n = r.n_after
+        gen.manual_seed(wl.seed_noise + s)
+        with torch.cuda.stream(stream):
+            p = [t[:n] for t in dom.pos]
+            noise = torch.randn((wl.dim, n), generator=gen, device=dev, dtype=torch.float32)
+            u = wl.velocity(torch, p, s, noise)
+            for c in range(wl.dim):
+                p[c].add_(u[c] * wl.dt)
+    stream.synchronize()
+    log(f"{wl.name}: prepared {last} steps in {time.perf_counter() - t_leg:.1f} s")
+
+    flush = torch.ones(1 << 28, dtype=torch.float32, device=dev)       # 1 GB, read-only flush
+    n_cells = int(S.sph_celllist_view(dom.ctx)[3])
+
+    def run_window(k):
+        work = [Snapshot(dom) for _ in range(Wm + K)]
+        parts = [S.particles_from_tensors(w.pos, w.carried, w.label, w.id, w.n_dev) for w in work]
+
+        def reset(ctx):
+            with torch.cuda.stream(stream):
+                for w, sn in zip(work, snaps[k]):
+                    for dst, src in zip(w.tensors(), sn.tensors()):
+                        dst.copy_(src)
+                # reading 1 GB evicts the 256 MB Infinity Cache without leaving dirty lines
+                float(flush.sum())
+            stream.synchronize()
+            S.check(S.sph_state_set(ctx, *states[k][0]), "state_set")
+
+        def replay(mode, ctx, profile):
+            reset(ctx)
+            S.check(S.sph_profile_enable(ctx, False), "profile")
+            for s in range(Wm):
+                if mode == "local":
+                    S.check(S.sph_celllist_build(ctx, parts[s]), "build")
+                    S.check(S.sph_buffer_update_async(ctx, parts[s]), "update")
+                else:
+                    S.check(S.sph_buffer_update_fullscan_async(ctx, parts[s]), "fullscan")
+            stream.synchronize()
+            if profile:
+                S.check(S.sph_profile_enable(ctx, True), "profile")
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            e0.record(stream)
+            for s in range(Wm, Wm + K):
+                if mode == "local":
+                    S.sph_celllist_build(ctx, parts[s])
+                    S.sph_buffer_update_async(ctx, parts[s])
+                else:
+                    S.sph_buffer_update_fullscan_async(ctx, parts[s])
+            e1.record(stream)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            ms = e0.elapsed_time(e1) / K
+            rs, r = S.sph_last_result(ctx)
+            S.check(r.status, f"{mode} replay")
+            assert (r.n_before, r.n_after, r.n_generated, r.n_deleted) == nlist[k][-1], (mode, k)
+            prof = None
+            if profile:
+                st, pms, pn = S.sph_profile_read(ctx, reset=True)
+                S.check(S.sph_profile_enable(ctx, False), "profile")
+                prof = {S.PHASES[i]: float(pms[i]) / max(1, int(pn[i])) for i in range(S.SPH_NPHASE) if pn[i] > 0}
+            return ms, wall / K * 1e3, prof
+
+        out = {}
+        out["ms_merged"], out["wall_merged"], _ = replay("local", dom.ctx, False)
+        out["ms_full"], _, _ = replay("fullscan", dom.ctx, False)
+        out["ms_cells"], _, _ = replay("local", ctx_cells, False)
+        if not args.no_profile_pass:
+            _, _, out["prof_merged"] = replay("local", dom.ctx, True)
+            _, _, out["prof_full"] = replay("fullscan", dom.ctx, True)
+            _, _, out["prof_cells"] = replay("local", ctx_cells, True)
+        out["n_mean"] = float(np.mean([x[0] for x in nlist[k][Wm:]]))
+        out["g_mean"] = float(np.mean([x[2] for x in nlist[k][Wm:]]))
+        out["d_mean"] = float(np.mean([x[3] for x in nlist[k][Wm:]]))
+        out["work"], out["parts"] = work, parts
+        return out
+
+    res = {}
+    for k in ("early", "late"):
+        res[k] = run_window(k)
+        if k == "early":  # its working copies are not needed any more
+            del res[k]["work"], res[k]["parts"]
+            del snaps[k][:]
+            torch.cuda.empty_cache()
+    L = res["late"]
+    # candidates of the local path on the first timed late state
+    s0 = snaps["late"][Wm]
+    n0 = int(s0.n_dev.item())
+    cand = cover_candidates(np, S, wl, rots, [t.cpu().numpy() for t in s0.pos], n0)
+    pb = phase_bytes(wl.dim, int(L["n_mean"]), n_cells, cand, int(L["g_mean"]), int(L["d_mean"]), len(wl.carried))
+    pb["count"] += 4 * cand   # the classifying count pass also reads each candidate's label
+    kernel_of = {"count": "k_count_cls", "finalize": "k_scan_finalize", "scatter": "k_scatter"}
+    step_bytes = pb["build"] + pb["classify"] + pb["finalize"]
+    ms = L["ms_merged"]
+    n_mean = L["n_mean"]
+    out = {"ms_per_step": round(ms, 5), "Mparticles_per_s": round(n_mean / (ms * 1e-3) / 1e6, 1),
+           "n_particles": int(n_mean), "cells": n_cells, "candidates_per_update": cand,
+           "events_per_step": {"generated": L["g_mean"], "deleted": L["d_mean"]},
+           "timed_steps": f"{late + Wm}..{late + Wm + K - 1} (warm-up {late}..{late + Wm - 1})",
+           "pct_hbm_peak_step": round(step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS * 100, 2),
+           "fullscan": {"ms_per_update": round(L["ms_full"], 5),
+                        "Mparticles_per_s": round(n_mean / (L["ms_full"] * 1e-3) / 1e6, 1)},
+           "speedup_step_vs_fullscan": round(L["ms_full"] / ms, 3)}
+    pm, pf, pc = L.get("prof_merged"), L.get("prof_full"), L.get("prof_cells")
+    if pm:
+        dom_phase = max(pm, key=lambda k: pm[k])
+        avg_ms = pm[dom_phase]
+        achieved = pb[dom_phase] / (avg_ms * 1e-3) / 1e9
+        kname = kernel_of.get(dom_phase, "k_" + dom_phase)
+        out["roofline"] = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                           "traffic": measured_traffic(wl.name, kname), "avg_launch_us": round(avg_ms * 1e3, 2),
+                           "algorithmic_bytes_per_launch": int(pb[dom_phase])}
+        out["phases_us"] = {k: round(v * 1e3, 2) for k, v in pm.items()}
+        out["phases_note"] = ("merged step: count = the classifying count pass, finalize = the finalize "
+                              "workgroups beside the scan tiles in one launch")
+    if pc:
+        t_upd = pc.get("classify", 0.0) + pc.get("finalize", 0.0)
+        t_full = pf["fullscan"] + pf.get("candidates", 0.0) + pf["finalize"] if pf else None
+        out["local_update_only"] = {
+            "ms": round(t_upd, 5), "Mparticles_per_s": round(n_mean / (t_upd * 1e-3) / 1e6, 1),
+            "fullscan_update_ms": round(t_full, 5) if t_full else None,
+            "speedup_vs_fullscan": round(t_full / t_upd, 2) if t_full else None,
+            "what": "cover-cell walk's update (classify + finalize) with the cell list already built, against "
+                    "the all-particle update (filter + candidates + finalize)"}
+    out["cover_cell_walk"] = {"ms_per_step": round(L["ms_cells"], 5),
+                              "Mparticles_per_s": round(n_mean / (L["ms_cells"] * 1e-3) / 1e6, 1),
+                              "phases_us": {k: round(v * 1e3, 2) for k, v in pc.items()} if pc else None}
+    if pf:
+        out["fullscan_phases_us"] = {k: round(v * 1e3, 2) for k, v in pf.items()}
+    E = res["early"]
+    out["early_window"] = {"timed_steps": f"{early + Wm}..{early + Wm + K - 1}",
+                           "ms_per_step": round(E["ms_merged"], 5),
+                           "Mparticles_per_s": round(E["n_mean"] / (E["ms_merged"] * 1e-3) / 1e6, 1),
+                           "phases_us": {k: round(v * 1e3, 2) for k, v in E["prof_merged"].items()}
+                           if E.get("prof_merged") else None,
+                           "cover_cell_walk_ms": round(E["ms_cells"], 5),
+                           "fullscan_ms": round(E["ms_full"], 5)}
+    out["drift_late_over_early"] = round(ms / E["ms_merged"], 3)
+    log(f"{wl.name}: late step {ms * 1e3:.1f} us (early {E['ms_merged'] * 1e3:.1f}), cover-cell walk "
+        f"{L['ms_cells'] * 1e3:.1f} us, full-scan update {L['ms_full'] * 1e3:.1f} us; phases (us): "
+        + ", ".join(f"{k} {v * 1e3:.1f}" for k, v in (pm or {}).items()))
+    leg = {"out": out, "dom": dom, "ctx_cells": ctx_cells, "snaps": snaps["late"], "states": states["late"],
+           "work": L["work"], "parts": L["parts"], "rots": rots, "stream": stream, "flush": flush}
+    return leg
+
+
+def close_leg(leg, S, torch):
+    S.sph_destroy(leg["ctx_cells"])
+    leg["dom"].close()
+    leg.clear()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def bc_and_neighbor_legs(torch, np, S, leg, wl, K, Wm, args):
+    """Boundary conditions and the solver's neighbour search on the pipe's states."""
+    out = {}
+    dom, snaps, states, work, parts, stream = (leg["dom"], leg["snaps"], leg["states"], leg["work"], leg["parts"],
+                                               leg["stream"])
+
+    def reset():
+        with torch.cuda.stream(stream):
+            for w, sn in zip(work, snaps):
+                for dst, src in zip(w.tensors(), sn.tensors()):
+                    dst.copy_(src)
+            float(leg["flush"].sum())
+        stream.synchronize()
+
+    if not args.no_bc and wl.dim == 3:
+        S.check(S.sph_set_fields(dom.ctx, [0, 1, 2], 4), "fields")
+        S.check(S.sph_buffer_set_bc(dom.ctx, 1, S.SPH_BC_VELOCITY, profile=S.SPH_PROFILE_PARABOLIC_R, u=1.0,
+                                    radius=0.05), "bc inlet")
+        S.check(S.sph_buffer_set_bc(dom.ctx, 2, S.SPH_BC_PRESSURE, p_b=0.0, rho0=1000.0, c0=10.0), "bc outlet")
+        reset()
+        S.check(S.sph_profile_enable(dom.ctx, True), "profile")
+        for s in range(Wm, Wm + K):
+            S.check(S.sph_state_set(dom.ctx, *states[s]), "state_set")
+            S.sph_celllist_build(dom.ctx, parts[s])
+            S.check(S.sph_buffer_apply_bc(dom.ctx, parts[s]), "apply_bc")
+        st_, pms, pn = S.sph_profile_read(dom.ctx, reset=True)
+        S.check(S.sph_profile_enable(dom.ctx, False), "profile")
+        bc_us = float(pms[S.PHASES.index("bc")]) / max(1, int(pn[S.PHASES.index("bc")])) * 1e3
+        n_buf = int(sum(states[Wm][1][:2]))
+        out["boundary_conditions"] = {
+            "apply_bc_us": round(bc_us, 2), "buffer_particles": n_buf,
+            "what": "velocity inlet (pipe profile) + pressure outlet (normal projection) on the labelled particles, "
+                    "one kernel over the local cells"}
+        log(f"apply_bc {bc_us:.1f} us on {n_buf} buffer particles")
+    if not args.no_neighbor:
+        dev = torch.device("cuda:0")
+        counts = torch.empty(wl.capacity, dtype=torch.int32, device=dev)
+        reset()
+        S.check(S.sph_profile_enable(dom.ctx, True), "profile")
+        n_nb = min(K, 5)
+        for s in range(Wm, Wm + n_nb):
+            S.check(S.sph_state_set(dom.ctx, *states[s]), "state_set")
+            S.sph_celllist_build(dom.ctx, parts[s])
+            S.check(S.sph_neighbor_count(dom.ctx, parts[s], wl.cell_size, counts.data_ptr()), "neighbor_count")
+        st_, pms, pn = S.sph_profile_read(dom.ctx, reset=True)
+        S.check(S.sph_profile_enable(dom.ctx, False), "profile")
+        nb_us = float(pms[S.PHASES.index("neighbor")]) / max(1, int(pn[S.PHASES.index("neighbor")])) * 1e3
+        n_last = int(snaps[Wm + n_nb - 1].n_dev.item())
+        mean_nb = float(counts[:n_last].double().mean().item())
+        out["neighbor_search"] = {
+            "us": round(nb_us, 1), "radius": "cell size (2h = 2.6 dp)", "mean_neighbors": round(mean_nb, 2),
+            "Mparticles_per_s": round(n_last / (nb_us * 1e-6) / 1e6, 1),
+            "what": "neighbour counts over the library's cell list (FP32 distances, FP64 in the 2^-16 band)"}
+        log(f"neighbor_count {nb_us:.1f} us, {mean_nb:.1f} neighbours per particle")
+    return out
+
+
+def sprinkler_leg(torch, np, S, W, Domain, steps: int = 40):
     """Rotating sprinkler (2-D) on a lawn of 2 M resting particles: per step the
     cell list, the update at the turning inlet, its velocity profile, the move of
     every particle with its own velocity and the turn of the buffer."""
@@ -108,38 +412,50 @@ def sprinkler_leg(torch, np, S, W, Domain, log, steps: int = 40):
     stream = d.stream
 
     def step():
+        # no host wait inside a step: the boundary conditions and the turn are
+        # enqueued, and every slot of the arrays is moved (those past the live count
+        # are never read)
         d.build()
         S.check(d.update_async(), "update")
         d.build()
-        S.check(d.apply_bc(), "apply_bc")
-        n = d.n()
+        S.check(d.apply_bc_async(), "apply_bc")
         with torch.cuda.stream(stream):
             for c in range(2):
-                d.pos[c][:n].add_(d.carried[c][:n] * wl.dt)
+                d.pos[c].add_(d.carried[c] * wl.dt)
         d.build()
-        S.check(d.rotate(1, (0.0, 0.0), m), "rotate")
+        S.check(d.rotate_async(1, (0.0, 0.0), m), "rotate")
 
     for _ in range(5):
         step()
     torch.cuda.synchronize()
-    S.check(S.sph_profile_enable(d.ctx, True), "profile")
     t0 = time.perf_counter()
     for _ in range(steps):
         step()
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / steps
+    S.check(d.bc_status(), "boundary conditions and turns")
+    S.check(d.result()[1].status, "update")
+    # the library's kernel time per step, in a second run with per-launch events
+    S.check(S.sph_profile_enable(d.ctx, True), "profile")
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
     st, pms, pn = S.sph_profile_read(d.ctx, reset=True)
     ph = {S.PHASES[i]: float(pms[i]) / max(1, int(pn[i])) * 1e3 for i in range(S.SPH_NPHASE) if pn[i] > 0}
+    per_step = sum(float(pms[i]) for i in range(S.SPH_NPHASE)) / steps * 1e3
     n = d.n()
     d.close()
-    log(f"sprinkler: N = {n}, rotate {ph.get('rotate', 0):.1f} us, bc {ph.get('bc', 0):.1f} us, "
-        f"wall {wall * 1e3:.2f} ms/step (with host syncs)")
+    log(f"sprinkler: N = {n}, rotate {ph.get('rotate', 0):.1f} us + cover {ph.get('cover', 0):.1f} us, "
+        f"bc {ph.get('bc', 0):.1f} us, "
+        f"wall {wall * 1e3:.3f} ms/step, library kernels {per_step:.1f} us/step")
     return {"n_particles": n, "steps": steps, "rotate_us": round(ph.get("rotate", 0.0), 2),
+            "turned_cover_us": round(ph.get("cover", 0.0), 2),
             "apply_bc_us": round(ph.get("bc", 0.0), 2), "phases_us": {k: round(v, 2) for k, v in ph.items()},
-            "wall_ms_per_step": round(wall * 1e3, 3)}
+            "wall_ms_per_step": round(wall * 1e3, 3), "library_kernels_us_per_step": round(per_step, 2),
+            "wall_over_kernels": round(wall * 1e6 / per_step, 2) if per_step > 0 else None}
 
 
-def batch_leg(torch, np, S, W, Domain, steps: int, warmup: int, log, fixed=None):
+def batch_leg(torch, np, S, W, Domain, steps: int, warmup: int, fixed=None):
     """64 hub-and-spoke domains: batched step (autotuned launch mode, graph replay)
     against a per-domain loop of plain launches, on the same prepared states.
     fixed = (mode, particles per count block) skips the autotuner."""
@@ -165,7 +481,7 @@ def batch_leg(torch, np, S, W, Domain, steps: int, warmup: int, log, fixed=None)
     gen = torch.Generator(device=dev)
     for s in range(n_snap):
         states.append([S.sph_state_get(d.ctx)[1:] for d in doms])
-        snaps.append([Snapshot(d, torch) for d in doms])
+        snaps.append([Snapshot(d) for d in doms])
         for d in doms:
             d.build()
             S.check(d.update_async(), "update")
@@ -180,7 +496,7 @@ def batch_leg(torch, np, S, W, Domain, steps: int, warmup: int, log, fixed=None)
                 for c in range(wl.dim):
                     p[c].add_(u[c] * wl.dt)
     stream.synchronize()
-    work = [[Snapshot(d, torch) for d in doms] for _ in range(n_snap)]
+    work = [[Snapshot(d) for d in doms] for _ in range(n_snap)]
     parts = [[S.particles_from_tensors(w.pos, w.carried, w.label, w.id, w.n_dev) for w in ws] for ws in work]
     flush = torch.ones(1 << 28, dtype=torch.float32, device=dev)
     bstream = torch.cuda.Stream()
@@ -250,51 +566,140 @@ def batch_leg(torch, np, S, W, Domain, steps: int, warmup: int, log, fixed=None)
     torch.cuda.synchronize()
     ms_batch = e0.elapsed_time(e1) / steps
     check_final()
+    # per-launch times of the batched phases (launch mode, same states)
+    reset()
+    for s in range(warmup):
+        S.check(S.sph_batch_set_mode(batches[s], S.SPH_BATCH_KERNELS), "mode")
+        S.check(S.sph_batch_step(batches[s]), "batch step")
+    for s in range(warmup, n_snap):
+        S.check(S.sph_batch_set_mode(batches[s], S.SPH_BATCH_KERNELS), "mode")
+        S.check(S.sph_batch_profile_enable(batches[s], True), "profile")
+        S.check(S.sph_batch_step(batches[s]), "batch step")
+    torch.cuda.synchronize()
+    tot = np.zeros(5)
+    cnt = np.zeros(5, dtype=np.int64)
+    for s in range(warmup, n_snap):
+        st, pms, pn = S.sph_batch_profile_read(batches[s])
+        tot += pms
+        cnt += pn
+    ph = {S.BATCH_PHASES[i]: tot[i] / max(1, cnt[i]) for i in range(5) if cnt[i] > 0}
+    check_final()
     n_total = sum(w.n for w in wls)
+    count_bytes = sum(4 * w.dim * w.n for w in wls)
+    step_bytes = sum((4 * w.dim + 4) * w.n for w in wls)
+    roof = None
+    if "count" in ph:
+        ach = count_bytes / (ph["count"] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": "kb_count", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "avg_launch_us": round(ph["count"] * 1e3, 2), "algorithmic_bytes_per_launch": int(count_bytes)}
     for b in batches:
         S.sph_batch_destroy(b)
     for d in doms:
         d.close()
     log(f"batch: loop {ms_loop * 1e3:.0f} us/step, batched {ms_batch * 1e3:.0f} us/step "
-        f"(mode {'graph' if mode == 1 else 'kernels'}, {ppb} particles per count block)")
+        f"(mode {'graph' if mode == 1 else 'kernels'}, {ppb} particles per count block); phases (us): "
+        + ", ".join(f"{k} {v * 1e3:.1f}" for k, v in ph.items()))
     return {"domains": len(wls), "n_particles": n_total, "buffers": sum(len(w.buffers) for w in wls),
             "ms_per_step_batched": round(ms_batch, 4), "ms_per_step_loop": round(ms_loop, 4),
             "speedup_batched_vs_loop": round(ms_loop / ms_batch, 2),
             "Mparticles_per_s_batched": round(n_total / (ms_batch * 1e-3) / 1e6, 1),
             "Mparticles_per_s_loop": round(n_total / (ms_loop * 1e-3) / 1e6, 1),
+            "pct_hbm_peak_build": round(step_bytes / (ms_batch * 1e-3) / 1e9 / HBM_PEAK_GBS * 100, 2),
+            "phases_us": {k: round(v * 1e3, 2) for k, v in ph.items()}, "roofline": roof,
             "tuned": {"mode": "graph" if mode == 1 else "kernels", "particles_per_count_block": ppb}}
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(np, leg, wl, Wm, budget_s: float):
+    """The FP64 oracle on this host's cores, on the first timed state of the
+    headline workload: brute force on one thread and on all threads, and the
+    paper's local-cell method (cell list given) on all threads."""
+    import oracle
+    sn, nid = leg["snaps"][Wm], int(leg["states"][Wm][0])
+    nl_in = [int(x) for x in leg["states"][Wm][1][: len(wl.buffers)]]
+    pos = [t.cpu().numpy() for t in sn.pos]
+    car = [t.cpu().numpy() for t in sn.carried]
+    lab = sn.label.cpu().numpy()
+    ids = sn.id.cpu().numpy()
+    n0 = int(sn.n_dev.item())
+    ob = []
+    for b in wl.buffers:
+        q = oracle.rotation_2d(b.angle) if wl.dim == 2 else oracle.rotation_from_direction(b.direction)
+        ob.append(oracle.Buffer(b.kind, b.origin, q, b.half, b.margin))
+
+    def fresh():
+        return oracle.State(wl.dim, [a.copy() for a in pos], [a.copy() for a in car], lab.copy(), ids.copy(), n0, nid)
+
+    def timed(fn, seconds, max_n=50):
+        times = []
+        t_start = time.perf_counter()
+        while not times or (time.perf_counter() - t_start < seconds and len(times) < max_n):
+            st = fresh()
+            t0 = time.perf_counter()
+            res = fn(st)
+            times.append(time.perf_counter() - t0)
+            assert res.status == 0, res.status
+        return float(np.median(times)), len(times)
+
+    n_all = oracle.set_threads(0)
+    oracle.set_threads(1)
+    t1, k1 = timed(lambda st: oracle.update(ob, st), 0.35 * budget_s)
+    oracle.set_threads(n_all)
+    ta, ka = timed(lambda st: oracle.update(ob, st), 0.3 * budget_s)
+    dims = [int(math.ceil((wl.hi[c] - wl.lo[c]) / wl.cell_size)) for c in range(wl.dim)]
+    lo32 = np.float32(wl.lo[: wl.dim])
+    inv = np.float32(1.0 / wl.cell_size)
+    t0 = time.perf_counter()
+    start, idx = oracle.cell_list(wl.dim, lo32, inv, dims, pos[0][:n0], pos[1][:n0], pos[2][:n0] if wl.dim == 3 else None)
+    t_cells = time.perf_counter() - t0
+    tl, kl = timed(lambda st: oracle.update_local(ob, st, lo32, inv, dims, start, idx, nl_in), 0.2 * budget_s)
+    del start, idx
+    log(f"cpu oracle ({n_all} threads, {cpu_model()}): brute 1T {t1 * 1e3:.0f} ms, brute {n_all}T "
+        f"{ta * 1e3:.0f} ms, local-cell {tl * 1e3:.1f} ms (+ cell list {t_cells * 1e3:.0f} ms, 1T)")
+    return {"value": round(n0 / ta / 1e6, 2), "unit": "Mparticles/s", "cores": n_all, "kind": "oracle",
+            "sample": f"{ka} FP64 brute-force oracle updates of the first timed state of {wl.name} (N = {n0}) on "
+                      f"{n_all} threads, median {ta * 1e3:.0f} ms",
+            "cpu_model": cpu_model(), "os_cpu_count": os.cpu_count(),
+            "one_thread": {"value": round(n0 / t1 / 1e6, 2), "median_ms": round(t1 * 1e3, 1), "updates": k1},
+            "all_threads": {"value": round(n0 / ta / 1e6, 2), "median_ms": round(ta * 1e3, 1), "updates": ka},
+            "local_cell_all_threads": {"value": round(n0 / tl / 1e6, 2), "median_ms": round(tl * 1e3, 2),
+                                       "updates": kl, "cell_list_build_ms_one_thread": round(t_cells * 1e3, 1),
+                                       "what": "the paper's method on the CPU: candidates only from the cells "
+                                               "near each check region of a dense FP32 cell list (given)"}}
 
 
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="pipe3d", choices=["pipe3d", "bent_channel2d", "channel2d"])
-    ap.add_argument("--order", default="lattice", choices=["lattice", "blocked"])
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="tree3d", choices=sorted(DESCRIPTION))
+    ap.add_argument("--late", type=int, default=None, help="first state of the timed (late) window")
+    ap.add_argument("--early", type=int, default=5, help="first state of the early window")
+    ap.add_argument("--cpu-seconds", type=float, default=24.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile-pass", action="store_true")
+    ap.add_argument("--no-pipe", action="store_true", help="skip the 3-D pipe leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-domain batched leg")
     ap.add_argument("--no-bc", action="store_true", help="skip the boundary-condition leg")
     ap.add_argument("--no-sprinkler", action="store_true", help="skip the rotating-sprinkler leg")
     ap.add_argument("--no-neighbor", action="store_true", help="skip the neighbour-search leg")
-    ap.add_argument("--build", default=None, choices=["split", "fused"],
-                    help="cell-list build variant (default: the library's)")
-    ap.add_argument("--update", default="merged", choices=["cells", "overlap", "merged"],
-                    help="update path of the timed step (the cover-cell walk is timed beside it as well)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus_requested": args.gpus}), flush=True)
         return 2
 
-    if args.build:
-        os.environ["SPHBUF_BUILD"] = args.build
-    if args.update in ("overlap", "merged"):
-        os.environ["SPHBUF_UPDATE"] = args.update
-    elif args.update == "cells":
-        os.environ.pop("SPHBUF_UPDATE", None)
     import numpy as np
     import torch
 
@@ -303,333 +708,64 @@ def main() -> int:
     from paper_2406_16786_amd.domain import Domain
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    dev = torch.device("cuda:0")
     K, Wm = args.steps, args.warmup
     t_all = time.perf_counter()
+    late = args.late if args.late is not None else LATE_START[args.workload]
 
-    wl = make_workload(args.workload, args.order)
-    log(f"workload {wl.name}: N = {wl.n}, dim {wl.dim}, capacity {wl.capacity}")
-    rots = [rotation_of(S, b, wl.dim) for b in wl.buffers]
-    dom = Domain(wl.dim, wl.lo, wl.hi, wl.cell_size, wl.dp, wl.capacity, wl.pos, wl.carried, wl.label, wl.id,
-                 wl.n, wl.n, max_events=S.SPH_MAX_EVENTS_LIMIT)
-    for b, q in zip(wl.buffers, rots):
-        dom.define(b.kind, b.origin, q, b.half, b.margin)
-    S.check(dom.identify(-1), "identify")
-    stream = dom.stream
-    # the cover-cell walk (the library's default update) replays the same states
-    # through a context of its own, on the same stream
-    ctx_cells = None
-    if args.update != "cells":
-        saved = os.environ.pop("SPHBUF_UPDATE", None)
-        st_c, ctx_cells = S.sph_create(wl.dim, wl.lo, wl.hi, wl.cell_size, wl.dp, wl.capacity,
-                                       max_events=S.SPH_MAX_EVENTS_LIMIT, next_id=wl.n, stream=stream.cuda_stream)
-        S.check(st_c, "create (cover-cell walk)")
-        if saved is not None:
-            os.environ["SPHBUF_UPDATE"] = saved
-        for b, q in zip(wl.buffers, rots):
-            st_c, _ = S.sph_buffer_define(ctx_cells, b.kind, b.origin, q, b.half, b.margin)
-            S.check(st_c, "define (cover-cell walk)")
-
-    # ---- prepare the states the timed steps consume (the real loop, untimed) ----
-    n_snap = Wm + K
-    snaps, states, n_list = [], [], []
-    gen = torch.Generator(device=dev)
-    for s in range(n_snap):
-        st, nid, nl = S.sph_state_get(dom.ctx)
-        states.append((nid, nl.copy()))
-        snaps.append(Snapshot(dom, torch))
-        dom.build()
-        S.check(dom.update_async(), "update")
-        rs, r = dom.result()
-        S.check(r.status, f"update in preparation step {s}")
-        n_list.append((r.n_before, r.n_after, r.n_generated, r.n_deleted))
-        n = r.n_after
-        gen.manual_seed(wl.seed_noise + s)
-        with torch.cuda.stream(stream):
-            p = [t[:n] for t in dom.pos]
-            noise = torch.randn((wl.dim, n), generator=gen, device=dev, dtype=torch.float32)
-            u = wl.velocity(torch, p, s, noise)
-            for c in range(wl.dim):
-                p[c].add_(u[c] * wl.dt)
-    stream.synchronize()
-    log(f"prepared {n_snap} states in {time.perf_counter() - t_all:.1f} s; events/step "
-        f"G={np.mean([x[2] for x in n_list]):.0f} D={np.mean([x[3] for x in n_list]):.0f}")
-
-    # ---- candidate count of the local path (for the classify bytes) ----
-    cand = 0
-    # rebuild on the first state to read its cell starts
-    work0 = Snapshot(dom, torch)
-    for dst, src in zip(work0.tensors(), snaps[0].tensors()):
-        dst.copy_(src)
-    p0 = S.particles_from_tensors(work0.pos, work0.carried, work0.label, work0.id, work0.n_dev)
-    S.check(S.sph_celllist_build(dom.ctx, p0), "build")
-    _, cs_ptr, _, n_cells, dims = S.sph_celllist_view(dom.ctx)  # (completes a merged build's cell list)
-    stream.synchronize()
-    import ctypes
-    hip = ctypes.CDLL("libamdhip64.so")
-    host_start = np.zeros(n_cells + 1, dtype=np.int32)
-    hip.hipMemcpy(ctypes.c_void_p(host_start.ctypes.data), ctypes.c_void_p(cs_ptr),
-                  ctypes.c_size_t(host_start.nbytes), 2)
-    for b, q in zip(wl.buffers, rots):
-        st, f, ln = S.sph_grid_cover(wl.dim, wl.lo, wl.cell_size, dims, b.origin, q, b.half, b.margin)
-        cand += int(np.sum(host_start[f + ln] - host_start[f]))
-    del work0, p0
-
-    # ---- working copies + replay ----
-    work = [Snapshot(dom, torch) for _ in range(n_snap)]
-    parts = [S.particles_from_tensors(w.pos, w.carried, w.label, w.id, w.n_dev) for w in work]
-    flush = torch.ones(1 << 28, dtype=torch.float32, device=dev)       # 1 GB, read-only flush
-
-    def reset_work(ctx=None):
-        ctx = ctx or dom.ctx
-        with torch.cuda.stream(stream):
-            for w, s in zip(work, snaps):
-                for dst, src in zip(w.tensors(), s.tensors()):
-                    dst.copy_(src)
-            # Reading 1 GB evicts the 256 MB Infinity Cache without leaving dirty lines,
-            # so the timed steps neither hit in it nor pay for write-backs of this setup.
-            float(flush.sum())
-        stream.synchronize()
-        nid, nl = states[0]
-        S.check(S.sph_state_set(ctx, nid, nl), "state_set")
-
-    def replay(mode: str, profile: bool, ctx=None):
-        ctx = ctx or dom.ctx
-        reset_work(ctx)
-        S.check(S.sph_profile_enable(ctx, False), "profile")
-        for s in range(Wm):
-            if mode == "local":
-                S.check(S.sph_celllist_build(ctx, parts[s]), "build")
-                S.check(S.sph_buffer_update_async(ctx, parts[s]), "update")
-            else:
-                S.check(S.sph_buffer_update_fullscan_async(ctx, parts[s]), "fullscan")
-        stream.synchronize()
-        if profile:
-            S.check(S.sph_profile_enable(ctx, True), "profile")
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        e0.record(stream)
-        for s in range(Wm, Wm + K):
-            if mode == "local":
-                S.sph_celllist_build(ctx, parts[s])
-                S.sph_buffer_update_async(ctx, parts[s])
-            else:
-                S.sph_buffer_update_fullscan_async(ctx, parts[s])
-        e1.record(stream)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        ms = e0.elapsed_time(e1) / K
-        rs, r = S.sph_last_result(ctx)
-        S.check(r.status, f"{mode} replay")
-        expect = n_list[Wm + K - 1]
-        assert (r.n_before, r.n_after, r.n_generated, r.n_deleted) == expect, (mode, expect, r.n_after)
-        prof = None
-        if profile:
-            st, pms, pn = S.sph_profile_read(ctx, reset=True)
-            S.check(S.sph_profile_enable(ctx, False), "profile")
-            prof = {S.PHASES[i]: (float(pms[i]) / max(1, int(pn[i])), int(pn[i])) for i in range(S.SPH_NPHASE)
-                    if pn[i] > 0}
-        return ms, wall / K * 1e3, prof
-
-    ms_local, wall_local, _ = replay("local", False)
-    ms_full, wall_full, _ = replay("fullscan", False)
-    ms_cells = prof_cells = None
-    if ctx_cells is not None:
-        ms_cells, _, _ = replay("local", False, ctx_cells)
-    prof_local = prof_full = None
-    if not args.no_profile_pass:
-        _, _, prof_local = replay("local", True)
-        _, _, prof_full = replay("fullscan", True)
-        if ctx_cells is not None:
-            _, _, prof_cells = replay("local", True, ctx_cells)
-    if ctx_cells is None:
-        ms_cells, prof_cells = ms_local, prof_local
-    else:
-        log(f"cover-cell walk step {ms_cells * 1e3:.1f} us; phases (us): "
-            + ", ".join(f"{k} {v[0] * 1e3:.1f}" for k, v in (prof_cells or {}).items()))
-    log(f"local step {ms_local * 1e3:.1f} us (wall {wall_local * 1e3:.1f} us); "
-        f"full-scan update {ms_full * 1e3:.1f} us")
-    log(f"local phases (us): " + ", ".join(f"{k} {v[0] * 1e3:.1f}" for k, v in (prof_local or {}).items()))
-    log(f"full phases (us): " + ", ".join(f"{k} {v[0] * 1e3:.1f}" for k, v in (prof_full or {}).items()))
-
-    n_mean = float(np.mean([x[0] for x in n_list[Wm:]]))
-    g_mean = float(np.mean([x[2] for x in n_list[Wm:]]))
-    d_mean = float(np.mean([x[3] for x in n_list[Wm:]]))
-    pb = phase_bytes(wl.dim, int(n_mean), int(n_cells), cand, int(g_mean), int(d_mean), len(wl.carried))
-    merged = args.update == "merged"
-    if merged:
-        # the classifying count pass also reads the label of each candidate (its
-        # position is the one the count already read)
-        pb["count"] += 4 * cand
-    kernel_of = {"count": "count_cls" if merged else "count", "finalize": "scan_finalize" if merged else "finalize"}
-    step_bytes = pb["build"] + pb["classify"] + pb["finalize"]
-    upd_local_bytes = pb["classify"] + pb["finalize"]
-
-    def measured_traffic(kernel: str):
-        """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-        was taken on the current kernel source (else None)."""
-        import hashlib
-        path = os.path.join(ROOT, "profiles", "traffic.json")
-        src_path = os.path.join(ROOT, "paper_2406_16786_amd", "csrc", "sphbuf.hip")
-        try:
-            t = json.load(open(path))
-            if t.get("source_sha256") != hashlib.sha256(open(src_path, "rb").read()).hexdigest():
-                return None
-            if t.get("workload") != wl.name:
-                return None
-            e = max(t["kernels"]["k_" + kernel], key=lambda r: r["grid"])
-            return int(e["fetch_bytes"] + e["write_bytes"])
-        except (OSError, KeyError, ValueError):
-            return None
-
-    roof = None
-    if prof_local:
-        dom_phase = max((k for k in prof_local if k != "fullscan"), key=lambda k: prof_local[k][0])
-        avg_ms = prof_local[dom_phase][0]
-        achieved = pb[dom_phase] / (avg_ms * 1e-3) / 1e9
-        kname = kernel_of.get(dom_phase, dom_phase)
-        roof = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kname),
-                "avg_launch_us": round(avg_ms * 1e3, 2), "algorithmic_bytes_per_launch": int(pb[dom_phase])}
-
-    t_upd_local = None
-    if prof_cells:  # the update of the cover-cell walk: classify + finalize
-        t_upd_local = (prof_cells.get("classify", (0, 0))[0] + prof_cells.get("finalize", (0, 0))[0])
-    value = n_mean / (ms_local * 1e-3) / 1e6
+    t0 = time.perf_counter()
+    wl = make_workload(args.workload)
+    log(f"workload {wl.name}: N = {wl.n}, dim {wl.dim}, capacity {wl.capacity} "
+        f"(generated in {time.perf_counter() - t0:.1f} s)")
+    leg = single_leg(torch, np, S, W, Domain, wl, K, Wm, late, args.early, args)
+    h = leg["out"]
     out = {
         "metric": METRIC,
-        "value": round(value, 1),
+        "value": h["Mparticles_per_s"],
         "unit": "Mparticles/s",
         "n_gpus": 1,
         "steps": K,
         "warmup": Wm,
-        "ms_per_step": round(ms_local, 5),
+        "ms_per_step": h["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32 (f64 recheck in the guard band)",
         "data": "synthetic",
-        "config": {"workload": f"{wl.name} (3-D pipe R=0.05 L=1.0 dp=0.001, inlet 20 deg, outlet 35 deg)"
-                   if wl.name == "pipe3d" else wl.name,
-                   "n_particles": int(n_mean), "dim": wl.dim, "buffers": len(wl.buffers), "cells": int(n_cells),
-                   "candidates_per_update": cand, "events_per_step": {"generated": g_mean, "deleted": d_mean},
-                   "particle_order": args.order, "path": PATHS[args.update or "cells"]},
-        "pct_hbm_peak_step": round(step_bytes / (ms_local * 1e-3) / 1e9 / HBM_PEAK_GBS * 100, 2),
-        "fullscan": {"ms_per_update": round(ms_full, 5),
-                     "Mparticles_per_s": round(n_mean / (ms_full * 1e-3) / 1e6, 1)},
-        "speedup_step_vs_fullscan": round(ms_full / ms_local, 3),
-        "roofline": roof,
+        "config": {"workload": f"{wl.name}: {DESCRIPTION[wl.name]}", "n_particles": h["n_particles"],
+                   "dim": wl.dim, "buffers": len(wl.buffers), "cells": h["cells"],
+                   "candidates_per_update": h["candidates_per_update"], "events_per_step": h["events_per_step"],
+                   "timed_steps": h["timed_steps"],
+                   "path": "merged step: cell-list build classifying the cover cells' particles in its count "
+                           "pass + finalize beside the scan, then the scatter"},
+        "roofline": h.get("roofline"),
     }
-    if t_upd_local:
-        # the paper's framing: the solver rebuilds the cell list every step anyway, so the
-        # update with local cells (classify + finalize) against the all-particle update
-        # (full classify + finalize)
-        t_upd_full = (prof_full["fullscan"][0] + prof_full.get("candidates", (0.0, 0))[0] + prof_full["finalize"][0]
-                      if prof_full else None)
-        out["local_update_only"] = {
-            "ms": round(t_upd_local, 5),
-            "Mparticles_per_s": round(n_mean / (t_upd_local * 1e-3) / 1e6, 1),
-            "fullscan_update_ms": round(t_upd_full, 5) if t_upd_full else None,
-            "speedup_vs_fullscan": round(t_upd_full / t_upd_local, 2) if t_upd_full else None,
-            "speedup_classify_vs_fullscan": round((prof_full["fullscan"][0] + prof_full.get("candidates", (0.0, 0))[0])
-                                                  / prof_cells["classify"][0], 2)
-            if prof_full and "classify" in prof_cells else None}
-    if prof_local:
-        out["phases_us"] = {k: round(v[0] * 1e3, 2) for k, v in prof_local.items()}
-        if merged:
-            out["phases_note"] = ("merged step: count = the classifying count pass, finalize = the finalize "
-                                  "workgroups beside the scan tiles in one launch")
-    if ctx_cells is not None:
-        out["cover_cell_walk"] = {
-            "ms_per_step": round(ms_cells, 5), "Mparticles_per_s": round(n_mean / (ms_cells * 1e-3) / 1e6, 1),
-            "path": PATHS["cells"],
-            "phases_us": {k: round(v[0] * 1e3, 2) for k, v in prof_cells.items()} if prof_cells else None,
-            "speedup_of_timed_step": round(ms_cells / ms_local, 3)}
-    if prof_full:
-        out["fullscan_phases_us"] = {k: round(v[0] * 1e3, 2) for k, v in prof_full.items()}
-
-    # ---- boundary conditions on the same states: velocity inlet, pressure outlet ----
-    if not args.no_bc and wl.dim == 3:
-        S.check(S.sph_set_fields(dom.ctx, [0, 1, 2], 4), "fields")
-        S.check(S.sph_buffer_set_bc(dom.ctx, 1, S.SPH_BC_VELOCITY, profile=S.SPH_PROFILE_PARABOLIC_R, u=1.0,
-                                    radius=0.05), "bc inlet")
-        S.check(S.sph_buffer_set_bc(dom.ctx, 2, S.SPH_BC_PRESSURE, p_b=0.0, rho0=1000.0, c0=10.0), "bc outlet")
-        reset_work()
-        S.check(S.sph_profile_enable(dom.ctx, True), "profile")
-        for s in range(Wm, Wm + K):
-            S.check(S.sph_state_set(dom.ctx, *states[s]), "state_set")
-            S.sph_celllist_build(dom.ctx, parts[s])
-            S.check(S.sph_buffer_apply_bc(dom.ctx, parts[s]), "apply_bc")
-        st_, pms, pn = S.sph_profile_read(dom.ctx, reset=True)
-        S.check(S.sph_profile_enable(dom.ctx, False), "profile")
-        bc_us = float(pms[S.PHASES.index("bc")]) / max(1, int(pn[S.PHASES.index("bc")])) * 1e3
-        n_buf = int(sum(states[Wm][1][:2]))
-        out["boundary_conditions"] = {
-            "apply_bc_us": round(bc_us, 2), "buffer_particles": n_buf,
-            "what": "velocity inlet (pipe profile) + pressure outlet (normal projection) on the labelled particles, "
-                    "one kernel over the local cells"}
-        log(f"apply_bc {bc_us:.1f} us on {n_buf} buffer particles")
-    # ---- the cell list reused by the solver's neighbour search (radius = cell size = 2h) ----
-    if not args.no_neighbor:
-        counts = torch.empty(wl.capacity, dtype=torch.int32, device=dev)
-        reset_work()
-        S.check(S.sph_profile_enable(dom.ctx, True), "profile")
-        n_nb = min(K, 5)
-        for s in range(Wm, Wm + n_nb):
-            S.check(S.sph_state_set(dom.ctx, *states[s]), "state_set")
-            S.sph_celllist_build(dom.ctx, parts[s])
-            S.check(S.sph_neighbor_count(dom.ctx, parts[s], wl.cell_size, counts.data_ptr()), "neighbor_count")
-        st_, pms, pn = S.sph_profile_read(dom.ctx, reset=True)
-        S.check(S.sph_profile_enable(dom.ctx, False), "profile")
-        nb_us = float(pms[S.PHASES.index("neighbor")]) / max(1, int(pn[S.PHASES.index("neighbor")])) * 1e3
-        n_last = int(snaps[Wm + n_nb - 1].n_dev.item())
-        mean_nb = float(counts[:n_last].double().mean().item())
-        out["neighbor_search"] = {
-            "us": round(nb_us, 1), "radius": "cell size (2h = 2.6 dp)", "mean_neighbors": round(mean_nb, 2),
-            "Mparticles_per_s": round(n_last / (nb_us * 1e-6) / 1e6, 1),
-            "what": "neighbour counts over the library's cell list (FP32 distances, FP64 in the 2^-16 band)"}
-        log(f"neighbor_count {nb_us:.1f} us, {mean_nb:.1f} neighbours per particle")
-    if not args.no_sprinkler:
-        out["sprinkler"] = sprinkler_leg(torch, np, S, W, Domain, log)
-
-    # ---- many domains: batched step against a per-domain launch loop ----
-    if not args.no_batch:
-        out["batched"] = batch_leg(torch, np, S, W, Domain, max(4, K // 2), max(1, Wm // 2), log)
-
-    # ---- CPU baseline: the FP64 oracle on this host, bounded sample ----
+    for k, v in h.items():
+        if k not in ("ms_per_step", "Mparticles_per_s", "n_particles", "cells", "candidates_per_update",
+                     "events_per_step", "timed_steps", "roofline"):
+            out[k] = v
     if not args.no_cpu_baseline:
-        import oracle
-        pos = [t.cpu().numpy() for t in snaps[Wm].pos]
-        car = [t.cpu().numpy() for t in snaps[Wm].carried]
-        lab = snaps[Wm].label.cpu().numpy()
-        ids = snaps[Wm].id.cpu().numpy()
-        n0 = int(snaps[Wm].n_dev.item())
-        ob = []
-        for b in wl.buffers:
-            q = oracle.rotation_2d(b.angle) if wl.dim == 2 else oracle.rotation_from_direction(b.direction)
-            ob.append(oracle.Buffer(b.kind, b.origin, q, b.half, b.margin))
-        times = []
-        t_start = time.perf_counter()
-        while not times or (time.perf_counter() - t_start < args.cpu_seconds and len(times) < 50):
-            st_o = oracle.State(wl.dim, [a.copy() for a in pos], [a.copy() for a in car], lab.copy(), ids.copy(),
-                                n0, int(states[Wm][0]))
-            t0 = time.perf_counter()
-            res = oracle.update(ob, st_o)
-            times.append(time.perf_counter() - t0)
-            assert res.status == 0
-        t_o = float(np.median(times))
-        out["cpu_baseline"] = {"value": round(n0 / t_o / 1e6, 2), "unit": "Mparticles/s", "cores": 1,
-                               "kind": "oracle",
-                               "sample": f"{len(times)} FP64 brute-force oracle updates of the first timed state "
-                                         f"(N = {n0}), median {t_o * 1e3:.0f} ms; single-threaded C"}
-        log(f"cpu oracle: {len(times)} updates, median {t_o * 1e3:.1f} ms")
+        out["cpu_baseline"] = cpu_baseline(np, leg, wl, Wm, args.cpu_seconds)
+    close_leg(leg, S, torch)
+    del wl
+
+    out["legs"] = {}
+    if not args.no_pipe and args.workload != "pipe3d":
+        t0 = time.perf_counter()
+        wp = make_workload("pipe3d")
+        log(f"workload pipe3d: N = {wp.n} (generated in {time.perf_counter() - t0:.1f} s)")
+        lp = single_leg(torch, np, S, W, Domain, wp, K, Wm, LATE_START["pipe3d"], args.early, args)
+        o = lp["out"]
+        o["workload"] = f"pipe3d: {DESCRIPTION['pipe3d']}"
+        out["legs"]["pipe3d"] = o
+        out.update(bc_and_neighbor_legs(torch, np, S, lp, wp, K, Wm, args))
+        close_leg(lp, S, torch)
+        del wp
+    if not args.no_sprinkler:
+        out["sprinkler"] = sprinkler_leg(torch, np, S, W, Domain)
+    if not args.no_batch:
+        out["batched"] = batch_leg(torch, np, S, W, Domain, max(4, K // 2), max(1, Wm // 2))
     log(f"total {time.perf_counter() - t_all:.1f} s")
     print(json.dumps(out), flush=True)
-    if ctx_cells is not None:
-        S.sph_destroy(ctx_cells)
-    dom.close()
     return 0
 
 

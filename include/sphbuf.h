@@ -295,12 +295,28 @@ sph_status sph_buffer_apply_bc(sph_ctx *ctx, sph_particles *p);
  * check region moves to C + m (r - C), its velocity (if velocity fields are set)
  * to m v, both in FP64 rounded to FP32 once; then the frame follows,
  * O' <- C + m (O' - C), Q <- Q m^T, and the cell cover of the check region is
- * recomputed.  Needs a cell list of the current positions; invalidates it
- * (rebuild before the next update).  Sync.  Errors: SPH_ERR_ROTATION (m not
- * orthonormal), SPH_ERR_OVERLAP (the turned check region would meet another
- * buffer's: nothing changes), SPH_ERR_CFL as for sph_buffer_apply_bc. */
+ * recomputed on the device (into the buffer's own range of the run lists, sized
+ * at definition for any orientation; no allocation, no host work on the cells).
+ * Needs a cell list of the current positions; invalidates it (rebuild before the
+ * next update).  Sync: returns the outcome of the turn.  Errors: SPH_ERR_ROTATION
+ * (m not orthonormal), SPH_ERR_OVERLAP (the turned check region would meet
+ * another buffer's: nothing changes), SPH_ERR_CFL as for sph_buffer_apply_bc. */
 sph_status sph_buffer_rotate(sph_ctx *ctx, sph_particles *p, int32_t buffer_id, const double center[3],
                              const double m[9]);
+/* The same, enqueue only (argument, rotation and overlap errors are still
+ * returned at once); the CFL outcome is read later with sph_last_bc_status. */
+sph_status sph_buffer_rotate_async(sph_ctx *ctx, sph_particles *p, int32_t buffer_id, const double center[3],
+                                   const double m[9]);
+/* sph_buffer_apply_bc, enqueue only; outcome with sph_last_bc_status. */
+sph_status sph_buffer_apply_bc_async(sph_ctx *ctx, sph_particles *p);
+/* Sync: outcome of the last boundary-condition pass or turn enqueued (SPH_OK or
+ * SPH_ERR_CFL). */
+sph_status sph_last_bc_status(sph_ctx *ctx);
+/* Sync: the cover of a buffer as the library holds it now (after definition,
+ * grid fit or turns): runs of consecutive cell keys (first key, length), at most
+ * cap of them; *n_runs receives the count (SPH_ERR_ARG if it exceeds cap). */
+sph_status sph_buffer_cover(sph_ctx *ctx, int32_t buffer_id, int32_t *first, int32_t *len, int64_t cap,
+                            int64_t *n_runs);
 
 /* Library state that is not in the particle arrays: next_id and each buffer's
  * labelled count (sync).  Lets a caller checkpoint and restore a run. */
@@ -325,10 +341,11 @@ typedef enum {
     SPH_PHASE_FULLSCAN = 4,   /* full scan: every particle, FP32 filter (baseline)*/
     SPH_PHASE_FINALIZE = 5,   /* status, sort, duplicate/recycle/relabel/compact  */
     SPH_PHASE_BC = 6,         /* boundary conditions on buffer particles          */
-    SPH_PHASE_ROTATE = 7,     /* rigid turn of a buffer's particles (and cover)   */
+    SPH_PHASE_ROTATE = 7,     /* rigid turn of a buffer's particles               */
     SPH_PHASE_CANDIDATES = 8, /* full scan: the filter's candidates, exact tests  */
     SPH_PHASE_NEIGHBOR = 9,   /* neighbour counts over the cell list              */
-    SPH_NPHASE = 10
+    SPH_PHASE_COVER = 10,     /* cover cells of a turned buffer (two launches)    */
+    SPH_NPHASE = 11
 } sph_phase;
 
 /* When on, every kernel launch of the context is bracketed by two HIP events on
@@ -347,10 +364,12 @@ sph_status sph_profile_read(sph_ctx *ctx, double ms[SPH_NPHASE], int64_t launche
  * block to a domain), either enqueued directly or replayed from a HIP graph
  * captured at the first step.  Member contexts keep their own results
  * (sph_last_result, sph_last_events) and must be fully set up first: a later
- * sph_buffer_define, sph_grid_fit, sph_buffer_rotate or a change of the density
- * field in sph_set_fields on a member invalidates the batch (its launch tables
- * hold the member's cover cells, grid arrays and field roles): sph_batch_step
- * then returns SPH_ERR_STATE and launches nothing. */
+ * sph_buffer_define, sph_grid_fit or a change of the density field in
+ * sph_set_fields on a member invalidates the batch (its launch tables hold the
+ * member's grid arrays, run-list arrays and field roles): sph_batch_step then
+ * returns SPH_ERR_STATE and launches nothing.  Turning a member's buffer
+ * (sph_buffer_rotate) keeps the batch valid: the turned cover is recomputed on
+ * the device into the same arrays. */
 typedef struct sph_batch sph_batch;
 typedef enum { SPH_BATCH_KERNELS = 0, SPH_BATCH_GRAPH = 1 } sph_batch_mode;
 
@@ -376,6 +395,12 @@ sph_status sph_batch_graph_capture(sph_batch *b);
 sph_status sph_batch_graph_launch(sph_batch *b);
 /* Sync: out[d] = result of domain d's last update. */
 sph_status sph_batch_results(sph_batch *b, sph_result *out);
+/* Per-launch timing of the five launches of a step in SPH_BATCH_KERNELS mode
+ * (two HIP events on the batch stream around each; up to 8192 launches are
+ * kept).  enable: sync, drops what was recorded.  read: sync; ms and launches
+ * have 5 entries (count, scan, scatter, classify, finalize); reset != 0 clears. */
+sph_status sph_batch_profile_enable(sph_batch *b, int32_t on);
+sph_status sph_batch_profile_read(sph_batch *b, double ms[5], int64_t launches[5], int32_t reset);
 /* Autotuner: times `trials` steps of each launch mode x particles-per-block
  * candidate and keeps the fastest (steps are real updates of the current
  * states).  cache_path (optional) holds earlier choices keyed by device, domain

@@ -228,30 +228,46 @@ double binning_error_cells(int dim, const double glo[3], double cs, const int32_
     return off + 3.0001 * u * (span + off);
 }
 
+sph_status cover_box(int dim, const double glo[3], double cs, const int32_t dims[3], const double origin[3],
+                     const double rot[9], const double half[3], double margin, CoverBox &out) {
+    const Obb b = check_box(dim, origin, rot, half, margin);
+    for (int i = 0; i < 3; ++i) {
+        out.c[i] = b.c[i];
+        out.h[i] = b.h[i];
+        for (int j = 0; j < 3; ++j) out.ax[i][j] = b.ax[i][j];
+        out.lo_i[i] = out.hi_i[i] = 0;
+    }
+    obb_aabb(b, out.blo, out.bhi);
+    // Cell boxes are dilated by more than the FP32 binning error, so a particle of
+    // the check region binned into a cell puts that cell in the cover; grids whose
+    // error reaches a quarter cell are refused.
+    const double err = binning_error_cells(dim, glo, cs, dims);
+    if (!(err < kMaxBinningError)) return SPH_ERR_ARG;
+    out.eps = std::max(1e-2, 1.5 * err) * cs;
+    for (int j = 0; j < dim; ++j) {
+        double a = std::floor((out.blo[j] - out.eps - glo[j]) / cs) - 1.0;
+        double z = std::floor((out.bhi[j] + out.eps - glo[j]) / cs) + 1.0;
+        a = std::max(0.0, std::min(a, (double)dims[j] - 1.0));
+        z = std::max(0.0, std::min(z, (double)dims[j] - 1.0));
+        out.lo_i[j] = (int)a;
+        out.hi_i[j] = (int)z;
+        if ((double)out.hi_i[j] - (double)out.lo_i[j] > (double)(1 << 20)) return SPH_ERR_ARG;
+    }
+    return SPH_OK;
+}
+
 sph_status grid_cover(int dim, const double glo[3], double cs, const int32_t dims[3], const double origin[3],
                       const double rot[9], const double half[3], double margin, std::vector<int32_t> &first,
                       std::vector<int32_t> &len) {
     first.clear();
     len.clear();
     const Obb b = check_box(dim, origin, rot, half, margin);
-    double blo[3], bhi[3];
-    obb_aabb(b, blo, bhi);
-    // Cell boxes are dilated by more than the FP32 binning error, so a particle of
-    // the check region binned into a cell puts that cell in the cover; grids whose
-    // error reaches a quarter cell are refused.
-    const double err = binning_error_cells(dim, glo, cs, dims);
-    if (!(err < kMaxBinningError)) return SPH_ERR_ARG;
-    const double eps = std::max(1e-2, 1.5 * err) * cs;
-    int lo_i[3] = {0, 0, 0}, hi_i[3] = {0, 0, 0};
-    for (int j = 0; j < dim; ++j) {
-        double a = std::floor((blo[j] - eps - glo[j]) / cs) - 1.0;
-        double z = std::floor((bhi[j] + eps - glo[j]) / cs) + 1.0;
-        a = std::max(0.0, std::min(a, (double)dims[j] - 1.0));
-        z = std::max(0.0, std::min(z, (double)dims[j] - 1.0));
-        lo_i[j] = (int)a;
-        hi_i[j] = (int)z;
-        if ((double)hi_i[j] - (double)lo_i[j] > (double)(1 << 20)) return SPH_ERR_ARG;
-    }
+    CoverBox cb;
+    const sph_status st = cover_box(dim, glo, cs, dims, origin, rot, half, margin, cb);
+    if (st != SPH_OK) return st;
+    const double *blo = cb.blo, *bhi = cb.bhi;
+    const double eps = cb.eps;
+    const int32_t *lo_i = cb.lo_i, *hi_i = cb.hi_i;
     const int nz = dim == 3 ? hi_i[2] - lo_i[2] + 1 : 1;
     for (int kz = 0; kz < nz; ++kz) {
         const int iz = lo_i[2] + kz;

@@ -104,6 +104,9 @@ struct Ctl {
     unsigned int pad1;
     unsigned long long ident_count[16];
     int64_t n_built;               // particles of the latest count pass (what its scatter places)
+    int32_t run_cnt[16];           // cover runs of each buffer (in its range of the per-buffer run lists)
+    int32_t n_runs;                // runs of the compact list the classify and BC kernels walk
+    int32_t cover_fault;           // a turned buffer's cover needed more runs than its range holds
 };
 
 // ------------------------------------------------------------ device utils --
@@ -285,15 +288,6 @@ constexpr int kCountReplicas = 64;
 
 __device__ __forceinline__ void block_counts_init(unsigned *s_cnt) {
     if (threadIdx.x < 2 * SPH_MAX_BUFFERS) s_cnt[threadIdx.x] = 0u;
-}
-__device__ __forceinline__ void block_counts_add(unsigned *s_cnt, int k, unsigned long long found,
-                                                 unsigned long long post) {
-    found = wave_sum(found);
-    post = wave_sum(post);
-    if (lane_id() == 0 && (found | post)) {
-        atomicAdd(&s_cnt[2 * k], (unsigned)found);
-        atomicAdd(&s_cnt[2 * k + 1], (unsigned)post);
-    }
 }
 __device__ __forceinline__ void block_counts_store(const EventArgs &e, const unsigned *s_cnt, int nb) {
     if (threadIdx.x < 2 * nb && s_cnt[threadIdx.x])
@@ -900,43 +894,79 @@ struct LocalArgs {
     Parts p;
     const BufDev *bufs;
     int nb;
-    const int32_t *run_first;
+    const int32_t *run_first;  // compact run list; its length is Ctl::n_runs
     const int32_t *run_len;
     const uint8_t *run_buf;
-    int n_runs;
     const int32_t *cell_start;
     const int32_t *cell_idx;
     EventArgs e;
 };
 
+// A workgroup takes kRunsPerBlock runs of cover cells at a time: wave 0 loads
+// their records and the particle ranges of their cells, the block lays the runs'
+// particles out flat (a prefix over the runs in LDS), and every thread takes one
+// particle per round -- its cell_idx entry, then its position, label and (where
+// a duplicate may be made) carried fields, the test, the decision and the
+// emission.  The buffer varies from lane to lane.
+constexpr int kRunsPerBlock = 3;
+
 __device__ __forceinline__ void classify_body(const LocalArgs &a, const int vb, const int vg) {
     __shared__ BufDev sb[SPH_MAX_BUFFERS];
     __shared__ unsigned s_cnt[2 * SPH_MAX_BUFFERS];
+    __shared__ int s_j0[kRunsPerBlock], s_pre[kRunsPerBlock + 1], s_k[kRunsPerBlock];
+    __shared__ int s_nruns, s_fault;
     for (int t = threadIdx.x; t < a.nb * (int)(sizeof(BufDev) / 4); t += blockDim.x)
         reinterpret_cast<uint32_t *>(sb)[t] = reinterpret_cast<const uint32_t *>(a.bufs)[t];
+    if (threadIdx.x == 0) {  // with the records: one round trip
+        s_nruns = a.e.ctl->n_runs;
+        s_fault = (int)a.e.ctl->scan_fault;
+    }
     block_counts_init(s_cnt);
     __syncthreads();
-    if (a.e.ctl->scan_fault) {
+    if (s_fault) {
         block_counts_store(a.e, s_cnt, a.nb);
         return;
     }
+    const int n_runs = s_nruns;
     const int64_t N = live_count(a.p.n_dev, a.p.capacity);
-    const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
     const int wpb = blockDim.x / kWave;
     const int dim = a.p.dim;
-    for (int r = vb * wpb + wave; r < a.n_runs; r += vg * wpb) {
-        const int k = a.run_buf[r];
-        const BufDev &b = sb[k];
-        const int seg = r % kSeg;
-        const int c0 = a.run_first[r];
-        const int j0 = a.cell_start[c0];
-        const int j1 = a.cell_start[c0 + a.run_len[r]];
-        unsigned long long found = 0, post = 0;
-        for (int jb = j0; jb < j1; jb += kWave) {
-            const int j = jb + lane;
-            int64_t i = j < j1 ? a.cell_idx[j] : 0;
-            const bool valid = j < j1 && i < N;  // a list older than the live count cannot index past it
+    const int seg = (vb * wpb + wave) % kSeg;
+    for (int r0 = vb * kRunsPerBlock; r0 < n_runs; r0 += vg * kRunsPerBlock) {  // block-uniform
+        if (threadIdx.x < kWave) {  // wave 0: the runs' records and candidate ranges
+            const int q = threadIdx.x, r = r0 + q;
+            int len = 0, j0 = 0, k = 0;
+            if (q < kRunsPerBlock && r < n_runs) {
+                k = a.run_buf[r];
+                const int c0 = a.run_first[r], c1 = c0 + a.run_len[r];
+                j0 = a.cell_start[c0];
+                len = a.cell_start[c1] - j0;
+            }
+            int incl = len;
+            for (int off = 1; off < kRunsPerBlock; off <<= 1) {
+                const int t = __shfl_up(incl, off);
+                if (q >= off) incl += t;
+            }
+            if (q < kRunsPerBlock) {
+                s_j0[q] = j0;
+                s_pre[q] = incl - len;
+                s_k[q] = k;
+                if (q == kRunsPerBlock - 1) s_pre[kRunsPerBlock] = incl;
+            }
+        }
+        __syncthreads();
+        const int total = s_pre[kRunsPerBlock];
+        for (int base = 0; base < total; base += blockDim.x) {  // block-uniform
+            const int t = base + (int)threadIdx.x;
+            int q = 0;
+#pragma unroll
+            for (int qq = 1; qq < kRunsPerBlock; ++qq)
+                if (s_pre[qq] <= t) q = qq;
+            const int k = s_k[q];
+            const BufDev &b = sb[k];
+            int64_t i = t < total ? a.cell_idx[s_j0[q] + (t - s_pre[q])] : 0;
+            const bool valid = t < total && i < N;  // a list older than the live count cannot index past it
             int lab = 0;
             float x = 0.0f, y = 0.0f, z = 0.0f;
             float carv[SPH_MAX_CARRIED];
@@ -956,9 +986,12 @@ __device__ __forceinline__ void classify_body(const LocalArgs &a, const int vb, 
                 const unsigned bits = classify(b, dim, x, y, z);
                 if (bits & kIn) o = decide(b, k, dim, bits, lab, x, y, z);
             }
+            unsigned long long found = 0, post = 0;
             emit<true>(a.e, a.p, b, k, seg, valid, i, lab, o, x, y, z, carv, found, post);
+            if (found) atomicAdd(&s_cnt[2 * k], 1u);  // the buffer differs from lane to lane
+            if (post) atomicAdd(&s_cnt[2 * k + 1], 1u);
         }
-        block_counts_add(s_cnt, k, found, post);
+        __syncthreads();  // the run tables are reused by the next round
     }
     __syncthreads();
     block_counts_store(a.e, s_cnt, a.nb);
@@ -1155,22 +1188,31 @@ __global__ __launch_bounds__(kClassifyBlock) void k_classify_cand(FullArgs a) {
 
 // ------------------------------------------------------------- K2 finalize --
 //
-// nfb workgroups per domain.  Every block reads the counters and takes the
-// status decision (all checks come before any write), loads the event lists
-// and sorts the generated sources and the deleted indices in LDS; each block
-// then applies its share of the writes, and no block writes a location that
-// another block reads:
-//   * recycle and relabel of particles below the new count N' = N - |D| are
-//     done in place (those particles neither move nor are deleted), split by
-//     event number;
-//   * the positions p of the tail [N', N' + max(|G|, |D|)) are split among the
-//     blocks: the thread of p first moves the survivor at p (its recycle and
-//     relabel applied from an LDS map of the tail) into its hole, then writes
-//     the duplicate appended at p.  Holes are deleted particles below N'.
+// nfb workgroups per domain, each through the same four phases; every block
+// takes the status decision itself (all checks come before any write) and sorts
+// both event lists in LDS, and no block writes a location that another block
+// reads:
+//   A. one round of loads: the counters, the label counts and the first kSpec
+//      slots of every event segment (the entries of a segment past kSpec, rare,
+//      take a second round once the counters are known);
+//   B. the entries into flat lists; recycle and relabel of particles below the
+//      new count N' = N - |D| are issued in place by the entry's owner block
+//      (those particles neither move nor are deleted); an LDS map of the tail
+//      [N', N) holds each tail particle's recycle entry and new label;
+//   C. both lists sorted: 256-key chunks in registers (one wave each), then the
+//      rank of every key is its place in its chunk plus the keys below it in the
+//      list's other chunks (binary searches in LDS);
+//   D. the positions p of the tail [N', N' + max(|G|, |D|)) are split among the
+//      blocks: the thread of p loads the survivor at p (with its map entry) and
+//      the payload of the duplicate appended at p, then moves the survivor into
+//      its hole (the k-th surviving tail particle fills the k-th smallest
+//      deleted index) and writes the duplicate at p.
 // The block that takes the last ticket (every block has read the counters by
 // then) writes the result and clears the counters for the next update.
 
 constexpr int kFinBlocksMax = 32;
+constexpr int kSpec = 128;  // slots per event segment loaded with the counters
+static_assert(kSeg * kSpec == 2 * 1024, "two speculative entries per finalize thread");
 
 struct FinArgs {
     Parts p;
@@ -1253,37 +1295,13 @@ __device__ __forceinline__ void bitonic_sort256(uint32_t (&k)[4], uint32_t (&v)[
     if constexpr (K < kChunk) bitonic_sort256<K * 2>(k, v, lane);
 }
 
-// For two keys at once (independent searches, so their LDS reads overlap): the
-// number of entries of the sorted run r[0, len) below the key (or not above it,
-// if or_equal).  w is a power of two >= len; len 0 means no search.
-__device__ __forceinline__ void run_rank2(const uint32_t *r0, unsigned len0, uint32_t key0, bool oe0,
-                                          const uint32_t *r1, unsigned len1, uint32_t key1, bool oe1, unsigned w,
-                                          unsigned &c0, unsigned &c1) {
-    unsigned lo0 = 0, lo1 = 0;
-    for (unsigned step = w >> 1; step > 0; step >>= 1) {
-        const unsigned j0 = lo0 + step - 1, j1 = lo1 + step - 1;
-        bool t0 = false, t1 = false;
-        if (j0 < len0) {
-            const uint32_t x = r0[j0];
-            t0 = oe0 ? x <= key0 : x < key0;
-        }
-        if (j1 < len1) {
-            const uint32_t x = r1[j1];
-            t1 = oe1 ? x <= key1 : x < key1;
-        }
-        lo0 += t0 ? step : 0u;
-        lo1 += t1 ? step : 0u;
-    }
-    if (lo0 < len0) {
-        const uint32_t x = r0[lo0];
-        lo0 += (oe0 ? x <= key0 : x < key0) ? 1u : 0u;
-    }
-    if (lo1 < len1) {
-        const uint32_t x = r1[lo1];
-        lo1 += (oe1 ? x <= key1 : x < key1) ? 1u : 0u;
-    }
-    c0 = lo0;
-    c1 = lo1;
+// Keys of a sorted 256-key chunk below x (keys are distinct; padding is all ones).
+__device__ __forceinline__ unsigned below_in_chunk(const uint32_t *c, uint32_t x) {
+    unsigned lo = 0;
+#pragma unroll
+    for (unsigned step = kChunk / 2; step > 0; step >>= 1)
+        if (c[lo + step - 1] < x) lo += step;
+    return lo + (c[lo] < x ? 1u : 0u);
 }
 
 // Even split of [0, n) among nparts: part q gets [lo, hi).
@@ -1293,87 +1311,50 @@ __device__ __forceinline__ void share_of(unsigned n, int q, int nparts, unsigned
     hi = min(n, lo + chunk);
 }
 
-// Segment of a flat event number e, given the exclusive segment offsets.
-__device__ __forceinline__ int seg_of(const unsigned *off, unsigned e) {
-    // the last segment g with off[g] <= e (off is non-decreasing, off[0] = 0):
-    // four dependent LDS reads
-    static_assert(kSeg == 16, "segment search");
-    int g = 0;
-#pragma unroll
-    for (int step = kSeg / 2; step > 0; step >>= 1)
-        if (off[g + step] <= e) g += step;
-    return g;
-}
-
-constexpr uint32_t kMapRelShift = 20;  // tail map: bits 0..19 recycle entry + 1, bits 20.. new label + 1
-constexpr int kSortBuckets = 8192;   // buckets per list of the finalize's counting sort (16-bit counters)
-constexpr int kSortBucketMax = 64;   // fuller buckets: comparison sort instead
-// LDS position of word w of the bucket counters: one pad word per 32, so that the
-// bucket scan's per-thread runs of kSortBuckets / kFinBlock words do not pile up
-// on a few banks
-__device__ __forceinline__ unsigned hx(unsigned w) { return w + (w >> 5); }
-static_assert(kMaxEv % kFinBlock == 0 && kSortBuckets % kFinBlock == 0 && kMaxEv < 65536, "finalize sort layout");
+constexpr uint32_t kMapRelShift = 20;  // tail map: bits 0..19 recycle slot + 1, bits 20.. new label + 1
+static_assert(kSeg * kMaxEv < (1u << kMapRelShift), "recycle slot fits the tail map");
 
 // LDS of one finalize workgroup (declared by the kernel, so that a launch that
 // also runs scan tiles can overlay both in one allocation).
 struct FinLds {
-    uint32_t k[2][2][kMaxEv];          // [list: 0 sources, 1 deleted][ping-pong] keys
-    uint32_t v[2][kMaxEv];             // [ping-pong] event entry of each source
-    uint32_t map[kMaxEv];              // tail position t = p - N': recycle entry and new label
+    uint32_t k[2][2][kMaxEv];          // [list: 0 sources, 1 deleted][0: flat, 1: sorted] keys
+    uint32_t v[2][kMaxEv];             // event slot of each source, [0: flat, 1: sorted]
+    uint32_t map[kMaxEv];              // tail position t = p - N': recycle slot and new label
     unsigned bits[kMaxEv / 32], wpre[kMaxEv / 32];  // deleted tail positions, prefix per word
-    unsigned off[3][kSeg + 1];         // per list: segment counts, then exclusive offsets; [kSeg] = total
+    unsigned cnt[3][kSeg];             // per list (gen, del, rel): segment counts
+    unsigned off[3][kSeg + 1];         // exclusive offsets; [kSeg] = total
+    unsigned ovf[3][kSeg + 1];         // exclusive offsets of the entries past kSpec; [kSeg] = total
     int status;
     unsigned last;
     long long N, next;
     unsigned found[SPH_MAX_BUFFERS], post[SPH_MAX_BUFFERS];
     long long nl[SPH_MAX_BUFFERS];
     unsigned flags[3];
-    uint32_t hist[kSortBuckets + kSortBuckets / 32];  // per list, two buckets per word: counts, then starts (padded, hx)
-    uint32_t mm[2][2];                 // per list: min and max key
-    unsigned fat[2];                   // per list: keys in the fullest bucket
-    unsigned wsum[kFinBlock / kWave];
 };
 
 __device__ __forceinline__ void finalize_body(const FinArgs &a, const int fb, const int nfb, FinLds &L) {
-    auto &s_k = L.k;
-    auto &s_v = L.v;
-    auto &s_map = L.map;
-    auto &s_bits = L.bits;
-    auto &s_wpre = L.wpre;
-    auto &s_off = L.off;
-    int &s_status = L.status;
-    unsigned &s_last = L.last;
-    long long &s_N = L.N, &s_next = L.next;
-    auto &s_found = L.found;
-    auto &s_post = L.post;
-    auto &s_nl = L.nl;
-    auto &s_flags = L.flags;
-    auto &s_hist = L.hist;
-    auto &s_mm = L.mm;
-    auto &s_fat = L.fat;
-    auto &s_wsum = L.wsum;
     Ctl *c = a.e.ctl;
     const int tid = threadIdx.x;
     const unsigned bd = blockDim.x;
+    const unsigned cap = a.e.cap_ev, cap_rel = a.e.cap_rel;
     const int words = kCountReplicas * 2 * SPH_MAX_BUFFERS;
-    // ---- read everything the status decision needs in one round trip ----
-    if (tid < SPH_MAX_BUFFERS) {
-        s_found[tid] = 0u;
-        s_post[tid] = 0u;
-        s_nl[tid] = c->n_labelled[tid];
-    }
-    if (tid >= kWave && tid < kWave + kSeg) {
-        const int g = tid - kWave;
-        s_off[0][g] = c->seg[g].n_gen;
-        s_off[1][g] = c->seg[g].n_del;
-        s_off[2][g] = c->seg[g].n_rel;
-    }
-    if (tid == 2 * kWave) {
-        s_next = c->next_id;
-        s_N = *a.p.n_dev;
-        s_flags[0] = c->scan_fault;
-        s_flags[1] = a.nf_full ? c->nonfinite_full : c->nonfinite_seen;
-        s_flags[2] = c->cand_overflow;
+    // ---- A: counters, label counts and the first kSpec slots of every segment,
+    //      all in one round of loads ----
+    unsigned sc[3] = {0u, 0u, 0u};
+    long long nlk = 0, nx = 0, nN = 0;
+    unsigned fl[3] = {0u, 0u, 0u};
+    if (tid < kSeg) {
+        sc[0] = c->seg[tid].n_gen;
+        sc[1] = c->seg[tid].n_del;
+        sc[2] = c->seg[tid].n_rel;
+    } else if (tid >= kWave && tid < kWave + SPH_MAX_BUFFERS) {
+        nlk = c->n_labelled[tid - kWave];
+    } else if (tid == 2 * kWave) {
+        nx = c->next_id;
+        nN = *a.p.n_dev;
+        fl[0] = c->scan_fault;
+        fl[1] = a.nf_full ? c->nonfinite_full : c->nonfinite_seen;
+        fl[2] = c->cand_overflow;
     }
     unsigned pv[(kCountReplicas * 2 * SPH_MAX_BUFFERS + 1023) / 1024];
 #pragma unroll
@@ -1381,335 +1362,238 @@ __device__ __forceinline__ void finalize_body(const FinArgs &a, const int fb, co
         const int w = q * (int)bd + tid;
         pv[q] = w < words ? a.e.part[w] : 0u;
     }
-    for (unsigned t = tid; t < kMaxEv; t += bd) s_map[t] = 0u;
-    for (unsigned w = tid; w < kMaxEv / 32; w += bd) s_bits[w] = 0u;
-    for (unsigned t = tid; t < kSortBuckets + kSortBuckets / 32; t += bd) s_hist[t] = 0u;
-    if (tid < 2) {
-        s_mm[tid][0] = 0xffffffffu;
-        s_mm[tid][1] = 0u;
-        s_fat[tid] = 0u;
+    uint32_t gi[2], di[2];
+    unsigned long long rv[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {  // speculative entry q * 1024 + tid: segment e / kSpec, slot e % kSpec
+        const unsigned e = (unsigned)q * 1024u + (unsigned)tid, g = e / kSpec, sl = e % kSpec;
+        gi[q] = sl < cap ? a.e.gen_idx[(size_t)g * cap + sl] : 0u;
+        di[q] = sl < cap ? a.e.del_idx[(size_t)g * cap + sl] : 0u;
+        rv[q] = sl < cap_rel ? a.e.rel[(size_t)g * cap_rel + sl] : 0ull;
+    }
+    if (tid < SPH_MAX_BUFFERS) {
+        L.found[tid] = 0u;
+        L.post[tid] = 0u;
     }
     __syncthreads();
+    if (tid < kSeg) {
+        L.cnt[0][tid] = sc[0];
+        L.cnt[1][tid] = sc[1];
+        L.cnt[2][tid] = sc[2];
+    } else if (tid >= kWave && tid < kWave + SPH_MAX_BUFFERS) {
+        L.nl[tid - kWave] = nlk;
+    } else if (tid == 2 * kWave) {
+        L.next = nx;
+        L.N = nN;
+        L.flags[0] = fl[0];
+        L.flags[1] = fl[1];
+        L.flags[2] = fl[2];
+    }
+    for (unsigned w = tid; w < kMaxEv / 32; w += bd) L.bits[w] = 0u;
+    for (unsigned t = tid; t < kMaxEv; t += bd) L.map[t] = 0u;
 #pragma unroll
     for (int q = 0; q < (int)(sizeof(pv) / sizeof(pv[0])); ++q) {
         const int w = q * (int)bd + tid;
         const int slot = w % (2 * SPH_MAX_BUFFERS);
-        if (pv[q]) atomicAdd(slot & 1 ? &s_post[slot >> 1] : &s_found[slot >> 1], pv[q]);
+        if (pv[q]) atomicAdd(slot & 1 ? &L.post[slot >> 1] : &L.found[slot >> 1], pv[q]);
     }
     __syncthreads();
+    // Every counter this block reads has been read: its ticket can be taken now
+    // (the result is needed only at the end).
     unsigned ticket = 0u;
-    if (tid < kWave) {  // segment offsets (lane l * kSeg + g: segment g of list l), totals, status
+    if (tid == 0) ticket = __hip_atomic_fetch_add(&c->fin_ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (tid < kWave) {  // segment offsets (lane l * kSeg + g: segment g of list l), overflow offsets, status
         const int l = tid / kSeg, g = tid % kSeg;
-        const unsigned v = tid < 3 * kSeg ? s_off[l][g] : 0u;
-        unsigned incl = v;
+        const unsigned v = tid < 3 * kSeg ? L.cnt[l][g] : 0u;
+        const unsigned o = v > (unsigned)kSpec ? v - (unsigned)kSpec : 0u;
+        unsigned incl = v, oincl = o;
         for (int off = 1; off < kSeg; off <<= 1) {
-            const unsigned t = __shfl_up(incl, off, kSeg);
-            if (g >= off) incl += t;
+            const unsigned t = __shfl_up(incl, off, kSeg), to = __shfl_up(oincl, off, kSeg);
+            if (g >= off) {
+                incl += t;
+                oincl += to;
+            }
         }
         if (tid < 3 * kSeg) {
-            s_off[l][g] = incl - v;
-            if (g == kSeg - 1) s_off[l][kSeg] = incl;
+            L.off[l][g] = incl - v;
+            L.ovf[l][g] = oincl - o;
+            if (g == kSeg - 1) {
+                L.off[l][kSeg] = incl;
+                L.ovf[l][kSeg] = oincl;
+            }
         }
         const unsigned tot0 = __shfl(incl, kSeg - 1), tot1 = __shfl(incl, 2 * kSeg - 1),
                        tot2 = __shfl(incl, 3 * kSeg - 1);
         if (tid == 0) {
-            const long long N_raw = s_N;
+            const long long N_raw = L.N;
             const long long N = N_raw < 0 ? 0 : (N_raw > a.p.capacity ? a.p.capacity : N_raw);
             int st = SPH_OK;
             if (N_raw != N) st = SPH_ERR_ARG;
-            else if (a.local && s_flags[0]) st = SPH_ERR_HIP;
-            else if (s_flags[1]) st = SPH_ERR_NONFINITE;
+            else if (a.local && L.flags[0]) st = SPH_ERR_HIP;
+            else if (L.flags[1]) st = SPH_ERR_NONFINITE;
             for (int k = 0; k < a.nb && st == SPH_OK; ++k)
-                if ((long long)s_found[k] < s_nl[k]) st = SPH_ERR_CFL;
-            if (st == SPH_OK && (tot0 > a.e.cap_ev || tot1 > a.e.cap_ev || tot2 > a.e.cap_rel)) st = SPH_ERR_EVENTS;
-        if (st == SPH_OK && !a.local && s_flags[2]) st = SPH_ERR_EVENTS;  // the full scan's candidate list overflowed
+                if ((long long)L.found[k] < L.nl[k]) st = SPH_ERR_CFL;
+            if (st == SPH_OK && (tot0 > cap || tot1 > cap || tot2 > cap_rel)) st = SPH_ERR_EVENTS;
+            if (st == SPH_OK && !a.local && L.flags[2]) st = SPH_ERR_EVENTS;  // the full scan's candidate list overflowed
             if (st == SPH_OK && N - (long long)tot1 + (long long)tot0 > a.p.capacity) st = SPH_ERR_CAPACITY;
-            s_status = st;
-            s_N = N;
-            // Every counter this block reads has been read (the values are used
-            // above); the ticket's result is only needed at the end.  With no error
-            // it is taken after the event lists are loaded: a wave waiting for its
-            // loads also waits for every access it issued before them.
-            if (st != SPH_OK)
-                ticket = __hip_atomic_fetch_add(&c->fin_ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            L.status = st;
+            L.N = N;
         }
     }
     __syncthreads();
-    const int st = s_status;
-    const unsigned G = s_off[0][kSeg], D = s_off[1][kSeg], R = s_off[2][kSeg];
-    const long long N = s_N;
+    const int st = L.status;
+    const unsigned G = L.off[0][kSeg], D = L.off[1][kSeg];
+    const long long N = L.N;
     if (st == SPH_OK) {
         const Parts &p = a.p;
         const long long Np = N - (long long)D;
         const int dim = p.dim, nc = p.nc, ds = 3 + nc;
-        const unsigned cap = a.e.cap_ev;
-        // ---- event lists into LDS; tail map and deleted bits; in-place writes below N' ----
-        unsigned g0, g1, r0, r1;
-        share_of(G, fb, nfb, g0, g1);
-        share_of(R, fb, nfb, r0, r1);
-        uint32_t mn0 = 0xffffffffu, mx0 = 0u, mn1 = 0xffffffffu, mx1 = 0u;  // key ranges, for the sort
-        // One round per bd entries of the longest list: the generation, deletion and
-        // relabel entries of index e are all loaded before any is used (one round trip
-        // for the three lists).
-        const unsigned nround = max(G, max(D, R));
-        for (unsigned base = 0; base < nround; base += bd) {  // block-uniform
-            const unsigned e = base + (unsigned)tid;
-            const bool hg = e < G, hd = e < D, hr = e < R;
-            const bool mine = hg && e >= g0 && e < g1;
-            unsigned ev = 0u;
-            uint32_t gi = 0u, di = 0u;
-            unsigned long long rv = 0ull;
-            float rn[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-            if (hg) {
-                const int g = seg_of(s_off[0], e);
-                ev = (unsigned)g * cap + (e - s_off[0][g]);
-                if (mine)
-                    for (int q = 0; q < 4; ++q)
-                        if (q < dim || (q == 3 && a.e.rho_field >= 0)) rn[q] = a.e.gen_new[4 * (size_t)ev + q];
-                gi = a.e.gen_idx[ev];
-            }
-            if (hd) {
-                const int g = seg_of(s_off[1], e);
-                di = a.e.del_idx[(size_t)g * cap + (e - s_off[1][g])];
-            }
-            if (hr) {
-                const int g = seg_of(s_off[2], e);
-                rv = a.e.rel[(size_t)g * a.e.cap_rel + (e - s_off[2][g])];
-            }
-            if (hg) {
-                const uint32_t i = gi;
-                s_k[0][0][e] = i;
-                s_v[0][e] = ev;
-                mn0 = min(mn0, i);
-                mx0 = max(mx0, i);
-                if ((long long)i >= Np) {
-                    atomicOr(&s_map[i - Np], ev + 1u);
-                } else if (mine) {
-                    for (int q = 0; q < dim; ++q) p.pos[q][i] = rn[q];
-                    if (a.e.rho_field >= 0) p.car[a.e.rho_field][i] = rn[3];
+        // ---- B: entries into the flat lists, the tail map and the deleted bits;
+        //      in-place recycle and relabel below N' by the entry's owner block ----
+        // (an entry is owned by block (its speculative or overflow number) % nfb)
+        unsigned own_slot[2] = {0u, 0u}, own_i[2] = {0u, 0u};
+        bool own_rec[2] = {false, false};
+        auto place = [&](int l, unsigned g, unsigned sl, uint32_t idx, unsigned long long r, bool mine, int q) {
+            const unsigned e = L.off[l][g] + sl;
+            if (l == 0) {
+                L.k[0][0][e] = idx;
+                L.v[0][e] = g * cap + sl;
+                if ((long long)idx >= Np) atomicOr(&L.map[idx - Np], g * cap + sl + 1u);
+                else if (mine) {  // recycle in place (its recycled position is loaded in D)
+                    own_rec[q] = true;
+                    own_slot[q] = g * cap + sl;
+                    own_i[q] = idx;
                 }
+            } else if (l == 1) {
+                L.k[1][0][e] = idx;
+                if ((long long)idx >= Np) atomicOr(&L.bits[(idx - Np) >> 5], 1u << ((idx - Np) & 31));
+            } else {
+                const long long i = (long long)(r >> 32);
+                const uint32_t lab = (uint32_t)(r & 0xffffffffull);
+                if (i >= Np) atomicOr(&L.map[i - Np], (lab + 1u) << kMapRelShift);
+                else if (mine) p.label[i] = (int32_t)lab;
             }
-            if (hd) {
-                const uint32_t i = di;
-                s_k[1][0][e] = i;
-                mn1 = min(mn1, i);
-                mx1 = max(mx1, i);
-                if ((long long)i >= Np) atomicOr(&s_bits[(i - Np) >> 5], 1u << ((i - Np) & 31));
-            }
-            if (hr) {
-                const long long i = (long long)(rv >> 32);
-                const uint32_t lab = (uint32_t)(rv & 0xffffffffull);
-                if (i >= Np) atomicOr(&s_map[i - Np], (lab + 1u) << kMapRelShift);
-                else if (e >= r0 && e < r1) p.label[i] = (int32_t)lab;  // in place, this block's share
-            }
+        };
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const unsigned e = (unsigned)q * 1024u + (unsigned)tid, g = e / kSpec, sl = e % kSpec;
+            const bool mine = (int)(e % (unsigned)nfb) == fb;
+            if (sl < L.cnt[0][g]) place(0, g, sl, gi[q], 0ull, mine, q);
+            if (sl < L.cnt[1][g]) place(1, g, sl, di[q], 0ull, mine, q);
+            if (sl < L.cnt[2][g]) place(2, g, sl, 0u, rv[q], mine, q);
         }
-        if (tid == 0) ticket = __hip_atomic_fetch_add(&c->fin_ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        for (int off = 32; off > 0; off >>= 1) {
-            mn0 = min(mn0, (uint32_t)__shfl_xor(mn0, off));
-            mx0 = max(mx0, (uint32_t)__shfl_xor(mx0, off));
-            mn1 = min(mn1, (uint32_t)__shfl_xor(mn1, off));
-            mx1 = max(mx1, (uint32_t)__shfl_xor(mx1, off));
-        }
-        if ((tid & (kWave - 1)) == 0) {
-            if (mx0 >= mn0) {
-                atomicMin(&s_mm[0][0], mn0);
-                atomicMax(&s_mm[0][1], mx0);
-            }
-            if (mx1 >= mn1) {
-                atomicMin(&s_mm[1][0], mn1);
-                atomicMax(&s_mm[1][1], mx1);
+        // entries past the first kSpec slots of their segment (block-uniform test)
+        if (L.ovf[0][kSeg] + L.ovf[1][kSeg] + L.ovf[2][kSeg] > 0u) {
+            for (int l = 0; l < 3; ++l) {
+                const unsigned tot = L.ovf[l][kSeg];
+                for (unsigned f = tid; f < tot; f += bd) {
+                    int g = 0;
+                    while (g + 1 < kSeg && L.ovf[l][g + 1] <= f) ++g;
+                    const unsigned sl = (unsigned)kSpec + (f - L.ovf[l][g]);
+                    const bool mine = (int)(f % (unsigned)nfb) == fb;
+                    if (l == 0) {
+                        const uint32_t idx = a.e.gen_idx[(size_t)g * cap + sl];
+                        const unsigned e = L.off[0][g] + sl;
+                        L.k[0][0][e] = idx;
+                        L.v[0][e] = g * cap + sl;
+                        if ((long long)idx >= Np) atomicOr(&L.map[idx - Np], g * cap + sl + 1u);
+                        else if (mine) {  // recycled in place below, right away (rare path)
+                            for (int q2 = 0; q2 < dim; ++q2)
+                                p.pos[q2][idx] = a.e.gen_new[4 * ((size_t)g * cap + sl) + q2];
+                            if (a.e.rho_field >= 0)
+                                p.car[a.e.rho_field][idx] = a.e.gen_new[4 * ((size_t)g * cap + sl) + 3];
+                        }
+                    } else if (l == 1) {
+                        const uint32_t idx = a.e.del_idx[(size_t)g * cap + sl];
+                        L.k[1][0][L.off[1][g] + sl] = idx;
+                        if ((long long)idx >= Np) atomicOr(&L.bits[(idx - Np) >> 5], 1u << ((idx - Np) & 31));
+                    } else {
+                        const unsigned long long r = a.e.rel[(size_t)g * cap_rel + sl];
+                        const long long i = (long long)(r >> 32);
+                        const uint32_t lab = (uint32_t)(r & 0xffffffffull);
+                        if (i >= Np) atomicOr(&L.map[i - Np], (lab + 1u) << kMapRelShift);
+                        else if (mine) p.label[i] = (int32_t)lab;
+                    }
+                }
             }
         }
         __syncthreads();
-        // ---- sort both lists.  Counting sort into kSortBuckets buckets over each
-        //      list's key range, then the rank inside a bucket by comparing with
-        //      its other keys; if a bucket holds more than kSortBucketMax keys,
-        //      256-key chunk sorts in registers and merge rounds instead. ----
-        constexpr int kPer = kMaxEv / kFinBlock;  // keys of one list per thread at most
-        const unsigned nl[2] = {G, D};
+        // ---- C: sort both lists (256-key chunks in registers, then ranks by search) ----
         if (tid >= kFinBlock - kWave) {  // exclusive prefix of the deleted bits per 32-position word (<= 128 words)
             const unsigned lane = (unsigned)tid & (kWave - 1), nw = (D + 31) / 32;
             const unsigned w0 = 2u * lane, w1 = w0 + 1u;
-            const unsigned c0 = w0 < nw ? (unsigned)__popc(s_bits[w0]) : 0u;
-            const unsigned c1 = w1 < nw ? (unsigned)__popc(s_bits[w1]) : 0u;
+            const unsigned c0 = w0 < nw ? (unsigned)__popc(L.bits[w0]) : 0u;
+            const unsigned c1 = w1 < nw ? (unsigned)__popc(L.bits[w1]) : 0u;
             unsigned incl = c0 + c1;
             for (unsigned off = 1; off < kWave; off <<= 1) {
                 const unsigned t = __shfl_up(incl, off);
                 if (lane >= off) incl += t;
             }
             const unsigned excl = incl - c0 - c1;
-            if (w0 < nw) s_wpre[w0] = excl;
-            if (w1 < nw) s_wpre[w1] = excl + c0;
+            if (w0 < nw) L.wpre[w0] = excl;
+            if (w1 < nw) L.wpre[w1] = excl + c0;
         }
-        unsigned shift[2];
+        const unsigned ncg = (G + kChunk - 1) / kChunk, ncd = (D + kChunk - 1) / kChunk;
+        {
+            const unsigned wave = (unsigned)tid / kWave, lane = (unsigned)tid & (kWave - 1), nwave = bd / kWave;
+            for (unsigned ch = wave; ch < ncg + ncd; ch += nwave) {  // wave-uniform
+                const bool is_g = ch < ncg;
+                const unsigned base = (is_g ? ch : ch - ncg) * kChunk, n = is_g ? G : D;
+                uint32_t *kk = L.k[is_g ? 0 : 1][0];
+                uint32_t key[4], val[4];
 #pragma unroll
-        for (int l = 0; l < 2; ++l) {
-            const uint32_t span = nl[l] > 0 ? s_mm[l][1] - s_mm[l][0] : 0u;
-            unsigned sh = 0;
-            while ((span >> sh) >= (uint32_t)kSortBuckets) ++sh;
-            shift[l] = sh;
-        }
-        uint32_t slot[2][kPer];
-#pragma unroll
-        for (int l = 0; l < 2; ++l)
-#pragma unroll
-            for (int q = 0; q < kPer; ++q) {
-                const unsigned e = (unsigned)q * kFinBlock + tid;
-                slot[l][q] = 0u;
-                if (e < nl[l]) {
-                    const uint32_t b = (s_k[l][0][e] - s_mm[l][0]) >> shift[l], sh = (b & 1u) * 16u;
-                    slot[l][q] = (atomicAdd(&s_hist[hx(l * (kSortBuckets / 2) + (b >> 1))], 1u << sh) >> sh) & 0xffffu;
+                for (int r = 0; r < 4; ++r) {
+                    const unsigned e = base + (unsigned)r * kWave + lane;
+                    key[r] = e < n ? kk[e] : 0xffffffffu;
+                    val[r] = is_g && e < n ? L.v[0][e] : 0u;
                 }
-            }
-        __syncthreads();
-        {   // exclusive bucket starts; list 0 in the first half of the waves, list 1 in the second
-            constexpr int kWords = kSortBuckets / kFinBlock;  // words of 16-bit counters per thread
-            const int lane = tid & (kWave - 1), wave = tid / kWave, half = kFinBlock / kWave / 2;
-            uint32_t v[kWords], sum = 0, fat = 0;
+                bitonic_sort256<2>(key, val, (int)lane);
 #pragma unroll
-            for (int q = 0; q < kWords; ++q) {
-                v[q] = s_hist[hx(kWords * tid + q)];
-                const uint32_t lo = v[q] & 0xffffu, hi = v[q] >> 16;
-                sum += lo + hi;
-                fat = max(fat, max(lo, hi));
-            }
-            uint32_t incl = sum;
-            for (int off = 1; off < kWave; off <<= 1) {
-                const uint32_t t = __shfl_up(incl, off);
-                if (lane >= off) incl += t;
-            }
-            for (int off = 32; off > 0; off >>= 1) fat = max(fat, (uint32_t)__shfl_xor(fat, off));
-            if (lane == kWave - 1) s_wsum[wave] = incl;
-            if (lane == 0) atomicMax(&s_fat[wave / half], fat);
-            __syncthreads();
-            uint32_t run = incl - sum;
-            for (int w = (wave / half) * half; w < wave; ++w) run += s_wsum[w];
-#pragma unroll
-            for (int q = 0; q < kWords; ++q) {
-                const uint32_t lo = run;
-                run += v[q] & 0xffffu;
-                s_hist[hx(kWords * tid + q)] = lo | (run << 16);
-                run += v[q] >> 16;
+                for (int r = 0; r < 4; ++r) {
+                    const unsigned e = base + (unsigned)r * kWave + lane;
+                    kk[e] = key[r];  // padding included: a chunk is always whole
+                    if (is_g) L.v[0][e] = val[r];
+                }
             }
         }
         __syncthreads();
-        const bool fast = s_fat[0] <= (unsigned)kSortBucketMax && s_fat[1] <= (unsigned)kSortBucketMax;
-        unsigned cur = 0;
-        if (fast) {
-#pragma unroll
-            for (int l = 0; l < 2; ++l)  // keys (and source entries) grouped by bucket
-#pragma unroll
-                for (int q = 0; q < kPer; ++q) {
-                    const unsigned e = (unsigned)q * kFinBlock + tid;
-                    if (e < nl[l]) {
-                        const uint32_t k = s_k[l][0][e];
-                        const uint32_t b = (k - s_mm[l][0]) >> shift[l];
-                        const uint32_t pos =
-                            ((s_hist[hx(l * (kSortBuckets / 2) + (b >> 1))] >> ((b & 1u) * 16u)) & 0xffffu) + slot[l][q];
-                        s_k[l][1][pos] = k;
-                        if (l == 0) s_v[1][pos] = s_v[0][e];
-                    }
-                }
-            __syncthreads();
-#pragma unroll
-            for (int l = 0; l < 2; ++l)  // rank inside the bucket
-#pragma unroll
-                for (int q = 0; q < kPer; ++q) {
-                    const unsigned t = (unsigned)q * kFinBlock + tid;
-                    if (t < nl[l]) {
-                        const uint32_t k = s_k[l][1][t];
-                        const uint32_t b = (k - s_mm[l][0]) >> shift[l];
-                        const unsigned hb = l * (kSortBuckets / 2);
-                        const uint32_t b0 = (s_hist[hx(hb + (b >> 1))] >> ((b & 1u) * 16u)) & 0xffffu;
-                        const uint32_t b1 = b + 1 < (uint32_t)kSortBuckets
-                                                ? (s_hist[hx(hb + ((b + 1) >> 1))] >> (((b + 1) & 1u) * 16u)) & 0xffffu
-                                                : nl[l];
-                        uint32_t rank = b0;
-                        for (uint32_t j = b0; j < b1; ++j) rank += s_k[l][1][j] < k ? 1u : 0u;
-                        s_k[l][0][rank] = k;
-                        if (l == 0) s_v[0][rank] = s_v[1][t];
-                    }
-                }
-            __syncthreads();
-        } else {
-            // ---- sort: 256-key chunks in registers, then merge rounds (runs of w -> 2w) ----
-            const unsigned PA = (G + kChunk - 1) / kChunk * kChunk, PB = (D + kChunk - 1) / kChunk * kChunk;
-            {
-                const unsigned wave = (unsigned)tid / kWave, lane = (unsigned)tid & (kWave - 1), nwave = bd / kWave;
-                const unsigned ncha = PA / kChunk, nch = ncha + PB / kChunk;
-                for (unsigned ch = wave; ch < nch; ch += nwave) {  // wave-uniform
-                    const bool is_a = ch < ncha;
-                    const unsigned base = (is_a ? ch : ch - ncha) * kChunk, n = is_a ? G : D;
-                    uint32_t *kk = s_k[is_a ? 0 : 1][0];
-                    uint32_t key[4], val[4];
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const unsigned e = base + (unsigned)r * kWave + lane;
-                        key[r] = e < n ? kk[e] : 0xffffffffu;
-                        val[r] = is_a && e < n ? s_v[0][e] : 0u;
-                    }
-                    bitonic_sort256<2>(key, val, (int)lane);
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const unsigned e = base + (unsigned)r * kWave + lane;
-                        kk[e] = key[r];
-                        if (is_a) s_v[0][e] = val[r];
-                    }
-                }
-            }
-            __syncthreads();
-            const unsigned PM = PA > PB ? PA : PB, tot = PA + PB;
-            for (unsigned w = kChunk; w < PM; w <<= 1) {
-                // two elements per thread (t and t + bd); each wave's 64 lie in one run of one list
-                for (unsigned t = tid; t < tot; t += 2 * bd) {
-                    unsigned e[2], len[2], rr[2], cnt[2];
-                    uint32_t key[2];
-                    bool isa[2], oe[2];
-                    const uint32_t *base[2];
-#pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        const unsigned tt = t + (unsigned)h * bd;
-                        const bool ok = tt < tot;
-                        isa[h] = tt < PA;
-                        e[h] = isa[h] ? tt : tt - PA;
-                        const unsigned P = isa[h] ? PA : PB;
-                        const uint32_t *src = s_k[isa[h] ? 0 : 1][cur];
-                        key[h] = ok ? src[e[h]] : 0u;
-                        rr[h] = e[h] / w;
-                        const unsigned sr = rr[h] ^ 1u;
-                        len[h] = ok && sr * w < P ? min(w, P - sr * w) : 0u;
-                        base[h] = src + (size_t)sr * w;
-                        oe[h] = (rr[h] & 1u) != 0u;
-                    }
-                    run_rank2(base[0], len[0], key[0], oe[0], base[1], len[1], key[1], oe[1], w, cnt[0], cnt[1]);
-#pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        if (t + (unsigned)h * bd >= tot) continue;
-                        const unsigned dst = (rr[h] & ~1u) * w + (e[h] - rr[h] * w) + cnt[h];
-                        s_k[isa[h] ? 0 : 1][cur ^ 1u][dst] = key[h];
-                        if (isa[h]) s_v[cur ^ 1u][dst] = s_v[cur][e[h]];
-                    }
-                }
-                cur ^= 1u;
-                __syncthreads();
-            }
+        for (unsigned t = tid; t < G + D; t += bd) {  // rank = place in the chunk + keys below in the other chunks
+            const bool is_g = t < G;
+            const unsigned e = is_g ? t : t - G, nch = is_g ? ncg : ncd, own = e / kChunk;
+            const uint32_t *kk = L.k[is_g ? 0 : 1][0];
+            const uint32_t x = kk[e];
+            unsigned rank = e - own * kChunk;
+            for (unsigned chn = 0; chn < nch; ++chn)
+                if (chn != own) rank += below_in_chunk(kk + chn * kChunk, x);
+            L.k[is_g ? 0 : 1][1][rank] = x;
+            if (is_g) L.v[1][rank] = L.v[0][e];
         }
-        const uint32_t *gsrc = s_k[0][cur], *gslot = s_v[cur], *del = s_k[1][cur];
-        // ---- tail positions: move the survivor at p into its hole, then append at p ----
+        __syncthreads();
+        const uint32_t *gslot = L.v[1], *del = L.k[1][1];
+        // ---- D: one round of loads (the recycled positions of this block's
+        //      in-place recycles, the tail survivors, the appended payloads), then
+        //      the stores ----
+        float rec[2][4];
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int f = 0; f < 4; ++f)
+                rec[q][f] = own_rec[q] && (f < dim || (f == 3 && a.e.rho_field >= 0))
+                                ? a.e.gen_new[4 * (size_t)own_slot[q] + f] : 0.0f;
         unsigned t0, t1;
         share_of(G > D ? G : D, fb, nfb, t0, t1);
         for (unsigned t = t0 + tid; t < t1; t += bd) {
             const long long pi = Np + t;
-            const bool survivor = t < D && !((s_bits[t >> 5] >> (t & 31)) & 1u);
+            const bool survivor = t < D && !((L.bits[t >> 5] >> (t & 31)) & 1u);
             const bool append = t < G;
             float v[3 + SPH_MAX_CARRIED], d[3 + SPH_MAX_CARRIED];
             int32_t lab = 0;
             int64_t id = 0;
             long long hole = 0;
             if (survivor) {  // issue every load before any store
-                const unsigned below = s_wpre[t >> 5] + (unsigned)__popc(s_bits[t >> 5] & ((1u << (t & 31)) - 1u));
+                const unsigned below = L.wpre[t >> 5] + (unsigned)__popc(L.bits[t >> 5] & ((1u << (t & 31)) - 1u));
                 hole = del[t - below];  // the k-th survivor of the tail fills the k-th smallest hole
-                const uint32_t m = s_map[t];
+                const uint32_t m = L.map[t];
                 const uint32_t ge = m & ((1u << kMapRelShift) - 1u), rl = m >> kMapRelShift;
 #pragma unroll
                 for (int q = 0; q < 3; ++q)
@@ -1744,31 +1628,36 @@ __device__ __forceinline__ void finalize_body(const FinArgs &a, const int fb, co
                 for (int f = 0; f < SPH_MAX_CARRIED; ++f)
                     if (f < nc) p.car[f][pi] = d[3 + f];
                 p.label[pi] = 0;
-                p.id[pi] = s_next + (long long)t;
+                p.id[pi] = L.next + (long long)t;
             }
         }
-        // the sorted lists for sph_last_events, after the tail loads (a wave waiting
-        // for a load also waits for the stores it issued before it)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+            if (own_rec[q]) {
+                for (int f = 0; f < dim; ++f) p.pos[f][own_i[q]] = rec[q][f];
+                if (a.e.rho_field >= 0) p.car[a.e.rho_field][own_i[q]] = rec[q][3];
+            }
+        // the sorted lists for sph_last_events
         if (fb == 0) {
-            for (unsigned j = tid; j < G; j += bd) a.gen_sorted[j] = gsrc[j];
+            for (unsigned j = tid; j < G; j += bd) a.gen_sorted[j] = L.k[0][1][j];
             for (unsigned j = tid; j < D; j += bd) a.del_sorted[j] = del[j];
         }
     }
     // ---- the last block to take a ticket publishes the result and clears the counters ----
-    if (tid == 0) s_last = ticket == (unsigned)nfb - 1u ? 1u : 0u;
+    if (tid == 0) L.last = ticket == (unsigned)nfb - 1u ? 1u : 0u;
     __syncthreads();
-    if (s_last) {
+    if (L.last) {
         sph_result *r = a.result;
         if (tid < SPH_MAX_BUFFERS) {
-            const long long nl = st == SPH_OK && tid < a.nb ? (long long)s_post[tid] : s_nl[tid];
+            const long long nl = st == SPH_OK && tid < a.nb ? (long long)L.post[tid] : L.nl[tid];
             r->n_labelled[tid] = nl;
             c->n_labelled[tid] = nl;
         }
         if (tid >= kWave && tid < kWave + kSeg) {
-            SegCtr &sc = c->seg[tid - kWave];
-            sc.n_gen = 0u;
-            sc.n_del = 0u;
-            sc.n_rel = 0u;
+            SegCtr &sc2 = c->seg[tid - kWave];
+            sc2.n_gen = 0u;
+            sc2.n_del = 0u;
+            sc2.n_rel = 0u;
         }
         if (tid == 2 * kWave) {
             r->status = st;
@@ -1777,13 +1666,13 @@ __device__ __forceinline__ void finalize_body(const FinArgs &a, const int fb, co
             r->n_deleted = st == SPH_OK ? D : 0;
             r->n_before = N;
             r->n_after = st == SPH_OK ? N - (long long)D + (long long)G : N;
-            r->next_id = st == SPH_OK ? s_next + G : s_next;
+            r->next_id = st == SPH_OK ? L.next + G : L.next;
             if (a.nf_full) c->nonfinite_full = 0u;
             c->cand_count = 0ull;
             c->cand_overflow = 0u;
             c->fin_ticket = 0u;
             if (st == SPH_OK) {
-                c->next_id = s_next + G;
+                c->next_id = L.next + G;
                 *a.p.n_dev = N - (long long)D + (long long)G;
             }
         }
@@ -1888,10 +1777,10 @@ struct BcArgs {
     Parts p;
     const BufDev *bufs;
     int nb;
+    const Ctl *ctl;            // Ctl::n_runs: length of the compact run list
     const int32_t *run_first;
     const int32_t *run_len;
     const uint8_t *run_buf;
-    int n_runs;
     const int32_t *cell_start;
     const int32_t *cell_idx;
     int32_t vel[3];
@@ -1966,16 +1855,19 @@ __device__ void rotate_one(const BcArgs &a, int64_t i, float x, float y, float z
 __global__ __launch_bounds__(kClassifyBlock) void k_buffer_bc(BcArgs a) {
     __shared__ BufDev sb[SPH_MAX_BUFFERS];
     __shared__ unsigned s_cnt[SPH_MAX_BUFFERS];
+    __shared__ int s_nruns;
     for (int t = threadIdx.x; t < a.nb * (int)(sizeof(BufDev) / 4); t += blockDim.x)
         reinterpret_cast<uint32_t *>(sb)[t] = reinterpret_cast<const uint32_t *>(a.bufs)[t];
     if (threadIdx.x < SPH_MAX_BUFFERS) s_cnt[threadIdx.x] = 0u;
+    if (threadIdx.x == 0) s_nruns = a.ctl->n_runs;
     __syncthreads();
+    const int n_runs = s_nruns;
     const int64_t N = live_count(a.p.n_dev, a.p.capacity);
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = threadIdx.x / kWave;
     const int wpb = blockDim.x / kWave;
     const int dim = a.p.dim;
-    for (int r = blockIdx.x * wpb + wave; r < a.n_runs; r += gridDim.x * wpb) {
+    for (int r = blockIdx.x * wpb + wave; r < n_runs; r += gridDim.x * wpb) {
         const int k = a.run_buf[r];
         const BufDev &b = sb[k];
         if (a.which < 0 ? b.bc_kind == SPH_BC_NONE : k != a.which) continue;  // wave-uniform
@@ -2028,6 +1920,333 @@ __global__ __launch_bounds__(kBcFinishBlock) void k_bc_finish(unsigned *found, c
             if (involved && (long long)s_tot[j] != ctl->n_labelled[j]) bad = 1;
         }
         ctl->bc_status = bad ? (unsigned)SPH_ERR_CFL : (unsigned)SPH_OK;
+    }
+}
+
+// ------------------------------------------- cover cells of a turned buffer --
+//
+// The cells of a dense grid whose boxes, dilated by eps and with the edge cells
+// extended to infinity, meet a buffer's check region (an oriented box), as the
+// host computes them at definition, here on the device for a buffer that has
+// just been turned.  Along a row of cells (fixed y and z) the cells that meet a
+// convex region form an interval; its ends are found by two binary searches on
+// unions of consecutive cells (the union of cells lo..x is one box, and whether
+// it meets the region is monotone in x).  One thread per row finds the interval
+// (k_cover_rows), then one workgroup lays the rows' runs out (k_cover_write),
+// maps them to cell keys, keeps the per-cell cover mask, and rebuilds the
+// compact run list that the classify and boundary kernels walk.
+
+struct CoverObb {
+    double c[3];
+    double ax[3][3];  // rows: local axes
+    double h[3];      // half-extents of the check region
+};
+
+// Separating-axis test of the oriented box against the axis-aligned box lo..hi
+// (true when they may intersect; a relative 1e-12 slack keeps it conservative
+// near touching), as in the host geometry.
+__device__ bool obb_meets_box(int m, const CoverObb &b, const double lo[3], const double hi[3]) {
+    double ac[3], ah[3], t[3];
+    for (int j = 0; j < 3; ++j) {
+        ac[j] = 0.5 * (lo[j] + hi[j]);
+        ah[j] = 0.5 * (hi[j] - lo[j]);
+        t[j] = ac[j] - b.c[j];
+    }
+    auto separated = [&](const double L[3]) {
+        double proj_t = 0.0, ra = 0.0, rb = 0.0;
+        for (int j = 0; j < m; ++j) {
+            proj_t += L[j] * t[j];
+            ra += ah[j] * fabs(L[j]);
+        }
+        for (int i = 0; i < m; ++i) {
+            double d = 0.0;
+            for (int j = 0; j < m; ++j) d += L[j] * b.ax[i][j];
+            rb += b.h[i] * fabs(d);
+        }
+        const double slack = 1e-12 * (fabs(proj_t) + ra + rb);
+        return fabs(proj_t) > ra + rb + slack;
+    };
+    for (int j = 0; j < m; ++j) {
+        double L[3] = {0.0, 0.0, 0.0};
+        L[j] = 1.0;
+        if (separated(L)) return false;
+    }
+    for (int i = 0; i < m; ++i)
+        if (separated(b.ax[i])) return false;
+    if (m == 3) {
+        for (int j = 0; j < 3; ++j)
+            for (int i = 0; i < 3; ++i) {
+                double E[3] = {0.0, 0.0, 0.0};
+                E[j] = 1.0;
+                const double *a = b.ax[i];
+                const double L[3] = {E[1] * a[2] - E[2] * a[1], E[2] * a[0] - E[0] * a[2], E[0] * a[1] - E[1] * a[0]};
+                if (L[0] * L[0] + L[1] * L[1] + L[2] * L[2] < 1e-20) continue;
+                if (separated(L)) return false;
+            }
+    }
+    return true;
+}
+
+struct CoverArgs {
+    Ctl *ctl;
+    int k, dim;
+    CoverObb obb;
+    double blo[3], bhi[3];       // axis-aligned box of the check region
+    double glo[3], cs, eps;      // grid origin, cell size, dilation of the cell boxes
+    int32_t dims[3];
+    int32_t lo_i[3], hi_i[3];    // cells to consider (inclusive)
+    int32_t *row_lo, *row_hi;    // per row (y fastest, then z): covered x interval (lo > hi: none)
+    int64_t max_rows;
+    // k_cover_write
+    BufDev rec;                  // the turned buffer's record
+    BufDev *bufs;
+    int nb;
+    int cap;                     // cells per run at most
+    int32_t rbase[SPH_MAX_BUFFERS], rmax[SPH_MAX_BUFFERS];
+    int32_t *src_first, *src_len;
+    int32_t *run_first, *run_len;
+    uint8_t *run_buf;
+    unsigned *cover;             // per-cell mask (two 16-bit cells per word), or null
+    Grid g;                      // key mapping (dense or brick-sparse)
+};
+
+// Box of the cells ix0..ix1 of row (iy, iz), dilated and edge-extended.
+__device__ void cells_box(const CoverArgs &a, int ix0, int ix1, int iy, int iz, double lo[3], double hi[3]) {
+    const int idx0[3] = {ix0, iy, iz}, idx1[3] = {ix1, iy, iz};
+    for (int j = 0; j < 3; ++j) {
+        lo[j] = hi[j] = 0.0;
+        if (j >= a.dim) continue;
+        lo[j] = a.glo[j] + idx0[j] * a.cs - a.eps;
+        hi[j] = a.glo[j] + (idx1[j] + 1) * a.cs + a.eps;
+        if (idx0[j] == 0) lo[j] = fmin(lo[j], a.blo[j] - a.cs);
+        if (idx1[j] == a.dims[j] - 1) hi[j] = fmax(hi[j], a.bhi[j] + a.cs);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_cover_rows(CoverArgs a) {
+    const int ny = a.hi_i[1] - a.lo_i[1] + 1;
+    const int nz = a.dim == 3 ? a.hi_i[2] - a.lo_i[2] + 1 : 1;
+    const int64_t rows = (int64_t)ny * nz;
+    // the buffer's old cover leaves the mask (its new one is set by k_cover_write)
+    if (a.cover) {
+        const int n_old = a.ctl->run_cnt[a.k];
+        const unsigned clear = ~(1u << a.k);
+        for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n_old; r += gridDim.x * blockDim.x) {
+            const int32_t f = a.src_first[a.rbase[a.k] + r], l = a.src_len[a.rbase[a.k] + r];
+            for (int32_t q = 0; q < l; ++q) {
+                const uint32_t key = (uint32_t)(f + q);
+                atomicAnd(&a.cover[key >> 1], (key & 1u) ? ((clear << 16) | 0xffffu) : (clear | 0xffff0000u));
+            }
+        }
+    }
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < rows && r < a.max_rows;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const int iy = a.lo_i[1] + (int)(r % ny), iz = a.dim == 3 ? a.lo_i[2] + (int)(r / ny) : 0;
+        const int x0 = a.lo_i[0], x1 = a.hi_i[0];
+        double lo[3], hi[3];
+        int xa = x1 + 1, xb = x0 - 1;
+        cells_box(a, x0, x1, iy, iz, lo, hi);
+        if (obb_meets_box(a.dim, a.obb, lo, hi)) {
+            // leftmost x whose union x0..x meets the region, rightmost whose union x..x1 does
+            int l = x0 - 1, h = x1;  // P(l) false (empty union), P(h) true
+            while (h - l > 1) {
+                const int mid = l + (h - l) / 2;
+                cells_box(a, x0, mid, iy, iz, lo, hi);
+                if (obb_meets_box(a.dim, a.obb, lo, hi)) h = mid;
+                else l = mid;
+            }
+            xa = h;
+            l = x0;
+            h = x1 + 1;  // Q(l) true, Q(h) false (empty union)
+            while (h - l > 1) {
+                const int mid = l + (h - l) / 2;
+                cells_box(a, mid, x1, iy, iz, lo, hi);
+                if (obb_meets_box(a.dim, a.obb, lo, hi)) l = mid;
+                else h = mid;
+            }
+            xb = l;
+        }
+        a.row_lo[r] = xa;
+        a.row_hi[r] = xb;
+    }
+}
+
+// Runs of row r (covered cells xa..xb) as keys: consecutive keys, at most cap
+// cells; on the brick-sparse grid a run also ends at a brick face, and cells of
+// inactive bricks are left to the overflow cell (reported through *ovf).
+template <bool kWrite>
+__device__ int row_runs(const CoverArgs &a, int xa, int xb, int iy, int iz, int32_t *first, int32_t *len, bool &ovf) {
+    int n = 0;
+    uint32_t start = 0, prev = 0;
+    int cur = 0;
+    for (int ix = xa; ix <= xb; ++ix) {
+        const uint32_t key = key_of_cell(a.g, (uint32_t)ix, (uint32_t)iy, (uint32_t)iz);
+        if (a.g.blog2 > 0 && key == a.g.overflow_key) {
+            ovf = true;
+            if (cur > 0) {
+                if (kWrite) {
+                    first[n] = (int32_t)start;
+                    len[n] = cur;
+                }
+                ++n;
+                cur = 0;
+            }
+            continue;
+        }
+        if (cur > 0 && key == prev + 1u && cur < a.cap) {
+            ++cur;
+        } else {
+            if (cur > 0) {
+                if (kWrite) {
+                    first[n] = (int32_t)start;
+                    len[n] = cur;
+                }
+                ++n;
+            }
+            start = key;
+            cur = 1;
+        }
+        prev = key;
+    }
+    if (cur > 0) {
+        if (kWrite) {
+            first[n] = (int32_t)start;
+            len[n] = cur;
+        }
+        ++n;
+    }
+    return n;
+}
+
+constexpr int kCoverBlock = 1024;
+
+// One workgroup: the turned buffer's record, its runs from the row intervals, its
+// mask bits and run count, then the compact run list of every buffer.
+__global__ __launch_bounds__(kCoverBlock) void k_cover_write(CoverArgs a) {
+    __shared__ int s_wave[kCoverBlock / kWave];
+    __shared__ int s_base, s_ovf;
+    __shared__ int s_pre[SPH_MAX_BUFFERS + 1];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    if (tid == 0) {
+        s_base = 0;
+        s_ovf = 0;
+    }
+    for (int w = tid; w < (int)(sizeof(BufDev) / 4); w += blockDim.x)
+        reinterpret_cast<uint32_t *>(a.bufs + a.k)[w] = reinterpret_cast<const uint32_t *>(&a.rec)[w];
+    __syncthreads();
+    const int ny = a.hi_i[1] - a.lo_i[1] + 1;
+    const int nz = a.dim == 3 ? a.hi_i[2] - a.lo_i[2] + 1 : 1;
+    const int64_t rows = min((int64_t)ny * nz, a.max_rows);
+    int32_t *df = a.src_first + a.rbase[a.k], *dl = a.src_len + a.rbase[a.k];
+    for (int64_t r0 = 0; r0 < rows; r0 += blockDim.x) {  // block-uniform
+        const int64_t r = r0 + tid;
+        int xa = 0, xb = -1, iy = 0, iz = 0;
+        if (r < rows) {
+            xa = a.row_lo[r];
+            xb = a.row_hi[r];
+            iy = a.lo_i[1] + (int)(r % ny);
+            iz = a.dim == 3 ? a.lo_i[2] + (int)(r / ny) : 0;
+        }
+        bool ovf = false;
+        const int n = xa <= xb ? row_runs<false>(a, xa, xb, iy, iz, nullptr, nullptr, ovf) : 0;
+        if (ovf) s_ovf = 1;
+        int incl = n;
+        for (int off = 1; off < kWave; off <<= 1) {
+            const int t = __shfl_up(incl, off);
+            if (lane >= off) incl += t;
+        }
+        if (lane == kWave - 1) s_wave[wave] = incl;
+        __syncthreads();
+        int before = s_base;
+        for (int w = 0; w < wave; ++w) before += s_wave[w];
+        int total = 0;
+        for (int w = 0; w < (int)(blockDim.x / kWave); ++w) total += s_wave[w];
+        const int at = before + incl - n;
+        if (n > 0 && at + n <= a.rmax[a.k]) row_runs<true>(a, xa, xb, iy, iz, df + at, dl + at, ovf);
+        __syncthreads();
+        if (tid == 0) s_base += total;
+        __syncthreads();
+    }
+    int cnt = s_base;
+    if (s_ovf && a.g.blog2 > 0) {  // every inactive brick is one overflow cell: one run for it
+        if (tid == 0 && cnt < a.rmax[a.k]) {
+            df[cnt] = (int32_t)a.g.overflow_key;
+            dl[cnt] = 1;
+        }
+        ++cnt;
+    }
+    if (cnt > a.rmax[a.k]) {  // cannot happen with the range sized from the sphere bound; keep what fits
+        if (tid == 0) {
+            a.ctl->cover_fault = 1;
+            a.ctl->bc_status = (unsigned)SPH_ERR_HIP;
+        }
+        cnt = a.rmax[a.k];
+    }
+    __syncthreads();
+    if (a.cover) {  // the new cover's mask bits
+        for (int r = tid; r < cnt; r += blockDim.x)
+            for (int32_t q = 0; q < dl[r]; ++q) {
+                const uint32_t key = (uint32_t)(df[r] + q);
+                atomicOr(&a.cover[key >> 1], (1u << a.k) << ((key & 1u) * 16u));
+            }
+    }
+    // the compact list of every buffer's runs
+    if (tid == 0) {
+        int acc = 0;
+        for (int k = 0; k < a.nb; ++k) {
+            const int c = k == a.k ? cnt : a.ctl->run_cnt[k];
+            s_pre[k] = acc;
+            acc += c;
+        }
+        s_pre[a.nb] = acc;
+        a.ctl->run_cnt[a.k] = cnt;
+        a.ctl->n_runs = acc;
+    }
+    __syncthreads();
+    for (int k = 0; k < a.nb; ++k) {
+        const int c = s_pre[k + 1] - s_pre[k];
+        for (int q = tid; q < c; q += blockDim.x) {
+            a.run_first[s_pre[k] + q] = a.src_first[a.rbase[k] + q];
+            a.run_len[s_pre[k] + q] = a.src_len[a.rbase[k] + q];
+            a.run_buf[s_pre[k] + q] = (uint8_t)k;
+        }
+    }
+}
+
+// Compact run list from the per-buffer ranges (after a definition or a grid fit).
+__global__ __launch_bounds__(kCoverBlock) void k_runs_assemble(CoverArgs a) {
+    __shared__ int s_pre[SPH_MAX_BUFFERS + 1];
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        int acc = 0;
+        for (int k = 0; k < a.nb; ++k) {
+            s_pre[k] = acc;
+            acc += a.ctl->run_cnt[k];
+        }
+        s_pre[a.nb] = acc;
+        a.ctl->n_runs = acc;
+    }
+    __syncthreads();
+    for (int k = 0; k < a.nb; ++k) {
+        const int c = s_pre[k + 1] - s_pre[k];
+        for (int q = tid; q < c; q += blockDim.x) {
+            a.run_first[s_pre[k] + q] = a.src_first[a.rbase[k] + q];
+            a.run_len[s_pre[k] + q] = a.src_len[a.rbase[k] + q];
+            a.run_buf[s_pre[k] + q] = (uint8_t)k;
+        }
+    }
+}
+
+// Per-cell cover mask from the compact run list (the mask is cleared before).
+__global__ __launch_bounds__(256) void k_mask_set(CoverArgs a) {
+    const int n = a.ctl->n_runs;
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+        const int32_t f = a.run_first[r], l = a.run_len[r];
+        const unsigned bit = 1u << a.run_buf[r];
+        for (int32_t q = 0; q < l; ++q) {
+            const uint32_t key = (uint32_t)(f + q);
+            atomicOr(&a.cover[key >> 1], bit << ((key & 1u) * 16u));
+        }
     }
 }
 
@@ -2215,13 +2434,19 @@ struct sph_ctx {
     BufDev hb[SPH_MAX_BUFFERS];
     double b_origin[SPH_MAX_BUFFERS][3], b_rot[SPH_MAX_BUFFERS][9], b_half[SPH_MAX_BUFFERS][3],
         b_margin[SPH_MAX_BUFFERS];
-    std::vector<int32_t> h_run_first, h_run_len;
-    std::vector<uint8_t> h_run_buf;
+    // Cover runs: buffer k's runs live in its own range [rbase[k], rbase[k] + rmax[k])
+    // of d_src_* (sized for any orientation, so a turn recomputes them in place on
+    // the device); the compact list d_run_* (all buffers' runs back to back, count
+    // in Ctl::n_runs) is what the classify and boundary kernels walk.
+    int32_t rbase[SPH_MAX_BUFFERS] = {}, rmax[SPH_MAX_BUFFERS] = {}, hcnt[SPH_MAX_BUFFERS] = {};
+    int64_t src_cap = 0, max_rows = 0;
+    int32_t *d_src_first = nullptr, *d_src_len = nullptr;
+    int32_t *d_row_lo = nullptr, *d_row_hi = nullptr;  // per-row intervals of a turned buffer's cover
 
     BufDev *d_bufs = nullptr;
     int32_t *d_run_first = nullptr, *d_run_len = nullptr;
     uint8_t *d_run_buf = nullptr;
-    int n_runs = 0;
+    int n_runs = 0;  // runs at the last host computation (launch sizes; the kernels read Ctl::n_runs)
 
     int32_t *d_count = nullptr, *d_cell_start = nullptr, *d_cell_idx = nullptr;
     unsigned long long *d_cand = nullptr;        // candidate list of the full scan
@@ -2275,6 +2500,7 @@ namespace {
     } while (0)
 
 constexpr size_t kProfSlots = 8192;
+constexpr int kBatchPhases = 5;  // count, scan, scatter, classify, finalize
 
 // Bracket one launch with events when profiling is on (a no-op otherwise).
 struct ProfScope {
@@ -2421,7 +2647,6 @@ LocalArgs local_args(const sph_ctx *ctx, const Parts &pp) {
     la.run_first = ctx->d_run_first;
     la.run_len = ctx->d_run_len;
     la.run_buf = ctx->d_run_buf;
-    la.n_runs = ctx->n_runs;
     la.cell_start = ctx->d_cell_start;
     la.cell_idx = ctx->d_cell_idx;
     la.e = events_of(ctx);
@@ -2503,6 +2728,10 @@ void free_ctx(sph_ctx *c) {
     (void)hipFree(c->d_run_first);
     (void)hipFree(c->d_run_len);
     (void)hipFree(c->d_run_buf);
+    (void)hipFree(c->d_src_first);
+    (void)hipFree(c->d_src_len);
+    (void)hipFree(c->d_row_lo);
+    (void)hipFree(c->d_row_hi);
     (void)hipFree(c->d_count);
     (void)hipFree(c->d_brick_slot);
     (void)hipFree(c->d_cell_start);
@@ -2633,58 +2862,135 @@ static sph_status cover_runs(const sph_ctx *ctx, const double o[3], const double
     return SPH_OK;
 }
 
-// Replace the device copy of the run list of all buffers (allocation: setup only).
-static sph_status upload_runs(sph_ctx *ctx, std::vector<int32_t> &rf, std::vector<int32_t> &rl,
-                              std::vector<uint8_t> &rb) {
-    int32_t *nf = nullptr, *nl = nullptr;
-    uint8_t *nbuf = nullptr;
-    const size_t nr = rf.size();
-    if (nr > 0) {
-        if (hipMalloc(&nf, sizeof(int32_t) * nr) != hipSuccess || hipMalloc(&nl, sizeof(int32_t) * nr) != hipSuccess ||
-            hipMalloc(&nbuf, nr) != hipSuccess) {
-            (void)hipFree(nf);
-            (void)hipFree(nl);
-            (void)hipFree(nbuf);
-            return SPH_ERR_HIP;
-        }
-        if (hipMemcpyAsync(nf, rf.data(), sizeof(int32_t) * nr, hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
-            hipMemcpyAsync(nl, rl.data(), sizeof(int32_t) * nr, hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
-            hipMemcpyAsync(nbuf, rb.data(), nr, hipMemcpyHostToDevice, ctx->stream) != hipSuccess)
-            return SPH_ERR_HIP;
+// Cells of a run at most (a wave of the classify takes a few runs).
+static int run_cap(const sph_ctx *ctx) { return ctx->dim == 3 ? 4 : 12; }
+
+// Size of a buffer's run range: its cover in any orientation.  The check box lies
+// in the sphere of radius R around its origin, so in at most n = 2 (R + eps) / cs
+// + 4 cells per axis, n^(d-1) rows of at most n + 1 runs each, plus the overflow
+// cell of a brick-sparse grid.
+static void run_range(const sph_ctx *ctx, const double h[3], double margin, int32_t &rmax, int64_t &rows) {
+    const double R = sphbuf::sphere_radius(ctx->dim, h, margin);
+    const double err = sphbuf::binning_error_cells(ctx->dim, ctx->lo, ctx->cs, ctx->dims);
+    const double eps = std::max(1e-2, 1.5 * err) * ctx->cs;
+    const int64_t n = (int64_t)std::ceil(2.0 * (R + eps) / ctx->cs) + 4;
+    rows = ctx->dim == 3 ? n * n : n;
+    rmax = (int32_t)std::min<int64_t>(rows * (n + 1) + 1, (int64_t)1 << 30);
+}
+
+static CoverArgs cover_args(const sph_ctx *ctx) {
+    CoverArgs a{};
+    a.ctl = ctx->d_ctl;
+    a.dim = ctx->dim;
+    a.nb = ctx->nb;
+    a.cap = run_cap(ctx);
+    for (int k = 0; k < SPH_MAX_BUFFERS; ++k) {
+        a.rbase[k] = ctx->rbase[k];
+        a.rmax[k] = ctx->rmax[k];
     }
-    // per-cell cover mask for the classification of the merged step
-    std::vector<uint16_t> mask;
+    a.src_first = ctx->d_src_first;
+    a.src_len = ctx->d_src_len;
+    a.run_first = ctx->d_run_first;
+    a.run_len = ctx->d_run_len;
+    a.run_buf = ctx->d_run_buf;
+    a.cover = ctx->merged ? reinterpret_cast<unsigned *>(ctx->d_cover) : nullptr;
+    a.g = grid_of(ctx);
+    for (int c = 0; c < 3; ++c) {
+        a.glo[c] = ctx->lo[c];
+        a.dims[c] = ctx->dims[c];
+    }
+    a.cs = ctx->cs;
+    a.row_lo = ctx->d_row_lo;
+    a.row_hi = ctx->d_row_hi;
+    a.max_rows = ctx->max_rows;
+    return a;
+}
+
+// Grow the per-buffer run ranges and the compact list to hold buffer k's range
+// (setup: allocates, copies the other buffers' runs over).
+static sph_status grow_ranges(sph_ctx *ctx, int k, int32_t rmax, int64_t rows) {
+    const int64_t cap = ctx->src_cap + rmax;
+    int32_t *sf = nullptr, *sl = nullptr, *rf = nullptr, *rl = nullptr, *lo = nullptr, *hi = nullptr;
+    uint8_t *rb = nullptr;
+    const int64_t mr = std::max(ctx->max_rows, rows);
+    bool ok = hipMalloc(&sf, sizeof(int32_t) * cap) == hipSuccess && hipMalloc(&sl, sizeof(int32_t) * cap) == hipSuccess &&
+              hipMalloc(&rf, sizeof(int32_t) * cap) == hipSuccess && hipMalloc(&rl, sizeof(int32_t) * cap) == hipSuccess &&
+              hipMalloc(&rb, (size_t)cap) == hipSuccess && hipMalloc(&lo, sizeof(int32_t) * mr) == hipSuccess &&
+              hipMalloc(&hi, sizeof(int32_t) * mr) == hipSuccess;
+    if (ok && ctx->src_cap > 0)
+        ok = hipMemcpyAsync(sf, ctx->d_src_first, sizeof(int32_t) * ctx->src_cap, hipMemcpyDeviceToDevice,
+                            ctx->stream) == hipSuccess &&
+             hipMemcpyAsync(sl, ctx->d_src_len, sizeof(int32_t) * ctx->src_cap, hipMemcpyDeviceToDevice,
+                            ctx->stream) == hipSuccess;
+    if (ok) ok = hipStreamSynchronize(ctx->stream) == hipSuccess;
+    if (!ok) {
+        for (void *q : {(void *)sf, (void *)sl, (void *)rf, (void *)rl, (void *)rb, (void *)lo, (void *)hi})
+            (void)hipFree(q);
+        return SPH_ERR_HIP;
+    }
+    for (void *q : {(void *)ctx->d_src_first, (void *)ctx->d_src_len, (void *)ctx->d_run_first,
+                    (void *)ctx->d_run_len, (void *)ctx->d_run_buf, (void *)ctx->d_row_lo, (void *)ctx->d_row_hi})
+        (void)hipFree(q);
+    ctx->d_src_first = sf;
+    ctx->d_src_len = sl;
+    ctx->d_run_first = rf;
+    ctx->d_run_len = rl;
+    ctx->d_run_buf = rb;
+    ctx->d_row_lo = lo;
+    ctx->d_row_hi = hi;
+    ctx->rbase[k] = (int32_t)ctx->src_cap;
+    ctx->rmax[k] = rmax;
+    ctx->src_cap = cap;
+    ctx->max_rows = mr;
+    ctx->layout_gen++;
+    return SPH_OK;
+}
+
+// Install host-computed runs of the given buffers into their ranges, rebuild the
+// compact list and the per-cell cover mask (setup: waits for the stream).
+static sph_status install_runs(sph_ctx *ctx, const std::vector<int> &which,
+                               const std::vector<std::vector<int32_t>> &first,
+                               const std::vector<std::vector<int32_t>> &len) {
+    for (size_t w = 0; w < which.size(); ++w) {
+        const int k = which[w];
+        const size_t nr = first[w].size();
+        if ((int64_t)nr > ctx->rmax[k]) return SPH_ERR_ARG;  // cannot happen: the range holds any orientation
+        if (nr > 0) {
+            HIP_TRY(hipMemcpyAsync(ctx->d_src_first + ctx->rbase[k], first[w].data(), sizeof(int32_t) * nr,
+                                   hipMemcpyHostToDevice, ctx->stream));
+            HIP_TRY(hipMemcpyAsync(ctx->d_src_len + ctx->rbase[k], len[w].data(), sizeof(int32_t) * nr,
+                                   hipMemcpyHostToDevice, ctx->stream));
+        }
+        ctx->hcnt[k] = (int32_t)nr;
+    }
+    HIP_TRY(hipMemcpyAsync(ctx->d_ctl->run_cnt, ctx->hcnt, sizeof(int32_t) * SPH_MAX_BUFFERS, hipMemcpyHostToDevice,
+                           ctx->stream));
+    // the cover mask of the merged step (two 16-bit cells per word)
     if (ctx->merged) {
+        const int64_t words = (ctx->n_cells + 1) / 2;
         if (ctx->cover_cells != ctx->n_cells) {
             HIP_TRY(hipStreamSynchronize(ctx->stream));
             (void)hipFree(ctx->d_cover);
             ctx->d_cover = nullptr;
             ctx->cover_cells = 0;
-            HIP_TRY(hipMalloc(&ctx->d_cover, sizeof(uint16_t) * (size_t)ctx->n_cells));
+            HIP_TRY(hipMalloc(&ctx->d_cover, sizeof(uint32_t) * (size_t)words));
             ctx->cover_cells = ctx->n_cells;
         }
-        mask.assign((size_t)ctx->n_cells, 0);
-        for (size_t r = 0; r < nr; ++r)
-            for (int32_t q = 0; q < rl[r]; ++q) {
-                const int64_t key = (int64_t)rf[r] + q;
-                if (key >= 0 && key < ctx->n_cells) mask[(size_t)key] |= (uint16_t)(1u << rb[r]);
-            }
-        HIP_TRY(hipMemcpyAsync(ctx->d_cover, mask.data(), sizeof(uint16_t) * mask.size(), hipMemcpyHostToDevice,
-                               ctx->stream));
+        HIP_TRY(hipMemsetAsync(ctx->d_cover, 0, sizeof(uint32_t) * (size_t)words, ctx->stream));
+    }
+    CoverArgs a = cover_args(ctx);
+    hipLaunchKernelGGL(k_runs_assemble, dim3(1), dim3(kCoverBlock), 0, ctx->stream, a);
+    HIP_TRY(hipGetLastError());
+    int64_t total = 0;
+    for (int k = 0; k < ctx->nb; ++k) total += ctx->hcnt[k];
+    if (ctx->merged && total > 0) {
+        const int blocks = (int)std::min<int64_t>(1024, (total + 255) / 256);
+        hipLaunchKernelGGL(k_mask_set, dim3(blocks), dim3(256), 0, ctx->stream, a);
+        HIP_TRY(hipGetLastError());
     }
     HIP_TRY(hipStreamSynchronize(ctx->stream));
+    ctx->n_runs = (int)total;
     ctx->built = false;  // covers changed: the next update needs a build with them
-    ctx->layout_gen++;
-    (void)hipFree(ctx->d_run_first);
-    (void)hipFree(ctx->d_run_len);
-    (void)hipFree(ctx->d_run_buf);
-    ctx->d_run_first = nf;
-    ctx->d_run_len = nl;
-    ctx->d_run_buf = nbuf;
-    ctx->n_runs = (int)nr;
-    ctx->h_run_first.swap(rf);
-    ctx->h_run_len.swap(rl);
-    ctx->h_run_buf.swap(rb);
     return SPH_OK;
 }
 
@@ -2845,24 +3151,26 @@ extern "C" sph_status sph_buffer_define(sph_ctx *ctx, sph_kind kind, const doubl
 
     const int k = ctx->nb;
     const BufDev b = frame_record(ctx, kind, o, q, h, margin);
-
-    // rebuild the device run list with the new buffer's runs appended
-    std::vector<int32_t> rf = ctx->h_run_first, rl = ctx->h_run_len;
-    std::vector<uint8_t> rb = ctx->h_run_buf;
-    rf.insert(rf.end(), first.begin(), first.end());
-    rl.insert(rl.end(), len.begin(), len.end());
-    rb.insert(rb.end(), first.size(), (uint8_t)k);
+    // the new buffer's run range (sized for any orientation), its runs, the
+    // compact list and the mask
+    int32_t rmax = 0;
+    int64_t rows = 0;
+    run_range(ctx, h, margin, rmax, rows);
+    HIP_CHECKED(grow_ranges(ctx, k, rmax, rows));
     ctx->hb[k] = b;
     HIP_TRY(hipMemcpyAsync(ctx->d_bufs + k, &ctx->hb[k], sizeof(BufDev), hipMemcpyHostToDevice, ctx->stream));
-    const sph_status us = upload_runs(ctx, rf, rl, rb);
-    if (us != SPH_OK) return us;
+    ctx->nb = k + 1;
+    const sph_status us = install_runs(ctx, {k}, {first}, {len});
+    if (us != SPH_OK) {
+        ctx->nb = k;
+        return us;
+    }
     for (int c = 0; c < 3; ++c) {
         ctx->b_origin[k][c] = o[c];
         ctx->b_half[k][c] = h[c];
     }
     std::copy(q, q + 9, ctx->b_rot[k]);
     ctx->b_margin[k] = margin;
-    ctx->nb = k + 1;
     if (buffer_id) *buffer_id = k + 1;
     return SPH_OK;
 }
@@ -2967,8 +3275,7 @@ extern "C" sph_status sph_buffer_update_async(sph_ctx *ctx, sph_particles *p) {
     int n_part = 0;
     if (ctx->n_runs > 0) {
         const LocalArgs la = local_args(ctx, pp);
-        const int wpb = kClassifyBlock / kWave;
-        n_part = std::max(1, std::min(kMaxPartBlocks, (ctx->n_runs + wpb - 1) / wpb));
+        n_part = std::max(1, std::min(kMaxPartBlocks, (ctx->n_runs + kRunsPerBlock - 1) / kRunsPerBlock));
         ProfScope ps(ctx, SPH_PHASE_CLASSIFY);
         hipLaunchKernelGGL(k_classify_local, dim3(n_part), dim3(kClassifyBlock), 0, ctx->stream, la);
         HIP_TRY(hipGetLastError());
@@ -3166,7 +3473,7 @@ static sph_status launch_buffer_pass(sph_ctx *ctx, const Parts &pp, int which, c
     a.run_first = ctx->d_run_first;
     a.run_len = ctx->d_run_len;
     a.run_buf = ctx->d_run_buf;
-    a.n_runs = ctx->n_runs;
+    a.ctl = ctx->d_ctl;
     a.cell_start = ctx->d_cell_start;
     a.cell_idx = ctx->d_cell_idx;
     for (int c = 0; c < 3; ++c) a.vel[c] = c < ctx->dim ? ctx->fields.vel[c] : -1;
@@ -3195,7 +3502,7 @@ static sph_status read_bc_status(sph_ctx *ctx) {
     return (sph_status)*ctx->h_bc_status;
 }
 
-extern "C" sph_status sph_buffer_apply_bc(sph_ctx *ctx, sph_particles *p) {
+extern "C" sph_status sph_buffer_apply_bc_async(sph_ctx *ctx, sph_particles *p) {
     if (!ctx) return SPH_ERR_ARG;
     HIP_CHECKED(merged_drop(ctx, false));
     Parts pp;
@@ -3203,8 +3510,16 @@ extern "C" sph_status sph_buffer_apply_bc(sph_ctx *ctx, sph_particles *p) {
     if (st != SPH_OK) return st;
     if (!velocity_fields_ok(ctx, pp)) return SPH_ERR_ARG;
     if (!ctx->built) return SPH_ERR_STATE;
-    const sph_status ls = launch_buffer_pass(ctx, pp, -1, nullptr, nullptr);
-    if (ls != SPH_OK) return ls;
+    return launch_buffer_pass(ctx, pp, -1, nullptr, nullptr);
+}
+
+extern "C" sph_status sph_buffer_apply_bc(sph_ctx *ctx, sph_particles *p) {
+    HIP_CHECKED(sph_buffer_apply_bc_async(ctx, p));
+    return read_bc_status(ctx);
+}
+
+extern "C" sph_status sph_last_bc_status(sph_ctx *ctx) {
+    if (!ctx) return SPH_ERR_ARG;
     return read_bc_status(ctx);
 }
 
@@ -3217,8 +3532,8 @@ static void mat_vec_host(int dim, const double m[9], const double x[3], double y
     }
 }
 
-extern "C" sph_status sph_buffer_rotate(sph_ctx *ctx, sph_particles *p, int32_t buffer_id, const double center[3],
-                                        const double m[9]) {
+extern "C" sph_status sph_buffer_rotate_async(sph_ctx *ctx, sph_particles *p, int32_t buffer_id,
+                                              const double center[3], const double m[9]) {
     if (!ctx || !center || !m || buffer_id < 1 || buffer_id > ctx->nb) return SPH_ERR_ARG;
     HIP_CHECKED(merged_drop(ctx, false));
     const int dim = ctx->dim;
@@ -3252,35 +3567,70 @@ extern "C" sph_status sph_buffer_rotate(sph_ctx *ctx, sph_particles *p, int32_t 
         if (j != k && sphbuf::check_regions_overlap(dim, o, q, ctx->b_half[k], ctx->b_margin[k], ctx->b_origin[j],
                                                     ctx->b_rot[j], ctx->b_half[j], ctx->b_margin[j]))
             return SPH_ERR_OVERLAP;
-    std::vector<int32_t> first, len;
+    // where the turned check region's cover is searched (host FP64, no device work)
+    sphbuf::CoverBox cb;
     {
-        const sph_status cs = cover_runs(ctx, o, q, ctx->b_half[k], ctx->b_margin[k], first, len);
+        const sph_status cs =
+            sphbuf::cover_box(dim, ctx->lo, ctx->cs, ctx->dims, o, q, ctx->b_half[k], ctx->b_margin[k], cb);
         if (cs != SPH_OK) return cs;
     }
-    // turn the particles with the old frame and cover, then install the new ones
+    // turn the particles with the old frame and cover, then compute the new cover on
+    // the device: its rows (k_cover_rows), then its runs, mask bits, the new frame
+    // record and the compact run list (k_cover_write); nothing waits for the stream
     const sph_status ls = launch_buffer_pass(ctx, pp, k, center, m);
     if (ls != SPH_OK) return ls;
     BufDev b = frame_record(ctx, ctx->hb[k].kind, o, q, ctx->b_half[k], ctx->b_margin[k]);
     copy_bc(b, ctx->hb[k]);
     ctx->hb[k] = b;
-    HIP_TRY(hipMemcpyAsync(ctx->d_bufs + k, &ctx->hb[k], sizeof(BufDev), hipMemcpyHostToDevice, ctx->stream));
-    std::vector<int32_t> rf, rl;
-    std::vector<uint8_t> rb;
-    for (size_t r = 0; r < ctx->h_run_buf.size(); ++r)
-        if (ctx->h_run_buf[r] != (uint8_t)k) {
-            rf.push_back(ctx->h_run_first[r]);
-            rl.push_back(ctx->h_run_len[r]);
-            rb.push_back(ctx->h_run_buf[r]);
-        }
-    rf.insert(rf.end(), first.begin(), first.end());
-    rl.insert(rl.end(), len.begin(), len.end());
-    rb.insert(rb.end(), first.size(), (uint8_t)k);
-    const sph_status us = upload_runs(ctx, rf, rl, rb);  // waits for the stream
-    if (us != SPH_OK) return us;
+    CoverArgs ca = cover_args(ctx);
+    ca.k = k;
+    for (int i = 0; i < 3; ++i) {
+        ca.obb.c[i] = cb.c[i];
+        ca.obb.h[i] = cb.h[i];
+        for (int j = 0; j < 3; ++j) ca.obb.ax[i][j] = cb.ax[i][j];
+        ca.blo[i] = cb.blo[i];
+        ca.bhi[i] = cb.bhi[i];
+        ca.lo_i[i] = cb.lo_i[i];
+        ca.hi_i[i] = cb.hi_i[i];
+    }
+    ca.eps = cb.eps;
+    ca.rec = b;
+    ca.bufs = ctx->d_bufs;
+    {
+        const int64_t rows = (int64_t)(cb.hi_i[1] - cb.lo_i[1] + 1) * (dim == 3 ? cb.hi_i[2] - cb.lo_i[2] + 1 : 1);
+        const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(256, (std::max(rows, (int64_t)ctx->hcnt[k]) + 255) / 256));
+        ProfScope ps(ctx, SPH_PHASE_COVER);
+        hipLaunchKernelGGL(k_cover_rows, dim3(blocks), dim3(256), 0, ctx->stream, ca);
+        hipLaunchKernelGGL(k_cover_write, dim3(1), dim3(kCoverBlock), 0, ctx->stream, ca);
+    }
+    HIP_TRY(hipGetLastError());
     for (int c = 0; c < 3; ++c) ctx->b_origin[k][c] = o[c];
     std::copy(q, q + 9, ctx->b_rot[k]);
     ctx->built = false;  // the buffer's particles moved
+    return SPH_OK;
+}
+
+extern "C" sph_status sph_buffer_rotate(sph_ctx *ctx, sph_particles *p, int32_t buffer_id, const double center[3],
+                                        const double m[9]) {
+    HIP_CHECKED(sph_buffer_rotate_async(ctx, p, buffer_id, center, m));
     return read_bc_status(ctx);
+}
+
+extern "C" sph_status sph_buffer_cover(sph_ctx *ctx, int32_t buffer_id, int32_t *first, int32_t *len, int64_t cap,
+                                       int64_t *n_runs) {
+    if (!ctx || !n_runs || buffer_id < 1 || buffer_id > ctx->nb || cap < 0) return SPH_ERR_ARG;
+    const int k = buffer_id - 1;
+    int32_t cnt = 0;
+    HIP_TRY(hipMemcpyAsync(&cnt, &ctx->d_ctl->run_cnt[k], sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    *n_runs = cnt;
+    if (cnt > cap) return SPH_ERR_ARG;
+    if (cnt > 0) {
+        if (!first || !len) return SPH_ERR_ARG;
+        HIP_TRY(hipMemcpy(first, ctx->d_src_first + ctx->rbase[k], sizeof(int32_t) * cnt, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(len, ctx->d_src_len + ctx->rbase[k], sizeof(int32_t) * cnt, hipMemcpyDeviceToHost));
+    }
+    return SPH_OK;
 }
 
 extern "C" sph_status sph_buffer_identify(sph_ctx *ctx, sph_particles *p, int32_t buffer_id) {
@@ -3457,18 +3807,18 @@ extern "C" sph_status sph_grid_fit(sph_ctx *ctx, const sph_particles *p) {
     ctx->rbits = rank_bits(cells);
     ctx->n_tiles = tiles;
     ctx->built = false;
-    // candidate cells of every buffer in the new key space
-    std::vector<int32_t> rf, rl;
-    std::vector<uint8_t> rb;
+    // candidate cells of every buffer in the new key space (frames as they are now)
+    std::vector<int> which;
+    std::vector<std::vector<int32_t>> rf, rl;
     for (int k = 0; k < ctx->nb; ++k) {
         std::vector<int32_t> f, l;
         const sph_status cs = cover_runs(ctx, ctx->b_origin[k], ctx->b_rot[k], ctx->b_half[k], ctx->b_margin[k], f, l);
         if (cs != SPH_OK) return cs;
-        rf.insert(rf.end(), f.begin(), f.end());
-        rl.insert(rl.end(), l.begin(), l.end());
-        rb.insert(rb.end(), f.size(), (uint8_t)k);
+        which.push_back(k);
+        rf.push_back(std::move(f));
+        rl.push_back(std::move(l));
     }
-    return upload_runs(ctx, rf, rl, rb);
+    return install_runs(ctx, which, rf, rl);
 }
 
 // ================================================================== batches ==
@@ -3493,6 +3843,13 @@ struct sph_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     sph_result *h_res = nullptr;  // pinned, one per domain
+    // optional per-launch timing of the five launches (launch mode only)
+    bool prof_on = false;
+    std::vector<hipEvent_t> prof_ev;  // 2 per launch slot
+    std::vector<int> prof_phase;
+    size_t prof_used = 0;
+    double prof_ms[kBatchPhases] = {};
+    int64_t prof_n[kBatchPhases] = {};
 };
 
 namespace {
@@ -3519,7 +3876,6 @@ sph_status batch_layout(sph_batch *b) {
     batch_drop_graph(b);
     std::vector<BlockMap> mc, ms, ml;
     std::vector<int32_t> vgc, vgl;
-    const int wpb = kClassifyBlock / kWave;
     for (size_t d = 0; d < b->doms.size(); ++d) {
         const sph_ctx *c = b->doms[d];
         const int64_t cap = b->parts[d].capacity;
@@ -3527,7 +3883,8 @@ sph_status batch_layout(sph_batch *b) {
         vgc.push_back(vc);
         for (int v = 0; v < vc; ++v) mc.push_back({(int32_t)d, v});
         for (int64_t t = 0; t < c->n_tiles; ++t) ms.push_back({(int32_t)d, (int32_t)t});
-        const int vl = c->n_runs > 0 ? std::max(1, std::min(kMaxPartBlocks, (c->n_runs + wpb - 1) / wpb)) : 0;
+        const int vl =
+            c->n_runs > 0 ? std::max(1, std::min(kMaxPartBlocks, (c->n_runs + kRunsPerBlock - 1) / kRunsPerBlock)) : 0;
         vgl.push_back(vl);
         for (int v = 0; v < vl; ++v) ml.push_back({(int32_t)d, v});
     }
@@ -3546,18 +3903,49 @@ sph_status batch_layout(sph_batch *b) {
     return SPH_OK;
 }
 
+// Brackets one batch launch with events when the batch's profiling is on.
+struct BatchProf {
+    sph_batch *b;
+    size_t slot = 0;
+    bool on = false;
+    BatchProf(sph_batch *bb, int phase) : b(bb) {
+        if (!b->prof_on || b->prof_used >= kProfSlots) return;
+        slot = b->prof_used++;
+        b->prof_phase[slot] = phase;
+        on = hipEventRecord(b->prof_ev[2 * slot], b->stream) == hipSuccess;
+    }
+    ~BatchProf() {
+        if (on) (void)hipEventRecord(b->prof_ev[2 * slot + 1], b->stream);
+    }
+};
+
 // One step of every domain: five launches whatever the number of domains.
 sph_status batch_enqueue(sph_batch *b) {
     const int nd = (int)b->doms.size();
-    hipLaunchKernelGGL(kb_count, dim3(b->nb_count), dim3(kBuildBlock), 0, b->stream, b->d_ca, b->d_map_count,
-                       b->d_vg_count);
-    hipLaunchKernelGGL(kb_scan, dim3(b->nb_scan), dim3(kScanBlock), 0, b->stream, b->d_sa, b->d_map_scan);
-    hipLaunchKernelGGL(kb_scatter, dim3(b->nb_count), dim3(kBuildBlock), 0, b->stream, b->d_xa, b->d_map_count,
-                       b->d_vg_count);
-    if (b->nb_cls > 0)
+    {
+        BatchProf p(b, 0);
+        hipLaunchKernelGGL(kb_count, dim3(b->nb_count), dim3(kBuildBlock), 0, b->stream, b->d_ca, b->d_map_count,
+                           b->d_vg_count);
+    }
+    {
+        BatchProf p(b, 1);
+        hipLaunchKernelGGL(kb_scan, dim3(b->nb_scan), dim3(kScanBlock), 0, b->stream, b->d_sa, b->d_map_scan);
+    }
+    {
+        BatchProf p(b, 2);
+        hipLaunchKernelGGL(kb_scatter, dim3(b->nb_count), dim3(kBuildBlock), 0, b->stream, b->d_xa, b->d_map_count,
+                           b->d_vg_count);
+    }
+    if (b->nb_cls > 0) {
+        BatchProf p(b, 3);
         hipLaunchKernelGGL(kb_classify, dim3(b->nb_cls), dim3(kClassifyBlock), 0, b->stream, b->d_la, b->d_map_cls,
                            b->d_vg_cls);
-    hipLaunchKernelGGL(kb_finalize, dim3(nd * b->fin_blocks), dim3(kFinBlock), 0, b->stream, b->d_fa, b->fin_blocks);
+    }
+    {
+        BatchProf p(b, 4);
+        hipLaunchKernelGGL(kb_finalize, dim3(nd * b->fin_blocks), dim3(kFinBlock), 0, b->stream, b->d_fa,
+                           b->fin_blocks);
+    }
     HIP_TRY(hipGetLastError());
     return SPH_OK;
 }
@@ -3565,6 +3953,7 @@ sph_status batch_enqueue(sph_batch *b) {
 void batch_free(sph_batch *b) {
     if (!b) return;
     batch_drop_graph(b);
+    for (hipEvent_t e : b->prof_ev) (void)hipEventDestroy(e);
     (void)hipFree(b->d_ca);
     (void)hipFree(b->d_sa);
     (void)hipFree(b->d_xa);
@@ -3695,6 +4084,46 @@ extern "C" sph_status sph_batch_graph_launch(sph_batch *b) {
         if (b->doms[d]->layout_gen != b->gens[d]) return SPH_ERR_STATE;
     if (!b->exec) HIP_CHECKED(sph_batch_graph_capture(b));
     HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+    return SPH_OK;
+}
+
+extern "C" sph_status sph_batch_profile_enable(sph_batch *b, int32_t on) {
+    if (!b) return SPH_ERR_ARG;
+    if (on && b->prof_ev.empty()) {
+        b->prof_ev.resize(2 * kProfSlots);
+        b->prof_phase.resize(kProfSlots);
+        for (auto &e : b->prof_ev)
+            if (hipEventCreate(&e) != hipSuccess) return SPH_ERR_HIP;
+    }
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    b->prof_used = 0;
+    for (int i = 0; i < kBatchPhases; ++i) {
+        b->prof_ms[i] = 0.0;
+        b->prof_n[i] = 0;
+    }
+    b->prof_on = on != 0;
+    return SPH_OK;
+}
+
+extern "C" sph_status sph_batch_profile_read(sph_batch *b, double ms[5], int64_t launches[5], int32_t reset) {
+    if (!b) return SPH_ERR_ARG;
+    for (size_t s = 0; s < b->prof_used; ++s) {
+        float t = 0.0f;
+        if (hipEventSynchronize(b->prof_ev[2 * s + 1]) == hipSuccess &&
+            hipEventElapsedTime(&t, b->prof_ev[2 * s], b->prof_ev[2 * s + 1]) == hipSuccess) {
+            b->prof_ms[b->prof_phase[s]] += t;
+            b->prof_n[b->prof_phase[s]] += 1;
+        }
+    }
+    b->prof_used = 0;
+    for (int i = 0; i < kBatchPhases; ++i) {
+        if (ms) ms[i] = b->prof_ms[i];
+        if (launches) launches[i] = b->prof_n[i];
+        if (reset) {
+            b->prof_ms[i] = 0.0;
+            b->prof_n[i] = 0;
+        }
+    }
     return SPH_OK;
 }
 

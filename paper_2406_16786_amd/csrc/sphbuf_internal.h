@@ -9,6 +9,19 @@ namespace sphbuf {
 
 struct Obb;
 
+// Where a check region's cover is searched: the oriented check box (centre,
+// axes as rows, half-extents), its axis-aligned box, the dilation of the cell
+// boxes and the inclusive cell ranges per axis.
+struct CoverBox {
+    double c[3];
+    double ax[3][3];
+    double h[3];
+    double blo[3], bhi[3];
+    double eps;
+    int32_t lo_i[3], hi_i[3];
+};
+sph_status cover_box(int dim, const double glo[3], double cs, const int32_t dims[3], const double origin[3],
+                     const double rot[9], const double half[3], double margin, CoverBox &out);
 sph_status grid_cover(int dim, const double glo[3], double cs, const int32_t dims[3], const double origin[3],
                       const double rot[9], const double half[3], double margin, std::vector<int32_t> &first,
                       std::vector<int32_t> &len);

@@ -101,6 +101,15 @@ class Domain:
     def rotate(self, buffer_id: int, center, m) -> int:
         return S.sph_buffer_rotate(self.ctx, self.p, buffer_id, center, m)
 
+    def rotate_async(self, buffer_id: int, center, m) -> int:
+        return S.sph_buffer_rotate_async(self.ctx, self.p, buffer_id, center, m)
+
+    def apply_bc_async(self) -> int:
+        return S.sph_buffer_apply_bc_async(self.ctx, self.p)
+
+    def bc_status(self) -> int:
+        return S.sph_last_bc_status(self.ctx)
+
     def neighbor_count(self, radius: float):
         """(status, int32 device tensor of the capacity; entries below N hold the counts)."""
         counts = torch.full((self.capacity,), -1, dtype=torch.int32, device=self.device)

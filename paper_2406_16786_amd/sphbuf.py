@@ -44,10 +44,14 @@ EXPORTED = (
     "sph_batch_step", "sph_batch_results", "sph_batch_tune",
     "sph_set_fields", "sph_buffer_set_bc", "sph_buffer_apply_bc", "sph_buffer_rotate", "sph_neighbor_count",
     "sph_state_export", "sph_state_import", "sph_batch_graph_capture", "sph_batch_graph_launch",
+    "sph_batch_profile_enable", "sph_batch_profile_read",
+    "sph_buffer_rotate_async", "sph_buffer_apply_bc_async", "sph_last_bc_status", "sph_buffer_cover",
 )
+BATCH_PHASES = ("count", "scan", "scatter", "classify", "finalize")
 SPH_BATCH_KERNELS, SPH_BATCH_GRAPH = 0, 1
-SPH_NPHASE = 10
-PHASES = ("count", "scan", "scatter", "classify", "fullscan", "finalize", "bc", "rotate", "candidates", "neighbor")
+SPH_NPHASE = 11
+PHASES = ("count", "scan", "scatter", "classify", "fullscan", "finalize", "bc", "rotate", "candidates", "neighbor",
+          "cover")
 SPH_BC_NONE, SPH_BC_VELOCITY, SPH_BC_PRESSURE = 0, 1, 2
 SPH_PROFILE_PLUG, SPH_PROFILE_PARABOLIC_Y, SPH_PROFILE_PARABOLIC_R = 0, 1, 2
 
@@ -170,6 +174,8 @@ def lib() -> ctypes.CDLL:
             "sph_state_import": ([_VP, _VP, ctypes.c_size_t], ctypes.c_int),
             "sph_batch_graph_capture": ([_VP], ctypes.c_int),
             "sph_batch_graph_launch": ([_VP], ctypes.c_int),
+            "sph_batch_profile_enable": ([_VP, ctypes.c_int32], ctypes.c_int),
+            "sph_batch_profile_read": ([_VP, _D, _I64, ctypes.c_int32], ctypes.c_int),
             "sph_rotation_2d": ([ctypes.c_double, _D], ctypes.c_int),
             "sph_rotation_axis_angle": ([_D, ctypes.c_double, _D], ctypes.c_int),
             "sph_rotation_from_direction": ([_D, _D], ctypes.c_int),
@@ -184,6 +190,10 @@ def lib() -> ctypes.CDLL:
             "sph_buffer_set_bc": ([_VP, ctypes.c_int32, ctypes.POINTER(sph_bc)], ctypes.c_int),
             "sph_buffer_apply_bc": ([_VP, ctypes.POINTER(sph_particles)], ctypes.c_int),
             "sph_buffer_rotate": ([_VP, ctypes.POINTER(sph_particles), ctypes.c_int32, _D, _D], ctypes.c_int),
+            "sph_buffer_rotate_async": ([_VP, ctypes.POINTER(sph_particles), ctypes.c_int32, _D, _D], ctypes.c_int),
+            "sph_buffer_apply_bc_async": ([_VP, ctypes.POINTER(sph_particles)], ctypes.c_int),
+            "sph_last_bc_status": ([_VP], ctypes.c_int),
+            "sph_buffer_cover": ([_VP, ctypes.c_int32, _I32, _I32, ctypes.c_int64, _I64], ctypes.c_int),
             "sph_neighbor_count": ([_VP, ctypes.POINTER(sph_particles), ctypes.c_double, _VP], ctypes.c_int),
             "sph_batch_create": ([ctypes.POINTER(_VP), ctypes.POINTER(sph_particles), ctypes.c_int32, _VP,
                                   ctypes.POINTER(_VP)], ctypes.c_int),
@@ -297,6 +307,31 @@ def sph_buffer_rotate(ctx: int, p: sph_particles, buffer_id: int, center: Sequen
     c[: len(center)] = center
     mm = np.ascontiguousarray(m, dtype=np.float64).reshape(9)
     return lib().sph_buffer_rotate(ctx, ctypes.byref(p), int(buffer_id), c.ctypes.data_as(_D), mm.ctypes.data_as(_D))
+
+
+def sph_buffer_rotate_async(ctx: int, p: sph_particles, buffer_id: int, center: Sequence[float], m) -> int:
+    c = np.zeros(3)
+    c[: len(center)] = center
+    mm = np.ascontiguousarray(m, dtype=np.float64).reshape(9)
+    return lib().sph_buffer_rotate_async(ctx, ctypes.byref(p), int(buffer_id), c.ctypes.data_as(_D),
+                                         mm.ctypes.data_as(_D))
+
+
+def sph_buffer_apply_bc_async(ctx: int, p: sph_particles) -> int:
+    return lib().sph_buffer_apply_bc_async(ctx, ctypes.byref(p))
+
+
+def sph_last_bc_status(ctx: int) -> int:
+    return lib().sph_last_bc_status(ctx)
+
+
+def sph_buffer_cover(ctx: int, buffer_id: int, cap: int = 1 << 22):
+    f = np.zeros(max(1, cap), dtype=np.int32)
+    ln = np.zeros(max(1, cap), dtype=np.int32)
+    n = ctypes.c_int64(0)
+    st = lib().sph_buffer_cover(ctx, int(buffer_id), f.ctypes.data_as(_I32), ln.ctypes.data_as(_I32), int(cap),
+                                ctypes.byref(n))
+    return st, f[: n.value].copy(), ln[: n.value].copy()
 
 
 def sph_buffer_identify(ctx: int, p: sph_particles, buffer_id: int = -1) -> int:
@@ -433,6 +468,17 @@ def sph_batch_create(ctxs, parts, stream: int = 0):
 def sph_batch_destroy(b: int) -> int:
     _live_batch.discard(b)
     return lib().sph_batch_destroy(b)
+
+
+def sph_batch_profile_enable(b: int, on: bool) -> int:
+    return lib().sph_batch_profile_enable(b, 1 if on else 0)
+
+
+def sph_batch_profile_read(b: int, reset: bool = False):
+    ms = np.zeros(5)
+    n = np.zeros(5, dtype=np.int64)
+    st = lib().sph_batch_profile_read(b, ms.ctypes.data_as(_D), n.ctypes.data_as(_I64), 1 if reset else 0)
+    return st, ms, n
 
 
 def sph_batch_graph_capture(b: int) -> int:

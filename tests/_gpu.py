@@ -48,3 +48,33 @@ def assert_same_state(d, st: oracle.State, what: str = "") -> None:
         np.testing.assert_array_equal(car[f][:n], st.carried[f][:n], err_msg=f"{what}: carried[{f}]")
     np.testing.assert_array_equal(lab[:n], st.label[:n], err_msg=f"{what}: label")
     np.testing.assert_array_equal(ids[:n], st.id[:n], err_msg=f"{what}: id")
+
+
+def advect_device(wl, d, step: int, gen) -> None:
+    """x <- x + u dt on the GPU with the workload's prescribed velocity (seeded
+    noise from a torch generator): the harness's move between two updates of a
+    long full-size run.  The oracle is then fed the GPU's own pre-update states."""
+    import torch
+    n = d.n()
+    gen.manual_seed(wl.seed_noise + step)
+    with torch.cuda.stream(d.stream):
+        p = [t[:n] for t in d.pos]
+        noise = torch.randn((wl.dim, n), generator=gen, device=d.device, dtype=torch.float32)
+        u = wl.velocity(torch, p, step, noise)
+        for c in range(wl.dim):
+            p[c].add_(u[c] * wl.dt)
+    d.stream.synchronize()
+
+
+def host_state(d, n_carried_kept=None) -> oracle.State:
+    """Host copy of a domain's live state (all carried fields, or the first
+    n_carried_kept of them) as an oracle State with the library's next_id."""
+    from paper_2406_16786_amd import sphbuf as S
+    d.stream.synchronize()
+    n = int(d.n_dev.item())
+    pos = [t.cpu().numpy() for t in d.pos]
+    car = [t.cpu().numpy() for t in d.carried[: n_carried_kept]] if n_carried_kept != 0 else []
+    lab = d.label.cpu().numpy()
+    ids = d.id.cpu().numpy()
+    nid = int(S.sph_state_get(d.ctx)[1])
+    return oracle.State(len(pos), pos, car, lab, ids, n, nid)

@@ -122,10 +122,10 @@ def test_graph_capture_and_launch_calls():
         d.close()
 
 
-@pytest.mark.parametrize("change", ["rotate", "define", "fields"])
+@pytest.mark.parametrize("change", ["define", "fields"])
 def test_batch_refuses_to_step_after_a_member_changed(change):
-    """A batch bakes its members' cover cells, grid arrays and field roles into its
-    launch tables: after a turn, a new buffer or a new density field on a member it
+    """A batch bakes its members' grid arrays, run-list arrays and field roles into
+    its launch tables: after a new buffer or a new density field on a member it
     refuses to step (SPH_ERR_STATE, nothing launched) and the particle arrays stay
     as they were; a new batch steps again."""
     import torch
@@ -133,12 +133,7 @@ def test_batch_refuses_to_step_after_a_member_changed(change):
     wls = W.hub_batch(3, 2e3, 1e4, seed=7)
     doms, bufs, states, batch, stream = _setup(wls)
     d0 = doms[0]
-    if change == "rotate":
-        d0.build()
-        c = np.array(wls[0].buffers[0].origin, dtype=np.float64)
-        m = np.eye(3)   # the identity is a turn too: the cover is recomputed
-        assert d0.rotate(1, c[:wls[0].dim], m) == 0
-    elif change == "define":
+    if change == "define":
         far = [0.9 * h for h in wls[0].hi]
         assert S.sph_buffer_define(d0.ctx, S.SPH_OUTLET, far, np.eye(3), [1e-3, 1e-3, 1e-3], 1e-3)[0] == 0
     else:
@@ -157,5 +152,46 @@ def test_batch_refuses_to_step_after_a_member_changed(change):
     assert st == 0 and S.sph_batch_step(batch2) == 0
     torch.cuda.synchronize()
     S.sph_batch_destroy(batch2)
+    for d in doms:
+        d.close()
+
+
+def test_batch_steps_after_a_member_turned():
+    """A turn recomputes the member's cover on the device, in the arrays the batch
+    already holds: the batch keeps stepping, and every domain matches the oracle
+    (with the turned buffer's frame)."""
+    import math
+    import torch
+    from paper_2406_16786_amd import sphbuf as S
+    wls = W.hub_batch(3, 2e3, 1e4, seed=7)
+    doms, bufs, states, batch, stream = _setup(wls)
+    fields = [oracle.Fields(vel=tuple(range(w.dim)), rho=-1) for w in wls]
+    for d, w in zip(doms, wls):
+        d.set_fields(list(range(w.dim)), -1)
+    S.sph_batch_destroy(batch)   # field roles changed: a new batch
+    st, batch = S.sph_batch_create([d.ctx for d in doms], [d.p for d in doms], stream.cuda_stream)
+    assert st == 0
+    for step in range(8):
+        for wl, s, d in zip(wls, states, doms):
+            W.advect_host(wl, s.pos, s.n, step)
+            upload_state(d, s)
+        torch.cuda.synchronize()
+        assert S.sph_batch_step(batch) == 0
+        st, res = S.sph_batch_results(batch, len(doms))
+        for k, (d, b, s) in enumerate(zip(doms, bufs, states)):
+            ro = oracle.update(b, s)
+            assert res[k].status == ro.status == 0, (step, k)
+            assert_same_state(d, s, f"step {step} domain {k}")
+        # turn the first buffer of domain 0 a little about its own origin
+        d0, w0 = doms[0], wls[0]
+        m = np.eye(3)
+        th = math.radians(0.7)
+        m[0, 0], m[0, 1], m[1, 0], m[1, 1] = math.cos(th), -math.sin(th), math.sin(th), math.cos(th)
+        c = list(bufs[0][0].origin)[: w0.dim]
+        d0.build()
+        assert d0.rotate(1, c, m) == oracle.rotate_buffer(bufs[0], 1, c, m, fields[0], states[0]) == 0
+        assert_same_state(d0, states[0], f"step {step} turn")
+        torch.cuda.synchronize()
+    S.sph_batch_destroy(batch)
     for d in doms:
         d.close()

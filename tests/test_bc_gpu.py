@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 import workloads as W
-from tests._gpu import assert_same_state, make_domain, upload_state
+from tests._gpu import assert_same_state, make_domain, make_domain_raw, upload_state
 from tests._support import make_state, oracle_buffers, oracle_state
 
 pytestmark = pytest.mark.gpu
@@ -228,4 +228,102 @@ def test_boundary_calls_need_a_current_cell_list_and_fields():
     assert S.sph_buffer_set_bc(d.ctx, 2, S.SPH_BC_VELOCITY, profile=S.SPH_PROFILE_PARABOLIC_Y, radius=-1.0) == \
         S.SPH_ERR_ARG
     assert S.sph_buffer_set_bc(d.ctx, 3, S.SPH_BC_NONE) == S.SPH_ERR_ARG
+    d.close()
+
+
+def _cells(f, ln):
+    return set(int(c) for a, l in zip(f, ln) for c in range(a, a + l))
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_turned_cover_equals_the_host_cover(dim):
+    """After each turn the library recomputes the buffer's cover on the device; on
+    a dense grid its cells must be those of the host's separating-axis cover of
+    the turned frame (sph_grid_cover), turn after turn, for oblique turns about
+    a centre off the buffer."""
+    S = _sph()
+    rng = np.random.default_rng(dim)
+    dp = 0.01
+    cs = 2.6 * dp
+    lo, hi = (-0.6, -0.6, -0.6), (0.6, 0.6, 0.6 if dim == 3 else 0.0)
+    half = (2 * dp, 0.12, 0.09)
+    q0 = oracle.rotation_2d(0.4) if dim == 2 else oracle.rotation_from_direction((0.3, -0.5, 0.8))
+    bufs = [oracle.Buffer(oracle.INLET, (0.1, 0.05, 0.02 if dim == 3 else 0.0), q0, half, cs)]
+    pts = rng.uniform(-0.5, 0.5, size=(4000, dim))
+    st = make_state(dim, pts, carried=3)
+    d = make_domain_raw(dim, lo, hi, cs, dp, bufs, st)
+    d.set_fields([0, 1, 2][:dim], -1)
+    dims = [int(math.ceil((hi[c] - lo[c]) / cs)) for c in range(dim)] + [1] * (3 - dim)
+    center = (0.02, -0.03, 0.01)
+    m = W.rotation_z(math.radians(7.0)) if dim == 2 else _turn((0.2, 1.0, 0.4), math.radians(11.0))
+    for turn in range(12):
+        b = bufs[0]
+        st_h, f, ln = S.sph_grid_cover(dim, lo, cs, dims, b.origin, b.rot, b.half, b.margin)
+        st_d, fd, lnd = S.sph_buffer_cover(d.ctx, 1)
+        assert st_h == 0 and st_d == 0
+        assert _cells(fd, lnd) == _cells(f, ln), f"turn {turn}"
+        d.build()
+        assert d.rotate(1, center[:dim], m) == 0
+        oracle.rotate_buffer(bufs, 1, center[:dim], m, oracle.Fields(vel=tuple(range(dim)), rho=-1), st)
+    d.close()
+
+
+def test_turns_on_the_brick_sparse_grid():
+    """The branching network (scaled, brick-sparse grid): the trunk's buffer turned
+    about an oblique axis through its origin every step, with updates between the
+    turns; every array and event against the oracle, including the buffer's
+    cover reaching into inactive bricks (the overflow cell)."""
+    wl = W.tree3d(dp=0.004)
+    bufs = oracle_buffers(wl)
+    st = oracle_state(wl)
+    d = make_domain(wl, bufs, st, brick_log2=3)
+    d.set_fields([0, 1, 2], 4)
+    fields = oracle.Fields(vel=(0, 1, 2), rho=4)
+    assert oracle.identify(bufs, st, -1)[0] == 0 and d.identify(-1) == 0
+    m = _turn((1.0, 0.4, 0.7), math.radians(0.5))
+    center = tuple(bufs[0].origin)
+    for step in range(20):
+        W.advect_host(wl, st.pos, st.n, step)
+        upload_state(d, st)
+        d.build()
+        gst, g, dl = d.update()
+        res = oracle.update(bufs, st)
+        assert gst == res.status == 0, (step, gst, res.status)
+        np.testing.assert_array_equal(d.events()[1], res.gen)
+        np.testing.assert_array_equal(d.events()[2], res.dele)
+        d.build()
+        assert d.rotate(1, center, m) == oracle.rotate_buffer(bufs, 1, center, m, fields, st) == 0
+        assert_same_state(d, st, f"step {step} turn")
+    d.close()
+
+
+def test_async_turn_and_boundary_conditions():
+    """sph_buffer_rotate_async and sph_buffer_apply_bc_async enqueue only; their
+    outcome is read with sph_last_bc_status; results as the sync calls (the
+    sprinkler, 30 steps with no host wait inside a step but the update's)."""
+    wl = W.sprinkler2d(n_background=3000)
+    bufs = oracle_buffers(wl)
+    st = oracle_state(wl)
+    bcs = [oracle.BC(oracle.BC_VELOCITY, oracle.PROFILE_PARABOLIC_Y, u=wl.bc_u, radius=wl.bc_radius)]
+    fields = oracle.Fields(vel=(0, 1), rho=3)
+    d = make_domain(wl, bufs, st)
+    d.set_fields([0, 1], 3)
+    d.set_bc(1, _sph().SPH_BC_VELOCITY, profile=_sph().SPH_PROFILE_PARABOLIC_Y, u=wl.bc_u, radius=wl.bc_radius)
+    assert oracle.identify(bufs, st, -1)[0] == 0 and d.identify(-1) == 0
+    m = W.rotation_z(wl.omega * wl.dt)
+    for step in range(30):
+        d.build()
+        gst, g, dl = d.update()
+        res = oracle.update(bufs, st, bcs, fields)
+        assert gst == res.status == 0
+        d.build()
+        assert d.apply_bc_async() == 0
+        assert d.bc_status() == oracle.apply_bc(bufs, bcs, fields, st) == 0
+        W.advect_carried(wl, st.pos, st.carried, st.n)
+        upload_state(d, st)
+        d.build()
+        assert d.rotate_async(1, (0.0, 0.0), m) == 0
+        assert oracle.rotate_buffer(bufs, 1, (0.0, 0.0), m, fields, st) == 0
+        assert d.bc_status() == 0
+        assert_same_state(d, st, f"step {step}")
     d.close()
