@@ -7,7 +7,7 @@
  * One update runs five steps on the GPU:
  *   1. a cell-linked list over all particles (counting sort: cell_start, cell_idx),
  *   2. per in-/outlet, candidates gathered only from the cells that overlap its
- *      check region (Section 3.1, the "local cell-linked lists"),
+ *      check region (Section 3.1: the cell-linked lists local to each buffer),
  *   3. each candidate rotated into the buffer's local frame (Eq. 2D_transformation,
  *      Eq. 3D_transformation) so that crossing is a one-coordinate comparison,
  *   4. inlet generation: the crossing buffer particle is duplicated and recycled
@@ -154,8 +154,10 @@ sph_status sph_destroy(sph_ctx *ctx);
  * local frame, box of half-extents a/2, b/2, c/2 centred at O').  margin > 0 is
  * the check-region margin delta (<= 0 selects cell_size): the check region is the
  * box dilated by delta on every side and stands for the local cell-linked lists
- * "a little larger than the buffer".  Host FP64 work only (frame validation,
- * cell cover of the check region, guard band), then one small upload.
+ * that extend slightly past the buffer.  Host FP64 work (frame validation, cell
+ * cover of the check region, guard band), then the buffer's range of the run
+ * lists is allocated, sized for its cover in any orientation (a turn recomputes
+ * the cover in place), and filled (setup: waits for the stream).
  * Errors: SPH_ERR_ARG (kind, non-positive or non-finite extents, a check region
  * wider than 2^20 cells), SPH_ERR_ROTATION, SPH_ERR_OVERLAP (check regions of two
  * buffers intersect), SPH_ERR_TOO_MANY_BUFFERS.  *buffer_id receives 1..15.
@@ -189,7 +191,7 @@ sph_status sph_grid_fit(sph_ctx *ctx, const sph_particles *p);
  * build. */
 sph_status sph_celllist_build(sph_ctx *ctx, const sph_particles *p);
 
-/* Algorithm 1, identification ("execute only once"): label k for every live
+/* Algorithm 1, identification (run once, before the first update): label k for every live
  * particle inside buffer k's box; buffer_id = -1 for all buffers.  Full pass over
  * the particles (sync).  SPH_ERR_NONFINITE leaves labels untouched. */
 sph_status sph_buffer_identify(sph_ctx *ctx, sph_particles *p, int32_t buffer_id);
@@ -385,6 +387,14 @@ sph_status sph_batch_set_mode(sph_batch *b, int32_t mode);
 /* Particles per block of the count and scatter launches (256 .. 2^20; default
  * 2048).  Sync; drops a captured graph. */
 sph_status sph_batch_set_count_block(sph_batch *b, int32_t particles_per_block);
+/* Cover runs (row runs of cover cells) that one classify workgroup gathers
+ * (1 .. 8; default 3): fewer give more workgroups, more give each workgroup a
+ * longer candidate list.  Sync; drops a captured graph. */
+sph_status sph_batch_set_gather(sph_batch *b, int32_t runs_per_block);
+/* The batch's launch mode, particles per count block and runs per classify
+ * workgroup (outputs may be NULL). */
+sph_status sph_batch_get_config(sph_batch *b, int32_t *mode, int32_t *particles_per_block,
+                                int32_t *runs_per_block);
 /* Async: one step (build + local-cell update) of every domain.  SPH_ERR_STATE if
  * a member was redefined since sph_batch_create (nothing is enqueued). */
 sph_status sph_batch_step(sph_batch *b);
@@ -402,9 +412,11 @@ sph_status sph_batch_results(sph_batch *b, sph_result *out);
 sph_status sph_batch_profile_enable(sph_batch *b, int32_t on);
 sph_status sph_batch_profile_read(sph_batch *b, double ms[5], int64_t launches[5], int32_t reset);
 /* Autotuner: times `trials` steps of each launch mode x particles-per-block
- * candidate and keeps the fastest (steps are real updates of the current
- * states).  cache_path (optional) holds earlier choices keyed by device, domain
- * count and total capacity; a hit skips the sweep.  Outputs may be NULL. */
+ * candidate, then of each runs-per-classify-workgroup choice at the best of
+ * those, and keeps the fastest (steps are real updates of the current states;
+ * sph_batch_get_config reports the choice).  cache_path (optional) holds earlier
+ * choices keyed by device, domain count and total capacity; a hit skips the
+ * sweep.  Outputs may be NULL. */
 sph_status sph_batch_tune(sph_batch *b, int32_t trials, const char *cache_path, int32_t *mode,
                           int32_t *particles_per_block, double *ms_per_step);
 

@@ -135,7 +135,7 @@ static int in_box(int dim, const orc_buffer *b, const double lc[3]) {
 }
 
 /* Check region: the box dilated by the margin on every side, standing for the
- * local cell-linked lists "a little larger than the buffer" (Section 3.1). */
+ * local cell-linked lists, which reach slightly past the buffer (Section 3.1). */
 static int in_check(int dim, const orc_buffer *b, const double lc[3]) {
     if (!(fabs(lc[0]) < b->half[0] + b->margin)) return 0;
     if (!(fabs(lc[1]) < b->half[1] + b->margin)) return 0;
@@ -170,7 +170,7 @@ static void count_labels(int nb, const orc_state *s, int64_t *n_labelled) {
 
 /* ------------------------------------------------------- identification --- */
 
-/* Algorithm 1, first procedure ("execute only once"): every particle inside the
+/* Algorithm 1, first procedure (run a single time, at set-up): every particle inside the
  * box of buffer k is added to buffer k's set, i.e. receives label k. */
 int orc_identify(const orc_buffer *bufs, int nb, int which, orc_state *s, int64_t *n_labelled) {
     if (!valid_args(bufs, nb, s)) return ORC_ERR_ARG;

@@ -17,8 +17,8 @@
  *     see orc_rotation_from_direction).
  *   - half = (a/2, b/2, c/2): buffer half-extents along X', Y', Z'.
  *   - margin = delta: the check region C = box dilated by delta on every side
- *     stands for the "local cell-linked lists ... a little larger than the
- *     buffer" of Section 3.1.
+ *     stands for the cell-linked lists local to the buffer of Section 3.1,
+ *     which reach slightly past it.
  *   - label 0 = ordinary fluid particle, label k (1..n_buffers) = buffer k.
  */
 #ifndef SPHBUF_ORACLE_H

@@ -749,7 +749,7 @@ __device__ __forceinline__ void scan_body(const ScanArgs &a, ScanLds &L) {
     for (int q = 0; q < kScanItems; ++q) {
         const int j = q * kScanBlock + (int)threadIdx.x;
         const int64_t gj = t0 + j;
-        if (gj < a.m) a.count[gj] = 0;
+        if (gj < a.m && vq[q] != 0) a.count[gj] = 0;  // empty cells are left alone (no write)
         s_buf[j + j / 32] = vq[q];
     }
     __syncthreads();
@@ -900,6 +900,7 @@ struct LocalArgs {
     const int32_t *cell_start;
     const int32_t *cell_idx;
     EventArgs e;
+    int rpb;  // runs per workgroup and round, 1..kMaxRunsPerBlock
 };
 
 // A workgroup takes kRunsPerBlock runs of cover cells at a time: wave 0 loads
@@ -908,12 +909,13 @@ struct LocalArgs {
 // particle per round -- its cell_idx entry, then its position, label and (where
 // a duplicate may be made) carried fields, the test, the decision and the
 // emission.  The buffer varies from lane to lane.
-constexpr int kRunsPerBlock = 3;
+constexpr int kMaxRunsPerBlock = 8;
+constexpr int kRunsPerBlock = 3;  // default
 
 __device__ __forceinline__ void classify_body(const LocalArgs &a, const int vb, const int vg) {
     __shared__ BufDev sb[SPH_MAX_BUFFERS];
     __shared__ unsigned s_cnt[2 * SPH_MAX_BUFFERS];
-    __shared__ int s_j0[kRunsPerBlock], s_pre[kRunsPerBlock + 1], s_k[kRunsPerBlock];
+    __shared__ int s_j0[kMaxRunsPerBlock], s_pre[kMaxRunsPerBlock + 1], s_k[kMaxRunsPerBlock];
     __shared__ int s_nruns, s_fault;
     for (int t = threadIdx.x; t < a.nb * (int)(sizeof(BufDev) / 4); t += blockDim.x)
         reinterpret_cast<uint32_t *>(sb)[t] = reinterpret_cast<const uint32_t *>(a.bufs)[t];
@@ -933,36 +935,37 @@ __device__ __forceinline__ void classify_body(const LocalArgs &a, const int vb, 
     const int wpb = blockDim.x / kWave;
     const int dim = a.p.dim;
     const int seg = (vb * wpb + wave) % kSeg;
-    for (int r0 = vb * kRunsPerBlock; r0 < n_runs; r0 += vg * kRunsPerBlock) {  // block-uniform
+    const int R = a.rpb < 1 ? 1 : (a.rpb > kMaxRunsPerBlock ? kMaxRunsPerBlock : a.rpb);
+    for (int r0 = vb * R; r0 < n_runs; r0 += vg * R) {  // block-uniform
         if (threadIdx.x < kWave) {  // wave 0: the runs' records and candidate ranges
             const int q = threadIdx.x, r = r0 + q;
             int len = 0, j0 = 0, k = 0;
-            if (q < kRunsPerBlock && r < n_runs) {
+            if (q < R && r < n_runs) {
                 k = a.run_buf[r];
                 const int c0 = a.run_first[r], c1 = c0 + a.run_len[r];
                 j0 = a.cell_start[c0];
                 len = a.cell_start[c1] - j0;
             }
             int incl = len;
-            for (int off = 1; off < kRunsPerBlock; off <<= 1) {
+            for (int off = 1; off < kMaxRunsPerBlock; off <<= 1) {
                 const int t = __shfl_up(incl, off);
                 if (q >= off) incl += t;
             }
-            if (q < kRunsPerBlock) {
+            if (q < R) {
                 s_j0[q] = j0;
                 s_pre[q] = incl - len;
                 s_k[q] = k;
-                if (q == kRunsPerBlock - 1) s_pre[kRunsPerBlock] = incl;
+                if (q == R - 1) s_pre[R] = incl;
             }
         }
         __syncthreads();
-        const int total = s_pre[kRunsPerBlock];
+        const int total = s_pre[R];
         for (int base = 0; base < total; base += blockDim.x) {  // block-uniform
             const int t = base + (int)threadIdx.x;
             int q = 0;
 #pragma unroll
-            for (int qq = 1; qq < kRunsPerBlock; ++qq)
-                if (s_pre[qq] <= t) q = qq;
+            for (int qq = 1; qq < kMaxRunsPerBlock; ++qq)
+                if (qq < R && s_pre[qq] <= t) q = qq;
             const int k = s_k[q];
             const BufDev &b = sb[k];
             int64_t i = t < total ? a.cell_idx[s_j0[q] + (t - s_pre[q])] : 0;
@@ -2650,6 +2653,7 @@ LocalArgs local_args(const sph_ctx *ctx, const Parts &pp) {
     la.cell_start = ctx->d_cell_start;
     la.cell_idx = ctx->d_cell_idx;
     la.e = events_of(ctx);
+    la.rpb = kRunsPerBlock;
     return la;
 }
 
@@ -3831,7 +3835,9 @@ struct sph_batch {
     bool own_stream = false;
     int mode = SPH_BATCH_GRAPH;
     int count_ppb = 2048;  // particles per block of the count / scatter phases
+    int cls_rpb = kRunsPerBlock;  // cover runs per classify workgroup (the gather schedule)
     int fin_blocks = 1;    // finalize workgroups per domain
+    std::vector<LocalArgs> la_host;  // classify arguments per domain (re-uploaded with the schedule)
     CountArgs *d_ca = nullptr;
     ScanArgs *d_sa = nullptr;
     ScatterArgs *d_xa = nullptr;
@@ -3884,13 +3890,15 @@ sph_status batch_layout(sph_batch *b) {
         for (int v = 0; v < vc; ++v) mc.push_back({(int32_t)d, v});
         for (int64_t t = 0; t < c->n_tiles; ++t) ms.push_back({(int32_t)d, (int32_t)t});
         const int vl =
-            c->n_runs > 0 ? std::max(1, std::min(kMaxPartBlocks, (c->n_runs + kRunsPerBlock - 1) / kRunsPerBlock)) : 0;
+            c->n_runs > 0 ? std::max(1, std::min(kMaxPartBlocks, (c->n_runs + b->cls_rpb - 1) / b->cls_rpb)) : 0;
         vgl.push_back(vl);
         for (int v = 0; v < vl; ++v) ml.push_back({(int32_t)d, v});
     }
     for (auto *t : {&mc, &ms, &ml})  // padding for the XCD renumbering (a multiple of 8 blocks)
         while (!t->empty() && t->size() % 8) t->push_back({-1, 0});
     sph_status st;
+    for (LocalArgs &la : b->la_host) la.rpb = b->cls_rpb;
+    if ((st = upload_table(b->d_la, b->la_host, b->stream)) != SPH_OK) return st;
     if ((st = upload_table(b->d_map_count, mc, b->stream)) != SPH_OK) return st;
     if ((st = upload_table(b->d_map_scan, ms, b->stream)) != SPH_OK) return st;
     if ((st = upload_table(b->d_map_cls, ml, b->stream)) != SPH_OK) return st;
@@ -4017,8 +4025,9 @@ extern "C" sph_status sph_batch_create(sph_ctx *const *domains, const sph_partic
     // one round of finalize workgroups over the CUs: fewer per domain in large batches
     b->fin_blocks = std::max(1, std::min(kFinBlocksMax, 256 / n_domains));
     sph_status st = SPH_OK;
+    b->la_host = la;
     if ((st = upload_table(b->d_ca, ca, b->stream)) != SPH_OK || (st = upload_table(b->d_sa, sa, b->stream)) != SPH_OK ||
-        (st = upload_table(b->d_xa, xa, b->stream)) != SPH_OK || (st = upload_table(b->d_la, la, b->stream)) != SPH_OK ||
+        (st = upload_table(b->d_xa, xa, b->stream)) != SPH_OK ||
         (st = upload_table(b->d_fa, fa, b->stream)) != SPH_OK || (st = batch_layout(b)) != SPH_OK ||
         hipHostMalloc(&b->h_res, sizeof(sph_result) * n_domains, hipHostMallocDefault) != hipSuccess) {
         batch_free(b);
@@ -4046,6 +4055,22 @@ extern "C" sph_status sph_batch_set_count_block(sph_batch *b, int32_t particles_
     HIP_TRY(hipStreamSynchronize(b->stream));
     b->count_ppb = particles_per_block;
     return batch_layout(b);
+}
+
+extern "C" sph_status sph_batch_set_gather(sph_batch *b, int32_t runs_per_block) {
+    if (!b || runs_per_block < 1 || runs_per_block > kMaxRunsPerBlock) return SPH_ERR_ARG;
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    b->cls_rpb = runs_per_block;
+    return batch_layout(b);
+}
+
+extern "C" sph_status sph_batch_get_config(sph_batch *b, int32_t *mode, int32_t *particles_per_block,
+                                           int32_t *runs_per_block) {
+    if (!b) return SPH_ERR_ARG;
+    if (mode) *mode = b->mode;
+    if (particles_per_block) *particles_per_block = b->count_ppb;
+    if (runs_per_block) *runs_per_block = b->cls_rpb;
+    return SPH_OK;
 }
 
 extern "C" sph_status sph_batch_step(sph_batch *b) {
@@ -4137,11 +4162,12 @@ extern "C" sph_status sph_batch_results(sph_batch *b, sph_result *out) {
     return SPH_OK;
 }
 
-// Autotuner: times `trials` real steps of every candidate (launch mode x
-// particles per count block) and keeps the fastest.  Steps during tuning are
-// genuine updates; once a state has been updated, further updates of unchanged
-// positions change nothing.  With a cache path, the choice is read from / appended
-// to a text file keyed by device, domain count and total capacity.
+// Autotuner: times `trials` real steps of every candidate and keeps the fastest:
+// first launch mode x particles per count block, then, at the best of those, the
+// cover runs per classify workgroup (the gather schedule).  Steps during tuning
+// are genuine updates; once a state has been updated, further updates of
+// unchanged positions change nothing.  With a cache path, the choice is read from
+// / appended to a text file keyed by device, domain count and total capacity.
 extern "C" sph_status sph_batch_tune(sph_batch *b, int32_t trials, const char *cache_path, int32_t *mode_out,
                                      int32_t *ppb_out, double *ms_out) {
     if (!b || trials < 1) return SPH_ERR_ARG;
@@ -4154,26 +4180,25 @@ extern "C" sph_status sph_batch_tune(sph_batch *b, int32_t trials, const char *c
     if (cache_path) {
         if (FILE *f = std::fopen(cache_path, "r")) {
             char line[256];
-            int m = -1, ppb = 0;
+            int m = -1, ppb = 0, rpb = 0;
             double ms = 0;
             while (std::fgets(line, sizeof(line), f)) {
                 char k2[160];
-                int mm, pp2;
+                int mm, pp2, rr;
                 double t;
-                if (std::sscanf(line, "%159[^|]|%d|%d|%lf", k2, &mm, &pp2, &t) == 4 && std::strcmp(k2, key) == 0) {
+                if (std::sscanf(line, "%159[^|]|%d|%d|%d|%lf", k2, &mm, &pp2, &rr, &t) == 5 && std::strcmp(k2, key) == 0) {
                     m = mm;
                     ppb = pp2;
+                    rpb = rr;
                     ms = t;
                 }
             }
             std::fclose(f);
-            if (m >= 0) {
+            if (m >= 0 && rpb >= 1 && rpb <= kMaxRunsPerBlock) {
                 b->mode = m;
-                if (ppb != b->count_ppb) {
-                    b->count_ppb = ppb;
-                    sph_status st = batch_layout(b);
-                    if (st != SPH_OK) return st;
-                }
+                b->count_ppb = ppb;
+                b->cls_rpb = rpb;
+                HIP_CHECKED(batch_layout(b));
                 if (mode_out) *mode_out = m;
                 if (ppb_out) *ppb_out = ppb;
                 if (ms_out) *ms_out = ms;
@@ -4184,47 +4209,55 @@ extern "C" sph_status sph_batch_tune(sph_batch *b, int32_t trials, const char *c
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
+    auto time_config = [&](int mode, int ppb, int rpb, double &ms_step) -> sph_status {
+        b->mode = mode;
+        if (ppb != b->count_ppb || rpb != b->cls_rpb) {
+            b->count_ppb = ppb;
+            b->cls_rpb = rpb;
+            HIP_CHECKED(batch_layout(b));
+        }
+        for (int w = 0; w < 2; ++w) HIP_CHECKED(sph_batch_step(b));
+        HIP_TRY(hipEventRecord(e0, b->stream));
+        for (int t = 0; t < trials; ++t) HIP_CHECKED(sph_batch_step(b));
+        HIP_TRY(hipEventRecord(e1, b->stream));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        ms_step = ms / trials;
+        return SPH_OK;
+    };
     const int ppbs[] = {1024, 2048, 4096, 8192};
+    const int rpbs[] = {1, 2, 3, 4, 6, 8};
     double best = 1e30;
-    int best_mode = b->mode, best_ppb = b->count_ppb;
+    int best_mode = b->mode, best_ppb = b->count_ppb, best_rpb = b->cls_rpb;
     for (int mode = SPH_BATCH_KERNELS; mode <= SPH_BATCH_GRAPH; ++mode)
         for (int ppb : ppbs) {
-            b->mode = mode;
-            if (ppb != b->count_ppb) {
-                b->count_ppb = ppb;
-                sph_status st = batch_layout(b);
-                if (st != SPH_OK) return st;
-            }
-            for (int w = 0; w < 2; ++w) {
-                sph_status st = sph_batch_step(b);
-                if (st != SPH_OK) return st;
-            }
-            HIP_TRY(hipEventRecord(e0, b->stream));
-            for (int t = 0; t < trials; ++t) {
-                sph_status st = sph_batch_step(b);
-                if (st != SPH_OK) return st;
-            }
-            HIP_TRY(hipEventRecord(e1, b->stream));
-            HIP_TRY(hipEventSynchronize(e1));
-            float ms = 0;
-            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-            if (ms / trials < best) {
-                best = ms / trials;
+            double ms = 0;
+            HIP_CHECKED(time_config(mode, ppb, best_rpb, ms));
+            if (ms < best) {
+                best = ms;
                 best_mode = mode;
                 best_ppb = ppb;
             }
         }
+    for (int rpb : rpbs) {
+        if (rpb == best_rpb) continue;
+        double ms = 0;
+        HIP_CHECKED(time_config(best_mode, best_ppb, rpb, ms));
+        if (ms < best) {
+            best = ms;
+            best_rpb = rpb;
+        }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     b->mode = best_mode;
-    if (best_ppb != b->count_ppb) {
-        b->count_ppb = best_ppb;
-        sph_status st = batch_layout(b);
-        if (st != SPH_OK) return st;
-    }
+    b->count_ppb = best_ppb;
+    b->cls_rpb = best_rpb;
+    HIP_CHECKED(batch_layout(b));
     if (cache_path)
         if (FILE *f = std::fopen(cache_path, "a")) {
-            std::fprintf(f, "%s|%d|%d|%.6f\n", key, best_mode, best_ppb, best);
+            std::fprintf(f, "%s|%d|%d|%d|%.6f\n", key, best_mode, best_ppb, best_rpb, best);
             std::fclose(f);
         }
     if (mode_out) *mode_out = best_mode;

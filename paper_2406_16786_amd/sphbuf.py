@@ -41,6 +41,7 @@ EXPORTED = (
     "sph_rotation_from_direction", "sph_check_rotation", "sph_grid_cover", "sph_guard_band",
     "sph_status_str", "sph_profile_enable", "sph_profile_read", "sph_grid_fit",
     "sph_batch_create", "sph_batch_destroy", "sph_batch_set_mode", "sph_batch_set_count_block",
+    "sph_batch_set_gather", "sph_batch_get_config",
     "sph_batch_step", "sph_batch_results", "sph_batch_tune",
     "sph_set_fields", "sph_buffer_set_bc", "sph_buffer_apply_bc", "sph_buffer_rotate", "sph_neighbor_count",
     "sph_state_export", "sph_state_import", "sph_batch_graph_capture", "sph_batch_graph_launch",
@@ -200,6 +201,8 @@ def lib() -> ctypes.CDLL:
             "sph_batch_destroy": ([_VP], ctypes.c_int),
             "sph_batch_set_mode": ([_VP, ctypes.c_int32], ctypes.c_int),
             "sph_batch_set_count_block": ([_VP, ctypes.c_int32], ctypes.c_int),
+            "sph_batch_set_gather": ([_VP, ctypes.c_int32], ctypes.c_int),
+            "sph_batch_get_config": ([_VP, _I32, _I32, _I32], ctypes.c_int),
             "sph_batch_step": ([_VP], ctypes.c_int),
             "sph_batch_results": ([_VP, ctypes.POINTER(sph_result)], ctypes.c_int),
             "sph_batch_tune": ([_VP, ctypes.c_int32, ctypes.c_char_p, _I32, _I32, _D], ctypes.c_int),
@@ -495,6 +498,17 @@ def sph_batch_set_mode(b: int, mode: int) -> int:
 
 def sph_batch_set_count_block(b: int, ppb: int) -> int:
     return lib().sph_batch_set_count_block(b, int(ppb))
+
+
+def sph_batch_set_gather(b: int, runs_per_block: int) -> int:
+    return lib().sph_batch_set_gather(b, int(runs_per_block))
+
+
+def sph_batch_get_config(b: int):
+    """(status, mode, particles per count block, runs per classify workgroup)."""
+    m, ppb, rpb = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+    st = lib().sph_batch_get_config(b, ctypes.byref(m), ctypes.byref(ppb), ctypes.byref(rpb))
+    return st, m.value, ppb.value, rpb.value
 
 
 def sph_batch_step(b: int) -> int:
