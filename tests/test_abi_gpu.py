@@ -124,10 +124,12 @@ def test_state_export_import_round_trip():
         W.advect_host(wl, st.pos, st.n, step)
         upload_state(d, st)
         d.build()
-        assert d.update()[0] == 0
+        res = oracle.update(bufs, st)   # the host state follows the device's
+        assert d.update()[0] == res.status == 0
     rc, blob = S.sph_state_export(d.ctx)
     assert rc == 0 and len(blob) == S.SPH_STATE_BLOB_BYTES
     rc, nid, nl = S.sph_state_get(d.ctx)
+    assert nid == st.next_id and list(nl[: len(bufs)]) == list(res.n_labelled)
     d2 = make_domain(wl, bufs, oracle_state(wl))
     assert S.sph_state_import(d2.ctx, blob) == 0
     rc2, nid2, nl2 = S.sph_state_get(d2.ctx)
