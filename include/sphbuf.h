@@ -191,6 +191,30 @@ sph_status sph_grid_fit(sph_ctx *ctx, const sph_particles *p);
  * build. */
 sph_status sph_celllist_build(sph_ctx *ctx, const sph_particles *p);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the cell-list build of
+ * sph_celllist_build on a dense grid, without a context.  Every scratch array of
+ * the build (cell counts, packed cell keys and ranks, scan tile states, control
+ * words) lives in one library-owned device array of fixed size, one copy per GPU,
+ * held until the process ends; nothing is allocated or freed, no allocating
+ * library routine is called.  Calls on one GPU share that array: calls that
+ * overlap on one GPU (different streams, threads) race, so order them.
+ *   dim, lo, cell_size, dims: the grid (cells per axis; particles outside it are
+ *     binned into the edge cells; FP32 binning as sph_create requires);
+ *   x, y, z: device FP32 positions (z ignored in 2-D), at least capacity long;
+ *   n_dev: device int64, the live count (clamped to [0, capacity]);
+ *   cell_start: device int32 [cells + 1], cell_idx: device int32 [capacity]
+ *     (caller-owned outputs, as sph_celllist_view describes them);
+ *   stream: hipStream_t (NULL = the null stream).  Async.
+ * SPH_ERR_ARG for a NULL pointer, a bad grid, more than SPH_NOALLOC_MAX_CELLS
+ * cells or a capacity above SPH_NOALLOC_MAX_PARTICLES (nothing is launched).  The
+ * first call on a GPU also clears its copy of the array (a small kernel). */
+#define SPH_NOALLOC_MAX_PARTICLES (1 << 20)
+#define SPH_NOALLOC_MAX_CELLS (1 << 20)
+sph_status sph_celllist_build_noalloc(int32_t dim, const double lo[3], double cell_size, const int32_t dims[3],
+                                      const float *x, const float *y, const float *z, const int64_t *n_dev,
+                                      int64_t capacity, int32_t *cell_start, int32_t *cell_idx, void *stream);
+
 /* Algorithm 1, identification (run once, before the first update): label k for every live
  * particle inside buffer k's box; buffer_id = -1 for all buffers.  Full pass over
  * the particles (sync).  SPH_ERR_NONFINITE leaves labels untouched. */

@@ -24,6 +24,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -3230,6 +3231,139 @@ extern "C" sph_status sph_celllist_build(sph_ctx *ctx, const sph_particles *p) {
     }
     HIP_TRY(hipGetLastError());
     ctx->built = true;
+    return SPH_OK;
+}
+
+// ----------------------------------------- cell-list build, no allocation --
+//
+// The three-kernel build of sph_celllist_build for callers that cannot allocate
+// device memory: every scratch array of the build (cell counts, packed (key,
+// rank) words, their spill words, the scan's tile states, the control block)
+// lives in one file-scope device array of fixed size, one copy per GPU for the
+// life of the process.  Its address on a device is taken once, with that device
+// current, and used for every launch there.
+
+namespace {
+
+constexpr int64_t kNaParticles = SPH_NOALLOC_MAX_PARTICLES;
+constexpr int64_t kNaCells = SPH_NOALLOC_MAX_CELLS;
+constexpr int64_t kNaTiles = (kNaCells + 1 + kScanTile - 1) / kScanTile;
+constexpr size_t kNaAlign = 256;
+constexpr size_t na_up(size_t b) { return (b + kNaAlign - 1) / kNaAlign * kNaAlign; }
+constexpr size_t kNaCountOff = 0;
+constexpr size_t kNaPackedOff = kNaCountOff + na_up(sizeof(int32_t) * (kNaCells + 1));
+constexpr size_t kNaSpillOff = kNaPackedOff + na_up(sizeof(uint32_t) * kNaParticles);
+constexpr size_t kNaTileOff = kNaSpillOff + na_up(sizeof(unsigned long long) * kNaParticles);
+constexpr size_t kNaCtlOff = kNaTileOff + na_up(sizeof(unsigned long long) * kNaTiles);
+constexpr size_t kNaBytes = kNaCtlOff + na_up(sizeof(Ctl));
+constexpr int kNaMaxDevices = 64;
+
+// Clears a word range (the counts and the control block start at zero).
+__global__ void k_fill_words(uint32_t *w, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        w[i] = 0u;
+}
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+// Device address of scratch on each device (taken once per device, with that
+// device current); host code uses these, never the symbol itself.
+static unsigned char *g_na_ptr[kNaMaxDevices];
+static std::mutex g_na_mutex;
+
+extern "C" sph_status sph_celllist_build_noalloc(int32_t dim, const double lo[3], double cell_size,
+                                                 const int32_t dims[3], const float *x, const float *y, const float *z,
+                                                 const int64_t *n_dev, int64_t capacity, int32_t *cell_start,
+                                                 int32_t *cell_idx, void *stream) {
+    if ((dim != 2 && dim != 3) || !lo || !dims || !x || !y || (dim == 3 && !z) || !n_dev || !cell_start || !cell_idx)
+        return SPH_ERR_ARG;
+    if (!(cell_size > 0.0) || !std::isfinite(cell_size)) return SPH_ERR_ARG;
+    if (capacity < 1 || capacity > kNaParticles) return SPH_ERR_ARG;
+    int64_t cells = 1;
+    int32_t d3[3] = {1, 1, 1};
+    double glo[3] = {0.0, 0.0, 0.0};
+    for (int c = 0; c < dim; ++c) {
+        if (dims[c] < 1 || !std::isfinite(lo[c])) return SPH_ERR_ARG;
+        d3[c] = dims[c];
+        glo[c] = lo[c];
+        cells *= dims[c];
+        if (cells > kNaCells) return SPH_ERR_ARG;
+    }
+    if (!(sphbuf::binning_error_cells(dim, glo, cell_size, d3) < sphbuf::kMaxBinningError)) return SPH_ERR_ARG;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNaMaxDevices) return SPH_ERR_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    unsigned char *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_na_mutex);
+        if (!g_na_ptr[dev]) {
+            void *ptr = nullptr;
+            HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+            // the counts and the control block start at zero (later builds leave the
+            // counts they used at zero again: the scan clears them)
+            hipLaunchKernelGGL(k_fill_words, dim3(256), dim3(256), 0, st,
+                               reinterpret_cast<uint32_t *>(static_cast<unsigned char *>(ptr) + kNaCountOff),
+                               (int64_t)(kNaPackedOff / 4));
+            hipLaunchKernelGGL(k_fill_words, dim3(1), dim3(256), 0, st,
+                               reinterpret_cast<uint32_t *>(static_cast<unsigned char *>(ptr) + kNaCtlOff),
+                               (int64_t)(na_up(sizeof(Ctl)) / 4));
+            HIP_TRY(hipGetLastError());
+            g_na_ptr[dev] = static_cast<unsigned char *>(ptr);
+        }
+        base = g_na_ptr[dev];
+    }
+    Ctl *ctl = reinterpret_cast<Ctl *>(base + kNaCtlOff);
+    Grid g{};
+    for (int c = 0; c < 3; ++c) {
+        g.lo[c] = (float)glo[c];
+        g.dims[c] = d3[c];
+        g.bdims[c] = 1;
+    }
+    g.inv_cs = (float)(1.0 / cell_size);
+    g.dim = dim;
+    g.blog2 = 0;
+    g.brick_slot = nullptr;
+    g.overflow_key = (uint32_t)(cells - 1);
+    const int64_t m = cells + 1;
+    CountArgs ca{};
+    ca.x = x;
+    ca.y = y;
+    ca.z = dim == 3 ? z : nullptr;
+    ca.n_dev = n_dev;
+    ca.capacity = capacity;
+    ca.g = g;
+    ca.count = reinterpret_cast<int32_t *>(base + kNaCountOff);
+    ca.packed = reinterpret_cast<uint32_t *>(base + kNaPackedOff);
+    ca.spill = reinterpret_cast<unsigned long long *>(base + kNaSpillOff);
+    ca.rbits = rank_bits(cells);
+    ca.tile_state = reinterpret_cast<unsigned long long *>(base + kNaTileOff);
+    ca.n_tiles = (m + kScanTile - 1) / kScanTile;
+    ca.ctl = ctl;
+    ca.nonfinite = &ctl->nonfinite_build;
+    hipLaunchKernelGGL(k_count, dim3(count_blocks(capacity)), dim3(kBuildBlock), 0, st, ca);
+    ScanArgs sa{};
+    sa.count = ca.count;
+    sa.cell_start = cell_start;
+    sa.m = m;
+    sa.tile_state = ca.tile_state;
+    sa.ctl = ctl;
+    hipLaunchKernelGGL(k_scan, dim3((unsigned)ca.n_tiles), dim3(kScanBlock), 0, st, sa);
+    ScatterArgs xa{};
+    xa.n_dev = &ctl->n_built;
+    xa.capacity = capacity;
+    xa.ctl = ctl;
+    xa.packed = ca.packed;
+    xa.spill = ca.spill;
+    xa.rbits = ca.rbits;
+    xa.cell_start = cell_start;
+    xa.cell_idx = cell_idx;
+    const int64_t want = (capacity + kBuildBlock - 1) / kBuildBlock;
+    const int blocks = (int)std::max<int64_t>(8, std::min<int64_t>(8192, (want + 7) / 8 * 8));
+    hipLaunchKernelGGL(k_scatter, dim3(blocks), dim3(kBuildBlock), 0, st, xa);
+    HIP_TRY(hipGetLastError());
     return SPH_OK;
 }
 

@@ -47,7 +47,10 @@ EXPORTED = (
     "sph_state_export", "sph_state_import", "sph_batch_graph_capture", "sph_batch_graph_launch",
     "sph_batch_profile_enable", "sph_batch_profile_read",
     "sph_buffer_rotate_async", "sph_buffer_apply_bc_async", "sph_last_bc_status", "sph_buffer_cover",
+    "sph_celllist_build_noalloc",
 )
+SPH_NOALLOC_MAX_PARTICLES = 1 << 20
+SPH_NOALLOC_MAX_CELLS = 1 << 20
 BATCH_PHASES = ("count", "scan", "scatter", "classify", "finalize")
 SPH_BATCH_KERNELS, SPH_BATCH_GRAPH = 0, 1
 SPH_NPHASE = 11
@@ -195,6 +198,8 @@ def lib() -> ctypes.CDLL:
             "sph_buffer_apply_bc_async": ([_VP, ctypes.POINTER(sph_particles)], ctypes.c_int),
             "sph_last_bc_status": ([_VP], ctypes.c_int),
             "sph_buffer_cover": ([_VP, ctypes.c_int32, _I32, _I32, ctypes.c_int64, _I64], ctypes.c_int),
+            "sph_celllist_build_noalloc": ([ctypes.c_int32, _D, ctypes.c_double, _I32, _VP, _VP, _VP, _VP,
+                                            ctypes.c_int64, _VP, _VP, _VP], ctypes.c_int),
             "sph_neighbor_count": ([_VP, ctypes.POINTER(sph_particles), ctypes.c_double, _VP], ctypes.c_int),
             "sph_batch_create": ([ctypes.POINTER(_VP), ctypes.POINTER(sph_particles), ctypes.c_int32, _VP,
                                   ctypes.POINTER(_VP)], ctypes.c_int),
@@ -335,6 +340,16 @@ def sph_buffer_cover(ctx: int, buffer_id: int, cap: int = 1 << 22):
     st = lib().sph_buffer_cover(ctx, int(buffer_id), f.ctypes.data_as(_I32), ln.ctypes.data_as(_I32), int(cap),
                                 ctypes.byref(n))
     return st, f[: n.value].copy(), ln[: n.value].copy()
+
+
+def sph_celllist_build_noalloc(dim: int, lo, cell_size: float, dims, x_ptr: int, y_ptr: int, z_ptr: int,
+                               n_dev_ptr: int, capacity: int, cell_start_ptr: int, cell_idx_ptr: int,
+                               stream: int = 0) -> int:
+    """Device pointers throughout (async on stream)."""
+    d3 = (ctypes.c_int32 * 3)(*[int(v) for v in (list(dims) + [1, 1, 1])[:3]])
+    return lib().sph_celllist_build_noalloc(int(dim), _d3(lo), float(cell_size), d3, _VP(x_ptr), _VP(y_ptr),
+                                            _VP(z_ptr or None), _VP(n_dev_ptr), int(capacity), _VP(cell_start_ptr),
+                                            _VP(cell_idx_ptr), _VP(stream or None))
 
 
 def sph_buffer_identify(ctx: int, p: sph_particles, buffer_id: int = -1) -> int:
