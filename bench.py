@@ -120,14 +120,18 @@ class Snapshot:
 
 
 def phase_bytes(dim: int, n: int, n_cells: int, cand: int, g: int, d: int, n_carried: int):
-    """Algorithmic bytes per launch of each kernel phase (what the step must move)."""
+    """Algorithmic bytes per launch of each kernel phase: its inputs and outputs in
+    HBM, the bucketed build's intermediates included ("build" is the least any
+    build must move: positions in, cell list out)."""
     state = 4 * dim + 4 * n_carried + 4 + 8          # bytes of one particle's state
     return {
         "build": (4 * dim + 4) * n + 4 * (n_cells + 1), # read positions, write cell_idx and cell_start
-        "count": 4 * dim * n,                           # read positions
-        "scan": 8 * (n_cells + 1),                      # read counts, write cell starts
-        "scatter": 4 * n,                               # write the cell-ordered index list
+        "count": (4 * dim + 8) * n,                     # read positions, write (key, rank in bucket)
+        "scatter": 16 * n,                              # read (key, rank), write (key, particle) in bucket order
+        "sort": 12 * n + 4 * (n_cells + 1),             # read (key, particle), write cell_idx and cell_start
+        "scan": 8 * (n_cells + 1),                      # (batched build) read counts, write cell starts
         "classify": cand * (4 * dim + 8),               # candidate index, position, label
+        "candidates": cand * (4 * dim + 8),
         "fullscan": 4 * dim * n,                        # read positions
         "finalize": (g + d) * 8 + g * (2 * state) + d * 2 * state,  # events, duplicates, refills
     }
@@ -317,8 +321,7 @@ def single_leg(torch, np, S, W, Domain, wl, K, Wm, late, early, args):
     n0 = int(s0.n_dev.item())
     cand = cover_candidates(np, S, wl, rots, [t.cpu().numpy() for t in s0.pos], n0)
     pb = phase_bytes(wl.dim, int(L["n_mean"]), n_cells, cand, int(L["g_mean"]), int(L["d_mean"]), len(wl.carried))
-    pb["count"] += 4 * cand   # the classifying count pass also reads each candidate's label
-    kernel_of = {"count": "k_count_cls", "finalize": "k_scan_finalize", "scatter": "k_scatter"}
+    kernel_of = {"count": "k_bk_count", "scatter": "k_bk_scatter_cls", "sort": "k_bk_sort", "finalize": "k_finalize"}
     step_bytes = pb["build"] + pb["classify"] + pb["finalize"]
     ms = L["ms_merged"]
     n_mean = L["n_mean"]
@@ -341,8 +344,9 @@ def single_leg(torch, np, S, W, Domain, wl, K, Wm, late, early, args):
                            "traffic": measured_traffic(wl.name, kname), "avg_launch_us": round(avg_ms * 1e3, 2),
                            "algorithmic_bytes_per_launch": int(pb[dom_phase])}
         out["phases_us"] = {k: round(v * 1e3, 2) for k, v in pm.items()}
-        out["phases_note"] = ("merged step: count = the classifying count pass, finalize = the finalize "
-                              "workgroups beside the scan tiles in one launch")
+        out["phases_note"] = ("merged step: count = bucket counts and the candidate list, scatter = the bucket "
+                              "scatter with the candidates' exact tests beside it, sort = the per-bucket counting "
+                              "sort, finalize = the events applied")
     if pc:
         t_upd = pc.get("classify", 0.0) + pc.get("finalize", 0.0)
         t_full = pf["fullscan"] + pf.get("candidates", 0.0) + pf["finalize"] if pf else None
@@ -784,8 +788,8 @@ def main() -> int:
                    "dim": wl.dim, "buffers": len(wl.buffers), "cells": h["cells"],
                    "candidates_per_update": h["candidates_per_update"], "events_per_step": h["events_per_step"],
                    "timed_steps": h["timed_steps"],
-                   "path": "merged step: cell-list build classifying the cover cells' particles in its count "
-                           "pass + finalize beside the scan, then the scatter"},
+                   "path": "merged step: bucketed cell-list build whose count pass lists the cover cells' "
+                           "candidates; their exact tests beside the bucket scatter; bucket sort; finalize"},
         "roofline": h.get("roofline"),
     }
     for k, v in h.items():

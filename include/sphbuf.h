@@ -360,9 +360,10 @@ sph_status sph_state_import(sph_ctx *ctx, const void *blob, size_t len);
 
 /* Kernel phases timed by the optional per-launch HIP events. */
 typedef enum {
-    SPH_PHASE_COUNT = 0,      /* cell keys + per-cell ranks (atomics)            */
-    SPH_PHASE_SCAN = 1,       /* exclusive scan of the cell counts                */
-    SPH_PHASE_SCATTER = 2,    /* particle indices into cell order                 */
+    SPH_PHASE_COUNT = 0,      /* cell keys; bucket ranks (or per-cell ranks)      */
+    SPH_PHASE_SCAN = 1,       /* exclusive scan of the cell counts (batch, large grids) */
+    SPH_PHASE_SCATTER = 2,    /* into bucket order (or cell order); merged step:
+                                 with the candidates' exact tests beside it      */
     SPH_PHASE_CLASSIFY = 3,   /* local-cell candidates, frame, crossing tests     */
     SPH_PHASE_FULLSCAN = 4,   /* full scan: every particle, FP32 filter (baseline)*/
     SPH_PHASE_FINALIZE = 5,   /* status, sort, duplicate/recycle/relabel/compact  */
@@ -371,7 +372,8 @@ typedef enum {
     SPH_PHASE_CANDIDATES = 8, /* full scan: the filter's candidates, exact tests  */
     SPH_PHASE_NEIGHBOR = 9,   /* neighbour counts over the cell list              */
     SPH_PHASE_COVER = 10,     /* cover cells of a turned buffer (two launches)    */
-    SPH_NPHASE = 11
+    SPH_PHASE_SORT = 11,      /* per-bucket counting sort: cell starts, cell_idx  */
+    SPH_NPHASE = 12
 } sph_phase;
 
 /* When on, every kernel launch of the context is bracketed by two HIP events on

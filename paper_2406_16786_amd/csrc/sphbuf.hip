@@ -105,6 +105,8 @@ struct Ctl {
     unsigned int pad1;
     unsigned long long ident_count[16];
     int64_t n_built;               // particles of the latest count pass (what its scatter places)
+    unsigned int bk_ticket;        // bucketed build: count workgroups that have finished
+    unsigned int pad2;
     int32_t run_cnt[16];           // cover runs of each buffer (in its range of the per-buffer run lists)
     int32_t n_runs;                // runs of the compact list the classify and BC kernels walk
     int32_t cover_fault;           // a turned buffer's cover needed more runs than its range holds
@@ -439,8 +441,6 @@ __device__ __forceinline__ T &at32(T *base, uint32_t o) {
 
 constexpr int kCountBatch = 2;
 constexpr int64_t kCountPer = 2048;  // particles per count workgroup (single domain)
-constexpr int kClsList = 2048;       // classifying count pass: particles per workgroup at most
-constexpr int kClsStash = 384;       // ... of which keep their position and label in LDS
 
 struct CountArgs {
     const float *x, *y, *z;
@@ -457,20 +457,7 @@ struct CountArgs {
     unsigned int *nonfinite;        // flag to raise on a non-finite position
 };
 
-// The classifying count pass of the merged step: every particle whose cell is in
-// buffer k's cover (bit k of cover[key]) is tested against buffer k there and its
-// events emitted, so that the update only has to finalize them.  (Its own
-// argument block: the plain pass keeps a small one.)
-struct ClsArgs : CountArgs {
-    const uint16_t *cover;
-    int nb;
-    Parts p;
-    const BufDev *bufs;
-    EventArgs e;
-};
-
-template <bool kCls, class A>  // the merged step's classification compiled in (A = ClsArgs; its own kernel: registers)
-__device__ __forceinline__ void count_body(const A &a, const int lb, const int G) {
+__device__ __forceinline__ void count_body(const CountArgs &a, const int lb, const int G) {
     const int64_t N = live_count(a.n_dev, a.capacity);
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t nthreads = (int64_t)G * blockDim.x;
@@ -481,31 +468,12 @@ __device__ __forceinline__ void count_body(const A &a, const int lb, const int G
         a.ctl->scan_fault = 0u;
         a.ctl->n_built = N;
     }
-    // classification: the block's particles in cover cells, as (offset << 16 | cover
-    // bits), classified after the count loop (its registers are free by then); the
-    // first kClsStash of them keep their position and label here too
-    __shared__ uint32_t s_cl[kClsList];
-    __shared__ float s_px[kClsStash], s_py[kClsStash], s_pz[kClsStash];
-    __shared__ int32_t s_lab[kClsStash];
-    __shared__ unsigned s_ncl;
-    __shared__ unsigned s_cnt[2 * SPH_MAX_BUFFERS];  // label counts of the classification
-    __shared__ BufDev s_b[SPH_MAX_BUFFERS];
-    if constexpr (kCls) {
-        block_counts_init(s_cnt);
-        if (threadIdx.x == 0) s_ncl = 0u;
-        for (int t = threadIdx.x; t < a.nb * (int)(sizeof(BufDev) / 4); t += blockDim.x)
-            reinterpret_cast<uint32_t *>(s_b)[t] = reinterpret_cast<const uint32_t *>(a.bufs)[t];
-        __syncthreads();
-    }
     // Each logical block walks kCountBatch * W slices of L particles, one per wave and
     // row (kCountBatch rows per wave): at every step the block's waves take the next
     // 64 particles of each of their slices, so the particles whose atomics are in
     // flight together lie a slice apart -- beyond the few lattice rows that share a
     // cell -- and rarely meet on one counter (same-address atomics queue at the
-    // memory side).  The plain pass cuts one contiguous segment of the block into
-    // its slices; the classifying pass takes slice q of block lb at (q * G + lb) * L,
-    // so the particles of a buffer's cover (a contiguous stretch of a spatially
-    // ordered array) spread over many workgroups instead of crowding a few.
+    // memory side).  One contiguous segment of the block is cut into its slices.
     const int W = (int)(blockDim.x / kWave);
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));  // uniform: scalar row bases
     const int64_t slices = (int64_t)W * kCountBatch;
@@ -514,7 +482,7 @@ __device__ __forceinline__ void count_body(const A &a, const int lb, const int G
     const int64_t s0 = (int64_t)lb * per;
     bool bad = false;
     const uint32_t rmask = (1u << a.rbits) - 1u;
-    if ((kCls ? (int64_t)lb * L : s0) >= N) return;  // block-uniform: no particle here
+    if (s0 >= N) return;  // block-uniform: no particle here
     constexpr int J = kCountBatch;
     const uint32_t L32 = (uint32_t)L;
     // per row: first particle, particles in it (slice-relative 32-bit offsets from
@@ -524,7 +492,7 @@ __device__ __forceinline__ void count_body(const A &a, const int lb, const int G
 #pragma unroll
     for (int j = 0; j < J; ++j) {
         const int64_t q = (int64_t)j * W + w;
-        rb[j] = kCls ? (q * G + lb) * L : s0 + q * L;
+        rb[j] = s0 + q * L;
         const int64_t left = N - rb[j];
         nr[j] = left <= 0 ? 0u : (left >= L ? L32 : (uint32_t)left);
     }
@@ -569,51 +537,10 @@ __device__ __forceinline__ void count_body(const A &a, const int lb, const int G
 #pragma unroll
         for (int j = 0; j < J; ++j) valid[j] = o < nr[j];
         group_keys<J>(a.g, px, py, pz, valid, key, bad);
-        // classification: the cover bits are loaded before the next positions and the
-        // atomics, so waiting for them waits for nothing else
-        uint32_t cm[J];
-        float cx[J], cy[J], cz[J];
-        if constexpr (kCls) {
-#pragma unroll
-            for (int j = 0; j < J; ++j) {
-                cm[j] = valid[j] ? a.cover[key[j]] : 0u;
-                cx[j] = px[j];
-                cy[j] = py[j];
-                cz[j] = pz[j];
-            }
-        }
         const uint32_t nx = it + kWave;
         if (nx < L32) load(nx);  // block-uniform; the positions are consumed
         int my_head[J], old[J];
         group_runs_issue<J>(a.count, key, valid, lane, my_head, old);
-        if constexpr (kCls) {  // the particles in some cover cell join the block's list
-            bool has[J];
-            bool any = false;
-#pragma unroll
-            for (int j = 0; j < J; ++j) {
-                has[j] = cm[j] != 0u;
-                any = any || has[j];
-            }
-            if (__ballot(any) != 0ull) {  // wave-uniform
-#pragma unroll
-                for (int j = 0; j < J; ++j) {
-                    const unsigned long long mj = __ballot(has[j]);
-                    if (mj == 0ull) continue;
-                    unsigned at = 0u;
-                    if (lane == 0) at = atomicAdd(&s_ncl, (unsigned)__popcll(mj));
-                    at = __shfl(at, 0) + mbcnt(mj);
-                    if (has[j]) {
-                        s_cl[at] = (((uint32_t)(j * W + w) * L32 + o) << 16) | cm[j];
-                        if (at < (unsigned)kClsStash) {  // label load in flight with the atomics
-                            s_px[at] = cx[j];
-                            s_py[at] = cy[j];
-                            s_pz[at] = cz[j];
-                            s_lab[at] = at32(a.p.label + rb[j], o);
-                        }
-                    }
-                }
-            }
-        }
         group_ranks<J>(my_head, old, lane, rank);
 #pragma unroll
         for (int j = 0; j < kCountBatch; ++j) {
@@ -627,70 +554,9 @@ __device__ __forceinline__ void count_body(const A &a, const int lb, const int G
         }
     }
     if (__ballot(bad) != 0ull && lane == 0) atomicOr(a.nonfinite, 1u);
-    if constexpr (kCls) {
-        __syncthreads();
-        const unsigned ncl = s_ncl;
-        if (ncl == 0u) return;  // block-uniform
-        const int dim = a.g.dim;
-        const int sg = (int)(((unsigned)lb * (unsigned)W + (unsigned)w) % (unsigned)kSeg);
-        for (unsigned e0 = 0; e0 < ncl; e0 += blockDim.x) {  // block-uniform trip count
-            const unsigned e = e0 + threadIdx.x;
-            const uint32_t ent = e < ncl ? s_cl[e] : 0u;
-            const uint32_t vo = ent >> 16;  // slice * L + offset in the slice
-            uint32_t bm = ent & 0xffffu;
-            const int64_t i = ((int64_t)(vo / L32) * G + lb) * L + (int64_t)(vo % L32);
-            float x = 0.0f, y = 0.0f, z = 0.0f;
-            int lab = 0;
-            if (bm && e < (unsigned)kClsStash) {
-                x = s_px[e];
-                y = s_py[e];
-                z = s_pz[e];
-                lab = s_lab[e];
-            } else if (bm) {
-                x = a.x[i];
-                y = a.y[i];
-                z = d3 ? a.z[i] : 0.0f;
-                lab = a.p.label[i];
-            }
-            while (__ballot(bm != 0u) != 0ull) {  // each lane's buffers in turn (the buffer varies per lane)
-                const bool c = bm != 0u;
-                const int k = c ? __ffs(bm) - 1 : 0;
-                bm &= bm - 1u;
-                const BufDev &b = s_b[k];
-                Outcome oc{kEvNone, -1, false};
-                if (c) {
-                    const unsigned bits = classify(b, dim, x, y, z);
-                    if (bits & kIn) oc = decide(b, k, dim, bits, lab, x, y, z);
-                }
-                unsigned long long found = 0, post = 0;
-                const float carv[SPH_MAX_CARRIED] = {};
-                emit<false>(a.e, a.p, b, k, sg, c, i, lab, oc, x, y, z, carv, found, post);
-                // label counts: one LDS atomic per wave and buffer, not per lane
-                unsigned ks = c ? 1u << k : 0u;
-                for (int off = 32; off > 0; off >>= 1) ks |= (unsigned)__shfl_xor((int)ks, off);
-                while (ks) {  // wave-uniform
-                    const int kk = __ffs(ks) - 1;
-                    ks &= ks - 1u;
-                    const unsigned nf = (unsigned)__popcll(__ballot(c && k == kk && found));
-                    const unsigned np = (unsigned)__popcll(__ballot(c && k == kk && post));
-                    if (lane == 0 && (nf | np)) {
-                        atomicAdd(&s_cnt[2 * kk], nf);
-                        atomicAdd(&s_cnt[2 * kk + 1], np);
-                    }
-                }
-            }
-        }
-        __syncthreads();
-        block_counts_store(a.e, s_cnt, a.nb);
-    }
 }
 
-__global__ __launch_bounds__(kBuildBlock) void k_count(CountArgs a) { count_body<false>(a, logical_block(), gridDim.x); }
-
-// The count pass of the merged step (classification of the cover cells' particles).
-__global__ __launch_bounds__(kBuildBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_count_cls(ClsArgs a) {
-    count_body<true>(a, logical_block(), gridDim.x);
-}
+__global__ __launch_bounds__(kBuildBlock) void k_count(CountArgs a) { count_body(a, logical_block(), gridDim.x); }
 
 // Decoupled look-back scan state: bits 62..63 = flag (1 aggregate, 2 prefix),
 // low 32 bits = value.
@@ -1016,6 +882,7 @@ __global__ __launch_bounds__(kClassifyBlock) void k_classify_local(LocalArgs a) 
 constexpr int kFullVec = 4;  // particles per thread per step of the filter (a multiple of 4)
 constexpr int64_t kCandSlack = 4096;  // candidate list: capacity + this many entries
 constexpr int kCandBlocks = 2048;     // grid of the candidate pass (grid-stride over the list)
+constexpr int kCandBlocksMerged = 1024;  // ... beside the bucket scatter (fewer candidates: cover cells only)
 
 struct FullArgs {
     Parts p;
@@ -1142,11 +1009,15 @@ __global__ void k_reset_events(Ctl *ctl, unsigned *part, int clear_nf) {
         ctl->seg[threadIdx.x].n_del = 0u;
         ctl->seg[threadIdx.x].n_rel = 0u;
     }
-    if (threadIdx.x == 0 && clear_nf) ctl->nonfinite_full = 0u;
+    if (threadIdx.x == 0) {
+        if (clear_nf) ctl->nonfinite_full = 0u;
+        ctl->cand_count = 0ull;  // the merged step's candidates
+        ctl->cand_overflow = 0u;
+    }
     for (int w = threadIdx.x; w < kCountReplicas * 2 * SPH_MAX_BUFFERS; w += blockDim.x) part[w] = 0u;
 }
 
-__global__ __launch_bounds__(kClassifyBlock) void k_classify_cand(FullArgs a) {
+__device__ __forceinline__ void classify_cand_body(const FullArgs &a, const int lb, const int G) {
     __shared__ BufDev sb[SPH_MAX_BUFFERS];
     __shared__ unsigned s_cnt[2 * SPH_MAX_BUFFERS];
     for (int t = threadIdx.x; t < a.nb * (int)(sizeof(BufDev) / 4); t += blockDim.x)
@@ -1156,8 +1027,8 @@ __global__ __launch_bounds__(kClassifyBlock) void k_classify_cand(FullArgs a) {
     const unsigned long long cc = a.e.ctl->cand_count;
     const int64_t n_cand = cc < (unsigned long long)a.cap_cand ? (int64_t)cc : a.cap_cand;
     const int dim = a.p.dim;
-    const int seg = (int)((blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave) % kSeg);
-    for (int64_t t0 = (int64_t)blockIdx.x * blockDim.x; t0 < n_cand; t0 += (int64_t)gridDim.x * blockDim.x) {
+    const int seg = (int)((lb * (blockDim.x / kWave) + threadIdx.x / kWave) % kSeg);
+    for (int64_t t0 = (int64_t)lb * blockDim.x; t0 < n_cand; t0 += (int64_t)G * blockDim.x) {
         const int64_t t = t0 + threadIdx.x;
         const bool valid = t < n_cand;
         const unsigned long long ent = valid ? a.cand[t] : 0ull;
@@ -1189,6 +1060,354 @@ __global__ __launch_bounds__(kClassifyBlock) void k_classify_cand(FullArgs a) {
     __syncthreads();
     block_counts_store(a.e, s_cnt, a.nb);
 }
+
+__global__ __launch_bounds__(kClassifyBlock) void k_classify_cand(FullArgs a) {
+    classify_cand_body(a, blockIdx.x, gridDim.x);
+}
+
+// ----------------------------------------------------- bucketed cell list --
+//
+// The cell list of a context is built by a two-level counting sort whose memory
+// traffic does not depend on the order of the particle arrays (particles drift out
+// of any spatial order as the flow shears them; with one global atomic per cell
+// run, the counting-sort build above then pays for line-sized atomics spread over
+// the whole counter array and shared by all XCDs):
+//   k_bk_count : workgroups of kBkPer particles in array order (coalesced loads):
+//                cell keys, an LDS histogram over buckets of 2^bshift consecutive
+//                cells, one global atomic per (workgroup, bucket) for the
+//                workgroup's base in the bucket, then each particle's (key, rank
+//                in its bucket); the workgroup with the last ticket turns the
+//                bucket counts into bucket starts.  On the merged path the
+//                particles of the buffers' cover cells that lie near a check
+//                region are also appended to the candidate list.
+//   k_bk_scatter : (key, particle) into bucket order; a workgroup's run of a
+//                bucket lands contiguously.
+//   k_bk_sort  : one workgroup per bucket: an LDS counting sort of its entries
+//                over its cells, writing the bucket's cell starts and its
+//                contiguous range of cell_idx.
+// The order inside a cell is whatever the LDS atomics make it.
+
+constexpr int kBkBlock = 256;
+constexpr int kBkPer = 4096;          // particles per k_bk_count workgroup
+constexpr int kBkIt = kBkPer / kBkBlock;
+constexpr int kBkBatch = 4;           // particles per thread with loads in flight together
+constexpr int kMaxBuckets = 4096;
+constexpr int kMaxBucketCells = 4096;
+static_assert(kBkIt % kBkBatch == 0, "whole batches");
+
+struct BkArgs {
+    const float *x, *y, *z;
+    const int64_t *n_dev;
+    int64_t capacity;
+    Grid g;
+    int32_t bshift;           // cells per bucket: 1 << bshift
+    int32_t nbk;              // buckets
+    int64_t n_cells;          // C: cell_start holds C + 1 entries
+    uint32_t *bk_count;       // [nbk] zero between builds
+    uint32_t *bk_start;       // [nbk + 1]
+    uint2 *ent;               // [capacity] (key, rank in its bucket) per particle
+    uint2 *tmp;               // [capacity] (key, particle) in bucket order
+    int32_t *cell_start;
+    int32_t *cell_idx;
+    Ctl *ctl;
+    unsigned int *nonfinite;  // flag to raise on a non-finite position
+    // merged step: candidate list of the cover cells
+    const uint16_t *cover;
+    const BufDev *bufs;
+    int nb;
+    unsigned long long *cand;  // (index << 4) | buffer
+    int64_t cap_cand;
+};
+
+// Runs of equal values in consecutive lanes: the head lane of this lane's run and
+// the run's length (an invalid lane is a run of its own, of length 0).
+__device__ __forceinline__ void lane_runs(uint32_t v, bool valid, int lane, int &head, int &len) {
+    const uint32_t prev = __shfl_up(v, 1);
+    const bool h = !valid || lane == 0 || v != prev;
+    const unsigned long long heads = __ballot(h);
+    const unsigned long long le = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+    head = 63 - __clzll((long long)(heads & le));
+    const unsigned long long gt = heads & ~le;
+    len = valid ? (gt ? __ffsll((long long)gt) - 1 : 64) - head : 0;
+}
+
+// Exclusive prefix over v[0..n) in LDS, in place, by one workgroup of NT threads
+// (each takes kMaxBuckets / NT consecutive entries); returns the total.
+template <int NT>
+__device__ __forceinline__ uint32_t lds_exclusive_scan(uint32_t *v, int n, uint32_t *s_w) {
+    constexpr int kPer = kMaxBuckets / NT;
+    static_assert(kMaxBuckets == kMaxBucketCells, "one scan for both");
+    const int t0 = (int)threadIdx.x * kPer;
+    uint32_t loc[kPer];
+    uint32_t sum = 0u;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        loc[q] = t0 + q < n ? v[t0 + q] : 0u;
+        sum += loc[q];
+    }
+    const int lane = (int)threadIdx.x & (kWave - 1), wave = (int)threadIdx.x / kWave;
+    uint32_t incl = sum;
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint32_t t = __shfl_up(incl, off);
+        if (lane >= off) incl += t;
+    }
+    if (lane == kWave - 1) s_w[wave] = incl;
+    __syncthreads();
+    uint32_t base = 0u, total = 0u;
+    for (int w = 0; w < NT / kWave; ++w) {
+        if (w < wave) base += s_w[w];
+        total += s_w[w];
+    }
+    uint32_t run = base + incl - sum;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        if (t0 + q < n) v[t0 + q] = run;
+        run += loc[q];
+    }
+    __syncthreads();
+    return total;
+}
+
+template <bool kCand>
+__global__ __launch_bounds__(kBkBlock) void k_bk_count(BkArgs a) {
+    __shared__ uint32_t s_h[kMaxBuckets];  // counts, then bases, then cursors per bucket
+    __shared__ BufDev sb[kCand ? SPH_MAX_BUFFERS : 1];
+    __shared__ uint32_t s_w[kBkBlock / kWave];
+    __shared__ unsigned s_last;
+    const int64_t N = live_count(a.n_dev, a.capacity);
+    const int lb = logical_block(), G = (int)gridDim.x;
+    const int lane = (int)threadIdx.x & (kWave - 1);
+    if (lb == 0 && threadIdx.x == 0) a.ctl->n_built = N;
+    for (int t = threadIdx.x; t < a.nbk; t += kBkBlock) s_h[t] = 0u;
+    if constexpr (kCand)
+        for (int t = threadIdx.x; t < a.nb * (int)(sizeof(BufDev) / 4); t += kBkBlock)
+            reinterpret_cast<uint32_t *>(sb)[t] = reinterpret_cast<const uint32_t *>(a.bufs)[t];
+    __syncthreads();
+    const int64_t s0 = (int64_t)lb * kBkPer;
+    const bool d3 = a.g.dim == 3;
+    const float *zb = d3 ? a.z : a.x;  // a 2-D z is a copy of x, unused
+    bool bad = false;
+    const int dim = a.g.dim;
+    // keys of this thread's particles s0 + it * kBkBlock + threadIdx.x (kept for the ranks)
+    uint32_t key[kBkIt];
+    const bool live = s0 < N;  // block-uniform
+    if (live) {
+        // ---- counts per bucket (and the merged step's candidates) ----
+#pragma unroll
+        for (int it = 0; it < kBkIt; it += kBkBatch) {
+            float px[kBkBatch], py[kBkBatch], pz[kBkBatch];
+            bool ok[kBkBatch];
+#pragma unroll
+            for (int q = 0; q < kBkBatch; ++q) {  // every load of the batch first (no branch)
+                const int64_t i = s0 + (int64_t)(it + q) * kBkBlock + threadIdx.x;
+                ok[q] = i < N;
+                const int64_t ic = ok[q] ? i : 0;
+                px[q] = a.x[ic];
+                py[q] = a.y[ic];
+                pz[q] = zb[ic];
+            }
+#pragma unroll
+            for (int q = 0; q < kBkBatch; ++q) {
+                key[it + q] = 0u;
+                if (ok[q]) {
+                    bad |= !(isfinite(px[q]) && isfinite(py[q]) && isfinite(pz[q]));
+                    key[it + q] = cell_key(a.g, px[q], py[q], pz[q]);
+                }
+            }
+            uint32_t cm[kBkBatch];
+            if constexpr (kCand) {  // the cover bits of the batch, all loads issued together
+#pragma unroll
+                for (int q = 0; q < kBkBatch; ++q) cm[q] = ok[q] ? a.cover[key[it + q]] : 0u;
+            }
+#pragma unroll
+            for (int q = 0; q < kBkBatch; ++q) {
+                int head, len;
+                lane_runs(key[it + q] >> a.bshift, ok[q], lane, head, len);
+                if (len > 0 && lane == head) atomicAdd(&s_h[key[it + q] >> a.bshift], (uint32_t)len);
+            }
+            if constexpr (kCand) {
+#pragma unroll
+                for (int q = 0; q < kBkBatch; ++q) {
+                    // each cover bit kept only if the particle is near that check region
+                    // (the full scan's FP32 test widened by the guard band, which keeps
+                    // every member)
+                    if (__ballot(cm[q] != 0u) == 0ull) continue;  // wave-uniform
+                    const int64_t i = s0 + (int64_t)(it + q) * kBkBlock + threadIdx.x;
+                    const float zq = d3 ? pz[q] : 0.0f;
+                    unsigned cb = 0u;
+                    uint32_t m = cm[q];
+                    while (m) {
+                        const int k = __ffs(m) - 1;
+                        m &= m - 1u;
+                        const BufDev &b = sb[k];
+                        const bool in_box = px[q] > b.bmin[0] && px[q] < b.bmax[0] && py[q] > b.bmin[1] &&
+                                            py[q] < b.bmax[1] && zq > b.bmin[2] && zq < b.bmax[2];
+                        if (in_box && near_region(b, dim, px[q], py[q], zq)) cb |= 1u << k;
+                    }
+                    const unsigned mine = (unsigned)__popc(cb);
+                    unsigned incl = mine;
+                    for (int off = 1; off < kWave; off <<= 1) {
+                        const unsigned t = __shfl_up(incl, off);
+                        if (lane >= off) incl += t;
+                    }
+                    const unsigned tot = __shfl(incl, kWave - 1);
+                    unsigned long long at = 0ull;
+                    if (lane == 0 && tot) at = atomicAdd(&a.ctl->cand_count, (unsigned long long)tot);
+                    at = __shfl(at, 0) + (incl - mine);
+                    while (cb) {
+                        const int k = __ffs(cb) - 1;
+                        cb &= cb - 1u;
+                        if (at < (unsigned long long)a.cap_cand)
+                            a.cand[at] = ((unsigned long long)i << 4) | (unsigned long long)k;
+                        else
+                            a.ctl->cand_overflow = 1u;
+                        ++at;
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // ---- the workgroup's base in each bucket it meets: one global atomic each ----
+    for (int t = threadIdx.x; t < a.nbk; t += kBkBlock) {
+        const uint32_t c = s_h[t];
+        if (c) s_h[t] = atomicAdd(&a.bk_count[t], c);
+    }
+    __syncthreads();
+    if (live) {
+        // ---- each particle's rank in its bucket ----
+#pragma unroll
+        for (int it = 0; it < kBkIt; ++it) {
+            const int64_t i = s0 + (int64_t)it * kBkBlock + threadIdx.x;
+            const bool ok = i < N;
+            int head, len;
+            lane_runs(key[it] >> a.bshift, ok, lane, head, len);
+            uint32_t old = 0u;
+            if (len > 0 && lane == head) old = atomicAdd(&s_h[key[it] >> a.bshift], (uint32_t)len);
+            const uint32_t rank = __shfl(old, head) + (uint32_t)(lane - head);
+            if (ok) a.ent[i] = make_uint2(key[it], rank);
+        }
+    }
+    if (__ballot(bad) != 0ull && lane == 0) atomicOr(a.nonfinite, 1u);
+    // ---- the last workgroup: bucket starts from the counts (then cleared) ----
+    // Every bucket atomic of a workgroup has returned (its base was stored in LDS)
+    // before the barrier that precedes its ticket, so the workgroup that draws the
+    // last ticket finds all of them done; it takes the counts by atomic exchanges.
+    // (No fence: a device-scope release would write back the whole L2.)
+    __syncthreads();
+    if (threadIdx.x == 0)
+        s_last = __hip_atomic_fetch_add(&a.ctl->bk_ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+                 (unsigned)G - 1u;
+    __syncthreads();
+    if (!s_last) return;
+    for (int t = threadIdx.x; t < a.nbk; t += kBkBlock)  // read and cleared where the atomics were done
+        s_h[t] = atomicExch(&a.bk_count[t], 0u);
+    __syncthreads();
+    const uint32_t total = lds_exclusive_scan<kBkBlock>(s_h, a.nbk, s_w);
+    for (int t = threadIdx.x; t < a.nbk; t += kBkBlock) a.bk_start[t] = s_h[t];
+    if (threadIdx.x == 0) {
+        a.bk_start[a.nbk] = total;
+        a.ctl->bk_ticket = 0u;
+    }
+}
+
+// (key, particle) of every particle the count pass saw into bucket order.
+__device__ __forceinline__ void bk_scatter_body(const BkArgs &a, const int lb, const int G) {
+    if (lb == 0 && threadIdx.x == 0) {  // the count pass is complete: keep its verdict for the update
+        a.ctl->nonfinite_seen = a.ctl->nonfinite_build;
+        a.ctl->nonfinite_build = 0u;
+    }
+    const int64_t nb_ = a.ctl->n_built;
+    const int64_t N = nb_ < 0 ? 0 : (nb_ > a.capacity ? a.capacity : nb_);
+    constexpr int kB = 4;
+    const int64_t quant = (int64_t)kBkBlock * kB;
+    const int64_t per = ((N + G - 1) / G + quant - 1) / quant * quant;
+    const int64_t s0 = (int64_t)lb * per, s1 = min(N, s0 + per);
+    for (int64_t base = s0 + threadIdx.x; base < s1; base += quant) {
+        uint2 e[kB];
+#pragma unroll
+        for (int q = 0; q < kB; ++q) {
+            const int64_t i = base + (int64_t)q * kBkBlock;
+            e[q] = i < s1 ? a.ent[i] : make_uint2(0u, 0u);
+        }
+        uint32_t st[kB];
+#pragma unroll
+        for (int q = 0; q < kB; ++q) st[q] = base + (int64_t)q * kBkBlock < s1 ? a.bk_start[e[q].x >> a.bshift] : 0u;
+#pragma unroll
+        for (int q = 0; q < kB; ++q) {
+            const int64_t i = base + (int64_t)q * kBkBlock;
+            if (i < s1) a.tmp[st[q] + e[q].y] = make_uint2(e[q].x, (uint32_t)i);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBkBlock) void k_bk_scatter(BkArgs a) { bk_scatter_body(a, logical_block(), gridDim.x); }
+
+// The merged step's update, first launch: the candidates' classification (the
+// first ncls workgroups) beside the bucket scatter (the others).
+__global__ __launch_bounds__(kBkBlock) void k_bk_scatter_cls(BkArgs a, FullArgs f, int ncls) {
+    static_assert(kBkBlock == kClassifyBlock, "one launch");
+    if ((int)blockIdx.x < ncls)
+        classify_cand_body(f, (int)blockIdx.x, ncls);
+    else
+        bk_scatter_body(a, (int)blockIdx.x - ncls, (int)gridDim.x - ncls);
+}
+
+constexpr int kSortBlock = 512;
+
+__global__ __launch_bounds__(kSortBlock) void k_bk_sort(BkArgs a) {
+    __shared__ uint32_t s_c[kMaxBucketCells];
+    __shared__ uint32_t s_w[kSortBlock / kWave];
+    const int b = (int)blockIdx.x;
+    if (b >= a.nbk) return;
+    const uint32_t n0 = a.bk_start[b], n1 = a.bk_start[b + 1];
+    const int64_t c0 = (int64_t)b << a.bshift;
+    const int nc = (int)min<int64_t>((int64_t)1 << a.bshift, a.n_cells - c0);
+    const int lane = (int)threadIdx.x & (kWave - 1);
+    for (int t = threadIdx.x; t < nc; t += kSortBlock) s_c[t] = 0u;
+    __syncthreads();
+    constexpr int kB = 4;  // entries per thread with their loads in flight together
+    constexpr uint32_t kStep = (uint32_t)kSortBlock * kB;
+    for (uint32_t e0 = n0; e0 < n1; e0 += kStep) {  // block-uniform trip count
+        uint32_t lk[kB];
+#pragma unroll
+        for (int q = 0; q < kB; ++q) {
+            const uint32_t e = e0 + (uint32_t)q * kSortBlock + threadIdx.x;
+            lk[q] = e < n1 ? a.tmp[e].x - (uint32_t)c0 : 0u;
+        }
+#pragma unroll
+        for (int q = 0; q < kB; ++q) {
+            const bool ok = e0 + (uint32_t)q * kSortBlock + threadIdx.x < n1;
+            int head, len;
+            lane_runs(lk[q], ok, lane, head, len);
+            if (len > 0 && lane == head) atomicAdd(&s_c[lk[q]], (uint32_t)len);
+        }
+    }
+    __syncthreads();
+    lds_exclusive_scan<kSortBlock>(s_c, nc, s_w);
+    for (int t = threadIdx.x; t < nc; t += kSortBlock) a.cell_start[c0 + t] = (int32_t)(n0 + s_c[t]);
+    if (b == a.nbk - 1 && threadIdx.x == 0) a.cell_start[a.n_cells] = (int32_t)n1;
+    for (uint32_t e0 = n0; e0 < n1; e0 += kStep) {
+        uint2 u[kB];
+#pragma unroll
+        for (int q = 0; q < kB; ++q) {
+            const uint32_t e = e0 + (uint32_t)q * kSortBlock + threadIdx.x;
+            u[q] = e < n1 ? a.tmp[e] : make_uint2((uint32_t)c0, 0u);
+        }
+#pragma unroll
+        for (int q = 0; q < kB; ++q) {
+            const bool ok = e0 + (uint32_t)q * kSortBlock + threadIdx.x < n1;
+            const uint32_t lk = u[q].x - (uint32_t)c0;
+            int head, len;
+            lane_runs(lk, ok, lane, head, len);
+            uint32_t old = 0u;
+            if (len > 0 && lane == head) old = atomicAdd(&s_c[lk], (uint32_t)len);
+            const uint32_t pos = __shfl(old, head) + (uint32_t)(lane - head);
+            if (ok) a.cell_idx[n0 + pos] = (int32_t)u[q].y;
+        }
+    }
+}
+
 
 // ------------------------------------------------------------- K2 finalize --
 //
@@ -1318,8 +1537,7 @@ __device__ __forceinline__ void share_of(unsigned n, int q, int nparts, unsigned
 constexpr uint32_t kMapRelShift = 20;  // tail map: bits 0..19 recycle slot + 1, bits 20.. new label + 1
 static_assert(kSeg * kMaxEv < (1u << kMapRelShift), "recycle slot fits the tail map");
 
-// LDS of one finalize workgroup (declared by the kernel, so that a launch that
-// also runs scan tiles can overlay both in one allocation).
+// LDS of one finalize workgroup.
 struct FinLds {
     uint32_t k[2][2][kMaxEv];          // [list: 0 sources, 1 deleted][0: flat, 1: sorted] keys
     uint32_t v[2][kMaxEv];             // event slot of each source, [0: flat, 1: sorted]
@@ -1687,30 +1905,6 @@ __device__ __forceinline__ void finalize_body(const FinArgs &a, const int fb, co
 __global__ __launch_bounds__(kFinBlock) void k_finalize(FinArgs a) {
     __shared__ FinLds L;
     finalize_body(a, blockIdx.x, gridDim.x, L);
-}
-
-// Update of the merged step: the finalize workgroups (the first nfin) and the scan
-// tiles of the cell list side by side in one launch.  They touch disjoint state
-// (event lists and particle arrays; cell counts, tile states and cell starts); the
-// scatter that follows places the particles the count pass saw (its own count of
-// them, not the updated one).
-struct ScanFinArgs {
-    ScanArgs s;
-    FinArgs f;
-    int nfin;
-};
-
-static_assert(kFinBlock == kScanBlock, "finalize and scan workgroups share one launch");
-
-__global__ __launch_bounds__(kFinBlock) void k_scan_finalize(ScanFinArgs a) {
-    __shared__ union {
-        FinLds f;
-        ScanLds s;
-    } L;
-    if ((int)blockIdx.x < a.nfin)
-        finalize_body(a.f, (int)blockIdx.x, a.nfin, L.f);
-    else
-        scan_body(a.s, L.s);
 }
 
 // ------------------------------------------------------------- identify --
@@ -2377,7 +2571,7 @@ __global__ __launch_bounds__(kBuildBlock) void kb_count(const CountArgs *args, c
                                                         const int32_t *vg) {
     const BlockMap m = map[logical_block()];
     if (m.d < 0) return;
-    count_body<false>(args[m.d], m.vb, vg[m.d]);
+    count_body(args[m.d], m.vb, vg[m.d]);
 }
 
 __global__ __launch_bounds__(kScanBlock) void kb_scan(const ScanArgs *args, const BlockMap *map) {
@@ -2454,14 +2648,22 @@ struct sph_ctx {
 
     int32_t *d_count = nullptr, *d_cell_start = nullptr, *d_cell_idx = nullptr;
     unsigned long long *d_cand = nullptr;        // candidate list of the full scan
-    // merged step (the default update path): the count pass also classifies the cover
-    // cells' particles and emits their events; the update runs the finalize beside
-    // the scan, then the scatter.  Off: the update walks the cover cells.
+    // merged step (the default update path): the count pass of the bucketed build also
+    // lists the cover cells' particles near a check region as candidates; the update
+    // classifies them beside the bucket scatter, then sorts the buckets and
+    // finalizes.  Off (or a grid too large for the bucketed build): the update walks
+    // the cover cells of the finished cell list.
     bool merged = true;
-    bool scan_pending = false;   // a merged build's scan and scatter are not enqueued yet
-    bool ev_pending = false;     // a merged build's events are not finalized yet
+    bool scan_pending = false;   // a merged build's bucket scatter and sort are not enqueued yet
+    bool ev_pending = false;     // a merged build's candidates are not classified and finalized yet
     bool nf_full_next = false;   // the next cover-walk finalize reads the count pass's non-finite flag
     uint16_t *d_cover = nullptr; // per cell: bit k set if the cell is in buffer k's cover
+    // bucketed build (grids of at most kMaxBuckets * kMaxBucketCells cells; the
+    // three-kernel counting sort otherwise)
+    bool bk = false;
+    int bshift = 0, nbk = 0;
+    uint32_t *d_bk_count = nullptr, *d_bk_start = nullptr;
+    uint2 *d_ent = nullptr, *d_tmp = nullptr;
     int64_t cover_cells = 0;
     uint32_t *d_keys = nullptr;                  // packed (key, rank) of each particle (three-kernel build)
     unsigned long long *d_keyrank = nullptr;     // full (key, rank) of the particles that do not fit
@@ -2594,6 +2796,22 @@ EventArgs events_of(const sph_ctx *ctx) {
     return e;
 }
 
+// Buckets of the bucketed build: the fewest cells per bucket (a power of two) that
+// keep the buckets within kMaxBuckets; grids beyond kMaxBuckets * kMaxBucketCells
+// cells take the three-kernel counting sort.
+void bk_layout(sph_ctx *c) {
+    c->bk = c->n_cells >= 1 && c->n_cells <= (int64_t)kMaxBuckets * kMaxBucketCells;
+    c->bshift = 0;
+    while (((c->n_cells + (int64_t(1) << c->bshift) - 1) >> c->bshift) > kMaxBuckets) ++c->bshift;
+    c->nbk = (int)((c->n_cells + (int64_t(1) << c->bshift) - 1) >> c->bshift);
+}
+
+// Workgroups of k_bk_count for a particle array of this capacity (a multiple of 8).
+int bk_blocks(int64_t capacity) {
+    const int64_t want = (capacity + kBkPer - 1) / kBkPer;
+    return (int)std::max<int64_t>(8, (want + 7) / 8 * 8);
+}
+
 // Count workgroups for a particle array of this capacity (a multiple of 8, so the
 // XCD renumbering applies).
 int count_blocks(int64_t capacity) {
@@ -2685,24 +2903,80 @@ sph_status launch_finalize(sph_ctx *ctx, const Parts &pp, bool local, int n_part
     return SPH_OK;
 }
 
-// Merged step: enqueue the scan and the scatter a merged build left for its update
-// (every call that reads the cell list needs them first).
-sph_status merged_cells(sph_ctx *c) {
-    if (!c->scan_pending) return SPH_OK;
-    c->scan_pending = false;
-    const ScanArgs sa = scan_args(c);
-    {
-        ProfScope ps(c, SPH_PHASE_SCAN);
-        hipLaunchKernelGGL(k_scan, dim3((unsigned)c->n_tiles), dim3(kScanBlock), 0, c->stream, sa);
+// Arguments of the bucketed build; the count pass reads the particles of pp
+// (cand: with the merged step's candidate list), the scatter and the sort only
+// the context's arrays.
+BkArgs bk_args(const sph_ctx *ctx, const Parts *pp, bool cand) {
+    BkArgs a{};
+    if (pp) {
+        a.x = pp->pos[0];
+        a.y = pp->pos[1];
+        a.z = pp->pos[2];
+        a.n_dev = pp->n_dev;
     }
-    HIP_TRY(hipGetLastError());
-    const ScatterArgs xa = scatter_args(c, c->built_capacity);
+    a.capacity = ctx->built_capacity;
+    a.g = grid_of(ctx);
+    a.bshift = ctx->bshift;
+    a.nbk = ctx->nbk;
+    a.n_cells = ctx->n_cells;
+    a.bk_count = ctx->d_bk_count;
+    a.bk_start = ctx->d_bk_start;
+    a.ent = ctx->d_ent;
+    a.tmp = ctx->d_tmp;
+    a.cell_start = ctx->d_cell_start;
+    a.cell_idx = ctx->d_cell_idx;
+    a.ctl = ctx->d_ctl;
+    a.nonfinite = cand ? &ctx->d_ctl->nonfinite_full : &ctx->d_ctl->nonfinite_build;
+    if (cand) {
+        a.cover = ctx->d_cover;
+        a.bufs = ctx->d_bufs;
+        a.nb = ctx->nb;
+        a.cand = ctx->d_cand;
+        a.cap_cand = ctx->capacity + kCandSlack;
+    }
+    return a;
+}
+
+// The candidate list's exact tests (full scan, merged step).
+FullArgs cand_args(const sph_ctx *ctx, const Parts &pp) {
+    FullArgs fa{};
+    fa.p = pp;
+    fa.bufs = ctx->d_bufs;
+    fa.nb = ctx->nb;
+    fa.e = events_of(ctx);
+    fa.vec = aligned16(pp.pos[0]) && aligned16(pp.pos[1]) && aligned16(pp.pos[2]) ? 1 : 0;
+    fa.cand = ctx->d_cand;
+    fa.cap_cand = ctx->capacity + kCandSlack;
+    return fa;
+}
+
+// Bucketed build after its count pass: the bucket scatter, then the bucket sort
+// (fa: the merged step's candidates are classified beside the scatter).
+sph_status bk_cells(sph_ctx *c, const FullArgs *fa) {
+    const BkArgs ba = bk_args(c, nullptr, false);
     {
         ProfScope ps(c, SPH_PHASE_SCATTER);
-        hipLaunchKernelGGL(k_scatter, dim3(c->build_blocks), dim3(kBuildBlock), 0, c->stream, xa);
+        if (fa)
+            hipLaunchKernelGGL(k_bk_scatter_cls, dim3(kCandBlocksMerged + c->build_blocks), dim3(kBkBlock), 0,
+                               c->stream, ba, *fa, kCandBlocksMerged);
+        else
+            hipLaunchKernelGGL(k_bk_scatter, dim3(c->build_blocks), dim3(kBkBlock), 0, c->stream, ba);
+    }
+    HIP_TRY(hipGetLastError());
+    {
+        ProfScope ps(c, SPH_PHASE_SORT);
+        hipLaunchKernelGGL(k_bk_sort, dim3(c->nbk), dim3(kSortBlock), 0, c->stream, ba);
     }
     HIP_TRY(hipGetLastError());
     return SPH_OK;
+}
+
+// Merged step: enqueue the bucket scatter and sort a merged build left for its
+// update (every call that reads the cell list needs them first).
+sph_status merged_cells(sph_ctx *c) {
+    if (!c->scan_pending) return SPH_OK;
+    c->scan_pending = false;
+    return bk_cells(c, nullptr);
 }
 
 // Merged step: drop the events of a merged build once a call changes what they were
@@ -2745,6 +3019,10 @@ void free_ctx(sph_ctx *c) {
     (void)hipFree(c->d_keys);
     (void)hipFree(c->d_cand);
     (void)hipFree(c->d_cover);
+    (void)hipFree(c->d_bk_count);
+    (void)hipFree(c->d_bk_start);
+    (void)hipFree(c->d_ent);
+    (void)hipFree(c->d_tmp);
     (void)hipFree(c->d_tile_state);
     (void)hipFree(c->d_gen_idx);
     (void)hipFree(c->d_del_idx);
@@ -3048,6 +3326,7 @@ extern "C" sph_status sph_create(const sph_config *cfg, sph_ctx **out) {
     c->cs = cfg->cell_size;
     c->dp = cfg->dp;
     c->n_cells = (int64_t)cells;
+    bk_layout(c);
     c->rbits = rank_bits(c->n_cells);
     c->blog2 = blog2;
     c->bmargin = cfg->brick_margin;
@@ -3088,6 +3367,10 @@ extern "C" sph_status sph_create(const sph_config *cfg, sph_ctx **out) {
               (blog2 == 0 || hipMalloc(&c->d_brick_slot, sizeof(int32_t) * c->n_bricks) == hipSuccess) &&
               hipMalloc(&c->d_part, sizeof(unsigned) * 2 * SPH_MAX_BUFFERS * kMaxPartBlocks) == hipSuccess &&
               hipMalloc(&c->d_result, sizeof(sph_result)) == hipSuccess &&
+              hipMalloc(&c->d_bk_count, sizeof(uint32_t) * kMaxBuckets) == hipSuccess &&
+              hipMalloc(&c->d_bk_start, sizeof(uint32_t) * (kMaxBuckets + 1)) == hipSuccess &&
+              hipMalloc(&c->d_ent, sizeof(uint2) * c->capacity) == hipSuccess &&
+              hipMalloc(&c->d_tmp, sizeof(uint2) * c->capacity) == hipSuccess &&
               hipMalloc(&c->d_bcfound, sizeof(unsigned) * kCountReplicas * SPH_MAX_BUFFERS) == hipSuccess &&
               hipHostMalloc(&c->h_bc_status, sizeof(unsigned), hipHostMallocDefault) == hipSuccess &&
               hipHostMalloc(&c->h_result, sizeof(sph_result), hipHostMallocDefault) == hipSuccess;
@@ -3103,6 +3386,7 @@ extern "C" sph_status sph_create(const sph_config *cfg, sph_ctx **out) {
              hipMemcpyAsync(c->d_ctl, &init, sizeof(Ctl), hipMemcpyHostToDevice, c->stream) == hipSuccess &&
              hipMemsetAsync(c->d_bcfound, 0, sizeof(unsigned) * kCountReplicas * SPH_MAX_BUFFERS, c->stream) ==
                  hipSuccess &&
+             hipMemsetAsync(c->d_bk_count, 0, sizeof(uint32_t) * kMaxBuckets, c->stream) == hipSuccess &&
              (blog2 == 0 || hipMemsetAsync(c->d_brick_slot, 0xff, sizeof(int32_t) * c->n_bricks, c->stream) ==
                                 hipSuccess) &&
              hipMemcpyAsync(c->d_result, &r0, sizeof(r0), hipMemcpyHostToDevice, c->stream) == hipSuccess &&
@@ -3187,29 +3471,25 @@ extern "C" sph_status sph_celllist_build(sph_ctx *ctx, const sph_particles *p) {
     if (st != SPH_OK) return st;
     HIP_CHECKED(merged_drop(ctx, true));
     ctx->built_capacity = pp.capacity;
-    // merged step: a workgroup's list holds at most kClsList particles (capacities
-    // beyond 2^25 particles, and domains without buffers, take the plain build)
-    if (ctx->merged && ctx->d_cover && ctx->nb > 0 &&
-        (int64_t)count_blocks(pp.capacity) * kClsList >= pp.capacity) {
-        // count + classification of the cover cells' particles here; the scan and the
-        // scatter are left for the update (or the next call that needs the cell list)
-        ClsArgs ca{};
-        static_cast<CountArgs &>(ca) = count_args(ctx, pp);
-        ca.nonfinite = &ctx->d_ctl->nonfinite_full;
-        ca.cover = ctx->d_cover;
-        ca.nb = ctx->nb;
-        ca.p = pp;
-        ca.bufs = ctx->d_bufs;
-        ca.e = events_of(ctx);
+    if (ctx->bk) {
+        // merged step (domains with buffers): the count pass also lists the
+        // candidates; the bucket scatter and sort are left for the update (or the
+        // next call that needs the cell list)
+        const bool cand = ctx->merged && ctx->d_cover && ctx->nb > 0;
+        const BkArgs ba = bk_args(ctx, &pp, cand);
         {
             ProfScope ps(ctx, SPH_PHASE_COUNT);
-            hipLaunchKernelGGL(k_count_cls, dim3(count_blocks(pp.capacity)), dim3(kBuildBlock), 0, ctx->stream, ca);
+            if (cand)
+                hipLaunchKernelGGL(k_bk_count<true>, dim3(bk_blocks(pp.capacity)), dim3(kBkBlock), 0, ctx->stream, ba);
+            else
+                hipLaunchKernelGGL(k_bk_count<false>, dim3(bk_blocks(pp.capacity)), dim3(kBkBlock), 0, ctx->stream, ba);
         }
         HIP_TRY(hipGetLastError());
+        ctx->built = true;
+        if (!cand) return bk_cells(ctx, nullptr);
         ctx->scan_pending = true;
         ctx->ev_pending = true;
         ctx->nf_full_next = true;
-        ctx->built = true;
         return SPH_OK;
     }
     const CountArgs ca = count_args(ctx, pp);
@@ -3375,39 +3655,23 @@ extern "C" sph_status sph_buffer_update_async(sph_ctx *ctx, sph_particles *p) {
     if (st != SPH_OK) return st;
     if (ctx->fields.rho >= pp.nc) return SPH_ERR_ARG;
     if (ctx->merged && ctx->ev_pending) {
-        // the events are already emitted: the finalize runs beside the scan tiles,
-        // then the scatter (or the finalize alone if a call needed the cell list first)
-        FinArgs f = fin_args(ctx, pp, false);
+        // the count pass listed the candidates: their exact tests run beside the
+        // bucket scatter, then the bucket sort and the finalize (or the tests alone
+        // if a call needed the cell list first)
+        const FullArgs fa = cand_args(ctx, pp);
         if (ctx->scan_pending) {
-            ScanFinArgs sf{};
-            sf.s = scan_args(ctx);
-            sf.f = f;
-            sf.nfin = kFinBlocksMax;
-            {
-                ProfScope ps(ctx, SPH_PHASE_FINALIZE);
-                hipLaunchKernelGGL(k_scan_finalize, dim3((unsigned)(kFinBlocksMax + ctx->n_tiles)), dim3(kFinBlock), 0,
-                                   ctx->stream, sf);
-            }
-            HIP_TRY(hipGetLastError());
-            const ScatterArgs xa = scatter_args(ctx, ctx->built_capacity);
-            {
-                ProfScope ps(ctx, SPH_PHASE_SCATTER);
-                hipLaunchKernelGGL(k_scatter, dim3(ctx->build_blocks), dim3(kBuildBlock), 0, ctx->stream, xa);
-            }
-            HIP_TRY(hipGetLastError());
             ctx->scan_pending = false;
+            HIP_CHECKED(bk_cells(ctx, &fa));
         } else {
             {
-                ProfScope ps(ctx, SPH_PHASE_FINALIZE);
-                hipLaunchKernelGGL(k_finalize, dim3(kFinBlocksMax), dim3(kFinBlock), 0, ctx->stream, f);
+                ProfScope ps(ctx, SPH_PHASE_CANDIDATES);
+                hipLaunchKernelGGL(k_classify_cand, dim3(kCandBlocksMerged), dim3(kClassifyBlock), 0, ctx->stream, fa);
             }
             HIP_TRY(hipGetLastError());
         }
         ctx->ev_pending = false;
-        ctx->nf_full_next = false;
         ctx->built = false;
-        ctx->any_update = true;
-        return SPH_OK;
+        return launch_finalize(ctx, pp, false, kCandBlocksMerged);
     }
     HIP_CHECKED(merged_cells(ctx));  // a merged build whose events were dropped: walk the cover cells
     int n_part = 0;
@@ -3429,14 +3693,7 @@ static sph_status fullscan_enqueue(sph_ctx *ctx, sph_particles *p) {
     const sph_status st = parts_of(ctx, p, pp);
     if (st != SPH_OK) return st;
     if (ctx->fields.rho >= pp.nc) return SPH_ERR_ARG;
-    FullArgs fa{};
-    fa.p = pp;
-    fa.bufs = ctx->d_bufs;
-    fa.nb = ctx->nb;
-    fa.e = events_of(ctx);
-    fa.vec = aligned16(pp.pos[0]) && aligned16(pp.pos[1]) && aligned16(pp.pos[2]) ? 1 : 0;
-    fa.cand = ctx->d_cand;
-    fa.cap_cand = ctx->capacity + kCandSlack;
+    const FullArgs fa = cand_args(ctx, pp);
     {
         ProfScope ps(ctx, SPH_PHASE_FULLSCAN);
         hipLaunchKernelGGL(k_filter_full, dim3(ctx->full_blocks), dim3(kClassifyBlock), 0, ctx->stream, fa);
@@ -3942,6 +4199,7 @@ extern "C" sph_status sph_grid_fit(sph_ctx *ctx, const sph_particles *p) {
     ctx->d_cell_start = start;
     ctx->d_tile_state = ts;
     ctx->n_cells = cells;
+    bk_layout(ctx);
     ctx->rbits = rank_bits(cells);
     ctx->n_tiles = tiles;
     ctx->built = false;

@@ -53,9 +53,9 @@ SPH_NOALLOC_MAX_PARTICLES = 1 << 20
 SPH_NOALLOC_MAX_CELLS = 1 << 20
 BATCH_PHASES = ("count", "scan", "scatter", "classify", "finalize")
 SPH_BATCH_KERNELS, SPH_BATCH_GRAPH = 0, 1
-SPH_NPHASE = 11
+SPH_NPHASE = 12
 PHASES = ("count", "scan", "scatter", "classify", "fullscan", "finalize", "bc", "rotate", "candidates", "neighbor",
-          "cover")
+          "cover", "sort")
 SPH_BC_NONE, SPH_BC_VELOCITY, SPH_BC_PRESSURE = 0, 1, 2
 SPH_PROFILE_PLUG, SPH_PROFILE_PARABOLIC_Y, SPH_PROFILE_PARABOLIC_R = 0, 1, 2
 
@@ -266,6 +266,10 @@ def sph_create(dim: int, lo, hi, cell_size: float, dp: float, capacity: int, max
 
 
 def sph_destroy(ctx: int) -> int:
+    """Destroys a context made by sph_create; a handle that is not alive (already
+    destroyed, e.g. by the exit hook) is refused with SPH_ERR_ARG, never freed twice."""
+    if ctx not in _live_ctx:
+        return SPH_ERR_ARG
     _live_ctx.discard(ctx)
     return lib().sph_destroy(ctx)
 
@@ -484,6 +488,9 @@ def sph_batch_create(ctxs, parts, stream: int = 0):
 
 
 def sph_batch_destroy(b: int) -> int:
+    """As sph_destroy, for batches."""
+    if b not in _live_batch:
+        return SPH_ERR_ARG
     _live_batch.discard(b)
     return lib().sph_batch_destroy(b)
 

@@ -167,3 +167,32 @@ def test_exit_with_live_contexts_and_batch():
     r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, (r.returncode, r.stdout[-2000:], r.stderr[-2000:])
     assert "stepped" in r.stdout
+
+
+def test_exit_after_an_error_with_live_handles():
+    """A program that raises with a domain and a batch alive: the exit hook destroys
+    them, and the domain's own close() when it is collected afterwards does nothing
+    (no second free): the process ends with the error's status 1, not a crash."""
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "import torch, workloads as W\n"
+        "from paper_2406_16786_amd import sphbuf as S\n"
+        "from paper_2406_16786_amd.domain import Domain\n"
+        "def run():\n"
+        "    wl = W.channel2d()\n"
+        "    d = Domain(wl.dim, wl.lo, wl.hi, wl.cell_size, wl.dp, wl.capacity, wl.pos, wl.carried, wl.label,\n"
+        "               wl.id, wl.n, wl.n)\n"
+        "    for b in wl.buffers:\n"
+        "        d.define(b.kind, b.origin, S.sph_rotation_2d(b.angle)[1], b.half, b.margin)\n"
+        "    d.identify(-1); d.build(); d.update_async()\n"
+        "    stream = torch.cuda.Stream()\n"
+        "    torch.cuda.synchronize()\n"
+        "    st, b = S.sph_batch_create([d.ctx], [d.p], stream.cuda_stream)\n"
+        "    assert st == 0 and S.sph_batch_step(b) == 0\n"
+        "    print('stepped', flush=True)\n"
+        "    raise RuntimeError('planned')\n"
+        "run()\n" % ROOT)
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 1, (r.returncode, r.stdout[-2000:], r.stderr[-2000:])
+    assert "stepped" in r.stdout and "planned" in r.stderr
+    assert "double free" not in r.stderr and "corruption" not in r.stderr
