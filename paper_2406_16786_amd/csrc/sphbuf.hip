@@ -1168,20 +1168,30 @@ __device__ __forceinline__ uint32_t lds_exclusive_scan(uint32_t *v, int n, uint3
     return total;
 }
 
+constexpr int kCandLds = 2048;  // candidates a count workgroup gathers in LDS (more go out one by one)
+
 template <bool kCand>
 __global__ __launch_bounds__(kBkBlock) void k_bk_count(BkArgs a) {
     __shared__ uint32_t s_h[kMaxBuckets];  // counts, then bases, then cursors per bucket
     __shared__ BufDev sb[kCand ? SPH_MAX_BUFFERS : 1];
+    __shared__ uint16_t s_cand[kCand ? kCandLds : 1];  // (particle offset in the workgroup << 4) | buffer
+    __shared__ unsigned s_ncand;
+    __shared__ unsigned long long s_cbase;
     __shared__ uint32_t s_w[kBkBlock / kWave];
     __shared__ unsigned s_last;
     const int64_t N = live_count(a.n_dev, a.capacity);
     const int lb = logical_block(), G = (int)gridDim.x;
     const int lane = (int)threadIdx.x & (kWave - 1);
-    if (lb == 0 && threadIdx.x == 0) a.ctl->n_built = N;
+    if (lb == 0 && threadIdx.x == 0) {
+        a.ctl->n_built = N;
+        a.ctl->scan_fault = 0u;  // (raised only by the look-back scan of the three-kernel build)
+    }
     for (int t = threadIdx.x; t < a.nbk; t += kBkBlock) s_h[t] = 0u;
-    if constexpr (kCand)
+    if constexpr (kCand) {
         for (int t = threadIdx.x; t < a.nb * (int)(sizeof(BufDev) / 4); t += kBkBlock)
             reinterpret_cast<uint32_t *>(sb)[t] = reinterpret_cast<const uint32_t *>(a.bufs)[t];
+        if (threadIdx.x == 0) s_ncand = 0u;
+    }
     __syncthreads();
     const int64_t s0 = (int64_t)lb * kBkPer;
     const bool d3 = a.g.dim == 3;
@@ -1250,17 +1260,24 @@ __global__ __launch_bounds__(kBkBlock) void k_bk_count(BkArgs a) {
                         const unsigned t = __shfl_up(incl, off);
                         if (lane >= off) incl += t;
                     }
+                    // gathered in LDS (one LDS atomic per wave), listed once per workgroup
                     const unsigned tot = __shfl(incl, kWave - 1);
-                    unsigned long long at = 0ull;
-                    if (lane == 0 && tot) at = atomicAdd(&a.ctl->cand_count, (unsigned long long)tot);
+                    unsigned at = 0u;
+                    if (lane == 0 && tot) at = atomicAdd(&s_ncand, tot);
                     at = __shfl(at, 0) + (incl - mine);
+                    const uint32_t local = (uint32_t)((it + q) * kBkBlock) + threadIdx.x;
                     while (cb) {
                         const int k = __ffs(cb) - 1;
                         cb &= cb - 1u;
-                        if (at < (unsigned long long)a.cap_cand)
-                            a.cand[at] = ((unsigned long long)i << 4) | (unsigned long long)k;
-                        else
-                            a.ctl->cand_overflow = 1u;
+                        if (at < (unsigned)kCandLds) {
+                            s_cand[at] = (uint16_t)((local << 4) | (uint32_t)k);
+                        } else {  // a workgroup full of candidates: the rest one by one
+                            const unsigned long long g = atomicAdd(&a.ctl->cand_count, 1ull);
+                            if (g < (unsigned long long)a.cap_cand)
+                                a.cand[g] = ((unsigned long long)i << 4) | (unsigned long long)k;
+                            else
+                                a.ctl->cand_overflow = 1u;
+                        }
                         ++at;
                     }
                 }
@@ -1268,6 +1285,19 @@ __global__ __launch_bounds__(kBkBlock) void k_bk_count(BkArgs a) {
         }
     }
     __syncthreads();
+    if constexpr (kCand) {  // the workgroup's candidates into the list
+        const unsigned nc = min(s_ncand, (unsigned)kCandLds);
+        if (threadIdx.x == 0) s_cbase = nc ? atomicAdd(&a.ctl->cand_count, (unsigned long long)nc) : 0ull;
+        __syncthreads();
+        for (unsigned e = threadIdx.x; e < nc; e += kBkBlock) {
+            const unsigned long long g = s_cbase + e;
+            const uint32_t v = s_cand[e];
+            if (g < (unsigned long long)a.cap_cand)
+                a.cand[g] = ((unsigned long long)(s0 + (v >> 4)) << 4) | (unsigned long long)(v & 15u);
+            else
+                a.ctl->cand_overflow = 1u;
+        }
+    }
     // ---- the workgroup's base in each bucket it meets: one global atomic each ----
     for (int t = threadIdx.x; t < a.nbk; t += kBkBlock) {
         const uint32_t c = s_h[t];
@@ -1366,7 +1396,7 @@ __global__ __launch_bounds__(kSortBlock) void k_bk_sort(BkArgs a) {
     const int lane = (int)threadIdx.x & (kWave - 1);
     for (int t = threadIdx.x; t < nc; t += kSortBlock) s_c[t] = 0u;
     __syncthreads();
-    constexpr int kB = 4;  // entries per thread with their loads in flight together
+    constexpr int kB = 8;  // entries per thread with their loads in flight together
     constexpr uint32_t kStep = (uint32_t)kSortBlock * kB;
     for (uint32_t e0 = n0; e0 < n1; e0 += kStep) {  // block-uniform trip count
         uint32_t lk[kB];
@@ -1387,6 +1417,7 @@ __global__ __launch_bounds__(kSortBlock) void k_bk_sort(BkArgs a) {
     lds_exclusive_scan<kSortBlock>(s_c, nc, s_w);
     for (int t = threadIdx.x; t < nc; t += kSortBlock) a.cell_start[c0 + t] = (int32_t)(n0 + s_c[t]);
     if (b == a.nbk - 1 && threadIdx.x == 0) a.cell_start[a.n_cells] = (int32_t)n1;
+    __syncthreads();  // every offset read before the cursors move
     for (uint32_t e0 = n0; e0 < n1; e0 += kStep) {
         uint2 u[kB];
 #pragma unroll

@@ -125,6 +125,56 @@ def test_celllist_random_9_5m():
     d.close()
 
 
+def test_celllist_buckets_of_4096_cells():
+    """A 2-D grid of 16.4 M cells takes buckets of 4096 cells (the largest): each
+    bucket's counting sort walks its cells in several rounds of its workgroup.
+    3 M random particles against the oracle's cell list."""
+    n = 3_000_000
+    rng = np.random.default_rng(23)
+    pts = rng.uniform((0.0, 0.0), (1.0, 4000.0 / 4096.0), (n, 2))
+    st = make_state(2, pts, capacity=n + 16)
+    cs_ = 1.0 / 4096.0
+    d = make_domain_raw(2, (0, 0, 0), (1.0, 4000.0 / 4096.0, 0.0), cs_, cs_, [], st)
+    d.build()
+    cs, ci, dims = _cell_list(d, n)
+    assert dims[0] * dims[1] > 4096 * 2048
+    ocs, oci = oracle.cell_list(2, np.float32([0, 0]), np.float32(1.0 / cs_), dims[:2], st.pos[0][:n], st.pos[1][:n])
+    np.testing.assert_array_equal(cs, ocs)
+    cell_of = np.repeat(np.arange(len(ocs) - 1), np.diff(ocs))
+    np.testing.assert_array_equal(ci[np.lexsort((ci, cell_of))], oci)
+    d.close()
+
+
+def test_celllist_full_size_network_repeatable():
+    """The branching network at full size (16.1 M particles, brick-sparse grid,
+    buckets of 1024 cells): three builds through a cover-walk context and one
+    through a merged one give the same cell starts and the same particles in every
+    cell (the order inside a cell is free)."""
+    import tests._gpu as G
+    wl = W.tree3d()
+    bufs = oracle_buffers(wl)
+    st = oracle_state(wl)
+    n = st.n
+    lists = []
+    for path, builds in (("cells", 3), ("merged", 1)):
+        old = G.UPDATE_PATH
+        G.UPDATE_PATH = path
+        try:
+            d = make_domain(wl, bufs, st, brick_log2=3)
+        finally:
+            G.UPDATE_PATH = old
+        for _ in range(builds):
+            d.build()
+            cs, ci, _ = _cell_list(d, n)
+            cell_of = np.repeat(np.arange(len(cs) - 1), np.diff(cs))
+            lists.append((cs, ci[np.lexsort((ci, cell_of))]))
+        d.close()
+    for cs, ci in lists[1:]:
+        np.testing.assert_array_equal(cs, lists[0][0])
+        np.testing.assert_array_equal(ci, lists[0][1])
+    assert lists[0][0][-1] == n
+
+
 def test_celllist_crowded_cell_on_a_fine_grid():
     """33 M cells leave 6 bits for the rank in the packed (key, rank) word, so
     500 particles in one cell take the full-width spill path of the build."""
