@@ -119,22 +119,60 @@ class Snapshot:
         return self.pos + self.carried + [self.label, self.id, self.n_dev]
 
 
-def phase_bytes(dim: int, n: int, n_cells: int, cand: int, g: int, d: int, n_carried: int):
+def phase_bytes(dim: int, n: int, n_cells: int, cand: int, g: int, d: int, n_carried: int,
+                method: str = "bucketed"):
     """Algorithmic bytes per launch of each kernel phase: its inputs and outputs in
-    HBM, the bucketed build's intermediates included ("build" is the least any
-    build must move: positions in, cell list out)."""
+    HBM, the build's intermediates included ("build" is the least any build must
+    move: positions in, cell list out).  The build's phases differ by method."""
     state = 4 * dim + 4 * n_carried + 4 + 8          # bytes of one particle's state
+    if method == "counting":
+        build = {
+            "count": (4 * dim + 4) * n + 4 * n_cells,   # read positions, write packed (key, rank); the counters
+            "scan": 8 * (n_cells + 1),                  # read counts, write cell starts
+            "scatter": 8 * n + 4 * (n_cells + 1),       # read packed words and cell starts, write cell_idx
+        }
+    else:
+        build = {
+            "count": (4 * dim + 8) * n,                 # read positions, write (key, rank in bucket)
+            "scatter": 16 * n,                          # read (key, rank), write (key, particle) in bucket order
+            "sort": 12 * n + 4 * (n_cells + 1),         # read (key, particle), write cell_idx and cell_start
+        }
     return {
         "build": (4 * dim + 4) * n + 4 * (n_cells + 1), # read positions, write cell_idx and cell_start
-        "count": (4 * dim + 8) * n,                     # read positions, write (key, rank in bucket)
-        "scatter": 16 * n,                              # read (key, rank), write (key, particle) in bucket order
-        "sort": 12 * n + 4 * (n_cells + 1),             # read (key, particle), write cell_idx and cell_start
         "scan": 8 * (n_cells + 1),                      # (batched build) read counts, write cell starts
+        **build,
         "classify": cand * (4 * dim + 8),               # candidate index, position, label
         "candidates": cand * (4 * dim + 8),
         "fullscan": 4 * dim * n,                        # read positions
         "finalize": (g + d) * 8 + g * (2 * state) + d * 2 * state,  # events, duplicates, refills
     }
+
+
+TUNE_BUILDS = 10
+# the merged step's kernels per phase, by build method
+KERNEL_OF = {
+    "bucketed": {"count": "k_bk_count<true>", "scatter": "k_bk_scatter_cls", "sort": "k_bk_sort",
+                 "finalize": "k_finalize"},
+    "counting": {"count": "k_count<true>", "scan": "k_scan", "scatter": "k_scatter_cls", "finalize": "k_finalize"},
+}
+PHASES_NOTE = {
+    "bucketed": "merged step, bucketed build: count = bucket counts and the candidate list, scatter = the bucket "
+                "scatter with the candidates' exact tests beside it, sort = the per-bucket counting sort, "
+                "finalize = the events applied",
+    "counting": "merged step, counting build: count = cell counts and the candidate list, scan = the look-back "
+                "scan of the counts, scatter = the cell-list scatter with the candidates' exact tests beside it, "
+                "finalize = the events applied",
+}
+
+
+def build_method(ctx):
+    """The automatic build method's choice for a context and the times it rests on."""
+    from paper_2406_16786_amd import sphbuf as S
+    st, m, us, ns = S.sph_build_stats(ctx)
+    S.check(st, "build_stats")
+    name = {S.SPH_BUILD_COUNTING: "counting", S.SPH_BUILD_BUCKETED: "bucketed"}.get(m, "none")
+    return {"chosen": name, "us_counting": round(us[0], 1), "us_bucketed": round(us[1], 1),
+            "timed_builds": {"counting": int(ns[0]), "bucketed": int(ns[1])}}
 
 
 def measured_traffic(workload: str, kernel: str):
@@ -248,6 +286,14 @@ def single_leg(torch, np, S, W, Domain, wl, K, Wm, late, early, args):
         def replay(mode, ctx, profile):
             reset(ctx)
             S.check(S.sph_profile_enable(ctx, False), "profile")
+            if mode == "local":
+                # the automatic build method times both builds on the warm-up states
+                # (synchronised builds, so every timing is read) and settles before
+                # the timed steps, where it re-checks its choice every 64 builds
+                S.check(S.sph_build_retune(ctx), "retune")
+                for r in range(TUNE_BUILDS):
+                    S.check(S.sph_celllist_build(ctx, parts[r % Wm]), "build")
+                    stream.synchronize()
             for s in range(Wm):
                 if mode == "local":
                     S.check(S.sph_celllist_build(ctx, parts[s]), "build")
@@ -297,6 +343,7 @@ def single_leg(torch, np, S, W, Domain, wl, K, Wm, late, early, args):
             torch.cuda.synchronize()
             REGIONS.end()
         out["ms_merged"], out["wall_merged"], _ = replay("local", dom.ctx, False)
+        out["method"] = build_method(dom.ctx)
         out["ms_full"], _, _ = replay("fullscan", dom.ctx, False)
         out["ms_cells"], _, _ = replay("local", ctx_cells, False)
         if not args.no_profile_pass:
@@ -321,8 +368,12 @@ def single_leg(torch, np, S, W, Domain, wl, K, Wm, late, early, args):
     s0 = snaps["late"][Wm]
     n0 = int(s0.n_dev.item())
     cand = cover_candidates(np, S, wl, rots, [t.cpu().numpy() for t in s0.pos], n0)
-    pb = phase_bytes(wl.dim, int(L["n_mean"]), n_cells, cand, int(L["g_mean"]), int(L["d_mean"]), len(wl.carried))
-    kernel_of = {"count": "k_bk_count", "scatter": "k_bk_scatter_cls", "sort": "k_bk_sort", "finalize": "k_finalize"}
+    pm = L.get("prof_merged")
+    # the method of the profiled replay (its timed steps run one method: no re-check falls there)
+    meth = ("counting" if "scan" in pm else "bucketed") if pm else L["method"]["chosen"]
+    pb = phase_bytes(wl.dim, int(L["n_mean"]), n_cells, cand, int(L["g_mean"]), int(L["d_mean"]), len(wl.carried),
+                     meth)
+    kernel_of = KERNEL_OF[meth]
     step_bytes = pb["build"] + pb["classify"] + pb["finalize"]
     ms = L["ms_merged"]
     n_mean = L["n_mean"]
@@ -345,9 +396,8 @@ def single_leg(torch, np, S, W, Domain, wl, K, Wm, late, early, args):
                            "traffic": measured_traffic(wl.name, kname), "avg_launch_us": round(avg_ms * 1e3, 2),
                            "algorithmic_bytes_per_launch": int(pb[dom_phase])}
         out["phases_us"] = {k: round(v * 1e3, 2) for k, v in pm.items()}
-        out["phases_note"] = ("merged step: count = bucket counts and the candidate list, scatter = the bucket "
-                              "scatter with the candidates' exact tests beside it, sort = the per-bucket counting "
-                              "sort, finalize = the events applied")
+        out["phases_note"] = PHASES_NOTE[meth]
+    out["build_method"] = L["method"]
     if pc:
         t_upd = pc.get("classify", 0.0) + pc.get("finalize", 0.0)
         t_full = pf["fullscan"] + pf.get("candidates", 0.0) + pf["finalize"] if pf else None
@@ -370,6 +420,7 @@ def single_leg(torch, np, S, W, Domain, wl, K, Wm, late, early, args):
                                "phases_us": {k: round(v * 1e3, 2) for k, v in E["prof_merged"].items()}
                                if E.get("prof_merged") else None,
                                "cover_cell_walk_ms": round(E["ms_cells"], 5),
+                               "build_method": E["method"],
                                "fullscan_ms": round(E["ms_full"], 5)}
         out["drift_late_over_early"] = round(ms / E["ms_merged"], 3)
     log(f"{wl.name}: late step {ms * 1e3:.1f} us" + (f" (early {E['ms_merged'] * 1e3:.1f})" if E else "")

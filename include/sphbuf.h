@@ -86,13 +86,25 @@ typedef enum { SPH_INLET = 1, SPH_OUTLET = 2, SPH_BIDIR = 3 } sph_kind;
 #define SPH_MAX_EVENTS_LIMIT 4096
 
 /* How an update finds its candidates.  Both give the same events and arrays.
- *   SPH_UPDATE_MERGED (default): the count pass of sph_celllist_build classifies
- *     the particles of every buffer's cover cells as it bins them and emits their
- *     events; the update then runs the finalize beside the scan of the cell
- *     counts and the scatter of the cell list.
- *   SPH_UPDATE_CELLS: the build only builds the cell list; the update walks the
+ *   SPH_UPDATE_MERGED (default): the count pass of sph_celllist_build lists the
+ *     particles of every buffer's cover cells that lie near its check region (an
+ *     FP32 test widened by the guard band) as it bins them; the update runs their
+ *     exact tests beside the build's scatter, then the finalize.
+ *   SPH_UPDATE_CELLS: the build builds the whole cell list; the update walks the
  *     cover cells of the finished list (one wave per run of cells). */
 typedef enum { SPH_UPDATE_MERGED = 0, SPH_UPDATE_CELLS = 1 } sph_update_path;
+
+/* How sph_celllist_build sorts the particles into cells (section 2.3's cell
+ * list).  Every method gives each cell the same set of particles; the order
+ * inside a cell is unspecified.
+ *   SPH_BUILD_AUTO (default): times both methods on the context's stream (HIP
+ *     events, read once complete: the host never waits) and runs the faster, with
+ *     a re-check every 64 builds; grids of more than 2^24 cells use counting.
+ *   SPH_BUILD_COUNTING: count per cell (atomics), look-back scan, scatter.
+ *   SPH_BUILD_BUCKETED: count per bucket of consecutive cells, bucket scatter, a
+ *     counting sort of each bucket in LDS; grids of at most 2^24 cells (counting
+ *     beyond). */
+typedef enum { SPH_BUILD_AUTO = 0, SPH_BUILD_COUNTING = 1, SPH_BUILD_BUCKETED = 2 } sph_build_method;
 
 typedef struct sph_ctx sph_ctx;
 
@@ -121,7 +133,7 @@ typedef struct {
     int32_t brick_log2;     /* 0: dense grid; 1..5: brick-sparse grid of 2^b cells per axis   */
     int32_t brick_margin;   /* sparse grid: active bricks = occupied ones dilated by this     */
     int32_t update_path;    /* sph_update_path (0 = SPH_UPDATE_MERGED)                         */
-    int32_t pad2_;
+    int32_t build_method;   /* sph_build_method (0 = SPH_BUILD_AUTO)                           */
 } sph_config;
 
 /* Result of the last update (see sph_last_result). */
@@ -141,7 +153,7 @@ typedef struct {
 /* Create a context: validates cfg, allocates the cell grid and all scratch on the
  * current HIP device.  SPH_ERR_ARG for a bad config (dim, cell_size <= 0, empty or
  * non-finite bounds, more than 2^31 cells, capacity <= 0 or >= 2^31, max_events
- * outside 1..4096, an unknown update_path, or a grid on which FP32 binning can
+ * outside 1..4096, an unknown update_path or build_method, or a grid on which FP32 binning can
  * misplace a particle by a quarter cell or more: the cell coordinate
  * fl32(fl32(x - fl32(lo)) * fl32(1/cell_size)) is off by at most
  * |lo - fl32(lo)|/cell_size + 3.0001 2^-24 (cells per axis + 1 + that offset)
@@ -248,6 +260,19 @@ sph_status sph_last_events(sph_ctx *ctx, int64_t *gen_src, int64_t *del_idx, int
  * has n_cells + 1 entries, cell_idx has N entries (pre-update indices). */
 sph_status sph_celllist_view(sph_ctx *ctx, const int32_t **cell_start, const int32_t **cell_idx,
                              int64_t *n_cells, int32_t dims[3]);
+
+/* The build method of the last build (SPH_BUILD_COUNTING or SPH_BUILD_BUCKETED;
+ * SPH_BUILD_AUTO before the first) and, for SPH_BUILD_AUTO, each method's smoothed
+ * build time in microseconds (count pass plus cells pass, from HIP events; index
+ * 0 counting, 1 bucketed; 0 while unmeasured) and the number of timed builds it
+ * rests on.  Any output may be NULL.  Host-only: reads what the context has
+ * harvested, never waits. */
+sph_status sph_build_stats(sph_ctx *ctx, int32_t *method, double us[2], int64_t samples[2]);
+
+/* SPH_BUILD_AUTO: forget both methods' build times and time them again over the
+ * next builds (for a flow that has changed its character, e.g. after a restart
+ * from a checkpoint).  Host-only; SPH_OK also for a fixed method (no effect). */
+sph_status sph_build_retune(sph_ctx *ctx);
 
 /* Async: neighbour search on the cell list of the last build, the use a solver
  * makes of the same list (the kernel support 2h of Section 3, h = 1.3 dp, is the

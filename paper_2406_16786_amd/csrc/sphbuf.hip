@@ -1,20 +1,23 @@
 // MI355X (gfx950, CDNA4) kernels and C ABI of the arbitrary-positioned SPH
 // in-/outlet buffer update (arXiv 2406.16786, Section 3, Algorithms 1-3).
 //
-// Per update:
-//   K0a count   : cell key of every particle (FP32 floor), per-cell rank from
-//                 wave-run-aggregated atomics (one atomic per run of equal keys).
-//   K0b scan    : single-pass decoupled look-back exclusive scan of the cell
-//                 counts -> cell_start; zeroes the counts for the next build.
-//   K0c scatter : cell_idx[cell_start[key] + rank] = i.
-//   K1  classify: one wave per run of cover cells of one buffer; candidates are
-//                 rotated into the buffer frame in FP32 (hi/lo origin), decisions
-//                 inside the guard band are redone in FP64 exactly as defined;
-//                 ballot/mbcnt wave compaction appends generation, deletion and
-//                 relabel events.  (K1f: the same over every particle.)
-//   K2  finalize: one workgroup: status checks before any write, LDS bitonic
-//                 sort of the event lists, duplicate capture, recycle, relabel,
-//                 hole refill from the tail, append, counters.
+// Per step of a context (the merged step, the default): a build, then an update.
+//   build, count pass: cell key of every particle (FP32 floor) and its rank -- in
+//     its cell (k_count: one atomic per run of equal keys in a wave) or in a bucket
+//     of consecutive cells (k_bk_count: LDS histogram, one global atomic per
+//     workgroup and bucket); the cover cells' particles near a check region are
+//     listed as candidates;
+//   update, cells pass with the candidates' exact tests beside it (rotation into
+//     the buffer frame in FP32 with a hi/lo origin, the decisions inside the guard
+//     band redone in FP64 exactly as defined, events appended by ballot/mbcnt wave
+//     compaction): k_scan (look-back scan of the cell counts) and k_scatter_cls, or
+//     k_bk_scatter_cls and k_bk_sort (a counting sort inside each bucket);
+//   k_finalize: status checks before any write, the event lists sorted in LDS,
+//     recycle, relabel, hole refill from the tail, append.
+// Which build runs is timed and chosen per context (SPH_BUILD_AUTO).  The
+// cover-cell walk (SPH_UPDATE_CELLS) classifies the particles of the cover cells
+// from the finished cell list (k_classify_local); the full scan (k_filter_full,
+// k_classify_cand) tests every particle; batches build by the counting sort.
 // Everything reads the live count from device memory, so the whole chain can be
 // enqueued without host round trips.
 #include <hip/hip_runtime.h>
@@ -26,6 +29,7 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "sphbuf.h"
@@ -442,6 +446,104 @@ __device__ __forceinline__ T &at32(T *base, uint32_t o) {
 constexpr int kCountBatch = 2;
 constexpr int64_t kCountPer = 2048;  // particles per count workgroup (single domain)
 
+// FP32 check-region test widened by the guard band: true for every member of C_k.
+// (The caller first tests the axis-aligned box bmin..bmax, rounded outward: it
+// never drops a member, and a NaN coordinate fails it.)
+__device__ __forceinline__ bool near_region(const BufDev &b, int dim, float x, float y, float z) {
+    const float d0 = (x - b.ohi[0]) - b.olo[0];
+    const float d1 = (y - b.ohi[1]) - b.olo[1];
+    const float d2 = dim == 3 ? (z - b.ohi[2]) - b.olo[2] : 0.0f;
+    const float l0 = b.qf[0] * d0 + b.qf[1] * d1 + b.qf[2] * d2;
+    const float l1 = b.qf[3] * d0 + b.qf[4] * d1 + b.qf[5] * d2;
+    const float l2 = b.qf[6] * d0 + b.qf[7] * d1 + b.qf[8] * d2;
+    const float g = b.guard;
+    return fabsf(l0) < b.thrf[3] + g && fabsf(l1) < b.thrf[4] + g && (dim == 2 || fabsf(l2) < b.thrf[5] + g);
+}
+
+// ------------------------------------------------- merged step: candidates --
+//
+// The count pass of a merged step lists its candidates: the particles of the
+// buffers' cover cells (bit k of the cell's cover mask) that lie near check region
+// k.  A workgroup gathers them in LDS (particle offset in the workgroup << 4 |
+// buffer; one LDS atomic per wave) and appends them to the candidate list with one
+// global atomic; a workgroup with more than kCandLds of them appends the rest one
+// by one.  E holds the offset: 16 bits for workgroups of at most 4096 particles.
+
+constexpr int kCandLds = 2048;
+
+template <typename E>
+struct CandLds {
+    E e[kCandLds];
+    unsigned n;
+    unsigned long long base;
+};
+
+struct CandArgs {
+    const uint16_t *cover;   // per cell: cover bits of the buffers
+    const BufDev *bufs;
+    int nb;
+    unsigned long long *cand;  // (index << 4) | buffer
+    int64_t cap_cand;
+};
+
+// Called by whole waves (cm = 0 where there is nothing to test; z = 0 in 2-D).
+template <typename E>
+__device__ __forceinline__ void cand_append(const CandArgs &c, const BufDev *sb, int dim, uint32_t cm, float x,
+                                            float y, float z, uint32_t local, int64_t i, int lane,
+                                            CandLds<E> &L, Ctl *ctl) {
+    if (__ballot(cm != 0u) == 0ull) return;  // wave-uniform
+    unsigned cb = 0u;
+    uint32_t m = cm;
+    while (m) {
+        const int k = __ffs(m) - 1;
+        m &= m - 1u;
+        const BufDev &b = sb[k];
+        const bool in_box = x > b.bmin[0] && x < b.bmax[0] && y > b.bmin[1] && y < b.bmax[1] && z > b.bmin[2] &&
+                            z < b.bmax[2];
+        if (in_box && near_region(b, dim, x, y, z)) cb |= 1u << k;
+    }
+    const unsigned mine = (unsigned)__popc(cb);
+    unsigned incl = mine;
+    for (int off = 1; off < kWave; off <<= 1) {
+        const unsigned t = __shfl_up(incl, off);
+        if (lane >= off) incl += t;
+    }
+    const unsigned tot = __shfl(incl, kWave - 1);
+    unsigned at = 0u;
+    if (lane == 0 && tot) at = atomicAdd(&L.n, tot);
+    at = __shfl(at, 0) + (incl - mine);
+    while (cb) {
+        const int k = __ffs(cb) - 1;
+        cb &= cb - 1u;
+        if (at < (unsigned)kCandLds) {
+            L.e[at] = (E)((local << 4) | (uint32_t)k);
+        } else {  // a workgroup full of candidates: the rest one by one
+            const unsigned long long g = atomicAdd(&ctl->cand_count, 1ull);
+            if (g < (unsigned long long)c.cap_cand)
+                c.cand[g] = ((unsigned long long)i << 4) | (unsigned long long)k;
+            else
+                ctl->cand_overflow = 1u;
+        }
+        ++at;
+    }
+}
+
+// The workgroup's gathered candidates into the list (after a barrier; has barriers).
+template <typename E>
+__device__ __forceinline__ void cand_flush(const CandArgs &c, CandLds<E> &L, int64_t s0, Ctl *ctl) {
+    const unsigned nc = min(L.n, (unsigned)kCandLds);
+    if (threadIdx.x == 0) L.base = nc ? atomicAdd(&ctl->cand_count, (unsigned long long)nc) : 0ull;
+    __syncthreads();
+    for (unsigned e = threadIdx.x; e < nc; e += blockDim.x) {
+        const unsigned long long g = L.base + e;
+        const uint32_t v = (uint32_t)L.e[e];
+        if (g < (unsigned long long)c.cap_cand)
+            c.cand[g] = ((unsigned long long)(s0 + (v >> 4)) << 4) | (unsigned long long)(v & 15u);
+        else
+            ctl->cand_overflow = 1u;
+    }
+}
+
 struct CountArgs {
     const float *x, *y, *z;
     const int64_t *n_dev;
@@ -455,8 +557,10 @@ struct CountArgs {
     int64_t n_tiles;
     Ctl *ctl;
     unsigned int *nonfinite;        // flag to raise on a non-finite position
+    CandArgs c;                     // merged step: the candidate list
 };
 
+template <bool kCand>
 __device__ __forceinline__ void count_body(const CountArgs &a, const int lb, const int G) {
     const int64_t N = live_count(a.n_dev, a.capacity);
     const int lane = threadIdx.x & (kWave - 1);
@@ -483,6 +587,14 @@ __device__ __forceinline__ void count_body(const CountArgs &a, const int lb, con
     bool bad = false;
     const uint32_t rmask = (1u << a.rbits) - 1u;
     if (s0 >= N) return;  // block-uniform: no particle here
+    __shared__ BufDev sb[kCand ? SPH_MAX_BUFFERS : 1];
+    __shared__ std::conditional_t<kCand, CandLds<uint32_t>, char> s_cand;
+    if constexpr (kCand) {
+        for (int t = threadIdx.x; t < a.c.nb * (int)(sizeof(BufDev) / 4); t += blockDim.x)
+            reinterpret_cast<uint32_t *>(sb)[t] = reinterpret_cast<const uint32_t *>(a.c.bufs)[t];
+        if (threadIdx.x == 0) s_cand.n = 0u;
+        __syncthreads();
+    }
     constexpr int J = kCountBatch;
     const uint32_t L32 = (uint32_t)L;
     // per row: first particle, particles in it (slice-relative 32-bit offsets from
@@ -537,6 +649,19 @@ __device__ __forceinline__ void count_body(const CountArgs &a, const int lb, con
 #pragma unroll
         for (int j = 0; j < J; ++j) valid[j] = o < nr[j];
         group_keys<J>(a.g, px, py, pz, valid, key, bad);
+        // merged step: the cover bits of the keys' cells, loaded before the next
+        // positions and the atomics (their positions kept for the tests)
+        uint32_t cm[J];
+        float cx[J], cy[J], cz[J];
+        if constexpr (kCand) {
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                cm[j] = valid[j] ? a.c.cover[key[j]] : 0u;
+                cx[j] = px[j];
+                cy[j] = py[j];
+                cz[j] = d3 ? pz[j] : 0.0f;
+            }
+        }
         const uint32_t nx = it + kWave;
         if (nx < L32) load(nx);  // block-uniform; the positions are consumed
         int my_head[J], old[J];
@@ -552,11 +677,26 @@ __device__ __forceinline__ void count_body(const CountArgs &a, const int lb, con
                 at32(a.spill + rb[j], o) = ((unsigned long long)key[j] << 32) | (unsigned)rank[j];
             }
         }
+        if constexpr (kCand) {
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                const int64_t i = rb[j] + (int64_t)o;
+                cand_append(a.c, sb, a.g.dim, cm[j], cx[j], cy[j], cz[j], (uint32_t)(i - s0), i, lane, s_cand,
+                            a.ctl);
+            }
+        }
     }
     if (__ballot(bad) != 0ull && lane == 0) atomicOr(a.nonfinite, 1u);
+    if constexpr (kCand) {  // the workgroup's candidates into the list
+        __syncthreads();
+        cand_flush(a.c, s_cand, s0, a.ctl);
+    }
 }
 
-__global__ __launch_bounds__(kBuildBlock) void k_count(CountArgs a) { count_body(a, logical_block(), gridDim.x); }
+template <bool kCand>
+__global__ __launch_bounds__(kBuildBlock) void k_count(CountArgs a) {
+    count_body<kCand>(a, logical_block(), gridDim.x);
+}
 
 // Decoupled look-back scan state: bits 62..63 = flag (1 aggregate, 2 prefix),
 // low 32 bits = value.
@@ -894,19 +1034,6 @@ struct FullArgs {
     int vec;                   // positions 16-byte aligned: vector loads allowed
 };
 
-// FP32 check-region test widened by the guard band: true for every member of C_k.
-// (The caller first tests the axis-aligned box bmin..bmax, rounded outward: it
-// never drops a member, and a NaN coordinate fails it.)
-__device__ __forceinline__ bool near_region(const BufDev &b, int dim, float x, float y, float z) {
-    const float d0 = (x - b.ohi[0]) - b.olo[0];
-    const float d1 = (y - b.ohi[1]) - b.olo[1];
-    const float d2 = dim == 3 ? (z - b.ohi[2]) - b.olo[2] : 0.0f;
-    const float l0 = b.qf[0] * d0 + b.qf[1] * d1 + b.qf[2] * d2;
-    const float l1 = b.qf[3] * d0 + b.qf[4] * d1 + b.qf[5] * d2;
-    const float l2 = b.qf[6] * d0 + b.qf[7] * d1 + b.qf[8] * d2;
-    const float g = b.guard;
-    return fabsf(l0) < b.thrf[3] + g && fabsf(l1) < b.thrf[4] + g && (dim == 2 || fabsf(l2) < b.thrf[5] + g);
-}
 
 __global__ __launch_bounds__(kClassifyBlock) void k_filter_full(FullArgs a) {
     __shared__ BufDev sb[SPH_MAX_BUFFERS];
@@ -1168,15 +1295,12 @@ __device__ __forceinline__ uint32_t lds_exclusive_scan(uint32_t *v, int n, uint3
     return total;
 }
 
-constexpr int kCandLds = 2048;  // candidates a count workgroup gathers in LDS (more go out one by one)
-
 template <bool kCand>
 __global__ __launch_bounds__(kBkBlock) void k_bk_count(BkArgs a) {
+    static_assert(kBkPer <= 4096, "candidate offsets are 12 bits");
     __shared__ uint32_t s_h[kMaxBuckets];  // counts, then bases, then cursors per bucket
     __shared__ BufDev sb[kCand ? SPH_MAX_BUFFERS : 1];
-    __shared__ uint16_t s_cand[kCand ? kCandLds : 1];  // (particle offset in the workgroup << 4) | buffer
-    __shared__ unsigned s_ncand;
-    __shared__ unsigned long long s_cbase;
+    __shared__ std::conditional_t<kCand, CandLds<uint16_t>, char> s_cand;
     __shared__ uint32_t s_w[kBkBlock / kWave];
     __shared__ unsigned s_last;
     const int64_t N = live_count(a.n_dev, a.capacity);
@@ -1190,9 +1314,10 @@ __global__ __launch_bounds__(kBkBlock) void k_bk_count(BkArgs a) {
     if constexpr (kCand) {
         for (int t = threadIdx.x; t < a.nb * (int)(sizeof(BufDev) / 4); t += kBkBlock)
             reinterpret_cast<uint32_t *>(sb)[t] = reinterpret_cast<const uint32_t *>(a.bufs)[t];
-        if (threadIdx.x == 0) s_ncand = 0u;
+        if (threadIdx.x == 0) s_cand.n = 0u;
     }
     __syncthreads();
+    const CandArgs ca{a.cover, a.bufs, a.nb, a.cand, a.cap_cand};
     const int64_t s0 = (int64_t)lb * kBkPer;
     const bool d3 = a.g.dim == 3;
     const float *zb = d3 ? a.z : a.x;  // a 2-D z is a copy of x, unused
@@ -1241,63 +1366,16 @@ __global__ __launch_bounds__(kBkBlock) void k_bk_count(BkArgs a) {
                     // each cover bit kept only if the particle is near that check region
                     // (the full scan's FP32 test widened by the guard band, which keeps
                     // every member)
-                    if (__ballot(cm[q] != 0u) == 0ull) continue;  // wave-uniform
                     const int64_t i = s0 + (int64_t)(it + q) * kBkBlock + threadIdx.x;
-                    const float zq = d3 ? pz[q] : 0.0f;
-                    unsigned cb = 0u;
-                    uint32_t m = cm[q];
-                    while (m) {
-                        const int k = __ffs(m) - 1;
-                        m &= m - 1u;
-                        const BufDev &b = sb[k];
-                        const bool in_box = px[q] > b.bmin[0] && px[q] < b.bmax[0] && py[q] > b.bmin[1] &&
-                                            py[q] < b.bmax[1] && zq > b.bmin[2] && zq < b.bmax[2];
-                        if (in_box && near_region(b, dim, px[q], py[q], zq)) cb |= 1u << k;
-                    }
-                    const unsigned mine = (unsigned)__popc(cb);
-                    unsigned incl = mine;
-                    for (int off = 1; off < kWave; off <<= 1) {
-                        const unsigned t = __shfl_up(incl, off);
-                        if (lane >= off) incl += t;
-                    }
-                    // gathered in LDS (one LDS atomic per wave), listed once per workgroup
-                    const unsigned tot = __shfl(incl, kWave - 1);
-                    unsigned at = 0u;
-                    if (lane == 0 && tot) at = atomicAdd(&s_ncand, tot);
-                    at = __shfl(at, 0) + (incl - mine);
                     const uint32_t local = (uint32_t)((it + q) * kBkBlock) + threadIdx.x;
-                    while (cb) {
-                        const int k = __ffs(cb) - 1;
-                        cb &= cb - 1u;
-                        if (at < (unsigned)kCandLds) {
-                            s_cand[at] = (uint16_t)((local << 4) | (uint32_t)k);
-                        } else {  // a workgroup full of candidates: the rest one by one
-                            const unsigned long long g = atomicAdd(&a.ctl->cand_count, 1ull);
-                            if (g < (unsigned long long)a.cap_cand)
-                                a.cand[g] = ((unsigned long long)i << 4) | (unsigned long long)k;
-                            else
-                                a.ctl->cand_overflow = 1u;
-                        }
-                        ++at;
-                    }
+                    cand_append(ca, sb, dim, cm[q], px[q], py[q], d3 ? pz[q] : 0.0f, local, i, lane, s_cand,
+                                a.ctl);
                 }
             }
         }
     }
     __syncthreads();
-    if constexpr (kCand) {  // the workgroup's candidates into the list
-        const unsigned nc = min(s_ncand, (unsigned)kCandLds);
-        if (threadIdx.x == 0) s_cbase = nc ? atomicAdd(&a.ctl->cand_count, (unsigned long long)nc) : 0ull;
-        __syncthreads();
-        for (unsigned e = threadIdx.x; e < nc; e += kBkBlock) {
-            const unsigned long long g = s_cbase + e;
-            const uint32_t v = s_cand[e];
-            if (g < (unsigned long long)a.cap_cand)
-                a.cand[g] = ((unsigned long long)(s0 + (v >> 4)) << 4) | (unsigned long long)(v & 15u);
-            else
-                a.ctl->cand_overflow = 1u;
-        }
-    }
+    if constexpr (kCand) cand_flush(ca, s_cand, s0, a.ctl);  // the workgroup's candidates into the list
     // ---- the workgroup's base in each bucket it meets: one global atomic each ----
     for (int t = threadIdx.x; t < a.nbk; t += kBkBlock) {
         const uint32_t c = s_h[t];
@@ -1383,6 +1461,15 @@ __global__ __launch_bounds__(kBkBlock) void k_bk_scatter_cls(BkArgs a, FullArgs 
         bk_scatter_body(a, (int)blockIdx.x - ncls, (int)gridDim.x - ncls);
 }
 
+// The same for the counting build: classification beside its scatter.
+__global__ __launch_bounds__(kBuildBlock) void k_scatter_cls(ScatterArgs a, FullArgs f, int ncls) {
+    static_assert(kBuildBlock == kClassifyBlock, "one launch");
+    if ((int)blockIdx.x < ncls)
+        classify_cand_body(f, (int)blockIdx.x, ncls);
+    else
+        scatter_body(a, (int)blockIdx.x - ncls, (int)gridDim.x - ncls);
+}
+
 constexpr int kSortBlock = 512;
 
 __global__ __launch_bounds__(kSortBlock) void k_bk_sort(BkArgs a) {
@@ -1393,49 +1480,49 @@ __global__ __launch_bounds__(kSortBlock) void k_bk_sort(BkArgs a) {
     const uint32_t n0 = a.bk_start[b], n1 = a.bk_start[b + 1];
     const int64_t c0 = (int64_t)b << a.bshift;
     const int nc = (int)min<int64_t>((int64_t)1 << a.bshift, a.n_cells - c0);
-    const int lane = (int)threadIdx.x & (kWave - 1);
     for (int t = threadIdx.x; t < nc; t += kSortBlock) s_c[t] = 0u;
     __syncthreads();
-    constexpr int kB = 8;  // entries per thread with their loads in flight together
+    // Both passes software pipelined: the next round's entries are loaded before the
+    // current round is counted or placed (the LDS atomics and stores of a round then
+    // overlap the next round's loads).  One LDS atomic per entry: in bucket order the
+    // lanes of a wave rarely share a cell, so grouping equal keys first costs more
+    // than it saves.
+    constexpr int kB = 4;  // entries per thread and round
     constexpr uint32_t kStep = (uint32_t)kSortBlock * kB;
-    for (uint32_t e0 = n0; e0 < n1; e0 += kStep) {  // block-uniform trip count
-        uint32_t lk[kB];
+    auto load = [&](uint32_t e0, uint2 (&u)[kB]) {
 #pragma unroll
         for (int q = 0; q < kB; ++q) {
             const uint32_t e = e0 + (uint32_t)q * kSortBlock + threadIdx.x;
-            lk[q] = e < n1 ? a.tmp[e].x - (uint32_t)c0 : 0u;
+            u[q] = e < n1 ? a.tmp[e] : make_uint2((uint32_t)c0, 0u);
         }
+    };
+    uint2 u[kB], un[kB];
+    if (n0 < n1) load(n0, u);
+    for (uint32_t e0 = n0; e0 < n1; e0 += kStep) {  // block-uniform trip count
+        if (e0 + kStep < n1) load(e0 + kStep, un);
 #pragma unroll
         for (int q = 0; q < kB; ++q) {
             const bool ok = e0 + (uint32_t)q * kSortBlock + threadIdx.x < n1;
-            int head, len;
-            lane_runs(lk[q], ok, lane, head, len);
-            if (len > 0 && lane == head) atomicAdd(&s_c[lk[q]], (uint32_t)len);
+            if (ok) atomicAdd(&s_c[u[q].x - (uint32_t)c0], 1u);
         }
+#pragma unroll
+        for (int q = 0; q < kB; ++q) u[q] = un[q];
     }
     __syncthreads();
     lds_exclusive_scan<kSortBlock>(s_c, nc, s_w);
     for (int t = threadIdx.x; t < nc; t += kSortBlock) a.cell_start[c0 + t] = (int32_t)(n0 + s_c[t]);
     if (b == a.nbk - 1 && threadIdx.x == 0) a.cell_start[a.n_cells] = (int32_t)n1;
     __syncthreads();  // every offset read before the cursors move
+    if (n0 < n1) load(n0, u);
     for (uint32_t e0 = n0; e0 < n1; e0 += kStep) {
-        uint2 u[kB];
-#pragma unroll
-        for (int q = 0; q < kB; ++q) {
-            const uint32_t e = e0 + (uint32_t)q * kSortBlock + threadIdx.x;
-            u[q] = e < n1 ? a.tmp[e] : make_uint2((uint32_t)c0, 0u);
-        }
+        if (e0 + kStep < n1) load(e0 + kStep, un);
 #pragma unroll
         for (int q = 0; q < kB; ++q) {
             const bool ok = e0 + (uint32_t)q * kSortBlock + threadIdx.x < n1;
-            const uint32_t lk = u[q].x - (uint32_t)c0;
-            int head, len;
-            lane_runs(lk, ok, lane, head, len);
-            uint32_t old = 0u;
-            if (len > 0 && lane == head) old = atomicAdd(&s_c[lk], (uint32_t)len);
-            const uint32_t pos = __shfl(old, head) + (uint32_t)(lane - head);
-            if (ok) a.cell_idx[n0 + pos] = (int32_t)u[q].y;
+            if (ok) a.cell_idx[n0 + atomicAdd(&s_c[u[q].x - (uint32_t)c0], 1u)] = (int32_t)u[q].y;
         }
+#pragma unroll
+        for (int q = 0; q < kB; ++q) u[q] = un[q];
     }
 }
 
@@ -2602,7 +2689,7 @@ __global__ __launch_bounds__(kBuildBlock) void kb_count(const CountArgs *args, c
                                                         const int32_t *vg) {
     const BlockMap m = map[logical_block()];
     if (m.d < 0) return;
-    count_body(args[m.d], m.vb, vg[m.d]);
+    count_body<false>(args[m.d], m.vb, vg[m.d]);
 }
 
 __global__ __launch_bounds__(kScanBlock) void kb_scan(const ScanArgs *args, const BlockMap *map) {
@@ -2634,6 +2721,40 @@ __global__ __launch_bounds__(kFinBlock) void kb_finalize(const FinArgs *args, in
 }  // namespace
 
 // ====================================================================== host ==
+
+// ------------------------------------------------------------ build method --
+//
+// Two builds give the same cell list (up to the order inside a cell): the
+// three-kernel counting sort (one atomic per run of equal keys in a wave on the
+// cell counters, look-back scan, scatter) and the bucketed one (workgroup
+// histograms of cell buckets, bucket scatter, LDS counting sort per bucket).  Which
+// is faster depends on the particle order: the counting sort wins while the array
+// keeps long runs of one cell (a lattice just built), the bucketed one once the
+// flow has scattered it.  SPH_BUILD_AUTO times both on the stream with events and
+// runs the faster: each is timed on kExploreSamples builds after one untimed
+// warm-up build, then the choice is re-checked every kReprobe builds by timing one
+// build of each (a 3 % margin before switching).  A method's time is the median of
+// its last three timings (with two, the smaller): a build slowed by something else
+// on the GPU only ever adds time.  Events are read only once they have completed
+// (hipEventQuery), so the host never waits on them.
+
+constexpr int kMethCounting = 0, kMethBucketed = 1;
+constexpr int kTimerSets = 8;
+constexpr int kExploreSamples = 3;
+constexpr int kReprobe = 64;
+
+struct BuildTimer {
+    bool init = false, ok = false;   // events created (ok: all of them)
+    hipEvent_t ev[kTimerSets][4] = {};  // count pass start/end, cells pass start/end
+    bool busy[kTimerSets] = {};
+    bool cells_done[kTimerSets] = {};
+    int meth[kTimerSets] = {};
+    double last[2][3] = {};          // latest timings per method (us), a ring
+    double est[2] = {0.0, 0.0};      // build time per method (us) from the ring
+    int64_t samples[2] = {0, 0};
+    int64_t builds = 0;
+    int cur = kMethCounting;
+};
 
 struct sph_ctx {
     int dim = 2;
@@ -2679,13 +2800,12 @@ struct sph_ctx {
 
     int32_t *d_count = nullptr, *d_cell_start = nullptr, *d_cell_idx = nullptr;
     unsigned long long *d_cand = nullptr;        // candidate list of the full scan
-    // merged step (the default update path): the count pass of the bucketed build also
-    // lists the cover cells' particles near a check region as candidates; the update
-    // classifies them beside the bucket scatter, then sorts the buckets and
-    // finalizes.  Off (or a grid too large for the bucketed build): the update walks
-    // the cover cells of the finished cell list.
+    // merged step (the default update path): the count pass of the build also lists
+    // the cover cells' particles near a check region as candidates; the update
+    // classifies them beside the build's scatter, then finalizes.  Off: the update
+    // walks the cover cells of the finished cell list.
     bool merged = true;
-    bool scan_pending = false;   // a merged build's bucket scatter and sort are not enqueued yet
+    bool scan_pending = false;   // a merged build's cells pass is not enqueued yet
     bool ev_pending = false;     // a merged build's candidates are not classified and finalized yet
     bool nf_full_next = false;   // the next cover-walk finalize reads the count pass's non-finite flag
     uint16_t *d_cover = nullptr; // per cell: bit k set if the cell is in buffer k's cover
@@ -2695,6 +2815,13 @@ struct sph_ctx {
     int bshift = 0, nbk = 0;
     uint32_t *d_bk_count = nullptr, *d_bk_start = nullptr;
     uint2 *d_ent = nullptr, *d_tmp = nullptr;
+    // build method: sph_config::build_method; meth is the latest build's (its cells
+    // pass follows it), timed on timer set tset (-1: untimed)
+    int build_pref = SPH_BUILD_AUTO;
+    int last_method = SPH_BUILD_AUTO;  // sph_build_method of the latest build (AUTO: none yet)
+    int meth = 0;
+    int tset = -1;
+    BuildTimer bt;
     int64_t cover_cells = 0;
     uint32_t *d_keys = nullptr;                  // packed (key, rank) of each particle (three-kernel build)
     unsigned long long *d_keyrank = nullptr;     // full (key, rank) of the particles that do not fit
@@ -2835,6 +2962,9 @@ void bk_layout(sph_ctx *c) {
     c->bshift = 0;
     while (((c->n_cells + (int64_t(1) << c->bshift) - 1) >> c->bshift) > kMaxBuckets) ++c->bshift;
     c->nbk = (int)((c->n_cells + (int64_t(1) << c->bshift) - 1) >> c->bshift);
+    // a new grid: the build times start over (the events in flight are still read)
+    c->bt.samples[0] = c->bt.samples[1] = 0;
+    c->bt.est[0] = c->bt.est[1] = 0.0;
 }
 
 // Workgroups of k_bk_count for a particle array of this capacity (a multiple of 8).
@@ -2850,7 +2980,9 @@ int count_blocks(int64_t capacity) {
     return (int)std::max<int64_t>(8, std::min<int64_t>(16384, (want + 7) / 8 * 8));
 }
 
-CountArgs count_args(const sph_ctx *ctx, const Parts &pp) {
+// Arguments of the counting build's count pass (cand: with the merged step's
+// candidate list).
+CountArgs count_args(const sph_ctx *ctx, const Parts &pp, bool cand = false) {
     CountArgs ca{};
     ca.x = pp.pos[0];
     ca.y = pp.pos[1];
@@ -2865,7 +2997,14 @@ CountArgs count_args(const sph_ctx *ctx, const Parts &pp) {
     ca.tile_state = ctx->d_tile_state;
     ca.n_tiles = ctx->n_tiles;
     ca.ctl = ctx->d_ctl;
-    ca.nonfinite = &ctx->d_ctl->nonfinite_build;
+    ca.nonfinite = cand ? &ctx->d_ctl->nonfinite_full : &ctx->d_ctl->nonfinite_build;
+    if (cand) {
+        ca.c.cover = ctx->d_cover;
+        ca.c.bufs = ctx->d_bufs;
+        ca.c.nb = ctx->nb;
+        ca.c.cand = ctx->d_cand;
+        ca.c.cap_cand = ctx->capacity + kCandSlack;
+    }
     return ca;
 }
 
@@ -3002,12 +3141,158 @@ sph_status bk_cells(sph_ctx *c, const FullArgs *fa) {
     return SPH_OK;
 }
 
-// Merged step: enqueue the bucket scatter and sort a merged build left for its
-// update (every call that reads the cell list needs them first).
+// Counting build after its count pass: the look-back scan, then the scatter (fa:
+// the merged step's candidates are classified beside it).
+sph_status count_cells(sph_ctx *c, const FullArgs *fa) {
+    const ScanArgs sa = scan_args(c);
+    {
+        ProfScope ps(c, SPH_PHASE_SCAN);
+        hipLaunchKernelGGL(k_scan, dim3((unsigned)c->n_tiles), dim3(kScanBlock), 0, c->stream, sa);
+    }
+    HIP_TRY(hipGetLastError());
+    const ScatterArgs xa = scatter_args(c, c->built_capacity);
+    {
+        ProfScope ps(c, SPH_PHASE_SCATTER);
+        if (fa)
+            hipLaunchKernelGGL(k_scatter_cls, dim3(kCandBlocksMerged + c->build_blocks), dim3(kBuildBlock), 0,
+                               c->stream, xa, *fa, kCandBlocksMerged);
+        else
+            hipLaunchKernelGGL(k_scatter, dim3(c->build_blocks), dim3(kBuildBlock), 0, c->stream, xa);
+    }
+    HIP_TRY(hipGetLastError());
+    return SPH_OK;
+}
+
+// Timer events of the build method choice, created at the first automatic build.
+bool timers_ready(sph_ctx *c) {
+    BuildTimer &t = c->bt;
+    if (!t.init) {
+        t.init = true;
+        t.ok = true;
+        for (auto &set : t.ev)
+            for (hipEvent_t &e : set)
+                if (hipEventCreate(&e) != hipSuccess) {
+                    e = nullptr;
+                    t.ok = false;
+                }
+        (void)hipGetLastError();
+    }
+    return t.ok;
+}
+
+void timers_free(sph_ctx *c) {
+    for (auto &set : c->bt.ev)
+        for (hipEvent_t e : set)
+            if (e) (void)hipEventDestroy(e);
+}
+
+// Timings whose events have completed into the estimates (never waits).
+void timers_harvest(sph_ctx *c) {
+    BuildTimer &t = c->bt;
+    for (int s = 0; s < kTimerSets; ++s) {
+        if (!t.busy[s]) continue;
+        if (!t.cells_done[s]) {  // its build ended early (an error): nothing to read
+            if (s != c->tset) t.busy[s] = false;
+            continue;
+        }
+        const hipError_t q = hipEventQuery(t.ev[s][3]);
+        if (q == hipErrorNotReady) {
+            (void)hipGetLastError();  // not an error of any call
+            continue;
+        }
+        t.busy[s] = false;
+        float a = 0.0f, b = 0.0f;
+        if (q != hipSuccess || hipEventElapsedTime(&a, t.ev[s][0], t.ev[s][1]) != hipSuccess ||
+            hipEventElapsedTime(&b, t.ev[s][2], t.ev[s][3]) != hipSuccess) {
+            (void)hipGetLastError();
+            continue;
+        }
+        const double us = 1e3 * ((double)a + (double)b);
+        const int m = t.meth[s];
+        t.last[m][t.samples[m] % 3] = us;
+        ++t.samples[m];
+        const double *v = t.last[m];
+        if (t.samples[m] == 1)
+            t.est[m] = v[0];
+        else if (t.samples[m] == 2)
+            t.est[m] = std::min(v[0], v[1]);
+        else
+            t.est[m] = std::max(std::min(v[0], v[1]), std::min(std::max(v[0], v[1]), v[2]));
+    }
+    if (t.samples[0] >= kExploreSamples && t.samples[1] >= kExploreSamples) {
+        const int o = 1 - t.cur;
+        if (t.est[o] < 0.97 * t.est[t.cur]) t.cur = o;
+    }
+}
+
+// The next build's method; sets c->tset when it is to be timed.
+int pick_method(sph_ctx *c) {
+    c->tset = -1;
+    if (!c->bk || c->build_pref == SPH_BUILD_COUNTING) return kMethCounting;
+    if (c->build_pref == SPH_BUILD_BUCKETED) return kMethBucketed;
+    BuildTimer &t = c->bt;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(c->stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+        (void)hipGetLastError();
+        return t.cur;  // no events inside a captured graph
+    }
+    if (!timers_ready(c)) return kMethBucketed;
+    timers_harvest(c);
+    const int64_t b = t.builds++;
+    int m = t.cur;
+    bool timed = false;
+    if (b < 2) {
+        m = (int)b;  // warm-up: one untimed build of each
+    } else if (t.samples[0] < kExploreSamples || t.samples[1] < kExploreSamples) {
+        m = (int)(b & 1);
+        timed = true;
+    } else {
+        const int64_t k = b % kReprobe;
+        m = k == kReprobe - 1 ? 1 - t.cur : t.cur;
+        timed = k >= kReprobe - 2;
+    }
+    for (int s = 0; timed && s < kTimerSets; ++s) {
+        if (t.busy[s]) continue;
+        t.busy[s] = true;
+        t.cells_done[s] = false;
+        t.meth[s] = m;
+        c->tset = s;
+        break;
+    }
+    return m;
+}
+
+// Timer event k (0, 1: around the count pass; 2, 3: around the cells pass) of a
+// timed build.
+void tmark(sph_ctx *c, int k) {
+    if (c->tset < 0) return;
+    BuildTimer &t = c->bt;
+    if (hipEventRecord(t.ev[c->tset][k], c->stream) != hipSuccess) {
+        (void)hipGetLastError();
+        t.busy[c->tset] = false;
+        c->tset = -1;
+        return;
+    }
+    if (k == 3) {
+        t.cells_done[c->tset] = true;
+        c->tset = -1;
+    }
+}
+
+// The cells pass of the latest build (after its count pass), by its method.
+sph_status build_cells(sph_ctx *c, const FullArgs *fa) {
+    tmark(c, 2);
+    HIP_CHECKED(c->meth == kMethBucketed ? bk_cells(c, fa) : count_cells(c, fa));
+    tmark(c, 3);
+    return SPH_OK;
+}
+
+// Merged step: enqueue the cells pass a merged build left for its update (every
+// call that reads the cell list needs it first).
 sph_status merged_cells(sph_ctx *c) {
     if (!c->scan_pending) return SPH_OK;
     c->scan_pending = false;
-    return bk_cells(c, nullptr);
+    return build_cells(c, nullptr);
 }
 
 // Merged step: drop the events of a merged build once a call changes what they were
@@ -3069,6 +3354,7 @@ void free_ctx(sph_ctx *c) {
     (void)hipFree(c->d_result);
     if (c->h_result) (void)hipHostFree(c->h_result);
     for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
+    timers_free(c);
     delete c;
 }
 
@@ -3340,6 +3626,7 @@ extern "C" sph_status sph_create(const sph_config *cfg, sph_ctx **out) {
         return SPH_ERR_ARG;
     }
     if (cfg->update_path != SPH_UPDATE_MERGED && cfg->update_path != SPH_UPDATE_CELLS) return SPH_ERR_ARG;
+    if (cfg->build_method < SPH_BUILD_AUTO || cfg->build_method > SPH_BUILD_BUCKETED) return SPH_ERR_ARG;
     {   // FP32 binning must place every particle within a quarter cell of its cell
         double glo[3] = {0.0, 0.0, 0.0};
         for (int c = 0; c < cfg->dim; ++c) glo[c] = cfg->lo[c];
@@ -3368,6 +3655,7 @@ extern "C" sph_status sph_create(const sph_config *cfg, sph_ctx **out) {
     c->max_events = (unsigned)cfg->max_events;
     c->stream = (hipStream_t)cfg->stream;
     c->merged = cfg->update_path == SPH_UPDATE_MERGED;
+    c->build_pref = cfg->build_method;
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
         return SPH_ERR_HIP;
@@ -3502,46 +3790,35 @@ extern "C" sph_status sph_celllist_build(sph_ctx *ctx, const sph_particles *p) {
     if (st != SPH_OK) return st;
     HIP_CHECKED(merged_drop(ctx, true));
     ctx->built_capacity = pp.capacity;
-    if (ctx->bk) {
-        // merged step (domains with buffers): the count pass also lists the
-        // candidates; the bucket scatter and sort are left for the update (or the
-        // next call that needs the cell list)
-        const bool cand = ctx->merged && ctx->d_cover && ctx->nb > 0;
-        const BkArgs ba = bk_args(ctx, &pp, cand);
-        {
-            ProfScope ps(ctx, SPH_PHASE_COUNT);
+    ctx->meth = pick_method(ctx);
+    ctx->last_method = ctx->meth == kMethBucketed ? SPH_BUILD_BUCKETED : SPH_BUILD_COUNTING;
+    // merged step (domains with buffers): the count pass also lists the candidates;
+    // the cells pass is left for the update (or the next call that needs the list)
+    const bool cand = ctx->merged && ctx->d_cover && ctx->nb > 0;
+    tmark(ctx, 0);
+    {
+        ProfScope ps(ctx, SPH_PHASE_COUNT);
+        if (ctx->meth == kMethBucketed) {
+            const BkArgs ba = bk_args(ctx, &pp, cand);
             if (cand)
                 hipLaunchKernelGGL(k_bk_count<true>, dim3(bk_blocks(pp.capacity)), dim3(kBkBlock), 0, ctx->stream, ba);
             else
                 hipLaunchKernelGGL(k_bk_count<false>, dim3(bk_blocks(pp.capacity)), dim3(kBkBlock), 0, ctx->stream, ba);
+        } else {
+            const CountArgs ca = count_args(ctx, pp, cand);
+            if (cand)
+                hipLaunchKernelGGL(k_count<true>, dim3(count_blocks(pp.capacity)), dim3(kBuildBlock), 0, ctx->stream, ca);
+            else
+                hipLaunchKernelGGL(k_count<false>, dim3(count_blocks(pp.capacity)), dim3(kBuildBlock), 0, ctx->stream, ca);
         }
-        HIP_TRY(hipGetLastError());
-        ctx->built = true;
-        if (!cand) return bk_cells(ctx, nullptr);
-        ctx->scan_pending = true;
-        ctx->ev_pending = true;
-        ctx->nf_full_next = true;
-        return SPH_OK;
-    }
-    const CountArgs ca = count_args(ctx, pp);
-    {
-        ProfScope ps(ctx, SPH_PHASE_COUNT);
-        hipLaunchKernelGGL(k_count, dim3(count_blocks(pp.capacity)), dim3(kBuildBlock), 0, ctx->stream, ca);
     }
     HIP_TRY(hipGetLastError());
-    const ScanArgs sa = scan_args(ctx);
-    {
-        ProfScope ps(ctx, SPH_PHASE_SCAN);
-        hipLaunchKernelGGL(k_scan, dim3((unsigned)ctx->n_tiles), dim3(kScanBlock), 0, ctx->stream, sa);
-    }
-    HIP_TRY(hipGetLastError());
-    const ScatterArgs xa = scatter_args(ctx, pp.capacity);
-    {
-        ProfScope ps(ctx, SPH_PHASE_SCATTER);
-        hipLaunchKernelGGL(k_scatter, dim3(ctx->build_blocks), dim3(kBuildBlock), 0, ctx->stream, xa);
-    }
-    HIP_TRY(hipGetLastError());
+    tmark(ctx, 1);
     ctx->built = true;
+    if (!cand) return build_cells(ctx, nullptr);
+    ctx->scan_pending = true;
+    ctx->ev_pending = true;
+    ctx->nf_full_next = true;
     return SPH_OK;
 }
 
@@ -3654,7 +3931,7 @@ extern "C" sph_status sph_celllist_build_noalloc(int32_t dim, const double lo[3]
     ca.n_tiles = (m + kScanTile - 1) / kScanTile;
     ca.ctl = ctl;
     ca.nonfinite = &ctl->nonfinite_build;
-    hipLaunchKernelGGL(k_count, dim3(count_blocks(capacity)), dim3(kBuildBlock), 0, st, ca);
+    hipLaunchKernelGGL(k_count<false>, dim3(count_blocks(capacity)), dim3(kBuildBlock), 0, st, ca);
     ScanArgs sa{};
     sa.count = ca.count;
     sa.cell_start = cell_start;
@@ -3687,12 +3964,12 @@ extern "C" sph_status sph_buffer_update_async(sph_ctx *ctx, sph_particles *p) {
     if (ctx->fields.rho >= pp.nc) return SPH_ERR_ARG;
     if (ctx->merged && ctx->ev_pending) {
         // the count pass listed the candidates: their exact tests run beside the
-        // bucket scatter, then the bucket sort and the finalize (or the tests alone
-        // if a call needed the cell list first)
+        // build's scatter, then the finalize (or the tests alone if a call needed
+        // the cell list first)
         const FullArgs fa = cand_args(ctx, pp);
         if (ctx->scan_pending) {
             ctx->scan_pending = false;
-            HIP_CHECKED(bk_cells(ctx, &fa));
+            HIP_CHECKED(build_cells(ctx, &fa));
         } else {
             {
                 ProfScope ps(ctx, SPH_PHASE_CANDIDATES);
@@ -3792,6 +4069,31 @@ extern "C" sph_status sph_last_events(sph_ctx *ctx, int64_t *gen_src, int64_t *d
         HIP_TRY(hipMemcpy(tmp.data(), ctx->d_del_sorted, sizeof(uint32_t) * d, hipMemcpyDeviceToHost));
         for (int64_t j = 0; j < d; ++j) del_idx[j] = (int64_t)tmp[j];
     }
+    return SPH_OK;
+}
+
+extern "C" sph_status sph_build_stats(sph_ctx *ctx, int32_t *method, double us[2], int64_t samples[2]) {
+    if (!ctx) return SPH_ERR_ARG;
+    if (ctx->bt.init) timers_harvest(ctx);
+    if (method) *method = ctx->last_method;
+    for (int m = 0; m < 2; ++m) {
+        if (us) us[m] = ctx->bt.samples[m] ? ctx->bt.est[m] : 0.0;
+        if (samples) samples[m] = ctx->bt.samples[m];
+    }
+    return SPH_OK;
+}
+
+extern "C" sph_status sph_build_retune(sph_ctx *ctx) {
+    if (!ctx) return SPH_ERR_ARG;
+    BuildTimer &t = ctx->bt;
+    if (t.init) timers_harvest(ctx);
+    for (int m = 0; m < 2; ++m) {
+        t.samples[m] = 0;
+        t.est[m] = 0.0;
+    }
+    for (int s = 0; s < kTimerSets; ++s)  // timings in flight would count: drop them
+        if (t.busy[s] && s != ctx->tset) t.busy[s] = false;
+    t.builds = std::min<int64_t>(t.builds, 2);
     return SPH_OK;
 }
 

@@ -19,7 +19,7 @@ class Domain:
                  pos: Sequence[np.ndarray], carried: Sequence[np.ndarray], label: np.ndarray, ids: np.ndarray,
                  n: int, next_id: int, max_events: int = 4096, device: str = "cuda:0",
                  stream: Optional[torch.cuda.Stream] = None, brick_log2: int = 0, brick_margin: int = 1,
-                 update_path: str = "merged"):
+                 update_path: str = "merged", build_method: str = "auto"):
         self.dim = dim
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
@@ -32,7 +32,8 @@ class Domain:
         self.capacity = capacity
         self.upload(pos, carried, label, ids, n)
         st, ctx = S.sph_create(dim, lo, hi, cell_size, dp, capacity, max_events, next_id,
-                               self.stream.cuda_stream, brick_log2, brick_margin, S.UPDATE_PATHS[update_path])
+                               self.stream.cuda_stream, brick_log2, brick_margin, S.UPDATE_PATHS[update_path],
+                               S.BUILD_METHODS[build_method])
         S.check(st, "sph_create")
         self.ctx = ctx
         self.p = S.particles_from_tensors(self.pos, self.carried, self.label, self.id, self.n_dev)

@@ -31,12 +31,15 @@ SPH_MAX_CARRIED = 16
 SPH_MAX_EVENTS_LIMIT = 4096
 SPH_UPDATE_MERGED, SPH_UPDATE_CELLS = 0, 1
 UPDATE_PATHS = {"merged": SPH_UPDATE_MERGED, "cells": SPH_UPDATE_CELLS}
+SPH_BUILD_AUTO, SPH_BUILD_COUNTING, SPH_BUILD_BUCKETED = 0, 1, 2
+BUILD_METHODS = {"auto": SPH_BUILD_AUTO, "counting": SPH_BUILD_COUNTING, "bucketed": SPH_BUILD_BUCKETED}
 SPH_STATE_BLOB_BYTES = 136
 
 EXPORTED = (
     "sph_create", "sph_destroy", "sph_buffer_define", "sph_celllist_build", "sph_buffer_identify",
     "sph_buffer_update", "sph_buffer_update_async", "sph_buffer_update_fullscan",
     "sph_buffer_update_fullscan_async", "sph_last_result", "sph_last_events", "sph_celllist_view",
+    "sph_build_stats", "sph_build_retune",
     "sph_state_get", "sph_state_set", "sph_rotation_2d", "sph_rotation_axis_angle",
     "sph_rotation_from_direction", "sph_check_rotation", "sph_grid_cover", "sph_guard_band",
     "sph_status_str", "sph_profile_enable", "sph_profile_read", "sph_grid_fit",
@@ -88,7 +91,7 @@ class sph_config(ctypes.Structure):
         ("brick_log2", ctypes.c_int32),
         ("brick_margin", ctypes.c_int32),
         ("update_path", ctypes.c_int32),
-        ("pad2_", ctypes.c_int32),
+        ("build_method", ctypes.c_int32),
     ]
 
 
@@ -172,6 +175,8 @@ def lib() -> ctypes.CDLL:
             "sph_last_result": ([_VP, ctypes.POINTER(sph_result)], ctypes.c_int),
             "sph_last_events": ([_VP, _I64, _I64, ctypes.c_int64, _I64, _I64], ctypes.c_int),
             "sph_celllist_view": ([_VP, ctypes.POINTER(_VP), ctypes.POINTER(_VP), _I64, _I32], ctypes.c_int),
+            "sph_build_stats": ([_VP, _I32, ctypes.POINTER(ctypes.c_double), _I64], ctypes.c_int),
+            "sph_build_retune": ([_VP], ctypes.c_int),
             "sph_state_get": ([_VP, _I64, _I64], ctypes.c_int),
             "sph_state_set": ([_VP, ctypes.c_int64, _I64], ctypes.c_int),
             "sph_state_export": ([_VP, _VP, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
@@ -244,7 +249,8 @@ def sph_status_str(status: int) -> str:
 
 def sph_create(dim: int, lo, hi, cell_size: float, dp: float, capacity: int, max_events: int = 4096,
                next_id: int = 0, stream: int = 0, brick_log2: int = 0,
-               brick_margin: int = 1, update_path: int = SPH_UPDATE_MERGED) -> Tuple[int, Optional[int]]:
+               brick_margin: int = 1, update_path: int = SPH_UPDATE_MERGED,
+               build_method: int = SPH_BUILD_AUTO) -> Tuple[int, Optional[int]]:
     cfg = sph_config()
     cfg.dim = dim
     cfg.lo = _d3(lo)
@@ -258,6 +264,7 @@ def sph_create(dim: int, lo, hi, cell_size: float, dp: float, capacity: int, max
     cfg.brick_log2 = brick_log2
     cfg.brick_margin = brick_margin
     cfg.update_path = int(update_path)
+    cfg.build_method = int(build_method)
     out = _VP()
     st = lib().sph_create(ctypes.byref(cfg), ctypes.byref(out))
     if st == SPH_OK and out.value:
@@ -393,6 +400,20 @@ def sph_last_events(ctx: int, cap: int) -> Tuple[int, np.ndarray, np.ndarray]:
     st = lib().sph_last_events(ctx, gen.ctypes.data_as(_I64), dele.ctypes.data_as(_I64), int(cap), ctypes.byref(ng),
                                ctypes.byref(nd))
     return st, gen[: min(cap, ng.value)].copy(), dele[: min(cap, nd.value)].copy()
+
+
+def sph_build_stats(ctx: int):
+    """(status, method of the last build, [us counting, us bucketed], [samples
+    counting, samples bucketed]) -- the automatic method choice's view."""
+    m = ctypes.c_int32()
+    us = (ctypes.c_double * 2)()
+    ns = (ctypes.c_int64 * 2)()
+    st = lib().sph_build_stats(ctx, ctypes.byref(m), us, ns)
+    return st, m.value, [us[0], us[1]], [ns[0], ns[1]]
+
+
+def sph_build_retune(ctx: int) -> int:
+    return lib().sph_build_retune(ctx)
 
 
 def sph_celllist_view(ctx: int):

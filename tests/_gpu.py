@@ -10,16 +10,19 @@ import oracle
 from tests._support import oracle_state
 
 # Update path of the contexts the tests make ("merged", the library's default, or
-# "cells"); tests of one path set it with monkeypatch.setattr.
+# "cells") and their cell-list build method ("auto", the default, "counting" or
+# "bucketed"); tests of one path or method set them with monkeypatch.setattr.
 UPDATE_PATH = "merged"
+BUILD_METHOD = "auto"
 
 
 def make_domain_raw(dim, lo, hi, cell_size, dp, bufs: Sequence[oracle.Buffer], st: oracle.State,
-                    max_events: int = 4096, brick_log2: int = 0, brick_margin: int = 1, update_path: str = None):
+                    max_events: int = 4096, brick_log2: int = 0, brick_margin: int = 1, update_path: str = None,
+                    build_method: str = None):
     from paper_2406_16786_amd.domain import Domain
     d = Domain(dim, lo, hi, cell_size, dp, st.capacity, st.pos, st.carried, st.label, st.id, st.n, st.next_id,
                max_events=max_events, brick_log2=brick_log2, brick_margin=brick_margin,
-               update_path=update_path or UPDATE_PATH)
+               update_path=update_path or UPDATE_PATH, build_method=build_method or BUILD_METHOD)
     for b in bufs:
         d.define(b.kind, b.origin, b.rot, b.half, b.margin)
     if brick_log2:

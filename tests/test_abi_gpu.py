@@ -73,6 +73,8 @@ def test_too_many_buffers():
 def test_create_refusals():
     from paper_2406_16786_amd import sphbuf as S
     assert _ctx(update_path=5)[0] == S.SPH_ERR_ARG
+    assert _ctx(build_method=3)[0] == S.SPH_ERR_ARG
+    assert _ctx(build_method=-1)[0] == S.SPH_ERR_ARG
     # 2^23 cells along x: FP32 binning is off by more than a cell there
     st, ctx = S.sph_create(2, (0, 0, 0), ((1 << 23) * 1e-3, 0.004, 0), 1e-3, 4e-4, 1024)
     assert st == S.SPH_ERR_ARG and not ctx

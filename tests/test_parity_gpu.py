@@ -83,11 +83,13 @@ def _run_steps(wl, steps, mode="local", identify=True, check_every=1, cell_size=
 
 # ------------------------------------------------------------- cell list ---
 
+@pytest.mark.parametrize("method", ["counting", "bucketed"])
 @pytest.mark.parametrize("path", ["merged", "cells"])
 @pytest.mark.parametrize("name", ["channel2d", "bent_channel2d", "pipe3d_small"])
-def test_celllist_matches_oracle(name, path, monkeypatch):
+def test_celllist_matches_oracle(name, path, method, monkeypatch):
     import tests._gpu as G
     monkeypatch.setattr(G, "UPDATE_PATH", path)
+    monkeypatch.setattr(G, "BUILD_METHOD", method)
     wl = {"channel2d": W.channel2d, "bent_channel2d": W.bent_channel2d,
           "pipe3d_small": lambda: W.pipe3d(dp=0.004)}[name]()
     bufs = oracle_buffers(wl)
@@ -108,13 +110,13 @@ def test_celllist_matches_oracle(name, path, monkeypatch):
     d.close()
 
 
-def test_celllist_random_9_5m():
+@pytest.mark.parametrize("method", ["counting", "bucketed"])
+def test_celllist_random_9_5m(method):
     """9.5 M random particles in a box (no buffer: the plain count pass)."""
     n = 9_500_000
     pos, car, lab, ids = W.random_box_particles(7, n, 3, (0, 0, 0), (1.0, 0.5, 0.5), capacity=n + 16, n_carried=1)
-    st = make_state(3, np.zeros((0, 3)))
     st = oracle.State(3, pos, car, lab, ids, n, n)
-    d = make_domain_raw(3, (0, 0, 0), (1.0, 0.5, 0.5), 0.01, 0.004, [], st)
+    d = make_domain_raw(3, (0, 0, 0), (1.0, 0.5, 0.5), 0.01, 0.004, [], st, build_method=method)
     d.build()
     cs, ci, dims = _cell_list(d, n)
     ocs, oci = oracle.cell_list(3, np.float32([0, 0, 0]), np.float32(1.0 / 0.01), dims, pos[0][:n], pos[1][:n],
@@ -199,6 +201,44 @@ def test_celllist_crowded_cell_on_a_fine_grid():
 
 
 # ----------------------------------------------------------- update parity ---
+
+@pytest.mark.parametrize("method", ["counting", "bucketed"])
+@pytest.mark.parametrize("name", ["channel2d", "pipe3d_small"])
+def test_update_with_each_build_method(name, method, monkeypatch):
+    """The merged step's candidates come from the count pass of either build: 40
+    steps of each against the oracle (the default automatic choice alternates the
+    two while it times them, which every other test goes through)."""
+    import tests._gpu as G
+    monkeypatch.setattr(G, "BUILD_METHOD", method)
+    wl = W.channel2d() if name == "channel2d" else W.pipe3d(dp=0.004)
+    g, dl = _run_steps(wl, 40, check_every=10)
+    assert g > 0 and dl > 0
+
+
+def test_automatic_build_method_times_both():
+    """SPH_BUILD_AUTO: after a few synchronised builds both methods have been
+    timed (positive times, at least the exploration's samples), and the method
+    it settles on is the faster one within its 3 % margin."""
+    from paper_2406_16786_amd import sphbuf as S
+    wl = W.pipe3d(dp=0.004)
+    bufs = oracle_buffers(wl)
+    d = make_domain(wl, bufs)
+    st, m, us, ns = S.sph_build_stats(d.ctx)
+    assert st == 0 and m == S.SPH_BUILD_AUTO and ns == [0, 0]
+    for _ in range(24):
+        d.build()
+        d.stream.synchronize()
+    st, m, us, ns = S.sph_build_stats(d.ctx)
+    assert st == 0 and min(ns) >= 3 and min(us) > 0.0, (us, ns)
+    for _ in range(4):
+        d.build()
+    d.stream.synchronize()
+    st, m, us, ns = S.sph_build_stats(d.ctx)
+    fast = S.SPH_BUILD_COUNTING if us[0] <= us[1] else S.SPH_BUILD_BUCKETED
+    slow = S.SPH_BUILD_BUCKETED if fast == S.SPH_BUILD_COUNTING else S.SPH_BUILD_COUNTING
+    assert m == fast or us[slow - 1] * 0.97 <= us[fast - 1] * (1 + 1e-12), (m, us)
+    d.close()
+
 
 def test_channel2d_200_steps_local():
     g, dl = _run_steps(W.channel2d(), 200)
