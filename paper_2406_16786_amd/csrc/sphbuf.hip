@@ -385,18 +385,46 @@ __device__ __forceinline__ void emit(const EventArgs &e, const Parts &p, const B
 // The order inside a cell is whatever the atomics make it; nothing downstream
 // depends on it.
 
+// Cell keys of J particles (none = the key of an invalid one).  On a brick grid
+// the J brick-slot loads are issued together before any key is formed: one
+// round trip per group, not one per particle.  Coordinates are clamped (NaN lands
+// in cell 0), so every brick index is in range, invalid lanes included.
+template <int J>
+__device__ __forceinline__ void keys_of(const Grid &g, const float (&px)[J], const float (&py)[J],
+                                        const float (&pz)[J], const bool (&valid)[J], uint32_t none,
+                                        uint32_t (&key)[J], bool &bad) {
+    uint32_t ix[J], iy[J], iz[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        if (valid[j]) bad |= !(isfinite(px[j]) && isfinite(py[j]) && isfinite(pz[j]));
+        cell_coords(g, px[j], py[j], pz[j], ix[j], iy[j], iz[j]);
+    }
+    if (g.blog2 == 0) {
+#pragma unroll
+        for (int j = 0; j < J; ++j) key[j] = ix[j] + (uint32_t)g.dims[0] * (iy[j] + (uint32_t)g.dims[1] * iz[j]);
+    } else {
+        const uint32_t b = (uint32_t)g.blog2, m = (1u << b) - 1u;
+        int32_t slot[J];
+#pragma unroll
+        for (int j = 0; j < J; ++j)
+            slot[j] = g.brick_slot[(ix[j] >> b) +
+                                   (uint32_t)g.bdims[0] * ((iy[j] >> b) + (uint32_t)g.bdims[1] * (iz[j] >> b))];
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const uint32_t local = (ix[j] & m) + ((iy[j] & m) << b) + (g.dim == 3 ? ((iz[j] & m) << (2 * b)) : 0u);
+            key[j] = slot[j] < 0 ? g.overflow_key : ((uint32_t)slot[j] << (g.dim * b)) + local;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < J; ++j)
+        if (!valid[j]) key[j] = none;
+}
+
 template <int J>
 __device__ __forceinline__ void group_keys(const Grid &g, const float (&px)[J], const float (&py)[J],
                                            const float (&pz)[J], const bool (&valid)[J], uint32_t (&key)[J],
                                            bool &bad) {
-#pragma unroll
-    for (int j = 0; j < J; ++j) {
-        key[j] = 0xffffffffu;
-        if (valid[j]) {
-            bad |= !(isfinite(px[j]) && isfinite(py[j]) && isfinite(pz[j]));
-            key[j] = cell_key(g, px[j], py[j], pz[j]);
-        }
-    }
+    keys_of<J>(g, px, py, pz, valid, 0xffffffffu, key, bad);
 }
 
 // Runs of equal keys in consecutive lanes: the run's first lane (head) issues one
@@ -466,17 +494,52 @@ __device__ __forceinline__ bool near_region(const BufDev &b, int dim, float x, f
 // buffers' cover cells (bit k of the cell's cover mask) that lie near check region
 // k.  A workgroup gathers them in LDS (particle offset in the workgroup << 4 |
 // buffer; one LDS atomic per wave) and appends them to the candidate list with one
-// global atomic; a workgroup with more than kCandLds of them appends the rest one
-// by one.  E holds the offset: 16 bits for workgroups of at most 4096 particles.
+// global atomic; a workgroup with more than Cap of them appends the rest one by
+// one.  E holds the offset: 16 bits for workgroups of at most 4096 particles.
 
-constexpr int kCandLds = 2048;
-
-template <typename E>
+template <typename E, int Cap>
 struct CandLds {
-    E e[kCandLds];
+    E e[Cap];
     unsigned n;
     unsigned long long base;
 };
+
+// What the candidate test reads of a buffer, kept in LDS (the full record is 15
+// times larger): the FP32 frame, the widened half-extents, the axis-aligned box.
+struct BufNear {
+    float qf[9], ohi[3], olo[3];
+    float lim[3];        // thrf[3..5] + guard, summed in FP32 as the full scan's filter does
+    float bmin[3], bmax[3];
+};
+
+__device__ __forceinline__ void near_load(BufNear *sb, const BufDev *bufs, int nb) {
+    for (int k = threadIdx.x; k < nb; k += blockDim.x) {
+        const BufDev &b = bufs[k];
+        BufNear n;
+        for (int q = 0; q < 9; ++q) n.qf[q] = b.qf[q];
+        for (int q = 0; q < 3; ++q) {
+            n.ohi[q] = b.ohi[q];
+            n.olo[q] = b.olo[q];
+            n.lim[q] = b.thrf[3 + q] + b.guard;
+            n.bmin[q] = b.bmin[q];
+            n.bmax[q] = b.bmax[q];
+        }
+        sb[k] = n;
+    }
+}
+
+// near_region's test (and the box in front of it) on the LDS record.
+__device__ __forceinline__ bool near_test(const BufNear &b, int dim, float x, float y, float z) {
+    if (!(x > b.bmin[0] && x < b.bmax[0] && y > b.bmin[1] && y < b.bmax[1] && z > b.bmin[2] && z < b.bmax[2]))
+        return false;
+    const float d0 = (x - b.ohi[0]) - b.olo[0];
+    const float d1 = (y - b.ohi[1]) - b.olo[1];
+    const float d2 = dim == 3 ? (z - b.ohi[2]) - b.olo[2] : 0.0f;
+    const float l0 = b.qf[0] * d0 + b.qf[1] * d1 + b.qf[2] * d2;
+    const float l1 = b.qf[3] * d0 + b.qf[4] * d1 + b.qf[5] * d2;
+    const float l2 = b.qf[6] * d0 + b.qf[7] * d1 + b.qf[8] * d2;
+    return fabsf(l0) < b.lim[0] && fabsf(l1) < b.lim[1] && (dim == 2 || fabsf(l2) < b.lim[2]);
+}
 
 struct CandArgs {
     const uint16_t *cover;   // per cell: cover bits of the buffers
@@ -486,23 +549,33 @@ struct CandArgs {
     int64_t cap_cand;
 };
 
-// Called by whole waves (cm = 0 where there is nothing to test; z = 0 in 2-D).
-template <typename E>
-__device__ __forceinline__ void cand_append(const CandArgs &c, const BufDev *sb, int dim, uint32_t cm, float x,
-                                            float y, float z, uint32_t local, int64_t i, int lane,
-                                            CandLds<E> &L, Ctl *ctl) {
-    if (__ballot(cm != 0u) == 0ull) return;  // wave-uniform
-    unsigned cb = 0u;
-    uint32_t m = cm;
-    while (m) {
-        const int k = __ffs(m) - 1;
-        m &= m - 1u;
-        const BufDev &b = sb[k];
-        const bool in_box = x > b.bmin[0] && x < b.bmax[0] && y > b.bmin[1] && y < b.bmax[1] && z > b.bmin[2] &&
-                            z < b.bmax[2];
-        if (in_box && near_region(b, dim, x, y, z)) cb |= 1u << k;
+// Q particles per lane at once (cm = 0 where there is nothing to test; z = 0 in
+// 2-D); called by whole waves.  One branch, one prefix sum and one LDS atomic per
+// wave for all Q, and none of them when no lane has a cover bit or nothing passes
+// the test.
+template <int Q, typename E, int Cap>
+__device__ __forceinline__ void cand_append(const CandArgs &c, const BufNear *sb, int dim, const uint32_t (&cm)[Q],
+                                            const float (&x)[Q], const float (&y)[Q], const float (&z)[Q],
+                                            const uint32_t (&local)[Q], const int64_t (&idx)[Q], int lane,
+                                            CandLds<E, Cap> &L, Ctl *ctl) {
+    bool any = false;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) any |= cm[q] != 0u;
+    if (__ballot(any) == 0ull) return;  // wave-uniform
+    uint32_t cb[Q];
+    unsigned mine = 0u;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        cb[q] = 0u;
+        uint32_t m = cm[q];
+        while (m) {
+            const int k = __ffs(m) - 1;
+            m &= m - 1u;
+            if (near_test(sb[k], dim, x[q], y[q], z[q])) cb[q] |= 1u << k;
+        }
+        mine += (unsigned)__popc(cb[q]);
     }
-    const unsigned mine = (unsigned)__popc(cb);
+    if (__ballot(mine != 0u) == 0ull) return;  // cover cells, but nothing near a region
     unsigned incl = mine;
     for (int off = 1; off < kWave; off <<= 1) {
         const unsigned t = __shfl_up(incl, off);
@@ -510,28 +583,32 @@ __device__ __forceinline__ void cand_append(const CandArgs &c, const BufDev *sb,
     }
     const unsigned tot = __shfl(incl, kWave - 1);
     unsigned at = 0u;
-    if (lane == 0 && tot) at = atomicAdd(&L.n, tot);
+    if (lane == 0) at = atomicAdd(&L.n, tot);
     at = __shfl(at, 0) + (incl - mine);
-    while (cb) {
-        const int k = __ffs(cb) - 1;
-        cb &= cb - 1u;
-        if (at < (unsigned)kCandLds) {
-            L.e[at] = (E)((local << 4) | (uint32_t)k);
-        } else {  // a workgroup full of candidates: the rest one by one
-            const unsigned long long g = atomicAdd(&ctl->cand_count, 1ull);
-            if (g < (unsigned long long)c.cap_cand)
-                c.cand[g] = ((unsigned long long)i << 4) | (unsigned long long)k;
-            else
-                ctl->cand_overflow = 1u;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        uint32_t m = cb[q];
+        while (m) {
+            const int k = __ffs(m) - 1;
+            m &= m - 1u;
+            if (at < (unsigned)Cap) {
+                L.e[at] = (E)((local[q] << 4) | (uint32_t)k);
+            } else {  // a workgroup full of candidates: the rest one by one
+                const unsigned long long g = atomicAdd(&ctl->cand_count, 1ull);
+                if (g < (unsigned long long)c.cap_cand)
+                    c.cand[g] = ((unsigned long long)idx[q] << 4) | (unsigned long long)k;
+                else
+                    ctl->cand_overflow = 1u;
+            }
+            ++at;
         }
-        ++at;
     }
 }
 
 // The workgroup's gathered candidates into the list (after a barrier; has barriers).
-template <typename E>
-__device__ __forceinline__ void cand_flush(const CandArgs &c, CandLds<E> &L, int64_t s0, Ctl *ctl) {
-    const unsigned nc = min(L.n, (unsigned)kCandLds);
+template <typename E, int Cap>
+__device__ __forceinline__ void cand_flush(const CandArgs &c, CandLds<E, Cap> &L, int64_t s0, Ctl *ctl) {
+    const unsigned nc = min(L.n, (unsigned)Cap);
     if (threadIdx.x == 0) L.base = nc ? atomicAdd(&ctl->cand_count, (unsigned long long)nc) : 0ull;
     __syncthreads();
     for (unsigned e = threadIdx.x; e < nc; e += blockDim.x) {
@@ -587,11 +664,10 @@ __device__ __forceinline__ void count_body(const CountArgs &a, const int lb, con
     bool bad = false;
     const uint32_t rmask = (1u << a.rbits) - 1u;
     if (s0 >= N) return;  // block-uniform: no particle here
-    __shared__ BufDev sb[kCand ? SPH_MAX_BUFFERS : 1];
-    __shared__ std::conditional_t<kCand, CandLds<uint32_t>, char> s_cand;
+    __shared__ BufNear sb[kCand ? SPH_MAX_BUFFERS : 1];
+    __shared__ std::conditional_t<kCand, CandLds<uint32_t, 2048>, char> s_cand;
     if constexpr (kCand) {
-        for (int t = threadIdx.x; t < a.c.nb * (int)(sizeof(BufDev) / 4); t += blockDim.x)
-            reinterpret_cast<uint32_t *>(sb)[t] = reinterpret_cast<const uint32_t *>(a.c.bufs)[t];
+        near_load(sb, a.c.bufs, a.c.nb);
         if (threadIdx.x == 0) s_cand.n = 0u;
         __syncthreads();
     }
@@ -678,12 +754,14 @@ __device__ __forceinline__ void count_body(const CountArgs &a, const int lb, con
             }
         }
         if constexpr (kCand) {
+            uint32_t loc[J];
+            int64_t idx[J];
 #pragma unroll
             for (int j = 0; j < J; ++j) {
-                const int64_t i = rb[j] + (int64_t)o;
-                cand_append(a.c, sb, a.g.dim, cm[j], cx[j], cy[j], cz[j], (uint32_t)(i - s0), i, lane, s_cand,
-                            a.ctl);
+                idx[j] = rb[j] + (int64_t)o;
+                loc[j] = (uint32_t)(idx[j] - s0);
             }
+            cand_append<J>(a.c, sb, a.g.dim, cm, cx, cy, cz, loc, idx, lane, s_cand, a.ctl);
         }
     }
     if (__ballot(bad) != 0ull && lane == 0) atomicOr(a.nonfinite, 1u);
@@ -1299,8 +1377,9 @@ template <bool kCand>
 __global__ __launch_bounds__(kBkBlock) void k_bk_count(BkArgs a) {
     static_assert(kBkPer <= 4096, "candidate offsets are 12 bits");
     __shared__ uint32_t s_h[kMaxBuckets];  // counts, then bases, then cursors per bucket
-    __shared__ BufDev sb[kCand ? SPH_MAX_BUFFERS : 1];
-    __shared__ std::conditional_t<kCand, CandLds<uint16_t>, char> s_cand;
+    __shared__ BufNear sb[kCand ? SPH_MAX_BUFFERS : 1];
+    // (1024 slots: the LDS of eight workgroups per CU)
+    __shared__ std::conditional_t<kCand, CandLds<uint16_t, 1024>, char> s_cand;
     __shared__ uint32_t s_w[kBkBlock / kWave];
     __shared__ unsigned s_last;
     const int64_t N = live_count(a.n_dev, a.capacity);
@@ -1312,8 +1391,7 @@ __global__ __launch_bounds__(kBkBlock) void k_bk_count(BkArgs a) {
     }
     for (int t = threadIdx.x; t < a.nbk; t += kBkBlock) s_h[t] = 0u;
     if constexpr (kCand) {
-        for (int t = threadIdx.x; t < a.nb * (int)(sizeof(BufDev) / 4); t += kBkBlock)
-            reinterpret_cast<uint32_t *>(sb)[t] = reinterpret_cast<const uint32_t *>(a.bufs)[t];
+        near_load(sb, a.bufs, a.nb);
         if (threadIdx.x == 0) s_cand.n = 0u;
     }
     __syncthreads();
@@ -1341,13 +1419,11 @@ __global__ __launch_bounds__(kBkBlock) void k_bk_count(BkArgs a) {
                 py[q] = a.y[ic];
                 pz[q] = zb[ic];
             }
+            {
+                uint32_t kq[kBkBatch];
+                keys_of<kBkBatch>(a.g, px, py, pz, ok, 0u, kq, bad);
 #pragma unroll
-            for (int q = 0; q < kBkBatch; ++q) {
-                key[it + q] = 0u;
-                if (ok[q]) {
-                    bad |= !(isfinite(px[q]) && isfinite(py[q]) && isfinite(pz[q]));
-                    key[it + q] = cell_key(a.g, px[q], py[q], pz[q]);
-                }
+                for (int q = 0; q < kBkBatch; ++q) key[it + q] = kq[q];
             }
             uint32_t cm[kBkBatch];
             if constexpr (kCand) {  // the cover bits of the batch, all loads issued together
@@ -1361,25 +1437,42 @@ __global__ __launch_bounds__(kBkBlock) void k_bk_count(BkArgs a) {
                 if (len > 0 && lane == head) atomicAdd(&s_h[key[it + q] >> a.bshift], (uint32_t)len);
             }
             if constexpr (kCand) {
+                // each cover bit kept only if the particle is near that check region
+                // (the full scan's FP32 test widened by the guard band, which keeps
+                // every member)
+                uint32_t loc[kBkBatch];
+                int64_t idx[kBkBatch];
+                float zq[kBkBatch];
 #pragma unroll
                 for (int q = 0; q < kBkBatch; ++q) {
-                    // each cover bit kept only if the particle is near that check region
-                    // (the full scan's FP32 test widened by the guard band, which keeps
-                    // every member)
-                    const int64_t i = s0 + (int64_t)(it + q) * kBkBlock + threadIdx.x;
-                    const uint32_t local = (uint32_t)((it + q) * kBkBlock) + threadIdx.x;
-                    cand_append(ca, sb, dim, cm[q], px[q], py[q], d3 ? pz[q] : 0.0f, local, i, lane, s_cand,
-                                a.ctl);
+                    loc[q] = (uint32_t)((it + q) * kBkBlock) + threadIdx.x;
+                    idx[q] = s0 + (int64_t)loc[q];
+                    zq[q] = d3 ? pz[q] : 0.0f;
                 }
+                cand_append<kBkBatch>(ca, sb, dim, cm, px, py, zq, loc, idx, lane, s_cand, a.ctl);
             }
         }
     }
     __syncthreads();
     if constexpr (kCand) cand_flush(ca, s_cand, s0, a.ctl);  // the workgroup's candidates into the list
     // ---- the workgroup's base in each bucket it meets: one global atomic each ----
-    for (int t = threadIdx.x; t < a.nbk; t += kBkBlock) {
-        const uint32_t c = s_h[t];
-        if (c) s_h[t] = atomicAdd(&a.bk_count[t], c);
+    // A thread issues all its atomics before it uses the first result (a loop that
+    // stores each result before the next atomic waits a device atomic's full round
+    // trip per bucket).
+    constexpr int kPerT = kMaxBuckets / kBkBlock;
+    {
+        uint32_t r[kPerT];
+#pragma unroll
+        for (int q = 0; q < kPerT; ++q) {
+            const int t = q * kBkBlock + (int)threadIdx.x;
+            const uint32_t c = t < a.nbk ? s_h[t] : 0u;
+            r[q] = c ? atomicAdd(&a.bk_count[t], c) : 0u;
+        }
+#pragma unroll
+        for (int q = 0; q < kPerT; ++q) {
+            const int t = q * kBkBlock + (int)threadIdx.x;
+            if (t < a.nbk) s_h[t] = r[q];
+        }
     }
     __syncthreads();
     if (live) {
@@ -1408,8 +1501,19 @@ __global__ __launch_bounds__(kBkBlock) void k_bk_count(BkArgs a) {
                  (unsigned)G - 1u;
     __syncthreads();
     if (!s_last) return;
-    for (int t = threadIdx.x; t < a.nbk; t += kBkBlock)  // read and cleared where the atomics were done
-        s_h[t] = atomicExch(&a.bk_count[t], 0u);
+    {  // read and cleared where the atomics were done, all of a thread's in flight together
+        uint32_t r[kPerT];
+#pragma unroll
+        for (int q = 0; q < kPerT; ++q) {
+            const int t = q * kBkBlock + (int)threadIdx.x;
+            r[q] = t < a.nbk ? atomicExch(&a.bk_count[t], 0u) : 0u;
+        }
+#pragma unroll
+        for (int q = 0; q < kPerT; ++q) {
+            const int t = q * kBkBlock + (int)threadIdx.x;
+            if (t < a.nbk) s_h[t] = r[q];
+        }
+    }
     __syncthreads();
     const uint32_t total = lds_exclusive_scan<kBkBlock>(s_h, a.nbk, s_w);
     for (int t = threadIdx.x; t < a.nbk; t += kBkBlock) a.bk_start[t] = s_h[t];
@@ -1480,15 +1584,27 @@ __global__ __launch_bounds__(kSortBlock) void k_bk_sort(BkArgs a) {
     const uint32_t n0 = a.bk_start[b], n1 = a.bk_start[b + 1];
     const int64_t c0 = (int64_t)b << a.bshift;
     const int nc = (int)min<int64_t>((int64_t)1 << a.bshift, a.n_cells - c0);
+    // The bucket's first kHeld entries are read once and kept in registers (kR per
+    // thread, all loads in flight together) for both passes; only the entries of a
+    // bucket past that are read again (streamed, the next round's loads issued before
+    // the current round is counted or placed).  One LDS atomic per entry: in bucket
+    // order the lanes of a wave rarely share a cell.
+    constexpr int kR = 8;
+    constexpr uint32_t kHeld = (uint32_t)kSortBlock * kR;
+    uint2 h[kR];
+#pragma unroll
+    for (int q = 0; q < kR; ++q) {
+        const uint32_t e = n0 + (uint32_t)q * kSortBlock + threadIdx.x;
+        h[q] = e < n1 ? a.tmp[e] : make_uint2((uint32_t)c0, 0u);
+    }
     for (int t = threadIdx.x; t < nc; t += kSortBlock) s_c[t] = 0u;
     __syncthreads();
-    // Both passes software pipelined: the next round's entries are loaded before the
-    // current round is counted or placed (the LDS atomics and stores of a round then
-    // overlap the next round's loads).  One LDS atomic per entry: in bucket order the
-    // lanes of a wave rarely share a cell, so grouping equal keys first costs more
-    // than it saves.
-    constexpr int kB = 4;  // entries per thread and round
+#pragma unroll
+    for (int q = 0; q < kR; ++q)
+        if (n0 + (uint32_t)q * kSortBlock + threadIdx.x < n1) atomicAdd(&s_c[h[q].x - (uint32_t)c0], 1u);
+    constexpr int kB = 4;  // entries per thread and round of the streamed rest
     constexpr uint32_t kStep = (uint32_t)kSortBlock * kB;
+    const uint32_t r0 = n0 + kHeld;  // first streamed entry
     auto load = [&](uint32_t e0, uint2 (&u)[kB]) {
 #pragma unroll
         for (int q = 0; q < kB; ++q) {
@@ -1497,14 +1613,12 @@ __global__ __launch_bounds__(kSortBlock) void k_bk_sort(BkArgs a) {
         }
     };
     uint2 u[kB], un[kB];
-    if (n0 < n1) load(n0, u);
-    for (uint32_t e0 = n0; e0 < n1; e0 += kStep) {  // block-uniform trip count
+    if (r0 < n1) load(r0, u);
+    for (uint32_t e0 = r0; e0 < n1; e0 += kStep) {  // block-uniform trip count
         if (e0 + kStep < n1) load(e0 + kStep, un);
 #pragma unroll
-        for (int q = 0; q < kB; ++q) {
-            const bool ok = e0 + (uint32_t)q * kSortBlock + threadIdx.x < n1;
-            if (ok) atomicAdd(&s_c[u[q].x - (uint32_t)c0], 1u);
-        }
+        for (int q = 0; q < kB; ++q)
+            if (e0 + (uint32_t)q * kSortBlock + threadIdx.x < n1) atomicAdd(&s_c[u[q].x - (uint32_t)c0], 1u);
 #pragma unroll
         for (int q = 0; q < kB; ++q) u[q] = un[q];
     }
@@ -1513,14 +1627,17 @@ __global__ __launch_bounds__(kSortBlock) void k_bk_sort(BkArgs a) {
     for (int t = threadIdx.x; t < nc; t += kSortBlock) a.cell_start[c0 + t] = (int32_t)(n0 + s_c[t]);
     if (b == a.nbk - 1 && threadIdx.x == 0) a.cell_start[a.n_cells] = (int32_t)n1;
     __syncthreads();  // every offset read before the cursors move
-    if (n0 < n1) load(n0, u);
-    for (uint32_t e0 = n0; e0 < n1; e0 += kStep) {
+#pragma unroll
+    for (int q = 0; q < kR; ++q)
+        if (n0 + (uint32_t)q * kSortBlock + threadIdx.x < n1)
+            a.cell_idx[n0 + atomicAdd(&s_c[h[q].x - (uint32_t)c0], 1u)] = (int32_t)h[q].y;
+    if (r0 < n1) load(r0, u);
+    for (uint32_t e0 = r0; e0 < n1; e0 += kStep) {
         if (e0 + kStep < n1) load(e0 + kStep, un);
 #pragma unroll
-        for (int q = 0; q < kB; ++q) {
-            const bool ok = e0 + (uint32_t)q * kSortBlock + threadIdx.x < n1;
-            if (ok) a.cell_idx[n0 + atomicAdd(&s_c[u[q].x - (uint32_t)c0], 1u)] = (int32_t)u[q].y;
-        }
+        for (int q = 0; q < kB; ++q)
+            if (e0 + (uint32_t)q * kSortBlock + threadIdx.x < n1)
+                a.cell_idx[n0 + atomicAdd(&s_c[u[q].x - (uint32_t)c0], 1u)] = (int32_t)u[q].y;
 #pragma unroll
         for (int q = 0; q < kB; ++q) u[q] = un[q];
     }
