@@ -843,8 +843,9 @@ def main() -> int:
                    "dim": wl.dim, "buffers": len(wl.buffers), "cells": h["cells"],
                    "candidates_per_update": h["candidates_per_update"], "events_per_step": h["events_per_step"],
                    "timed_steps": h["timed_steps"],
-                   "path": "merged step: bucketed cell-list build whose count pass lists the cover cells' "
-                           "candidates; their exact tests beside the bucket scatter; bucket sort; finalize"},
+                   "path": "merged step: cell-list build (counting or bucketed sort, whichever the context "
+                           "timed faster; build_method) whose count pass lists the cover cells' candidates; their "
+                           "exact tests beside the build's scatter; finalize"},
         "roofline": h.get("roofline"),
     }
     for k, v in h.items():
