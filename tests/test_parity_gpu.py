@@ -237,7 +237,33 @@ def test_automatic_build_method_times_both():
     fast = S.SPH_BUILD_COUNTING if us[0] <= us[1] else S.SPH_BUILD_BUCKETED
     slow = S.SPH_BUILD_BUCKETED if fast == S.SPH_BUILD_COUNTING else S.SPH_BUILD_COUNTING
     assert m == fast or us[slow - 1] * 0.97 <= us[fast - 1] * (1 + 1e-12), (m, us)
+    # a retune forgets both times and measures them again
+    assert S.sph_build_retune(d.ctx) == 0
+    st, m, us, ns = S.sph_build_stats(d.ctx)
+    assert st == 0 and ns == [0, 0] and us == [0.0, 0.0]
+    for _ in range(12):
+        d.build()
+        d.stream.synchronize()
+    st, m, us, ns = S.sph_build_stats(d.ctx)
+    assert st == 0 and min(ns) >= 3 and min(us) > 0.0, (us, ns)
     d.close()
+
+
+def test_fixed_build_methods_report_themselves():
+    """A fixed method runs on every build and is reported as the last build's; no
+    timing is taken (both times stay 0)."""
+    from paper_2406_16786_amd import sphbuf as S
+    import tests._gpu as G
+    wl = W.pipe3d(dp=0.004)
+    bufs = oracle_buffers(wl)
+    for name, code in (("counting", S.SPH_BUILD_COUNTING), ("bucketed", S.SPH_BUILD_BUCKETED)):
+        d = G.make_domain_raw(wl.dim, wl.lo, wl.hi, wl.cell_size, wl.dp, bufs, oracle_state(wl), build_method=name)
+        for _ in range(3):
+            d.build()
+        d.stream.synchronize()
+        st, m, us, ns = S.sph_build_stats(d.ctx)
+        assert st == 0 and m == code and ns == [0, 0] and us == [0.0, 0.0], (name, m, us, ns)
+        d.close()
 
 
 def test_channel2d_200_steps_local():
