@@ -1378,7 +1378,7 @@ __global__ __launch_bounds__(kBkBlock) void k_bk_count(BkArgs a) {
     static_assert(kBkPer <= 4096, "candidate offsets are 12 bits");
     __shared__ uint32_t s_h[kMaxBuckets];  // counts, then bases, then cursors per bucket
     __shared__ BufNear sb[kCand ? SPH_MAX_BUFFERS : 1];
-    // (1024 slots: the LDS of eight workgroups per CU)
+    // (1024 slots: every workgroup of 4096 particles but those crowded with candidates)
     __shared__ std::conditional_t<kCand, CandLds<uint16_t, 1024>, char> s_cand;
     __shared__ uint32_t s_w[kBkBlock / kWave];
     __shared__ unsigned s_last;
