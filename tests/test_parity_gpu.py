@@ -127,6 +127,33 @@ def test_celllist_random_9_5m(method):
     d.close()
 
 
+def test_bucketed_builds_of_changing_particle_sets():
+    """Bucketed builds of very different particle sets on one context (uniform,
+    crowded into one corner, uniform again): nothing of one build's bucket layout
+    or counts may leak into the next; every cell list equals the oracle's."""
+    import torch
+    n = 400_000
+    rng = np.random.default_rng(31)
+    pts_a = rng.uniform((0.0, 0.0, 0.0), (1.0, 0.5, 0.5), (n, 3))
+    pts_b = rng.uniform((0.0, 0.0, 0.0), (0.3, 0.2, 0.1), (n, 3))
+    st = make_state(3, pts_a, capacity=n + 16)
+    d = make_domain_raw(3, (0, 0, 0), (1.0, 0.5, 0.5), 0.01, 0.004, [], st, build_method="bucketed")
+    for pts in (pts_a, pts_b, pts_a):
+        stp = make_state(3, pts, capacity=n + 16)
+        with torch.cuda.stream(d.stream):
+            for c in range(3):
+                d.pos[c].copy_(torch.from_numpy(stp.pos[c][: n + 16]))
+        d.stream.synchronize()
+        d.build()
+        cs, ci, dims = _cell_list(d, n)
+        ocs, oci = oracle.cell_list(3, np.float32([0, 0, 0]), np.float32(1.0 / 0.01), dims, stp.pos[0][:n],
+                                    stp.pos[1][:n], stp.pos[2][:n])
+        np.testing.assert_array_equal(cs, ocs)
+        cell_of = np.repeat(np.arange(len(ocs) - 1), np.diff(ocs))
+        np.testing.assert_array_equal(ci[np.lexsort((ci, cell_of))], oci[np.lexsort((oci, cell_of))])
+    d.close()
+
+
 def test_celllist_buckets_of_4096_cells():
     """A 2-D grid of 16.4 M cells takes buckets of 4096 cells (the largest): each
     bucket's counting sort walks its cells in several rounds of its workgroup.
