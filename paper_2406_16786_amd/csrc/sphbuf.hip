@@ -3280,7 +3280,8 @@ sph_status count_cells(sph_ctx *c, const FullArgs *fa) {
     return SPH_OK;
 }
 
-// Timer events of the build method choice, created at the first automatic build.
+// Timer events of the build method choice (created with an automatic context, so
+// that builds allocate nothing).
 bool timers_ready(sph_ctx *c) {
     BuildTimer &t = c->bt;
     if (!t.init) {
@@ -3828,6 +3829,7 @@ extern "C" sph_status sph_create(const sph_config *cfg, sph_ctx **out) {
              hipMemcpyAsync(c->d_result, &r0, sizeof(r0), hipMemcpyHostToDevice, c->stream) == hipSuccess &&
              hipStreamSynchronize(c->stream) == hipSuccess;
     }
+    if (ok && c->build_pref == SPH_BUILD_AUTO) (void)timers_ready(c);  // no events: the bucketed build, untimed
     if (!ok) {
         free_ctx(c);
         return SPH_ERR_HIP;
