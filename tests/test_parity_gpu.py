@@ -176,22 +176,22 @@ def test_celllist_buckets_of_4096_cells():
 
 def test_celllist_full_size_network_repeatable():
     """The branching network at full size (16.1 M particles, brick-sparse grid,
-    buckets of 1024 cells): three builds through a cover-walk context and one
-    through a merged one give the same cell starts and the same particles in every
-    cell (the order inside a cell is free)."""
+    buckets of 1024 cells): repeated builds by each method through cover-walk
+    contexts and one through a merged context give the same cell starts and the
+    same particles in every cell (the order inside a cell is free)."""
     import tests._gpu as G
     wl = W.tree3d()
     bufs = oracle_buffers(wl)
     st = oracle_state(wl)
     n = st.n
     lists = []
-    for path, builds in (("cells", 3), ("merged", 1)):
-        old = G.UPDATE_PATH
-        G.UPDATE_PATH = path
+    for path, method, builds in (("cells", "counting", 2), ("cells", "bucketed", 2), ("merged", "auto", 1)):
+        old, oldm = G.UPDATE_PATH, G.BUILD_METHOD
+        G.UPDATE_PATH, G.BUILD_METHOD = path, method
         try:
             d = make_domain(wl, bufs, st, brick_log2=3)
         finally:
-            G.UPDATE_PATH = old
+            G.UPDATE_PATH, G.BUILD_METHOD = old, oldm
         for _ in range(builds):
             d.build()
             cs, ci, _ = _cell_list(d, n)
