@@ -229,9 +229,22 @@ def single_leg(torch, np, S, W, Domain, wl, K, Wm, late, early, args):
     S.check(st_c, "create (cover-cell walk)")
     for b, q in zip(wl.buffers, rots):
         S.check(S.sph_buffer_define(ctx_cells, b.kind, b.origin, q, b.half, b.margin)[0], "define (cells)")
-    if blog2:  # both contexts fit their bricks to the same initial state
+    # merged-step contexts with a fixed build method: the automatic choice's evidence
+    fixed = {}
+    for mname in ("counting", "bucketed"):
+        st_m, ctx_m = S.sph_create(wl.dim, wl.lo, wl.hi, wl.cell_size, wl.dp, wl.capacity,
+                                   max_events=S.SPH_MAX_EVENTS_LIMIT, next_id=wl.n, stream=dom.stream.cuda_stream,
+                                   brick_log2=blog2, update_path=S.SPH_UPDATE_MERGED,
+                                   build_method=S.BUILD_METHODS[mname])
+        S.check(st_m, f"create ({mname})")
+        for b, q in zip(wl.buffers, rots):
+            S.check(S.sph_buffer_define(ctx_m, b.kind, b.origin, q, b.half, b.margin)[0], f"define ({mname})")
+        fixed[mname] = ctx_m
+    if blog2:  # every context fits its bricks to the same initial state
         dom.fit()
         S.check(S.sph_grid_fit(ctx_cells, dom.p), "grid_fit (cells)")
+        for mname, ctx_m in fixed.items():
+            S.check(S.sph_grid_fit(ctx_m, dom.p), f"grid_fit ({mname})")
     S.check(dom.identify(-1), "identify")
     stream = dom.stream
 
@@ -283,7 +296,7 @@ def single_leg(torch, np, S, W, Domain, wl, K, Wm, late, early, args):
             stream.synchronize()
             S.check(S.sph_state_set(ctx, *states[k][0]), "state_set")
 
-        def replay(mode, ctx, profile):
+        def replay(mode, ctx, profile, region=True):
             reset(ctx)
             S.check(S.sph_profile_enable(ctx, False), "profile")
             if mode == "local":
@@ -306,7 +319,7 @@ def single_leg(torch, np, S, W, Domain, wl, K, Wm, late, early, args):
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             torch.cuda.synchronize()
-            if k == "late":
+            if k == "late" and region:
                 REGIONS.begin()
             t0 = time.perf_counter()
             e0.record(stream)
@@ -319,7 +332,7 @@ def single_leg(torch, np, S, W, Domain, wl, K, Wm, late, early, args):
             e1.record(stream)
             torch.cuda.synchronize()
             wall = time.perf_counter() - t0
-            if k == "late":
+            if k == "late" and region:
                 REGIONS.end()
             ms = e0.elapsed_time(e1) / K
             rs, r = S.sph_last_result(ctx)
@@ -346,6 +359,8 @@ def single_leg(torch, np, S, W, Domain, wl, K, Wm, late, early, args):
         out["method"] = build_method(dom.ctx)
         out["ms_full"], _, _ = replay("fullscan", dom.ctx, False)
         out["ms_cells"], _, _ = replay("local", ctx_cells, False)
+        # outside the profiler's regions: the profiled kernels stay those of the paths above
+        out["ms_fixed"] = {m: replay("local", c, False, region=False)[0] for m, c in fixed.items()}
         if not args.no_profile_pass:
             _, _, out["prof_merged"] = replay("local", dom.ctx, True)
             _, _, out["prof_full"] = replay("fullscan", dom.ctx, True)
@@ -427,6 +442,11 @@ def single_leg(torch, np, S, W, Domain, wl, K, Wm, late, early, args):
         + ", cover-cell walk "
         f"{L['ms_cells'] * 1e3:.1f} us, full-scan update {L['ms_full'] * 1e3:.1f} us; phases (us): "
         + ", ".join(f"{k} {v * 1e3:.1f}" for k, v in (pm or {}).items()))
+    out["build_method"]["step_ms_each_method"] = {m: round(v, 5) for m, v in L["ms_fixed"].items()}
+    if E is not None:
+        out["early_window"]["build_method"]["step_ms_each_method"] = {m: round(v, 5) for m, v in E["ms_fixed"].items()}
+    for c in fixed.values():
+        S.sph_destroy(c)
     leg = {"out": out, "dom": dom, "ctx_cells": ctx_cells, "snaps": snaps["late"], "states": states["late"],
            "work": L["work"], "parts": L["parts"], "rots": rots, "stream": stream, "flush": flush}
     return leg
