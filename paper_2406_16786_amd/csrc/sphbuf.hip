@@ -1588,9 +1588,12 @@ __global__ __launch_bounds__(kSortBlock) void k_bk_sort(BkArgs a) {
     // thread, all loads in flight together) for both passes; only the entries of a
     // bucket past that are read again (streamed, the next round's loads issued before
     // the current round is counted or placed).  One LDS atomic per entry: in bucket
-    // order the lanes of a wave rarely share a cell.
+    // order the lanes of a wave rarely share a cell.  A bucket of at most kHeld
+    // entries is placed in LDS and stored in order (scattered 4-byte stores into
+    // the bucket's range cost more than the LDS round).
     constexpr int kR = 8;
     constexpr uint32_t kHeld = (uint32_t)kSortBlock * kR;
+    __shared__ int32_t s_out[kHeld];
     uint2 h[kR];
 #pragma unroll
     for (int q = 0; q < kR; ++q) {
@@ -1627,6 +1630,15 @@ __global__ __launch_bounds__(kSortBlock) void k_bk_sort(BkArgs a) {
     for (int t = threadIdx.x; t < nc; t += kSortBlock) a.cell_start[c0 + t] = (int32_t)(n0 + s_c[t]);
     if (b == a.nbk - 1 && threadIdx.x == 0) a.cell_start[a.n_cells] = (int32_t)n1;
     __syncthreads();  // every offset read before the cursors move
+    if (n1 - n0 <= kHeld) {  // block-uniform: every entry is held
+#pragma unroll
+        for (int q = 0; q < kR; ++q)
+            if (n0 + (uint32_t)q * kSortBlock + threadIdx.x < n1)
+                s_out[atomicAdd(&s_c[h[q].x - (uint32_t)c0], 1u)] = (int32_t)h[q].y;
+        __syncthreads();
+        for (uint32_t t = threadIdx.x; t < n1 - n0; t += kSortBlock) a.cell_idx[n0 + t] = s_out[t];
+        return;
+    }
 #pragma unroll
     for (int q = 0; q < kR; ++q)
         if (n0 + (uint32_t)q * kSortBlock + threadIdx.x < n1)
