@@ -227,6 +227,39 @@ def test_celllist_crowded_cell_on_a_fine_grid():
     d.close()
 
 
+@pytest.mark.parametrize("method", ["counting", "bucketed"])
+def test_celllist_cells_around_the_held_entries(method):
+    """A grid of 3600 cells makes every cell a bucket of its own, so cells of 4095,
+    4096 and 4097 particles sit on either side of the bucket sort's 4096 held
+    entries (placed in LDS and stored in order up to there, stored one by one
+    past it) and one of 9000 streams most of its entries; 50 k particles spread
+    over the other cells.  Both builds against the oracle's cell list."""
+    rng = np.random.default_rng(41)
+    cs_ = 1.0 / 60.0
+    crowds = {(7, 9): 4095, (30, 30): 4096, (31, 30): 4097, (52, 3): 9000}
+    parts = [rng.uniform(0.0, 1.0, (50_000, 2))]
+    for (ix, iy), m in crowds.items():
+        ctr = np.array([(ix + 0.5) * cs_, (iy + 0.5) * cs_])
+        parts.append(ctr + rng.uniform(-0.3 * cs_, 0.3 * cs_, (m, 2)))
+    pts = np.concatenate(parts)
+    pts = pts[rng.permutation(len(pts))]
+    n = len(pts)
+    st = make_state(2, pts, capacity=n + 16)
+    d = make_domain_raw(2, (0, 0, 0), (1.0, 1.0, 0.0), cs_, cs_, [], st, build_method=method)
+    d.build()
+    cs, ci, dims = _cell_list(d, n)
+    assert dims[0] * dims[1] <= 4096
+    ocs, oci = oracle.cell_list(2, np.float32([0, 0]), np.float32(1.0 / cs_), dims[:2], st.pos[0][:n], st.pos[1][:n],
+                                None)
+    np.testing.assert_array_equal(cs, ocs)
+    counts = np.diff(ocs)
+    for m in crowds.values():
+        assert (counts >= m).sum() >= 1
+    cell_of = np.repeat(np.arange(len(ocs) - 1), counts)
+    np.testing.assert_array_equal(ci[np.lexsort((ci, cell_of))], oci[np.lexsort((oci, cell_of))])
+    d.close()
+
+
 # ----------------------------------------------------------- update parity ---
 
 @pytest.mark.parametrize("method", ["counting", "bucketed"])
