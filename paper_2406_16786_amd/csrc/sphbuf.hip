@@ -2736,18 +2736,42 @@ __global__ __launch_bounds__(kNbrBlock) void k_nbr_order(NbrArgs a) {
     }
 }
 
-// Pairs of slot k with the slots [m0, m1): FP32 test, FP64 in the band.
+// Pairs of slot k with the slots [m0, m1): FP32 test, FP64 in the band.  The main
+// loop counts the pairs surely inside without a branch (four candidates' loads
+// issued together) and only notes whether any pair fell in the band; the rare
+// range that has one is walked again for the exact decisions of those pairs.
+template <bool d3>
 __device__ __forceinline__ int nbr_range(const NbrArgs &a, int64_t k, const float (&pi)[3], int32_t m0, int32_t m1) {
+    constexpr int U = 4;
     int cnt = 0;
-    const bool d3 = a.g.dim == 3;
-    for (int32_t m = m0; m < m1; ++m) {
-        if (m == k) continue;
-        const float xj = a.xs[m], yj = a.ys[m], zj = d3 ? a.zs[m] : 0.0f;
+    bool band = false;
+    auto test = [&](int32_t m, float xj, float yj, float zj) {
         const float dx = pi[0] - xj, dy = pi[1] - yj, dz = pi[2] - zj;
         const float d2 = (dx * dx + dy * dy) + dz * dz;
-        if (d2 < a.r2_in) {
-            ++cnt;
-        } else if (!(d2 > a.r2_out)) {
+        const bool other = m != k;
+        cnt += (other && d2 < a.r2_in) ? 1 : 0;
+        band = band || (other && !(d2 < a.r2_in) && !(d2 > a.r2_out));
+    };
+    int32_t m = m0;
+    for (; m + U <= m1; m += U) {
+        float xj[U], yj[U], zj[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            xj[u] = a.xs[m + u];
+            yj[u] = a.ys[m + u];
+            zj[u] = d3 ? a.zs[m + u] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) test(m + u, xj[u], yj[u], zj[u]);
+    }
+    for (; m < m1; ++m) test(m, a.xs[m], a.ys[m], d3 ? a.zs[m] : 0.0f);
+    if (band) {
+        for (m = m0; m < m1; ++m) {
+            if (m == k) continue;
+            const float xj = a.xs[m], yj = a.ys[m], zj = d3 ? a.zs[m] : 0.0f;
+            const float dx = pi[0] - xj, dy = pi[1] - yj, dz = pi[2] - zj;
+            const float d2 = (dx * dx + dy * dy) + dz * dz;
+            if (d2 < a.r2_in || d2 > a.r2_out) continue;  // decided above
             const double ex = __dadd_rn((double)pi[0], -(double)xj);
             const double ey = __dadd_rn((double)pi[1], -(double)yj);
             const double ez = __dadd_rn((double)pi[2], -(double)zj);
@@ -2758,13 +2782,15 @@ __device__ __forceinline__ int nbr_range(const NbrArgs &a, int64_t k, const floa
     return cnt;
 }
 
+template <int dim>
 __global__ __launch_bounds__(kNbrBlock) void k_neighbor_count(NbrArgs a) {
+    constexpr bool d3 = dim == 3;
     const int64_t N = live_count(a.p.n_dev, a.p.capacity);
     const Grid &g = a.g;
-    const int dim = g.dim;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < N; k += (int64_t)gridDim.x * blockDim.x) {
-        const float pi[3] = {a.xs[k], a.ys[k], dim == 3 ? a.zs[k] : 0.0f};
+        const float pi[3] = {a.xs[k], a.ys[k], d3 ? a.zs[k] : 0.0f};
         int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+#pragma unroll
         for (int ax = 0; ax < dim; ++ax) {
             const float t = (pi[ax] - g.lo[ax]) * g.inv_cs;  // as in cell_coords
             const float f = floorf(t);
@@ -2782,7 +2808,7 @@ __global__ __launch_bounds__(kNbrBlock) void k_neighbor_count(NbrArgs a) {
                 for (int iy = lo[1]; iy <= hi[1]; ++iy) {
                     const uint32_t k0 = key_of_cell(g, (uint32_t)lo[0], (uint32_t)iy, (uint32_t)iz);
                     const uint32_t k1 = k0 + (uint32_t)(hi[0] - lo[0]);
-                    cnt += nbr_range(a, k, pi, a.cell_start[k0], a.cell_start[k1 + 1]);
+                    cnt += nbr_range<d3>(a, k, pi, a.cell_start[k0], a.cell_start[k1 + 1]);
                 }
         } else {
             bool overflow_seen = false;
@@ -2794,7 +2820,7 @@ __global__ __launch_bounds__(kNbrBlock) void k_neighbor_count(NbrArgs a) {
                             if (overflow_seen) continue;
                             overflow_seen = true;
                         }
-                        cnt += nbr_range(a, k, pi, a.cell_start[key], a.cell_start[key + 1]);
+                        cnt += nbr_range<d3>(a, k, pi, a.cell_start[key], a.cell_start[key + 1]);
                     }
         }
         a.counts[a.cell_idx[k]] = cnt;
@@ -4276,7 +4302,10 @@ extern "C" sph_status sph_neighbor_count(sph_ctx *ctx, const sph_particles *p, d
     {
         ProfScope ps(ctx, SPH_PHASE_NEIGHBOR);
         hipLaunchKernelGGL(k_nbr_order, dim3(blocks), dim3(kNbrBlock), 0, ctx->stream, a);
-        hipLaunchKernelGGL(k_neighbor_count, dim3(blocks), dim3(kNbrBlock), 0, ctx->stream, a);
+        if (a.g.dim == 3)
+            hipLaunchKernelGGL(k_neighbor_count<3>, dim3(blocks), dim3(kNbrBlock), 0, ctx->stream, a);
+        else
+            hipLaunchKernelGGL(k_neighbor_count<2>, dim3(blocks), dim3(kNbrBlock), 0, ctx->stream, a);
     }
     HIP_TRY(hipGetLastError());
     return SPH_OK;
