@@ -2797,7 +2797,9 @@ __global__ __launch_bounds__(kNbrBlock) void k_neighbor_count(NbrArgs a) {
     constexpr bool d3 = dim == 3;
     const int64_t N = live_count(a.p.n_dev, a.p.capacity);
     const Grid &g = a.g;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < N; k += (int64_t)gridDim.x * blockDim.x) {
+    // XCD-contiguous tiles: the stencil rows an XCD reads stay within a narrower slot
+    // window, so more of them hit its L2 (2.12 -> 2.01 ms on the pipe)
+    for (int64_t k = (int64_t)logical_block() * blockDim.x + threadIdx.x; k < N; k += (int64_t)gridDim.x * blockDim.x) {
         const float pi[3] = {a.xs[k], a.ys[k], d3 ? a.zs[k] : 0.0f};
         int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
 #pragma unroll
@@ -4308,7 +4310,8 @@ extern "C" sph_status sph_neighbor_count(sph_ctx *ctx, const sph_particles *p, d
     a.r2_out = (float)(r2 * (1.0 + 0x1p-16));
     a.band = (float)band;
     a.counts = counts;
-    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(65536, (pp.capacity + kNbrBlock - 1) / kNbrBlock));
+    // (a multiple of 8, so the XCD renumbering applies)
+    const int blocks = (int)std::max<int64_t>(8, std::min<int64_t>(65536, (pp.capacity + kNbrBlock - 1) / kNbrBlock + 7) / 8 * 8);
     {
         ProfScope ps(ctx, SPH_PHASE_NEIGHBOR);
         hipLaunchKernelGGL(k_nbr_order, dim3(blocks), dim3(kNbrBlock), 0, ctx->stream, a);
